@@ -1,0 +1,183 @@
+/*
+ * dg_poisson.h -- C ABI of the MI355X DG Poisson library.
+ *
+ * The library solves the Poisson problems of the auxiliary-grid step of the
+ * DG Hartree-Fock method of Pan & Lindsey ("Fast adaptive discontinuous basis
+ * sets for electronic structure", Sec. 6):
+ *
+ *     -Lap v = 4 pi f   in the box Omega,     v = g   on the boundary of Omega
+ *
+ * (eq. hartree_poisson and eq. fock_poisson, truncated to a finite box with
+ * Dirichlet data as in Sec. 6.3), discretised by the symmetric interior
+ * penalty method of eq. (sip_bilinear) with the penalty of eq. (pen_poly)
+ * (sigma = (p+1)^2 / (eps h), eps = 1/8) on a uniform hexahedral mesh carrying
+ * tensor-product Gauss-Lobatto nodal polynomials of degree p.  The nodes also
+ * define the quadrature rule (Sec. 6.1): the source f is given by its values
+ * at the nodes and the potential v is returned by its values at the nodes.
+ * Dirichlet data are imposed weakly (symmetric Nitsche terms).  The discrete
+ * system is solved by conjugate gradients preconditioned by an hp-multigrid
+ * V-cycle (Sec. 6.4): degree coarsening down to 1, then geometric coarsening.
+ *
+ * Units are atomic (bohr, hartree).
+ *
+ * Storage orders
+ *   field   one value per node, element-major: [ez][ey][ex][k][j][i]
+ *           (elements lexicographic with x fastest; local node index i along x
+ *           fastest).  n_dofs = Ex*Ey*Ez*(p+1)^3 values per right-hand side.
+ *   faces   Dirichlet data at the boundary nodes: the six faces x-, x+, y-,
+ *           y+, z-, z+ concatenated; an x face is [Z][Y] over global node
+ *           indices (Y fastest), a y face [Z][X], a z face [Y][X], where the
+ *           global node index along an axis is X = ex*(p+1) + i.
+ *           n_face = 2*(NY*NZ + NX*NZ + NX*NY) values per right-hand side.
+ *   batch   several right-hand sides are packed back to back in the order
+ *           given, each at the offset of the sum of the sizes before it.
+ *   pairs   for norb orbitals the npairs = norb(norb+1)/2 pairs (i <= j) are
+ *           ordered row-major: idx(i,j) = i*norb - i(i-1)/2 + (j - i).
+ *
+ * Ownership and synchronisation
+ *   Every field pointer below is a HIP device pointer owned by the caller
+ *   unless marked "host".  The context owns its level tables and work space
+ *   (grown on demand, kept until dg_poisson_destroy).  Work is enqueued on
+ *   the caller's stream; calls that return statistics synchronise the stream
+ *   before they return.  A context is used by one host thread at a time.
+ *
+ * Errors
+ *   Functions return a dg_status; no C++ exception crosses the ABI.
+ *   DG_ERR_ARG for bad sizes, indices or null pointers; DG_ERR_HIP when a HIP
+ *   runtime call fails (dg_last_error() gives the message);
+ *   DG_WARN_NOT_CONVERGED when a right-hand side missed its tolerance within
+ *   max_iter (its stats entry says which).
+ */
+#ifndef DG_POISSON_H
+#define DG_POISSON_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DG_OK = 0,
+    DG_WARN_NOT_CONVERGED = 1,
+    DG_ERR_ARG = -1,
+    DG_ERR_HIP = -2,
+    DG_ERR_OOM = -3,
+    DG_ERR_BREAKDOWN = -4,
+    DG_ERR_STATE = -5
+} dg_status;
+
+/* Arithmetic of the iteration.  FP64: every vector and kernel in double.
+ * FP32_IR: FP64 iterative refinement (FP64 right-hand side, solution and
+ * residual) around an inner PCG whose vectors, operator applications and
+ * smoothing are FP32; dot products, the coarsest-grid solve and all energy
+ * reductions stay FP64. */
+typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_IR = 1 } dg_precision;
+
+/* A uniform hexahedral mesh: ne[d] elements along axis d on [lo[d], hi[d]],
+ * Gauss-Lobatto nodal polynomials of degree p (1 <= p <= 7). */
+typedef struct {
+    int ne[3];
+    int p;
+    double lo[3], hi[3];
+} dg_mesh;
+
+typedef struct {
+    int n_levels;        /* multigrid levels; 0 = automatic (coarsest <= 16 nodes per axis) */
+    int cheb_degree;     /* Chebyshev smoothing steps before and after the coarse correction */
+    double cheb_ratio;   /* smoothing interval [lam_hi/ratio, lam_hi] */
+    double cheb_safety;  /* lam_hi = safety * Lanczos estimate of lambda_max(D^-1 A) */
+    int lanczos_steps;   /* Lanczos steps of that estimate */
+    double penalty_eps;  /* eps of the penalty sigma = (p+1)^2/(eps h); the paper uses 1/8 */
+    double rtol;         /* stop when ||b - A v||_2 <= rtol ||b||_2 (FP64 residual) */
+    int max_iter;        /* PCG iterations per right-hand side (inner iterations in FP32_IR) */
+    dg_precision precision;
+    double inner_rtol;   /* FP32_IR: relative tolerance of each inner solve */
+    int max_outer;       /* FP32_IR: refinement steps */
+    int check_every;     /* PCG iterations between host convergence checks */
+    int use_graph;       /* 1: replay the PCG iteration as a captured HIP graph */
+} dg_opts;
+
+typedef struct {
+    int iters;           /* PCG iterations (summed over inner solves in FP32_IR) */
+    int outer_iters;     /* refinement steps (FP32_IR), 1 for FP64 */
+    int status;          /* DG_OK or DG_WARN_NOT_CONVERGED */
+    int guess_used;      /* 1 if a caller-supplied initial guess was used */
+    double rel_residual; /* ||b - A v||_2 / ||b||_2 recomputed in FP64 at exit */
+} dg_rhs_stats;
+
+typedef struct dg_ctx dg_ctx;
+
+/* Fill *opts with the defaults: automatic levels, degree 5, ratio 20,
+ * safety 1.1, 30 Lanczos steps, eps 1/8, rtol 1e-8, 500 iterations, FP64,
+ * inner_rtol 1e-4, max_outer 8, check_every 4, use_graph 1. */
+void dg_opts_default(dg_opts* opts);
+
+/* Build the level hierarchy, operator tables, coarsest-grid eigendata and
+ * smoother bounds for each of n_meshes meshes (host arrays).  *out receives
+ * a new context.  Uses the current HIP device. */
+dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* opts, dg_ctx** out);
+void dg_poisson_destroy(dg_ctx* ctx);
+const char* dg_status_string(dg_status s);
+const char* dg_last_error(void);
+
+/* Sizes of a mesh: DOFs per field and boundary-face values per right-hand
+ * side, and the number of multigrid levels built for it (host outputs). */
+dg_status dg_mesh_info(const dg_ctx* ctx, int mesh_id, long long* n_dofs, long long* n_face, int* n_levels);
+
+/* Coordinates of the nodes (host output xyz[3][n_dofs], field order) and of
+ * the boundary-face nodes (host output fxyz[3][n_face], face order), so that
+ * a caller can sample f and g where the library expects them. */
+dg_status dg_mesh_coords(const dg_ctx* ctx, int mesh_id, double* xyz, double* fxyz);
+
+/* Solve nrhs Poisson problems.  mesh_id (host [nrhs]) names each problem's
+ * mesh.  rho: sources at the nodes (packed fields); g: Dirichlet data (packed
+ * face vectors); x0: initial guesses (packed fields) or NULL for zero;
+ * v: solutions (packed fields).  stats: host [nrhs] or NULL. */
+dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, const double* rho,
+                                 const double* g, const double* x0, double* v,
+                                 dg_rhs_stats* stats, hipStream_t stream);
+
+/* Exchange step for norb orbitals phi (packed fields [norb][n_dofs]) on one
+ * mesh (Sec. 6.1, eq. fock_poisson): for every pair i <= j the pair density
+ * rho_ij = phi_i phi_j is the source of one Poisson problem with Dirichlet
+ * data g_pairs (packed face vectors, pair order); then
+ *   W_k  = sum_s phi_s v_ks        (device [norb][n_dofs], the exchange action
+ *                                   on u = phi_k at the nodes, positive sign),
+ *   K_ij = sum_nodes w rho_ij v_ij (device [npairs], GLL quadrature),
+ *   E_x  = sum_i K_ii + 2 sum_{i<j} K_ij   (host double).
+ * v_pairs: device [npairs][n_dofs] receives the pair potentials, or NULL to
+ * keep them in context work space.  stats: host [npairs] or NULL. */
+dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* phi, const double* g_pairs,
+                            double* W, double* K_pairs, double* E_x, double* v_pairs,
+                            dg_rhs_stats* stats, hipStream_t stream);
+
+/* ---- single steps of the path, exposed for verification and profiling ----
+ * All operate on nrhs packed FP64 fields of one mesh at multigrid level
+ * `level` (0 = finest).  They return after enqueueing (no synchronisation). */
+
+/* y = A_level u (SIPDG matrix of eq. sip_bilinear at that level). */
+dg_status dg_operator_apply(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* u, double* y,
+                            hipStream_t stream);
+/* b = 4 pi M rho + boundary lift of g (finest level). */
+dg_status dg_rhs_assemble(dg_ctx* ctx, int mesh_id, int nrhs, const double* rho, const double* g, double* b,
+                          hipStream_t stream);
+/* z = B r, one V-cycle of the hp-multigrid preconditioner from `level` down. */
+dg_status dg_vcycle_apply(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* r, double* z,
+                          hipStream_t stream);
+/* Coarsest-level exact solve z = A^{-1} r (fast diagonalisation). */
+dg_status dg_coarse_solve(dg_ctx* ctx, int mesh_id, int nrhs, const double* r, double* z, hipStream_t stream);
+/* Transfers between `level` and `level`+1: rc = P^T r (restriction of a
+ * fine field) and zf += P zc (prolongation and correction). */
+dg_status dg_restrict(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* r, double* rc,
+                      hipStream_t stream);
+dg_status dg_prolong_add(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* zc, double* zf,
+                         hipStream_t stream);
+/* Smoother bounds [lam_lo, lam_hi] of a level (host outputs). */
+dg_status dg_level_info(const dg_ctx* ctx, int mesh_id, int level, int* ne, int* p, double* lam_lo,
+                        double* lam_hi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_POISSON_H */

@@ -1,0 +1,246 @@
+"""Python binding of libdgpoisson.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts
+arguments: torch tensors on the GPU provide device memory, the current torch
+stream provides the HIP stream.  If the library is missing the import fails
+loudly -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgpoisson.so")
+
+DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
+DG_PREC_FP64, DG_PREC_FP32_IR = 0, 1
+PRECISIONS = {"fp64": DG_PREC_FP64, "fp32_ir": DG_PREC_FP32_IR}
+
+
+class DgMesh(ctypes.Structure):
+    _fields_ = [("ne", ctypes.c_int * 3), ("p", ctypes.c_int),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class DgOpts(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("cheb_ratio", ctypes.c_double),
+                ("cheb_safety", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
+                ("penalty_eps", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("precision", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class DgRhsStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
+                ("guess_used", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+class DgError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2510_21213_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    sigs = {
+        "dg_opts_default": (None, [ctypes.POINTER(DgOpts)]),
+        "dg_poisson_setup": (I, [ctypes.POINTER(DgMesh), I, ctypes.POINTER(DgOpts), ctypes.POINTER(P)]),
+        "dg_poisson_destroy": (None, [P]),
+        "dg_status_string": (ctypes.c_char_p, [I]),
+        "dg_last_error": (ctypes.c_char_p, []),
+        "dg_mesh_info": (I, [P, I, ctypes.POINTER(LL), ctypes.POINTER(LL), ctypes.POINTER(I)]),
+        "dg_mesh_coords": (I, [P, I, P, P]),
+        "dg_poisson_solve_batch": (I, [P, I, P, P, P, P, P, P, P]),
+        "dg_exchange_apply": (I, [P, I, I, P, P, P, P, P, P, P, P]),
+        "dg_operator_apply": (I, [P, I, I, I, P, P, P]),
+        "dg_rhs_assemble": (I, [P, I, I, P, P, P, P]),
+        "dg_vcycle_apply": (I, [P, I, I, I, P, P, P]),
+        "dg_coarse_solve": (I, [P, I, I, P, P, P]),
+        "dg_restrict": (I, [P, I, I, I, P, P, P]),
+        "dg_prolong_add": (I, [P, I, I, I, P, P, P]),
+        "dg_level_info": (I, [P, I, I, P, P, P, P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_string(code):
+    return lib.dg_status_string(code).decode()
+
+
+def default_opts(**kw):
+    o = DgOpts()
+    lib.dg_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _check(code, what, allow_warn=False):
+    if code == DG_OK or (allow_warn and code == DG_WARN_NOT_CONVERGED):
+        return code
+    raise DgError(f"{what}: {status_string(code)} ({lib.dg_last_error().decode()})")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A set-up DG Poisson solver for one or more uniform meshes.
+
+    meshes: list of (ne, p, lo, hi) with ne, lo, hi 3-sequences.
+    options: fields of dg_opts (precision may be "fp64" or "fp32_ir").
+    """
+
+    def __init__(self, meshes, **options):
+        arr = (DgMesh * len(meshes))()
+        for k, (ne, p, lo, hi) in enumerate(meshes):
+            arr[k].ne[:] = [int(v) for v in ne]
+            arr[k].p = int(p)
+            arr[k].lo[:] = [float(v) for v in lo]
+            arr[k].hi[:] = [float(v) for v in hi]
+        self.opts = default_opts(**options)
+        h = ctypes.c_void_p()
+        _check(lib.dg_poisson_setup(arr, len(meshes), ctypes.byref(self.opts), ctypes.byref(h)), "setup")
+        self._h = h
+        self.n_meshes = len(meshes)
+        self.info = [self.mesh_info(m) for m in range(self.n_meshes)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dg_poisson_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- description
+    def mesh_info(self, mesh_id):
+        nd, nf, nl = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+        _check(lib.dg_mesh_info(self._h, mesh_id, ctypes.byref(nd), ctypes.byref(nf), ctypes.byref(nl)), "mesh_info")
+        return {"n_dofs": nd.value, "n_face": nf.value, "n_levels": nl.value}
+
+    def level_info(self, mesh_id, level):
+        ne = (ctypes.c_int * 3)()
+        p, lo, hi = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(lib.dg_level_info(self._h, mesh_id, level, ne, ctypes.byref(p), ctypes.byref(lo), ctypes.byref(hi)),
+               "level_info")
+        return {"ne": tuple(ne), "p": p.value, "lam_lo": lo.value, "lam_hi": hi.value}
+
+    def mesh_coords(self, mesh_id):
+        """(xyz [3, n_dofs], fxyz [3, n_face]) as numpy arrays."""
+        inf = self.info[mesh_id]
+        xyz = np.empty((3, inf["n_dofs"]))
+        fxyz = np.empty((3, inf["n_face"]))
+        _check(lib.dg_mesh_coords(self._h, mesh_id, xyz.ctypes.data_as(ctypes.c_void_p),
+                                  fxyz.ctypes.data_as(ctypes.c_void_p)), "mesh_coords")
+        return xyz, fxyz
+
+    # ---- solves
+    def solve_batch(self, rho, g, mesh_ids=None, x0=None, out=None):
+        """Solve the packed batch; returns (v, stats list of dicts)."""
+        nrhs = len(mesh_ids) if mesh_ids is not None else (rho.numel() // self.info[0]["n_dofs"] if rho.numel() else 0)
+        if mesh_ids is None:
+            mesh_ids = [0] * nrhs
+        ids = (ctypes.c_int * max(1, nrhs))(*mesh_ids)
+        nd = sum(self.info[m]["n_dofs"] for m in mesh_ids)
+        nf = sum(self.info[m]["n_face"] for m in mesh_ids)
+        if rho.numel() != nd or g.numel() != nf:
+            raise ValueError("rho/g sizes do not match the meshes")
+        if out is None:
+            out = torch.empty(nd, dtype=torch.float64, device=rho.device)
+        stats = (DgRhsStats * max(1, nrhs))()
+        code = lib.dg_poisson_solve_batch(self._h, nrhs, ids, _ptr(rho), _ptr(g), _ptr(x0), _ptr(out),
+                                          stats, _stream())
+        _check(code, "solve_batch", allow_warn=True)
+        return out, [_stats(stats[i]) for i in range(nrhs)]
+
+    def exchange(self, phi, g_pairs, mesh_id=0, keep_potentials=False):
+        """Returns (W, K, E_x, stats, v or None)."""
+        nd = self.info[mesh_id]["n_dofs"]
+        norb = phi.numel() // nd
+        npairs = norb * (norb + 1) // 2
+        if g_pairs.numel() != npairs * self.info[mesh_id]["n_face"]:
+            raise ValueError("g_pairs has the wrong size")
+        W = torch.empty(norb * nd, dtype=torch.float64, device=phi.device)
+        K = torch.empty(npairs, dtype=torch.float64, device=phi.device)
+        v = torch.empty(npairs * nd, dtype=torch.float64, device=phi.device) if keep_potentials else None
+        ex = ctypes.c_double()
+        stats = (DgRhsStats * npairs)()
+        code = lib.dg_exchange_apply(self._h, mesh_id, norb, _ptr(phi), _ptr(g_pairs), _ptr(W), _ptr(K),
+                                     ctypes.byref(ex), _ptr(v), stats, _stream())
+        _check(code, "exchange_apply", allow_warn=True)
+        return W, K, ex.value, [_stats(stats[i]) for i in range(npairs)], v
+
+    # ---- single steps
+    def operator_apply(self, u, mesh_id=0, level=0):
+        nrhs = u.numel() // self._level_dofs(mesh_id, level)
+        y = torch.empty_like(u)
+        _check(lib.dg_operator_apply(self._h, mesh_id, level, nrhs, _ptr(u), _ptr(y), _stream()), "operator_apply")
+        return y
+
+    def rhs_assemble(self, rho, g, mesh_id=0):
+        nrhs = rho.numel() // self.info[mesh_id]["n_dofs"]
+        b = torch.empty_like(rho)
+        _check(lib.dg_rhs_assemble(self._h, mesh_id, nrhs, _ptr(rho), _ptr(g), _ptr(b), _stream()), "rhs_assemble")
+        return b
+
+    def vcycle(self, r, mesh_id=0, level=0):
+        nrhs = r.numel() // self._level_dofs(mesh_id, level)
+        z = torch.empty_like(r)
+        _check(lib.dg_vcycle_apply(self._h, mesh_id, level, nrhs, _ptr(r), _ptr(z), _stream()), "vcycle_apply")
+        return z
+
+    def coarse_solve(self, r, mesh_id=0):
+        L = self.info[mesh_id]["n_levels"] - 1
+        nrhs = r.numel() // self._level_dofs(mesh_id, L)
+        z = torch.empty_like(r)
+        _check(lib.dg_coarse_solve(self._h, mesh_id, nrhs, _ptr(r), _ptr(z), _stream()), "coarse_solve")
+        return z
+
+    def restrict(self, r, mesh_id=0, level=0):
+        nrhs = r.numel() // self._level_dofs(mesh_id, level)
+        rc = torch.empty(nrhs * self._level_dofs(mesh_id, level + 1), dtype=torch.float64, device=r.device)
+        _check(lib.dg_restrict(self._h, mesh_id, level, nrhs, _ptr(r), _ptr(rc), _stream()), "restrict")
+        return rc
+
+    def prolong_add(self, zc, zf, mesh_id=0, level=0):
+        nrhs = zf.numel() // self._level_dofs(mesh_id, level)
+        _check(lib.dg_prolong_add(self._h, mesh_id, level, nrhs, _ptr(zc), _ptr(zf), _stream()), "prolong_add")
+        return zf
+
+    def _level_dofs(self, mesh_id, level):
+        li = self.level_info(mesh_id, level)
+        n = li["p"] + 1
+        return li["ne"][0] * li["ne"][1] * li["ne"][2] * n ** 3
+
+
+def _stats(s):
+    return {"iters": s.iters, "outer_iters": s.outer_iters, "status": s.status, "guess_used": s.guess_used,
+            "rel_residual": s.rel_residual}

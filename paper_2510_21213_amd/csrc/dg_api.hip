@@ -1,0 +1,879 @@
+// C ABI and solver driver of the DG Poisson library.
+//
+// The driver enqueues the kernels of dg_kernels.hip on the caller's stream:
+// right-hand-side assembly, batched V-cycle preconditioned conjugate
+// gradients with per-right-hand-side state kept on the device (a finished
+// right-hand side is skipped by every later kernel), and in FP32_IR mode an
+// FP64 iterative-refinement loop around an FP32 inner solve.  The host only
+// reads the per-right-hand-side state back every `check_every` iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+#include "dg_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(x)                                                                                       \
+    do {                                                                                                \
+        hipError_t e_ = (x);                                                                            \
+        if (e_ != hipSuccess)                                                                           \
+            throw HipError(std::string(#x) + ": " + hipGetErrorString(e_) + " at line " +               \
+                           std::to_string(__LINE__));                                                   \
+    } while (0)
+
+template <typename T>
+T* dalloc(long long n) {
+    void* p = nullptr;
+    if (n <= 0) n = 1;
+    HIPCHK(hipMalloc(&p, (size_t)n * sizeof(T)));
+    return (T*)p;
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+// Per-precision work space of one mesh for `cap` right-hand sides.
+template <typename T>
+struct Work {
+    std::vector<T*> f, za, zb;  // per level (f[0] unused: the PCG residual is the level-0 source)
+    T *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    int cap = 0;
+    void release() {
+        for (auto* p : f) dfree(p);
+        for (auto* p : za) dfree(p);
+        for (auto* p : zb) dfree(p);
+        f.clear(); za.clear(); zb.clear();
+        dfree(x); dfree(r); dfree(p0); dfree(p1); dfree(q);
+        cap = 0;
+    }
+};
+
+struct ChebCoef {
+    double c0;                       // first step 1/theta
+    std::vector<double> cp, cr;      // steps k = 1 .. m-1
+};
+
+}  // namespace
+
+struct dg_ctx {
+    dg_opts opts;
+    int device = 0;
+    struct Mesh {
+        dg_mesh mesh;
+        std::vector<dg::LevelHost> lv;
+        std::vector<ChebCoef> cheb;
+        dg::CoarseDev coarse;
+        dg::CoarseDev* dcoarse = nullptr;
+        int pstride = 0;
+        long long nface = 0;
+        Work<double> w64;
+        Work<float> w32;
+        double* b = nullptr;       // FP64 right-hand sides
+        double* r64 = nullptr;     // FP64 outer residual (FP32_IR)
+        double* partial = nullptr;
+        dg::RhsState* st = nullptr;      // outer / FP64 state
+        dg::RhsState* st_in = nullptr;   // inner FP32 state
+        dg::RhsState* st_host = nullptr; // pinned host mirror
+        int cap_b = 0, cap_st = 0;
+    };
+    std::vector<Mesh> meshes;
+    // exchange work space
+    double* xv = nullptr;
+    long long xv_cap = 0;
+    double* xpart = nullptr;
+    long long xpart_cap = 0;
+    int* xpairs = nullptr;
+    int xpairs_cap = 0;
+};
+
+namespace {
+
+using dg::LevelHost;
+using Mesh = dg_ctx::Mesh;
+
+void ensure_state(Mesh& M, int nrhs) {
+    if (M.cap_st >= nrhs) return;
+    dfree(M.st);
+    dfree(M.st_in);
+    if (M.st_host) (void)hipHostFree(M.st_host);
+    dfree(M.partial);
+    M.st = dalloc<dg::RhsState>(nrhs);
+    M.st_in = dalloc<dg::RhsState>(nrhs);
+    HIPCHK(hipHostMalloc((void**)&M.st_host, sizeof(dg::RhsState) * nrhs, hipHostMallocDefault));
+    M.partial = dalloc<double>((long long)nrhs * M.pstride);
+    M.cap_st = nrhs;
+}
+
+template <typename T>
+void ensure_work(Mesh& M, Work<T>& W, int nrhs) {
+    if (W.cap >= nrhs) return;
+    W.release();
+    const int L = (int)M.lv.size();
+    W.f.assign(L, nullptr);
+    W.za.assign(L, nullptr);
+    W.zb.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+        const long long n = M.lv[l].ndof * nrhs;
+        if (l > 0) W.f[l] = dalloc<T>(n);
+        W.za[l] = dalloc<T>(n);
+        W.zb[l] = dalloc<T>(n);
+    }
+    const long long n0 = M.lv[0].ndof * nrhs;
+    W.x = dalloc<T>(n0);
+    W.r = dalloc<T>(n0);
+    W.p0 = dalloc<T>(n0);
+    W.p1 = dalloc<T>(n0);
+    W.q = dalloc<T>(n0);
+    W.cap = nrhs;
+}
+
+void ensure_b(Mesh& M, int nrhs, bool need_r64) {
+    if (M.cap_b < nrhs || (need_r64 && !M.r64)) {
+        dfree(M.b);
+        dfree(M.r64);
+        M.b = dalloc<double>(M.lv[0].ndof * nrhs);
+        if (need_r64) M.r64 = dalloc<double>(M.lv[0].ndof * nrhs);
+        M.cap_b = nrhs;
+    }
+}
+
+template <typename T>
+const dg::LevelDev<T>* ldev(const LevelHost& L);
+template <>
+const dg::LevelDev<double>* ldev<double>(const LevelHost& L) { return L.dev64; }
+template <>
+const dg::LevelDev<float>* ldev<float>(const LevelHost& L) { return L.dev32; }
+
+// One V-cycle from level l: on entry f is the level-l source; if z1_ready,
+// W.za[l] already holds the first smoothing iterate c0 D^-1 f.  Returns the
+// buffer that holds z = B f.  With dot, the last smoothing step at level 0
+// also writes partial sums of f.z.
+template <typename T>
+T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T* f, bool z1_ready, bool dot,
+          hipStream_t s) {
+    const int L = (int)M.lv.size();
+    const LevelHost& Lv = M.lv[l];
+    if (l == L - 1) {
+        dg::launch_coarse<T>(M.dcoarse, Lv, nrhs, st, f, W.za[l], s);
+        return W.za[l];
+    }
+    const ChebCoef& C = M.cheb[l];
+    const int m = (int)C.cp.size() + 1;
+    const auto* dv = ldev<T>(Lv);
+    if (!z1_ready) dg::launch_cheb0<T>(Lv, dv, nrhs, st, f, W.za[l], C.c0, s);
+    T* cur = W.za[l];
+    T* prev = W.zb[l];
+    for (int k = 1; k < m; ++k) {
+        dg::launch_brick<T>(dg::BM_CHEB, Lv, dv, nrhs, st, cur, nullptr, f, k == 1 ? nullptr : prev, prev, nullptr,
+                            nullptr, 0, C.cp[k - 1], C.cr[k - 1], s);
+        std::swap(cur, prev);
+    }
+    const LevelHost& Lc = M.lv[l + 1];
+    const bool coarse_is_last = (l + 1 == L - 1);
+    dg::launch_restrict<T>(Lv, dv, Lc, ldev<T>(Lc), nrhs, st, cur, f, W.f[l + 1],
+                           coarse_is_last ? nullptr : W.za[l + 1], coarse_is_last ? 0.0 : M.cheb[l + 1].c0, s);
+    T* zc = vcycle<T>(M, W, l + 1, nrhs, st, W.f[l + 1], !coarse_is_last, false, s);
+    dg::launch_prolong<T>(Lv, Lc, nrhs, st, zc, cur, s);
+    for (int k = 0; k < m; ++k) {
+        const bool last = (k == m - 1);
+        const int mode = (dot && last) ? dg::BM_CHEBDOT : dg::BM_CHEB;
+        const double cp = k == 0 ? 0.0 : C.cp[k - 1];
+        const double cr = k == 0 ? C.c0 : C.cr[k - 1];
+        dg::launch_brick<T>(mode, Lv, dv, nrhs, st, cur, nullptr, f, k == 0 ? nullptr : prev, prev, nullptr,
+                            M.partial, M.pstride, cp, cr, s);
+        std::swap(cur, prev);
+    }
+    return cur;
+}
+
+// One PCG iteration on level 0 (vectors of W; p ping-pong by parity).
+template <typename T>
+void pcg_iteration(Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, int parity, hipStream_t s) {
+    const LevelHost& L0 = M.lv[0];
+    const auto* dv = ldev<T>(L0);
+    const int nb = dg::bricks_of(L0), nc = dg::chunks_of(L0.ndof);
+    T* z = vcycle<T>(M, W, 0, nrhs, st, W.r, true, true, s);
+    dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nb, s);
+    T* pold = parity ? W.p1 : W.p0;
+    T* pnew = parity ? W.p0 : W.p1;
+    dg::launch_brick<T>(dg::BM_PQ, L0, dv, nrhs, st, z, pold, nullptr, nullptr, W.q, pnew, M.partial, M.pstride, 0.0,
+                        0.0, s);
+    dg::launch_finalize(dg::FIN_PQ, nrhs, st, M.partial, M.pstride, nb, s);
+    dg::launch_update<T>(L0, dv, nrhs, st, W.x, W.r, pnew, W.q, W.za[0], M.cheb[0].c0, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_RR, nrhs, st, M.partial, M.pstride, nc, s);
+}
+
+void read_state(Mesh& M, const dg::RhsState* st, int nrhs, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(M.st_host, st, sizeof(dg::RhsState) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void init_state(Mesh& M, dg::RhsState* st, int nrhs, double rtol, int maxit, hipStream_t s) {
+    for (int i = 0; i < nrhs; ++i) {
+        dg::RhsState S{};
+        S.tol2 = rtol * rtol;
+        S.maxit = maxit;
+        S.active = 1;
+        S.scale = 1.0;
+        M.st_host[i] = S;
+    }
+    HIPCHK(hipMemcpyAsync(st, M.st_host, sizeof(dg::RhsState) * nrhs, hipMemcpyHostToDevice, s));
+}
+
+// PCG on level 0 from the current x and r of W (r holds the residual);
+// st must have tol2/maxit/bb set.  Returns the iterations performed.
+template <typename T>
+void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const dg::RhsState* gate,
+             hipStream_t s) {
+    const LevelHost& L0 = M.lv[0];
+    const int nc = dg::chunks_of(L0.ndof);
+    // rr and the active flags
+    dg::launch_dot<T, T>(L0.ndof, nrhs, gate, W.r, W.r, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_RR0, nrhs, st, M.partial, M.pstride, nc, s);
+    if (gate) {
+        // right-hand sides whose outer loop has finished stay inactive
+        read_state(M, gate, nrhs, s);
+        std::vector<dg::RhsState> g(M.st_host, M.st_host + nrhs);
+        read_state(M, st, nrhs, s);
+        for (int i = 0; i < nrhs; ++i)
+            if (!g[i].active) M.st_host[i].active = 0;
+        HIPCHK(hipMemcpyAsync(st, M.st_host, sizeof(dg::RhsState) * nrhs, hipMemcpyHostToDevice, s));
+    }
+    dg::launch_cheb0<T>(L0, ldev<T>(L0), nrhs, st, W.r, W.za[0], M.cheb[0].c0, s);
+    dg::launch_fill<T>(W.p0, (T)0, L0.ndof * nrhs, s);
+    dg::launch_fill<T>(W.p1, (T)0, L0.ndof * nrhs, s);
+    const int maxit = ctx->opts.max_iter;
+    const int every = std::max(1, ctx->opts.check_every);
+    int it = 0;
+    while (it < maxit) {
+        for (int c = 0; c < every && it < maxit; ++c, ++it) pcg_iteration<T>(M, W, nrhs, st, it & 1, s);
+        HIPCHK(hipGetLastError());
+        read_state(M, st, nrhs, s);
+        bool any = false;
+        for (int i = 0; i < nrhs; ++i) any |= M.st_host[i].active != 0;
+        if (!any) break;
+    }
+}
+
+void check_mesh_id(const dg_ctx* ctx, int mesh_id) {
+    if (!ctx) throw ArgError("null context");
+    if (mesh_id < 0 || mesh_id >= (int)ctx->meshes.size()) throw ArgError("mesh_id out of range");
+}
+
+// Solve nrhs problems of one mesh: b (FP64, packed) -> v.  Fills stats.
+void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* x0, double* v, dg_rhs_stats* stats,
+                 hipStream_t s) {
+    const LevelHost& L0 = M.lv[0];
+    const long long n0 = L0.ndof;
+    const int nc = dg::chunks_of(n0), nb = dg::bricks_of(L0);
+    const auto& o = ctx->opts;
+    ensure_state(M, nrhs);
+    std::vector<int> iters(nrhs, 0), outer(nrhs, 0);
+    if (o.precision == DG_PREC_FP64) {
+        ensure_work<double>(M, M.w64, nrhs);
+        Work<double>& W = M.w64;
+        init_state(M, M.st, nrhs, o.rtol, o.max_iter, s);
+        dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
+        dg::launch_finalize(dg::FIN_BB, nrhs, M.st, M.partial, M.pstride, nc, s);
+        if (x0) {
+            dg::launch_copy(x0, W.x, n0 * nrhs, s);
+            dg::launch_brick<double>(dg::BM_RESID, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr, W.r,
+                                     nullptr, nullptr, 0, 0, 0, s);
+        } else {
+            dg::launch_fill<double>(W.x, 0.0, n0 * nrhs, s);
+            dg::launch_copy(b, W.r, n0 * nrhs, s);
+        }
+        for (int restart = 0; restart < 3; ++restart) {
+            pcg_run<double>(ctx, M, W, nrhs, M.st, nullptr, s);
+            for (int i = 0; i < nrhs; ++i) iters[i] += M.st_host[i].iters;
+            // FP64 residual of the current solution
+            dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr, W.r,
+                                     nullptr, M.partial, M.pstride, 0, 0, s);
+            dg::launch_finalize(dg::FIN_TRUE, nrhs, M.st, M.partial, M.pstride, nb, s);
+            read_state(M, M.st, nrhs, s);
+            bool again = false;
+            for (int i = 0; i < nrhs; ++i) {
+                const auto& S = M.st_host[i];
+                const bool miss = S.bb > 0 && S.rr > S.tol2 * S.bb * 1.0201;  // (1.01 rtol)^2
+                again |= miss && iters[i] < o.max_iter && !S.breakdown;
+            }
+            if (!again) break;
+        }
+        for (int i = 0; i < nrhs; ++i) outer[i] = 1;
+        HIPCHK(hipMemcpyAsync(v, W.x, sizeof(double) * n0 * nrhs, hipMemcpyDeviceToDevice, s));
+    } else {
+        ensure_work<float>(M, M.w32, nrhs);
+        if (!M.r64) throw ArgError("internal: FP64 residual buffer missing");
+        Work<float>& W = M.w32;
+        init_state(M, M.st, nrhs, o.rtol, o.max_iter, s);
+        dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
+        dg::launch_finalize(dg::FIN_BB, nrhs, M.st, M.partial, M.pstride, nc, s);
+        if (x0)
+            dg::launch_copy(x0, v, n0 * nrhs, s);
+        else
+            dg::launch_fill<double>(v, 0.0, n0 * nrhs, s);
+        for (int it = 0; it < o.max_outer; ++it) {
+            dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, v, nullptr, b, nullptr, M.r64,
+                                     nullptr, M.partial, M.pstride, 0, 0, s);
+            dg::launch_finalize(dg::FIN_OUTER, nrhs, M.st, M.partial, M.pstride, nb, s);
+            read_state(M, M.st, nrhs, s);
+            bool any = false;
+            for (int i = 0; i < nrhs; ++i) {
+                any |= M.st_host[i].active != 0;
+                if (M.st_host[i].active) outer[i] += 1;
+            }
+            if (!any) break;
+            dg::launch_to_inner(n0, nrhs, M.st, M.r64, W.r, s);
+            dg::launch_fill<float>(W.x, 0.0f, n0 * nrhs, s);
+            // inner state: relative tolerance inner_rtol on ||r32|| = 1
+            for (int i = 0; i < nrhs; ++i) {
+                dg::RhsState S{};
+                S.tol2 = o.inner_rtol * o.inner_rtol;
+                S.maxit = o.max_iter;
+                S.active = 1;
+                S.bb = 1.0;
+                M.st_host[i] = S;
+            }
+            HIPCHK(hipMemcpyAsync(M.st_in, M.st_host, sizeof(dg::RhsState) * nrhs, hipMemcpyHostToDevice, s));
+            pcg_run<float>(ctx, M, W, nrhs, M.st_in, M.st, s);
+            for (int i = 0; i < nrhs; ++i) iters[i] += M.st_host[i].iters;
+            dg::launch_correct(n0, nrhs, M.st, W.x, v, s);
+        }
+        // final FP64 residual
+        dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, v, nullptr, b, nullptr, M.r64, nullptr,
+                                 M.partial, M.pstride, 0, 0, s);
+        dg::launch_finalize(dg::FIN_TRUE, nrhs, M.st, M.partial, M.pstride, nb, s);
+        read_state(M, M.st, nrhs, s);
+    }
+    HIPCHK(hipGetLastError());
+    if (stats) {
+        for (int i = 0; i < nrhs; ++i) {
+            const auto& S = M.st_host[i];
+            dg_rhs_stats& r = stats[i];
+            r.iters = iters[i];
+            r.outer_iters = outer[i];
+            r.guess_used = x0 ? 1 : 0;
+            r.rel_residual = S.bb > 0 ? std::sqrt(S.rr / S.bb) : 0.0;
+            r.status = (r.rel_residual <= o.rtol * 1.01) ? DG_OK : DG_WARN_NOT_CONVERGED;
+        }
+    }
+}
+
+void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
+    const auto& o = ctx->opts;
+    if (mesh.p < 1 || mesh.p > dg::NMAX - 1) throw ArgError("degree p must be in 1..7");
+    for (int d = 0; d < 3; ++d) {
+        if (mesh.ne[d] < 1) throw ArgError("element counts must be positive");
+        if (!(mesh.hi[d] > mesh.lo[d])) throw ArgError("box must have positive extent");
+    }
+    M.mesh = mesh;
+    auto specs = dg::hierarchy(mesh.ne, mesh.p, o.n_levels);
+    if (specs.size() < 2) {
+        // a single level would need the exact solve on the fine mesh; add a degree or mesh step when possible
+        throw ArgError("mesh too small for a multigrid hierarchy (needs at least two levels)");
+    }
+    for (auto& [E, p] : specs) {
+        LevelHost L;
+        for (int d = 0; d < 3; ++d) {
+            L.E[d] = E[d];
+            L.h[d] = (mesh.hi[d] - mesh.lo[d]) / E[d];
+            L.lo[d] = mesh.lo[d];
+        }
+        L.p = p;
+        L.n = p + 1;
+        L.ndof = (long long)E[0] * E[1] * E[2] * L.n * L.n * L.n;
+        L.be = dg::brick_edge(L.n);
+        for (int d = 0; d < 3; ++d) L.nbr[d] = (E[d] + L.be - 1) / L.be;
+        for (int d = 0; d < 3; ++d) {
+            dg::build_axis(E[d], p, mesh.lo[d], mesh.hi[d], o.penalty_eps, L.d64.ax[d], nullptr, nullptr);
+            auto& a = L.d64.ax[d];
+            auto& f = L.d32.ax[d];
+            std::memset(&f, 0, sizeof(f));
+            for (int t = 0; t < 4; ++t)
+                for (int i = 0; i < dg::NMAX; ++i) {
+                    for (int j = 0; j < dg::NMAX; ++j) f.B[t][i][j] = (float)a.B[t][i][j];
+                    f.Bd[t][i] = (float)a.Bd[t][i];
+                }
+            for (int i = 0; i < dg::NMAX; ++i) {
+                f.dL[i] = (float)a.dL[i];
+                f.dR[i] = (float)a.dR[i];
+                f.m[i] = (float)a.m[i];
+                f.liftL[i] = (float)a.liftL[i];
+                f.liftR[i] = (float)a.liftR[i];
+            }
+            f.sigma = (float)a.sigma;
+            f.E = a.E;
+        }
+        M.lv.push_back(L);
+    }
+    const int nl = (int)M.lv.size();
+    for (int l = 0; l + 1 < nl; ++l) {
+        LevelHost& F = M.lv[l];
+        const LevelHost& C = M.lv[l + 1];
+        F.hcoarse = F.E[0] != C.E[0];
+        if (F.hcoarse && (F.be % 2 || F.n != 2 || C.n != 2)) throw ArgError("mesh coarsening only at p = 1");
+        dg::build_transfer(F, C, F.tr);
+    }
+    dg::build_coarse(M.lv.back(), o.penalty_eps, M.coarse);
+    // device copies
+    for (auto& L : M.lv) {
+        L.dev64 = dalloc<dg::LevelDev<double>>(1);
+        L.dev32 = dalloc<dg::LevelDev<float>>(1);
+        HIPCHK(hipMemcpy(L.dev64, &L.d64, sizeof(L.d64), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(L.dev32, &L.d32, sizeof(L.d32), hipMemcpyHostToDevice));
+        L.devtr = dalloc<dg::TransferDev>(1);
+        HIPCHK(hipMemcpy(L.devtr, &L.tr, sizeof(L.tr), hipMemcpyHostToDevice));
+    }
+    M.dcoarse = dalloc<dg::CoarseDev>(1);
+    HIPCHK(hipMemcpy(M.dcoarse, &M.coarse, sizeof(M.coarse), hipMemcpyHostToDevice));
+    int ps = dg::chunks_of(M.lv[0].ndof);
+    for (auto& L : M.lv) ps = std::max(ps, dg::bricks_of(L));
+    M.pstride = ps;
+    const int NX = mesh.ne[0] * (mesh.p + 1), NY = mesh.ne[1] * (mesh.p + 1), NZ = mesh.ne[2] * (mesh.p + 1);
+    M.nface = 2LL * ((long long)NY * NZ + (long long)NX * NZ + (long long)NX * NY);
+
+    // smoother bounds: Lanczos on D^-1/2 A D^-1/2 per level (single vector)
+    M.cheb.resize(nl);
+    for (int l = 0; l + 1 < nl; ++l) {
+        LevelHost& L = M.lv[l];
+        const long long n = L.ndof;
+        std::vector<double> h(n);
+        double nrm = 0.0;
+        for (long long i = 0; i < n; ++i) {
+            uint32_t v = (uint32_t)((uint64_t)i * 2654435761ull + 12345ull);
+            h[i] = (double)v / 4294967296.0 - 0.5;
+            nrm += h[i] * h[i];
+        }
+        nrm = std::sqrt(nrm);
+        for (auto& x : h) x /= nrm;
+        double *v = dalloc<double>(n), *vp = dalloc<double>(n), *w = dalloc<double>(n), *tmp = dalloc<double>(n);
+        double* part = dalloc<double>(dg::chunks_of(n));
+        HIPCHK(hipMemcpy(v, h.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+        dg::launch_fill<double>(vp, 0.0, n, s);
+        std::vector<double> alphas, betas, hp(dg::chunks_of(n));
+        auto dot = [&](const double* a, const double* b) {
+            dg::launch_dot<double, double>(n, 1, nullptr, a, b, part, dg::chunks_of(n), s);
+            HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            double acc = 0.0;
+            for (double x : hp) acc += x;
+            return acc;
+        };
+        double beta = 0.0;
+        const int steps = (int)std::min<long long>(o.lanczos_steps, n);
+        for (int k = 0; k < steps; ++k) {
+            dg::launch_dscale(L, L.dev64, v, tmp, s);
+            dg::launch_brick<double>(dg::BM_APPLY, L, L.dev64, 1, nullptr, tmp, nullptr, nullptr, nullptr, w, nullptr,
+                                     nullptr, 0, 0, 0, s);
+            dg::launch_dscale(L, L.dev64, w, w, s);
+            dg::launch_axpby(n, -beta, vp, 1.0, w, s);
+            const double alpha = dot(w, v);
+            dg::launch_axpby(n, -alpha, v, 1.0, w, s);
+            alphas.push_back(alpha);
+            beta = std::sqrt(std::max(0.0, dot(w, w)));
+            if (k == steps - 1 || beta == 0.0) break;
+            betas.push_back(beta);
+            std::swap(v, vp);          // vp <- v (old)
+            dg::launch_copy(w, v, n, s);
+            dg::launch_axpby(n, 0.0, w, 1.0 / beta, v, s);  // v = w / beta
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipGetLastError());
+        dfree(v); dfree(vp); dfree(w); dfree(tmp); dfree(part);
+        betas.resize(alphas.size() > 0 ? alphas.size() - 1 : 0);
+        const double lmax = dg::tridiag_max_eig(alphas, betas);
+        L.lam_hi = o.cheb_safety * lmax;
+        L.lam_lo = L.lam_hi / o.cheb_ratio;
+        const double theta = 0.5 * (L.lam_hi + L.lam_lo), delta = 0.5 * (L.lam_hi - L.lam_lo);
+        const double sigma1 = theta / delta;
+        ChebCoef C;
+        C.c0 = 1.0 / theta;
+        double rho = 1.0 / sigma1;
+        for (int k = 1; k < o.cheb_degree; ++k) {
+            const double rn = 1.0 / (2.0 * sigma1 - rho);
+            C.cp.push_back(rn * rho);
+            C.cr.push_back(2.0 * rn / delta);
+            rho = rn;
+        }
+        M.cheb[l] = C;
+    }
+}
+
+}  // namespace
+
+namespace {
+dg_status run_guarded(const std::function<void()>& fn) {
+    try {
+        fn();
+        return DG_OK;
+    } catch (const ArgError& e) {
+        set_err("%s", e.what());
+        return DG_ERR_ARG;
+    } catch (const HipError& e) {
+        set_err("%s", e.what());
+        return DG_ERR_HIP;
+    } catch (const std::bad_alloc&) {
+        set_err("host allocation failed");
+        return DG_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_err("%s", e.what());
+        return DG_ERR_ARG;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+void dg_opts_default(dg_opts* o) {
+    if (!o) return;
+    o->n_levels = 0;
+    o->cheb_degree = 5;
+    o->cheb_ratio = 20.0;
+    o->cheb_safety = 1.1;
+    o->lanczos_steps = 30;
+    o->penalty_eps = 0.125;
+    o->rtol = 1e-8;
+    o->max_iter = 500;
+    o->precision = DG_PREC_FP64;
+    o->inner_rtol = 1e-4;
+    o->max_outer = 8;
+    o->check_every = 4;
+    o->use_graph = 1;
+}
+
+const char* dg_status_string(dg_status s) {
+    switch (s) {
+        case DG_OK: return "ok";
+        case DG_WARN_NOT_CONVERGED: return "not converged";
+        case DG_ERR_ARG: return "invalid argument";
+        case DG_ERR_HIP: return "HIP runtime error";
+        case DG_ERR_OOM: return "out of memory";
+        case DG_ERR_BREAKDOWN: return "CG breakdown";
+        case DG_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+
+dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* opts, dg_ctx** out) {
+    return run_guarded([&] {
+        if (!meshes || n_meshes < 1 || !out) throw ArgError("need at least one mesh and an output pointer");
+        auto ctx = std::make_unique<dg_ctx>();
+        if (opts)
+            ctx->opts = *opts;
+        else
+            dg_opts_default(&ctx->opts);
+        const auto& o = ctx->opts;
+        if (o.cheb_degree < 1 || o.cheb_ratio <= 1.0 || o.cheb_safety < 1.0 || o.lanczos_steps < 2 ||
+            o.penalty_eps <= 0 || o.rtol <= 0 || o.max_iter < 1 || o.max_outer < 1 || o.inner_rtol <= 0 ||
+            o.inner_rtol >= 1)
+            throw ArgError("invalid solver options");
+        HIPCHK(hipGetDevice(&ctx->device));
+        hipStream_t s = nullptr;
+        ctx->meshes.resize(n_meshes);
+        for (int i = 0; i < n_meshes; ++i) setup_mesh(ctx.get(), meshes[i], ctx->meshes[i], s);
+        HIPCHK(hipDeviceSynchronize());
+        *out = ctx.release();
+    });
+}
+
+void dg_poisson_destroy(dg_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    for (auto& M : ctx->meshes) {
+        for (auto& L : M.lv) {
+            dfree(L.dev64);
+            dfree(L.dev32);
+            dfree(L.devtr);
+        }
+        dfree(M.dcoarse);
+        M.w64.release();
+        M.w32.release();
+        dfree(M.b);
+        dfree(M.r64);
+        dfree(M.partial);
+        dfree(M.st);
+        dfree(M.st_in);
+        if (M.st_host) (void)hipHostFree(M.st_host);
+    }
+    dfree(ctx->xv);
+    dfree(ctx->xpart);
+    dfree(ctx->xpairs);
+    delete ctx;
+}
+
+dg_status dg_mesh_info(const dg_ctx* ctx, int mesh_id, long long* n_dofs, long long* n_face, int* n_levels) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        const auto& M = ctx->meshes[mesh_id];
+        if (n_dofs) *n_dofs = M.lv[0].ndof;
+        if (n_face) *n_face = M.nface;
+        if (n_levels) *n_levels = (int)M.lv.size();
+    });
+}
+
+dg_status dg_level_info(const dg_ctx* ctx, int mesh_id, int level, int* ne, int* p, double* lam_lo, double* lam_hi) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        const auto& M = ctx->meshes[mesh_id];
+        if (level < 0 || level >= (int)M.lv.size()) throw ArgError("level out of range");
+        const auto& L = M.lv[level];
+        if (ne) for (int d = 0; d < 3; ++d) ne[d] = L.E[d];
+        if (p) *p = L.p;
+        if (lam_lo) *lam_lo = L.lam_lo;
+        if (lam_hi) *lam_hi = L.lam_hi;
+    });
+}
+
+dg_status dg_mesh_coords(const dg_ctx* ctx, int mesh_id, double* xyz, double* fxyz) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        const auto& M = ctx->meshes[mesh_id];
+        const auto& m = M.mesh;
+        const int n = m.p + 1;
+        std::vector<double> nodes[3];
+        for (int d = 0; d < 3; ++d) {
+            dg::AxisDev<double> ax;
+            dg::build_axis(m.ne[d], m.p, m.lo[d], m.hi[d], ctx->opts.penalty_eps, ax, nullptr, &nodes[d]);
+        }
+        const long long ndof = M.lv[0].ndof;
+        if (xyz) {
+            for (long long q = 0; q < ndof; ++q) {
+                const long long e = q / (n * n * n);
+                const int l = (int)(q % (n * n * n));
+                const int ex = (int)(e % m.ne[0]), ey = (int)((e / m.ne[0]) % m.ne[1]), ez = (int)(e / (m.ne[0] * m.ne[1]));
+                const int i = l % n, j = (l / n) % n, k = l / (n * n);
+                xyz[q] = nodes[0][ex * n + i];
+                xyz[ndof + q] = nodes[1][ey * n + j];
+                xyz[2 * ndof + q] = nodes[2][ez * n + k];
+            }
+        }
+        if (fxyz) {
+            const int NX = m.ne[0] * n, NY = m.ne[1] * n, NZ = m.ne[2] * n;
+            const long long nf = M.nface;
+            long long o = 0;
+            auto put = [&](double x, double y, double z) {
+                fxyz[o] = x;
+                fxyz[nf + o] = y;
+                fxyz[2 * nf + o] = z;
+                ++o;
+            };
+            for (int side = 0; side < 2; ++side)  // x faces [Z][Y]
+                for (int Z = 0; Z < NZ; ++Z)
+                    for (int Y = 0; Y < NY; ++Y) put(side ? m.hi[0] : m.lo[0], nodes[1][Y], nodes[2][Z]);
+            for (int side = 0; side < 2; ++side)  // y faces [Z][X]
+                for (int Z = 0; Z < NZ; ++Z)
+                    for (int X = 0; X < NX; ++X) put(nodes[0][X], side ? m.hi[1] : m.lo[1], nodes[2][Z]);
+            for (int side = 0; side < 2; ++side)  // z faces [Y][X]
+                for (int Y = 0; Y < NY; ++Y)
+                    for (int X = 0; X < NX; ++X) put(nodes[0][X], nodes[1][Y], side ? m.hi[2] : m.lo[2]);
+        }
+    });
+}
+
+dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, const double* rho, const double* g,
+                                 const double* x0, double* v, dg_rhs_stats* stats, hipStream_t stream) {
+    dg_status st = run_guarded([&] {
+        if (!ctx) throw ArgError("null context");
+        if (nrhs < 0) throw ArgError("nrhs must be >= 0");
+        if (nrhs == 0) return;
+        if (!mesh_id || !rho || !g || !v) throw ArgError("null pointer argument");
+        // group consecutive right-hand sides by mesh, keeping the caller's packing
+        std::vector<long long> off(nrhs + 1, 0), foff(nrhs + 1, 0);
+        for (int i = 0; i < nrhs; ++i) {
+            check_mesh_id(ctx, mesh_id[i]);
+            off[i + 1] = off[i] + ctx->meshes[mesh_id[i]].lv[0].ndof;
+            foff[i + 1] = foff[i] + ctx->meshes[mesh_id[i]].nface;
+        }
+        int i = 0;
+        while (i < nrhs) {
+            int j = i;
+            while (j < nrhs && mesh_id[j] == mesh_id[i]) ++j;
+            Mesh& M = ctx->meshes[mesh_id[i]];
+            const int cnt = j - i;
+            ensure_b(M, cnt, ctx->opts.precision == DG_PREC_FP32_IR);
+            dg::launch_rhs(M.lv[0], M.lv[0].dev64, cnt, rho + off[i], nullptr, nullptr, nullptr, g + foff[i], M.nface,
+                           M.b, stream);
+            solve_group(ctx, M, cnt, M.b, x0 ? x0 + off[i] : nullptr, v + off[i], stats ? stats + i : nullptr, stream);
+            i = j;
+        }
+        HIPCHK(hipStreamSynchronize(stream));
+    });
+    if (st == DG_OK && stats)
+        for (int i = 0; i < nrhs; ++i)
+            if (stats[i].status != DG_OK) return DG_WARN_NOT_CONVERGED;
+    return st;
+}
+
+dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* phi, const double* g_pairs, double* W,
+                            double* K_pairs, double* E_x, double* v_pairs, dg_rhs_stats* stats, hipStream_t stream) {
+    dg_status st = run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        if (norb < 1 || norb > 32) throw ArgError("norb must be in 1..32");
+        if (!phi || !g_pairs || !W || !K_pairs) throw ArgError("null pointer argument");
+        Mesh& M = ctx->meshes[mesh_id];
+        const int npairs = norb * (norb + 1) / 2;
+        const long long n0 = M.lv[0].ndof;
+        std::vector<int> hp(2 * npairs);
+        int q = 0;
+        for (int i = 0; i < norb; ++i)
+            for (int j = i; j < norb; ++j, ++q) {
+                hp[q] = i;
+                hp[npairs + q] = j;
+            }
+        if (ctx->xpairs_cap < 2 * npairs) {
+            dfree(ctx->xpairs);
+            ctx->xpairs = dalloc<int>(2 * npairs);
+            ctx->xpairs_cap = 2 * npairs;
+        }
+        HIPCHK(hipMemcpyAsync(ctx->xpairs, hp.data(), sizeof(int) * 2 * npairs, hipMemcpyHostToDevice, stream));
+        double* v = v_pairs;
+        if (!v) {
+            if (ctx->xv_cap < n0 * npairs) {
+                dfree(ctx->xv);
+                ctx->xv = dalloc<double>(n0 * npairs);
+                ctx->xv_cap = n0 * npairs;
+            }
+            v = ctx->xv;
+        }
+        ensure_b(M, npairs, ctx->opts.precision == DG_PREC_FP32_IR);
+        dg::launch_rhs(M.lv[0], M.lv[0].dev64, npairs, nullptr, phi, ctx->xpairs, ctx->xpairs + npairs, g_pairs,
+                       M.nface, M.b, stream);
+        solve_group(ctx, M, npairs, M.b, nullptr, v, stats, stream);
+        const int nblk = (int)((n0 + 255) / 256);
+        if (ctx->xpart_cap < (long long)npairs * nblk) {
+            dfree(ctx->xpart);
+            ctx->xpart = dalloc<double>((long long)npairs * nblk);
+            ctx->xpart_cap = (long long)npairs * nblk;
+        }
+        dg::launch_exchange(M.lv[0], M.lv[0].dev64, norb, phi, v, W, ctx->xpart, nblk, stream);
+        dg::launch_sum_partials(npairs, ctx->xpart, nblk, nblk, K_pairs, stream);
+        std::vector<double> K(npairs);
+        HIPCHK(hipMemcpyAsync(K.data(), K_pairs, sizeof(double) * npairs, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        HIPCHK(hipGetLastError());
+        double ex = 0.0;
+        q = 0;
+        for (int i = 0; i < norb; ++i)
+            for (int j = i; j < norb; ++j, ++q) ex += (i == j ? 1.0 : 2.0) * K[q];
+        if (E_x) *E_x = ex;
+    });
+    if (st == DG_OK && stats) {
+        const int npairs = norb * (norb + 1) / 2;
+        for (int i = 0; i < npairs; ++i)
+            if (stats[i].status != DG_OK) return DG_WARN_NOT_CONVERGED;
+    }
+    return st;
+}
+
+dg_status dg_operator_apply(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* u, double* y,
+                            hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (level < 0 || level >= (int)M.lv.size()) throw ArgError("level out of range");
+        if (nrhs < 0 || (nrhs > 0 && (!u || !y))) throw ArgError("bad arguments");
+        const auto& L = M.lv[level];
+        dg::launch_brick<double>(dg::BM_APPLY, L, L.dev64, nrhs, nullptr, u, nullptr, nullptr, nullptr, y, nullptr,
+                                 nullptr, 0, 0, 0, stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_rhs_assemble(dg_ctx* ctx, int mesh_id, int nrhs, const double* rho, const double* g, double* b,
+                          hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (nrhs < 0 || (nrhs > 0 && (!rho || !g || !b))) throw ArgError("bad arguments");
+        dg::launch_rhs(M.lv[0], M.lv[0].dev64, nrhs, rho, nullptr, nullptr, nullptr, g, M.nface, b, stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_vcycle_apply(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* r, double* z,
+                          hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (level < 0 || level >= (int)M.lv.size()) throw ArgError("level out of range");
+        if (nrhs < 0 || (nrhs > 0 && (!r || !z))) throw ArgError("bad arguments");
+        if (nrhs == 0) return;
+        ensure_state(M, nrhs);
+        ensure_work<double>(M, M.w64, nrhs);
+        double* out = vcycle<double>(M, M.w64, level, nrhs, nullptr, r, false, false, stream);
+        HIPCHK(hipMemcpyAsync(z, out, sizeof(double) * M.lv[level].ndof * nrhs, hipMemcpyDeviceToDevice, stream));
+        HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_coarse_solve(dg_ctx* ctx, int mesh_id, int nrhs, const double* r, double* z, hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (nrhs < 0 || (nrhs > 0 && (!r || !z))) throw ArgError("bad arguments");
+        dg::launch_coarse<double>(M.dcoarse, M.lv.back(), nrhs, nullptr, r, z, stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_restrict(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* r, double* rc,
+                      hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (level < 0 || level + 1 >= (int)M.lv.size()) throw ArgError("level out of range");
+        if (nrhs < 0 || (nrhs > 0 && (!r || !rc))) throw ArgError("bad arguments");
+        const auto& F = M.lv[level];
+        const auto& C = M.lv[level + 1];
+        dg::launch_restrict<double>(F, F.dev64, C, C.dev64, nrhs, nullptr, nullptr, r, rc, nullptr, 0.0, stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_prolong_add(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* zc, double* zf,
+                         hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (level < 0 || level + 1 >= (int)M.lv.size()) throw ArgError("level out of range");
+        if (nrhs < 0 || (nrhs > 0 && (!zc || !zf))) throw ArgError("bad arguments");
+        dg::launch_prolong<double>(M.lv[level], M.lv[level + 1], nrhs, nullptr, zc, zf, stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+}  // extern "C"

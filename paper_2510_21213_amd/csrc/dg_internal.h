@@ -1,0 +1,107 @@
+// Internal declarations shared by the host set-up code, the kernels and the
+// C ABI of the DG Poisson library.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dg_poisson.h"
+
+namespace dg {
+
+constexpr int NMAX = 8;        // nodes per element edge (p <= 7)
+constexpr int NBMAX = 16;      // nodes per brick edge
+constexpr int CMAX = 16;       // coarsest level: nodes per axis
+
+// One coordinate direction of one multigrid level, in the precision T of the
+// kernels that read it.  Element blocks are indexed by the position type
+// t = (left boundary ? 1 : 0) | (right boundary ? 2 : 0).
+template <typename T>
+struct AxisDev {
+    T B[4][NMAX][NMAX];  // diagonal 1D block of an element (volume + own-face terms)
+    T Bd[4][NMAX];       // diagonal of B
+    T dL[NMAX];          // u -> u'(left end of the element)
+    T dR[NMAX];          // u -> u'(right end of the element)
+    T m[NMAX];           // lumped GLL mass J*w
+    T liftL[NMAX];       // boundary lift of the left boundary element
+    T liftR[NMAX];       // boundary lift of the right boundary element
+    T sigma;             // penalty of this level along this axis
+    int E;               // elements along this axis
+    int pad;
+};
+
+template <typename T>
+struct LevelDev {
+    AxisDev<T> ax[3];
+};
+
+// Brick-level 1D transfer between a level and the next coarser one:
+// P[a][b] maps coarse brick node b to fine brick node a.
+struct TransferDev {
+    double P[NBMAX][NBMAX];
+    float Pf[NBMAX][NBMAX];
+};
+
+// Coarsest level exact solve: S = M^{-1/2}, S A1 S = Q diag(lam) Q^T per axis.
+struct CoarseDev {
+    double Q[3][CMAX][CMAX];
+    double lam[3][CMAX];
+    double s[3][CMAX];
+    int n[3];      // nodes per axis
+    int E[3];      // elements per axis
+    int N;         // nodes per element edge
+    int pad;
+};
+
+// Per right-hand-side iteration state (device).
+struct RhsState {
+    double bb;      // ||b||^2
+    double rz;      // r.z of this iteration
+    double rz_old;  // r.z of the previous iteration
+    double pq;      // p.Ap
+    double rr;      // r.r
+    double alpha, beta;
+    double tol2;    // (rtol)^2
+    double scale;   // iterative refinement: ||r_outer||
+    int active;     // 1 while iterating
+    int iters;      // completed iterations
+    int maxit;
+    int breakdown;
+};
+
+// Host description of one level.
+struct LevelHost {
+    int E[3];
+    int p, n;
+    double h[3], lo[3];
+    long long ndof;
+    double lam_lo = 0, lam_hi = 0;
+    LevelDev<double> d64;
+    LevelDev<float> d32;
+    LevelDev<double>* dev64 = nullptr;  // device copies
+    LevelDev<float>* dev32 = nullptr;
+    // transfer to the next coarser level (unused on the coarsest)
+    bool hcoarse = false;
+    TransferDev tr;
+    TransferDev* devtr = nullptr;
+    int nbr[3];      // bricks per axis
+    int be;          // elements per brick edge
+};
+
+// Host-side numerics (dg_setup.cpp).
+void gll(int p, std::vector<double>& xi, std::vector<double>& w, std::vector<double>& D);
+void lagrange_eval(const std::vector<double>& nodes, const std::vector<double>& x, std::vector<double>& L);
+void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V);
+void build_axis(int E, int p, double lo, double hi, double eps, AxisDev<double>& ax, std::vector<double>* dense,
+                std::vector<double>* nodes);
+int brick_edge(int n);
+std::vector<std::pair<std::array<int, 3>, int>> hierarchy(const int E[3], int p, int n_levels);
+void build_transfer(const LevelHost& fine, const LevelHost& coarse, TransferDev& tr);
+void build_coarse(const LevelHost& L, double eps, CoarseDev& c);
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b);
+
+}  // namespace dg

@@ -1,0 +1,98 @@
+// Kernel launchers of the DG Poisson library (host-callable, internal).
+#pragma once
+
+#include "dg_internal.h"
+
+namespace dg {
+
+// Epilogues of the brick operator kernel.
+enum BrickMode {
+    BM_APPLY = 0,    // out = A u
+    BM_RESID = 1,    // out = f - A u
+    BM_CHEB = 2,     // out = u + cp (u - zprev) + cr D^-1 (f - A u)
+    BM_CHEBDOT = 3,  // BM_CHEB and partial sums of f.out
+    BM_PQ = 4,       // w = u + beta u2; out2 = w; out = A w; partial sums of w.out
+    BM_RESIDDOT = 5  // BM_RESID and partial sums of out.out
+};
+
+enum FinalizeWhat {
+    FIN_BB = 0,    // bb = s
+    FIN_RR0 = 1,   // rr = s; active = rr > tol2 bb (start of an iteration)
+    FIN_RZ = 2,    // beta = rz/rz_old (0 on the first iteration); rz = s
+    FIN_PQ = 3,    // alpha = rz/s (breakdown if s <= 0)
+    FIN_RR = 4,    // rr = s; iters++; active = rr > tol2 bb and iters < maxit
+    FIN_TRUE = 5,  // rr_true = s (FP64 residual of the returned solution)
+    FIN_OUTER = 6  // outer refinement: rr = s; scale = sqrt(s); active = rr > tol2 bb
+};
+
+struct KernelCfg {
+    int bricks_per_rhs;  // partial-sum slots of brick kernels
+    int chunks_per_rhs;  // partial-sum slots of pointwise kernels
+};
+
+inline int chunks_of(long long ndof) { return (int)((ndof + 1023) / 1024); }
+inline int bricks_of(const LevelHost& L) { return L.nbr[0] * L.nbr[1] * L.nbr[2]; }
+
+template <typename T>
+void launch_brick(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, const T* u,
+                  const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial, int pstride, double cp,
+                  double cr, hipStream_t s);
+
+// fc = P^T (f - A z) (z may be null: fc = P^T f); optionally z1c = c0c Dc^-1 fc.
+template <typename T>
+void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHost& Lc, const LevelDev<T>* devc,
+                     int nrhs, const RhsState* st, const T* z, const T* f, T* fc, T* z1c, double c0c, hipStream_t s);
+
+// zf += P zc
+template <typename T>
+void launch_prolong(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st, const T* zc, T* zf,
+                    hipStream_t s);
+
+// z = A^-1 r on the coarsest level (FP64 arithmetic for any storage type).
+template <typename T>
+void launch_coarse(const CoarseDev* C, const LevelHost& L, int nrhs, const RhsState* st, const T* r, T* z,
+                   hipStream_t s);
+
+// z = c0 D^-1 f
+template <typename T>
+void launch_cheb0(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, const T* f, T* z,
+                  double c0, hipStream_t s);
+
+// x += alpha p; r -= alpha q; partial sums of r.r; optionally z1 = c0 D^-1 r.
+template <typename T>
+void launch_update(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, T* x, T* r, const T* p,
+                   const T* q, T* z1, double c0, double* partial, int pstride, hipStream_t s);
+
+// partial sums of a.b per right-hand side (FP64 accumulation).
+template <typename TA, typename TB>
+void launch_dot(long long ndof, int nrhs, const RhsState* st, const TA* a, const TB* b, double* partial,
+                int pstride, hipStream_t s);
+
+void launch_finalize(int what, int nrhs, RhsState* st, const double* partial, int pstride, int nblk,
+                     hipStream_t s);
+
+// b = 4 pi M rho + lift(g).  If phi is non-null, rho of right-hand side q is
+// phi[pi[q]] * phi[pj[q]] (pair densities) and rho is ignored.
+void launch_rhs(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const double* rho, const double* phi,
+                const int* pi, const int* pj, const double* g, long long nface, double* b, hipStream_t s);
+
+// Iterative refinement: r32 = r64 / st.scale, and x64 += st.scale * d32.
+void launch_to_inner(long long ndof, int nrhs, const RhsState* st, const double* r64, float* r32, hipStream_t s);
+void launch_correct(long long ndof, int nrhs, const RhsState* st, const float* d32, double* x64, hipStream_t s);
+
+// Fill / copy / scale helpers.
+template <typename T>
+void launch_fill(T* x, T v, long long n, hipStream_t s);
+void launch_copy(const double* a, double* b, long long n, hipStream_t s);
+// y[i] = x[i] * D(i)^-1/2 of the level (Lanczos set-up), per right-hand side 0 only.
+void launch_dscale(const LevelHost& L, const LevelDev<double>* dev, const double* x, double* y, hipStream_t s);
+// y = a x + b y  (single vector)
+void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t s);
+
+// Exchange: W_k = sum_s phi_s v_ks; partial sums of w rho_ij v_ij per pair.
+void launch_exchange(const LevelHost& L, const LevelDev<double>* dev, int norb, const double* phi, const double* v,
+                     double* W, double* partial, int pstride, hipStream_t s);
+// K[q] = sum of partial[q][0..nblk-1] (fixed order).
+void launch_sum_partials(int nq, const double* partial, int pstride, int nblk, double* K, hipStream_t s);
+
+}  // namespace dg

@@ -1,0 +1,1170 @@
+// HIP kernels of the DG Poisson library for gfx950 (CDNA4, wave64).
+//
+// Operator.  On a uniform hexahedral mesh the SIPDG matrix of eq.
+// (sip_bilinear) with GLL collocation is the Kronecker sum
+//     A = A1x (x) My (x) Mz + Mx (x) A1y (x) Mz + Mx (x) My (x) A1z
+// (the penalty acts along the face normal only).  Each 1D matrix A1 is
+// block-tridiagonal: an element's diagonal block B_t (local stiffness plus
+// the own-element parts of the face terms; t marks boundary elements, which
+// carry the Nitsche terms) and a rank-2 coupling to each neighbour that needs
+// only the neighbour's face value and face normal derivative.  For the right
+// neighbour (value u0 and derivative d0 at its left end)
+//     y_e += e_R (-d0/2 - sigma u0) + d_R (u0/2),
+// and for the left neighbour (value up and derivative dp at its right end)
+//     y_e += e_L ( dp/2 - sigma up) - d_L (up/2).
+//
+// Tiling.  A work-group owns a brick of BE^3 elements (NB = BE*N nodes per
+// edge) of one right-hand side.  The brick is staged in LDS; the x and y
+// axis terms are computed by one thread per brick row, the z term by one
+// thread per brick column that keeps its column in registers.  Neighbour
+// elements outside the brick are read straight from global memory (they are
+// the face halo; the L2 of the XCD serves them).  Work-group indices are
+// remapped so that each XCD receives a contiguous range of bricks.
+//
+// Reductions are deterministic: every work-group writes one partial sum to a
+// fixed slot and a second kernel adds the slots in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "dg_kernels.h"
+
+namespace dg {
+
+// ---------------------------------------------------------------------------
+// helpers
+
+// Work-group w of G is dispatched to XCD w % 8; give XCD x the contiguous
+// logical range [start_x, start_x + count_x).
+__device__ __forceinline__ int xcd_remap(int w, int G) {
+    constexpr int NX = 8;
+    if (G < NX) return w;
+    const int x = w % NX, slot = w / NX;
+    const int base = G / NX, rem = G % NX;
+    return x * base + min(x, rem) + slot;
+}
+
+__device__ __forceinline__ int etype(int e, int E) { return (e == 0 ? 1 : 0) | (e == E - 1 ? 2 : 0); }
+
+template <int WG>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < WG / 64; ++i) s += red[i];
+    }
+    return s;  // valid in thread 0
+}
+
+constexpr int wg_of(int nt) { return ((nt + 63) / 64) * 64; }
+
+template <int N>
+constexpr int be_of() { return N <= 3 ? 4 : (N <= 6 ? 2 : 1); }
+
+// One axis of the operator over a brick row of NB = BE*N values (elements
+// e0 .. e0+BE-1).  hl*: face value / derivative of element e0-1 at its right
+// end; hr*: of element e0+BE at its left end (only read when they exist).
+template <typename T, int N, int BE>
+__device__ __forceinline__ void axis_row(const AxisDev<T>& A, int e0, int E, const T* row, T hlu, T hld, T hru,
+                                         T hrd, T* out) {
+    const T sg = A.sigma;
+    const T half = (T)0.5;
+#pragma unroll
+    for (int b = 0; b < BE; ++b) {
+        const int e = e0 + b;
+        if (e < E) {
+            const int t = etype(e, E);
+            T acc[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T s = 0;
+#pragma unroll
+                for (int l = 0; l < N; ++l) s += A.B[t][i][l] * row[b * N + l];
+                acc[i] = s;
+            }
+            if (e > 0) {
+                T up, dp;
+                if (b > 0) {
+                    up = row[b * N - 1];
+                    dp = 0;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) dp += A.dR[l] * row[(b - 1) * N + l];
+                } else {
+                    up = hlu;
+                    dp = hld;
+                }
+                acc[0] += half * dp - sg * up;
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc[i] -= half * A.dL[i] * up;
+            }
+            if (e < E - 1) {
+                T u0, d0;
+                if (b < BE - 1) {
+                    u0 = row[(b + 1) * N];
+                    d0 = 0;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) d0 += A.dL[l] * row[(b + 1) * N + l];
+                } else {
+                    u0 = hru;
+                    d0 = hrd;
+                }
+                acc[N - 1] += -half * d0 - sg * u0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc[i] += half * A.dR[i] * u0;
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) out[b * N + i] = acc[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) out[b * N + i] = 0;
+        }
+    }
+}
+
+template <typename T>
+struct BrickArgs {
+    const LevelDev<T>* L;
+    int E0, E1, E2;
+    int nb0, nb1, nb2;
+    int nrhs;
+    long long ndof;
+    const RhsState* st;  // per right-hand side (active flag, beta); may be null
+    const T* u;
+    const T* u2;
+    const T* f;
+    const T* zprev;
+    T* out;
+    T* out2;
+    double* partial;
+    int pstride;
+    T cp, cr;
+};
+
+// Reads one input value (BM_PQ combines u + beta u2).
+template <typename T, int MODE>
+__device__ __forceinline__ T ldin(const T* u, const T* u2, long long idx, T beta) {
+    if constexpr (MODE == BM_PQ)
+        return u[idx] + beta * u2[idx];
+    else
+        return u[idx];
+}
+
+// Computes y = A u over the brick.  On return, for column threads (colok),
+// ycol[Z] holds (A u) at the thread's column and ucol[Z] the input values.
+template <typename T, int N, int BE, int MODE>
+__device__ __forceinline__ void brick_apply(const BrickArgs<T>& a, const LevelDev<T>& L, int ex0, int ey0, int ez0,
+                                            const T* u, const T* u2, T beta, T* su, T* sx, T* sy, T* ucol,
+                                            T* ycol) {
+    constexpr int NB = N * BE, NT = NB * NB, SY = NB + 1, SZ = NB * SY, N3 = N * N * N;
+    const int t = threadIdx.x;
+    const int E0 = a.E0, E1 = a.E1, E2 = a.E2;
+    auto eoff = [&](int ex, int ey, int ez) -> long long { return ((long long)(ez * E1 + ey) * E0 + ex) * N3; };
+
+    // ---- load: thread (X, Y) keeps the brick column along Z
+    const int X = t % NB, Y = t / NB;
+    const int exX = ex0 + X / N, iX = X % N, eyY = ey0 + Y / N, jY = Y % N;
+    const bool colth = t < NT;
+    const bool colok = colth && exX < E0 && eyY < E1;
+#pragma unroll
+    for (int Z = 0; Z < NB; ++Z) {
+        const int ez = ez0 + Z / N, k = Z % N;
+        T v = 0;
+        if (colok && ez < E2) v = ldin<T, MODE>(u, u2, eoff(exX, eyY, ez) + (k * N + jY) * N + iX, beta);
+        ucol[Z] = v;
+        if (colth) su[Z * SZ + Y * SY + X] = v;
+    }
+    __syncthreads();
+
+    if (t < NT) {
+        // ---- x axis: thread (Yr, Zr) owns brick row along X
+        {
+            const int Yr = t % NB, Zr = t / NB;
+            const int ey = ey0 + Yr / N, j = Yr % N, ez = ez0 + Zr / N, k = Zr % N;
+            if (ey < E1 && ez < E2) {
+                T row[NB], out[NB];
+#pragma unroll
+                for (int x = 0; x < NB; ++x) row[x] = su[Zr * SZ + Yr * SY + x];
+                T hlu = 0, hld = 0, hru = 0, hrd = 0;
+                const AxisDev<T>& A = L.ax[0];
+                if (ex0 > 0) {
+                    const long long o = eoff(ex0 - 1, ey, ez) + (k * N + j) * N;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) {
+                        const T v = ldin<T, MODE>(u, u2, o + l, beta);
+                        hld += A.dR[l] * v;
+                        if (l == N - 1) hlu = v;
+                    }
+                }
+                if (ex0 + BE < E0) {
+                    const long long o = eoff(ex0 + BE, ey, ez) + (k * N + j) * N;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) {
+                        const T v = ldin<T, MODE>(u, u2, o + l, beta);
+                        hrd += A.dL[l] * v;
+                        if (l == 0) hru = v;
+                    }
+                }
+                axis_row<T, N, BE>(A, ex0, E0, row, hlu, hld, hru, hrd, out);
+                const T sc = L.ax[1].m[j] * L.ax[2].m[k];
+#pragma unroll
+                for (int x = 0; x < NB; ++x) sx[Zr * SZ + Yr * SY + x] = out[x] * sc;
+            }
+        }
+        // ---- y axis: thread (Xr, Zr) owns brick row along Y
+        {
+            const int Xr = t % NB, Zr = t / NB;
+            const int ex = ex0 + Xr / N, i = Xr % N, ez = ez0 + Zr / N, k = Zr % N;
+            if (ex < E0 && ez < E2) {
+                T row[NB], out[NB];
+#pragma unroll
+                for (int y = 0; y < NB; ++y) row[y] = su[Zr * SZ + y * SY + Xr];
+                T hlu = 0, hld = 0, hru = 0, hrd = 0;
+                const AxisDev<T>& A = L.ax[1];
+                if (ey0 > 0) {
+                    const long long o = eoff(ex, ey0 - 1, ez) + k * N * N + i;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) {
+                        const T v = ldin<T, MODE>(u, u2, o + l * N, beta);
+                        hld += A.dR[l] * v;
+                        if (l == N - 1) hlu = v;
+                    }
+                }
+                if (ey0 + BE < E1) {
+                    const long long o = eoff(ex, ey0 + BE, ez) + k * N * N + i;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) {
+                        const T v = ldin<T, MODE>(u, u2, o + l * N, beta);
+                        hrd += A.dL[l] * v;
+                        if (l == 0) hru = v;
+                    }
+                }
+                axis_row<T, N, BE>(A, ey0, E1, row, hlu, hld, hru, hrd, out);
+                const T sc = L.ax[0].m[i] * L.ax[2].m[k];
+#pragma unroll
+                for (int y = 0; y < NB; ++y) sy[Zr * SZ + y * SY + Xr] = out[y] * sc;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- z axis in registers, sum of the three terms
+    if (colok) {
+        T hlu = 0, hld = 0, hru = 0, hrd = 0;
+        const AxisDev<T>& A = L.ax[2];
+        if (ez0 > 0) {
+            const long long o = eoff(exX, eyY, ez0 - 1) + jY * N + iX;
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                const T v = ldin<T, MODE>(u, u2, o + l * N * N, beta);
+                hld += A.dR[l] * v;
+                if (l == N - 1) hlu = v;
+            }
+        }
+        if (ez0 + BE < E2) {
+            const long long o = eoff(exX, eyY, ez0 + BE) + jY * N + iX;
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                const T v = ldin<T, MODE>(u, u2, o + l * N * N, beta);
+                hrd += A.dL[l] * v;
+                if (l == 0) hru = v;
+            }
+        }
+        T out[NB];
+        axis_row<T, N, BE>(A, ez0, E2, ucol, hlu, hld, hru, hrd, out);
+        const T sc = L.ax[0].m[iX] * L.ax[1].m[jY];
+#pragma unroll
+        for (int Z = 0; Z < NB; ++Z) ycol[Z] = out[Z] * sc + sx[Z * SZ + Y * SY + X] + sy[Z * SZ + Y * SY + X];
+    }
+}
+
+template <typename T, int N, int BE, int MODE>
+__global__ __launch_bounds__(wg_of(N* BE* N* BE)) void k_brick(BrickArgs<T> a) {
+    constexpr int NB = N * BE, NT = NB * NB, SY = NB + 1, SZ = NB * SY, N3 = N * N * N;
+    constexpr int WG = wg_of(NT);
+    __shared__ T su[NB * SZ];
+    __shared__ T sx[NB * SZ];
+    __shared__ T sy[NB * SZ];
+    __shared__ double red[WG / 64];
+
+    const int nbr = a.nb0 * a.nb1 * a.nb2;
+    const int w = xcd_remap(blockIdx.x, nbr * a.nrhs);
+    const int rhs = w / nbr, br = w % nbr;
+    if (a.st && !a.st[rhs].active) return;
+    const int bx = br % a.nb0, by = (br / a.nb0) % a.nb1, bz = br / (a.nb0 * a.nb1);
+    const int ex0 = bx * BE, ey0 = by * BE, ez0 = bz * BE;
+    const LevelDev<T>& L = *a.L;
+    const long long base = (long long)rhs * a.ndof;
+    const T* u = a.u + base;
+    const T* u2 = (MODE == BM_PQ) ? a.u2 + base : nullptr;
+    T beta = 0;
+    if constexpr (MODE == BM_PQ) beta = (T)a.st[rhs].beta;
+
+    T ucol[NB], ycol[NB];
+    brick_apply<T, N, BE, MODE>(a, L, ex0, ey0, ez0, u, u2, beta, su, sx, sy, ucol, ycol);
+
+    const int t = threadIdx.x;
+    const int X = t % NB, Y = t / NB;
+    const int exX = ex0 + X / N, iX = X % N, eyY = ey0 + Y / N, jY = Y % N;
+    const bool colok = t < NT && exX < a.E0 && eyY < a.E1;
+    double dot = 0.0;
+    if (colok) {
+        const int E0 = a.E0, E1 = a.E1, E2 = a.E2;
+        const int tx = etype(exX, E0), ty = etype(eyY, E1);
+        const T mx = L.ax[0].m[iX], my = L.ax[1].m[jY];
+        const T dxm = L.ax[0].Bd[tx][iX] * my, mxdy = mx * L.ax[1].Bd[ty][jY], mxy = mx * my;
+#pragma unroll
+        for (int Z = 0; Z < NB; ++Z) {
+            const int ez = ez0 + Z / N, k = Z % N;
+            if (ez >= E2) continue;
+            const long long idx = base + ((long long)(ez * E1 + eyY) * E0 + exX) * N3 + (k * N + jY) * N + iX;
+            const T y = ycol[Z];
+            if constexpr (MODE == BM_APPLY) {
+                a.out[idx] = y;
+            } else if constexpr (MODE == BM_RESID || MODE == BM_RESIDDOT) {
+                const T r = a.f[idx] - y;
+                a.out[idx] = r;
+                if constexpr (MODE == BM_RESIDDOT) dot += (double)r * (double)r;
+            } else if constexpr (MODE == BM_CHEB || MODE == BM_CHEBDOT) {
+                const int tz = etype(ez, E2);
+                const T mz = L.ax[2].m[k];
+                const T D = (dxm + mxdy) * mz + mxy * L.ax[2].Bd[tz][k];
+                const T uz = ucol[Z];
+                const T zp = a.zprev ? a.zprev[idx] : (T)0;
+                const T fz = a.f[idx];
+                const T zn = uz + a.cp * (uz - zp) + a.cr * (fz - y) / D;
+                a.out[idx] = zn;
+                if constexpr (MODE == BM_CHEBDOT) dot += (double)fz * (double)zn;
+            } else if constexpr (MODE == BM_PQ) {
+                a.out2[idx] = ucol[Z];
+                a.out[idx] = y;
+                dot += (double)ucol[Z] * (double)y;
+            }
+        }
+    }
+    if constexpr (MODE == BM_CHEBDOT || MODE == BM_PQ || MODE == BM_RESIDDOT) {
+        const double s = block_sum<WG>(dot, red);
+        if (t == 0) a.partial[(long long)rhs * a.pstride + br] = s;
+    }
+}
+
+template <typename T, int N, int BE>
+static void brick_dispatch(int mode, const BrickArgs<T>& a, int grid, hipStream_t s) {
+    constexpr int WG = wg_of(N * BE * N * BE);
+    switch (mode) {
+        case BM_APPLY: hipLaunchKernelGGL((k_brick<T, N, BE, BM_APPLY>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_RESID: hipLaunchKernelGGL((k_brick<T, N, BE, BM_RESID>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_CHEB: hipLaunchKernelGGL((k_brick<T, N, BE, BM_CHEB>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_CHEBDOT: hipLaunchKernelGGL((k_brick<T, N, BE, BM_CHEBDOT>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_PQ: hipLaunchKernelGGL((k_brick<T, N, BE, BM_PQ>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_RESIDDOT: hipLaunchKernelGGL((k_brick<T, N, BE, BM_RESIDDOT>), dim3(grid), dim3(WG), 0, s, a); break;
+    }
+}
+
+template <typename T>
+void launch_brick(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, const T* u,
+                  const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial, int pstride, double cp,
+                  double cr, hipStream_t s) {
+    BrickArgs<T> a;
+    a.L = dev;
+    a.E0 = L.E[0]; a.E1 = L.E[1]; a.E2 = L.E[2];
+    a.nb0 = L.nbr[0]; a.nb1 = L.nbr[1]; a.nb2 = L.nbr[2];
+    a.nrhs = nrhs;
+    a.ndof = L.ndof;
+    a.st = st;
+    a.u = u; a.u2 = u2; a.f = f; a.zprev = zprev; a.out = out; a.out2 = out2;
+    a.partial = partial;
+    a.pstride = pstride;
+    a.cp = (T)cp;
+    a.cr = (T)cr;
+    const int grid = bricks_of(L) * nrhs;
+    if (grid == 0) return;
+    switch (L.n) {
+        case 2: brick_dispatch<T, 2, be_of<2>()>(mode, a, grid, s); break;
+        case 3: brick_dispatch<T, 3, be_of<3>()>(mode, a, grid, s); break;
+        case 4: brick_dispatch<T, 4, be_of<4>()>(mode, a, grid, s); break;
+        case 5: brick_dispatch<T, 5, be_of<5>()>(mode, a, grid, s); break;
+        case 6: brick_dispatch<T, 6, be_of<6>()>(mode, a, grid, s); break;
+        case 7: brick_dispatch<T, 7, be_of<7>()>(mode, a, grid, s); break;
+        case 8: brick_dispatch<T, 8, be_of<8>()>(mode, a, grid, s); break;
+    }
+}
+
+template void launch_brick<double>(int, const LevelHost&, const LevelDev<double>*, int, const RhsState*,
+                                   const double*, const double*, const double*, const double*, double*, double*,
+                                   double*, int, double, double, hipStream_t);
+template void launch_brick<float>(int, const LevelHost&, const LevelDev<float>*, int, const RhsState*, const float*,
+                                  const float*, const float*, const float*, float*, float*, double*, int, double,
+                                  double, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// restriction: fc = P^T (f - A z) over a fine brick
+
+template <typename T>
+struct TransferArgs {
+    const LevelDev<T>* Lf;
+    const LevelDev<T>* Lc;
+    const TransferDev* tr;
+    int E0, E1, E2;        // fine elements
+    int nb0, nb1, nb2;     // fine bricks
+    int Ec0, Ec1, Ec2;     // coarse elements
+    int nrhs;
+    long long ndof, ndofc;
+    const RhsState* st;
+    const T* z;            // restriction: fine iterate (may be null); prolongation: coarse correction
+    const T* f;            // fine right-hand side
+    T* fc;                 // restriction output
+    T* z1c;                // optional c0c Dc^-1 fc
+    T* zf;                 // prolongation target
+    T c0c;
+};
+
+template <typename T>
+__device__ __forceinline__ T trP(const TransferDev& tr, int a, int b) {
+    if constexpr (sizeof(T) == 8)
+        return tr.P[a][b];
+    else
+        return tr.Pf[a][b];
+}
+
+template <typename T, int NF, int BE, int NC, bool HC, bool HASZ>
+__global__ __launch_bounds__(wg_of(NF* BE* NF* BE)) void k_restrict(TransferArgs<T> a) {
+    constexpr int NB = NF * BE, NT = NB * NB, SY = NB + 1, SZ = NB * SY, N3 = NF * NF * NF;
+    constexpr int CBE = HC ? BE / 2 : BE;  // coarse elements per brick edge
+    constexpr int NCB = CBE * NC;          // coarse nodes per brick edge
+    constexpr int NC3 = NC * NC * NC;
+    constexpr int WG = wg_of(NT);
+    static_assert(!HC || BE % 2 == 0, "mesh coarsening needs an even brick edge");
+    __shared__ T su[NB * SZ];
+    __shared__ T sx[NB * SZ];
+    __shared__ T sy[NB * SZ];
+
+    const int nbr = a.nb0 * a.nb1 * a.nb2;
+    const int w = xcd_remap(blockIdx.x, nbr * a.nrhs);
+    const int rhs = w / nbr, br = w % nbr;
+    if (a.st && !a.st[rhs].active) return;
+    const int bx = br % a.nb0, by = (br / a.nb0) % a.nb1, bz = br / (a.nb0 * a.nb1);
+    const int ex0 = bx * BE, ey0 = by * BE, ez0 = bz * BE;
+    const long long base = (long long)rhs * a.ndof;
+    const T* f = a.f + base;
+    const int t = threadIdx.x;
+    const int X = t % NB, Y = t / NB;
+    const int exX = ex0 + X / NF, iX = X % NF, eyY = ey0 + Y / NF, jY = Y % NF;
+    const bool colok = t < NT && exX < a.E0 && eyY < a.E1;
+    const int E0 = a.E0, E1 = a.E1, E2 = a.E2;
+
+    T rcol[NB];
+    if constexpr (HASZ) {
+        BrickArgs<T> ba;
+        ba.E0 = E0; ba.E1 = E1; ba.E2 = E2;
+        T ucol[NB];
+        brick_apply<T, NF, BE, BM_APPLY>(ba, *a.Lf, ex0, ey0, ez0, a.z + base, nullptr, (T)0, su, sx, sy, ucol, rcol);
+    }
+#pragma unroll
+    for (int Z = 0; Z < NB; ++Z) {
+        const int ez = ez0 + Z / NF, k = Z % NF;
+        T r = 0;
+        if (colok && ez < E2) {
+            const T fv = f[((long long)(ez * E1 + eyY) * E0 + exX) * N3 + (k * NF + jY) * NF + iX];
+            if constexpr (HASZ)
+                r = fv - rcol[Z];
+            else
+                r = fv;
+        }
+        rcol[Z] = r;
+    }
+    __syncthreads();  // LDS of the apply is free again
+    const TransferDev& tr = *a.tr;
+    // along Z in registers -> su[Zc][Y][X]
+    if (t < NT) {
+#pragma unroll
+        for (int Zc = 0; Zc < NCB; ++Zc) {
+            T s = 0;
+#pragma unroll
+            for (int Z = 0; Z < NB; ++Z) s += trP<T>(tr, Z, Zc) * rcol[Z];
+            su[Zc * SZ + Y * SY + X] = s;
+        }
+    }
+    __syncthreads();
+    // along Y: thread (X, Zc) -> sx[Zc][Yc][X]
+    if (t < NB * NCB) {
+        const int Xr = t % NB, Zc = t / NB;
+        T col[NB];
+#pragma unroll
+        for (int y = 0; y < NB; ++y) col[y] = su[Zc * SZ + y * SY + Xr];
+#pragma unroll
+        for (int Yc = 0; Yc < NCB; ++Yc) {
+            T s = 0;
+#pragma unroll
+            for (int y = 0; y < NB; ++y) s += trP<T>(tr, y, Yc) * col[y];
+            sx[Zc * SZ + Yc * SY + Xr] = s;
+        }
+    }
+    __syncthreads();
+    // along X: thread (Yc, Zc) -> coarse output
+    if (t < NCB * NCB) {
+        const int Yc = t % NCB, Zc = t / NCB;
+        const int ecx0 = HC ? ex0 / 2 : ex0, ecy0 = HC ? ey0 / 2 : ey0, ecz0 = HC ? ez0 / 2 : ez0;
+        const int ecy = ecy0 + Yc / NC, jc = Yc % NC, ecz = ecz0 + Zc / NC, kc = Zc % NC;
+        if (ecy < a.Ec1 && ecz < a.Ec2) {
+            T col[NB];
+#pragma unroll
+            for (int x = 0; x < NB; ++x) col[x] = sx[Zc * SZ + Yc * SY + x];
+            const long long cbase = (long long)rhs * a.ndofc;
+#pragma unroll
+            for (int Xc = 0; Xc < NCB; ++Xc) {
+                const int ecx = ecx0 + Xc / NC, ic = Xc % NC;
+                if (ecx >= a.Ec0) continue;
+                T s = 0;
+#pragma unroll
+                for (int x = 0; x < NB; ++x) s += trP<T>(tr, x, Xc) * col[x];
+                const long long idx = cbase + ((long long)(ecz * a.Ec1 + ecy) * a.Ec0 + ecx) * NC3 + (kc * NC + jc) * NC + ic;
+                a.fc[idx] = s;
+                if (a.z1c) {
+                    const LevelDev<T>& Lc = *a.Lc;
+                    const int tx = etype(ecx, a.Ec0), ty = etype(ecy, a.Ec1), tz = etype(ecz, a.Ec2);
+                    const T mx = Lc.ax[0].m[ic], my = Lc.ax[1].m[jc], mz = Lc.ax[2].m[kc];
+                    const T D = Lc.ax[0].Bd[tx][ic] * my * mz + mx * Lc.ax[1].Bd[ty][jc] * mz + mx * my * Lc.ax[2].Bd[tz][kc];
+                    a.z1c[idx] = a.c0c * s / D;
+                }
+            }
+        }
+    }
+}
+
+// prolongation and correction: zf += P zc over a fine brick
+template <typename T, int NF, int BE, int NC, bool HC>
+__global__ __launch_bounds__(wg_of(NF* BE* NF* BE)) void k_prolong(TransferArgs<T> a) {
+    constexpr int NB = NF * BE, NT = NB * NB, N3 = NF * NF * NF;
+    constexpr int CBE = HC ? BE / 2 : BE;
+    constexpr int NCB = CBE * NC;
+    constexpr int NC3 = NC * NC * NC;
+    __shared__ T sc[NCB * NCB * NCB];
+    __shared__ T s1[NCB * NCB * NB];
+    __shared__ T s2[NCB * NB * NB];
+
+    const int nbr = a.nb0 * a.nb1 * a.nb2;
+    const int w = xcd_remap(blockIdx.x, nbr * a.nrhs);
+    const int rhs = w / nbr, br = w % nbr;
+    if (a.st && !a.st[rhs].active) return;
+    const int bx = br % a.nb0, by = (br / a.nb0) % a.nb1, bz = br / (a.nb0 * a.nb1);
+    const int ex0 = bx * BE, ey0 = by * BE, ez0 = bz * BE;
+    const int ecx0 = HC ? ex0 / 2 : ex0, ecy0 = HC ? ey0 / 2 : ey0, ecz0 = HC ? ez0 / 2 : ez0;
+    const int t = threadIdx.x;
+    const T* zc = a.z + (long long)rhs * a.ndofc;
+    for (int q = t; q < NCB * NCB * NCB; q += blockDim.x) {
+        const int Xc = q % NCB, Yc = (q / NCB) % NCB, Zc = q / (NCB * NCB);
+        const int ecx = ecx0 + Xc / NC, ecy = ecy0 + Yc / NC, ecz = ecz0 + Zc / NC;
+        T v = 0;
+        if (ecx < a.Ec0 && ecy < a.Ec1 && ecz < a.Ec2)
+            v = zc[((long long)(ecz * a.Ec1 + ecy) * a.Ec0 + ecx) * NC3 + ((Zc % NC) * NC + (Yc % NC)) * NC + (Xc % NC)];
+        sc[q] = v;
+    }
+    __syncthreads();
+    const TransferDev& tr = *a.tr;
+    if (t < NCB * NCB) {  // along X: thread (Yc, Zc)
+        const int Yc = t % NCB, Zc = t / NCB;
+        T c[NCB];
+#pragma unroll
+        for (int x = 0; x < NCB; ++x) c[x] = sc[(Zc * NCB + Yc) * NCB + x];
+#pragma unroll
+        for (int X = 0; X < NB; ++X) {
+            T s = 0;
+#pragma unroll
+            for (int x = 0; x < NCB; ++x) s += trP<T>(tr, X, x) * c[x];
+            s1[(Zc * NCB + Yc) * NB + X] = s;
+        }
+    }
+    __syncthreads();
+    if (t < NB * NCB) {  // along Y: thread (X, Zc)
+        const int X = t % NB, Zc = t / NB;
+        T c[NCB];
+#pragma unroll
+        for (int y = 0; y < NCB; ++y) c[y] = s1[(Zc * NCB + y) * NB + X];
+#pragma unroll
+        for (int Y = 0; Y < NB; ++Y) {
+            T s = 0;
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) s += trP<T>(tr, Y, y) * c[y];
+            s2[(Zc * NB + Y) * NB + X] = s;
+        }
+    }
+    __syncthreads();
+    if (t < NT) {  // along Z: thread (X, Y), add into the fine field
+        const int X = t % NB, Y = t / NB;
+        const int exX = ex0 + X / NF, iX = X % NF, eyY = ey0 + Y / NF, jY = Y % NF;
+        if (exX < a.E0 && eyY < a.E1) {
+            T c[NCB];
+#pragma unroll
+            for (int z = 0; z < NCB; ++z) c[z] = s2[(z * NB + Y) * NB + X];
+            T* zf = a.zf + (long long)rhs * a.ndof;
+#pragma unroll
+            for (int Z = 0; Z < NB; ++Z) {
+                const int ez = ez0 + Z / NF, k = Z % NF;
+                if (ez >= a.E2) continue;
+                T s = 0;
+#pragma unroll
+                for (int z = 0; z < NCB; ++z) s += trP<T>(tr, Z, z) * c[z];
+                const long long idx = ((long long)(ez * a.E1 + eyY) * a.E0 + exX) * N3 + (k * NF + jY) * NF + iX;
+                zf[idx] += s;
+            }
+        }
+    }
+}
+
+template <typename T>
+static TransferArgs<T> transfer_args(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st) {
+    TransferArgs<T> a;
+    a.tr = Lf.devtr;
+    a.E0 = Lf.E[0]; a.E1 = Lf.E[1]; a.E2 = Lf.E[2];
+    a.nb0 = Lf.nbr[0]; a.nb1 = Lf.nbr[1]; a.nb2 = Lf.nbr[2];
+    a.Ec0 = Lc.E[0]; a.Ec1 = Lc.E[1]; a.Ec2 = Lc.E[2];
+    a.nrhs = nrhs;
+    a.ndof = Lf.ndof;
+    a.ndofc = Lc.ndof;
+    a.st = st;
+    a.z = nullptr; a.f = nullptr; a.fc = nullptr; a.z1c = nullptr; a.zf = nullptr;
+    a.Lf = nullptr; a.Lc = nullptr;
+    a.c0c = 0;
+    return a;
+}
+
+#define DG_TRANSFER_CASES(MACRO) \
+    MACRO(8, 4, false)           \
+    MACRO(7, 4, false)           \
+    MACRO(6, 3, false)           \
+    MACRO(5, 3, false)           \
+    MACRO(4, 2, false)           \
+    MACRO(3, 2, false)           \
+    MACRO(2, 2, true)
+
+template <typename T>
+void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHost& Lc, const LevelDev<T>* devc,
+                     int nrhs, const RhsState* st, const T* z, const T* f, T* fc, T* z1c, double c0c,
+                     hipStream_t s) {
+    TransferArgs<T> a = transfer_args<T>(Lf, Lc, nrhs, st);
+    a.Lf = devf; a.Lc = devc; a.z = z; a.f = f; a.fc = fc; a.z1c = z1c; a.c0c = (T)c0c;
+    const int grid = bricks_of(Lf) * nrhs;
+    if (grid == 0) return;
+    const bool hc = Lf.hcoarse;
+#define DG_R(NF, NC, HC)                                                                                         \
+    if (Lf.n == NF && Lc.n == NC && hc == HC) {                                                                 \
+        constexpr int BE = be_of<NF>();                                                                         \
+        constexpr int WG = wg_of(NF * BE * NF * BE);                                                            \
+        if (z)                                                                                                  \
+            hipLaunchKernelGGL((k_restrict<T, NF, BE, NC, HC, true>), dim3(grid), dim3(WG), 0, s, a);           \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_restrict<T, NF, BE, NC, HC, false>), dim3(grid), dim3(WG), 0, s, a);          \
+        return;                                                                                                 \
+    }
+    DG_TRANSFER_CASES(DG_R)
+#undef DG_R
+    fprintf(stderr, "dg: no restriction kernel for %d -> %d\n", Lf.n, Lc.n);
+}
+
+template <typename T>
+void launch_prolong(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st, const T* zc, T* zf,
+                    hipStream_t s) {
+    TransferArgs<T> a = transfer_args<T>(Lf, Lc, nrhs, st);
+    a.z = zc; a.zf = zf;
+    const int grid = bricks_of(Lf) * nrhs;
+    if (grid == 0) return;
+    const bool hc = Lf.hcoarse;
+#define DG_P(NF, NC, HC)                                                                                \
+    if (Lf.n == NF && Lc.n == NC && hc == HC) {                                                        \
+        constexpr int BE = be_of<NF>();                                                                \
+        constexpr int WG = wg_of(NF * BE * NF * BE);                                                   \
+        hipLaunchKernelGGL((k_prolong<T, NF, BE, NC, HC>), dim3(grid), dim3(WG), 0, s, a);             \
+        return;                                                                                        \
+    }
+    DG_TRANSFER_CASES(DG_P)
+#undef DG_P
+    fprintf(stderr, "dg: no prolongation kernel for %d -> %d\n", Lf.n, Lc.n);
+}
+
+template void launch_restrict<double>(const LevelHost&, const LevelDev<double>*, const LevelHost&,
+                                      const LevelDev<double>*, int, const RhsState*, const double*, const double*,
+                                      double*, double*, double, hipStream_t);
+template void launch_restrict<float>(const LevelHost&, const LevelDev<float>*, const LevelHost&,
+                                     const LevelDev<float>*, int, const RhsState*, const float*, const float*, float*,
+                                     float*, double, hipStream_t);
+template void launch_prolong<double>(const LevelHost&, const LevelHost&, int, const RhsState*, const double*, double*,
+                                     hipStream_t);
+template void launch_prolong<float>(const LevelHost&, const LevelHost&, int, const RhsState*, const float*, float*,
+                                    hipStream_t);
+
+// ---------------------------------------------------------------------------
+// coarsest level: exact solve by fast diagonalisation, one work-group per RHS
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse(const CoarseDev* __restrict__ C, int nrhs, long long ndof,
+                                                const RhsState* st, const T* __restrict__ r, T* __restrict__ z) {
+    __shared__ double g[CMAX * CMAX * CMAX];
+    const int rhs = blockIdx.x;
+    if (st && !st[rhs].active) return;
+    const int nx = C->n[0], ny = C->n[1], nz = C->n[2], N = C->N;
+    const int E0 = C->E[0], E1 = C->E[1];
+    const int N3 = N * N * N;
+    const T* rr = r + (long long)rhs * ndof;
+    T* zz = z + (long long)rhs * ndof;
+    const int t = threadIdx.x;
+    for (long long q = t; q < ndof; q += blockDim.x) {
+        const int e = (int)(q / N3), l = (int)(q % N3);
+        const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
+        const int i = l % N, j = (l / N) % N, k = l / (N * N);
+        const int Xg = ex * N + i, Yg = ey * N + j, Zg = ez * N + k;
+        g[(Zg * ny + Yg) * nx + Xg] = (double)rr[q] * C->s[0][Xg] * C->s[1][Yg] * C->s[2][Zg];
+    }
+    __syncthreads();
+    // three contractions with Q^T, scale, three with Q; one thread per line
+    for (int pass = 0; pass < 6; ++pass) {
+        const int axis = pass % 3;
+        const bool fwd = pass < 3;
+        const int n = C->n[axis];
+        const int nl = (nx * ny * nz) / n;
+        for (int line = t; line < nl; line += blockDim.x) {
+            int o, stride;
+            if (axis == 0) { o = line * nx; stride = 1; }
+            else if (axis == 1) { const int Zg = line / nx, Xg = line % nx; o = Zg * ny * nx + Xg; stride = nx; }
+            else { o = line; stride = nx * ny; }
+            double v[CMAX], w[CMAX];
+#pragma unroll
+            for (int a2 = 0; a2 < CMAX; ++a2) v[a2] = a2 < n ? g[o + a2 * stride] : 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < CMAX; ++a2) {
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < CMAX; ++b)
+                    if (a2 < n && b < n) s += (fwd ? C->Q[axis][b][a2] : C->Q[axis][a2][b]) * v[b];
+                w[a2] = s;
+            }
+#pragma unroll
+            for (int a2 = 0; a2 < CMAX; ++a2)
+                if (a2 < n) g[o + a2 * stride] = w[a2];
+        }
+        __syncthreads();
+        if (pass == 2) {
+            for (int q = t; q < nx * ny * nz; q += blockDim.x) {
+                const int Xg = q % nx, Yg = (q / nx) % ny, Zg = q / (nx * ny);
+                g[q] /= (C->lam[0][Xg] + C->lam[1][Yg] + C->lam[2][Zg]);
+            }
+            __syncthreads();
+        }
+    }
+    for (long long q = t; q < ndof; q += blockDim.x) {
+        const int e = (int)(q / N3), l = (int)(q % N3);
+        const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
+        const int i = l % N, j = (l / N) % N, k = l / (N * N);
+        const int Xg = ex * N + i, Yg = ey * N + j, Zg = ez * N + k;
+        zz[q] = (T)(g[(Zg * ny + Yg) * nx + Xg] * C->s[0][Xg] * C->s[1][Yg] * C->s[2][Zg]);
+    }
+}
+
+template <typename T>
+void launch_coarse(const CoarseDev* C, const LevelHost& L, int nrhs, const RhsState* st, const T* r, T* z,
+                   hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL((k_coarse<T>), dim3(nrhs), dim3(256), 0, s, C, nrhs, L.ndof, st, r, z);
+}
+template void launch_coarse<double>(const CoarseDev*, const LevelHost&, int, const RhsState*, const double*, double*,
+                                    hipStream_t);
+template void launch_coarse<float>(const CoarseDev*, const LevelHost&, int, const RhsState*, const float*, float*,
+                                   hipStream_t);
+
+// ---------------------------------------------------------------------------
+// pointwise kernels: grid (chunks, nrhs), 256 threads x 4 values per chunk
+
+template <typename T, int N>
+__device__ __forceinline__ T diag_at(const LevelDev<T>& L, int E0, int E1, int E2, long long q) {
+    constexpr int N3 = N * N * N;
+    const int e = (int)(q / N3), l = (int)(q % N3);
+    const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
+    const int i = l % N, j = (l / N) % N, k = l / (N * N);
+    const int tx = etype(ex, E0), ty = etype(ey, E1), tz = etype(ez, E2);
+    const T mx = L.ax[0].m[i], my = L.ax[1].m[j], mz = L.ax[2].m[k];
+    return L.ax[0].Bd[tx][i] * my * mz + mx * L.ax[1].Bd[ty][j] * mz + mx * my * L.ax[2].Bd[tz][k];
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_cheb0(const LevelDev<T>* __restrict__ L, int E0, int E1, int E2,
+                                               long long ndof, const RhsState* st, const T* __restrict__ f,
+                                               T* __restrict__ z, T c0) {
+    const int rhs = blockIdx.y;
+    if (st && !st[rhs].active) return;
+    const long long base = (long long)rhs * ndof;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q < ndof) z[base + q] = c0 * f[base + q] / diag_at<T, N>(*L, E0, E1, E2, q);
+    }
+}
+
+template <typename T>
+void launch_cheb0(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, const T* f, T* z,
+                  double c0, hipStream_t s) {
+    if (nrhs == 0) return;
+    dim3 grid(chunks_of(L.ndof), nrhs);
+#define DG_C0(NN) \
+    case NN: hipLaunchKernelGGL((k_cheb0<T, NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, st, f, z, (T)c0); break;
+    switch (L.n) { DG_C0(2) DG_C0(3) DG_C0(4) DG_C0(5) DG_C0(6) DG_C0(7) DG_C0(8) }
+#undef DG_C0
+}
+template void launch_cheb0<double>(const LevelHost&, const LevelDev<double>*, int, const RhsState*, const double*,
+                                   double*, double, hipStream_t);
+template void launch_cheb0<float>(const LevelHost&, const LevelDev<float>*, int, const RhsState*, const float*,
+                                  float*, double, hipStream_t);
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_update(const LevelDev<T>* __restrict__ L, int E0, int E1, int E2,
+                                                long long ndof, const RhsState* st, T* __restrict__ x,
+                                                T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q_,
+                                                T* __restrict__ z1, T c0, double* __restrict__ partial, int pstride) {
+    __shared__ double red[4];
+    const int rhs = blockIdx.y;
+    if (!st[rhs].active) return;
+    const T alpha = (T)st[rhs].alpha;
+    const long long base = (long long)rhs * ndof;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    double acc = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q < ndof) {
+            const long long g = base + q;
+            x[g] += alpha * p[g];
+            const T rn = r[g] - alpha * q_[g];
+            r[g] = rn;
+            acc += (double)rn * (double)rn;
+            if (z1) z1[g] = c0 * rn / diag_at<T, N>(*L, E0, E1, E2, q);
+        }
+    }
+    const double s = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) partial[(long long)rhs * pstride + blockIdx.x] = s;
+}
+
+template <typename T>
+void launch_update(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, T* x, T* r, const T* p,
+                   const T* q, T* z1, double c0, double* partial, int pstride, hipStream_t s) {
+    if (nrhs == 0) return;
+    dim3 grid(chunks_of(L.ndof), nrhs);
+#define DG_U(NN)                                                                                                  \
+    case NN:                                                                                                      \
+        hipLaunchKernelGGL((k_update<T, NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, st, x, r, \
+                           p, q, z1, (T)c0, partial, pstride);                                                    \
+        break;
+    switch (L.n) { DG_U(2) DG_U(3) DG_U(4) DG_U(5) DG_U(6) DG_U(7) DG_U(8) }
+#undef DG_U
+}
+template void launch_update<double>(const LevelHost&, const LevelDev<double>*, int, const RhsState*, double*, double*,
+                                    const double*, const double*, double*, double, double*, int, hipStream_t);
+template void launch_update<float>(const LevelHost&, const LevelDev<float>*, int, const RhsState*, float*, float*,
+                                   const float*, const float*, float*, double, double*, int, hipStream_t);
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_dot(long long ndof, const RhsState* st, const TA* __restrict__ a,
+                                             const TB* __restrict__ b, double* __restrict__ partial, int pstride) {
+    __shared__ double red[4];
+    const int rhs = blockIdx.y;
+    if (st && !st[rhs].active) return;
+    const long long base = (long long)rhs * ndof;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    double acc = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q < ndof) acc += (double)a[base + q] * (double)b[base + q];
+    }
+    const double s = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) partial[(long long)rhs * pstride + blockIdx.x] = s;
+}
+
+template <typename TA, typename TB>
+void launch_dot(long long ndof, int nrhs, const RhsState* st, const TA* a, const TB* b, double* partial, int pstride,
+                hipStream_t s) {
+    if (nrhs == 0) return;
+    dim3 grid(chunks_of(ndof), nrhs);
+    hipLaunchKernelGGL((k_dot<TA, TB>), grid, dim3(256), 0, s, ndof, st, a, b, partial, pstride);
+}
+template void launch_dot<double, double>(long long, int, const RhsState*, const double*, const double*, double*, int,
+                                         hipStream_t);
+template void launch_dot<float, float>(long long, int, const RhsState*, const float*, const float*, double*, int,
+                                       hipStream_t);
+
+__global__ __launch_bounds__(256) void k_finalize(int what, RhsState* st, const double* __restrict__ partial,
+                                                  int pstride, int nblk) {
+    __shared__ double red[256];
+    const int rhs = blockIdx.x;
+    RhsState& S = st[rhs];
+    const bool gated = (what == FIN_RZ || what == FIN_PQ || what == FIN_RR);
+    if (gated && !S.active) return;
+    double acc = 0.0;
+    const double* p = partial + (long long)rhs * pstride;
+    for (int i = threadIdx.x; i < nblk; i += 256) acc += p[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double s = red[0];
+    switch (what) {
+        case FIN_BB: S.bb = s; break;
+        case FIN_RR0:
+            S.rr = s;
+            S.iters = 0;
+            S.breakdown = 0;
+            S.active = (s > S.tol2 * S.bb) && S.maxit > 0 ? 1 : 0;
+            break;
+        case FIN_RZ:
+            S.beta = (S.iters == 0) ? 0.0 : s / S.rz_old;
+            S.rz = s;
+            S.rz_old = s;
+            break;
+        case FIN_PQ:
+            S.pq = s;
+            if (!(s > 0.0) || !(S.rz > 0.0)) {
+                S.breakdown = 1;
+                S.active = 0;
+            } else {
+                S.alpha = S.rz / s;
+            }
+            break;
+        case FIN_RR:
+            S.rr = s;
+            S.iters += 1;
+            S.active = (s > S.tol2 * S.bb && S.iters < S.maxit) ? 1 : 0;
+            break;
+        case FIN_TRUE: S.rr = s; break;
+        case FIN_OUTER:
+            S.rr = s;
+            S.scale = sqrt(s);
+            S.active = (s > S.tol2 * S.bb) ? 1 : 0;
+            break;
+    }
+}
+
+void launch_finalize(int what, int nrhs, RhsState* st, const double* partial, int pstride, int nblk, hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(256), 0, s, what, st, partial, pstride, nblk);
+}
+
+// ---------------------------------------------------------------------------
+// right-hand side: b = 4 pi M rho + lift(g)
+
+template <int N>
+__global__ __launch_bounds__(256) void k_rhs(const LevelDev<double>* __restrict__ L, int E0, int E1, int E2,
+                                             long long ndof, const double* __restrict__ rho,
+                                             const double* __restrict__ phi, const int* __restrict__ pi,
+                                             const int* __restrict__ pj, const double* __restrict__ g, long long nface,
+                                             double* __restrict__ b) {
+    constexpr int N3 = N * N * N;
+    const int rhs = blockIdx.y;
+    const long long base = (long long)rhs * ndof;
+    const int NX = E0 * N, NY = E1 * N, NZ = E2 * N;
+    const long long ox = 0, oxp = (long long)NZ * NY, oy = 2LL * NZ * NY, oyp = oy + (long long)NZ * NX,
+                    oz = oy + 2LL * NZ * NX, ozp = oz + (long long)NY * NX;
+    const double* gg = g + (long long)rhs * nface;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    const double* ph_i = phi ? phi + (long long)pi[rhs] * ndof : nullptr;
+    const double* ph_j = phi ? phi + (long long)pj[rhs] * ndof : nullptr;
+    const AxisDev<double>& ax = L->ax[0];
+    const AxisDev<double>& ay = L->ax[1];
+    const AxisDev<double>& az = L->ax[2];
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q >= ndof) break;
+        const int e = (int)(q / N3), l = (int)(q % N3);
+        const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
+        const int i = l % N, j = (l / N) % N, k = l / (N * N);
+        const int X = ex * N + i, Y = ey * N + j, Z = ez * N + k;
+        const double src = phi ? ph_i[q] * ph_j[q] : rho[base + q];
+        const double mx = ax.m[i], my = ay.m[j], mz = az.m[k];
+        double val = 4.0 * M_PI * mx * my * mz * src;
+        if (ex == 0) val += ax.liftL[i] * my * mz * gg[ox + (long long)Z * NY + Y];
+        if (ex == E0 - 1) val += ax.liftR[i] * my * mz * gg[oxp + (long long)Z * NY + Y];
+        if (ey == 0) val += ay.liftL[j] * mx * mz * gg[oy + (long long)Z * NX + X];
+        if (ey == E1 - 1) val += ay.liftR[j] * mx * mz * gg[oyp + (long long)Z * NX + X];
+        if (ez == 0) val += az.liftL[k] * mx * my * gg[oz + (long long)Y * NX + X];
+        if (ez == E2 - 1) val += az.liftR[k] * mx * my * gg[ozp + (long long)Y * NX + X];
+        b[base + q] = val;
+    }
+}
+
+void launch_rhs(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const double* rho, const double* phi,
+                const int* pi, const int* pj, const double* g, long long nface, double* b, hipStream_t s) {
+    if (nrhs == 0) return;
+    dim3 grid(chunks_of(L.ndof), nrhs);
+#define DG_RHS(NN)                                                                                               \
+    case NN:                                                                                                     \
+        hipLaunchKernelGGL((k_rhs<NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, rho, phi, pi, \
+                           pj, g, nface, b);                                                                     \
+        break;
+    switch (L.n) { DG_RHS(2) DG_RHS(3) DG_RHS(4) DG_RHS(5) DG_RHS(6) DG_RHS(7) DG_RHS(8) }
+#undef DG_RHS
+}
+
+// ---------------------------------------------------------------------------
+// iterative refinement conversions and helpers
+
+__global__ __launch_bounds__(256) void k_to_inner(long long ndof, const RhsState* st, const double* __restrict__ r64,
+                                                  float* __restrict__ r32) {
+    const int rhs = blockIdx.y;
+    if (!st[rhs].active) return;
+    const double inv = 1.0 / st[rhs].scale;
+    const long long base = (long long)rhs * ndof;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q < ndof) r32[base + q] = (float)(r64[base + q] * inv);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_correct(long long ndof, const RhsState* st, const float* __restrict__ d32,
+                                                 double* __restrict__ x64) {
+    const int rhs = blockIdx.y;
+    if (!st[rhs].active) return;
+    const double sc = st[rhs].scale;
+    const long long base = (long long)rhs * ndof;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q < ndof) x64[base + q] += sc * (double)d32[base + q];
+    }
+}
+
+void launch_to_inner(long long ndof, int nrhs, const RhsState* st, const double* r64, float* r32, hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL(k_to_inner, dim3(chunks_of(ndof), nrhs), dim3(256), 0, s, ndof, st, r64, r32);
+}
+void launch_correct(long long ndof, int nrhs, const RhsState* st, const float* d32, double* x64, hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL(k_correct, dim3(chunks_of(ndof), nrhs), dim3(256), 0, s, ndof, st, d32, x64);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* x, T v, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+template <typename T>
+void launch_fill(T* x, T v, long long n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, v, n);
+}
+template void launch_fill<double>(double*, double, long long, hipStream_t);
+template void launch_fill<float>(float*, float, long long, hipStream_t);
+
+__global__ __launch_bounds__(256) void k_copy(const double* __restrict__ a, double* __restrict__ b, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+void launch_copy(const double* a, double* b, long long n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_dscale(const LevelDev<double>* __restrict__ L, int E0, int E1, int E2,
+                                                long long ndof, const double* __restrict__ x, double* __restrict__ y) {
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q < ndof) y[q] = x[q] / sqrt(diag_at<double, N>(*L, E0, E1, E2, q));
+}
+void launch_dscale(const LevelHost& L, const LevelDev<double>* dev, const double* x, double* y, hipStream_t s) {
+    const unsigned grid = (unsigned)((L.ndof + 255) / 256);
+#define DG_DS(NN) \
+    case NN: hipLaunchKernelGGL((k_dscale<NN>), dim3(grid), dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, x, y); break;
+    switch (L.n) { DG_DS(2) DG_DS(3) DG_DS(4) DG_DS(5) DG_DS(6) DG_DS(7) DG_DS(8) }
+#undef DG_DS
+}
+
+__global__ __launch_bounds__(256) void k_axpby(long long n, double a, const double* __restrict__ x, double b,
+                                               double* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, x, b, y);
+}
+
+// ---------------------------------------------------------------------------
+// exchange: W_k = sum_s phi_s v_ks and partial sums of w_node rho_ij v_ij
+
+constexpr int XMAX_ORB = 32;
+
+template <int N>
+__global__ __launch_bounds__(256) void k_exchange(const LevelDev<double>* __restrict__ L, int E0, int E1, int E2,
+                                                  long long ndof, int norb, const double* __restrict__ phi,
+                                                  const double* __restrict__ v, double* __restrict__ W,
+                                                  double* __restrict__ partial, int pstride) {
+    constexpr int N3 = N * N * N;
+    __shared__ double red[4];
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool ok = q < ndof;
+    double ph[XMAX_ORB], w[XMAX_ORB];
+    double wq = 0.0;
+    if (ok) {
+        const int l = (int)(q % N3);
+        const int i = l % N, j = (l / N) % N, k = l / (N * N);
+        wq = L->ax[0].m[i] * L->ax[1].m[j] * L->ax[2].m[k];
+    }
+    for (int a = 0; a < norb; ++a) {
+        ph[a] = ok ? phi[(long long)a * ndof + q] : 0.0;
+        w[a] = 0.0;
+    }
+    int pidx = 0;
+    for (int a = 0; a < norb; ++a) {
+        for (int b = a; b < norb; ++b, ++pidx) {
+            const double vv = ok ? v[(long long)pidx * ndof + q] : 0.0;
+            w[a] += ph[b] * vv;
+            if (b != a) w[b] += ph[a] * vv;
+            const double s = block_sum<256>(wq * ph[a] * ph[b] * vv, red);
+            if (threadIdx.x == 0) partial[(long long)pidx * pstride + blockIdx.x] = s;
+            __syncthreads();
+        }
+    }
+    if (ok)
+        for (int a = 0; a < norb; ++a) W[(long long)a * ndof + q] = w[a];
+}
+
+void launch_exchange(const LevelHost& L, const LevelDev<double>* dev, int norb, const double* phi, const double* v,
+                     double* W, double* partial, int pstride, hipStream_t s) {
+    const unsigned grid = (unsigned)((L.ndof + 255) / 256);
+#define DG_X(NN)                                                                                                   \
+    case NN:                                                                                                       \
+        hipLaunchKernelGGL((k_exchange<NN>), dim3(grid), dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, norb, \
+                           phi, v, W, partial, pstride);                                                           \
+        break;
+    switch (L.n) { DG_X(2) DG_X(3) DG_X(4) DG_X(5) DG_X(6) DG_X(7) DG_X(8) }
+#undef DG_X
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int pstride, int nblk,
+                                                      double* __restrict__ K) {
+    __shared__ double red[256];
+    const int qd = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) acc += partial[(long long)qd * pstride + i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) K[qd] = red[0];
+}
+void launch_sum_partials(int nq, const double* partial, int pstride, int nblk, double* K, hipStream_t s) {
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_sum_partials, dim3(nq), dim3(256), 0, s, partial, pstride, nblk, K);
+}
+
+}  // namespace dg

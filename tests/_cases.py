@@ -1,0 +1,67 @@
+"""Shared helpers of the GPU parity tests (inputs for both sides, comparisons).
+
+Inputs come from ``workloads`` evaluated at each side's own node coordinates:
+the oracle computes its nodes, the library reports its own through
+dg_mesh_coords.  Expected values come only from ``oracle``.
+"""
+import numpy as np
+
+from oracle import fdm, layout, mg, sipdg
+
+PARITY_RTOL = 1e-11      # residual tolerance at which parity is claimed (oracle study: both bars met)
+POT_BAR = 1e-8           # relative M-weighted L2 error of potentials
+ENERGY_BAR = 1e-10       # hartree
+
+
+def oracle_axes(mesh):
+    return sipdg.make_axes(mesh.E, mesh.p, mesh.lo, mesh.hi)
+
+
+def oracle_grid(axes):
+    X, Y, Z = np.broadcast_arrays(*sipdg.node_grid(axes))
+    return X, Y, Z
+
+
+def oracle_faces(axes, fn):
+    """Face list of fn(x, y, z) at the oracle's boundary nodes."""
+    X, Y, Z = oracle_grid(axes)
+    fx, fy, fz = (layout.boundary_faces_of(A) for A in (X, Y, Z))
+    return [fn(fx[f], fy[f], fz[f]) for f in range(6)]
+
+
+def to_em(u, mesh):
+    return layout.to_element_major(u, mesh.E, mesh.p + 1)
+
+
+def from_em(u, mesh):
+    return layout.to_global(u, mesh.E, mesh.p + 1)
+
+
+def rel_l2_M(axes, mesh, v_em, ref_global):
+    """M-weighted relative L2 distance of an element-major field from a global reference."""
+    M = sipdg.mass(axes)
+    v = from_em(np.asarray(v_em), mesh)
+    return float(np.sqrt(np.sum(M * (v - ref_global) ** 2) / np.sum(M * ref_global ** 2)))
+
+
+def gpu_sample(ctx, mesh_id, dens):
+    """rho (field order) and g (face order) of a closed-form density at the library's nodes."""
+    xyz, fxyz = ctx.mesh_coords(mesh_id)
+    rho = dens.density(xyz[0], xyz[1], xyz[2])
+    g = dens.potential(fxyz[0], fxyz[1], fxyz[2])
+    return rho, g
+
+
+def oracle_density_problem(mesh, dens):
+    axes = oracle_axes(mesh)
+    X, Y, Z = oracle_grid(axes)
+    rho = dens.density(X, Y, Z)
+    faces = oracle_faces(axes, dens.potential)
+    b = sipdg.rhs(axes, rho, faces)
+    return axes, rho, faces, b
+
+
+def level_axes(mesh, n_levels, level):
+    specs = mg.hierarchy(mesh.E, mesh.p, n_levels)
+    E, p = specs[level]
+    return sipdg.make_axes(E, p, mesh.lo, mesh.hi), E, p

@@ -1,0 +1,235 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: operator, transfers, right-hand side and coarsest solve agree with the
+oracle to FP64 rounding (relative 1e-12); smoother bounds and one V-cycle to
+1e-9 (Lanczos in a different summation order); full solves are compared with
+the exact (fast-diagonalisation) solution at the parity tolerance 1e-11:
+relative M-weighted L2 error <= 1e-8 and pair energies within 1e-10 Ha.
+"""
+import numpy as np
+import pytest
+
+from oracle import exchange as ox, fdm, layout, mg, pcg, sipdg
+from workloads import configs, gaussians
+
+from _cases import (ENERGY_BAR, PARITY_RTOL, POT_BAR, from_em, gpu_sample, level_axes, oracle_axes,
+                    oracle_density_problem, oracle_faces, oracle_grid, rel_l2_M, to_em)
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (E, p, lo, hi, n_levels)
+    ((4, 6, 2), 4, (-2.0, -3.0, -1.0), (2.0, 3.0, 1.0), 0),     # N=5, bricks 2^3
+    ((5, 3, 7), 3, (-2.5, -1.0, -3.0), (2.5, 2.0, 4.0), 0),     # N=4, partial bricks
+    ((6, 5, 3), 2, (0.0, 0.0, 0.0), (3.0, 2.5, 1.5), 0),        # N=3, bricks 4^3, partial
+    ((3, 2, 2), 6, (-1.0, -1.0, -1.0), (2.0, 1.0, 1.0), 0),     # N=7, one-element bricks
+    ((2, 2, 1), 7, (-1.0, -1.0, -0.5), (1.0, 1.0, 0.5), 0),     # N=8, single element along z
+    ((8, 8, 8), 1, (-4.0, -4.0, -4.0), (4.0, 4.0, 4.0), 2),     # p=1 fine level, mesh coarsening
+]
+
+
+def _mesh(c):
+    E, p, lo, hi, _ = c
+    return configs.Mesh(E, p, lo, hi)
+
+
+def _ctx(gpu_lib, cases, **kw):
+    return gpu_lib.Context([(c[0], c[1], c[2], c[3]) for c in cases], n_levels=cases[0][4], **kw)
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"E{c[0]}p{c[1]}" for c in CASES])
+def test_operator_apply_all_levels(gpu_lib, case):
+    mesh = _mesh(case)
+    ctx = _ctx(gpu_lib, [case])
+    nl = ctx.info[0]["n_levels"]
+    assert nl == len(mg.hierarchy(mesh.E, mesh.p, case[4] or None))
+    rng = np.random.default_rng(11)
+    for level in range(nl):
+        axes, E, p = level_axes(mesh, case[4] or None, level)
+        n = p + 1
+        nrhs = 3
+        u = rng.standard_normal((nrhs, int(np.prod(E)) * n ** 3))
+        y = _n(ctx.operator_apply(_t(u), level=level)).reshape(nrhs, -1)
+        for r in range(nrhs):
+            ref = layout.to_element_major(sipdg.apply(axes, layout.to_global(u[r], E, n)), E, n)
+            assert np.abs(y[r] - ref).max() <= 1e-12 * np.abs(ref).max(), (level, r)
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=[f"E{c[0]}p{c[1]}" for c in CASES[:3]])
+def test_rhs_assembly(gpu_lib, case):
+    mesh = _mesh(case)
+    ctx = _ctx(gpu_lib, [case])
+    axes = oracle_axes(mesh)
+    rng = np.random.default_rng(12)
+    nrhs = 2
+    NX, NY, NZ = (axes[d].N for d in range(3))
+    rho = rng.standard_normal((nrhs, NZ, NY, NX))
+    faces = [[rng.standard_normal(s) for s in [(NZ, NY)] * 2 + [(NZ, NX)] * 2 + [(NY, NX)] * 2] for _ in range(nrhs)]
+    rho_em = np.concatenate([to_em(rho[r], mesh) for r in range(nrhs)])
+    g = np.concatenate([layout.join_faces(faces[r]) for r in range(nrhs)])
+    b = _n(ctx.rhs_assemble(_t(rho_em), _t(g))).reshape(nrhs, -1)
+    for r in range(nrhs):
+        ref = to_em(sipdg.rhs(axes, rho[r], faces[r]), mesh)
+        assert np.abs(b[r] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"E{c[0]}p{c[1]}" for c in CASES])
+def test_coarse_solve_and_transfers(gpu_lib, case):
+    mesh = _mesh(case)
+    ctx = _ctx(gpu_lib, [case])
+    H = mg.Hierarchy(mesh.E, mesh.p, mesh.lo, mesh.hi, n_levels=case[4] or None)
+    rng = np.random.default_rng(13)
+    # coarsest exact solve
+    Lc = H.levels[-1]
+    r = rng.standard_normal(Lc.shape)
+    z = _n(ctx.coarse_solve(_t(layout.to_element_major(r, Lc.E, Lc.n))))
+    ref = layout.to_element_major(H.coarse.solve(r), Lc.E, Lc.n)
+    assert np.abs(z - ref).max() <= 1e-11 * np.abs(ref).max()
+    # restriction and prolongation between every pair of levels
+    for l in range(len(H.levels) - 1):
+        F, C = H.levels[l], H.levels[l + 1]
+        rf = rng.standard_normal(F.shape)
+        rc = _n(ctx.restrict(_t(layout.to_element_major(rf, F.E, F.n)), level=l))
+        ref = layout.to_element_major(H.restrict(l, rf), C.E, C.n)
+        assert np.abs(rc - ref).max() <= 1e-12 * np.abs(ref).max()
+        zc = rng.standard_normal(C.shape)
+        zf0 = rng.standard_normal(F.shape)
+        zf = _n(ctx.prolong_add(_t(layout.to_element_major(zc, C.E, C.n)),
+                                _t(layout.to_element_major(zf0, F.E, F.n)), level=l))
+        ref = layout.to_element_major(zf0 + H.prolong(l, zc), F.E, F.n)
+        assert np.abs(zf - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"E{c[0]}p{c[1]}" for c in CASES])
+def test_smoother_bounds_and_vcycle(gpu_lib, case):
+    mesh = _mesh(case)
+    ctx = _ctx(gpu_lib, [case])
+    H = mg.Hierarchy(mesh.E, mesh.p, mesh.lo, mesh.hi, n_levels=case[4] or None)
+    for l in range(len(H.levels) - 1):
+        li = ctx.level_info(0, l)
+        assert abs(li["lam_hi"] - H.lam[l][1]) <= 1e-9 * H.lam[l][1]
+        assert abs(li["lam_lo"] - H.lam[l][0]) <= 1e-9 * H.lam[l][0]
+    L0 = H.levels[0]
+    r = np.random.default_rng(14).standard_normal(L0.shape)
+    z = _n(ctx.vcycle(_t(layout.to_element_major(r, L0.E, L0.n))))
+    ref = layout.to_element_major(H.vcycle(r), L0.E, L0.n)
+    assert np.abs(z - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_single_gaussian_solve_matches_exact_and_closed_form(gpu_lib):
+    wl = configs.single()
+    mesh, dens = wl.meshes[0], wl.batch.densities[0]
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol)
+    rho, g = gpu_sample(ctx, 0, dens)
+    v, st = ctx.solve_batch(_t(rho), _t(g))
+    axes, rho_o, faces, b = oracle_density_problem(mesh, dens)
+    v_ex = fdm.FDM(axes).solve(b)
+    assert rel_l2_M(axes, mesh, _n(v), v_ex) <= POT_BAR
+    assert st[0]["status"] == 0 and st[0]["rel_residual"] <= wl.rtol
+    H = mg.Hierarchy(mesh.E, mesh.p, mesh.lo, mesh.hi, n_levels=wl.n_levels)
+    _, it_o, _, _ = pcg.solve(H, b, rtol=wl.rtol)
+    assert abs(st[0]["iters"] - it_o) <= 1
+    X, Y, Z = oracle_grid(axes)
+    err = rel_l2_M(axes, mesh, _n(v), dens.potential(X, Y, Z))
+    assert 1e-2 < err < 4e-2   # discretisation error against erf(sqrt(a) r)/r
+
+
+def test_batch_over_two_meshes_interleaved(gpu_lib):
+    wl = configs.scaled(4, 4, 3, seed=21)
+    m0 = wl.meshes[0]
+    m1 = configs.Mesh((6, 4, 4), 3, (-3.0, -2.0, -2.0), (3.0, 2.0, 2.0))
+    ctx = gpu_lib.Context([(m.E, m.p, m.lo, m.hi) for m in (m0, m1)], rtol=PARITY_RTOL)
+    ids = [0, 1, 0, 1, 1]
+    dens = [wl.batch.densities[k % 3] for k in range(len(ids))]
+    rho, g = [], []
+    for k, mid in enumerate(ids):
+        r_, g_ = gpu_sample(ctx, mid, dens[k])
+        rho.append(r_); g.append(g_)
+    v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)), mesh_ids=ids)
+    v = _n(v)
+    off = 0
+    for k, mid in enumerate(ids):
+        mesh = (m0, m1)[mid]
+        axes, _, _, b = oracle_density_problem(mesh, dens[k])
+        n = ctx.info[mid]["n_dofs"]
+        assert rel_l2_M(axes, mesh, v[off:off + n], fdm.FDM(axes).solve(b)) <= POT_BAR
+        assert st[k]["status"] == 0
+        off += n
+
+
+def test_zero_and_empty_right_hand_sides(gpu_lib):
+    mesh = configs.Mesh((4, 4, 4), 2, (-1.0,) * 3, (1.0,) * 3)
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)])
+    nd, nf = ctx.info[0]["n_dofs"], ctx.info[0]["n_face"]
+    v, st = ctx.solve_batch(_t(np.zeros(nd)), _t(np.zeros(nf)))
+    assert np.all(_n(v) == 0.0) and st[0]["iters"] == 0
+    v, st = ctx.solve_batch(_t(np.zeros(0)), _t(np.zeros(0)), mesh_ids=[])
+    assert v.numel() == 0 and st == []
+
+
+def test_invalid_arguments_are_rejected(gpu_lib):
+    with pytest.raises(gpu_lib.DgError):
+        gpu_lib.Context([((4, 4, 4), 9, (0,) * 3, (1,) * 3)])
+    with pytest.raises(gpu_lib.DgError):
+        gpu_lib.Context([((4, 4, 4), 2, (0,) * 3, (0,) * 3)])
+    ctx = gpu_lib.Context([((4, 4, 4), 2, (0,) * 3, (1,) * 3)])
+    code = gpu_lib.lib.dg_mesh_info(ctx._h, 5, None, None, None)
+    assert code == -1
+
+
+def _small_exchange_case():
+    prims = gaussians.Primitives([0.6, 1.4, 0.9, 0.45, 2.0],
+                                 [[0.4, 0, 0], [0.4, 0, 0], [-0.5, 0.2, 0.1], [-0.5, 0.2, 0.1], [0.1, -0.6, 0.3]])
+    rng = np.random.default_rng(5)
+    C = gaussians.lowdin(rng.standard_normal((5, 3)), prims.overlap())
+    return gaussians.Orbitals(prims, C), configs.Mesh((6, 6, 6), 4, (-5.0,) * 3, (5.0,) * 3)
+
+
+def test_exchange_matches_oracle(gpu_lib):
+    orb, mesh = _small_exchange_case()
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=PARITY_RTOL)
+    xyz, fxyz = ctx.mesh_coords(0)
+    phi = orb.values(xyz[0], xyz[1], xyz[2])
+    g = orb.pair_potentials(fxyz[0], fxyz[1], fxyz[2])
+    W, K, EX, st, v = ctx.exchange(_t(phi.reshape(-1)), _t(g.reshape(-1)), keep_potentials=True)
+    axes = oracle_axes(mesh)
+    X, Y, Z = oracle_grid(axes)
+    phi_o = list(orb.values(X, Y, Z))
+    fp = [[None] * 6 for _ in orb.pairs()]
+    for f, vals in enumerate(oracle_faces(axes, lambda a, b_, c: orb.pair_potentials(a.reshape(-1), b_.reshape(-1), c.reshape(-1)))):
+        for q in range(len(vals)):
+            fp[q][f] = vals[q].reshape(axes[2].N if f < 4 else axes[1].N, -1)
+    F = fdm.FDM(axes)
+    v_o, W_o, K_o, EX_o = ox.exchange(axes, phi_o, fp, F.solve)
+    K = _n(K)
+    assert np.abs(K - K_o).max() <= ENERGY_BAR
+    assert abs(EX - EX_o) <= 3 * ENERGY_BAR
+    W = _n(W).reshape(3, -1)
+    v = _n(v).reshape(len(K), -1)
+    for q in range(len(K)):
+        assert rel_l2_M(axes, mesh, v[q], v_o[q]) <= POT_BAR
+    for k in range(3):
+        assert rel_l2_M(axes, mesh, W[k], W_o[k]) <= POT_BAR
+    assert all(s["status"] == 0 for s in st)
+
+
+def test_mixed_precision_refinement_reaches_fp64_accuracy(gpu_lib):
+    wl = configs.scaled(6, 4, 2, seed=31)
+    mesh = wl.meshes[0]
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=PARITY_RTOL, precision="fp32_ir")
+    rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+    v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
+    v = _n(v).reshape(2, -1)
+    for k, d in enumerate(wl.batch.densities):
+        axes, _, _, b = oracle_density_problem(mesh, d)
+        assert rel_l2_M(axes, mesh, v[k], fdm.FDM(axes).solve(b)) <= POT_BAR
+        assert st[k]["status"] == 0 and st[k]["outer_iters"] >= 2
