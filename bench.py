@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Benchmark: Poisson right-hand sides solved per second at FP64 relative residual 1e-8.
+
+Workload (default ``exchange8``): the exchange step of 8 Loewdin-orthonormal
+orbitals on a 16x16x16-element, degree-4 auxiliary mesh (512,000 nodes) --
+all 36 pair densities rho_ij = phi_i phi_j as Poisson right-hand sides with
+closed-form Dirichlet data, solved to 1e-8 by 4-level hp-multigrid PCG, then
+W_k, K_ij and E_x.  One step = one dg_exchange_apply call (RHS assembly, the
+batched solve and the exchange reductions) with all inputs resident in HBM.
+
+Arms: ``fp32_ir`` (FP32 inner PCG inside FP64 iterative refinement; the
+headline ``value``) and ``fp64`` (plain FP64 MG-PCG; reported beside it).
+
+Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="exchange8", choices=["exchange8", "exchange16"])
+    ap.add_argument("--arms", default="fp32_ir,fp64")
+    ap.add_argument("--cpu-sample", type=int, default=2, help="pair solves timed on the oracle (0: skip)")
+    ap.add_argument("--check-sample", type=int, default=4, help="pairs compared with the exact solve (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run 3 device-to-device copies of this many MiB (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2510_21213_amd import binding
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    wl = configs.exchange8() if args.config == "exchange8" else configs.exchange16()
+    mesh = wl.meshes[0]
+    orb = wl.orbitals
+    norb = orb.norb
+    npairs = norb * (norb + 1) // 2
+    arms = [a for a in args.arms.split(",") if a]
+    results = {}
+    first_ctx = None
+    for arm in arms:
+        ctx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
+                              precision=arm)
+        if first_ctx is None:
+            xyz, fxyz = ctx.mesh_coords(0)
+            phi = torch.as_tensor(orb.values(xyz[0], xyz[1], xyz[2]).reshape(-1)).cuda()
+            g = torch.as_tensor(orb.pair_potentials(fxyz[0], fxyz[1], fxyz[2]).reshape(-1)).cuda()
+            first_ctx = ctx
+        for _ in range(args.warmup):
+            ctx.exchange(phi, g)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        iters, outer, res = [], [], []
+        for _ in range(args.steps):
+            W, K, EX, st, _ = ctx.exchange(phi, g)
+            iters += [s["iters"] for s in st]
+            outer += [s["outer_iters"] for s in st]
+            res += [s["rel_residual"] for s in st]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        dt = t1 - t0
+        results[arm] = {
+            "value": npairs * args.steps / dt,
+            "ms_per_step": 1e3 * dt / args.steps,
+            "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
+            "outer_mean": float(np.mean(outer)),
+            "max_rel_residual": float(np.max(res)),
+            "E_x": EX,
+            "prof": prof,
+            "ctx": ctx,
+        }
+
+    head = results.get("fp32_ir") or results[arms[0]]
+    head_arm = "fp32_ir" if "fp32_ir" in results else arms[0]
+    prof = head["prof"]
+    achieved = prof["bytes"] / prof["seconds"] / 1e9 if prof["seconds"] > 0 else None
+    roofline = {
+        "bound": "hbm",
+        "kernel": "finest-level Chebyshev smoothing step (k_brick, N=5, BM_CHEB/BM_CHEBDOT, "
+                  + ("float" if head_arm == "fp32_ir" else "double") + ")",
+        "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+        "traffic": None,
+        "avg_launch_us": 1e6 * prof["seconds"] / max(1, prof["launches"]),
+        "launches": prof["launches"],
+    }
+
+    cpu = None
+    check = None
+    if args.cpu_sample > 0 or args.check_sample > 0:
+        cpu, check = cpu_leg(args, wl, results, phi, g, npairs)
+
+    arms_out = {a: {k: v for k, v in r.items() if k not in ("prof", "ctx")} for a, r in results.items()}
+    for a, r in results.items():
+        p = r["prof"]
+        arms_out[a]["cheb_step_GBs"] = p["bytes"] / p["seconds"] / 1e9 if p["seconds"] > 0 else None
+    line = {
+        "metric": "Poisson RHS solved/sec at 1e-8 rel. residual: learned+mixed vs plain FP64 MG-PCG",
+        "value": head["value"],
+        "unit": "RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head_arm == "fp32_ir" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {npairs} pair-density RHS, {mesh.E[0]}^3 elements p={mesh.p} "
+                               f"({first_ctx.info[0]['n_dofs']} DOFs/RHS), {wl.n_levels}-level MG-PCG to {wl.rtol}",
+                   "arm": head_arm, "learned_guess": False, "parallelism": "single GPU"},
+        "arms": arms_out,
+        "fp64_vs_mixed_speedup": (results["fp32_ir"]["value"] / results["fp64"]["value"])
+        if "fp32_ir" in results and "fp64" in results else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "check_vs_exact": check,
+    }
+    print(json.dumps(line))
+
+
+def cpu_leg(args, wl, results, phi, g, npairs):
+    """Oracle timing on the host cores, and the GPU potentials against the exact solve."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_info
+
+    from oracle import fdm, layout, mg, pcg, sipdg
+
+    mesh = wl.meshes[0]
+    orb = wl.orbitals
+    axes = sipdg.make_axes(mesh.E, mesh.p, mesh.lo, mesh.hi)
+    X, Y, Z = np.broadcast_arrays(*sipdg.node_grid(axes))
+    fx, fy, fz = (layout.boundary_faces_of(A) for A in (X, Y, Z))
+    phi_o = orb.values(X, Y, Z)
+    pairs = orb.pairs()
+    sample = list(range(0, npairs, max(1, npairs // max(1, max(args.cpu_sample, args.check_sample)))))
+
+    def problem(q):
+        i, j = pairs[q]
+        faces = []
+        for f in range(6):
+            vals = orb.pair_potentials(fx[f].reshape(-1), fy[f].reshape(-1), fz[f].reshape(-1))[q]
+            faces.append(vals.reshape(fx[f].shape))
+        return sipdg.rhs(axes, phi_o[i] * phi_o[j], faces)
+
+    cpu = None
+    if args.cpu_sample > 0:
+        H = mg.Hierarchy(mesh.E, mesh.p, mesh.lo, mesh.hi, n_levels=wl.n_levels)
+        qs = sample[:args.cpu_sample]
+        bs = [problem(q) for q in qs]
+        t0 = time.perf_counter()
+        its = []
+        for b in bs:
+            _, it, _, _ = pcg.solve(H, b, rtol=wl.rtol)
+            its.append(it)
+        dt = time.perf_counter() - t0
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        cpu = {"value": len(qs) / dt, "unit": "RHS/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(qs)} of {npairs} pair solves (pairs {qs}), oracle MG-PCG FP64 to {wl.rtol}, "
+                         f"iterations {its}; set-up excluded"}
+    check = None
+    if args.check_sample > 0:
+        out = {}
+        for arm, r in results.items():
+            ctx = r["ctx"]
+            _, _, _, _, v = ctx.exchange(phi, g, keep_potentials=True)
+            v = v.cpu().numpy().reshape(npairs, -1)
+            M = sipdg.mass(axes)
+            F = fdm.FDM(axes)
+            errs = []
+            for q in sample[:args.check_sample]:
+                ref = F.solve(problem(q))
+                got = layout.to_global(v[q], mesh.E, mesh.p + 1)
+                errs.append(float(np.sqrt(np.sum(M * (got - ref) ** 2) / np.sum(M * ref ** 2))))
+            out[arm] = {"pairs": sample[:args.check_sample], "max_rel_L2_err_vs_exact": max(errs)}
+        check = out
+    return cpu, check
+
+
+if __name__ == "__main__":
+    main()

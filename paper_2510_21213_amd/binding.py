@@ -63,6 +63,8 @@ def _load():
         "dg_restrict": (I, [P, I, I, I, P, P, P]),
         "dg_prolong_add": (I, [P, I, I, I, P, P, P]),
         "dg_level_info": (I, [P, I, I, P, P, P, P]),
+        "dg_profile_enable": (I, [P, I]),
+        "dg_profile_read": (I, [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -197,6 +199,15 @@ class Context:
                                      ctypes.byref(ex), _ptr(v), stats, _stream())
         _check(code, "exchange_apply", allow_warn=True)
         return W, K, ex.value, [_stats(stats[i]) for i in range(npairs)], v
+
+    # ---- timing of the finest-level Chebyshev step
+    def profile(self, enable=True):
+        _check(lib.dg_profile_enable(self._h, 1 if enable else 0), "profile_enable")
+
+    def profile_read(self):
+        n, sec, by = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        _check(lib.dg_profile_read(self._h, ctypes.byref(n), ctypes.byref(sec), ctypes.byref(by)), "profile_read")
+        return {"launches": n.value, "seconds": sec.value, "bytes": by.value}
 
     # ---- single steps
     def operator_apply(self, u, mesh_id=0, level=0):

@@ -109,6 +109,14 @@ struct dg_ctx {
         int cap_b = 0, cap_st = 0;
     };
     std::vector<Mesh> meshes;
+    // timing of the finest-level Chebyshev step
+    struct Prof {
+        bool on = false;
+        std::vector<hipEvent_t> ev;  // start/stop pairs
+        size_t used = 0;
+        long long launches = 0;
+        double seconds = 0.0, bytes = 0.0;
+    } prof;
     // exchange work space
     double* xv = nullptr;
     long long xv_cap = 0;
@@ -180,9 +188,34 @@ const dg::LevelDev<float>* ldev<float>(const LevelHost& L) { return L.dev32; }
 // W.za[l] already holds the first smoothing iterate c0 D^-1 f.  Returns the
 // buffer that holds z = B f.  With dot, the last smoothing step at level 0
 // also writes partial sums of f.z.
+dg_ctx::Prof* g_prof = nullptr;  // profiling state of the context being driven (one host thread per context)
+
+void prof_mark(hipStream_t s) {
+    auto& P = *g_prof;
+    if (P.used == P.ev.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        P.ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(P.ev[P.used++], s));
+}
+
+// Called after the stream has been synchronised: add up the timed launches.
+void prof_collect() {
+    auto& P = *g_prof;
+    for (size_t i = 0; i + 1 < P.used; i += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, P.ev[i], P.ev[i + 1]));
+        P.seconds += 1e-3 * ms;
+        P.launches += 1;
+    }
+    P.used = 0;
+}
+
 template <typename T>
 T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T* f, bool z1_ready, bool dot,
           hipStream_t s) {
+    const bool timed = l == 0 && g_prof && g_prof->on;
     const int L = (int)M.lv.size();
     const LevelHost& Lv = M.lv[l];
     if (l == L - 1) {
@@ -196,8 +229,10 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
     T* cur = W.za[l];
     T* prev = W.zb[l];
     for (int k = 1; k < m; ++k) {
+        if (timed) prof_mark(s);
         dg::launch_brick<T>(dg::BM_CHEB, Lv, dv, nrhs, st, cur, nullptr, f, k == 1 ? nullptr : prev, prev, nullptr,
                             nullptr, 0, C.cp[k - 1], C.cr[k - 1], s);
+        if (timed) prof_mark(s);
         std::swap(cur, prev);
     }
     const LevelHost& Lc = M.lv[l + 1];
@@ -211,8 +246,10 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
         const int mode = (dot && last) ? dg::BM_CHEBDOT : dg::BM_CHEB;
         const double cp = k == 0 ? 0.0 : C.cp[k - 1];
         const double cr = k == 0 ? C.c0 : C.cr[k - 1];
+        if (timed) prof_mark(s);
         dg::launch_brick<T>(mode, Lv, dv, nrhs, st, cur, nullptr, f, k == 0 ? nullptr : prev, prev, nullptr,
                             M.partial, M.pstride, cp, cr, s);
+        if (timed) prof_mark(s);
         std::swap(cur, prev);
     }
     return cur;
@@ -281,9 +318,19 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         for (int c = 0; c < every && it < maxit; ++c, ++it) pcg_iteration<T>(M, W, nrhs, st, it & 1, s);
         HIPCHK(hipGetLastError());
         read_state(M, st, nrhs, s);
+        if (g_prof && g_prof->on) prof_collect();
         bool any = false;
         for (int i = 0; i < nrhs; ++i) any |= M.st_host[i].active != 0;
         if (!any) break;
+    }
+    if (g_prof && g_prof->on) {
+        // algorithmic bytes of the timed steps: per V-cycle, pre-smoothing steps 1..m-1 and post-smoothing
+        // steps 0..m-1 read u and f, the steps with a previous iterate also read it, and all write one vector
+        const int m = (int)M.cheb[0].cp.size() + 1;
+        const double per_cycle = (m >= 2 ? 3.0 + 4.0 * (m - 2) : 0.0) + 3.0 + 4.0 * (m - 1);
+        long long cycles = 0;
+        for (int i = 0; i < nrhs; ++i) cycles += M.st_host[i].iters;
+        g_prof->bytes += per_cycle * (double)cycles * (double)L0.ndof * sizeof(T);
     }
 }
 
@@ -629,6 +676,7 @@ void dg_poisson_destroy(dg_ctx* ctx) {
         dfree(M.st_in);
         if (M.st_host) (void)hipHostFree(M.st_host);
     }
+    for (auto e : ctx->prof.ev) (void)hipEventDestroy(e);
     dfree(ctx->xv);
     dfree(ctx->xpart);
     dfree(ctx->xpairs);
@@ -708,6 +756,7 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
                                  const double* x0, double* v, dg_rhs_stats* stats, hipStream_t stream) {
     dg_status st = run_guarded([&] {
         if (!ctx) throw ArgError("null context");
+        g_prof = &ctx->prof;
         if (nrhs < 0) throw ArgError("nrhs must be >= 0");
         if (nrhs == 0) return;
         if (!mesh_id || !rho || !g || !v) throw ArgError("null pointer argument");
@@ -742,6 +791,7 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
                             double* K_pairs, double* E_x, double* v_pairs, dg_rhs_stats* stats, hipStream_t stream) {
     dg_status st = run_guarded([&] {
         check_mesh_id(ctx, mesh_id);
+        g_prof = &ctx->prof;
         if (norb < 1 || norb > 32) throw ArgError("norb must be in 1..32");
         if (!phi || !g_pairs || !W || !K_pairs) throw ArgError("null pointer argument");
         Mesh& M = ctx->meshes[mesh_id];
@@ -834,6 +884,7 @@ dg_status dg_vcycle_apply(dg_ctx* ctx, int mesh_id, int level, int nrhs, const d
         if (nrhs == 0) return;
         ensure_state(M, nrhs);
         ensure_work<double>(M, M.w64, nrhs);
+        g_prof = nullptr;
         double* out = vcycle<double>(M, M.w64, level, nrhs, nullptr, r, false, false, stream);
         HIPCHK(hipMemcpyAsync(z, out, sizeof(double) * M.lv[level].ndof * nrhs, hipMemcpyDeviceToDevice, stream));
         HIPCHK(hipGetLastError());
@@ -873,6 +924,29 @@ dg_status dg_prolong_add(dg_ctx* ctx, int mesh_id, int level, int nrhs, const do
         if (nrhs < 0 || (nrhs > 0 && (!zc || !zf))) throw ArgError("bad arguments");
         dg::launch_prolong<double>(M.lv[level], M.lv[level + 1], nrhs, nullptr, zc, zf, stream);
         HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_profile_enable(dg_ctx* ctx, int enable) {
+    return run_guarded([&] {
+        if (!ctx) throw ArgError("null context");
+        auto& P = ctx->prof;
+        P.on = enable != 0;
+        if (P.on) {
+            P.used = 0;
+            P.launches = 0;
+            P.seconds = 0.0;
+            P.bytes = 0.0;
+        }
+    });
+}
+
+dg_status dg_profile_read(const dg_ctx* ctx, long long* launches, double* seconds, double* bytes) {
+    return run_guarded([&] {
+        if (!ctx) throw ArgError("null context");
+        if (launches) *launches = ctx->prof.launches;
+        if (seconds) *seconds = ctx->prof.seconds;
+        if (bytes) *bytes = ctx->prof.bytes;
     });
 }
 

@@ -127,6 +127,27 @@ __device__ __forceinline__ void axis_row(const AxisDev<T>& A, int e0, int E, con
     }
 }
 
+// Element access through a uniform base pointer and a 32-bit element index
+// (one right-hand side holds far fewer than 2^29 values), so that loads use
+// the scalar-base + 32-bit-offset addressing form.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, uint32_t idx, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
+}
+
+// 1/x: hardware reciprocal, refined by Newton steps to full precision in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 template <typename T>
 struct BrickArgs {
     const LevelDev<T>* L;
@@ -148,145 +169,160 @@ struct BrickArgs {
 
 // Reads one input value (BM_PQ combines u + beta u2).
 template <typename T, int MODE>
-__device__ __forceinline__ T ldin(const T* u, const T* u2, long long idx, T beta) {
+__device__ __forceinline__ T ldin(const T* u, const T* u2, uint32_t idx, T beta) {
     if constexpr (MODE == BM_PQ)
-        return u[idx] + beta * u2[idx];
+        return ld32(u, idx) + beta * ld32(u2, idx);
     else
-        return u[idx];
+        return ld32(u, idx);
 }
 
-// Computes y = A u over the brick.  On return, for column threads (colok),
-// ycol[Z] holds (A u) at the thread's column and ucol[Z] the input values.
-template <typename T, int N, int BE, int MODE>
-__device__ __forceinline__ void brick_apply(const BrickArgs<T>& a, const LevelDev<T>& L, int ex0, int ey0, int ez0,
-                                            const T* u, const T* u2, T beta, T* su, T* sx, T* sy, T* ucol,
-                                            T* ycol) {
-    constexpr int NB = N * BE, NT = NB * NB, SY = NB + 1, SZ = NB * SY, N3 = N * N * N;
-    const int t = threadIdx.x;
-    const int E0 = a.E0, E1 = a.E1, E2 = a.E2;
-    auto eoff = [&](int ex, int ey, int ez) -> long long { return ((long long)(ez * E1 + ey) * E0 + ex) * N3; };
+// Inputs of the operator over one brick, held in registers: the thread's
+// own column along Z (thread (X, Y)), and the neighbour lines of the three
+// rows the thread owns in the face halo: its X row (thread (Yr, Zr)), its Y
+// row (thread (Xr, Zr)) and its Z column.  All of them are loaded before the
+// first barrier so that a work-group pays one round of memory latency.
+template <typename T, int N, int BE>
+struct BrickIn {
+    static constexpr int NB = N * BE;
+    T ucol[NB];
+    T hxl[N], hxr[N], hyl[N], hyr[N], hzl[N], hzr[N];
+};
 
-    // ---- load: thread (X, Y) keeps the brick column along Z
-    const int X = t % NB, Y = t / NB;
-    const int exX = ex0 + X / N, iX = X % N, eyY = ey0 + Y / N, jY = Y % N;
-    const bool colth = t < NT;
-    const bool colok = colth && exX < E0 && eyY < E1;
+// Element indices are clamped into the mesh so that every load is in bounds
+// and needs no branch: values loaded for a row, column or halo line outside
+// the mesh are never read by the operator (axis_row only touches elements
+// below E and neighbours that exist), so they need no masking.
+template <typename T, int N, int BE, int MODE>
+__device__ __forceinline__ void brick_load(int E0, int E1, int E2, int ex0, int ey0, int ez0, const T* u,
+                                           const T* u2, T beta, BrickIn<T, N, BE>& in) {
+    constexpr int NB = N * BE, N2 = N * N, N3 = N * N * N;
+    const int t = threadIdx.x;
+    auto eoff = [&](int ex, int ey, int ez) -> uint32_t {
+        ex = min(ex, E0 - 1);
+        ey = min(ey, E1 - 1);
+        ez = min(ez, E2 - 1);
+        return (uint32_t)((ez * E1 + ey) * E0 + ex) * N3;
+    };
+    const int a0 = (t % NB), a1 = min(t / NB, NB - 1);  // (X, Y) column, (Y, Z) X row, (X, Z) Y row
+    // own column and its Z halo: thread (X, Y) = (a0, a1)
+    {
+        const int ex = ex0 + a0 / N, i = a0 % N, ey = ey0 + a1 / N, j = a1 % N;
+        const uint32_t loc = j * N + i;
 #pragma unroll
-    for (int Z = 0; Z < NB; ++Z) {
-        const int ez = ez0 + Z / N, k = Z % N;
-        T v = 0;
-        if (colok && ez < E2) v = ldin<T, MODE>(u, u2, eoff(exX, eyY, ez) + (k * N + jY) * N + iX, beta);
-        ucol[Z] = v;
-        if (colth) su[Z * SZ + Y * SY + X] = v;
+        for (int b = 0; b < BE; ++b) {
+            const uint32_t o = eoff(ex, ey, ez0 + b) + loc;
+#pragma unroll
+            for (int k = 0; k < N; ++k) in.ucol[b * N + k] = ldin<T, MODE>(u, u2, o + k * N2, beta);
+        }
+        const uint32_t ol = eoff(ex, ey, max(ez0 - 1, 0)) + loc, orr = eoff(ex, ey, ez0 + BE) + loc;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            in.hzl[l] = ldin<T, MODE>(u, u2, ol + l * N2, beta);
+            in.hzr[l] = ldin<T, MODE>(u, u2, orr + l * N2, beta);
+        }
+    }
+    // X row (Yr, Zr) = (a0, a1): neighbour lines along x
+    {
+        const int ey = ey0 + a0 / N, j = a0 % N, ez = ez0 + a1 / N, k = a1 % N;
+        const uint32_t loc = (k * N + j) * N;
+        const uint32_t ol = eoff(max(ex0 - 1, 0), ey, ez) + loc, orr = eoff(ex0 + BE, ey, ez) + loc;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            in.hxl[l] = ldin<T, MODE>(u, u2, ol + l, beta);
+            in.hxr[l] = ldin<T, MODE>(u, u2, orr + l, beta);
+        }
+    }
+    // Y row (Xr, Zr) = (a0, a1): neighbour lines along y
+    {
+        const int ex = ex0 + a0 / N, i = a0 % N, ez = ez0 + a1 / N, k = a1 % N;
+        const uint32_t loc = k * N2 + i;
+        const uint32_t ol = eoff(ex, max(ey0 - 1, 0), ez) + loc, orr = eoff(ex, ey0 + BE, ez) + loc;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            in.hyl[l] = ldin<T, MODE>(u, u2, ol + l * N, beta);
+            in.hyr[l] = ldin<T, MODE>(u, u2, orr + l * N, beta);
+        }
+    }
+}
+
+// Face value and normal derivative of the neighbour lines.
+template <typename T, int N>
+__device__ __forceinline__ void halo_reduce(const AxisDev<T>& A, const T* hl, const T* hr, T& hlu, T& hld, T& hru,
+                                            T& hrd) {
+    hlu = hl[N - 1];
+    hru = hr[0];
+    hld = 0;
+    hrd = 0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+        hld += A.dR[l] * hl[l];
+        hrd += A.dL[l] * hr[l];
+    }
+}
+
+// Computes y = A u over the brick from the loaded inputs.  On return, for
+// column threads with a valid column, ycol[Z] holds (A u) along the column.
+template <typename T, int N, int BE>
+__device__ __forceinline__ void brick_compute(int E0, int E1, int E2, const LevelDev<T>& L, int ex0, int ey0,
+                                              int ez0, const BrickIn<T, N, BE>& in, T* su, T* sx, T* sy, T* ycol) {
+    constexpr int NB = N * BE, NT = NB * NB, SY = NB + 1, SZ = NB * SY;
+    const int t = threadIdx.x;
+    const int a0 = t % NB, a1 = t / NB;
+    if (t < NT) {
+#pragma unroll
+        for (int Z = 0; Z < NB; ++Z) su[Z * SZ + a1 * SY + a0] = in.ucol[Z];
     }
     __syncthreads();
-
     if (t < NT) {
-        // ---- x axis: thread (Yr, Zr) owns brick row along X
-        {
-            const int Yr = t % NB, Zr = t / NB;
-            const int ey = ey0 + Yr / N, j = Yr % N, ez = ez0 + Zr / N, k = Zr % N;
+        {  // x axis: thread (Yr, Zr) = (a0, a1)
+            const int ey = ey0 + a0 / N, j = a0 % N, ez = ez0 + a1 / N, k = a1 % N;
             if (ey < E1 && ez < E2) {
                 T row[NB], out[NB];
 #pragma unroll
-                for (int x = 0; x < NB; ++x) row[x] = su[Zr * SZ + Yr * SY + x];
-                T hlu = 0, hld = 0, hru = 0, hrd = 0;
-                const AxisDev<T>& A = L.ax[0];
-                if (ex0 > 0) {
-                    const long long o = eoff(ex0 - 1, ey, ez) + (k * N + j) * N;
-#pragma unroll
-                    for (int l = 0; l < N; ++l) {
-                        const T v = ldin<T, MODE>(u, u2, o + l, beta);
-                        hld += A.dR[l] * v;
-                        if (l == N - 1) hlu = v;
-                    }
-                }
-                if (ex0 + BE < E0) {
-                    const long long o = eoff(ex0 + BE, ey, ez) + (k * N + j) * N;
-#pragma unroll
-                    for (int l = 0; l < N; ++l) {
-                        const T v = ldin<T, MODE>(u, u2, o + l, beta);
-                        hrd += A.dL[l] * v;
-                        if (l == 0) hru = v;
-                    }
-                }
-                axis_row<T, N, BE>(A, ex0, E0, row, hlu, hld, hru, hrd, out);
+                for (int x = 0; x < NB; ++x) row[x] = su[a1 * SZ + a0 * SY + x];
+                T hlu, hld, hru, hrd;
+                halo_reduce<T, N>(L.ax[0], in.hxl, in.hxr, hlu, hld, hru, hrd);
+                axis_row<T, N, BE>(L.ax[0], ex0, E0, row, hlu, hld, hru, hrd, out);
                 const T sc = L.ax[1].m[j] * L.ax[2].m[k];
 #pragma unroll
-                for (int x = 0; x < NB; ++x) sx[Zr * SZ + Yr * SY + x] = out[x] * sc;
+                for (int x = 0; x < NB; ++x) sx[a1 * SZ + a0 * SY + x] = out[x] * sc;
             }
         }
-        // ---- y axis: thread (Xr, Zr) owns brick row along Y
-        {
-            const int Xr = t % NB, Zr = t / NB;
-            const int ex = ex0 + Xr / N, i = Xr % N, ez = ez0 + Zr / N, k = Zr % N;
+        {  // y axis: thread (Xr, Zr) = (a0, a1)
+            const int ex = ex0 + a0 / N, i = a0 % N, ez = ez0 + a1 / N, k = a1 % N;
             if (ex < E0 && ez < E2) {
                 T row[NB], out[NB];
 #pragma unroll
-                for (int y = 0; y < NB; ++y) row[y] = su[Zr * SZ + y * SY + Xr];
-                T hlu = 0, hld = 0, hru = 0, hrd = 0;
-                const AxisDev<T>& A = L.ax[1];
-                if (ey0 > 0) {
-                    const long long o = eoff(ex, ey0 - 1, ez) + k * N * N + i;
-#pragma unroll
-                    for (int l = 0; l < N; ++l) {
-                        const T v = ldin<T, MODE>(u, u2, o + l * N, beta);
-                        hld += A.dR[l] * v;
-                        if (l == N - 1) hlu = v;
-                    }
-                }
-                if (ey0 + BE < E1) {
-                    const long long o = eoff(ex, ey0 + BE, ez) + k * N * N + i;
-#pragma unroll
-                    for (int l = 0; l < N; ++l) {
-                        const T v = ldin<T, MODE>(u, u2, o + l * N, beta);
-                        hrd += A.dL[l] * v;
-                        if (l == 0) hru = v;
-                    }
-                }
-                axis_row<T, N, BE>(A, ey0, E1, row, hlu, hld, hru, hrd, out);
+                for (int y = 0; y < NB; ++y) row[y] = su[a1 * SZ + y * SY + a0];
+                T hlu, hld, hru, hrd;
+                halo_reduce<T, N>(L.ax[1], in.hyl, in.hyr, hlu, hld, hru, hrd);
+                axis_row<T, N, BE>(L.ax[1], ey0, E1, row, hlu, hld, hru, hrd, out);
                 const T sc = L.ax[0].m[i] * L.ax[2].m[k];
 #pragma unroll
-                for (int y = 0; y < NB; ++y) sy[Zr * SZ + y * SY + Xr] = out[y] * sc;
+                for (int y = 0; y < NB; ++y) sy[a1 * SZ + y * SY + a0] = out[y] * sc;
             }
         }
     }
     __syncthreads();
-
-    // ---- z axis in registers, sum of the three terms
-    if (colok) {
-        T hlu = 0, hld = 0, hru = 0, hrd = 0;
-        const AxisDev<T>& A = L.ax[2];
-        if (ez0 > 0) {
-            const long long o = eoff(exX, eyY, ez0 - 1) + jY * N + iX;
+    {  // z axis in registers: thread (X, Y) = (a0, a1)
+        const int ex = ex0 + a0 / N, i = a0 % N, ey = ey0 + a1 / N, j = a1 % N;
+        if (t < NT && ex < E0 && ey < E1) {
+            T hlu, hld, hru, hrd, out[NB];
+            halo_reduce<T, N>(L.ax[2], in.hzl, in.hzr, hlu, hld, hru, hrd);
+            axis_row<T, N, BE>(L.ax[2], ez0, E2, in.ucol, hlu, hld, hru, hrd, out);
+            const T sc = L.ax[0].m[i] * L.ax[1].m[j];
 #pragma unroll
-            for (int l = 0; l < N; ++l) {
-                const T v = ldin<T, MODE>(u, u2, o + l * N * N, beta);
-                hld += A.dR[l] * v;
-                if (l == N - 1) hlu = v;
-            }
+            for (int Z = 0; Z < NB; ++Z) ycol[Z] = out[Z] * sc + sx[Z * SZ + a1 * SY + a0] + sy[Z * SZ + a1 * SY + a0];
         }
-        if (ez0 + BE < E2) {
-            const long long o = eoff(exX, eyY, ez0 + BE) + jY * N + iX;
-#pragma unroll
-            for (int l = 0; l < N; ++l) {
-                const T v = ldin<T, MODE>(u, u2, o + l * N * N, beta);
-                hrd += A.dL[l] * v;
-                if (l == 0) hru = v;
-            }
-        }
-        T out[NB];
-        axis_row<T, N, BE>(A, ez0, E2, ucol, hlu, hld, hru, hrd, out);
-        const T sc = L.ax[0].m[iX] * L.ax[1].m[jY];
-#pragma unroll
-        for (int Z = 0; Z < NB; ++Z) ycol[Z] = out[Z] * sc + sx[Z * SZ + Y * SY + X] + sy[Z * SZ + Y * SY + X];
     }
 }
 
 template <typename T, int N, int BE, int MODE>
-__global__ __launch_bounds__(wg_of(N* BE* N* BE)) void k_brick(BrickArgs<T> a) {
+__global__ __launch_bounds__(wg_of(N* BE* N* BE), 2) void k_brick(BrickArgs<T> a) {
     constexpr int NB = N * BE, NT = NB * NB, SY = NB + 1, SZ = NB * SY, N3 = N * N * N;
     constexpr int WG = wg_of(NT);
+    constexpr bool HAS_F = MODE == BM_RESID || MODE == BM_RESIDDOT || MODE == BM_CHEB || MODE == BM_CHEBDOT;
+    constexpr bool IS_CHEB = MODE == BM_CHEB || MODE == BM_CHEBDOT;
     __shared__ T su[NB * SZ];
     __shared__ T sx[NB * SZ];
     __shared__ T sy[NB * SZ];
@@ -298,23 +334,52 @@ __global__ __launch_bounds__(wg_of(N* BE* N* BE)) void k_brick(BrickArgs<T> a) {
     if (a.st && !a.st[rhs].active) return;
     const int bx = br % a.nb0, by = (br / a.nb0) % a.nb1, bz = br / (a.nb0 * a.nb1);
     const int ex0 = bx * BE, ey0 = by * BE, ez0 = bz * BE;
+    const int E0 = a.E0, E1 = a.E1, E2 = a.E2;
     const LevelDev<T>& L = *a.L;
     const long long base = (long long)rhs * a.ndof;
     const T* u = a.u + base;
     const T* u2 = (MODE == BM_PQ) ? a.u2 + base : nullptr;
+    const T* fb = HAS_F ? a.f + base : nullptr;
+    const T* zpb = (IS_CHEB && a.zprev) ? a.zprev + base : nullptr;
+    T* ob = a.out + base;
+    T* ob2 = (MODE == BM_PQ) ? a.out2 + base : nullptr;
     T beta = 0;
     if constexpr (MODE == BM_PQ) beta = (T)a.st[rhs].beta;
-
-    T ucol[NB], ycol[NB];
-    brick_apply<T, N, BE, MODE>(a, L, ex0, ey0, ez0, u, u2, beta, su, sx, sy, ucol, ycol);
 
     const int t = threadIdx.x;
     const int X = t % NB, Y = t / NB;
     const int exX = ex0 + X / N, iX = X % N, eyY = ey0 + Y / N, jY = Y % N;
-    const bool colok = t < NT && exX < a.E0 && eyY < a.E1;
+    const bool colok = t < NT && exX < E0 && eyY < E1;
+    auto gidx = [&](int Z) -> uint32_t {
+        return (uint32_t)(((ez0 + Z / N) * E1 + eyY) * E0 + exX) * N3 + ((Z % N) * N + jY) * N + iX;
+    };
+    // clamped index for loads of the thread's column (in bounds for every lane)
+    auto cidx = [&](int Z) -> uint32_t {
+        const int ez = min(ez0 + Z / N, E2 - 1), ey = min(eyY, E1 - 1), ex = min(exX, E0 - 1);
+        return (uint32_t)((ez * E1 + ey) * E0 + ex) * N3 + ((Z % N) * N + jY) * N + iX;
+    };
+
+    BrickIn<T, N, BE> in;
+    brick_load<T, N, BE, MODE>(E0, E1, E2, ex0, ey0, ez0, u, u2, beta, in);
+    T fcol[NB], zpcol[NB];
+    if constexpr (HAS_F) {
+#pragma unroll
+        for (int Z = 0; Z < NB; ++Z) fcol[Z] = ld32(fb, cidx(Z));
+    }
+    if constexpr (IS_CHEB) {
+        if (zpb) {
+#pragma unroll
+            for (int Z = 0; Z < NB; ++Z) zpcol[Z] = ld32(zpb, cidx(Z));
+        } else {
+#pragma unroll
+            for (int Z = 0; Z < NB; ++Z) zpcol[Z] = (T)0;
+        }
+    }
+    T ycol[NB];
+    brick_compute<T, N, BE>(E0, E1, E2, L, ex0, ey0, ez0, in, su, sx, sy, ycol);
+
     double dot = 0.0;
     if (colok) {
-        const int E0 = a.E0, E1 = a.E1, E2 = a.E2;
         const int tx = etype(exX, E0), ty = etype(eyY, E1);
         const T mx = L.ax[0].m[iX], my = L.ax[1].m[jY];
         const T dxm = L.ax[0].Bd[tx][iX] * my, mxdy = mx * L.ax[1].Bd[ty][jY], mxy = mx * my;
@@ -322,28 +387,26 @@ __global__ __launch_bounds__(wg_of(N* BE* N* BE)) void k_brick(BrickArgs<T> a) {
         for (int Z = 0; Z < NB; ++Z) {
             const int ez = ez0 + Z / N, k = Z % N;
             if (ez >= E2) continue;
-            const long long idx = base + ((long long)(ez * E1 + eyY) * E0 + exX) * N3 + (k * N + jY) * N + iX;
+            const uint32_t idx = gidx(Z);
             const T y = ycol[Z];
             if constexpr (MODE == BM_APPLY) {
-                a.out[idx] = y;
+                st32(ob, idx, y);
             } else if constexpr (MODE == BM_RESID || MODE == BM_RESIDDOT) {
-                const T r = a.f[idx] - y;
-                a.out[idx] = r;
+                const T r = fcol[Z] - y;
+                st32(ob, idx, r);
                 if constexpr (MODE == BM_RESIDDOT) dot += (double)r * (double)r;
-            } else if constexpr (MODE == BM_CHEB || MODE == BM_CHEBDOT) {
+            } else if constexpr (IS_CHEB) {
                 const int tz = etype(ez, E2);
                 const T mz = L.ax[2].m[k];
                 const T D = (dxm + mxdy) * mz + mxy * L.ax[2].Bd[tz][k];
-                const T uz = ucol[Z];
-                const T zp = a.zprev ? a.zprev[idx] : (T)0;
-                const T fz = a.f[idx];
-                const T zn = uz + a.cp * (uz - zp) + a.cr * (fz - y) / D;
-                a.out[idx] = zn;
-                if constexpr (MODE == BM_CHEBDOT) dot += (double)fz * (double)zn;
+                const T uz = in.ucol[Z];
+                const T zn = uz + a.cp * (uz - zpcol[Z]) + a.cr * (fcol[Z] - y) * recip(D);
+                st32(ob, idx, zn);
+                if constexpr (MODE == BM_CHEBDOT) dot += (double)fcol[Z] * (double)zn;
             } else if constexpr (MODE == BM_PQ) {
-                a.out2[idx] = ucol[Z];
-                a.out[idx] = y;
-                dot += (double)ucol[Z] * (double)y;
+                st32(ob2, idx, in.ucol[Z]);
+                st32(ob, idx, y);
+                dot += (double)in.ucol[Z] * (double)y;
             }
         }
     }
@@ -433,7 +496,7 @@ __device__ __forceinline__ T trP(const TransferDev& tr, int a, int b) {
 }
 
 template <typename T, int NF, int BE, int NC, bool HC, bool HASZ>
-__global__ __launch_bounds__(wg_of(NF* BE* NF* BE)) void k_restrict(TransferArgs<T> a) {
+__global__ __launch_bounds__(wg_of(NF* BE* NF* BE), 2) void k_restrict(TransferArgs<T> a) {
     constexpr int NB = NF * BE, NT = NB * NB, SY = NB + 1, SZ = NB * SY, N3 = NF * NF * NF;
     constexpr int CBE = HC ? BE / 2 : BE;  // coarse elements per brick edge
     constexpr int NCB = CBE * NC;          // coarse nodes per brick edge
@@ -458,23 +521,24 @@ __global__ __launch_bounds__(wg_of(NF* BE* NF* BE)) void k_restrict(TransferArgs
     const bool colok = t < NT && exX < a.E0 && eyY < a.E1;
     const int E0 = a.E0, E1 = a.E1, E2 = a.E2;
 
-    T rcol[NB];
-    if constexpr (HASZ) {
-        BrickArgs<T> ba;
-        ba.E0 = E0; ba.E1 = E1; ba.E2 = E2;
-        T ucol[NB];
-        brick_apply<T, NF, BE, BM_APPLY>(ba, *a.Lf, ex0, ey0, ez0, a.z + base, nullptr, (T)0, su, sx, sy, ucol, rcol);
-    }
+    T rcol[NB], fcol[NB];
+    BrickIn<T, NF, BE> in;
+    if constexpr (HASZ) brick_load<T, NF, BE, BM_APPLY>(E0, E1, E2, ex0, ey0, ez0, a.z + base, nullptr, (T)0, in);
 #pragma unroll
     for (int Z = 0; Z < NB; ++Z) {
         const int ez = ez0 + Z / NF, k = Z % NF;
+        fcol[Z] = (colok && ez < E2) ? ld32(f, (uint32_t)((ez * E1 + eyY) * E0 + exX) * N3 + (k * NF + jY) * NF + iX) : (T)0;
+    }
+    if constexpr (HASZ) brick_compute<T, NF, BE>(E0, E1, E2, *a.Lf, ex0, ey0, ez0, in, su, sx, sy, rcol);
+#pragma unroll
+    for (int Z = 0; Z < NB; ++Z) {
+        const int ez = ez0 + Z / NF;
         T r = 0;
         if (colok && ez < E2) {
-            const T fv = f[((long long)(ez * E1 + eyY) * E0 + exX) * N3 + (k * NF + jY) * NF + iX];
             if constexpr (HASZ)
-                r = fv - rcol[Z];
+                r = fcol[Z] - rcol[Z];
             else
-                r = fv;
+                r = fcol[Z];
         }
         rcol[Z] = r;
     }
@@ -713,8 +777,9 @@ __global__ __launch_bounds__(256) void k_coarse(const CoarseDev* __restrict__ C,
     const T* rr = r + (long long)rhs * ndof;
     T* zz = z + (long long)rhs * ndof;
     const int t = threadIdx.x;
-    for (long long q = t; q < ndof; q += blockDim.x) {
-        const int e = (int)(q / N3), l = (int)(q % N3);
+    const int nd = (int)ndof;
+    for (int q = t; q < nd; q += blockDim.x) {
+        const int e = q / N3, l = q - e * N3;
         const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
         const int i = l % N, j = (l / N) % N, k = l / (N * N);
         const int Xg = ex * N + i, Yg = ey * N + j, Zg = ez * N + k;
@@ -756,8 +821,8 @@ __global__ __launch_bounds__(256) void k_coarse(const CoarseDev* __restrict__ C,
             __syncthreads();
         }
     }
-    for (long long q = t; q < ndof; q += blockDim.x) {
-        const int e = (int)(q / N3), l = (int)(q % N3);
+    for (int q = t; q < nd; q += blockDim.x) {
+        const int e = q / N3, l = q - e * N3;
         const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
         const int i = l % N, j = (l / N) % N, k = l / (N * N);
         const int Xg = ex * N + i, Yg = ey * N + j, Zg = ez * N + k;
@@ -780,9 +845,10 @@ template void launch_coarse<float>(const CoarseDev*, const LevelHost&, int, cons
 // pointwise kernels: grid (chunks, nrhs), 256 threads x 4 values per chunk
 
 template <typename T, int N>
-__device__ __forceinline__ T diag_at(const LevelDev<T>& L, int E0, int E1, int E2, long long q) {
+__device__ __forceinline__ T diag_at(const LevelDev<T>& L, int E0, int E1, int E2, long long q64) {
     constexpr int N3 = N * N * N;
-    const int e = (int)(q / N3), l = (int)(q % N3);
+    const int q = (int)q64;  // index within one right-hand side (< 2^31)
+    const int e = q / N3, l = q - e * N3;
     const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
     const int i = l % N, j = (l / N) % N, k = l / (N * N);
     const int tx = etype(ex, E0), ty = etype(ey, E1), tz = etype(ez, E2);
@@ -980,7 +1046,8 @@ __global__ __launch_bounds__(256) void k_rhs(const LevelDev<double>* __restrict_
     for (int v = 0; v < 4; ++v) {
         const long long q = q0 + v * 256;
         if (q >= ndof) break;
-        const int e = (int)(q / N3), l = (int)(q % N3);
+        const int qi = (int)q;
+        const int e = qi / N3, l = qi - e * N3;
         const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
         const int i = l % N, j = (l / N) % N, k = l / (N * N);
         const int X = ex * N + i, Y = ey * N + j, Z = ez * N + k;
@@ -1113,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_exchange(const LevelDev<double>* __rest
     double ph[XMAX_ORB], w[XMAX_ORB];
     double wq = 0.0;
     if (ok) {
-        const int l = (int)(q % N3);
+        const int l = (int)q % N3;
         const int i = l % N, j = (l / N) % N, k = l / (N * N);
         wq = L->ax[0].m[i] * L->ax[1].m[j] * L->ax[2].m[k];
     }
