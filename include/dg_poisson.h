@@ -176,9 +176,10 @@ dg_status dg_prolong_add(dg_ctx* ctx, int mesh_id, int level, int nrhs, const do
 /* Timing of the dominant kernel, the finest-level Chebyshev smoothing step.
  * dg_profile_enable(ctx, 1) resets the counters and brackets every later
  * launch of that kernel by HIP events on the solve's stream; 0 stops.
- * dg_profile_read returns the launches timed, their summed duration in
- * seconds and their algorithmic bytes: every vector the step reads or writes
- * counted once per right-hand side still iterating (host outputs). */
+ * dg_profile_read returns the launches timed (-1 if the runtime could not
+ * time them), their summed duration in seconds and their algorithmic bytes:
+ * every vector the step reads or writes counted once per right-hand side
+ * still iterating (host outputs). */
 dg_status dg_profile_enable(dg_ctx* ctx, int enable);
 dg_status dg_profile_read(const dg_ctx* ctx, long long* launches, double* seconds, double* bytes);
 

@@ -90,6 +90,8 @@ struct ChebCoef {
 struct dg_ctx {
     dg_opts opts;
     int device = 0;
+    hipStream_t stream = nullptr;        // internal stream (capturable), default priority
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     struct Mesh {
         dg_mesh mesh;
         std::vector<dg::LevelHost> lv;
@@ -107,6 +109,14 @@ struct dg_ctx {
         dg::RhsState* st_in = nullptr;   // inner FP32 state
         dg::RhsState* st_host = nullptr; // pinned host mirror
         int cap_b = 0, cap_st = 0;
+        // captured PCG iterations, per precision (index 0: FP64, 1: FP32)
+        struct Graph {
+            hipGraphExec_t exec = nullptr;
+            int nrhs = 0, every = 0;
+            bool prof = false;
+            std::vector<hipEvent_t> ev;
+            size_t nev = 0;
+        } graph[2];
     };
     std::vector<Mesh> meshes;
     // timing of the finest-level Chebyshev step
@@ -116,6 +126,7 @@ struct dg_ctx {
         size_t used = 0;
         long long launches = 0;
         double seconds = 0.0, bytes = 0.0;
+        bool failed = false;
     } prof;
     // exchange work space
     double* xv = nullptr;
@@ -131,8 +142,16 @@ namespace {
 using dg::LevelHost;
 using Mesh = dg_ctx::Mesh;
 
+void drop_graphs(Mesh& M) {
+    for (auto& G : M.graph) {
+        if (G.exec) (void)hipGraphExecDestroy(G.exec);
+        G.exec = nullptr;
+    }
+}
+
 void ensure_state(Mesh& M, int nrhs) {
     if (M.cap_st >= nrhs) return;
+    drop_graphs(M);
     dfree(M.st);
     dfree(M.st_in);
     if (M.st_host) (void)hipHostFree(M.st_host);
@@ -147,6 +166,7 @@ void ensure_state(Mesh& M, int nrhs) {
 template <typename T>
 void ensure_work(Mesh& M, Work<T>& W, int nrhs) {
     if (W.cap >= nrhs) return;
+    drop_graphs(M);
     W.release();
     const int L = (int)M.lv.size();
     W.f.assign(L, nullptr);
@@ -190,26 +210,38 @@ const dg::LevelDev<float>* ldev<float>(const LevelHost& L) { return L.dev32; }
 // also writes partial sums of f.z.
 dg_ctx::Prof* g_prof = nullptr;  // profiling state of the context being driven (one host thread per context)
 
+// Where prof_mark records: the context's pool (eager launches) or the event
+// set of a graph being captured (re-recorded at every replay).
+struct EventSink {
+    std::vector<hipEvent_t>* ev = nullptr;
+    size_t* used = nullptr;
+} g_sink;
+
 void prof_mark(hipStream_t s) {
-    auto& P = *g_prof;
-    if (P.used == P.ev.size()) {
+    auto& ev = *g_sink.ev;
+    auto& used = *g_sink.used;
+    if (used == ev.size()) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
-        P.ev.push_back(e);
+        ev.push_back(e);
     }
-    HIPCHK(hipEventRecord(P.ev[P.used++], s));
+    HIPCHK(hipEventRecord(ev[used++], s));
 }
 
 // Called after the stream has been synchronised: add up the timed launches.
-void prof_collect() {
+void prof_sum(const std::vector<hipEvent_t>& ev, size_t used) {
     auto& P = *g_prof;
-    for (size_t i = 0; i + 1 < P.used; i += 2) {
+    for (size_t i = 0; i + 1 < used; i += 2) {
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, P.ev[i], P.ev[i + 1]));
+        if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) {
+            // timing not available for these events: report nothing rather than fail the solve
+            (void)hipGetLastError();
+            P.failed = true;
+            return;
+        }
         P.seconds += 1e-3 * ms;
         P.launches += 1;
     }
-    P.used = 0;
 }
 
 template <typename T>
@@ -312,16 +344,72 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
     dg::launch_fill<T>(W.p0, (T)0, L0.ndof * nrhs, s);
     dg::launch_fill<T>(W.p1, (T)0, L0.ndof * nrhs, s);
     const int maxit = ctx->opts.max_iter;
-    const int every = std::max(1, ctx->opts.check_every);
+    const bool timed = g_prof && g_prof->on;
     int it = 0;
-    while (it < maxit) {
-        for (int c = 0; c < every && it < maxit; ++c, ++it) pcg_iteration<T>(M, W, nrhs, st, it & 1, s);
-        HIPCHK(hipGetLastError());
-        read_state(M, st, nrhs, s);
-        if (g_prof && g_prof->on) prof_collect();
-        bool any = false;
-        for (int i = 0; i < nrhs; ++i) any |= M.st_host[i].active != 0;
-        if (!any) break;
+    if (ctx->opts.use_graph) {
+        // `every` iterations captured once and replayed; an even count keeps the p ping-pong aligned
+        int every = std::max(2, ctx->opts.check_every);
+        every += every & 1;
+        auto& G = M.graph[sizeof(T) == 8 ? 0 : 1];
+        if (!G.exec || G.nrhs != nrhs || G.every != every || G.prof != timed) {
+            if (G.exec) (void)hipGraphExecDestroy(G.exec);
+            G.exec = nullptr;
+            size_t used = 0;
+            EventSink saved = g_sink;
+            if (timed) {
+                // events are created before the capture; the graph records them at every replay
+                const int m = (int)M.cheb[0].cp.size() + 1;
+                const size_t need = (size_t)every * 2 * (2 * m - 1);
+                while (G.ev.size() < need) {
+                    hipEvent_t e;
+                    HIPCHK(hipEventCreate(&e));
+                    G.ev.push_back(e);
+                }
+            }
+            g_sink = {&G.ev, &used};
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipGraph_t graph = nullptr;
+            try {
+                for (int c = 0; c < every; ++c) pcg_iteration<T>(M, W, nrhs, st, c & 1, s);
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &graph);  // leave capture mode before reporting
+                if (graph) (void)hipGraphDestroy(graph);
+                g_sink = saved;
+                throw;
+            }
+            HIPCHK(hipStreamEndCapture(s, &graph));
+            g_sink = saved;
+            hipError_t e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(e);
+            G.nrhs = nrhs;
+            G.every = every;
+            G.prof = timed;
+            G.nev = used;
+        }
+        while (it < maxit) {
+            HIPCHK(hipGraphLaunch(G.exec, s));
+            it += every;
+            read_state(M, st, nrhs, s);
+            if (timed) prof_sum(G.ev, G.nev);
+            bool any = false;
+            for (int i = 0; i < nrhs; ++i) any |= M.st_host[i].active != 0;
+            if (!any) break;
+        }
+    } else {
+        const int every = std::max(1, ctx->opts.check_every);
+        auto& P = ctx->prof;
+        while (it < maxit) {
+            P.used = 0;
+            g_sink = {&P.ev, &P.used};
+            for (int c = 0; c < every && it < maxit; ++c, ++it) pcg_iteration<T>(M, W, nrhs, st, it & 1, s);
+            HIPCHK(hipGetLastError());
+            read_state(M, st, nrhs, s);
+            if (timed) prof_sum(P.ev, P.used);
+            bool any = false;
+            for (int i = 0; i < nrhs; ++i) any |= M.st_host[i].active != 0;
+            if (!any) break;
+        }
     }
     if (g_prof && g_prof->on) {
         // algorithmic bytes of the timed steps: per V-cycle, pre-smoothing steps 1..m-1 and post-smoothing
@@ -332,6 +420,19 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         for (int i = 0; i < nrhs; ++i) cycles += M.st_host[i].iters;
         g_prof->bytes += per_cycle * (double)cycles * (double)L0.ndof * sizeof(T);
     }
+}
+
+// The solver runs on the context's own stream (the caller's may be the legacy
+// default stream, which cannot be captured into a graph): it waits for the
+// caller's stream on entry, and the caller's stream waits for it on exit.
+hipStream_t enter(dg_ctx* ctx, hipStream_t user) {
+    HIPCHK(hipEventRecord(ctx->ev_in, user));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    return ctx->stream;
+}
+void leave(dg_ctx* ctx, hipStream_t user) {
+    HIPCHK(hipEventRecord(ctx->ev_out, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(user, ctx->ev_out, 0));
 }
 
 void check_mesh_id(const dg_ctx* ctx, int mesh_id) {
@@ -649,7 +750,10 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
             o.inner_rtol >= 1)
             throw ArgError("invalid solver options");
         HIPCHK(hipGetDevice(&ctx->device));
-        hipStream_t s = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+        hipStream_t s = ctx->stream;
         ctx->meshes.resize(n_meshes);
         for (int i = 0; i < n_meshes; ++i) setup_mesh(ctx.get(), meshes[i], ctx->meshes[i], s);
         HIPCHK(hipDeviceSynchronize());
@@ -677,6 +781,14 @@ void dg_poisson_destroy(dg_ctx* ctx) {
         if (M.st_host) (void)hipHostFree(M.st_host);
     }
     for (auto e : ctx->prof.ev) (void)hipEventDestroy(e);
+    for (auto& M : ctx->meshes) {
+        drop_graphs(M);
+        for (auto& G : M.graph)
+            for (auto e : G.ev) (void)hipEventDestroy(e);
+    }
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     dfree(ctx->xv);
     dfree(ctx->xpart);
     dfree(ctx->xpairs);
@@ -760,6 +872,8 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
         if (nrhs < 0) throw ArgError("nrhs must be >= 0");
         if (nrhs == 0) return;
         if (!mesh_id || !rho || !g || !v) throw ArgError("null pointer argument");
+        const hipStream_t user = stream;
+        stream = enter(ctx, user);
         // group consecutive right-hand sides by mesh, keeping the caller's packing
         std::vector<long long> off(nrhs + 1, 0), foff(nrhs + 1, 0);
         for (int i = 0; i < nrhs; ++i) {
@@ -780,6 +894,7 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
             i = j;
         }
         HIPCHK(hipStreamSynchronize(stream));
+        leave(ctx, user);
     });
     if (st == DG_OK && stats)
         for (int i = 0; i < nrhs; ++i)
@@ -794,6 +909,8 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
         g_prof = &ctx->prof;
         if (norb < 1 || norb > 32) throw ArgError("norb must be in 1..32");
         if (!phi || !g_pairs || !W || !K_pairs) throw ArgError("null pointer argument");
+        const hipStream_t user = stream;
+        stream = enter(ctx, user);
         Mesh& M = ctx->meshes[mesh_id];
         const int npairs = norb * (norb + 1) / 2;
         const long long n0 = M.lv[0].ndof;
@@ -835,6 +952,7 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
         HIPCHK(hipMemcpyAsync(K.data(), K_pairs, sizeof(double) * npairs, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipGetLastError());
+        leave(ctx, user);
         double ex = 0.0;
         q = 0;
         for (int i = 0; i < norb; ++i)
@@ -937,6 +1055,7 @@ dg_status dg_profile_enable(dg_ctx* ctx, int enable) {
             P.launches = 0;
             P.seconds = 0.0;
             P.bytes = 0.0;
+            P.failed = false;
         }
     });
 }
@@ -944,7 +1063,7 @@ dg_status dg_profile_enable(dg_ctx* ctx, int enable) {
 dg_status dg_profile_read(const dg_ctx* ctx, long long* launches, double* seconds, double* bytes) {
     return run_guarded([&] {
         if (!ctx) throw ArgError("null context");
-        if (launches) *launches = ctx->prof.launches;
+        if (launches) *launches = ctx->prof.failed ? -1 : ctx->prof.launches;
         if (seconds) *seconds = ctx->prof.seconds;
         if (bytes) *bytes = ctx->prof.bytes;
     });

@@ -765,10 +765,17 @@ template void launch_prolong<float>(const LevelHost&, const LevelHost&, int, con
 // ---------------------------------------------------------------------------
 // coarsest level: exact solve by fast diagonalisation, one work-group per RHS
 
+// Padded LDS strides of the coarsest-level array g[Z][Y][X] (at most CMAX per
+// axis): odd row stride and a plane stride that spreads the Z lines over the
+// banks.
+constexpr int CSY = CMAX + 1;
+constexpr int CSZ = CMAX * CSY + 2;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse(const CoarseDev* __restrict__ C, int nrhs, long long ndof,
-                                                const RhsState* st, const T* __restrict__ r, T* __restrict__ z) {
-    __shared__ double g[CMAX * CMAX * CMAX];
+__global__ __launch_bounds__(1024) void k_coarse(const CoarseDev* __restrict__ C, int nrhs, long long ndof,
+                                                 const RhsState* st, const T* __restrict__ r, T* __restrict__ z) {
+    __shared__ double g[CMAX * CSZ];
+    __shared__ double Qs[3][CMAX][CMAX];
     const int rhs = blockIdx.x;
     if (st && !st[rhs].active) return;
     const int nx = C->n[0], ny = C->n[1], nz = C->n[2], N = C->N;
@@ -778,45 +785,58 @@ __global__ __launch_bounds__(256) void k_coarse(const CoarseDev* __restrict__ C,
     T* zz = z + (long long)rhs * ndof;
     const int t = threadIdx.x;
     const int nd = (int)ndof;
+    for (int q = t; q < 3 * CMAX * CMAX; q += blockDim.x) (&Qs[0][0][0])[q] = (&C->Q[0][0][0])[q];
     for (int q = t; q < nd; q += blockDim.x) {
         const int e = q / N3, l = q - e * N3;
         const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
         const int i = l % N, j = (l / N) % N, k = l / (N * N);
         const int Xg = ex * N + i, Yg = ey * N + j, Zg = ez * N + k;
-        g[(Zg * ny + Yg) * nx + Xg] = (double)rr[q] * C->s[0][Xg] * C->s[1][Yg] * C->s[2][Zg];
+        g[Zg * CSZ + Yg * CSY + Xg] = (double)rr[q] * C->s[0][Xg] * C->s[1][Yg] * C->s[2][Zg];
     }
     __syncthreads();
-    // three contractions with Q^T, scale, three with Q; one thread per line
+    // three contractions with Q^T, the eigenvalue scaling, three with Q.  A
+    // line of n values is shared by 4 threads, each producing a quarter of
+    // the outputs.
     for (int pass = 0; pass < 6; ++pass) {
         const int axis = pass % 3;
         const bool fwd = pass < 3;
         const int n = C->n[axis];
         const int nl = (nx * ny * nz) / n;
-        for (int line = t; line < nl; line += blockDim.x) {
-            int o, stride;
-            if (axis == 0) { o = line * nx; stride = 1; }
-            else if (axis == 1) { const int Zg = line / nx, Xg = line % nx; o = Zg * ny * nx + Xg; stride = nx; }
-            else { o = line; stride = nx * ny; }
-            double v[CMAX], w[CMAX];
+        const int part = t & 3;
+        double w[CMAX / 4];
+        int o = 0, stride = 1;
+        const int line = t >> 2;
+        const bool act = line < nl;
+        if (act) {
+            if (axis == 0) { const int Zg = line / ny, Yg = line % ny; o = Zg * CSZ + Yg * CSY; stride = 1; }
+            else if (axis == 1) { const int Zg = line / nx, Xg = line % nx; o = Zg * CSZ + Xg; stride = CSY; }
+            else { const int Yg = line / nx, Xg = line % nx; o = Yg * CSY + Xg; stride = CSZ; }
+            double v[CMAX];
 #pragma unroll
-            for (int a2 = 0; a2 < CMAX; ++a2) v[a2] = a2 < n ? g[o + a2 * stride] : 0.0;
+            for (int b = 0; b < CMAX; ++b) v[b] = b < n ? g[o + b * stride] : 0.0;
 #pragma unroll
-            for (int a2 = 0; a2 < CMAX; ++a2) {
+            for (int a4 = 0; a4 < CMAX / 4; ++a4) {
+                const int a2 = part + 4 * a4;
                 double s = 0.0;
 #pragma unroll
                 for (int b = 0; b < CMAX; ++b)
-                    if (a2 < n && b < n) s += (fwd ? C->Q[axis][b][a2] : C->Q[axis][a2][b]) * v[b];
-                w[a2] = s;
+                    if (a2 < n && b < n) s += (fwd ? Qs[axis][b][a2] : Qs[axis][a2][b]) * v[b];
+                w[a4] = s;
             }
+        }
+        __syncthreads();
+        if (act) {
 #pragma unroll
-            for (int a2 = 0; a2 < CMAX; ++a2)
-                if (a2 < n) g[o + a2 * stride] = w[a2];
+            for (int a4 = 0; a4 < CMAX / 4; ++a4) {
+                const int a2 = part + 4 * a4;
+                if (a2 < n) g[o + a2 * stride] = w[a4];
+            }
         }
         __syncthreads();
         if (pass == 2) {
             for (int q = t; q < nx * ny * nz; q += blockDim.x) {
                 const int Xg = q % nx, Yg = (q / nx) % ny, Zg = q / (nx * ny);
-                g[q] /= (C->lam[0][Xg] + C->lam[1][Yg] + C->lam[2][Zg]);
+                g[Zg * CSZ + Yg * CSY + Xg] /= (C->lam[0][Xg] + C->lam[1][Yg] + C->lam[2][Zg]);
             }
             __syncthreads();
         }
@@ -826,7 +846,7 @@ __global__ __launch_bounds__(256) void k_coarse(const CoarseDev* __restrict__ C,
         const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
         const int i = l % N, j = (l / N) % N, k = l / (N * N);
         const int Xg = ex * N + i, Yg = ey * N + j, Zg = ez * N + k;
-        zz[q] = (T)(g[(Zg * ny + Yg) * nx + Xg] * C->s[0][Xg] * C->s[1][Yg] * C->s[2][Zg]);
+        zz[q] = (T)(g[Zg * CSZ + Yg * CSY + Xg] * C->s[0][Xg] * C->s[1][Yg] * C->s[2][Zg]);
     }
 }
 
@@ -834,7 +854,7 @@ template <typename T>
 void launch_coarse(const CoarseDev* C, const LevelHost& L, int nrhs, const RhsState* st, const T* r, T* z,
                    hipStream_t s) {
     if (nrhs == 0) return;
-    hipLaunchKernelGGL((k_coarse<T>), dim3(nrhs), dim3(256), 0, s, C, nrhs, L.ndof, st, r, z);
+    hipLaunchKernelGGL((k_coarse<T>), dim3(nrhs), dim3(1024), 0, s, C, nrhs, L.ndof, st, r, z);
 }
 template void launch_coarse<double>(const CoarseDev*, const LevelHost&, int, const RhsState*, const double*, double*,
                                     hipStream_t);

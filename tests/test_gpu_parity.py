@@ -233,3 +233,28 @@ def test_mixed_precision_refinement_reaches_fp64_accuracy(gpu_lib):
         axes, _, _, b = oracle_density_problem(mesh, d)
         assert rel_l2_M(axes, mesh, v[k], fdm.FDM(axes).solve(b)) <= POT_BAR
         assert st[k]["status"] == 0 and st[k]["outer_iters"] >= 2
+
+
+def test_graph_replay_matches_eager_launches_bitwise(gpu_lib):
+    """The captured PCG iteration, replayed several times per solve and across
+    solves with eager work in between, gives bitwise the eager result."""
+    import torch
+    wl = configs.scaled(6, 4, 3, seed=41)
+    mesh = wl.meshes[0]
+    m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
+    outs = []
+    for use_graph in (0, 1):
+        for prec in ("fp64", "fp32_ir"):
+            ctx = gpu_lib.Context([m], rtol=1e-10, use_graph=use_graph, precision=prec, check_every=2)
+            rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+            rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+            v1, st1 = ctx.solve_batch(rho, g)
+            ctx.operator_apply(v1)           # eager work between graph replays
+            torch.cuda.synchronize()
+            v2, st2 = ctx.solve_batch(rho, g)
+            assert torch.equal(v1, v2)
+            assert [s["iters"] for s in st1] == [s["iters"] for s in st2]
+            outs.append((prec, _n(v1), [s["iters"] for s in st1]))
+    for prec in ("fp64", "fp32_ir"):
+        a, b = [o for o in outs if o[0] == prec]
+        assert np.array_equal(a[1], b[1]) and a[2] == b[2]
