@@ -187,6 +187,60 @@ dg_status dg_profile_read(const dg_ctx* ctx, long long* launches, double* second
 dg_status dg_level_info(const dg_ctx* ctx, int mesh_id, int level, int* ne, int* p, double* lam_lo,
                         double* lam_hi);
 
+/* ---- learned initial guess ----------------------------------------------
+ * A 3D U-Net on the element grid gives the PCG initial guess.  Tensors are
+ * FP32 channels-last [batch][z][y][x][channel] with one channel per node of
+ * an element, so an element-major field is a network tensor as it is.
+ * Architecture (levels L, channels C; ReLU after every convolution but the
+ * last; zero padding 1 for 3x3x3):
+ *   h = relu(in(x))                                   1x1x1, in_channels -> C
+ *   for l = 0..L-1: e_l = relu(enc_l_b(relu(enc_l_a(h))))    3x3x3, C -> C
+ *                   if l < L-1: h = relu(down_l(e_l))        3x3x3 stride 2
+ *   d = e_{L-1}
+ *   for l = L-2..0: u = relu(up_l(nearest_x2(d)))            3x3x3, C -> C
+ *                   d = relu(merge_l(concat(u, e_l)))        3x3x3, 2C -> C
+ *   y = out(d)                                        1x1x1, C -> out_channels
+ * Parameters: for each convolution in that order, W[tap][ci][co]
+ * (tap = (dz*3+dy)*3+dx) then bias[co].  The guess for a source rho is
+ * v0 = s * net(rho / s), s = rms(rho).  Training minimises the relative
+ * A-norm error ||s y - v_ref||_A^2 / ||v_ref||_A^2 with Adam.  The network is not
+ * part of the paper; it only changes where PCG starts, and every solve still
+ * stops on the FP64 residual. */
+typedef struct { int levels; int channels; int in_channels; int out_channels; } dg_net_config;
+typedef struct dg_net dg_net;
+
+dg_status dg_net_create(const dg_net_config* cfg, dg_net** out);
+void dg_net_destroy(dg_net* net);
+const char* dg_net_last_error(void);
+long long dg_net_num_params(const dg_net* net);
+/* Host float arrays of dg_net_num_params values (the optimiser state is reset). */
+dg_status dg_net_set_params(dg_net* net, const float* params, long long n);
+dg_status dg_net_get_params(const dg_net* net, float* params, long long n);
+/* y = net(x) for `batch` tensors on an ne[0] x ne[1] x ne[2] element grid (device). */
+dg_status dg_net_forward(dg_net* net, int batch, const int* ne, const float* x, float* y, hipStream_t stream);
+/* Gradient of sum(y * dy) for the last forward; grad (device, may be NULL) receives it. */
+dg_status dg_net_backward(dg_net* net, const float* dy, float* grad, hipStream_t stream);
+/* One Adam step on the gradient of the last backward. */
+dg_status dg_net_adam(dg_net* net, float lr, float b1, float b2, float eps, hipStream_t stream);
+/* x = rho / s, s = rms(rho) per sample (device: rho FP64 [batch][n_dofs], x FP32, scale FP64 [batch]). */
+dg_status dg_net_prepare_input(dg_net* net, int batch, long long n_dofs, const double* rho, float* x, double* scale,
+                               hipStream_t stream);
+/* One training step on mesh mesh_id of ctx: forward on x, relative A-norm loss
+ * against the scaled targets t = v_ref / s (FP64, packed fields), backward, Adam
+ * with learning rate lr; *loss (host) receives the batch mean before the step. */
+dg_status dg_net_train_step(dg_net* net, dg_ctx* ctx, int mesh_id, int batch, const float* x, const double* t, float lr,
+                            double* loss, hipStream_t stream);
+/* v0 = s * net(rho / s) (device FP64 packed fields). */
+dg_status dg_net_guess(dg_net* net, int batch, const int* ne, long long n_dofs, const double* rho, double* v0,
+                       hipStream_t stream);
+/* Flat binary weight file: "DGNET001", 4 ints of configuration, count, floats. */
+dg_status dg_net_save(const dg_net* net, const char* path);
+dg_status dg_net_load(dg_net* net, const char* path);
+/* Use net (or NULL to stop) for the initial guess of every later solve of ctx
+ * that passes no x0.  A guess is kept only if ||b - A v0|| < ||b||, right-hand
+ * side by right-hand side; stats.guess_used says which were kept. */
+dg_status dg_poisson_attach_guess(dg_ctx* ctx, dg_net* net);
+
 #ifdef __cplusplus
 }
 #endif

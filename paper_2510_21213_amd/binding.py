@@ -64,6 +64,21 @@ def _load():
         "dg_prolong_add": (I, [P, I, I, I, P, P, P]),
         "dg_level_info": (I, [P, I, I, P, P, P, P]),
         "dg_profile_enable": (I, [P, I]),
+        "dg_net_create": (I, [P, ctypes.POINTER(P)]),
+        "dg_net_destroy": (None, [P]),
+        "dg_net_last_error": (ctypes.c_char_p, []),
+        "dg_net_num_params": (LL, [P]),
+        "dg_net_set_params": (I, [P, P, LL]),
+        "dg_net_get_params": (I, [P, P, LL]),
+        "dg_net_forward": (I, [P, I, P, P, P, P]),
+        "dg_net_backward": (I, [P, P, P, P]),
+        "dg_net_adam": (I, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),
+        "dg_net_prepare_input": (I, [P, I, LL, P, P, P, P]),
+        "dg_net_train_step": (I, [P, P, I, I, P, P, ctypes.c_float, ctypes.POINTER(D), P]),
+        "dg_net_guess": (I, [P, I, P, LL, P, P, P]),
+        "dg_net_save": (I, [P, ctypes.c_char_p]),
+        "dg_net_load": (I, [P, ctypes.c_char_p]),
+        "dg_poisson_attach_guess": (I, [P, P]),
         "dg_profile_read": (I, [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]),
     }
     for name, (res, args) in sigs.items():
@@ -103,6 +118,14 @@ def _ptr(t):
         return None
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_t(t, dtype):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -200,6 +223,11 @@ class Context:
         _check(code, "exchange_apply", allow_warn=True)
         return W, K, ex.value, [_stats(stats[i]) for i in range(npairs)], v
 
+    def attach_guess(self, net):
+        """Use a trained Net for the initial guess of later solves (None to stop)."""
+        _check(lib.dg_poisson_attach_guess(self._h, net._h if net is not None else None), "attach_guess")
+        self._guess = net
+
     # ---- timing of the finest-level Chebyshev step
     def profile(self, enable=True):
         _check(lib.dg_profile_enable(self._h, 1 if enable else 0), "profile_enable")
@@ -255,3 +283,88 @@ class Context:
 def _stats(s):
     return {"iters": s.iters, "outer_iters": s.outer_iters, "status": s.status, "guess_used": s.guess_used,
             "rel_residual": s.rel_residual}
+
+
+class DgNetConfig(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("channels", ctypes.c_int), ("in_channels", ctypes.c_int),
+                ("out_channels", ctypes.c_int)]
+
+
+def _ncheck(code, what):
+    if code != DG_OK:
+        raise DgError(f"{what}: {status_string(code)} ({lib.dg_net_last_error().decode()})")
+
+
+class Net:
+    """The learned-initial-guess U-Net (include/dg_poisson.h, dg_net_*)."""
+
+    def __init__(self, levels=4, channels=32, in_channels=125, out_channels=125):
+        cfg = DgNetConfig(levels, channels, in_channels, out_channels)
+        h = ctypes.c_void_p()
+        _ncheck(lib.dg_net_create(ctypes.byref(cfg), ctypes.byref(h)), "net_create")
+        self._h = h
+        self.levels, self.channels = levels, channels
+        self.in_channels, self.out_channels = in_channels, out_channels
+        self.num_params = lib.dg_net_num_params(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dg_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _ncheck(lib.dg_net_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size), "net_set_params")
+
+    def get_params(self):
+        p = np.empty(self.num_params, dtype=np.float32)
+        _ncheck(lib.dg_net_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size), "net_get_params")
+        return p
+
+    def forward(self, x, ne, batch):
+        ne_c = (ctypes.c_int * 3)(*ne)
+        y = torch.empty(batch * ne[0] * ne[1] * ne[2] * self.out_channels, dtype=torch.float32, device=x.device)
+        _ncheck(lib.dg_net_forward(self._h, batch, ne_c, _ptr_t(x, torch.float32), _ptr_t(y, torch.float32),
+                                   _stream()), "net_forward")
+        return y
+
+    def backward(self, dy):
+        g = torch.empty(self.num_params, dtype=torch.float32, device=dy.device)
+        _ncheck(lib.dg_net_backward(self._h, _ptr_t(dy, torch.float32), _ptr_t(g, torch.float32), _stream()),
+                "net_backward")
+        return g
+
+    def adam(self, lr, b1=0.9, b2=0.999, eps=1e-8):
+        _ncheck(lib.dg_net_adam(self._h, lr, b1, b2, eps, _stream()), "net_adam")
+
+    def prepare_input(self, rho, batch, n_dofs):
+        x = torch.empty(batch * n_dofs, dtype=torch.float32, device=rho.device)
+        s = torch.empty(batch, dtype=torch.float64, device=rho.device)
+        _ncheck(lib.dg_net_prepare_input(self._h, batch, n_dofs, _ptr(rho), _ptr_t(x, torch.float32), _ptr(s),
+                                         _stream()), "net_prepare_input")
+        return x, s
+
+    def train_step(self, ctx, x, t, batch, lr, mesh_id=0):
+        loss = ctypes.c_double()
+        _ncheck(lib.dg_net_train_step(self._h, ctx._h, mesh_id, batch, _ptr_t(x, torch.float32), _ptr(t), lr,
+                                      ctypes.byref(loss), _stream()), "net_train_step")
+        return loss.value
+
+    def guess(self, rho, ne, batch):
+        n_dofs = rho.numel() // batch
+        ne_c = (ctypes.c_int * 3)(*ne)
+        v0 = torch.empty_like(rho)
+        _ncheck(lib.dg_net_guess(self._h, batch, ne_c, n_dofs, _ptr(rho), _ptr(v0), _stream()), "net_guess")
+        return v0
+
+    def save(self, path):
+        _ncheck(lib.dg_net_save(self._h, str(path).encode()), "net_save")
+
+    def load(self, path):
+        _ncheck(lib.dg_net_load(self._h, str(path).encode()), "net_load")

@@ -119,6 +119,10 @@ struct dg_ctx {
         } graph[2];
     };
     std::vector<Mesh> meshes;
+    dg_net* guess = nullptr;       // learned initial guess (not owned)
+    double* g_x0 = nullptr;        // guess work space
+    double* g_rho = nullptr;
+    long long g_cap = 0;
     // timing of the finest-level Chebyshev step
     struct Prof {
         bool on = false;
@@ -440,9 +444,14 @@ void check_mesh_id(const dg_ctx* ctx, int mesh_id) {
     if (mesh_id < 0 || mesh_id >= (int)ctx->meshes.size()) throw ArgError("mesh_id out of range");
 }
 
+// Learned guess for nrhs sources rho of mesh M (b already assembled): writes
+// ctx->g_x0, then zeroes the guesses whose residual is not below ||b||.
+// Returns the per-right-hand-side flags of the guesses kept.
+std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho, const double* b, hipStream_t s);
+
 // Solve nrhs problems of one mesh: b (FP64, packed) -> v.  Fills stats.
 void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* x0, double* v, dg_rhs_stats* stats,
-                 hipStream_t s) {
+                 hipStream_t s, const std::vector<int>* guess_used = nullptr) {
     const LevelHost& L0 = M.lv[0];
     const long long n0 = L0.ndof;
     const int nc = dg::chunks_of(n0), nb = dg::bricks_of(L0);
@@ -532,11 +541,44 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             dg_rhs_stats& r = stats[i];
             r.iters = iters[i];
             r.outer_iters = outer[i];
-            r.guess_used = x0 ? 1 : 0;
+            r.guess_used = guess_used ? (*guess_used)[i] : (x0 ? 1 : 0);
             r.rel_residual = S.bb > 0 ? std::sqrt(S.rr / S.bb) : 0.0;
             r.status = (r.rel_residual <= o.rtol * 1.01) ? DG_OK : DG_WARN_NOT_CONVERGED;
         }
     }
+}
+
+std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho, const double* b, hipStream_t s) {
+    const LevelHost& L0 = M.lv[0];
+    const long long n0 = L0.ndof;
+    if (ctx->g_cap < n0 * nrhs) {
+        dfree(ctx->g_x0);
+        dfree(ctx->g_rho);
+        ctx->g_x0 = dalloc<double>(n0 * nrhs);
+        ctx->g_rho = dalloc<double>(n0 * nrhs);
+        ctx->g_cap = n0 * nrhs;
+    }
+    const int ne[3] = {L0.E[0], L0.E[1], L0.E[2]};
+    if (dg_net_guess(ctx->guess, nrhs, ne, n0, rho, ctx->g_x0, s) != DG_OK)
+        throw ArgError(std::string("learned guess failed: ") + dg_net_last_error());
+    ensure_state(M, nrhs);
+    const int nc = dg::chunks_of(n0), nb = dg::bricks_of(L0);
+    init_state(M, M.st, nrhs, 1.0, 1, s);
+    dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_BB, nrhs, M.st, M.partial, M.pstride, nc, s);
+    ensure_b(M, std::max(M.cap_b, nrhs), ctx->opts.precision == DG_PREC_FP32_IR);
+    double* r = ctx->g_rho;  // rho is no longer needed: reuse as residual space
+    dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, ctx->g_x0, nullptr, b, nullptr, r, nullptr,
+                             M.partial, M.pstride, 0, 0, s);
+    dg::launch_finalize(dg::FIN_TRUE, nrhs, M.st, M.partial, M.pstride, nb, s);
+    read_state(M, M.st, nrhs, s);
+    std::vector<int> used(nrhs, 0);
+    for (int i = 0; i < nrhs; ++i) {
+        const auto& S = M.st_host[i];
+        used[i] = (S.bb > 0 && S.rr < S.bb) ? 1 : 0;
+        if (!used[i]) dg::launch_fill<double>(ctx->g_x0 + (long long)i * n0, 0.0, n0, s);
+    }
+    return used;
 }
 
 void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
@@ -702,6 +744,13 @@ dg_status run_guarded(const std::function<void()>& fn) {
 }
 }  // namespace
 
+namespace dg {
+const LevelHost& ctx_fine_level(const dg_ctx* ctx, int mesh_id) {
+    check_mesh_id(ctx, mesh_id);
+    return ctx->meshes[mesh_id].lv[0];
+}
+}  // namespace dg
+
 extern "C" {
 
 void dg_opts_default(dg_opts* o) {
@@ -789,6 +838,8 @@ void dg_poisson_destroy(dg_ctx* ctx) {
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    dfree(ctx->g_x0);
+    dfree(ctx->g_rho);
     dfree(ctx->xv);
     dfree(ctx->xpart);
     dfree(ctx->xpairs);
@@ -890,7 +941,21 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
             ensure_b(M, cnt, ctx->opts.precision == DG_PREC_FP32_IR);
             dg::launch_rhs(M.lv[0], M.lv[0].dev64, cnt, rho + off[i], nullptr, nullptr, nullptr, g + foff[i], M.nface,
                            M.b, stream);
-            solve_group(ctx, M, cnt, M.b, x0 ? x0 + off[i] : nullptr, v + off[i], stats ? stats + i : nullptr, stream);
+            if (!x0 && ctx->guess) {
+                if (ctx->g_cap < M.lv[0].ndof * cnt) {
+                    dfree(ctx->g_x0);
+                    dfree(ctx->g_rho);
+                    ctx->g_x0 = dalloc<double>(M.lv[0].ndof * cnt);
+                    ctx->g_rho = dalloc<double>(M.lv[0].ndof * cnt);
+                    ctx->g_cap = M.lv[0].ndof * cnt;
+                }
+                dg::launch_copy(rho + off[i], ctx->g_rho, M.lv[0].ndof * cnt, stream);
+                std::vector<int> used = learned_guess(ctx, M, cnt, ctx->g_rho, M.b, stream);
+                solve_group(ctx, M, cnt, M.b, ctx->g_x0, v + off[i], stats ? stats + i : nullptr, stream, &used);
+            } else {
+                solve_group(ctx, M, cnt, M.b, x0 ? x0 + off[i] : nullptr, v + off[i], stats ? stats + i : nullptr,
+                            stream);
+            }
             i = j;
         }
         HIPCHK(hipStreamSynchronize(stream));
@@ -939,7 +1004,20 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
         ensure_b(M, npairs, ctx->opts.precision == DG_PREC_FP32_IR);
         dg::launch_rhs(M.lv[0], M.lv[0].dev64, npairs, nullptr, phi, ctx->xpairs, ctx->xpairs + npairs, g_pairs,
                        M.nface, M.b, stream);
-        solve_group(ctx, M, npairs, M.b, nullptr, v, stats, stream);
+        if (ctx->guess) {
+            if (ctx->g_cap < n0 * npairs) {
+                dfree(ctx->g_x0);
+                dfree(ctx->g_rho);
+                ctx->g_x0 = dalloc<double>(n0 * npairs);
+                ctx->g_rho = dalloc<double>(n0 * npairs);
+                ctx->g_cap = n0 * npairs;
+            }
+            dg::launch_pair_products(n0, npairs, phi, ctx->xpairs, ctx->xpairs + npairs, ctx->g_rho, stream);
+            std::vector<int> used = learned_guess(ctx, M, npairs, ctx->g_rho, M.b, stream);
+            solve_group(ctx, M, npairs, M.b, ctx->g_x0, v, stats, stream, &used);
+        } else {
+            solve_group(ctx, M, npairs, M.b, nullptr, v, stats, stream);
+        }
         const int nblk = (int)((n0 + 255) / 256);
         if (ctx->xpart_cap < (long long)npairs * nblk) {
             dfree(ctx->xpart);
@@ -1042,6 +1120,13 @@ dg_status dg_prolong_add(dg_ctx* ctx, int mesh_id, int level, int nrhs, const do
         if (nrhs < 0 || (nrhs > 0 && (!zc || !zf))) throw ArgError("bad arguments");
         dg::launch_prolong<double>(M.lv[level], M.lv[level + 1], nrhs, nullptr, zc, zf, stream);
         HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_poisson_attach_guess(dg_ctx* ctx, dg_net* net) {
+    return run_guarded([&] {
+        if (!ctx) throw ArgError("null context");
+        ctx->guess = net;
     });
 }
 

@@ -92,6 +92,10 @@ void launch_axpby(long long n, double a, const double* x, double b, double* y, h
 // Exchange: W_k = sum_s phi_s v_ks; partial sums of w rho_ij v_ij per pair.
 void launch_exchange(const LevelHost& L, const LevelDev<double>* dev, int norb, const double* phi, const double* v,
                      double* W, double* partial, int pstride, hipStream_t s);
+// rho[q] = phi[pi[q]] * phi[pj[q]] for every pair q.
+void launch_pair_products(long long ndof, int npairs, const double* phi, const int* pi, const int* pj, double* rho,
+                          hipStream_t s);
+
 // K[q] = sum of partial[q][0..nblk-1] (fixed order).
 void launch_sum_partials(int nq, const double* partial, int pstride, int nblk, double* K, hipStream_t s);
 

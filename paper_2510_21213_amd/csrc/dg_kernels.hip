@@ -1235,6 +1235,21 @@ void launch_exchange(const LevelHost& L, const LevelDev<double>* dev, int norb, 
 #undef DG_X
 }
 
+__global__ __launch_bounds__(256) void k_pair_products(long long ndof, const double* __restrict__ phi,
+                                                       const int* __restrict__ pi, const int* __restrict__ pj,
+                                                       double* __restrict__ rho) {
+    const int q = blockIdx.y;
+    const double* a = phi + (long long)pi[q] * ndof;
+    const double* b = phi + (long long)pj[q] * ndof;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < ndof; i += (long long)gridDim.x * 256)
+        rho[(long long)q * ndof + i] = a[i] * b[i];
+}
+void launch_pair_products(long long ndof, int npairs, const double* phi, const int* pi, const int* pj, double* rho,
+                          hipStream_t s) {
+    if (npairs == 0) return;
+    hipLaunchKernelGGL(k_pair_products, dim3(256, npairs), dim3(256), 0, s, ndof, phi, pi, pj, rho);
+}
+
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int pstride, int nblk,
                                                       double* __restrict__ K) {
     __shared__ double red[256];

@@ -1,0 +1,876 @@
+// Learned initial guess: a 3D U-Net on the element grid, with hand-written
+// HIP forward, backward and Adam kernels, and its use as the PCG initial
+// guess.
+//
+// Tensors are channels-last [batch][z][y][x][channel] in FP32.  One channel
+// per node of an element, so an element-major field of the library is the
+// network's input or output tensor as it is.  Architecture, parameter order
+// and loss are fixed in include/dg_poisson.h (dg_net_*).
+//
+// Kernels: direct convolution (3x3x3 stride 1 or 2, 1x1x1) with the weights
+// of the work-group's output-channel group read by uniform (scalar) loads,
+// fused bias and ReLU; gradient with respect to the input by the same loop
+// over the taps that touch an input voxel; gradient with respect to the
+// weights by LDS-tiled partial sums over voxel chunks followed by a
+// fixed-order reduction (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+#include "dg_kernels.h"
+
+namespace {
+
+struct NetError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+#define NCHK(x)                                                                                              \
+    do {                                                                                                     \
+        hipError_t e_ = (x);                                                                                 \
+        if (e_ != hipSuccess)                                                                                \
+            throw NetError(std::string(#x) + ": " + hipGetErrorString(e_) + " at line " + std::to_string(__LINE__)); \
+    } while (0)
+
+constexpr int CO_GROUP = 8;   // output channels per thread in the convolution kernels
+
+// ---------------------------------------------------------------------------
+// kernels
+
+// y[b][o][co] = act(bias[co] + sum_t sum_ci x[b][in(o,t)][ci] W[t][ci][co])
+template <int KS, int STRIDE>
+__global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ x, const float* __restrict__ W,
+                                                  const float* __restrict__ bias, float* __restrict__ y, int D, int H,
+                                                  int Wd, int Ci, int Do, int Ho, int Wo, int Co, int relu) {
+    const int nvo = Do * Ho * Wo;
+    const int o = blockIdx.x * 256 + threadIdx.x;
+    const int co0 = blockIdx.y * CO_GROUP;
+    const int b = blockIdx.z;
+    if (o >= nvo) return;
+    const int ox = o % Wo, oy = (o / Wo) % Ho, oz = o / (Wo * Ho);
+    constexpr int PAD = (KS - 1) / 2;
+    float acc[CO_GROUP];
+#pragma unroll
+    for (int c = 0; c < CO_GROUP; ++c) acc[c] = (co0 + c < Co) ? bias[co0 + c] : 0.f;
+    const float* xb = x + (long long)b * D * H * Wd * Ci;
+    for (int t = 0; t < KS * KS * KS; ++t) {
+        const int dz = t / (KS * KS), dy = (t / KS) % KS, dx = t % KS;
+        const int iz = oz * STRIDE - PAD + dz, iy = oy * STRIDE - PAD + dy, ix = ox * STRIDE - PAD + dx;
+        if (iz < 0 || iz >= D || iy < 0 || iy >= H || ix < 0 || ix >= Wd) continue;
+        const float* xv = xb + ((long long)(iz * H + iy) * Wd + ix) * Ci;
+        const float* wt = W + ((long long)t * Ci) * Co + co0;
+        for (int ci = 0; ci < Ci; ++ci) {
+            const float v = xv[ci];
+            const float* w = wt + (long long)ci * Co;
+#pragma unroll
+            for (int c = 0; c < CO_GROUP; ++c)
+                if (co0 + c < Co) acc[c] += v * w[c];
+        }
+    }
+    float* yo = y + ((long long)b * nvo + o) * Co + co0;
+#pragma unroll
+    for (int c = 0; c < CO_GROUP; ++c)
+        if (co0 + c < Co) yo[c] = relu ? fmaxf(acc[c], 0.f) : acc[c];
+}
+
+// dx[b][i][ci] = sum over (o, t) with in(o,t) = i of sum_co dy[b][o][co] W[t][ci][co]
+template <int KS, int STRIDE>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const float* __restrict__ dy, const float* __restrict__ W,
+                                                       float* __restrict__ dx, int D, int H, int Wd, int Ci, int Do,
+                                                       int Ho, int Wo, int Co) {
+    const int nvi = D * H * Wd;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int ci0 = blockIdx.y * CO_GROUP;
+    const int b = blockIdx.z;
+    if (i >= nvi) return;
+    const int ix = i % Wd, iy = (i / Wd) % H, iz = i / (Wd * H);
+    constexpr int PAD = (KS - 1) / 2;
+    float acc[CO_GROUP] = {};
+    const float* dyb = dy + (long long)b * Do * Ho * Wo * Co;
+    for (int t = 0; t < KS * KS * KS; ++t) {
+        const int dz = t / (KS * KS), dyy = (t / KS) % KS, dxx = t % KS;
+        const int nz = iz + PAD - dz, ny = iy + PAD - dyy, nx = ix + PAD - dxx;
+        if (nz < 0 || ny < 0 || nx < 0) continue;
+        if (nz % STRIDE || ny % STRIDE || nx % STRIDE) continue;
+        const int oz = nz / STRIDE, oy = ny / STRIDE, ox = nx / STRIDE;
+        if (oz >= Do || oy >= Ho || ox >= Wo) continue;
+        const float* g = dyb + ((long long)(oz * Ho + oy) * Wo + ox) * Co;
+        const float* wt = W + (long long)t * Ci * Co + (long long)ci0 * Co;
+        for (int co = 0; co < Co; ++co) {
+            const float v = g[co];
+#pragma unroll
+            for (int c = 0; c < CO_GROUP; ++c)
+                if (ci0 + c < Ci) acc[c] += v * wt[(long long)c * Co + co];
+        }
+    }
+    float* out = dx + ((long long)b * nvi + i) * Ci + ci0;
+#pragma unroll
+    for (int c = 0; c < CO_GROUP; ++c)
+        if (ci0 + c < Ci) out[c] = acc[c];
+}
+
+// Partial weight gradients: block (tap, ci tile of 16, co tile of 16, chunk s)
+// sums x[b][in(o,t)][ci] dy[b][o][co] over its share of the (b, o) pairs.
+constexpr int WG_TILE = 16;
+constexpr int WG_CHUNK = 64;
+
+template <int KS, int STRIDE>
+__global__ __launch_bounds__(256) void k_conv_bwd_weight(const float* __restrict__ x, const float* __restrict__ dy,
+                                                         float* __restrict__ part, int B, int D, int H, int Wd,
+                                                         int Ci, int Do, int Ho, int Wo, int Co, int nsplit) {
+    __shared__ float sx[WG_CHUNK][WG_TILE + 1];
+    __shared__ float sg[WG_CHUNK][WG_TILE + 1];
+    constexpr int PAD = (KS - 1) / 2;
+    const int ntci = (Ci + WG_TILE - 1) / WG_TILE, ntco = (Co + WG_TILE - 1) / WG_TILE;
+    int bid = blockIdx.x;
+    const int split = bid % nsplit;
+    bid /= nsplit;
+    const int tco = bid % ntco;
+    bid /= ntco;
+    const int tci = bid % ntci;
+    const int t = bid / ntci;
+    const int dz = t / (KS * KS), dyy = (t / KS) % KS, dxx = t % KS;
+    const int tid = threadIdx.x;
+    const int lci = tid / WG_TILE, lco = tid % WG_TILE;
+    const int nvo = Do * Ho * Wo;
+    const long long total = (long long)B * nvo;
+    const long long per = (total + nsplit - 1) / nsplit;
+    const long long beg = split * per, end = min(total, beg + per);
+    float acc = 0.f;
+    for (long long c0 = beg; c0 < end; c0 += WG_CHUNK) {
+        // stage WG_CHUNK output voxels: their input voxel for this tap, and dy
+        for (int q = tid; q < WG_CHUNK * WG_TILE; q += 256) {
+            const int r = q / WG_TILE, c = q % WG_TILE;
+            const long long bo = c0 + r;
+            float vx = 0.f, vg = 0.f;
+            if (bo < end) {
+                const int b = (int)(bo / nvo), o = (int)(bo % nvo);
+                const int ox = o % Wo, oy = (o / Wo) % Ho, oz = o / (Wo * Ho);
+                const int iz = oz * STRIDE - PAD + dz, iy = oy * STRIDE - PAD + dyy, ix = ox * STRIDE - PAD + dxx;
+                const int ci = tci * WG_TILE + c, co = tco * WG_TILE + c;
+                if (ci < Ci && iz >= 0 && iz < D && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+                    vx = x[(((long long)b * D + iz) * H + iy) * Wd * (long long)Ci + (long long)ix * Ci + ci];
+                if (co < Co) vg = dy[((long long)b * nvo + o) * Co + co];
+            }
+            sx[r][c] = vx;
+            sg[r][c] = vg;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int r = 0; r < WG_CHUNK; ++r) acc += sx[r][lci] * sg[r][lco];
+        __syncthreads();
+    }
+    const int ci = tci * WG_TILE + lci, co = tco * WG_TILE + lco;
+    if (ci < Ci && co < Co) part[((long long)split * KS * KS * KS * Ci + (long long)t * Ci + ci) * Co + co] = acc;
+}
+
+// out[j] = sum_s part[s][j]  (fixed order)
+__global__ __launch_bounds__(256) void k_reduce_splits(const float* __restrict__ part, float* __restrict__ out,
+                                                       long long n, int nsplit) {
+    const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[(long long)k * n + j];
+    out[j] = s;
+}
+
+// db[co] = sum over (b, o) of dy[b][o][co]   (one block per co, fixed order)
+__global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ dy, float* __restrict__ db,
+                                                   long long nbo, int Co) {
+    __shared__ float red[256];
+    const int co = blockIdx.x;
+    float s = 0.f;
+    for (long long q = threadIdx.x; q < nbo; q += 256) s += dy[q * Co + co];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[co] = red[0];
+}
+
+// g *= (y > 0)
+__global__ __launch_bounds__(256) void k_relu_mask(float* __restrict__ g, const float* __restrict__ y, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n && !(y[i] > 0.f)) g[i] = 0.f;
+}
+
+// nearest x2 upsampling of [B][d][h][w][C] to [B][D][H][W][C] (D <= 2d ...)
+__global__ __launch_bounds__(256) void k_upsample(const float* __restrict__ s, float* __restrict__ u, int B, int d,
+                                                  int h, int w, int D, int H, int W, int C) {
+    const long long n = (long long)B * D * H * W * C;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    long long v = i / C;
+    const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)((v / (W * H)) % D), b = (int)(v / ((long long)W * H * D));
+    u[i] = s[((((long long)b * d + z / 2) * h + y / 2) * w + x / 2) * C + c];
+}
+
+__global__ __launch_bounds__(256) void k_upsample_bwd(const float* __restrict__ gu, float* __restrict__ gs, int B,
+                                                      int d, int h, int w, int D, int H, int W, int C) {
+    const long long n = (long long)B * d * h * w * C;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    long long v = i / C;
+    const int x = (int)(v % w), y = (int)((v / w) % h), z = (int)((v / (w * h)) % d), b = (int)(v / ((long long)w * h * d));
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int e = 0; e < 2; ++e)
+            for (int f = 0; f < 2; ++f) {
+                const int Z = 2 * z + a, Y = 2 * y + e, X = 2 * x + f;
+                if (Z < D && Y < H && X < W) s += gu[((((long long)b * D + Z) * H + Y) * W + X) * C + c];
+            }
+    gs[i] = s;
+}
+
+// cat[v][0:C1] = a[v], cat[v][C1:C1+C2] = b[v]  and the reverse split (add into ga, gb when acc)
+__global__ __launch_bounds__(256) void k_concat(const float* __restrict__ a, const float* __restrict__ b,
+                                                float* __restrict__ cat, long long nv, int C1, int C2) {
+    const int C = C1 + C2;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nv * C) return;
+    const long long v = i / C;
+    const int c = (int)(i % C);
+    cat[i] = c < C1 ? a[v * C1 + c] : b[v * C2 + c - C1];
+}
+__global__ __launch_bounds__(256) void k_split(const float* __restrict__ gcat, float* __restrict__ ga,
+                                               float* __restrict__ gb, long long nv, int C1, int C2, int acc_b) {
+    const int C = C1 + C2;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nv * C) return;
+    const long long v = i / C;
+    const int c = (int)(i % C);
+    if (c < C1)
+        ga[v * C1 + c] = gcat[i];
+    else if (acc_b)
+        gb[v * C2 + c - C1] += gcat[i];
+    else
+        gb[v * C2 + c - C1] = gcat[i];
+}
+
+__global__ __launch_bounds__(256) void k_add(float* __restrict__ a, const float* __restrict__ b, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) a[i] += b[i];
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, long long n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Per-sample scale and input: s = sqrt(mean(rho^2)); x = rho / s (FP32).
+__global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ a, double* __restrict__ part, long long n) {
+    __shared__ double red[256];
+    const int b = blockIdx.y;
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const double v = a[(long long)b * n + i];
+        s += v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = red[0];
+}
+__global__ void k_scale_of(const double* __restrict__ part, int nblk, long long n, double* __restrict__ scale) {
+    const int b = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += part[(long long)b * nblk + i];
+    const double r = sqrt(s / (double)n);
+    scale[b] = r > 0.0 ? r : 1.0;
+}
+__global__ __launch_bounds__(256) void k_to_input(const double* __restrict__ a, const double* __restrict__ scale,
+                                                  float* __restrict__ x, long long n) {
+    const int b = blockIdx.y;
+    const double inv = 1.0 / scale[b];
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        x[(long long)b * n + i] = (float)(a[(long long)b * n + i] * inv);
+}
+__global__ __launch_bounds__(256) void k_from_output(const float* __restrict__ y, const double* __restrict__ scale,
+                                                     double* __restrict__ v, long long n) {
+    const int b = blockIdx.y;
+    const double s = scale[b];
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        v[(long long)b * n + i] = s * (double)y[(long long)b * n + i];
+}
+
+// Loss pieces: e = y - t (FP64), and after Ae is known: per sample sum e.Ae, and
+// dy = 2 Ae / tAt.
+__global__ __launch_bounds__(256) void k_err(const float* __restrict__ y, const double* __restrict__ t,
+                                             double* __restrict__ e, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) e[i] = (double)y[i] - t[i];
+}
+__global__ __launch_bounds__(256) void k_loss_grad(const double* __restrict__ Ae, const double* __restrict__ tAt,
+                                                   float* __restrict__ dy, long long n) {
+    const int b = blockIdx.y;
+    const double c = 2.0 / tAt[b];
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        dy[(long long)b * n + i] = (float)(c * Ae[(long long)b * n + i]);
+}
+__global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ a, const double* __restrict__ b,
+                                                  double* __restrict__ part, long long n) {
+    __shared__ double red[256];
+    const int s = blockIdx.y;
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        acc += a[(long long)s * n + i] * b[(long long)s * n + i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = red[0];
+}
+
+inline unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// network object
+
+struct dg_net {
+    dg_net_config cfg;
+    struct Layer {
+        std::string name;
+        int k, s, ci, co;
+        long long woff, boff;  // offsets of W and bias in the parameter vector
+    };
+    std::vector<Layer> layers;
+    long long nparams = 0;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *part = nullptr;
+    long long part_cap = 0;
+    int t = 0;  // Adam steps taken
+    // activations for the current batch and grid
+    int B = 0, E[3] = {0, 0, 0};
+    struct Buf {
+        float* d = nullptr;
+        long long n = 0;
+    };
+    std::vector<Buf> act;   // per layer output
+    std::vector<Buf> aux;   // upsampled / concatenated inputs
+    std::vector<Buf> grd;   // gradient work buffers
+    std::vector<std::array<int, 3>> dims;  // spatial dims per level
+    Buf xin;                               // copy of the last forward input
+    double *e = nullptr, *Ae = nullptr, *tAt = nullptr, *dpart = nullptr, *scale = nullptr, *vtmp = nullptr;
+    float *xbuf = nullptr, *ybuf = nullptr, *dybuf = nullptr;
+    long long cap_field = 0;
+};
+
+namespace {
+
+thread_local std::string g_net_err;
+
+dg_status net_guard(const std::function<void()>& fn) {
+    try {
+        fn();
+        return DG_OK;
+    } catch (const NetError& e) {
+        g_net_err = e.what();
+        return std::string(e.what()).find("hip") != std::string::npos ? DG_ERR_HIP : DG_ERR_ARG;
+    } catch (const std::exception& e) {
+        g_net_err = e.what();
+        return DG_ERR_ARG;
+    }
+}
+
+template <typename T>
+T* nalloc(long long n) {
+    void* p = nullptr;
+    NCHK(hipMalloc(&p, (size_t)std::max(1LL, n) * sizeof(T)));
+    return (T*)p;
+}
+template <typename T>
+void nfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+int layer_index(const dg_net* net, const std::string& name) {
+    for (size_t i = 0; i < net->layers.size(); ++i)
+        if (net->layers[i].name == name) return (int)i;
+    throw NetError("no layer " + name);
+}
+
+void conv_forward(const dg_net::Layer& L, const float* P, const float* x, float* y, int B, const int* din,
+                  const int* dout, int relu, hipStream_t s) {
+    dim3 grid(nblocks((long long)dout[0] * dout[1] * dout[2]), (L.co + CO_GROUP - 1) / CO_GROUP, B);
+    const float* W = P + L.woff;
+    const float* b = P + L.boff;
+#define CF(KS, ST) hipLaunchKernelGGL((k_conv_fwd<KS, ST>), grid, dim3(256), 0, s, x, W, b, y, din[0], din[1], din[2], L.ci, dout[0], dout[1], dout[2], L.co, relu)
+    if (L.k == 1) CF(1, 1);
+    else if (L.s == 1) CF(3, 1);
+    else CF(3, 2);
+#undef CF
+}
+
+// Gradients of a convolution: dx (may be null), dW and db into net->g.
+void conv_backward(dg_net* net, const dg_net::Layer& L, const float* x, const float* dy, float* dx, int B,
+                   const int* din, const int* dout, hipStream_t s) {
+    const float* W = net->p + L.woff;
+    if (dx) {
+        dim3 grid(nblocks((long long)din[0] * din[1] * din[2]), (L.ci + CO_GROUP - 1) / CO_GROUP, B);
+#define CB(KS, ST) hipLaunchKernelGGL((k_conv_bwd_data<KS, ST>), grid, dim3(256), 0, s, dy, W, dx, din[0], din[1], din[2], L.ci, dout[0], dout[1], dout[2], L.co)
+        if (L.k == 1) CB(1, 1);
+        else if (L.s == 1) CB(3, 1);
+        else CB(3, 2);
+#undef CB
+    }
+    const int taps = L.k * L.k * L.k;
+    const long long nw = (long long)taps * L.ci * L.co;
+    const long long nbo = (long long)B * dout[0] * dout[1] * dout[2];
+    const int nsplit = (int)std::max(1LL, std::min(64LL, nbo / 512));
+    if (net->part_cap < nw * nsplit) throw NetError("internal: gradient work space too small");
+    const int ntci = (L.ci + WG_TILE - 1) / WG_TILE, ntco = (L.co + WG_TILE - 1) / WG_TILE;
+    const unsigned blocks = (unsigned)(taps * ntci * ntco * nsplit);
+#define CW(KS, ST) hipLaunchKernelGGL((k_conv_bwd_weight<KS, ST>), dim3(blocks), dim3(256), 0, s, x, dy, net->part, B, din[0], din[1], din[2], L.ci, dout[0], dout[1], dout[2], L.co, nsplit)
+    if (L.k == 1) CW(1, 1);
+    else if (L.s == 1) CW(3, 1);
+    else CW(3, 2);
+#undef CW
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(nw)), dim3(256), 0, s, net->part, net->g + L.woff, nw, nsplit);
+    hipLaunchKernelGGL(k_bias_grad, dim3(L.co), dim3(256), 0, s, dy, net->g + L.boff, nbo, L.co);
+}
+
+void ensure_buffers(dg_net* net, int B, const int* E) {
+    if (net->B == B && net->E[0] == E[0] && net->E[1] == E[1] && net->E[2] == E[2]) return;
+    NCHK(hipDeviceSynchronize());  // buffers may still be in use by queued kernels
+    for (auto& b : net->act) nfree(b.d);
+    for (auto& b : net->aux) nfree(b.d);
+    for (auto& b : net->grd) nfree(b.d);
+    const int Lv = net->cfg.levels, C = net->cfg.channels;
+    net->dims.assign(Lv, {0, 0, 0});
+    net->dims[0] = {E[2], E[1], E[0]};  // z, y, x
+    for (int l = 1; l < Lv; ++l)
+        for (int d = 0; d < 3; ++d) net->dims[l][d] = (net->dims[l - 1][d] + 1) / 2;
+    auto vox = [&](int l) { return (long long)net->dims[l][0] * net->dims[l][1] * net->dims[l][2]; };
+    net->act.assign(net->layers.size(), {});
+    for (size_t i = 0; i < net->layers.size(); ++i) {
+        const auto& L = net->layers[i];
+        int lev = 0;
+        if (L.name.rfind("enc", 0) == 0) lev = L.name[3] - '0';
+        else if (L.name.rfind("down", 0) == 0) lev = L.name[4] - '0' + 1;
+        else if (L.name.rfind("up", 0) == 0) lev = L.name[2] - '0';
+        else if (L.name.rfind("merge", 0) == 0) lev = L.name[5] - '0';
+        net->act[i].n = (long long)B * vox(lev) * L.co;
+        net->act[i].d = nalloc<float>(net->act[i].n);
+    }
+    // aux: per decoder level l: upsampled input [vox(l)][C], concat [vox(l)][2C]
+    net->aux.assign(2 * Lv, {});
+    net->grd.assign(4, {});
+    long long mx = 0;
+    for (int l = 0; l < Lv; ++l) {
+        net->aux[2 * l].n = (long long)B * vox(l) * C;
+        net->aux[2 * l + 1].n = (long long)B * vox(l) * 2 * C;
+        net->aux[2 * l].d = nalloc<float>(net->aux[2 * l].n);
+        net->aux[2 * l + 1].d = nalloc<float>(net->aux[2 * l + 1].n);
+        mx = std::max(mx, (long long)B * vox(l) * 2 * C);
+    }
+    mx = std::max(mx, (long long)B * vox(0) * std::max(net->cfg.in_channels, net->cfg.out_channels));
+    for (auto& b : net->grd) {
+        b.n = mx;
+        b.d = nalloc<float>(mx);
+    }
+    nfree(net->xin.d);
+    net->xin.n = (long long)B * vox(0) * net->cfg.in_channels;
+    net->xin.d = nalloc<float>(net->xin.n);
+    // weight-gradient partial sums: sized once for the largest layer, so that the
+    // buffer is never replaced while kernels that use it are queued
+    long long need = 0;
+    for (const auto& L : net->layers) {
+        int lev = 0;
+        if (L.name.rfind("enc", 0) == 0) lev = L.name[3] - '0';
+        else if (L.name.rfind("down", 0) == 0) lev = L.name[4] - '0' + 1;
+        else if (L.name.rfind("up", 0) == 0) lev = L.name[2] - '0';
+        else if (L.name.rfind("merge", 0) == 0) lev = L.name[5] - '0';
+        const long long nbo = (long long)B * vox(lev);
+        const long long nsplit = std::max(1LL, std::min(64LL, nbo / 512));
+        need = std::max(need, (long long)L.k * L.k * L.k * L.ci * L.co * nsplit);
+    }
+    if (net->part_cap < need) {
+        NCHK(hipDeviceSynchronize());
+        nfree(net->part);
+        net->part = nalloc<float>(need);
+        net->part_cap = need;
+    }
+    net->B = B;
+    net->E[0] = E[0]; net->E[1] = E[1]; net->E[2] = E[2];
+}
+
+// Forward pass on x [B][Ez][Ey][Ex][Cin]; the output is the activation of "out".
+const float* forward(dg_net* net, int B, const int* E, const float* x, hipStream_t s) {
+    ensure_buffers(net, B, E);
+    NCHK(hipMemcpyAsync(net->xin.d, x, sizeof(float) * net->xin.n, hipMemcpyDeviceToDevice, s));
+    x = net->xin.d;
+    const int Lv = net->cfg.levels, C = net->cfg.channels;
+    auto A = [&](const std::string& n) { return net->act[layer_index(net, n)].d; };
+    auto Ly = [&](const std::string& n) -> const dg_net::Layer& { return net->layers[layer_index(net, n)]; };
+    auto D = [&](int l) { return net->dims[l].data(); };
+    conv_forward(Ly("in"), net->p, x, A("in"), B, D(0), D(0), 1, s);
+    const float* h = A("in");
+    for (int l = 0; l < Lv; ++l) {
+        const std::string a = "enc" + std::to_string(l) + "a", b = "enc" + std::to_string(l) + "b";
+        conv_forward(Ly(a), net->p, h, A(a), B, D(l), D(l), 1, s);
+        conv_forward(Ly(b), net->p, A(a), A(b), B, D(l), D(l), 1, s);
+        if (l < Lv - 1) {
+            const std::string dn = "down" + std::to_string(l);
+            conv_forward(Ly(dn), net->p, A(b), A(dn), B, D(l), D(l + 1), 1, s);
+            h = A(dn);
+        }
+    }
+    const float* d = A("enc" + std::to_string(Lv - 1) + "b");
+    for (int l = Lv - 2; l >= 0; --l) {
+        const std::string up = "up" + std::to_string(l), mg = "merge" + std::to_string(l);
+        const long long nu = net->aux[2 * l].n;
+        hipLaunchKernelGGL(k_upsample, dim3(nblocks(nu)), dim3(256), 0, s, d, net->aux[2 * l].d, B, D(l + 1)[0],
+                           D(l + 1)[1], D(l + 1)[2], D(l)[0], D(l)[1], D(l)[2], C);
+        conv_forward(Ly(up), net->p, net->aux[2 * l].d, A(up), B, D(l), D(l), 1, s);
+        const long long nv = (long long)B * D(l)[0] * D(l)[1] * D(l)[2];
+        hipLaunchKernelGGL(k_concat, dim3(nblocks(nv * 2 * C)), dim3(256), 0, s, A(up),
+                           A("enc" + std::to_string(l) + "b"), net->aux[2 * l + 1].d, nv, C, C);
+        conv_forward(Ly(mg), net->p, net->aux[2 * l + 1].d, A(mg), B, D(l), D(l), 1, s);
+        d = A(mg);
+    }
+    conv_forward(Ly("out"), net->p, d, A("out"), B, D(0), D(0), 0, s);
+    return A("out");
+}
+
+// Backward pass for upstream gradient dy of the output; fills net->g.
+void backward(dg_net* net, const float* dy, hipStream_t s) {
+    const int B = net->B, Lv = net->cfg.levels, C = net->cfg.channels;
+    auto A = [&](const std::string& n) { return net->act[layer_index(net, n)].d; };
+    auto Ly = [&](const std::string& n) -> const dg_net::Layer& { return net->layers[layer_index(net, n)]; };
+    auto D = [&](int l) { return net->dims[l].data(); };
+    auto nv = [&](int l) { return (long long)B * D(l)[0] * D(l)[1] * D(l)[2]; };
+    float *g0 = net->grd[0].d, *g1 = net->grd[1].d, *g2 = net->grd[2].d, *g3 = net->grd[3].d;
+    // encoder skip gradients are kept in the aux buffers of the upsampled inputs (free after forward)
+    const float* dout = (Lv >= 2) ? A("merge0") : A("enc0b");
+    conv_backward(net, Ly("out"), dout, dy, g0, B, D(0), D(0), s);  // g0 = grad of d_0
+    for (int l = 0; l < Lv - 1; ++l) {
+        const std::string up = "up" + std::to_string(l), mg = "merge" + std::to_string(l);
+        // through the ReLU of merge_l
+        hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, g0, A(mg), nv(l) * C);
+        conv_backward(net, Ly(mg), net->aux[2 * l + 1].d, g0, g1, B, D(l), D(l), s);  // g1 = grad of concat
+        // split: u part -> g2, skip part -> aux[2l] (reused as the skip gradient of e_l)
+        hipLaunchKernelGGL(k_split, dim3(nblocks(nv(l) * 2 * C)), dim3(256), 0, s, g1, g2, net->aux[2 * l].d,
+                           nv(l), C, C, 0);
+        hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, g2, A(up), nv(l) * C);
+        // input of up_l is upsample(d_{l+1}); recompute it into g3 for the weight gradient
+        const float* dsrc = (l + 1 == Lv - 1) ? A("enc" + std::to_string(l + 1) + "b") : A("merge" + std::to_string(l + 1));
+        hipLaunchKernelGGL(k_upsample, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, dsrc, g3, B, D(l + 1)[0],
+                           D(l + 1)[1], D(l + 1)[2], D(l)[0], D(l)[1], D(l)[2], C);
+        conv_backward(net, Ly(up), g3, g2, g1, B, D(l), D(l), s);  // g1 = grad of the upsampled tensor
+        hipLaunchKernelGGL(k_upsample_bwd, dim3(nblocks(nv(l + 1) * C)), dim3(256), 0, s, g1, g0, B, D(l + 1)[0],
+                           D(l + 1)[1], D(l + 1)[2], D(l)[0], D(l)[1], D(l)[2], C);  // g0 = grad of d_{l+1}
+    }
+    // encoder, from the bottom level up; g0 holds the gradient of e_{L-1}
+    for (int l = Lv - 1; l >= 0; --l) {
+        const std::string a = "enc" + std::to_string(l) + "a", b = "enc" + std::to_string(l) + "b";
+        if (l < Lv - 1) {
+            // total gradient of e_l = skip part (aux[2l]) + down path (g0)
+            hipLaunchKernelGGL(k_add, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, g0, net->aux[2 * l].d, nv(l) * C);
+        }
+        hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, g0, A(b), nv(l) * C);
+        conv_backward(net, Ly(b), A(a), g0, g1, B, D(l), D(l), s);  // g1 = grad of a
+        hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, g1, A(a), nv(l) * C);
+        const float* hin = (l == 0) ? A("in") : A("down" + std::to_string(l - 1));
+        conv_backward(net, Ly(a), hin, g1, g0, B, D(l), D(l), s);  // g0 = grad of h_l
+        hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, g0, hin, nv(l) * C);
+        if (l > 0) {
+            const std::string dn = "down" + std::to_string(l - 1);
+            conv_backward(net, Ly(dn), A("enc" + std::to_string(l - 1) + "b"), g0, g1, B, D(l - 1), D(l), s);
+            std::swap(g0, g1);  // g0 = down-path gradient of e_{l-1}
+        }
+    }
+    conv_backward(net, Ly("in"), net->xin.d, g0, nullptr, B, D(0), D(0), s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_net_last_error(void) { return g_net_err.c_str(); }
+
+dg_status dg_net_create(const dg_net_config* cfg, dg_net** out) {
+    return net_guard([&] {
+        if (!cfg || !out) throw NetError("null argument");
+        if (cfg->levels < 1 || cfg->levels > 6 || cfg->channels < 1 || cfg->channels > 256 || cfg->in_channels < 1 ||
+            cfg->out_channels < 1)
+            throw NetError("invalid network configuration");
+        auto* net = new dg_net();
+        net->cfg = *cfg;
+        const int Lv = cfg->levels, C = cfg->channels;
+        auto add = [&](const std::string& n, int k, int s, int ci, int co) {
+            dg_net::Layer L{n, k, s, ci, co, 0, 0};
+            L.woff = net->nparams;
+            net->nparams += (long long)k * k * k * ci * co;
+            L.boff = net->nparams;
+            net->nparams += co;
+            net->layers.push_back(L);
+        };
+        add("in", 1, 1, cfg->in_channels, C);
+        for (int l = 0; l < Lv; ++l) {
+            add("enc" + std::to_string(l) + "a", 3, 1, C, C);
+            add("enc" + std::to_string(l) + "b", 3, 1, C, C);
+            if (l < Lv - 1) add("down" + std::to_string(l), 3, 2, C, C);
+        }
+        for (int l = Lv - 2; l >= 0; --l) {
+            add("up" + std::to_string(l), 3, 1, C, C);
+            add("merge" + std::to_string(l), 3, 1, 2 * C, C);
+        }
+        add("out", 1, 1, C, cfg->out_channels);
+        net->p = nalloc<float>(net->nparams);
+        net->g = nalloc<float>(net->nparams);
+        net->m = nalloc<float>(net->nparams);
+        net->v = nalloc<float>(net->nparams);
+        NCHK(hipMemset(net->p, 0, sizeof(float) * net->nparams));
+        NCHK(hipMemset(net->m, 0, sizeof(float) * net->nparams));
+        NCHK(hipMemset(net->v, 0, sizeof(float) * net->nparams));
+        *out = net;
+    });
+}
+
+void dg_net_destroy(dg_net* net) {
+    if (!net) return;
+    (void)hipDeviceSynchronize();
+    for (auto& b : net->act) nfree(b.d);
+    for (auto& b : net->aux) nfree(b.d);
+    for (auto& b : net->grd) nfree(b.d);
+    nfree(net->xin.d);
+    nfree(net->p); nfree(net->g); nfree(net->m); nfree(net->v); nfree(net->part);
+    nfree(net->e); nfree(net->Ae); nfree(net->tAt); nfree(net->dpart); nfree(net->scale); nfree(net->vtmp);
+    nfree(net->xbuf); nfree(net->ybuf); nfree(net->dybuf);
+    delete net;
+}
+
+long long dg_net_num_params(const dg_net* net) { return net ? net->nparams : -1; }
+
+dg_status dg_net_set_params(dg_net* net, const float* params, long long n) {
+    return net_guard([&] {
+        if (!net || !params || n != net->nparams) throw NetError("parameter count mismatch");
+        NCHK(hipMemcpy(net->p, params, sizeof(float) * n, hipMemcpyHostToDevice));
+        NCHK(hipMemset(net->m, 0, sizeof(float) * n));
+        NCHK(hipMemset(net->v, 0, sizeof(float) * n));
+        net->t = 0;
+    });
+}
+
+dg_status dg_net_get_params(const dg_net* net, float* params, long long n) {
+    return net_guard([&] {
+        if (!net || !params || n != net->nparams) throw NetError("parameter count mismatch");
+        NCHK(hipMemcpy(params, net->p, sizeof(float) * n, hipMemcpyDeviceToHost));
+    });
+}
+
+dg_status dg_net_forward(dg_net* net, int batch, const int* ne, const float* x, float* y, hipStream_t stream) {
+    return net_guard([&] {
+        if (!net || !ne || !x || !y || batch < 1) throw NetError("bad arguments");
+        const float* out = forward(net, batch, ne, x, stream);
+        const long long n = (long long)batch * ne[0] * ne[1] * ne[2] * net->cfg.out_channels;
+        NCHK(hipMemcpyAsync(y, out, sizeof(float) * n, hipMemcpyDeviceToDevice, stream));
+        NCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_net_backward(dg_net* net, const float* dy, float* grad, hipStream_t stream) {
+    return net_guard([&] {
+        if (!net || !dy || net->B == 0) throw NetError("call dg_net_forward first");
+        backward(net, dy, stream);
+        if (grad) NCHK(hipMemcpyAsync(grad, net->g, sizeof(float) * net->nparams, hipMemcpyDeviceToDevice, stream));
+        NCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_net_adam(dg_net* net, float lr, float b1, float b2, float eps, hipStream_t stream) {
+    return net_guard([&] {
+        if (!net) throw NetError("null net");
+        net->t += 1;
+        const float c1 = 1.f - std::pow(b1, (float)net->t), c2 = 1.f - std::pow(b2, (float)net->t);
+        hipLaunchKernelGGL(k_adam, dim3(nblocks(net->nparams)), dim3(256), 0, stream, net->p, net->g, net->m, net->v,
+                           net->nparams, lr, b1, b2, eps, c1, c2);
+        NCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_net_save(const dg_net* net, const char* path) {
+    return net_guard([&] {
+        if (!net || !path) throw NetError("bad arguments");
+        std::vector<float> h(net->nparams);
+        NCHK(hipMemcpy(h.data(), net->p, sizeof(float) * net->nparams, hipMemcpyDeviceToHost));
+        std::ofstream f(path, std::ios::binary);
+        if (!f) throw NetError(std::string("cannot write ") + path);
+        const char magic[8] = {'D', 'G', 'N', 'E', 'T', '0', '0', '1'};
+        f.write(magic, 8);
+        const int hdr[4] = {net->cfg.levels, net->cfg.channels, net->cfg.in_channels, net->cfg.out_channels};
+        f.write((const char*)hdr, sizeof(hdr));
+        const long long n = net->nparams;
+        f.write((const char*)&n, sizeof(n));
+        f.write((const char*)h.data(), sizeof(float) * n);
+    });
+}
+
+dg_status dg_net_load(dg_net* net, const char* path) {
+    return net_guard([&] {
+        if (!net || !path) throw NetError("bad arguments");
+        std::ifstream f(path, std::ios::binary);
+        if (!f) throw NetError(std::string("cannot read ") + path);
+        char magic[8];
+        f.read(magic, 8);
+        if (std::memcmp(magic, "DGNET001", 8) != 0) throw NetError("not a network file");
+        int hdr[4];
+        f.read((char*)hdr, sizeof(hdr));
+        if (hdr[0] != net->cfg.levels || hdr[1] != net->cfg.channels || hdr[2] != net->cfg.in_channels ||
+            hdr[3] != net->cfg.out_channels)
+            throw NetError("network file has a different configuration");
+        long long n = 0;
+        f.read((char*)&n, sizeof(n));
+        if (n != net->nparams) throw NetError("network file has a different size");
+        std::vector<float> h(n);
+        f.read((char*)h.data(), sizeof(float) * n);
+        if (!f) throw NetError("truncated network file");
+        NCHK(hipMemcpy(net->p, h.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+        NCHK(hipMemset(net->m, 0, sizeof(float) * n));
+        NCHK(hipMemset(net->v, 0, sizeof(float) * n));
+        net->t = 0;
+    });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// training step and guess, using the solver context (dg_api.hip)
+
+namespace dg {
+// Provided by dg_api.hip.
+const LevelHost& ctx_fine_level(const dg_ctx* ctx, int mesh_id);
+}
+
+namespace {
+
+void ensure_field(dg_net* net, long long n, int B) {
+    if (net->cap_field >= n) return;
+    nfree(net->e); nfree(net->Ae); nfree(net->tAt); nfree(net->dpart); nfree(net->scale); nfree(net->vtmp);
+    nfree(net->xbuf); nfree(net->ybuf); nfree(net->dybuf);
+    net->e = nalloc<double>(n);
+    net->Ae = nalloc<double>(n);
+    net->vtmp = nalloc<double>(n);
+    net->tAt = nalloc<double>(B * 4 + 4);
+    net->scale = nalloc<double>(B * 4 + 4);
+    net->dpart = nalloc<double>((long long)(B * 4 + 4) * 64);
+    net->xbuf = nalloc<float>(n);
+    net->ybuf = nalloc<float>(n);
+    net->dybuf = nalloc<float>(n);
+    net->cap_field = n;
+}
+
+// per-sample dot products a.b over n values, B samples -> host
+std::vector<double> sample_dots(dg_net* net, const double* a, const double* b, long long n, int B, hipStream_t s) {
+    const int nb = 64;
+    hipLaunchKernelGGL(k_dot_part, dim3(nb, B), dim3(256), 0, s, a, b, net->dpart, n);
+    std::vector<double> h((size_t)B * nb), out(B, 0.0);
+    NCHK(hipMemcpyAsync(h.data(), net->dpart, sizeof(double) * B * nb, hipMemcpyDeviceToHost, s));
+    NCHK(hipStreamSynchronize(s));
+    for (int b2 = 0; b2 < B; ++b2)
+        for (int i = 0; i < nb; ++i) out[b2] += h[(size_t)b2 * nb + i];
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Scaled input x = rho / s with s = rms(rho) per sample (FP32 out), s to scale (device [B]).
+dg_status dg_net_prepare_input(dg_net* net, int batch, long long n_dofs, const double* rho, float* x, double* scale,
+                               hipStream_t stream) {
+    return net_guard([&] {
+        if (!net || !rho || !x || !scale || batch < 1 || n_dofs < 1) throw NetError("bad arguments");
+        ensure_field(net, n_dofs * batch, batch);
+        const int nb = 64;
+        hipLaunchKernelGGL(k_sumsq, dim3(nb, batch), dim3(256), 0, stream, rho, net->dpart, n_dofs);
+        hipLaunchKernelGGL(k_scale_of, dim3(batch), dim3(64), 0, stream, net->dpart, nb, n_dofs, scale);
+        hipLaunchKernelGGL(k_to_input, dim3(nb, batch), dim3(256), 0, stream, rho, scale, x, n_dofs);
+        NCHK(hipGetLastError());
+    });
+}
+
+// One training step on a batch: forward on x, relative A-norm loss against the
+// scaled targets t (FP64, field order), backward, Adam.  Returns the mean loss.
+dg_status dg_net_train_step(dg_net* net, dg_ctx* ctx, int mesh_id, int batch, const float* x, const double* t,
+                            float lr, double* loss, hipStream_t stream) {
+    return net_guard([&] {
+        if (!net || !ctx || !x || !t || batch < 1) throw NetError("bad arguments");
+        const dg::LevelHost& L0 = dg::ctx_fine_level(ctx, mesh_id);
+        const int ne[3] = {L0.E[0], L0.E[1], L0.E[2]};
+        const long long nd = L0.ndof;
+        if (net->cfg.in_channels != L0.n * L0.n * L0.n || net->cfg.out_channels != L0.n * L0.n * L0.n)
+            throw NetError("network channels must equal the nodes per element");
+        ensure_field(net, nd * batch, batch);
+        const float* y = forward(net, batch, ne, x, stream);
+        const long long n = nd * batch;
+        hipLaunchKernelGGL(k_err, dim3(nblocks(n)), dim3(256), 0, stream, y, t, net->e, n);
+        dg::launch_brick<double>(dg::BM_APPLY, L0, L0.dev64, batch, nullptr, net->e, nullptr, nullptr, nullptr,
+                                 net->Ae, nullptr, nullptr, 0, 0, 0, stream);
+        dg::launch_brick<double>(dg::BM_APPLY, L0, L0.dev64, batch, nullptr, t, nullptr, nullptr, nullptr, net->vtmp,
+                                 nullptr, nullptr, 0, 0, 0, stream);
+        std::vector<double> eAe = sample_dots(net, net->e, net->Ae, nd, batch, stream);
+        std::vector<double> tAt = sample_dots(net, t, net->vtmp, nd, batch, stream);
+        double L = 0.0;
+        for (int b = 0; b < batch; ++b) L += eAe[b] / tAt[b];
+        if (loss) *loss = L / batch;
+        // d(mean loss)/dy = 2 A e / (tAt B)
+        std::vector<double> scaled(batch);
+        for (int b = 0; b < batch; ++b) scaled[b] = tAt[b] * batch;
+        NCHK(hipMemcpyAsync(net->tAt, scaled.data(), sizeof(double) * batch, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(k_loss_grad, dim3(64, batch), dim3(256), 0, stream, net->Ae, net->tAt, net->dybuf, nd);
+        backward(net, net->dybuf, stream);
+        net->t += 1;
+        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+        const float c1 = 1.f - std::pow(b1, (float)net->t), c2 = 1.f - std::pow(b2, (float)net->t);
+        hipLaunchKernelGGL(k_adam, dim3(nblocks(net->nparams)), dim3(256), 0, stream, net->p, net->g, net->m, net->v,
+                           net->nparams, lr, b1, b2, eps, c1, c2);
+        NCHK(hipGetLastError());
+    });
+}
+
+// Initial guesses v0 = s * net(rho / s) for a batch of fields (FP64 in and out).
+dg_status dg_net_guess(dg_net* net, int batch, const int* ne, long long n_dofs, const double* rho, double* v0,
+                       hipStream_t stream) {
+    return net_guard([&] {
+        if (!net || !ne || !rho || !v0 || batch < 1) throw NetError("bad arguments");
+        ensure_field(net, n_dofs * batch, batch);
+        const int nb = 64;
+        hipLaunchKernelGGL(k_sumsq, dim3(nb, batch), dim3(256), 0, stream, rho, net->dpart, n_dofs);
+        hipLaunchKernelGGL(k_scale_of, dim3(batch), dim3(64), 0, stream, net->dpart, nb, n_dofs, net->scale);
+        hipLaunchKernelGGL(k_to_input, dim3(nb, batch), dim3(256), 0, stream, rho, net->scale, net->xbuf, n_dofs);
+        const float* y = forward(net, batch, ne, net->xbuf, stream);
+        hipLaunchKernelGGL(k_from_output, dim3(nb, batch), dim3(256), 0, stream, y, net->scale, v0, n_dofs);
+        NCHK(hipGetLastError());
+    });
+}
+
+}  // extern "C"

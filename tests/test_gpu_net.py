@@ -1,0 +1,145 @@
+"""GPU parity of the learned-guess network against the oracle U-Net.
+
+Forward and backward of the HIP kernels (FP32) against oracle/convnet.py
+(FP64) with the same parameters, one training step (A-norm loss through the
+library's operator, gradient, Adam) against the oracle, and the guess path
+of the solver (a guess never changes the converged answer; the guard keeps
+only guesses whose residual is below ||b||).
+"""
+import numpy as np
+import pytest
+
+from oracle import convnet, layout, sipdg
+from workloads import configs
+
+from _cases import POT_BAR, gpu_sample, oracle_density_problem, rel_l2_M
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=np.float64):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+@pytest.mark.parametrize("levels,E", [(3, (6, 4, 5)), (1, (3, 3, 2)), (4, (8, 8, 8))])
+def test_forward_backward_match_oracle(gpu_lib, levels, E):
+    C, cin = 8, 27
+    specs = convnet.layer_specs(levels, C, cin, cin)
+    n = convnet.param_count(specs)
+    rng = np.random.default_rng(levels)
+    params = (0.3 * rng.standard_normal(n)).astype(np.float32)
+    net = gpu_lib.Net(levels, C, cin, cin)
+    assert net.num_params == n
+    net.set_params(params)
+    assert np.array_equal(net.get_params(), params)
+    B = 2
+    x = rng.standard_normal((B, E[2], E[1], E[0], cin)).astype(np.float32)
+    y = net.forward(_t(x, np.float32), E, B).cpu().numpy().reshape(B, E[2], E[1], E[0], cin)
+    y_ref, cache = convnet.forward(params.astype(np.float64), specs, levels, x.astype(np.float64))
+    assert np.abs(y - y_ref).max() <= 1e-4 * np.abs(y_ref).max()
+    dy = rng.standard_normal(y.shape).astype(np.float32)
+    g = net.backward(_t(dy, np.float32)).cpu().numpy()
+    g_ref = convnet.backward(params.astype(np.float64), specs, levels, cache, dy.astype(np.float64))
+    assert np.abs(g - g_ref).max() <= 2e-4 * np.abs(g_ref).max()
+
+
+def test_train_step_matches_oracle(gpu_lib):
+    import torch
+    mesh = configs.Mesh((4, 4, 4), 2, (-2.0,) * 3, (2.0,) * 3)
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)])
+    levels, C, cin = 2, 8, 27
+    specs = convnet.layer_specs(levels, C, cin, cin)
+    n = convnet.param_count(specs)
+    rng = np.random.default_rng(7)
+    params = (0.2 * rng.standard_normal(n)).astype(np.float32)
+    net = gpu_lib.Net(levels, C, cin, cin)
+    net.set_params(params)
+    B = 2
+    nd = ctx.info[0]["n_dofs"]
+    x = rng.standard_normal((B, nd)).astype(np.float32)
+    t = rng.standard_normal((B, nd))
+    lr = 1e-3
+    loss = net.train_step(ctx, _t(x, np.float32), _t(t), B, lr)
+    # oracle: the same loss, gradient and Adam step
+    axes = sipdg.make_axes(mesh.E, mesh.p, mesh.lo, mesh.hi)
+    xs = x.reshape(B, 4, 4, 4, cin).astype(np.float64)
+    y, cache = convnet.forward(params.astype(np.float64), specs, levels, xs)
+    y = y.reshape(B, nd)
+    dy = np.zeros_like(y)
+    L = 0.0
+    for b in range(B):
+        e = layout.to_global(y[b] - t[b], mesh.E, 3)
+        Ae = sipdg.apply(axes, e)
+        tg = layout.to_global(t[b], mesh.E, 3)
+        tAt = float(np.sum(tg * sipdg.apply(axes, tg)))
+        L += float(np.sum(e * Ae)) / tAt / B
+        dy[b] = layout.to_element_major(2.0 * Ae / (tAt * B), mesh.E, 3)
+    assert abs(loss - L) <= 1e-5 * abs(L)
+    g = convnet.backward(params.astype(np.float64), specs, levels, cache, dy.reshape(B, 4, 4, 4, cin))
+    p1, _, _ = convnet.adam(params.astype(np.float64), g, np.zeros(n), np.zeros(n), 1, lr)
+    got = net.get_params()
+    moved = np.abs(p1 - params) > 1e-5   # Adam's first step is lr * sign(g) where |g| is not tiny
+    assert np.abs(got - p1)[moved].max() <= 1e-6 + 1e-3 * lr
+
+
+def test_guess_path_keeps_converged_answer_and_guard(gpu_lib):
+    import torch
+    wl = configs.scaled(8, 4, 3, seed=51)
+    mesh = wl.meshes[0]
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=1e-11)
+    rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+    rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+    net = gpu_lib.Net(3, 8, 125, 125)
+    rng = np.random.default_rng(3)
+    net.set_params((0.05 * rng.standard_normal(net.num_params)).astype(np.float32))
+    ctx.attach_guess(net)
+    v, st = ctx.solve_batch(rho, g)
+    v = v.cpu().numpy().reshape(3, -1)
+    for k, d in enumerate(wl.batch.densities):
+        axes, _, _, b = oracle_density_problem(mesh, d)
+        from oracle import fdm
+        assert rel_l2_M(axes, mesh, v[k], fdm.FDM(axes).solve(b)) <= POT_BAR
+        assert st[k]["guess_used"] in (0, 1) and st[k]["status"] == 0
+    # a zero network gives v0 = 0, whose residual equals ||b||: the guard rejects it
+    net.set_params(np.zeros(net.num_params, dtype=np.float32))
+    _, st0 = ctx.solve_batch(rho, g)
+    assert all(s["guess_used"] == 0 for s in st0)
+    ctx.attach_guess(None)
+    _, st1 = ctx.solve_batch(rho, g)
+    assert [s["iters"] for s in st1] == [s["iters"] for s in st0]
+
+
+def test_training_reduces_loss_and_save_load_roundtrip(gpu_lib, tmp_path):
+    import torch
+    wl = configs.scaled(8, 4, 8, seed=61)
+    mesh = wl.meshes[0]
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=1e-8)
+    rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+    rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+    v, _ = ctx.solve_batch(rho, g)
+    net = gpu_lib.Net(3, 16, 125, 125)
+    rng = np.random.default_rng(9)
+    net.set_params(_init(net, rng))
+    B = 8
+    nd = ctx.info[0]["n_dofs"]
+    x, s = net.prepare_input(rho, B, nd)
+    t = v / s.repeat_interleave(nd)
+    losses = [net.train_step(ctx, x, t, B, 2e-3) for _ in range(60)]
+    assert losses[-1] < 0.5 * losses[0]
+    path = tmp_path / "net.bin"
+    net.save(path)
+    net2 = gpu_lib.Net(3, 16, 125, 125)
+    net2.load(path)
+    assert np.array_equal(net2.get_params(), net.get_params())
+
+
+def _init(net, rng):
+    """He-style initial weights for the layer sizes of the architecture (biases zero)."""
+    specs = convnet.layer_specs(net.levels, net.channels, net.in_channels, net.out_channels)
+    out = []
+    for name, k, s, ci, co in specs:
+        fan_in = k ** 3 * ci
+        scale = np.sqrt(2.0 / fan_in) if name != "out" else np.sqrt(1.0 / fan_in)
+        out += [scale * rng.standard_normal(k ** 3 * ci * co), np.zeros(co)]
+    return np.concatenate(out).astype(np.float32)
