@@ -31,7 +31,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="exchange8", choices=["exchange8", "exchange16"])
-    ap.add_argument("--arms", default="fp32_ir,fp64")
+    ap.add_argument("--arms", default="fp32_ir+learned,fp32_ir,fp64+learned,fp64")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2510_21213_amd", "weights", "guess_16e_p4.bin"))
     ap.add_argument("--cpu-sample", type=int, default=2, help="pair solves timed on the oracle (0: skip)")
     ap.add_argument("--check-sample", type=int, default=4, help="pairs compared with the exact solve (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -67,9 +68,16 @@ def main():
     arms = [a for a in args.arms.split(",") if a]
     results = {}
     first_ctx = None
+    net = None
     for arm in arms:
+        prec, _, learned = arm.partition("+")
         ctx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
-                              precision=arm)
+                              precision=prec)
+        if learned:
+            if net is None:
+                net = binding.Net(4, 32, 125, 27)
+                net.load(args.weights)
+            ctx.attach_guess(net)
         if first_ctx is None:
             xyz, fxyz = ctx.mesh_coords(0)
             phi = torch.as_tensor(orb.values(xyz[0], xyz[1], xyz[2]).reshape(-1)).cuda()
@@ -80,12 +88,13 @@ def main():
         torch.cuda.synchronize()
         ctx.profile(True)
         t0 = time.perf_counter()
-        iters, outer, res = [], [], []
+        iters, outer, res, used = [], [], [], []
         for _ in range(args.steps):
             W, K, EX, st, _ = ctx.exchange(phi, g)
             iters += [s["iters"] for s in st]
             outer += [s["outer_iters"] for s in st]
             res += [s["rel_residual"] for s in st]
+            used += [s["guess_used"] for s in st]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         prof = ctx.profile_read()
@@ -94,7 +103,9 @@ def main():
             # the runtime could not time events recorded inside the captured graph: time the
             # same steps on eager launches instead (same kernels, same inputs)
             ectx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
-                                   precision=arm, use_graph=0)
+                                   precision=prec, use_graph=0)
+            if learned:
+                ectx.attach_guess(net)
             ectx.exchange(phi, g)
             ectx.profile(True)
             for _ in range(args.steps):
@@ -112,23 +123,24 @@ def main():
             "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
             "outer_mean": float(np.mean(outer)),
             "max_rel_residual": float(np.max(res)),
+            "guess_used": float(np.mean(used)) if learned else 0.0,
             "E_x": EX,
             "prof": prof,
             "ctx": ctx,
         }
 
-    head = results.get("fp32_ir") or results[arms[0]]
-    head_arm = "fp32_ir" if "fp32_ir" in results else arms[0]
+    head_arm = arms[0]
+    head = results[head_arm]
     prof = head["prof"]
     achieved = prof["bytes"] / prof["seconds"] / 1e9 if prof["seconds"] > 0 else None
     roofline = {
         "bound": "hbm",
         "kernel": "finest-level Chebyshev smoothing step (k_brick, N=5, BM_CHEB/BM_CHEBDOT, "
-                  + ("float" if head_arm == "fp32_ir" else "double") + ")",
+                  + ("float" if head_arm.startswith("fp32_ir") else "double") + ")",
         "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
         "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
         "traffic": measured_traffic("cheb_step_exchange8.md", "dg_kernels.hip")
-        if (head_arm == "fp32_ir" and args.config == "exchange8") else None,
+        if (head_arm.startswith("fp32_ir") and args.config == "exchange8") else None,
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
         "algorithmic_bytes_per_launch": prof["bytes"] / max(1, prof["launches"]),
         "avg_launch_us": 1e6 * prof["seconds"] / max(1, prof["launches"]),
@@ -156,14 +168,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if head_arm == "fp32_ir" else "f64",
+        "dtype": "f32" if head_arm.startswith("fp32_ir") else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {npairs} pair-density RHS, {mesh.E[0]}^3 elements p={mesh.p} "
                                f"({first_ctx.info[0]['n_dofs']} DOFs/RHS), {wl.n_levels}-level MG-PCG to {wl.rtol}",
-                   "arm": head_arm, "learned_guess": False, "parallelism": "single GPU"},
+                   "arm": head_arm, "learned_guess": "learned" in head_arm, "parallelism": "single GPU"},
         "arms": arms_out,
-        "fp64_vs_mixed_speedup": (results["fp32_ir"]["value"] / results["fp64"]["value"])
-        if "fp32_ir" in results and "fp64" in results else None,
+        "speedup_vs_plain_fp64": (head["value"] / results["fp64"]["value"]) if "fp64" in results else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "check_vs_exact": check,

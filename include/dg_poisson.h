@@ -92,7 +92,8 @@ typedef struct {
     double rtol;         /* stop when ||b - A v||_2 <= rtol ||b||_2 (FP64 residual) */
     int max_iter;        /* PCG iterations per right-hand side (inner iterations in FP32_IR) */
     dg_precision precision;
-    double inner_rtol;   /* FP32_IR: relative tolerance of each inner solve */
+    double inner_rtol;   /* FP32_IR: relative tolerance of each inner solve (loosened for the last
+                            step to 0.9 rtol ||b|| / ||r_k|| when that is larger) */
     int max_outer;       /* FP32_IR: refinement steps */
     int check_every;     /* PCG iterations between host convergence checks */
     int use_graph;       /* 1: replay the PCG iteration as a captured HIP graph */
@@ -201,9 +202,11 @@ dg_status dg_level_info(const dg_ctx* ctx, int mesh_id, int level, int* ne, int*
  *                   d = relu(merge_l(concat(u, e_l)))        3x3x3, 2C -> C
  *   y = out(d)                                        1x1x1, C -> out_channels
  * Parameters: for each convolution in that order, W[tap][ci][co]
- * (tap = (dz*3+dy)*3+dx) then bias[co].  The guess for a source rho is
- * v0 = s * net(rho / s), s = rms(rho).  Training minimises the relative
- * A-norm error ||s y - v_ref||_A^2 / ||v_ref||_A^2 with Adam.  The network is not
+ * (tap = (dz*3+dy)*3+dx) then bias[co].  in_channels is the number of nodes
+ * of a finest-level element and out_channels that of a level-1 element.  The
+ * guess for a source rho is v0 = s P C net(rho / s), s = rms(rho) (see
+ * dg_net_guess).  Training minimises the relative A-norm error
+ * ||v0 - v_ref||_A^2 / ||v_ref||_A^2 with Adam.  The network is not
  * part of the paper; it only changes where PCG starts, and every solve still
  * stops on the FP64 residual. */
 typedef struct { int levels; int channels; int in_channels; int out_channels; } dg_net_config;
@@ -220,6 +223,9 @@ dg_status dg_net_get_params(const dg_net* net, float* params, long long n);
 dg_status dg_net_forward(dg_net* net, int batch, const int* ne, const float* x, float* y, hipStream_t stream);
 /* Gradient of sum(y * dy) for the last forward; grad (device, may be NULL) receives it. */
 dg_status dg_net_backward(dg_net* net, const float* dy, float* grad, hipStream_t stream);
+/* Forward convolutions on the matrix cores with BF16 operands and FP32
+ * accumulation (enable = 1, the default) or in FP32 on the vector units (0). */
+dg_status dg_net_set_bf16(dg_net* net, int enable);
 /* One Adam step on the gradient of the last backward. */
 dg_status dg_net_adam(dg_net* net, float lr, float b1, float b2, float eps, hipStream_t stream);
 /* x = rho / s, s = rms(rho) per sample (device: rho FP64 [batch][n_dofs], x FP32, scale FP64 [batch]). */
@@ -227,11 +233,18 @@ dg_status dg_net_prepare_input(dg_net* net, int batch, long long n_dofs, const d
                                hipStream_t stream);
 /* One training step on mesh mesh_id of ctx: forward on x, relative A-norm loss
  * against the scaled targets t = v_ref / s (FP64, packed fields), backward, Adam
- * with learning rate lr; *loss (host) receives the batch mean before the step. */
+ * with learning rate lr; *loss (host) receives the batch mean A-norm loss before
+ * the step.  mode selects the output gradient: 0 the A-norm gradient
+ * 2Ae/(t'At); 1 the relative nodal L2 gradient 2e/(t't); 2 the A-norm gradient
+ * preconditioned by one V-cycle, 2 B A e/(t'At) (well conditioned: B A e ~ e). */
 dg_status dg_net_train_step(dg_net* net, dg_ctx* ctx, int mesh_id, int batch, const float* x, const double* t, float lr,
-                            double* loss, hipStream_t stream);
-/* v0 = s * net(rho / s) (device FP64 packed fields). */
-dg_status dg_net_guess(dg_net* net, int batch, const int* ne, long long n_dofs, const double* rho, double* v0,
+                            int mode, double* loss, hipStream_t stream);
+/* v0 = s P C net(rho / s) for batch sources rho of mesh mesh_id of ctx (device
+ * FP64 packed fields).  The network's output is a field on multigrid level 1
+ * (one channel per node of that level's element); C averages every node
+ * shared by neighbouring elements over its copies (continuous field), P is
+ * the level-1 to level-0 interpolation of the V-cycle. */
+dg_status dg_net_guess(dg_net* net, const dg_ctx* ctx, int mesh_id, int batch, const double* rho, double* v0,
                        hipStream_t stream);
 /* Flat binary weight file: "DGNET001", 4 ints of configuration, count, floats. */
 dg_status dg_net_save(const dg_net* net, const char* path);

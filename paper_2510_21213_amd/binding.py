@@ -74,9 +74,10 @@ def _load():
         "dg_net_backward": (I, [P, P, P, P]),
         "dg_net_adam": (I, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),
         "dg_net_prepare_input": (I, [P, I, LL, P, P, P, P]),
-        "dg_net_train_step": (I, [P, P, I, I, P, P, ctypes.c_float, ctypes.POINTER(D), P]),
-        "dg_net_guess": (I, [P, I, P, LL, P, P, P]),
+        "dg_net_train_step": (I, [P, P, I, I, P, P, ctypes.c_float, I, ctypes.POINTER(D), P]),
+        "dg_net_guess": (I, [P, P, I, I, P, P, P]),
         "dg_net_save": (I, [P, ctypes.c_char_p]),
+        "dg_net_set_bf16": (I, [P, I]),
         "dg_net_load": (I, [P, ctypes.c_char_p]),
         "dg_poisson_attach_guess": (I, [P, P]),
         "dg_profile_read": (I, [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]),
@@ -298,7 +299,7 @@ def _ncheck(code, what):
 class Net:
     """The learned-initial-guess U-Net (include/dg_poisson.h, dg_net_*)."""
 
-    def __init__(self, levels=4, channels=32, in_channels=125, out_channels=125):
+    def __init__(self, levels=4, channels=32, in_channels=125, out_channels=27):
         cfg = DgNetConfig(levels, channels, in_channels, out_channels)
         h = ctypes.c_void_p()
         _ncheck(lib.dg_net_create(ctypes.byref(cfg), ctypes.byref(h)), "net_create")
@@ -317,6 +318,10 @@ class Net:
             self.close()
         except Exception:
             pass
+
+    def set_bf16(self, enable=True):
+        """Forward convolutions on the matrix cores (BF16 operands, FP32 accumulation) or in FP32."""
+        _ncheck(lib.dg_net_set_bf16(self._h, 1 if enable else 0), "net_set_bf16")
 
     def set_params(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
@@ -350,17 +355,16 @@ class Net:
                                          _stream()), "net_prepare_input")
         return x, s
 
-    def train_step(self, ctx, x, t, batch, lr, mesh_id=0):
+    def train_step(self, ctx, x, t, batch, lr, mesh_id=0, mode=0):
+        """mode 0: A-norm gradient; 1: nodal L2 gradient; 2: V-cycle preconditioned A-norm gradient."""
         loss = ctypes.c_double()
         _ncheck(lib.dg_net_train_step(self._h, ctx._h, mesh_id, batch, _ptr_t(x, torch.float32), _ptr(t), lr,
-                                      ctypes.byref(loss), _stream()), "net_train_step")
+                                      mode, ctypes.byref(loss), _stream()), "net_train_step")
         return loss.value
 
-    def guess(self, rho, ne, batch):
-        n_dofs = rho.numel() // batch
-        ne_c = (ctypes.c_int * 3)(*ne)
+    def guess(self, ctx, rho, batch, mesh_id=0):
         v0 = torch.empty_like(rho)
-        _ncheck(lib.dg_net_guess(self._h, batch, ne_c, n_dofs, _ptr(rho), _ptr(v0), _stream()), "net_guess")
+        _ncheck(lib.dg_net_guess(self._h, ctx._h, mesh_id, batch, _ptr(rho), _ptr(v0), _stream()), "net_guess")
         return v0
 
     def save(self, path):

@@ -514,10 +514,17 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             if (!any) break;
             dg::launch_to_inner(n0, nrhs, M.st, M.r64, W.r, s);
             dg::launch_fill<float>(W.x, 0.0f, n0 * nrhs, s);
-            // inner state: relative tolerance inner_rtol on ||r32|| = 1
+            // inner state on ||r32|| = 1: relative tolerance inner_rtol, loosened for the last
+            // refinement step to what the outer tolerance still needs, rtol ||b|| / ||r_k||
+            std::vector<double> tin(nrhs);
+            for (int i = 0; i < nrhs; ++i) {
+                const auto& O = M.st_host[i];
+                const double need = O.rr > 0 ? 0.9 * o.rtol * std::sqrt(O.bb / O.rr) : 1.0;
+                tin[i] = std::min(0.5, std::max(o.inner_rtol, need));
+            }
             for (int i = 0; i < nrhs; ++i) {
                 dg::RhsState S{};
-                S.tol2 = o.inner_rtol * o.inner_rtol;
+                S.tol2 = tin[i] * tin[i];
                 S.maxit = o.max_iter;
                 S.active = 1;
                 S.bb = 1.0;
@@ -558,8 +565,8 @@ std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho
         ctx->g_rho = dalloc<double>(n0 * nrhs);
         ctx->g_cap = n0 * nrhs;
     }
-    const int ne[3] = {L0.E[0], L0.E[1], L0.E[2]};
-    if (dg_net_guess(ctx->guess, nrhs, ne, n0, rho, ctx->g_x0, s) != DG_OK)
+    const int mesh_id = (int)(&M - ctx->meshes.data());
+    if (dg_net_guess(ctx->guess, ctx, mesh_id, nrhs, rho, ctx->g_x0, s) != DG_OK)
         throw ArgError(std::string("learned guess failed: ") + dg_net_last_error());
     ensure_state(M, nrhs);
     const int nc = dg::chunks_of(n0), nb = dg::bricks_of(L0);
@@ -748,6 +755,12 @@ namespace dg {
 const LevelHost& ctx_fine_level(const dg_ctx* ctx, int mesh_id) {
     check_mesh_id(ctx, mesh_id);
     return ctx->meshes[mesh_id].lv[0];
+}
+const LevelHost& ctx_level(const dg_ctx* ctx, int mesh_id, int level) {
+    check_mesh_id(ctx, mesh_id);
+    const auto& M = ctx->meshes[mesh_id];
+    if (level < 0 || level >= (int)M.lv.size()) throw std::runtime_error("level out of range");
+    return M.lv[level];
 }
 }  // namespace dg
 

@@ -81,6 +81,88 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ x, c
         if (co0 + c < Co) yo[c] = relu ? fmaxf(acc[c], 0.f) : acc[c];
 }
 
+// Same convolution as an implicit GEMM on the matrix cores: BF16 operands,
+// FP32 accumulation (v_mfma_f32_16x16x32_bf16).  A wave computes 16 output
+// voxels x 16*NB output channels; per tap and chunk of 32 input channels the
+// A operand is 8 channels of one input voxel per lane (lane = voxel m + 16 kb,
+// channels 8 kb .. 8 kb + 7) and the B operand 8 input channels of one output
+// channel from the transposed BF16 weights Wt[tap][co][ci] (zero padded to
+// CoP = 16 NB and CiP = multiple of 32).  The 16x16 result of a block holds
+// D[4 kb + r][m] in lane m + 16 kb, register r.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int KS, int STRIDE, int NB>
+__global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ x, const __bf16* __restrict__ Wt,
+                                                   const float* __restrict__ bias, float* __restrict__ y, int D, int H,
+                                                   int Wd, int Ci, int CiP, int Do, int Ho, int Wo, int Co,
+                                                   int relu) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nvo = Do * Ho * Wo;
+    const int vox0 = (blockIdx.x * 4 + wave) * 16;
+    const int b = blockIdx.y;
+    if (vox0 >= nvo) return;  // uniform per wave; the kernel has no barrier
+    const int m = lane & 15, kb = lane >> 4;
+    const int o = vox0 + m;
+    const bool ov = o < nvo;
+    const int ox = o % Wo, oy = (o / Wo) % Ho, oz = o / (Wo * Ho);
+    constexpr int PAD = (KS - 1) / 2;
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float* xb = x + (long long)b * D * H * Wd * Ci;
+    const bool vec = (Ci % 8) == 0;
+    for (int t = 0; t < KS * KS * KS; ++t) {
+        const int dz = t / (KS * KS), dy = (t / KS) % KS, dx = t % KS;
+        const int iz = oz * STRIDE - PAD + dz, iy = oy * STRIDE - PAD + dy, ix = ox * STRIDE - PAD + dx;
+        const bool valid = ov && iz >= 0 && iz < D && iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+        const float* xv = xb + (long long)((valid ? (iz * H + iy) * Wd + ix : 0)) * Ci;
+        for (int cc = 0; cc < CiP; cc += 32) {
+            const int ci0 = cc + 8 * kb;
+            bf16x8 a;
+            if (vec && valid && ci0 + 8 <= Ci) {
+                const float4 v0 = *reinterpret_cast<const float4*>(xv + ci0);
+                const float4 v1 = *reinterpret_cast<const float4*>(xv + ci0 + 4);
+                a[0] = (__bf16)v0.x; a[1] = (__bf16)v0.y; a[2] = (__bf16)v0.z; a[3] = (__bf16)v0.w;
+                a[4] = (__bf16)v1.x; a[5] = (__bf16)v1.y; a[6] = (__bf16)v1.z; a[7] = (__bf16)v1.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a[q] = (valid && ci0 + q < Ci) ? (__bf16)xv[ci0 + q] : (__bf16)0.f;
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const bf16x8 w = *reinterpret_cast<const bf16x8*>(Wt + ((long long)(t * NB * 16 + nb * 16 + m) * CiP + ci0));
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, acc[nb], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + m;
+        if (co >= Co) continue;
+        const float bco = bias[co];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o2 = vox0 + 4 * kb + r;
+            if (o2 < nvo) {
+                const float v = acc[nb][r] + bco;
+                y[((long long)b * nvo + o2) * Co + co] = relu ? fmaxf(v, 0.f) : v;
+            }
+        }
+    }
+}
+
+// Wt[t][co][ci] = bf16(W[t][ci][co]), zero padded to [taps][CoP][CiP].
+__global__ __launch_bounds__(256) void k_weights_bf16(const float* __restrict__ W, __bf16* __restrict__ Wt, int taps,
+                                                      int Ci, int Co, int CiP, int CoP) {
+    const long long n = (long long)taps * CoP * CiP;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int ci = (int)(i % CiP), co = (int)((i / CiP) % CoP), t = (int)(i / ((long long)CiP * CoP));
+    const float v = (ci < Ci && co < Co) ? W[((long long)t * Ci + ci) * Co + co] : 0.f;
+    Wt[i] = (__bf16)v;
+}
+
 // dx[b][i][ci] = sum over (o, t) with in(o,t) = i of sum_co dy[b][o][co] W[t][ci][co]
 template <int KS, int STRIDE>
 __global__ __launch_bounds__(256) void k_conv_bwd_data(const float* __restrict__ dy, const float* __restrict__ W,
@@ -331,6 +413,18 @@ __global__ __launch_bounds__(256) void k_loss_grad(const double* __restrict__ Ae
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
         dy[(long long)b * n + i] = (float)(c * Ae[(long long)b * n + i]);
 }
+__global__ __launch_bounds__(256) void k_err_d(const double* __restrict__ y, const double* __restrict__ t,
+                                               double* __restrict__ e, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) e[i] = y[i] - t[i];
+}
+__global__ __launch_bounds__(256) void k_loss_grad_d(const double* __restrict__ src, const double* __restrict__ den,
+                                                     double* __restrict__ g, long long n) {
+    const int b = blockIdx.y;
+    const double c = 2.0 / den[b];
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        g[(long long)b * n + i] = c * src[(long long)b * n + i];
+}
 __global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ a, const double* __restrict__ b,
                                                   double* __restrict__ part, long long n) {
     __shared__ double red[256];
@@ -345,6 +439,53 @@ __global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ a, 
         __syncthreads();
     }
     if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Continuous projection of a DG field (element-major, N nodes per element
+// edge): every node shared by neighbouring elements (faces, edges, corners)
+// is replaced by the average of its copies, gathered in a fixed order.
+template <int N>
+__global__ __launch_bounds__(256) void k_continuize(const double* __restrict__ u, double* __restrict__ w, int E0,
+                                                    int E1, int E2, long long ndof) {
+    constexpr int N3 = N * N * N;
+    const int b = blockIdx.y;
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= ndof) return;
+    const int qi = (int)q;
+    const int e = qi / N3, l = qi - e * N3;
+    const int ex = e % E0, ey = (e / E0) % E1, ez = e / (E0 * E1);
+    const int i = l % N, j = (l / N) % N, k = l / (N * N);
+    // per axis: own copy, plus the neighbour's copy when the node is on a shared face
+    int nex = 1, ney = 1, nez = 1;
+    int xe[2] = {ex, 0}, xi[2] = {i, 0}, ye[2] = {ey, 0}, yj[2] = {j, 0}, ze[2] = {ez, 0}, zk[2] = {k, 0};
+    if (i == 0 && ex > 0) { xe[1] = ex - 1; xi[1] = N - 1; nex = 2; }
+    if (i == N - 1 && ex < E0 - 1) { xe[1] = ex + 1; xi[1] = 0; nex = 2; }
+    if (j == 0 && ey > 0) { ye[1] = ey - 1; yj[1] = N - 1; ney = 2; }
+    if (j == N - 1 && ey < E1 - 1) { ye[1] = ey + 1; yj[1] = 0; ney = 2; }
+    if (k == 0 && ez > 0) { ze[1] = ez - 1; zk[1] = N - 1; nez = 2; }
+    if (k == N - 1 && ez < E2 - 1) { ze[1] = ez + 1; zk[1] = 0; nez = 2; }
+    const double* ub = u + (long long)b * ndof;
+    double s = 0.0;
+    for (int c = 0; c < nez; ++c)
+        for (int bb = 0; bb < ney; ++bb)
+            for (int a = 0; a < nex; ++a)
+                s += ub[(long long)((ze[c] * E1 + ye[bb]) * E0 + xe[a]) * N3 + (zk[c] * N + yj[bb]) * N + xi[a]];
+    w[(long long)b * ndof + q] = s / (double)(nex * ney * nez);
+}
+
+__global__ __launch_bounds__(256) void k_f2d(const float* __restrict__ a, double* __restrict__ b, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = (double)a[i];
+}
+__global__ __launch_bounds__(256) void k_d2f(const double* __restrict__ a, float* __restrict__ b, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+__global__ __launch_bounds__(256) void k_scale_samples(double* __restrict__ v, const double* __restrict__ scale,
+                                                       long long n) {
+    const int b = blockIdx.y;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        v[(long long)b * n + i] *= scale[b];
 }
 
 inline unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
@@ -363,6 +504,10 @@ struct dg_net {
     };
     std::vector<Layer> layers;
     long long nparams = 0;
+    bool bf16 = true;          // forward convolutions on the matrix cores (BF16 operands)
+    bool wt_dirty = true;      // BF16 weight copies out of date
+    __bf16* wt = nullptr;      // BF16 transposed weights, per layer at wtoff
+    std::vector<long long> wtoff;
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *part = nullptr;
     long long part_cap = 0;
     int t = 0;  // Adam steps taken
@@ -378,6 +523,7 @@ struct dg_net {
     std::vector<std::array<int, 3>> dims;  // spatial dims per level
     Buf xin;                               // copy of the last forward input
     double *e = nullptr, *Ae = nullptr, *tAt = nullptr, *dpart = nullptr, *scale = nullptr, *vtmp = nullptr;
+    double *w1 = nullptr, *w2 = nullptr, *x0 = nullptr;
     float *xbuf = nullptr, *ybuf = nullptr, *dybuf = nullptr;
     long long cap_field = 0;
 };
@@ -415,6 +561,45 @@ int layer_index(const dg_net* net, const std::string& name) {
     for (size_t i = 0; i < net->layers.size(); ++i)
         if (net->layers[i].name == name) return (int)i;
     throw NetError("no layer " + name);
+}
+
+inline int pad_to(int v, int m) { return (v + m - 1) / m * m; }
+
+void refresh_bf16(dg_net* net, hipStream_t s) {
+    if (!net->wt) {
+        long long tot = 0;
+        net->wtoff.clear();
+        for (const auto& L : net->layers) {
+            net->wtoff.push_back(tot);
+            tot += (long long)L.k * L.k * L.k * pad_to(L.co, 16) * pad_to(L.ci, 32);
+        }
+        net->wt = nalloc<__bf16>(tot);
+    }
+    for (size_t i = 0; i < net->layers.size(); ++i) {
+        const auto& L = net->layers[i];
+        const int taps = L.k * L.k * L.k, CiP = pad_to(L.ci, 32), CoP = pad_to(L.co, 16);
+        const long long n = (long long)taps * CoP * CiP;
+        hipLaunchKernelGGL(k_weights_bf16, dim3(nblocks(n)), dim3(256), 0, s, net->p + L.woff, net->wt + net->wtoff[i],
+                           taps, L.ci, L.co, CiP, CoP);
+    }
+    net->wt_dirty = false;
+}
+
+void conv_forward_mfma(const dg_net* net, int li, const float* x, float* y, int B, const int* din, const int* dout,
+                       int relu, hipStream_t s) {
+    const auto& L = net->layers[li];
+    const int CiP = pad_to(L.ci, 32), NB = pad_to(L.co, 16) / 16;
+    const int nvo = dout[0] * dout[1] * dout[2];
+    dim3 grid((nvo + 63) / 64, B);
+    const __bf16* Wt = net->wt + net->wtoff[li];
+    const float* b = net->p + L.boff;
+#define CM(KS, ST, NBV) hipLaunchKernelGGL((k_conv_mfma<KS, ST, NBV>), grid, dim3(256), 0, s, x, Wt, b, y, din[0], din[1], din[2], L.ci, CiP, dout[0], dout[1], dout[2], L.co, relu)
+#define CMN(KS, ST) switch (NB) { case 1: CM(KS, ST, 1); break; case 2: CM(KS, ST, 2); break; case 4: CM(KS, ST, 4); break; default: throw NetError("unsupported channel count for the matrix-core path"); }
+    if (L.k == 1) { CMN(1, 1) }
+    else if (L.s == 1) { CMN(3, 1) }
+    else { CMN(3, 2) }
+#undef CMN
+#undef CM
 }
 
 void conv_forward(const dg_net::Layer& L, const float* P, const float* x, float* y, int B, const int* din,
@@ -529,17 +714,25 @@ const float* forward(dg_net* net, int B, const int* E, const float* x, hipStream
     x = net->xin.d;
     const int Lv = net->cfg.levels, C = net->cfg.channels;
     auto A = [&](const std::string& n) { return net->act[layer_index(net, n)].d; };
-    auto Ly = [&](const std::string& n) -> const dg_net::Layer& { return net->layers[layer_index(net, n)]; };
     auto D = [&](int l) { return net->dims[l].data(); };
-    conv_forward(Ly("in"), net->p, x, A("in"), B, D(0), D(0), 1, s);
+    if (net->bf16 && net->wt_dirty) refresh_bf16(net, s);
+    // conv_forward by layer name, on the matrix cores when enabled
+    auto run = [&](const std::string& n, const float* in, float* out, const int* din, const int* dout, int relu) {
+        const int li = layer_index(net, n);
+        if (net->bf16)
+            conv_forward_mfma(net, li, in, out, B, din, dout, relu, s);
+        else
+            conv_forward(net->layers[li], net->p, in, out, B, din, dout, relu, s);
+    };
+    run("in", x, A("in"), D(0), D(0), 1);
     const float* h = A("in");
     for (int l = 0; l < Lv; ++l) {
         const std::string a = "enc" + std::to_string(l) + "a", b = "enc" + std::to_string(l) + "b";
-        conv_forward(Ly(a), net->p, h, A(a), B, D(l), D(l), 1, s);
-        conv_forward(Ly(b), net->p, A(a), A(b), B, D(l), D(l), 1, s);
+        run(a, h, A(a), D(l), D(l), 1);
+        run(b, A(a), A(b), D(l), D(l), 1);
         if (l < Lv - 1) {
             const std::string dn = "down" + std::to_string(l);
-            conv_forward(Ly(dn), net->p, A(b), A(dn), B, D(l), D(l + 1), 1, s);
+            run(dn, A(b), A(dn), D(l), D(l + 1), 1);
             h = A(dn);
         }
     }
@@ -549,14 +742,14 @@ const float* forward(dg_net* net, int B, const int* E, const float* x, hipStream
         const long long nu = net->aux[2 * l].n;
         hipLaunchKernelGGL(k_upsample, dim3(nblocks(nu)), dim3(256), 0, s, d, net->aux[2 * l].d, B, D(l + 1)[0],
                            D(l + 1)[1], D(l + 1)[2], D(l)[0], D(l)[1], D(l)[2], C);
-        conv_forward(Ly(up), net->p, net->aux[2 * l].d, A(up), B, D(l), D(l), 1, s);
+        run(up, net->aux[2 * l].d, A(up), D(l), D(l), 1);
         const long long nv = (long long)B * D(l)[0] * D(l)[1] * D(l)[2];
         hipLaunchKernelGGL(k_concat, dim3(nblocks(nv * 2 * C)), dim3(256), 0, s, A(up),
                            A("enc" + std::to_string(l) + "b"), net->aux[2 * l + 1].d, nv, C, C);
-        conv_forward(Ly(mg), net->p, net->aux[2 * l + 1].d, A(mg), B, D(l), D(l), 1, s);
+        run(mg, net->aux[2 * l + 1].d, A(mg), D(l), D(l), 1);
         d = A(mg);
     }
-    conv_forward(Ly("out"), net->p, d, A("out"), B, D(0), D(0), 0, s);
+    run("out", d, A("out"), D(0), D(0), 0);
     return A("out");
 }
 
@@ -662,9 +855,10 @@ void dg_net_destroy(dg_net* net) {
     for (auto& b : net->aux) nfree(b.d);
     for (auto& b : net->grd) nfree(b.d);
     nfree(net->xin.d);
+    nfree(net->wt);
     nfree(net->p); nfree(net->g); nfree(net->m); nfree(net->v); nfree(net->part);
     nfree(net->e); nfree(net->Ae); nfree(net->tAt); nfree(net->dpart); nfree(net->scale); nfree(net->vtmp);
-    nfree(net->xbuf); nfree(net->ybuf); nfree(net->dybuf);
+    nfree(net->xbuf); nfree(net->ybuf); nfree(net->dybuf); nfree(net->w1); nfree(net->w2); nfree(net->x0);
     delete net;
 }
 
@@ -677,6 +871,7 @@ dg_status dg_net_set_params(dg_net* net, const float* params, long long n) {
         NCHK(hipMemset(net->m, 0, sizeof(float) * n));
         NCHK(hipMemset(net->v, 0, sizeof(float) * n));
         net->t = 0;
+        net->wt_dirty = true;
     });
 }
 
@@ -713,7 +908,16 @@ dg_status dg_net_adam(dg_net* net, float lr, float b1, float b2, float eps, hipS
         const float c1 = 1.f - std::pow(b1, (float)net->t), c2 = 1.f - std::pow(b2, (float)net->t);
         hipLaunchKernelGGL(k_adam, dim3(nblocks(net->nparams)), dim3(256), 0, stream, net->p, net->g, net->m, net->v,
                            net->nparams, lr, b1, b2, eps, c1, c2);
+        net->wt_dirty = true;
         NCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_net_set_bf16(dg_net* net, int enable) {
+    return net_guard([&] {
+        if (!net) throw NetError("null net");
+        net->bf16 = enable != 0;
+        net->wt_dirty = true;
     });
 }
 
@@ -757,6 +961,7 @@ dg_status dg_net_load(dg_net* net, const char* path) {
         NCHK(hipMemset(net->m, 0, sizeof(float) * n));
         NCHK(hipMemset(net->v, 0, sizeof(float) * n));
         net->t = 0;
+        net->wt_dirty = true;
     });
 }
 
@@ -768,14 +973,52 @@ dg_status dg_net_load(dg_net* net, const char* path) {
 namespace dg {
 // Provided by dg_api.hip.
 const LevelHost& ctx_fine_level(const dg_ctx* ctx, int mesh_id);
+const LevelHost& ctx_level(const dg_ctx* ctx, int mesh_id, int level);
 }
+
+namespace {
+
+void launch_continuize(const dg::LevelHost& L, int batch, const double* u, double* w, hipStream_t s) {
+    dim3 grid(nblocks(L.ndof), batch);
+#define KC(NN) case NN: hipLaunchKernelGGL((k_continuize<NN>), grid, dim3(256), 0, s, u, w, L.E[0], L.E[1], L.E[2], L.ndof); break;
+    switch (L.n) { KC(2) KC(3) KC(4) KC(5) KC(6) KC(7) KC(8) default: throw NetError("unsupported degree"); }
+#undef KC
+}
+
+// The network's output is a field on multigrid level 1 (nodal, element-major,
+// one channel per node).  Its guess on the finest level is P C y: C makes it
+// continuous, P interpolates it to the finest degree.  y: FP32 [B][ndof1];
+// out: FP64 [B][ndof0].  tmp1, tmp2: FP64 [B][ndof1] work space.
+void output_map(const dg::LevelHost& L0, const dg::LevelHost& L1, int B, const float* y, double* out, double* tmp1,
+                double* tmp2, hipStream_t s) {
+    const long long n1 = L1.ndof * B;
+    hipLaunchKernelGGL(k_f2d, dim3(nblocks(n1)), dim3(256), 0, s, y, tmp1, n1);
+    launch_continuize(L1, B, tmp1, tmp2, s);
+    dg::launch_fill<double>(out, 0.0, L0.ndof * B, s);
+    dg::launch_prolong<double>(L0, L1, B, nullptr, tmp2, out, s);
+}
+
+// Transpose of output_map: gy = C P^T g (C is symmetric).  g: FP64 [B][ndof0].
+void output_map_transpose(const dg::LevelHost& L0, const dg::LevelHost& L1, int B, const double* g, float* gy,
+                          double* tmp1, double* tmp2, hipStream_t s) {
+    dg::launch_restrict<double>(L0, L0.dev64, L1, L1.dev64, B, nullptr, nullptr, g, tmp1, nullptr, 0.0, s);
+    launch_continuize(L1, B, tmp1, tmp2, s);
+    const long long n1 = L1.ndof * B;
+    hipLaunchKernelGGL(k_d2f, dim3(nblocks(n1)), dim3(256), 0, s, tmp2, gy, n1);
+}
+
+}  // namespace
 
 namespace {
 
 void ensure_field(dg_net* net, long long n, int B) {
     if (net->cap_field >= n) return;
+    NCHK(hipDeviceSynchronize());
     nfree(net->e); nfree(net->Ae); nfree(net->tAt); nfree(net->dpart); nfree(net->scale); nfree(net->vtmp);
-    nfree(net->xbuf); nfree(net->ybuf); nfree(net->dybuf);
+    nfree(net->xbuf); nfree(net->ybuf); nfree(net->dybuf); nfree(net->w1); nfree(net->w2); nfree(net->x0);
+    net->w1 = nalloc<double>(n);
+    net->w2 = nalloc<double>(n);
+    net->x0 = nalloc<double>(n);
     net->e = nalloc<double>(n);
     net->Ae = nalloc<double>(n);
     net->vtmp = nalloc<double>(n);
@@ -821,18 +1064,21 @@ dg_status dg_net_prepare_input(dg_net* net, int batch, long long n_dofs, const d
 // One training step on a batch: forward on x, relative A-norm loss against the
 // scaled targets t (FP64, field order), backward, Adam.  Returns the mean loss.
 dg_status dg_net_train_step(dg_net* net, dg_ctx* ctx, int mesh_id, int batch, const float* x, const double* t,
-                            float lr, double* loss, hipStream_t stream) {
+                            float lr, int mode, double* loss, hipStream_t stream) {
     return net_guard([&] {
         if (!net || !ctx || !x || !t || batch < 1) throw NetError("bad arguments");
         const dg::LevelHost& L0 = dg::ctx_fine_level(ctx, mesh_id);
+        const dg::LevelHost& L1 = dg::ctx_level(ctx, mesh_id, 1);
         const int ne[3] = {L0.E[0], L0.E[1], L0.E[2]};
         const long long nd = L0.ndof;
-        if (net->cfg.in_channels != L0.n * L0.n * L0.n || net->cfg.out_channels != L0.n * L0.n * L0.n)
-            throw NetError("network channels must equal the nodes per element");
+        if (net->cfg.in_channels != L0.n * L0.n * L0.n || net->cfg.out_channels != L1.n * L1.n * L1.n ||
+            L1.E[0] != L0.E[0] || L1.E[1] != L0.E[1] || L1.E[2] != L0.E[2])
+            throw NetError("network channels must equal the nodes per element of levels 0 (input) and 1 (output)");
         ensure_field(net, nd * batch, batch);
         const float* y = forward(net, batch, ne, x, stream);
         const long long n = nd * batch;
-        hipLaunchKernelGGL(k_err, dim3(nblocks(n)), dim3(256), 0, stream, y, t, net->e, n);
+        output_map(L0, L1, batch, y, net->x0, net->w1, net->w2, stream);
+        hipLaunchKernelGGL(k_err_d, dim3(nblocks(n)), dim3(256), 0, stream, net->x0, t, net->e, n);
         dg::launch_brick<double>(dg::BM_APPLY, L0, L0.dev64, batch, nullptr, net->e, nullptr, nullptr, nullptr,
                                  net->Ae, nullptr, nullptr, 0, 0, 0, stream);
         dg::launch_brick<double>(dg::BM_APPLY, L0, L0.dev64, batch, nullptr, t, nullptr, nullptr, nullptr, net->vtmp,
@@ -842,33 +1088,58 @@ dg_status dg_net_train_step(dg_net* net, dg_ctx* ctx, int mesh_id, int batch, co
         double L = 0.0;
         for (int b = 0; b < batch; ++b) L += eAe[b] / tAt[b];
         if (loss) *loss = L / batch;
-        // d(mean loss)/dy = 2 A e / (tAt B)
+        // output gradient: mode 0: 2 A e / (tAt B), the A-norm gradient;
+        // mode 1: 2 e / (t.t B), relative nodal L2; mode 2: 2 B_mg A e / (tAt B),
+        // the A-norm gradient preconditioned by one V-cycle (B_mg A e ~ e).
         std::vector<double> scaled(batch);
-        for (int b = 0; b < batch; ++b) scaled[b] = tAt[b] * batch;
+        const double* gsrc = net->Ae;
+        if (mode == 1) {
+            std::vector<double> tt = sample_dots(net, t, t, nd, batch, stream);
+            for (int b = 0; b < batch; ++b) scaled[b] = tt[b] * batch;
+            gsrc = net->e;
+        } else {
+            for (int b = 0; b < batch; ++b) scaled[b] = tAt[b] * batch;
+            if (mode == 2) {
+                if (dg_vcycle_apply(ctx, mesh_id, 0, batch, net->Ae, net->vtmp, stream) != DG_OK)
+                    throw NetError(std::string("V-cycle failed: ") + dg_last_error());
+                gsrc = net->vtmp;
+            }
+        }
         NCHK(hipMemcpyAsync(net->tAt, scaled.data(), sizeof(double) * batch, hipMemcpyHostToDevice, stream));
-        hipLaunchKernelGGL(k_loss_grad, dim3(64, batch), dim3(256), 0, stream, net->Ae, net->tAt, net->dybuf, nd);
+        // gradient with respect to the fine-level guess, then through P^T and C to the network output
+        double* gx = const_cast<double*>(gsrc);  // a work buffer of the network: scaled in place
+        hipLaunchKernelGGL(k_loss_grad_d, dim3(64, batch), dim3(256), 0, stream, gsrc, net->tAt, gx, nd);
+        output_map_transpose(L0, L1, batch, gx, net->dybuf, net->w1, net->w2, stream);
         backward(net, net->dybuf, stream);
         net->t += 1;
         const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
         const float c1 = 1.f - std::pow(b1, (float)net->t), c2 = 1.f - std::pow(b2, (float)net->t);
         hipLaunchKernelGGL(k_adam, dim3(nblocks(net->nparams)), dim3(256), 0, stream, net->p, net->g, net->m, net->v,
                            net->nparams, lr, b1, b2, eps, c1, c2);
+        net->wt_dirty = true;
         NCHK(hipGetLastError());
     });
 }
 
 // Initial guesses v0 = s * net(rho / s) for a batch of fields (FP64 in and out).
-dg_status dg_net_guess(dg_net* net, int batch, const int* ne, long long n_dofs, const double* rho, double* v0,
+dg_status dg_net_guess(dg_net* net, const dg_ctx* ctx, int mesh_id, int batch, const double* rho, double* v0,
                        hipStream_t stream) {
     return net_guard([&] {
-        if (!net || !ne || !rho || !v0 || batch < 1) throw NetError("bad arguments");
+        if (!net || !ctx || !rho || !v0 || batch < 1) throw NetError("bad arguments");
+        const dg::LevelHost& L0 = dg::ctx_fine_level(ctx, mesh_id);
+        const dg::LevelHost& L1 = dg::ctx_level(ctx, mesh_id, 1);
+        if (net->cfg.in_channels != L0.n * L0.n * L0.n || net->cfg.out_channels != L1.n * L1.n * L1.n)
+            throw NetError("network channels do not match the mesh levels 0 and 1");
+        const int ne[3] = {L0.E[0], L0.E[1], L0.E[2]};
+        const long long n_dofs = L0.ndof;
         ensure_field(net, n_dofs * batch, batch);
         const int nb = 64;
         hipLaunchKernelGGL(k_sumsq, dim3(nb, batch), dim3(256), 0, stream, rho, net->dpart, n_dofs);
         hipLaunchKernelGGL(k_scale_of, dim3(batch), dim3(64), 0, stream, net->dpart, nb, n_dofs, net->scale);
         hipLaunchKernelGGL(k_to_input, dim3(nb, batch), dim3(256), 0, stream, rho, net->scale, net->xbuf, n_dofs);
         const float* y = forward(net, batch, ne, net->xbuf, stream);
-        hipLaunchKernelGGL(k_from_output, dim3(nb, batch), dim3(256), 0, stream, y, net->scale, v0, n_dofs);
+        output_map(L0, L1, batch, y, v0, net->w1, net->w2, stream);
+        hipLaunchKernelGGL(k_scale_samples, dim3(nb, batch), dim3(256), 0, stream, v0, net->scale, n_dofs);
         NCHK(hipGetLastError());
     });
 }

@@ -35,8 +35,15 @@ def test_forward_backward_match_oracle(gpu_lib, levels, E):
     assert np.array_equal(net.get_params(), params)
     B = 2
     x = rng.standard_normal((B, E[2], E[1], E[0], cin)).astype(np.float32)
-    y = net.forward(_t(x, np.float32), E, B).cpu().numpy().reshape(B, E[2], E[1], E[0], cin)
     y_ref, cache = convnet.forward(params.astype(np.float64), specs, levels, x.astype(np.float64))
+    # matrix-core path: BF16 operands (8-bit mantissa), FP32 accumulation
+    net.set_bf16(True)
+    yb = net.forward(_t(x, np.float32), E, B).cpu().numpy().reshape(B, E[2], E[1], E[0], cin)
+    assert np.abs(yb - y_ref).max() <= 3e-2 * np.abs(y_ref).max()
+    assert np.abs(yb - y_ref).max() >= 1e-7 * np.abs(y_ref).max()   # it really ran in BF16
+    # FP32 vector path: exact up to FP32 rounding
+    net.set_bf16(False)
+    y = net.forward(_t(x, np.float32), E, B).cpu().numpy().reshape(B, E[2], E[1], E[0], cin)
     assert np.abs(y - y_ref).max() <= 1e-4 * np.abs(y_ref).max()
     dy = rng.standard_normal(y.shape).astype(np.float32)
     g = net.backward(_t(dy, np.float32)).cpu().numpy()
@@ -44,39 +51,60 @@ def test_forward_backward_match_oracle(gpu_lib, levels, E):
     assert np.abs(g - g_ref).max() <= 2e-4 * np.abs(g_ref).max()
 
 
-def test_train_step_matches_oracle(gpu_lib):
+def _continuize_1d(E, n):
+    """1D averaging of the two copies of every node shared by neighbouring elements."""
+    N = E * n
+    Cm = np.eye(N)
+    for e in range(E - 1):
+        a, b = e * n + n - 1, (e + 1) * n
+        Cm[a, a] = Cm[a, b] = Cm[b, a] = Cm[b, b] = 0.5
+    return Cm
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_train_step_matches_oracle(gpu_lib, mode):
     import torch
+    from oracle import mg
     mesh = configs.Mesh((4, 4, 4), 2, (-2.0,) * 3, (2.0,) * 3)
     ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)])
-    levels, C, cin = 2, 8, 27
-    specs = convnet.layer_specs(levels, C, cin, cin)
+    levels, C, cin, cout = 2, 8, 27, 8       # level 1 of a p=2 mesh is p=1: 8 nodes per element
+    specs = convnet.layer_specs(levels, C, cin, cout)
     n = convnet.param_count(specs)
     rng = np.random.default_rng(7)
     params = (0.2 * rng.standard_normal(n)).astype(np.float32)
-    net = gpu_lib.Net(levels, C, cin, cin)
+    net = gpu_lib.Net(levels, C, cin, cout)
+    net.set_bf16(False)
     net.set_params(params)
     B = 2
     nd = ctx.info[0]["n_dofs"]
     x = rng.standard_normal((B, nd)).astype(np.float32)
     t = rng.standard_normal((B, nd))
     lr = 1e-3
-    loss = net.train_step(ctx, _t(x, np.float32), _t(t), B, lr)
-    # oracle: the same loss, gradient and Adam step
-    axes = sipdg.make_axes(mesh.E, mesh.p, mesh.lo, mesh.hi)
+    loss = net.train_step(ctx, _t(x, np.float32), _t(t), B, lr, mode=mode)
+    # oracle: output map (continuous projection, then interpolation to degree 2),
+    # the same loss, gradient and Adam step
+    H = mg.Hierarchy(mesh.E, mesh.p, mesh.lo, mesh.hi)
+    axes = H.levels[0].axes
+    Cx = _continuize_1d(4, 2)
     xs = x.reshape(B, 4, 4, 4, cin).astype(np.float64)
     y, cache = convnet.forward(params.astype(np.float64), specs, levels, xs)
-    y = y.reshape(B, nd)
+    y = y.reshape(B, -1)
     dy = np.zeros_like(y)
     L = 0.0
     for b in range(B):
-        e = layout.to_global(y[b] - t[b], mesh.E, 3)
+        yg = layout.to_global(y[b], mesh.E, 2)
+        yc = np.einsum("Zc,Yb,Xa,cba->ZYX", Cx, Cx, Cx, yg)
+        x0 = H.prolong(0, yc)
+        e = x0 - layout.to_global(t[b], mesh.E, 3)
         Ae = sipdg.apply(axes, e)
         tg = layout.to_global(t[b], mesh.E, 3)
         tAt = float(np.sum(tg * sipdg.apply(axes, tg)))
         L += float(np.sum(e * Ae)) / tAt / B
-        dy[b] = layout.to_element_major(2.0 * Ae / (tAt * B), mesh.E, 3)
+        gx = 2.0 * (Ae if mode == 0 else H.vcycle(Ae)) / (tAt * B)
+        gy = np.einsum("Zc,Yb,Xa,cba->ZYX", Cx, Cx, Cx, H.restrict(0, gx))
+        dy[b] = layout.to_element_major(gy, mesh.E, 2)
     assert abs(loss - L) <= 1e-5 * abs(L)
-    g = convnet.backward(params.astype(np.float64), specs, levels, cache, dy.reshape(B, 4, 4, 4, cin))
+    g = convnet.backward(params.astype(np.float64), specs, levels, cache, dy.reshape(B, 4, 4, 4, cout))
     p1, _, _ = convnet.adam(params.astype(np.float64), g, np.zeros(n), np.zeros(n), 1, lr)
     got = net.get_params()
     moved = np.abs(p1 - params) > 1e-5   # Adam's first step is lr * sign(g) where |g| is not tiny
@@ -90,7 +118,7 @@ def test_guess_path_keeps_converged_answer_and_guard(gpu_lib):
     ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=1e-11)
     rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
     rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
-    net = gpu_lib.Net(3, 8, 125, 125)
+    net = gpu_lib.Net(3, 8, 125, 27)
     rng = np.random.default_rng(3)
     net.set_params((0.05 * rng.standard_normal(net.num_params)).astype(np.float32))
     ctx.attach_guess(net)
@@ -118,18 +146,18 @@ def test_training_reduces_loss_and_save_load_roundtrip(gpu_lib, tmp_path):
     rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
     rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
     v, _ = ctx.solve_batch(rho, g)
-    net = gpu_lib.Net(3, 16, 125, 125)
+    net = gpu_lib.Net(3, 16, 125, 27)
     rng = np.random.default_rng(9)
     net.set_params(_init(net, rng))
     B = 8
     nd = ctx.info[0]["n_dofs"]
     x, s = net.prepare_input(rho, B, nd)
     t = v / s.repeat_interleave(nd)
-    losses = [net.train_step(ctx, x, t, B, 2e-3) for _ in range(60)]
+    losses = [net.train_step(ctx, x, t, B, 2e-3, mode=2) for _ in range(60)]
     assert losses[-1] < 0.5 * losses[0]
     path = tmp_path / "net.bin"
     net.save(path)
-    net2 = gpu_lib.Net(3, 16, 125, 125)
+    net2 = gpu_lib.Net(3, 16, 125, 27)
     net2.load(path)
     assert np.array_equal(net2.get_params(), net.get_params())
 
