@@ -12,7 +12,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdgpoisson.so")
+# DG_POISSON_LIB selects another build of the same library (for example one
+# compiled with different tile parameters); the default is the in-tree build.
+LIB_PATH = os.environ.get("DG_POISSON_LIB", os.path.join(_HERE, "libdgpoisson.so"))
 
 DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
 DG_PREC_FP64, DG_PREC_FP32_IR = 0, 1

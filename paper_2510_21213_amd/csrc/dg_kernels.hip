@@ -262,9 +262,12 @@ __device__ __forceinline__ void halo_reduce(const AxisDev<T>& A, const T* hl, co
 
 // Computes y = A u over the brick from the loaded inputs.  On return, for
 // column threads with a valid column, ycol[Z] holds (A u) along the column.
+// The x and y terms accumulate in one LDS array (sx): the y phase adds to
+// what the x phase wrote, after a barrier; each y row touches only its own
+// entries, so the read-modify-write needs no atomics.
 template <typename T, int N, int BE>
 __device__ __forceinline__ void brick_compute(int E0, int E1, int E2, const LevelDev<T>& L, int ex0, int ey0,
-                                              int ez0, const BrickIn<T, N, BE>& in, T* su, T* sx, T* sy, T* ycol) {
+                                              int ez0, const BrickIn<T, N, BE>& in, T* su, T* sx, T* ycol) {
     constexpr int NB = N * BE, NT = NB * NB, SY = NB + 1, SZ = NB * SY;
     const int t = threadIdx.x;
     const int a0 = t % NB, a1 = t / NB;
@@ -288,6 +291,9 @@ __device__ __forceinline__ void brick_compute(int E0, int E1, int E2, const Leve
                 for (int x = 0; x < NB; ++x) sx[a1 * SZ + a0 * SY + x] = out[x] * sc;
             }
         }
+    }
+    __syncthreads();
+    if (t < NT) {
         {  // y axis: thread (Xr, Zr) = (a0, a1)
             const int ex = ex0 + a0 / N, i = a0 % N, ez = ez0 + a1 / N, k = a1 % N;
             if (ex < E0 && ez < E2) {
@@ -299,7 +305,7 @@ __device__ __forceinline__ void brick_compute(int E0, int E1, int E2, const Leve
                 axis_row<T, N, BE>(L.ax[1], ey0, E1, row, hlu, hld, hru, hrd, out);
                 const T sc = L.ax[0].m[i] * L.ax[2].m[k];
 #pragma unroll
-                for (int y = 0; y < NB; ++y) sy[a1 * SZ + y * SY + a0] = out[y] * sc;
+                for (int y = 0; y < NB; ++y) sx[a1 * SZ + y * SY + a0] += out[y] * sc;
             }
         }
     }
@@ -312,7 +318,7 @@ __device__ __forceinline__ void brick_compute(int E0, int E1, int E2, const Leve
             axis_row<T, N, BE>(L.ax[2], ez0, E2, in.ucol, hlu, hld, hru, hrd, out);
             const T sc = L.ax[0].m[i] * L.ax[1].m[j];
 #pragma unroll
-            for (int Z = 0; Z < NB; ++Z) ycol[Z] = out[Z] * sc + sx[Z * SZ + a1 * SY + a0] + sy[Z * SZ + a1 * SY + a0];
+            for (int Z = 0; Z < NB; ++Z) ycol[Z] = out[Z] * sc + sx[Z * SZ + a1 * SY + a0];
         }
     }
 }
@@ -325,7 +331,6 @@ __global__ __launch_bounds__(wg_of(N* BE* N* BE), 2) void k_brick(BrickArgs<T> a
     constexpr bool IS_CHEB = MODE == BM_CHEB || MODE == BM_CHEBDOT;
     __shared__ T su[NB * SZ];
     __shared__ T sx[NB * SZ];
-    __shared__ T sy[NB * SZ];
     __shared__ double red[WG / 64];
 
     const int nbr = a.nb0 * a.nb1 * a.nb2;
@@ -361,6 +366,10 @@ __global__ __launch_bounds__(wg_of(N* BE* N* BE), 2) void k_brick(BrickArgs<T> a
 
     BrickIn<T, N, BE> in;
     brick_load<T, N, BE, MODE>(E0, E1, E2, ex0, ey0, ez0, u, u2, beta, in);
+    // The column's f and zprev are loaded after the operator: issued before
+    // it they would hold registers through the three axis phases.
+    T ycol[NB];
+    brick_compute<T, N, BE>(E0, E1, E2, L, ex0, ey0, ez0, in, su, sx, ycol);
     T fcol[NB], zpcol[NB];
     if constexpr (HAS_F) {
 #pragma unroll
@@ -375,8 +384,6 @@ __global__ __launch_bounds__(wg_of(N* BE* N* BE), 2) void k_brick(BrickArgs<T> a
             for (int Z = 0; Z < NB; ++Z) zpcol[Z] = (T)0;
         }
     }
-    T ycol[NB];
-    brick_compute<T, N, BE>(E0, E1, E2, L, ex0, ey0, ez0, in, su, sx, sy, ycol);
 
     double dot = 0.0;
     if (colok) {
@@ -505,7 +512,6 @@ __global__ __launch_bounds__(wg_of(NF* BE* NF* BE), 2) void k_restrict(TransferA
     static_assert(!HC || BE % 2 == 0, "mesh coarsening needs an even brick edge");
     __shared__ T su[NB * SZ];
     __shared__ T sx[NB * SZ];
-    __shared__ T sy[NB * SZ];
 
     const int nbr = a.nb0 * a.nb1 * a.nb2;
     const int w = xcd_remap(blockIdx.x, nbr * a.nrhs);
@@ -523,13 +529,15 @@ __global__ __launch_bounds__(wg_of(NF* BE* NF* BE), 2) void k_restrict(TransferA
 
     T rcol[NB], fcol[NB];
     BrickIn<T, NF, BE> in;
-    if constexpr (HASZ) brick_load<T, NF, BE, BM_APPLY>(E0, E1, E2, ex0, ey0, ez0, a.z + base, nullptr, (T)0, in);
+    if constexpr (HASZ) {
+        brick_load<T, NF, BE, BM_APPLY>(E0, E1, E2, ex0, ey0, ez0, a.z + base, nullptr, (T)0, in);
+        brick_compute<T, NF, BE>(E0, E1, E2, *a.Lf, ex0, ey0, ez0, in, su, sx, rcol);
+    }
 #pragma unroll
     for (int Z = 0; Z < NB; ++Z) {
         const int ez = ez0 + Z / NF, k = Z % NF;
         fcol[Z] = (colok && ez < E2) ? ld32(f, (uint32_t)((ez * E1 + eyY) * E0 + exX) * N3 + (k * NF + jY) * NF + iX) : (T)0;
     }
-    if constexpr (HASZ) brick_compute<T, NF, BE>(E0, E1, E2, *a.Lf, ex0, ey0, ez0, in, su, sx, sy, rcol);
 #pragma unroll
     for (int Z = 0; Z < NB; ++Z) {
         const int ez = ez0 + Z / NF;
