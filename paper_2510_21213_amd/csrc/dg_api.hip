@@ -296,7 +296,7 @@ template <typename T>
 void pcg_iteration(Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, int parity, hipStream_t s) {
     const LevelHost& L0 = M.lv[0];
     const auto* dv = ldev<T>(L0);
-    const int nb = dg::bricks_of(L0), nc = dg::chunks_of(L0.ndof);
+    const int nb = dg::op_blocks<T>(L0), nc = dg::chunks_of(L0.ndof);
     T* z = vcycle<T>(M, W, 0, nrhs, st, W.r, true, true, s);
     dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nb, s);
     T* pold = parity ? W.p1 : W.p0;
@@ -454,7 +454,7 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
                  hipStream_t s, const std::vector<int>* guess_used = nullptr) {
     const LevelHost& L0 = M.lv[0];
     const long long n0 = L0.ndof;
-    const int nc = dg::chunks_of(n0), nb = dg::bricks_of(L0);
+    const int nc = dg::chunks_of(n0), nb = dg::op_blocks<double>(L0);
     const auto& o = ctx->opts;
     ensure_state(M, nrhs);
     std::vector<int> iters(nrhs, 0), outer(nrhs, 0);
@@ -569,7 +569,7 @@ std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho
     if (dg_net_guess(ctx->guess, ctx, mesh_id, nrhs, rho, ctx->g_x0, s) != DG_OK)
         throw ArgError(std::string("learned guess failed: ") + dg_net_last_error());
     ensure_state(M, nrhs);
-    const int nc = dg::chunks_of(n0), nb = dg::bricks_of(L0);
+    const int nc = dg::chunks_of(n0), nb = dg::op_blocks<double>(L0);
     init_state(M, M.st, nrhs, 1.0, 1, s);
     dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
     dg::launch_finalize(dg::FIN_BB, nrhs, M.st, M.partial, M.pstride, nc, s);
@@ -633,6 +633,20 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
             f.sigma = (float)a.sigma;
             f.E = a.E;
         }
+        dg::build_ref(p, o.penalty_eps, L.h, L.d64.ref);
+        {
+            const auto& r = L.d64.ref;
+            auto& f = L.d32.ref;
+            std::memset(&f, 0, sizeof(f));
+            for (int i = 0; i < dg::NMAX; ++i) {
+                for (int j = 0; j < dg::NMAX; ++j) f.B[i][j] = (float)r.B[i][j];
+                f.aL[i] = (float)r.aL[i];
+                f.aR[i] = (float)r.aR[i];
+                f.w[i] = (float)r.w[i];
+            }
+            f.sig = (float)r.sig;
+            for (int d = 0; d < 3; ++d) f.scale[d] = (float)r.scale[d];
+        }
         M.lv.push_back(L);
     }
     const int nl = (int)M.lv.size();
@@ -656,7 +670,8 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
     M.dcoarse = dalloc<dg::CoarseDev>(1);
     HIPCHK(hipMemcpy(M.dcoarse, &M.coarse, sizeof(M.coarse), hipMemcpyHostToDevice));
     int ps = dg::chunks_of(M.lv[0].ndof);
-    for (auto& L : M.lv) ps = std::max(ps, dg::bricks_of(L));
+    for (auto& L : M.lv)
+        ps = std::max({ps, dg::bricks_of(L), dg::op_blocks<float>(L), dg::op_blocks<double>(L)});
     M.pstride = ps;
     const int NX = mesh.ne[0] * (mesh.p + 1), NY = mesh.ne[1] * (mesh.p + 1), NZ = mesh.ne[2] * (mesh.p + 1);
     M.nface = 2LL * ((long long)NY * NZ + (long long)NX * NZ + (long long)NX * NY);

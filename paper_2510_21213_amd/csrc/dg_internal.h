@@ -34,9 +34,25 @@ struct AxisDev {
     int pad;
 };
 
+// Reference-element form of a level's interior 1D block, shared by the three
+// axes.  On an axis of element half-width J the interior block is B/J, the
+// face-derivative rows aL/J and aR/J, the penalty sig/J and the lumped mass
+// J w; so the x term of the operator is (J_y J_z / J_x) B (x) w (x) w, and
+// scale[d] holds that factor for axis d.  Elements on a domain face use the
+// same block: the Nitsche terms follow from ghost face data (see elem_op).
+template <typename T>
+struct RefDev {
+    T B[NMAX][NMAX];
+    T aL[NMAX], aR[NMAX];
+    T w[NMAX];
+    T sig;
+    T scale[3];
+};
+
 template <typename T>
 struct LevelDev {
     AxisDev<T> ax[3];
+    RefDev<T> ref;
 };
 
 // Brick-level 1D transfer between a level and the next coarser one:
@@ -98,6 +114,7 @@ void lagrange_eval(const std::vector<double>& nodes, const std::vector<double>& 
 void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V);
 void build_axis(int E, int p, double lo, double hi, double eps, AxisDev<double>& ax, std::vector<double>* dense,
                 std::vector<double>* nodes);
+void build_ref(int p, double eps, const double h[3], RefDev<double>& r);
 int brick_edge(int n);
 std::vector<std::pair<std::array<int, 3>, int>> hierarchy(const int E[3], int p, int n_levels);
 void build_transfer(const LevelHost& fine, const LevelHost& coarse, TransferDev& tr);

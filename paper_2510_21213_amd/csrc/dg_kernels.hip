@@ -25,6 +25,7 @@
 // fixed slot and a second kernel adds the slots in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -423,6 +424,427 @@ __global__ __launch_bounds__(wg_of(N* BE* N* BE), 2) void k_brick(BrickArgs<T> a
     }
 }
 
+// ---------------------------------------------------------------------------
+// Slab operator kernel (levels of degree 1, 2 and 4).
+//
+// A work-group owns a TX x TY tile of elements in the x-y plane of one
+// right-hand side and marches along z through a chunk of element layers.  Per
+// layer, the tile and the ring of x and y neighbour elements around it (the
+// face halo) are staged in LDS.  Every thread keeps one node column of the
+// layer in registers and computes its z term, with the previous and next
+// layers as neighbours (already in registers, so no z halo is read).  Half of
+// the threads compute the x terms of pairs of elements along x rows and the
+// other half the y terms of pairs along y rows, at the same time, into two LDS
+// arrays; each thread then adds the three terms of its column.  The loads of
+// the next layers are issued before the current layer is computed.  Every
+// element uses the interior block in reference units (RefDev); on a domain
+// face the Nitsche terms follow from ghost face data (elem_op).
+
+template <typename T>
+struct SlabArgs {
+    const LevelDev<T>* L;
+    int E0, E1, E2;
+    int nt0, nt1;   // tiles along x and y
+    int zlen, nzc;  // element layers per chunk, chunks along z
+    int nrhs;
+    long long ndof;
+    const RhsState* st;
+    const T* u;
+    const T* u2;
+    const T* f;
+    const T* zprev;
+    T* out;
+    T* out2;
+    double* partial;
+    int pstride;
+    T cp, cr;
+};
+
+template <typename T, int N>
+struct SlabCoef {
+    T B[N][N];
+    T aL[N], aR[N];
+    T sig;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ T face_l(const SlabCoef<T, N>& c, const T* v) {
+    T s = 0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) s += c.aL[l] * v[l];
+    return s;
+}
+template <typename T, int N>
+__device__ __forceinline__ T face_r(const SlabCoef<T, N>& c, const T* v) {
+    T s = 0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) s += c.aR[l] * v[l];
+    return s;
+}
+
+// One element along one axis, reference units: acc = B A plus the coupling to
+// the left neighbour (U its value at its right end, Dv = aR . its line) and to
+// the right neighbour (U0 its value at its left end, D0 = aL . its line):
+//   acc_i += (aR_i U0 - aL_i U) / 2,  acc_0 += Dv/2 - sig U,  acc_p -= D0/2 + sig U0.
+// With the ghost data U = -A_0, Dv = aL.A - 2 sig A_0 on a left domain face and
+// U0 = -A_p, D0 = aR.A + 2 sig A_p on a right one, the same formula gives the
+// block of a boundary element (its Nitsche face terms).
+template <typename T, int N>
+__device__ __forceinline__ void elem_op(const SlabCoef<T, N>& c, const T* A, T U, T Dv, T U0, T D0, T* acc) {
+    const T hU = (T)0.5 * U, hU0 = (T)0.5 * U0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        T s = c.aR[i] * hU0 - c.aL[i] * hU;
+#pragma unroll
+        for (int l = 0; l < N; ++l) s += c.B[i][l] * A[l];
+        acc[i] = s;
+    }
+    acc[0] += (T)0.5 * Dv - c.sig * U;
+    acc[N - 1] -= (T)0.5 * D0 + c.sig * U0;
+}
+
+// x or y term of the element pair (e, e+1) of a row staged in LDS at su[pb +
+// s PSTR]: s in [0, N) the left neighbour line, [N, 3N) the pair, [3N, 4N) the
+// right neighbour line.  nE elements along the axis; neighbours that do not
+// exist are replaced by ghost data and their lines are not used.  The
+// results, times sc, go to so[ob + s OSTR], s in [0, 2N) (the second element
+// only if it exists).
+template <typename T, int N, int PSTR, int OSTR>
+__device__ __forceinline__ void pair_row(const SlabCoef<T, N>& c, const T* su, int pb, T* so, int ob, int e, int nE,
+                                         T sc) {
+    T A[N], B[N], out[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+        A[l] = su[pb + (N + l) * PSTR];
+        B[l] = su[pb + (2 * N + l) * PSTR];
+    }
+    const bool has2 = e + 1 < nE;
+    const T fRA = face_r(c, A);
+    T U, Dv, U0, D0;
+    if (e > 0) {
+        T nl[N];
+#pragma unroll
+        for (int l = 0; l < N; ++l) nl[l] = su[pb + l * PSTR];
+        U = nl[N - 1];
+        Dv = face_r(c, nl);
+    } else {
+        U = -A[0];
+        Dv = face_l(c, A) - (T)2 * c.sig * A[0];
+    }
+    if (has2) {
+        U0 = B[0];
+        D0 = face_l(c, B);
+    } else {
+        U0 = -A[N - 1];
+        D0 = fRA + (T)2 * c.sig * A[N - 1];
+    }
+    elem_op(c, A, U, Dv, U0, D0, out);
+#pragma unroll
+    for (int i = 0; i < N; ++i) so[ob + i * OSTR] = out[i] * sc;
+    if (has2) {
+        if (e + 2 < nE) {
+            T nr[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) nr[l] = su[pb + (3 * N + l) * PSTR];
+            U0 = nr[0];
+            D0 = face_l(c, nr);
+        } else {
+            U0 = -B[N - 1];
+            D0 = face_r(c, B) + (T)2 * c.sig * B[N - 1];
+        }
+        elem_op(c, B, A[N - 1], fRA, U0, D0, out);
+#pragma unroll
+        for (int i = 0; i < N; ++i) so[ob + (N + i) * OSTR] = out[i] * sc;
+    }
+}
+
+typedef __amdgpu_buffer_rsrc_t brsrc;
+
+// Raw buffer access (byte offsets; voff per lane, soff uniform).  Loads outside
+// the buffer's size return 0 and such stores are dropped, so an indexing slip
+// cannot reach other memory.
+template <typename T>
+__device__ __forceinline__ brsrc rsrc_of(const T* p, long long n) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n * (long long)sizeof(T)), 0x00020000);
+}
+__device__ __forceinline__ void bload(float& v, brsrc r, uint32_t voff, uint32_t soff) {
+    v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bload(double& v, brsrc r, uint32_t voff, uint32_t soff) {
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, brsrc r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, brsrc r, uint32_t voff, uint32_t soff) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+// The N values of a node column of one element layer (stride N^2 values).
+template <typename T, int N, int MODE>
+__device__ __forceinline__ void load_col(T* v, brsrc ru, brsrc ru2, uint32_t voff, uint32_t soff, T beta) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) bload(v[k], ru, voff + k * N * N * (uint32_t)sizeof(T), soff);
+    if constexpr (MODE == BM_PQ) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            T w;
+            bload(w, ru2, voff + k * N * N * (uint32_t)sizeof(T), soff);
+            v[k] += beta * w;
+        }
+    }
+}
+
+template <typename T, int N, int TX, int TY, int MODE>
+__global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
+    constexpr int NX = TX * N, NY = TY * N, NT = NX * NY, N2 = N * N, N3 = N2 * N;
+    constexpr int WG = wg_of(NT);
+    constexpr int RS = NX + 2 * N, PS = RS * (NY + 2 * N);  // LDS staging: row and plane strides
+    constexpr int NP = NT / 2;                               // element pairs per axis and layer
+    constexpr int NH = 2 * (TX + TY);                        // halo elements per layer
+    constexpr int HS = (NH + TX * TY - 1) / (TX * TY);       // halo columns per thread
+    constexpr uint32_t SZ = sizeof(T);
+    static_assert(TX % 2 == 0 && TY % 2 == 0, "tiles hold whole element pairs");
+    constexpr bool HAS_F = MODE == BM_RESID || MODE == BM_RESIDDOT || MODE == BM_CHEB || MODE == BM_CHEBDOT;
+    constexpr bool IS_CHEB = MODE == BM_CHEB || MODE == BM_CHEBDOT;
+    constexpr bool DOT = MODE == BM_CHEBDOT || MODE == BM_PQ || MODE == BM_RESIDDOT;
+    __shared__ T su[N * PS];
+    __shared__ T sxy[2 * N * NT];
+    __shared__ double red[WG / 64];
+
+    const int per_rhs = a.nt0 * a.nt1 * a.nzc;
+    const int w = xcd_remap(blockIdx.x, per_rhs * a.nrhs);
+    const int rhs = w / per_rhs, slot = w % per_rhs;
+    if (a.st && !a.st[rhs].active) return;
+    const int chunk = slot / (a.nt0 * a.nt1), tile = slot % (a.nt0 * a.nt1);
+    const int tx0 = (tile % a.nt0) * TX, ty0 = (tile / a.nt0) * TY;
+    const int E0 = a.E0, E1 = a.E1, E2 = a.E2;
+    const int ezb = chunk * a.zlen, eze = min(E2, ezb + a.zlen);
+    const uint32_t lstride = (uint32_t)(E0 * E1 * N3) * SZ;  // bytes per element layer
+
+    const long long base = (long long)rhs * a.ndof;
+    const brsrc ru = rsrc_of(a.u + base, a.ndof);
+    const brsrc ru2 = rsrc_of(MODE == BM_PQ ? a.u2 + base : a.u + base, a.ndof);
+    const brsrc rf = rsrc_of(HAS_F ? a.f + base : a.u + base, a.ndof);
+    const brsrc rzp = rsrc_of(IS_CHEB && a.zprev ? a.zprev + base : a.u + base, a.ndof);
+    const brsrc ro = rsrc_of(a.out + base, a.ndof);
+    const brsrc ro2 = rsrc_of(MODE == BM_PQ ? a.out2 + base : a.out + base, a.ndof);
+    T beta = 0;
+    if constexpr (MODE == BM_PQ) beta = (T)a.st[rhs].beta;
+    const bool has_zp = IS_CHEB && a.zprev;
+
+    const RefDev<T>& R = a.L->ref;
+    SlabCoef<T, N> c;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int l = 0; l < N; ++l) c.B[i][l] = R.B[i][l];
+        c.aL[i] = R.aL[i];
+        c.aR[i] = R.aR[i];
+    }
+    c.sig = R.sig;
+
+    const int t = threadIdx.x;
+    const bool tact = t < NT;
+    // column role: thread -> (element el of the tile, node (i, j) of its face)
+    const int tc = min(t, NT - 1);
+    const int el = tc / N2, i = tc % N, j = (tc / N) % N;
+    const int exl = el % TX, eyl = el / TX;
+    const int X = exl * N + i, Y = eyl * N + j;
+    const int ex = tx0 + exl, ey = ty0 + eyl;
+    const bool colok = tact && ex < E0 && ey < E1;
+    const uint32_t coff = ((uint32_t)((min(ey, E1 - 1) * E0 + min(ex, E0 - 1)) * N3 + j * N + i)) * SZ;
+    const int su_own = (Y + N) * RS + X + N;
+    const int so_own = Y * NX + X;
+    const T wi = R.w[i], wj = R.w[j];
+    const T P2 = R.scale[2] * wi * wj;  // z-term scale, and the z part of the diagonal per reference entry
+    T P1 = 0;                           // x and y parts of the diagonal (times w_k)
+    if constexpr (IS_CHEB) {
+        T bdx = R.B[i][i], bdy = R.B[j][j];
+        if (ex == 0 && i == 0) bdx += R.aL[0];
+        if (ex == E0 - 1 && i == N - 1) bdx -= R.aR[N - 1];
+        if (ey == 0 && j == 0) bdy += R.aL[0];
+        if (ey == E1 - 1 && j == N - 1) bdy -= R.aR[N - 1];
+        P1 = R.scale[0] * bdx * wj + R.scale[1] * wi * bdy;
+    }
+    // halo role: the same node (i, j) of halo element he = el + s TX TY
+    uint32_t hoff[HS];
+    int hsu[HS];
+    bool hok[HS];
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+        const int he = el + s * TX * TY;
+        hok[s] = tact && he < NH;
+        const int hq = min(he, NH - 1);
+        int hx, hy, Xe, Ye;
+        if (hq < 2 * TY) {  // x sides
+            const int q = hq % TY, side = hq / TY;
+            hx = side ? tx0 + TX : tx0 - 1;
+            hy = ty0 + q;
+            Xe = side ? NX + N + i : i;
+            Ye = q * N + j + N;
+        } else {  // y sides
+            const int q = (hq - 2 * TY) % TX, side = (hq - 2 * TY) / TX;
+            hx = tx0 + q;
+            hy = side ? ty0 + TY : ty0 - 1;
+            Xe = q * N + i + N;
+            Ye = side ? NY + N + j : j;
+        }
+        hx = max(0, min(hx, E0 - 1));
+        hy = max(0, min(hy, E1 - 1));
+        hoff[s] = ((uint32_t)((hy * E0 + hx) * N3 + j * N + i)) * SZ;
+        hsu[s] = Ye * RS + Xe;
+    }
+    // pair role: x pairs for t < NP, y pairs for NP <= t < NT
+    const bool isx = t < NP;
+    int pb, ob, pe;
+    bool pok;
+    T psc;
+    if (isx) {
+        const int pa = t % (TX / 2), row = t / (TX / 2), Yr = row % NY, kr = row / NY;
+        pe = tx0 + 2 * pa;
+        pok = pe < E0 && ty0 + Yr / N < E1;
+        pb = kr * PS + (Yr + N) * RS + 2 * pa * N;
+        ob = kr * NT + Yr * NX + 2 * pa * N;
+        psc = R.scale[0] * R.w[Yr % N] * R.w[kr];
+    } else {
+        const int q = min(t, NT - 1) - NP, pa = q % (TY / 2), col = q / (TY / 2), Xc = col % NX, kr = col / NX;
+        pe = ty0 + 2 * pa;
+        pok = tact && pe < E1 && tx0 + Xc / N < E0;
+        pb = kr * PS + 2 * pa * N * RS + Xc + N;
+        ob = N * NT + kr * NT + 2 * pa * N * NX + Xc;
+        psc = R.scale[1] * R.w[Xc % N] * R.w[kr];
+    }
+
+    // prologue: face data of the layer below the chunk, this layer's column and halo, the next column
+    T cur[N], nxt[N], nx2[N], hal[HS][N];
+    T prevU = 0, prevD = 0;
+    if (ezb > 0) {
+        load_col<T, N, MODE>(nx2, ru, ru2, coff, (uint32_t)(ezb - 1) * lstride, beta);
+        prevU = nx2[N - 1];
+        prevD = face_r(c, nx2);
+    }
+    load_col<T, N, MODE>(cur, ru, ru2, coff, (uint32_t)ezb * lstride, beta);
+#pragma unroll
+    for (int s = 0; s < HS; ++s) load_col<T, N, MODE>(hal[s], ru, ru2, hoff[s], (uint32_t)ezb * lstride, beta);
+    if (ezb + 1 < E2) load_col<T, N, MODE>(nxt, ru, ru2, coff, (uint32_t)(ezb + 1) * lstride, beta);
+    T crD[N];  // cr / D for the nodes of an interior layer
+    if constexpr (IS_CHEB) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) crD[k] = a.cr * recip(P1 * R.w[k] + P2 * R.B[k][k]);
+    }
+
+    double dot = 0.0;
+    for (int ez = ezb; ez < eze; ++ez) {
+        const uint32_t soff = (uint32_t)ez * lstride;
+        // stage this layer
+        if (tact) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) su[k * PS + su_own] = cur[k];
+        }
+#pragma unroll
+        for (int s = 0; s < HS; ++s) {
+            if (hok[s]) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) su[k * PS + hsu[s]] = hal[s][k];
+            }
+        }
+        // loads for later layers and for this layer's epilogue
+        if (ez + 1 < eze) {
+#pragma unroll
+            for (int s = 0; s < HS; ++s) load_col<T, N, MODE>(hal[s], ru, ru2, hoff[s], soff + lstride, beta);
+        }
+        if (ez + 1 < eze && ez + 2 < E2) load_col<T, N, MODE>(nx2, ru, ru2, coff, soff + 2 * lstride, beta);
+        T fcol[N], zpcol[N];
+        if constexpr (HAS_F) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) bload(fcol[k], rf, coff + k * N2 * SZ, soff);
+        }
+        if constexpr (IS_CHEB) {
+            if (has_zp) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) bload(zpcol[k], rzp, coff + k * N2 * SZ, soff);
+            } else {
+#pragma unroll
+                for (int k = 0; k < N; ++k) zpcol[k] = 0;
+            }
+        }
+        __syncthreads();
+        // x and y terms of element pairs
+        if (pok) {
+            if (isx)
+                pair_row<T, N, 1, 1>(c, su, pb, sxy, ob, pe, E0, psc);
+            else
+                pair_row<T, N, RS, NX>(c, su, pb, sxy, ob, pe, E1, psc);
+        }
+        // z term of the column
+        T zacc[N];
+        {
+            T U, Dv, U0, D0;
+            if (ez > 0) {
+                U = prevU;
+                Dv = prevD;
+            } else {
+                U = -cur[0];
+                Dv = face_l(c, cur) - (T)2 * c.sig * cur[0];
+            }
+            const T fRc = face_r(c, cur);
+            if (ez + 1 < E2) {
+                U0 = nxt[0];
+                D0 = face_l(c, nxt);
+            } else {
+                U0 = -cur[N - 1];
+                D0 = fRc + (T)2 * c.sig * cur[N - 1];
+            }
+            elem_op(c, cur, U, Dv, U0, D0, zacc);
+            prevU = cur[N - 1];
+            prevD = fRc;
+        }
+        __syncthreads();
+        if (colok) {
+            const bool zb = ez == 0 || ez == E2 - 1;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const T y = zacc[k] * P2 + sxy[k * NT + so_own] + sxy[N * NT + k * NT + so_own];
+                const uint32_t vo = coff + k * N2 * SZ;
+                if constexpr (MODE == BM_APPLY) {
+                    bstore(y, ro, vo, soff);
+                } else if constexpr (MODE == BM_RESID || MODE == BM_RESIDDOT) {
+                    const T r = fcol[k] - y;
+                    bstore(r, ro, vo, soff);
+                    if constexpr (MODE == BM_RESIDDOT) dot += (double)r * (double)r;
+                } else if constexpr (IS_CHEB) {
+                    T cd = crD[k];
+                    if (zb) {
+                        T bdz = R.B[k][k];
+                        if (ez == 0 && k == 0) bdz += R.aL[0];
+                        if (ez == E2 - 1 && k == N - 1) bdz -= R.aR[N - 1];
+                        cd = a.cr * recip(P1 * R.w[k] + P2 * bdz);
+                    }
+                    const T uz = cur[k];
+                    const T zn = uz + a.cp * (uz - zpcol[k]) + cd * (fcol[k] - y);
+                    bstore(zn, ro, vo, soff);
+                    if constexpr (MODE == BM_CHEBDOT) dot += (double)fcol[k] * (double)zn;
+                } else if constexpr (MODE == BM_PQ) {
+                    bstore(cur[k], ro2, vo, soff);
+                    bstore(y, ro, vo, soff);
+                    dot += (double)cur[k] * (double)y;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            cur[k] = nxt[k];
+            nxt[k] = nx2[k];
+        }
+    }
+    if constexpr (DOT) {
+        const double s = block_sum<WG>(dot, red);
+        if (t == 0) a.partial[(long long)rhs * a.pstride + slot] = s;
+    }
+}
+
 template <typename T, int N, int BE>
 static void brick_dispatch(int mode, const BrickArgs<T>& a, int grid, hipStream_t s) {
     constexpr int WG = wg_of(N * BE * N * BE);
@@ -436,10 +858,90 @@ static void brick_dispatch(int mode, const BrickArgs<T>& a, int grid, hipStream_
     }
 }
 
+// Tile of the slab kernel for (precision, nodes per edge): TX x TY elements,
+// or {0, 0} where the brick kernel is used.  Layers per z chunk: enough
+// chunks for a few thousand work-groups at typical batch sizes.
+template <typename T>
+static void slab_shape(int n, int& tx, int& ty, int& zlen) {
+    tx = ty = 0;
+    zlen = 4;
+    switch (n) {
+        case 2: tx = ty = 8; zlen = 2; break;
+        case 3: tx = ty = 8; zlen = 2; break;
+        case 5: tx = ty = 4; zlen = 4; break;
+        default: break;
+    }
+}
+
+struct SlabGeom {
+    int tx, ty, nt0, nt1, zlen, nzc;
+};
+
+template <typename T>
+static SlabGeom slab_geom(const LevelHost& L) {
+    SlabGeom g;
+    slab_shape<T>(L.n, g.tx, g.ty, g.zlen);
+    if (!g.tx) return g;
+    g.nt0 = (L.E[0] + g.tx - 1) / g.tx;
+    g.nt1 = (L.E[1] + g.ty - 1) / g.ty;
+    g.zlen = std::min(g.zlen, L.E[2]);
+    g.nzc = (L.E[2] + g.zlen - 1) / g.zlen;
+    return g;
+}
+
+template <typename T>
+int op_blocks(const LevelHost& L) {
+    const SlabGeom g = slab_geom<T>(L);
+    return g.tx ? g.nt0 * g.nt1 * g.nzc : bricks_of(L);
+}
+template int op_blocks<float>(const LevelHost&);
+template int op_blocks<double>(const LevelHost&);
+
+template <typename T, int N, int TX, int TY>
+static void slab_dispatch(int mode, const SlabArgs<T>& a, int grid, hipStream_t s) {
+    constexpr int WG = wg_of(TX * TY * N * N);
+    switch (mode) {
+        case BM_APPLY: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_APPLY>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_RESID: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESID>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_CHEB: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_CHEB>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_CHEBDOT: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_CHEBDOT>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_PQ: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_PQ>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_RESIDDOT: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESIDDOT>), dim3(grid), dim3(WG), 0, s, a); break;
+    }
+}
+
+template <typename T>
+static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st,
+                        const T* u, const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial,
+                        int pstride, double cp, double cr, hipStream_t s) {
+    const SlabGeom g = slab_geom<T>(L);
+    if (!g.tx) return false;
+    SlabArgs<T> a;
+    a.L = dev;
+    a.E0 = L.E[0]; a.E1 = L.E[1]; a.E2 = L.E[2];
+    a.nt0 = g.nt0; a.nt1 = g.nt1; a.zlen = g.zlen; a.nzc = g.nzc;
+    a.nrhs = nrhs;
+    a.ndof = L.ndof;
+    a.st = st;
+    a.u = u; a.u2 = u2; a.f = f; a.zprev = zprev; a.out = out; a.out2 = out2;
+    a.partial = partial;
+    a.pstride = pstride;
+    a.cp = (T)cp;
+    a.cr = (T)cr;
+    const int grid = g.nt0 * g.nt1 * g.nzc * nrhs;
+    if (grid == 0) return true;
+    if (g.tx == 8 && g.ty == 8 && L.n == 2) slab_dispatch<T, 2, 8, 8>(mode, a, grid, s);
+    else if (g.tx == 8 && g.ty == 8 && L.n == 3) slab_dispatch<T, 3, 8, 8>(mode, a, grid, s);
+    else if (g.tx == 4 && g.ty == 4 && L.n == 5) slab_dispatch<T, 5, 4, 4>(mode, a, grid, s);
+    else return false;
+    return true;
+}
+
 template <typename T>
 void launch_brick(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, const T* u,
                   const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial, int pstride, double cp,
                   double cr, hipStream_t s) {
+    if (launch_slab<T>(mode, L, dev, nrhs, st, u, u2, f, zprev, out, out2, partial, pstride, cp, cr, s)) return;
     BrickArgs<T> a;
     a.L = dev;
     a.E0 = L.E[0]; a.E1 = L.E[1]; a.E2 = L.E[2];

@@ -205,6 +205,36 @@ void build_axis(int E, int p, double lo, double hi, double eps, AxisDev<double>&
     }
 }
 
+// Interior block in reference units (J = 1): stiffness D^T diag(w) D plus the
+// own-element halves of both interior faces; the penalty sigma J =
+// (p+1)^2 / (2 eps) follows from sigma = (p+1)^2 / (eps h) with h = 2J.
+void build_ref(int p, double eps, const double h[3], RefDev<double>& r) {
+    const int n = p + 1;
+    std::vector<double> xi, w, D;
+    gll(p, xi, w, D);
+    std::memset(&r, 0, sizeof(r));
+    const double sig = (p + 1.0) * (p + 1.0) / (2.0 * eps);
+    r.sig = sig;
+    for (int l = 0; l < n; ++l) {
+        r.aL[l] = D[0 * n + l];
+        r.aR[l] = D[p * n + l];
+        r.w[l] = w[l];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double v = 0.0;
+            for (int q = 0; q < n; ++q) v += D[q * n + i] * w[q] * D[q * n + j];
+            const double eLi = (i == 0), eLj = (j == 0), eRi = (i == p), eRj = (j == p);
+            v += 0.5 * (eLi * r.aL[j] + r.aL[i] * eLj) + sig * eLi * eLj;
+            v += -0.5 * (eRi * r.aR[j] + r.aR[i] * eRj) + sig * eRi * eRj;
+            r.B[i][j] = v;
+        }
+    const double J[3] = {0.5 * h[0], 0.5 * h[1], 0.5 * h[2]};
+    r.scale[0] = J[1] * J[2] / J[0];
+    r.scale[1] = J[0] * J[2] / J[1];
+    r.scale[2] = J[0] * J[1] / J[2];
+}
+
 int brick_edge(int n) { return n <= 3 ? 4 : (n <= 6 ? 2 : 1); }
 
 // Levels from fine to coarse: degree p -> p/2 -> ... -> 1, then halve the
