@@ -460,12 +460,39 @@ struct SlabArgs {
     T cp, cr;
 };
 
+// The interior block is symmetric and invariant under the reflection
+// (i, l) -> (p - l, p - i) of the reference element, and aR_l = -aL_{p-l}:
+// the kernel keeps only the distinct entries (15 scalars for p = 4 instead
+// of 36), so they stay in scalar registers for the whole work-group.
+constexpr int canon_row(int N, int i, int l) {
+    const int a = i < l ? i : l, b = i < l ? l : i;  // symmetric
+    const int ra = N - 1 - b, rb = N - 1 - a;         // reflected
+    return (ra < a || (ra == a && rb < b)) ? ra : a;
+}
+constexpr int canon_col(int N, int i, int l) {
+    const int a = i < l ? i : l, b = i < l ? l : i;
+    const int ra = N - 1 - b, rb = N - 1 - a;
+    return (ra < a || (ra == a && rb < b)) ? rb : b;
+}
+
 template <typename T, int N>
 struct SlabCoef {
-    T B[N][N];
-    T aL[N], aR[N];
+    T B[N][N];  // filled from the canonical entries only
+    T aL[N];
     T sig;
+    __device__ __forceinline__ T aR(int l) const { return -aL[N - 1 - l]; }
 };
+
+template <typename T, int N>
+__device__ __forceinline__ void load_coef(SlabCoef<T, N>& c, const RefDev<T>& R) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int l = 0; l < N; ++l) c.B[i][l] = R.B[canon_row(N, i, l)][canon_col(N, i, l)];
+        c.aL[i] = R.aL[i];
+    }
+    c.sig = R.sig;
+}
 
 template <typename T, int N>
 __device__ __forceinline__ T face_l(const SlabCoef<T, N>& c, const T* v) {
@@ -478,7 +505,7 @@ template <typename T, int N>
 __device__ __forceinline__ T face_r(const SlabCoef<T, N>& c, const T* v) {
     T s = 0;
 #pragma unroll
-    for (int l = 0; l < N; ++l) s += c.aR[l] * v[l];
+    for (int l = 0; l < N; ++l) s -= c.aL[N - 1 - l] * v[l];
     return s;
 }
 
@@ -494,7 +521,7 @@ __device__ __forceinline__ void elem_op(const SlabCoef<T, N>& c, const T* A, T U
     const T hU = (T)0.5 * U, hU0 = (T)0.5 * U0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        T s = c.aR[i] * hU0 - c.aL[i] * hU;
+        T s = c.aR(i) * hU0 - c.aL[i] * hU;
 #pragma unroll
         for (int l = 0; l < N; ++l) s += c.B[i][l] * A[l];
         acc[i] = s;
@@ -585,12 +612,12 @@ __device__ __forceinline__ void bstore(double v, brsrc r, uint32_t voff, uint32_
 template <typename T, int N, int MODE>
 __device__ __forceinline__ void load_col(T* v, brsrc ru, brsrc ru2, uint32_t voff, uint32_t soff, T beta) {
 #pragma unroll
-    for (int k = 0; k < N; ++k) bload(v[k], ru, voff + k * N * N * (uint32_t)sizeof(T), soff);
+    for (int k = 0; k < N; ++k) bload(v[k], ru, voff, soff + k * N * N * (uint32_t)sizeof(T));
     if constexpr (MODE == BM_PQ) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             T w;
-            bload(w, ru2, voff + k * N * N * (uint32_t)sizeof(T), soff);
+            bload(w, ru2, voff, soff + k * N * N * (uint32_t)sizeof(T));
             v[k] += beta * w;
         }
     }
@@ -601,6 +628,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr int NX = TX * N, NY = TY * N, NT = NX * NY, N2 = N * N, N3 = N2 * N;
     constexpr int WG = wg_of(NT);
     constexpr int RS = NX + 2 * N, PS = RS * (NY + 2 * N);  // LDS staging: row and plane strides
+    constexpr int OR = NX, OP = OR * NY;                     // LDS x / y terms: row and plane strides
     constexpr int NP = NT / 2;                               // element pairs per axis and layer
     constexpr int NH = 2 * (TX + TY);                        // halo elements per layer
     constexpr int HS = (NH + TX * TY - 1) / (TX * TY);       // halo columns per thread
@@ -610,7 +638,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr bool IS_CHEB = MODE == BM_CHEB || MODE == BM_CHEBDOT;
     constexpr bool DOT = MODE == BM_CHEBDOT || MODE == BM_PQ || MODE == BM_RESIDDOT;
     __shared__ T su[N * PS];
-    __shared__ T sxy[2 * N * NT];
+    __shared__ T sxy[2 * N * OP];
     __shared__ double red[WG / 64];
 
     const int per_rhs = a.nt0 * a.nt1 * a.nzc;
@@ -636,14 +664,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
 
     const RefDev<T>& R = a.L->ref;
     SlabCoef<T, N> c;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int l = 0; l < N; ++l) c.B[i][l] = R.B[i][l];
-        c.aL[i] = R.aL[i];
-        c.aR[i] = R.aR[i];
-    }
-    c.sig = R.sig;
+    load_coef(c, R);
 
     const int t = threadIdx.x;
     const bool tact = t < NT;
@@ -656,7 +677,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     const bool colok = tact && ex < E0 && ey < E1;
     const uint32_t coff = ((uint32_t)((min(ey, E1 - 1) * E0 + min(ex, E0 - 1)) * N3 + j * N + i)) * SZ;
     const int su_own = (Y + N) * RS + X + N;
-    const int so_own = Y * NX + X;
+    const int so_own = Y * OR + X;
     const T wi = R.w[i], wj = R.w[j];
     const T P2 = R.scale[2] * wi * wj;  // z-term scale, and the z part of the diagonal per reference entry
     T P1 = 0;                           // x and y parts of the diagonal (times w_k)
@@ -706,14 +727,14 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
         pe = tx0 + 2 * pa;
         pok = pe < E0 && ty0 + Yr / N < E1;
         pb = kr * PS + (Yr + N) * RS + 2 * pa * N;
-        ob = kr * NT + Yr * NX + 2 * pa * N;
+        ob = kr * OP + Yr * OR + 2 * pa * N;
         psc = R.scale[0] * R.w[Yr % N] * R.w[kr];
     } else {
         const int q = min(t, NT - 1) - NP, pa = q % (TY / 2), col = q / (TY / 2), Xc = col % NX, kr = col / NX;
         pe = ty0 + 2 * pa;
         pok = tact && pe < E1 && tx0 + Xc / N < E0;
         pb = kr * PS + 2 * pa * N * RS + Xc + N;
-        ob = N * NT + kr * NT + 2 * pa * N * NX + Xc;
+        ob = N * OP + kr * OP + 2 * pa * N * OR + Xc;
         psc = R.scale[1] * R.w[Xc % N] * R.w[kr];
     }
 
@@ -759,12 +780,12 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
         T fcol[N], zpcol[N];
         if constexpr (HAS_F) {
 #pragma unroll
-            for (int k = 0; k < N; ++k) bload(fcol[k], rf, coff + k * N2 * SZ, soff);
+            for (int k = 0; k < N; ++k) bload(fcol[k], rf, coff, soff + k * N2 * SZ);
         }
         if constexpr (IS_CHEB) {
             if (has_zp) {
 #pragma unroll
-                for (int k = 0; k < N; ++k) bload(zpcol[k], rzp, coff + k * N2 * SZ, soff);
+                for (int k = 0; k < N; ++k) bload(zpcol[k], rzp, coff, soff + k * N2 * SZ);
             } else {
 #pragma unroll
                 for (int k = 0; k < N; ++k) zpcol[k] = 0;
@@ -776,7 +797,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
             if (isx)
                 pair_row<T, N, 1, 1>(c, su, pb, sxy, ob, pe, E0, psc);
             else
-                pair_row<T, N, RS, NX>(c, su, pb, sxy, ob, pe, E1, psc);
+                pair_row<T, N, RS, OR>(c, su, pb, sxy, ob, pe, E1, psc);
         }
         // z term of the column
         T zacc[N];
@@ -806,13 +827,13 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
             const bool zb = ez == 0 || ez == E2 - 1;
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const T y = zacc[k] * P2 + sxy[k * NT + so_own] + sxy[N * NT + k * NT + so_own];
-                const uint32_t vo = coff + k * N2 * SZ;
+                const T y = zacc[k] * P2 + sxy[k * OP + so_own] + sxy[N * OP + k * OP + so_own];
+                const uint32_t so = soff + k * N2 * SZ;
                 if constexpr (MODE == BM_APPLY) {
-                    bstore(y, ro, vo, soff);
+                    bstore(y, ro, coff, so);
                 } else if constexpr (MODE == BM_RESID || MODE == BM_RESIDDOT) {
                     const T r = fcol[k] - y;
-                    bstore(r, ro, vo, soff);
+                    bstore(r, ro, coff, so);
                     if constexpr (MODE == BM_RESIDDOT) dot += (double)r * (double)r;
                 } else if constexpr (IS_CHEB) {
                     T cd = crD[k];
@@ -824,11 +845,11 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                     }
                     const T uz = cur[k];
                     const T zn = uz + a.cp * (uz - zpcol[k]) + cd * (fcol[k] - y);
-                    bstore(zn, ro, vo, soff);
+                    bstore(zn, ro, coff, so);
                     if constexpr (MODE == BM_CHEBDOT) dot += (double)fcol[k] * (double)zn;
                 } else if constexpr (MODE == BM_PQ) {
-                    bstore(cur[k], ro2, vo, soff);
-                    bstore(y, ro, vo, soff);
+                    bstore(cur[k], ro2, coff, so);
+                    bstore(y, ro, coff, so);
                     dot += (double)cur[k] * (double)y;
                 }
             }
@@ -868,7 +889,10 @@ static void slab_shape(int n, int& tx, int& ty, int& zlen) {
     switch (n) {
         case 2: tx = ty = 8; zlen = 2; break;
         case 3: tx = ty = 8; zlen = 2; break;
-        case 5: tx = ty = 4; zlen = 4; break;
+        case 5:  // FP64 needs twice the registers: smaller work-groups pack better
+            tx = ty = sizeof(T) == 8 ? 2 : 4;
+            zlen = 4;
+            break;
         default: break;
     }
 }
@@ -933,6 +957,7 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
     if (g.tx == 8 && g.ty == 8 && L.n == 2) slab_dispatch<T, 2, 8, 8>(mode, a, grid, s);
     else if (g.tx == 8 && g.ty == 8 && L.n == 3) slab_dispatch<T, 3, 8, 8>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 4 && L.n == 5) slab_dispatch<T, 5, 4, 4>(mode, a, grid, s);
+    else if (g.tx == 2 && g.ty == 2 && L.n == 5) slab_dispatch<T, 5, 2, 2>(mode, a, grid, s);
     else return false;
     return true;
 }
