@@ -888,7 +888,7 @@ static void slab_shape(int n, int& tx, int& ty, int& zlen) {
     zlen = 4;
     switch (n) {
         case 2: tx = ty = 8; zlen = 2; break;
-        case 3: tx = ty = 8; zlen = 2; break;
+        case 3: tx = ty = 4; zlen = 4; break;
         case 5:  // FP64 needs twice the registers: smaller work-groups pack better
             tx = ty = sizeof(T) == 8 ? 2 : 4;
             zlen = 4;
@@ -955,7 +955,7 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
     const int grid = g.nt0 * g.nt1 * g.nzc * nrhs;
     if (grid == 0) return true;
     if (g.tx == 8 && g.ty == 8 && L.n == 2) slab_dispatch<T, 2, 8, 8>(mode, a, grid, s);
-    else if (g.tx == 8 && g.ty == 8 && L.n == 3) slab_dispatch<T, 3, 8, 8>(mode, a, grid, s);
+    else if (g.tx == 4 && g.ty == 4 && L.n == 3) slab_dispatch<T, 3, 4, 4>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 4 && L.n == 5) slab_dispatch<T, 5, 4, 4>(mode, a, grid, s);
     else if (g.tx == 2 && g.ty == 2 && L.n == 5) slab_dispatch<T, 5, 2, 2>(mode, a, grid, s);
     else return false;

@@ -15,6 +15,7 @@
 // fixed-order reduction (deterministic).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -147,6 +148,125 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ x, 
             if (o2 < nvo) {
                 const float v = acc[nb][r] + bco;
                 y[((long long)b * nvo + o2) * Co + co] = relu ? fmaxf(v, 0.f) : v;
+            }
+        }
+    }
+}
+
+// 3x3x3 stride-1 convolution on the matrix cores with the input staged in
+// LDS.  A work-group of four waves owns CV_VPW consecutive output voxels of
+// one sample; the box of input voxels they read (their z planes and rows,
+// plus one voxel of padding on each side, zeros outside the grid) is staged
+// once per chunk of 32 input channels as BF16, [voxel][32 channels], so each
+// input value is converted once instead of once per tap.  Each wave computes
+// CV_MB blocks of 16 voxels x 16 NB output channels: per tap it reads its A
+// operands from LDS (16 bytes per lane, the 8 channels 8 kb .. 8 kb + 7 of
+// voxel m = lane % 16) and NB B operands from the transposed weights, and
+// issues CV_MB x NB MFMAs, so every weight load feeds CV_MB of them.
+constexpr int CV_MB = 2;                 // voxel blocks per wave
+constexpr int CV_VPW = 4 * 16 * CV_MB;  // voxels per work-group
+
+// Box of input voxels staged for the output voxels [v0, v1) of a D x H x W grid.
+struct ConvBox {
+    int z0, y0, bz, by, bx;  // first plane and row (may be -1), extents
+};
+__host__ __device__ inline ConvBox conv_box(int v0, int v1, int H, int W) {
+    const int HW = H * W;
+    const int zlo = v0 / HW, zhi = (v1 - 1) / HW;
+    int ylo = 0, yhi = H - 1;
+    if (zlo == zhi) {
+        ylo = (v0 % HW) / W;
+        yhi = ((v1 - 1) % HW) / W;
+    }
+    ConvBox b;
+    b.z0 = zlo - 1;
+    b.y0 = ylo - 1;
+    b.bz = zhi - zlo + 3;
+    b.by = yhi - ylo + 3;
+    b.bx = W + 2;
+    return b;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_conv3_lds(const float* __restrict__ x, const __bf16* __restrict__ Wt,
+                                                   const float* __restrict__ bias, float* __restrict__ y, int D, int H,
+                                                   int Wd, int Ci, int CiP, int Co, int relu) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char conv_lds[];
+    bf16x8* sx = reinterpret_cast<bf16x8*>(conv_lds);  // [box voxel][4 groups of 8 channels]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nvo = D * H * Wd;
+    const int v0 = blockIdx.x * CV_VPW, v1 = min(nvo, v0 + CV_VPW);
+    const int b = blockIdx.y;
+    const ConvBox bx = conv_box(v0, v1, H, Wd);
+    const int nbox = bx.bz * bx.by * bx.bx;
+    const int m = lane & 15, kb = lane >> 4;
+    // LDS voxel index of each block's voxel (centre tap), clamped to the grid
+    int cen[CV_MB];
+#pragma unroll
+    for (int q = 0; q < CV_MB; ++q) {
+        const int o = min(v0 + (wave * CV_MB + q) * 16 + m, nvo - 1);
+        const int ox = o % Wd, oy = (o / Wd) % H, oz = o / (Wd * H);
+        cen[q] = ((oz - bx.z0) * bx.by + (oy - bx.y0)) * bx.bx + ox + 1;
+    }
+    f32x4 acc[CV_MB][NB];
+#pragma unroll
+    for (int q = 0; q < CV_MB; ++q)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[q][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float* xb = x + (long long)b * nvo * Ci;
+    const bool vec = (Ci % 8) == 0;
+    for (int cc = 0; cc < CiP; cc += 32) {
+        if (cc) __syncthreads();  // the previous chunk's reads are done
+        for (int e = threadIdx.x; e < nbox * 4; e += 256) {
+            const int bv = e >> 2, g = e & 3;
+            const int ix = bv % bx.bx - 1, iy = (bv / bx.bx) % bx.by + bx.y0, iz = bv / (bx.bx * bx.by) + bx.z0;
+            const int ci0 = cc + 8 * g;
+            bf16x8 a;
+            const bool inside = ix >= 0 && ix < Wd && iy >= 0 && iy < H && iz >= 0 && iz < D;
+            const float* xv = xb + (long long)((inside ? (iz * H + iy) * Wd + ix : 0)) * Ci;
+            if (inside && vec && ci0 + 8 <= Ci) {
+                const float4 p0 = *reinterpret_cast<const float4*>(xv + ci0);
+                const float4 p1 = *reinterpret_cast<const float4*>(xv + ci0 + 4);
+                a[0] = (__bf16)p0.x; a[1] = (__bf16)p0.y; a[2] = (__bf16)p0.z; a[3] = (__bf16)p0.w;
+                a[4] = (__bf16)p1.x; a[5] = (__bf16)p1.y; a[6] = (__bf16)p1.z; a[7] = (__bf16)p1.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a[q] = (inside && ci0 + q < Ci) ? (__bf16)xv[ci0 + q] : (__bf16)0.f;
+            }
+            sx[e] = a;
+        }
+        __syncthreads();
+#pragma unroll 3
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const int toff = ((dz - 1) * bx.by + (dy - 1)) * bx.bx + (dx - 1);
+            bf16x8 w[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                w[nb] = *reinterpret_cast<const bf16x8*>(Wt + ((long long)(t * NB * 16 + nb * 16 + m) * CiP + cc + 8 * kb));
+#pragma unroll
+            for (int q = 0; q < CV_MB; ++q) {
+                const bf16x8 a = sx[(cen[q] + toff) * 4 + kb];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[nb], acc[q][nb], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CV_MB; ++q) {
+        const int vb = v0 + (wave * CV_MB + q) * 16;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int co = nb * 16 + m;
+            if (co >= Co) continue;
+            const float bco = bias[co];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o2 = vb + 4 * kb + r;
+                if (o2 < v1) {
+                    const float v = acc[q][nb][r] + bco;
+                    y[((long long)b * nvo + o2) * Co + co] = relu ? fmaxf(v, 0.f) : v;
+                }
             }
         }
     }
@@ -596,7 +716,25 @@ void conv_forward_mfma(const dg_net* net, int li, const float* x, float* y, int 
 #define CM(KS, ST, NBV) hipLaunchKernelGGL((k_conv_mfma<KS, ST, NBV>), grid, dim3(256), 0, s, x, Wt, b, y, din[0], din[1], din[2], L.ci, CiP, dout[0], dout[1], dout[2], L.co, relu)
 #define CMN(KS, ST) switch (NB) { case 1: CM(KS, ST, 1); break; case 2: CM(KS, ST, 2); break; case 4: CM(KS, ST, 4); break; default: throw NetError("unsupported channel count for the matrix-core path"); }
     if (L.k == 1) { CMN(1, 1) }
-    else if (L.s == 1) { CMN(3, 1) }
+    else if (L.s == 1) {
+        // LDS-staged kernel; the largest input box over the work-groups sizes its LDS
+        int maxbox = 0;
+        for (int v0 = 0; v0 < nvo; v0 += CV_VPW) {
+            const ConvBox bx = conv_box(v0, std::min(nvo, v0 + CV_VPW), dout[1], dout[2]);
+            maxbox = std::max(maxbox, bx.bz * bx.by * bx.bx);
+        }
+        const size_t lds = (size_t)maxbox * 64;
+        if (lds > 64 * 1024) throw NetError("convolution input box too large for LDS");
+        dim3 g3((nvo + CV_VPW - 1) / CV_VPW, B);
+#define C3(NBV) hipLaunchKernelGGL((k_conv3_lds<NBV>), g3, dim3(256), lds, s, x, Wt, b, y, din[0], din[1], din[2], L.ci, CiP, L.co, relu)
+        switch (NB) {
+            case 1: C3(1); break;
+            case 2: C3(2); break;
+            case 4: C3(4); break;
+            default: throw NetError("unsupported channel count for the matrix-core path");
+        }
+#undef C3
+    }
     else { CMN(3, 2) }
 #undef CMN
 #undef CM
