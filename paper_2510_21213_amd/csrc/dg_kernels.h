@@ -12,7 +12,8 @@ enum BrickMode {
     BM_CHEB = 2,     // out = u + cp (u - zprev) + cr D^-1 (f - A u)
     BM_CHEBDOT = 3,  // BM_CHEB and partial sums of f.out
     BM_PQ = 4,       // w = u + beta u2; out2 = w; out = A w; partial sums of w.out
-    BM_RESIDDOT = 5  // BM_RESID and partial sums of out.out
+    BM_RESIDDOT = 5,  // BM_RESID and partial sums of out.out
+    BM_RESTRICT = 6   // fc = P^T (f - A u) onto the next coarser (degree) level (launch_restrict only)
 };
 
 enum FinalizeWhat {

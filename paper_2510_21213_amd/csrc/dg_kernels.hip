@@ -458,6 +458,13 @@ struct SlabArgs {
     double* partial;
     int pstride;
     T cp, cr;
+    // BM_RESTRICT: coarse level (same elements, degree p/2) and its outputs
+    const LevelDev<T>* Lc;
+    const TransferDev* tr;
+    T* fc;
+    T* z1c;
+    long long ndofc;
+    T c0c;
 };
 
 // The interior block is symmetric and invariant under the reflection
@@ -634,10 +641,13 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr int HS = (NH + TX * TY - 1) / (TX * TY);       // halo columns per thread
     constexpr uint32_t SZ = sizeof(T);
     static_assert(TX % 2 == 0 && TY % 2 == 0, "tiles hold whole element pairs");
-    constexpr bool HAS_F = MODE == BM_RESID || MODE == BM_RESIDDOT || MODE == BM_CHEB || MODE == BM_CHEBDOT;
+    constexpr bool HAS_F = MODE == BM_RESID || MODE == BM_RESIDDOT || MODE == BM_CHEB || MODE == BM_CHEBDOT ||
+                           MODE == BM_RESTRICT;
     constexpr bool IS_CHEB = MODE == BM_CHEB || MODE == BM_CHEBDOT;
     constexpr bool DOT = MODE == BM_CHEBDOT || MODE == BM_PQ || MODE == BM_RESIDDOT;
+    constexpr int NC = (N - 1) / 2 + 1, NC3 = NC * NC * NC;  // BM_RESTRICT: coarse nodes per edge (degree p/2)
     __shared__ T su[N * PS];
+    __shared__ T sr[MODE == BM_RESTRICT ? NC * OP : 1];  // BM_RESTRICT: residual contracted along z
     __shared__ T sxy[2 * N * OP];
     __shared__ double red[WG / 64];
 
@@ -656,8 +666,9 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     const brsrc ru2 = rsrc_of(MODE == BM_PQ ? a.u2 + base : a.u + base, a.ndof);
     const brsrc rf = rsrc_of(HAS_F ? a.f + base : a.u + base, a.ndof);
     const brsrc rzp = rsrc_of(IS_CHEB && a.zprev ? a.zprev + base : a.u + base, a.ndof);
-    const brsrc ro = rsrc_of(a.out + base, a.ndof);
-    const brsrc ro2 = rsrc_of(MODE == BM_PQ ? a.out2 + base : a.out + base, a.ndof);
+    T* const obase = MODE == BM_RESTRICT ? const_cast<T*>(a.u) : a.out;  // BM_RESTRICT stores no fine field
+    const brsrc ro = rsrc_of(obase + base, a.ndof);
+    const brsrc ro2 = rsrc_of(MODE == BM_PQ ? a.out2 + base : obase + base, a.ndof);
     T beta = 0;
     if constexpr (MODE == BM_PQ) beta = (T)a.st[rhs].beta;
     const bool has_zp = IS_CHEB && a.zprev;
@@ -823,6 +834,11 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
             prevD = fRc;
         }
         __syncthreads();
+        T rr[N];  // BM_RESTRICT: the column's residual (0 outside the mesh)
+        if constexpr (MODE == BM_RESTRICT) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) rr[k] = 0;
+        }
         if (colok) {
             const bool zb = ez == 0 || ez == E2 - 1;
 #pragma unroll
@@ -851,6 +867,56 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                     bstore(cur[k], ro2, coff, so);
                     bstore(y, ro, coff, so);
                     dot += (double)cur[k] * (double)y;
+                } else if constexpr (MODE == BM_RESTRICT) {
+                    rr[k] = fcol[k] - y;
+                }
+            }
+        }
+        if constexpr (MODE == BM_RESTRICT) {
+            // fc = (P x P x P)^T r per element: along z in registers, then along y and x
+            // from LDS; one thread per coarse node of the tile's elements in this layer
+            const TransferDev& tr = *a.tr;
+            auto Pm = [&](int i, int c) -> T {
+                if constexpr (sizeof(T) == 8)
+                    return tr.P[i][c];
+                else
+                    return tr.Pf[i][c];
+            };
+            if (tact) {
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) {
+                    T s = 0;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) s += Pm(k, cc) * rr[k];
+                    sr[cc * OP + so_own] = s;
+                }
+            }
+            __syncthreads();
+            for (int o = t; o < TX * TY * NC3; o += WG) {
+                const int el2 = o / NC3, loc = o % NC3;
+                const int ca = loc % NC, cb = (loc / NC) % NC, cz = loc / (NC * NC);
+                const int exl2 = el2 % TX, eyl2 = el2 / TX, exo = tx0 + exl2, eyo = ty0 + eyl2;
+                if (exo >= E0 || eyo >= E1) continue;
+                T pa[N], s = 0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) pa[i] = Pm(i, ca);
+#pragma unroll
+                for (int jj = 0; jj < N; ++jj) {
+                    T u = 0;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) u += pa[i] * sr[cz * OP + (eyl2 * N + jj) * OR + exl2 * N + i];
+                    s += Pm(jj, cb) * u;
+                }
+                const long long idx =
+                    (long long)rhs * a.ndofc + ((long long)(ez * E1 + eyo) * E0 + exo) * NC3 + loc;
+                a.fc[idx] = s;
+                if (a.z1c) {
+                    const LevelDev<T>& Lc = *a.Lc;
+                    const int cx = etype(exo, E0), cy = etype(eyo, E1), czt = etype(ez, E2);
+                    const T mx = Lc.ax[0].m[ca], my = Lc.ax[1].m[cb], mz = Lc.ax[2].m[cz];
+                    const T D = Lc.ax[0].Bd[cx][ca] * my * mz + mx * Lc.ax[1].Bd[cy][cb] * mz +
+                                mx * my * Lc.ax[2].Bd[czt][cz];
+                    a.z1c[idx] = a.c0c * s / D;
                 }
             }
         }
@@ -931,16 +997,28 @@ static void slab_dispatch(int mode, const SlabArgs<T>& a, int grid, hipStream_t 
         case BM_CHEBDOT: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_CHEBDOT>), dim3(grid), dim3(WG), 0, s, a); break;
         case BM_PQ: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_PQ>), dim3(grid), dim3(WG), 0, s, a); break;
         case BM_RESIDDOT: hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESIDDOT>), dim3(grid), dim3(WG), 0, s, a); break;
+        case BM_RESTRICT:
+            if constexpr (N == 3 || N == 5)
+                hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESTRICT>), dim3(grid), dim3(WG), 0, s, a);
+            break;
     }
 }
 
 template <typename T>
 static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st,
                         const T* u, const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial,
-                        int pstride, double cp, double cr, hipStream_t s) {
+                        int pstride, double cp, double cr, hipStream_t s, const LevelHost* Lc = nullptr,
+                        const LevelDev<T>* devc = nullptr, T* fc = nullptr, T* z1c = nullptr, double c0c = 0) {
     const SlabGeom g = slab_geom<T>(L);
     if (!g.tx) return false;
+    if (mode == BM_RESTRICT && L.n != 3 && L.n != 5) return false;
     SlabArgs<T> a;
+    a.Lc = devc;
+    a.tr = L.devtr;
+    a.fc = fc;
+    a.z1c = z1c;
+    a.ndofc = Lc ? Lc->ndof : 0;
+    a.c0c = (T)c0c;
     a.L = dev;
     a.E0 = L.E[0]; a.E1 = L.E[1]; a.E2 = L.E[2];
     a.nt0 = g.nt0; a.nt1 = g.nt1; a.zlen = g.zlen; a.nzc = g.nzc;
@@ -1246,6 +1324,11 @@ template <typename T>
 void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHost& Lc, const LevelDev<T>* devc,
                      int nrhs, const RhsState* st, const T* z, const T* f, T* fc, T* z1c, double c0c,
                      hipStream_t s) {
+    // degree steps with an iterate: the slab kernel with the restriction in its epilogue
+    if (z && !Lf.hcoarse && Lc.n == (Lf.n - 1) / 2 + 1 &&
+        launch_slab<T>(BM_RESTRICT, Lf, devf, nrhs, st, z, nullptr, f, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, s,
+                       &Lc, devc, fc, z1c, c0c))
+        return;
     TransferArgs<T> a = transfer_args<T>(Lf, Lc, nrhs, st);
     a.Lf = devf; a.Lc = devc; a.z = z; a.f = f; a.fc = fc; a.z1c = z1c; a.c0c = (T)c0c;
     const int grid = bricks_of(Lf) * nrhs;
