@@ -135,7 +135,7 @@ def main():
     achieved = prof["bytes"] / prof["seconds"] / 1e9 if prof["seconds"] > 0 else None
     roofline = {
         "bound": "hbm",
-        "kernel": "finest-level Chebyshev smoothing step (k_brick, N=5, BM_CHEB/BM_CHEBDOT, "
+        "kernel": "finest-level Chebyshev smoothing step (k_slab, N=5, BM_CHEB/BM_CHEBDOT, "
                   + ("float" if head_arm.startswith("fp32_ir") else "double") + ")",
         "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
         "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
