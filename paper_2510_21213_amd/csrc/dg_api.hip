@@ -13,10 +13,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dg_internal.h"
@@ -117,6 +119,12 @@ struct dg_ctx {
             std::vector<hipEvent_t> ev;
             size_t nev = 0;
         } graph[2];
+        // multi-mesh batches: the mesh's own stream and completion event, and its
+        // right-hand sides gathered from the caller's packing when they are not contiguous
+        hipStream_t stream = nullptr;
+        hipEvent_t ev_done = nullptr;
+        double *grho = nullptr, *gface = nullptr, *gx0 = nullptr, *gv = nullptr;
+        int cap_g = 0;
     };
     std::vector<Mesh> meshes;
     dg_net* guess = nullptr;       // learned initial guess (not owned)
@@ -132,6 +140,10 @@ struct dg_ctx {
         double seconds = 0.0, bytes = 0.0;
         bool failed = false;
     } prof;
+    hipEvent_t ev_ready = nullptr;           // multi-mesh batches: inputs assembled
+    long long* segtab = nullptr;             // gather / scatter offset tables (device)
+    long long* segtab_host = nullptr;        // their pinned staging copy
+    long long segtab_cap = 0;
     // exchange work space
     double* xv = nullptr;
     long long xv_cap = 0;
@@ -212,14 +224,17 @@ const dg::LevelDev<float>* ldev<float>(const LevelHost& L) { return L.dev32; }
 // W.za[l] already holds the first smoothing iterate c0 D^-1 f.  Returns the
 // buffer that holds z = B f.  With dot, the last smoothing step at level 0
 // also writes partial sums of f.z.
-dg_ctx::Prof* g_prof = nullptr;  // profiling state of the context being driven (one host thread per context)
+// Profiling state of the context being driven by this host thread (null on the
+// worker threads of a multi-mesh batch, which are not timed).
+thread_local dg_ctx::Prof* g_prof = nullptr;
 
 // Where prof_mark records: the context's pool (eager launches) or the event
 // set of a graph being captured (re-recorded at every replay).
 struct EventSink {
     std::vector<hipEvent_t>* ev = nullptr;
     size_t* used = nullptr;
-} g_sink;
+};
+thread_local EventSink g_sink;
 
 void prof_mark(hipStream_t s) {
     auto& ev = *g_sink.ev;
@@ -404,8 +419,10 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         const int every = std::max(1, ctx->opts.check_every);
         auto& P = ctx->prof;
         while (it < maxit) {
-            P.used = 0;
-            g_sink = {&P.ev, &P.used};
+            if (timed) {
+                P.used = 0;
+                g_sink = {&P.ev, &P.used};
+            }
             for (int c = 0; c < every && it < maxit; ++c, ++it) pcg_iteration<T>(M, W, nrhs, st, it & 1, s);
             HIPCHK(hipGetLastError());
             read_state(M, st, nrhs, s);
@@ -830,9 +847,14 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
         HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ctx->ev_ready, hipEventDisableTiming));
         hipStream_t s = ctx->stream;
         ctx->meshes.resize(n_meshes);
-        for (int i = 0; i < n_meshes; ++i) setup_mesh(ctx.get(), meshes[i], ctx->meshes[i], s);
+        for (int i = 0; i < n_meshes; ++i) {
+            setup_mesh(ctx.get(), meshes[i], ctx->meshes[i], s);
+            HIPCHK(hipStreamCreateWithFlags(&ctx->meshes[i].stream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&ctx->meshes[i].ev_done, hipEventDisableTiming));
+        }
         HIPCHK(hipDeviceSynchronize());
         *out = ctx.release();
     });
@@ -856,6 +878,12 @@ void dg_poisson_destroy(dg_ctx* ctx) {
         dfree(M.st);
         dfree(M.st_in);
         if (M.st_host) (void)hipHostFree(M.st_host);
+        dfree(M.grho);
+        dfree(M.gface);
+        dfree(M.gx0);
+        dfree(M.gv);
+        if (M.ev_done) (void)hipEventDestroy(M.ev_done);
+        if (M.stream) (void)hipStreamDestroy(M.stream);
     }
     for (auto e : ctx->prof.ev) (void)hipEventDestroy(e);
     for (auto& M : ctx->meshes) {
@@ -865,6 +893,9 @@ void dg_poisson_destroy(dg_ctx* ctx) {
     }
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->ev_ready) (void)hipEventDestroy(ctx->ev_ready);
+    dfree(ctx->segtab);
+    if (ctx->segtab_host) (void)hipHostFree(ctx->segtab_host);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     dfree(ctx->g_x0);
     dfree(ctx->g_rho);
@@ -951,40 +982,165 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
         if (nrhs < 0) throw ArgError("nrhs must be >= 0");
         if (nrhs == 0) return;
         if (!mesh_id || !rho || !g || !v) throw ArgError("null pointer argument");
+        for (int i = 0; i < nrhs; ++i) check_mesh_id(ctx, mesh_id[i]);
         const hipStream_t user = stream;
         stream = enter(ctx, user);
-        // group consecutive right-hand sides by mesh, keeping the caller's packing
+        const bool fp32 = ctx->opts.precision == DG_PREC_FP32_IR;
         std::vector<long long> off(nrhs + 1, 0), foff(nrhs + 1, 0);
         for (int i = 0; i < nrhs; ++i) {
-            check_mesh_id(ctx, mesh_id[i]);
             off[i + 1] = off[i] + ctx->meshes[mesh_id[i]].lv[0].ndof;
             foff[i + 1] = foff[i] + ctx->meshes[mesh_id[i]].nface;
         }
-        int i = 0;
-        while (i < nrhs) {
-            int j = i;
-            while (j < nrhs && mesh_id[j] == mesh_id[i]) ++j;
-            Mesh& M = ctx->meshes[mesh_id[i]];
-            const int cnt = j - i;
-            ensure_b(M, cnt, ctx->opts.precision == DG_PREC_FP32_IR);
-            dg::launch_rhs(M.lv[0], M.lv[0].dev64, cnt, rho + off[i], nullptr, nullptr, nullptr, g + foff[i], M.nface,
-                           M.b, stream);
-            if (!x0 && ctx->guess) {
-                if (ctx->g_cap < M.lv[0].ndof * cnt) {
+        // One part per mesh: all of its right-hand sides, in the caller's order, solved
+        // together whatever the interleaving (gathered when they are not contiguous).
+        struct Part {
+            int m = 0, cnt = 0;
+            bool contig = true, guessed = false;
+            long long tab = 0;  // offset-table position (non-contiguous parts)
+            const double *rho = nullptr, *g = nullptr, *x0 = nullptr;
+            double* v = nullptr;
+            std::vector<int> idx, used;
+            std::vector<dg_rhs_stats> stats;
+        };
+        std::vector<Part> parts;
+        {
+            std::vector<int> pos(ctx->meshes.size(), -1);
+            for (int i = 0; i < nrhs; ++i) {
+                int& k = pos[mesh_id[i]];
+                if (k < 0) {
+                    k = (int)parts.size();
+                    parts.emplace_back();
+                    parts.back().m = mesh_id[i];
+                }
+                parts[k].idx.push_back(i);
+            }
+        }
+        long long ntab = 0;
+        for (auto& P : parts) {
+            P.cnt = (int)P.idx.size();
+            P.contig = P.idx.back() - P.idx.front() + 1 == P.cnt;
+            P.stats.assign(P.cnt, dg_rhs_stats{});
+            if (!P.contig) {
+                P.tab = ntab;
+                ntab += 4LL * P.cnt;
+            }
+        }
+        if (ntab > 0) {
+            // tables A = caller offsets, B = packed offsets (fields); C, D the same for the faces
+            if (ctx->segtab_cap < ntab) {
+                dfree(ctx->segtab);
+                if (ctx->segtab_host) (void)hipHostFree(ctx->segtab_host);
+                ctx->segtab_host = nullptr;
+                ctx->segtab = dalloc<long long>(ntab);
+                HIPCHK(hipHostMalloc((void**)&ctx->segtab_host, sizeof(long long) * ntab, hipHostMallocDefault));
+                ctx->segtab_cap = ntab;
+            }
+            for (auto& P : parts) {
+                if (P.contig) continue;
+                const Mesh& M = ctx->meshes[P.m];
+                long long* t = ctx->segtab_host + P.tab;
+                for (int q = 0; q < P.cnt; ++q) {
+                    t[q] = off[P.idx[q]];
+                    t[P.cnt + q] = q * M.lv[0].ndof;
+                    t[2 * P.cnt + q] = foff[P.idx[q]];
+                    t[3 * P.cnt + q] = q * M.nface;
+                }
+            }
+            HIPCHK(hipMemcpyAsync(ctx->segtab, ctx->segtab_host, sizeof(long long) * ntab, hipMemcpyHostToDevice,
+                                  stream));
+        }
+        for (auto& P : parts) {
+            Mesh& M = ctx->meshes[P.m];
+            const long long n0 = M.lv[0].ndof;
+            const int cnt = P.cnt;
+            // every buffer is sized here, on this thread: the solves below allocate nothing
+            ensure_b(M, cnt, fp32);
+            ensure_state(M, cnt);
+            if (fp32)
+                ensure_work<float>(M, M.w32, cnt);
+            else
+                ensure_work<double>(M, M.w64, cnt);
+            const bool want_guess = !x0 && ctx->guess;
+            if ((!P.contig || want_guess) && M.cap_g < cnt) {
+                dfree(M.grho);
+                dfree(M.gface);
+                dfree(M.gx0);
+                dfree(M.gv);
+                M.grho = dalloc<double>(n0 * cnt);
+                M.gface = dalloc<double>(M.nface * cnt);
+                M.gx0 = dalloc<double>(n0 * cnt);
+                M.gv = dalloc<double>(n0 * cnt);
+                M.cap_g = cnt;
+            }
+            if (P.contig) {
+                const int i0 = P.idx.front();
+                P.rho = rho + off[i0];
+                P.g = g + foff[i0];
+                P.x0 = x0 ? x0 + off[i0] : nullptr;
+                P.v = v + off[i0];
+            } else {
+                const long long* t = ctx->segtab + P.tab;
+                dg::launch_segcopy(rho, t, M.grho, t + cnt, n0, cnt, stream);
+                dg::launch_segcopy(g, t + 2 * cnt, M.gface, t + 3 * cnt, M.nface, cnt, stream);
+                if (x0) dg::launch_segcopy(x0, t, M.gx0, t + cnt, n0, cnt, stream);
+                P.rho = M.grho;
+                P.g = M.gface;
+                P.x0 = x0 ? M.gx0 : nullptr;
+                P.v = M.gv;
+            }
+            dg::launch_rhs(M.lv[0], M.lv[0].dev64, cnt, P.rho, nullptr, nullptr, nullptr, P.g, M.nface, M.b, stream);
+            if (want_guess) {
+                if (ctx->g_cap < n0 * cnt) {
                     dfree(ctx->g_x0);
                     dfree(ctx->g_rho);
-                    ctx->g_x0 = dalloc<double>(M.lv[0].ndof * cnt);
-                    ctx->g_rho = dalloc<double>(M.lv[0].ndof * cnt);
-                    ctx->g_cap = M.lv[0].ndof * cnt;
+                    ctx->g_x0 = dalloc<double>(n0 * cnt);
+                    ctx->g_rho = dalloc<double>(n0 * cnt);
+                    ctx->g_cap = n0 * cnt;
                 }
-                dg::launch_copy(rho + off[i], ctx->g_rho, M.lv[0].ndof * cnt, stream);
-                std::vector<int> used = learned_guess(ctx, M, cnt, ctx->g_rho, M.b, stream);
-                solve_group(ctx, M, cnt, M.b, ctx->g_x0, v + off[i], stats ? stats + i : nullptr, stream, &used);
-            } else {
-                solve_group(ctx, M, cnt, M.b, x0 ? x0 + off[i] : nullptr, v + off[i], stats ? stats + i : nullptr,
-                            stream);
+                dg::launch_copy(P.rho, ctx->g_rho, n0 * cnt, stream);
+                P.used = learned_guess(ctx, M, cnt, ctx->g_rho, M.b, stream);
+                dg::launch_copy(ctx->g_x0, M.gx0, n0 * cnt, stream);  // the guess buffer is shared by the parts
+                P.x0 = M.gx0;
+                P.guessed = true;
             }
-            i = j;
+        }
+        if (parts.size() == 1) {
+            auto& P = parts[0];
+            solve_group(ctx, ctx->meshes[P.m], P.cnt, ctx->meshes[P.m].b, P.x0, P.v, P.stats.data(), stream,
+                        P.guessed ? &P.used : nullptr);
+        } else {
+            // meshes are independent: each is solved on its own stream by its own host
+            // thread, so that the host waits of one overlap the kernels of the others
+            HIPCHK(hipEventRecord(ctx->ev_ready, stream));
+            std::vector<std::exception_ptr> err(parts.size());
+            std::vector<std::thread> th;
+            for (size_t k = 0; k < parts.size(); ++k) {
+                th.emplace_back([&, k] {
+                    try {
+                        HIPCHK(hipSetDevice(ctx->device));
+                        auto& P = parts[k];
+                        Mesh& M = ctx->meshes[P.m];
+                        HIPCHK(hipStreamWaitEvent(M.stream, ctx->ev_ready, 0));
+                        solve_group(ctx, M, P.cnt, M.b, P.x0, P.v, P.stats.data(), M.stream,
+                                    P.guessed ? &P.used : nullptr);
+                        HIPCHK(hipEventRecord(M.ev_done, M.stream));
+                    } catch (...) {
+                        err[k] = std::current_exception();
+                    }
+                });
+            }
+            for (auto& t : th) t.join();
+            for (auto& e : err)
+                if (e) std::rethrow_exception(e);
+            for (auto& P : parts) HIPCHK(hipStreamWaitEvent(stream, ctx->meshes[P.m].ev_done, 0));
+        }
+        for (auto& P : parts) {
+            if (!P.contig) {
+                const long long* t = ctx->segtab + P.tab;
+                dg::launch_segcopy(P.v, t + P.cnt, v, t, ctx->meshes[P.m].lv[0].ndof, P.cnt, stream);
+            }
+            if (stats)
+                for (int q = 0; q < P.cnt; ++q) stats[P.idx[q]] = P.stats[q];
         }
         HIPCHK(hipStreamSynchronize(stream));
         leave(ctx, user);

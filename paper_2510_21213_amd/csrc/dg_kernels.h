@@ -101,6 +101,10 @@ void launch_exchange(const LevelHost& L, const LevelDev<double>* dev, int norb, 
 void launch_pair_products(long long ndof, int npairs, const double* phi, const int* pi, const int* pj, double* rho,
                           hipStream_t s);
 
+// dst[doff[q] + i] = src[soff[q] + i] for i < len and q < nseg (offset tables on the device).
+void launch_segcopy(const double* src, const long long* soff, double* dst, const long long* doff, long long len,
+                    int nseg, hipStream_t s);
+
 // K[q] = sum of partial[q][0..nblk-1] (fixed order).
 void launch_sum_partials(int nq, const double* partial, int pstride, int nblk, double* K, hipStream_t s);
 

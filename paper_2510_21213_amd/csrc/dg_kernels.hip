@@ -1768,6 +1768,21 @@ void launch_fill(T* x, T v, long long n, hipStream_t s) {
 template void launch_fill<double>(double*, double, long long, hipStream_t);
 template void launch_fill<float>(float*, float, long long, hipStream_t);
 
+__global__ __launch_bounds__(256) void k_segcopy(const double* __restrict__ src, const long long* __restrict__ soff,
+                                                  double* __restrict__ dst, const long long* __restrict__ doff,
+                                                  long long len) {
+    const double* a = src + soff[blockIdx.y];
+    double* b = dst + doff[blockIdx.y];
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < len; i += (long long)gridDim.x * 256) b[i] = a[i];
+}
+
+void launch_segcopy(const double* src, const long long* soff, double* dst, const long long* doff, long long len,
+                    int nseg, hipStream_t s) {
+    if (nseg <= 0 || len <= 0) return;
+    const int gx = (int)std::min<long long>((len + 255) / 256, 256);
+    hipLaunchKernelGGL(k_segcopy, dim3(gx, nseg), dim3(256), 0, s, src, soff, dst, doff, len);
+}
+
 __global__ __launch_bounds__(256) void k_copy(const double* __restrict__ a, double* __restrict__ b, long long n) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i < n) b[i] = a[i];

@@ -166,6 +166,39 @@ def test_batch_over_two_meshes_interleaved(gpu_lib):
         off += n
 
 
+def test_uneven_batch_three_meshes_matches_oracle_and_per_mesh_solves(gpu_lib):
+    """Interleaved right-hand sides of three meshes (degrees 4, 3 and 2) in one call, mixed
+    precision: every potential against the exact solve, and bitwise equal to solving each
+    mesh's right-hand sides on their own (the batch only regroups and overlaps them)."""
+    meshes = [configs.Mesh((4, 4, 4), 4, (-2.0,) * 3, (2.0,) * 3),
+              configs.Mesh((6, 4, 4), 3, (-3.0, -2.0, -2.0), (3.0, 2.0, 2.0)),
+              configs.Mesh((4, 6, 4), 2, (-2.0, -3.0, -2.0), (2.0, 3.0, 2.0))]
+    wl = configs.scaled(4, 4, 7, seed=33)
+    ids = [2, 0, 1, 2, 0, 1, 1]
+    dens = [wl.batch.densities[k] for k in range(len(ids))]
+    ctx = gpu_lib.Context([(m.E, m.p, m.lo, m.hi) for m in meshes], rtol=PARITY_RTOL, precision="fp32_ir")
+    rho, g = [], []
+    for k, mid in enumerate(ids):
+        r_, g_ = gpu_sample(ctx, mid, dens[k])
+        rho.append(r_); g.append(g_)
+    v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)), mesh_ids=ids)
+    v = _n(v)
+    offs = np.cumsum([0] + [ctx.info[mid]["n_dofs"] for mid in ids])
+    for k, mid in enumerate(ids):
+        axes, _, _, b = oracle_density_problem(meshes[mid], dens[k])
+        assert rel_l2_M(axes, meshes[mid], v[offs[k]:offs[k + 1]], fdm.FDM(axes).solve(b)) <= POT_BAR
+        assert st[k]["status"] == 0
+    for mid in range(3):
+        ks = [k for k, m in enumerate(ids) if m == mid]
+        vm, sm = ctx.solve_batch(_t(np.concatenate([rho[k] for k in ks])), _t(np.concatenate([g[k] for k in ks])),
+                                 mesh_ids=[mid] * len(ks))
+        vm = _n(vm)
+        n = ctx.info[mid]["n_dofs"]
+        for q, k in enumerate(ks):
+            assert np.array_equal(vm[q * n:(q + 1) * n], v[offs[k]:offs[k + 1]])
+            assert sm[q]["iters"] == st[k]["iters"]
+
+
 def test_zero_and_empty_right_hand_sides(gpu_lib):
     mesh = configs.Mesh((4, 4, 4), 2, (-1.0,) * 3, (1.0,) * 3)
     ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)])
