@@ -95,7 +95,11 @@ typedef struct {
     double inner_rtol;   /* FP32_IR: relative tolerance of each inner solve (loosened for the last
                             step to 0.9 rtol ||b|| / ||r_k|| when that is larger) */
     int max_outer;       /* FP32_IR: refinement steps */
-    int check_every;     /* PCG iterations between host convergence checks */
+    int check_every;     /* PCG iterations per replay block (graph: rounded up to even) and
+                            between host convergence checks; with a graph the first check
+                            waits for as many iterations as the same PCG run of the previous
+                            solve on this mesh needed (finished right-hand sides are skipped
+                            on the device, so replays past convergence change nothing) */
     int use_graph;       /* 1: replay the PCG iteration as a captured HIP graph */
 } dg_opts;
 
@@ -111,7 +115,7 @@ typedef struct dg_ctx dg_ctx;
 
 /* Fill *opts with the defaults: automatic levels, degree 5, ratio 20,
  * safety 1.1, 30 Lanczos steps, eps 1/8, rtol 1e-8, 500 iterations, FP64,
- * inner_rtol 1e-4, max_outer 8, check_every 4, use_graph 1. */
+ * inner_rtol 1e-4, max_outer 8, check_every 2, use_graph 1. */
 void dg_opts_default(dg_opts* opts);
 
 /* Build the level hierarchy, operator tables, coarsest-grid eigendata and

@@ -123,6 +123,9 @@ struct dg_ctx {
         // right-hand sides gathered from the caller's packing when they are not contiguous
         hipStream_t stream = nullptr;
         hipEvent_t ev_done = nullptr;
+        // iterations the k-th PCG run of the last solve needed (per precision): the next
+        // solve replays that many before its first host check
+        std::vector<int> pred[2];
         double *grho = nullptr, *gface = nullptr, *gx0 = nullptr, *gv = nullptr;
         int cap_g = 0;
     };
@@ -343,7 +346,7 @@ void init_state(Mesh& M, dg::RhsState* st, int nrhs, double rtol, int maxit, hip
 // PCG on level 0 from the current x and r of W (r holds the residual);
 // st must have tol2/maxit/bb set.  Returns the iterations performed.
 template <typename T>
-void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const dg::RhsState* gate,
+void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const dg::RhsState* gate, int slot,
              hipStream_t s) {
     const LevelHost& L0 = M.lv[0];
     const int nc = dg::chunks_of(L0.ndof);
@@ -406,9 +409,15 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
             G.prof = timed;
             G.nev = used;
         }
+        // replay up to the count the same run of the previous solve needed, then check
+        // after every replay (finished right-hand sides cost only early-exiting launches)
+        auto& pred = M.pred[sizeof(T) == 8 ? 0 : 1];
+        const int ahead = slot < (int)pred.size() ? pred[slot] : 0;
         while (it < maxit) {
-            HIPCHK(hipGraphLaunch(G.exec, s));
-            it += every;
+            do {
+                HIPCHK(hipGraphLaunch(G.exec, s));
+                it += every;
+            } while (it + every <= ahead && it < maxit);
             read_state(M, st, nrhs, s);
             if (timed) prof_sum(G.ev, G.nev);
             bool any = false;
@@ -431,6 +440,13 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
             for (int i = 0; i < nrhs; ++i) any |= M.st_host[i].active != 0;
             if (!any) break;
         }
+    }
+    {
+        auto& pred = M.pred[sizeof(T) == 8 ? 0 : 1];
+        if ((int)pred.size() <= slot) pred.resize(slot + 1, 0);
+        int need = 0;
+        for (int i = 0; i < nrhs; ++i) need = std::max(need, M.st_host[i].iters);
+        pred[slot] = need;
     }
     if (g_prof && g_prof->on) {
         // algorithmic bytes of the timed steps: per V-cycle, pre-smoothing steps 1..m-1 and post-smoothing
@@ -490,7 +506,7 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             dg::launch_copy(b, W.r, n0 * nrhs, s);
         }
         for (int restart = 0; restart < 3; ++restart) {
-            pcg_run<double>(ctx, M, W, nrhs, M.st, nullptr, s);
+            pcg_run<double>(ctx, M, W, nrhs, M.st, nullptr, restart, s);
             for (int i = 0; i < nrhs; ++i) iters[i] += M.st_host[i].iters;
             // FP64 residual of the current solution
             dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr, W.r,
@@ -548,7 +564,7 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
                 M.st_host[i] = S;
             }
             HIPCHK(hipMemcpyAsync(M.st_in, M.st_host, sizeof(dg::RhsState) * nrhs, hipMemcpyHostToDevice, s));
-            pcg_run<float>(ctx, M, W, nrhs, M.st_in, M.st, s);
+            pcg_run<float>(ctx, M, W, nrhs, M.st_in, M.st, it, s);
             for (int i = 0; i < nrhs; ++i) iters[i] += M.st_host[i].iters;
             dg::launch_correct(n0, nrhs, M.st, W.x, v, s);
         }
@@ -811,7 +827,7 @@ void dg_opts_default(dg_opts* o) {
     o->precision = DG_PREC_FP64;
     o->inner_rtol = 1e-4;
     o->max_outer = 8;
-    o->check_every = 4;
+    o->check_every = 2;
     o->use_graph = 1;
 }
 
