@@ -170,6 +170,14 @@ dg_status dg_rhs_assemble(dg_ctx* ctx, int mesh_id, int nrhs, const double* rho,
 /* z = B r, one V-cycle of the hp-multigrid preconditioner from `level` down. */
 dg_status dg_vcycle_apply(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* r, double* z,
                           hipStream_t stream);
+/* The FP32 forms of the two entries above, as the inner solve of DG_PREC_FP32_IR
+ * runs them: FP32 fields and FP32 arithmetic for the operator, the smoother and
+ * the transfers; the coarsest solve still in FP64 arithmetic (on FP32 data).
+ * Same layout, ownership and errors as the FP64 entries. */
+dg_status dg_operator_apply_f32(dg_ctx* ctx, int mesh_id, int level, int nrhs, const float* u, float* y,
+                                hipStream_t stream);
+dg_status dg_vcycle_apply_f32(dg_ctx* ctx, int mesh_id, int level, int nrhs, const float* r, float* z,
+                              hipStream_t stream);
 /* Coarsest-level exact solve z = A^{-1} r (fast diagonalisation). */
 dg_status dg_coarse_solve(dg_ctx* ctx, int mesh_id, int nrhs, const double* r, double* z, hipStream_t stream);
 /* Transfers between `level` and `level`+1: rc = P^T r (restriction of a

@@ -59,6 +59,8 @@ def _load():
         "dg_poisson_solve_batch": (I, [P, I, P, P, P, P, P, P, P]),
         "dg_exchange_apply": (I, [P, I, I, P, P, P, P, P, P, P, P]),
         "dg_operator_apply": (I, [P, I, I, I, P, P, P]),
+        "dg_operator_apply_f32": (I, [P, I, I, I, P, P, P]),
+        "dg_vcycle_apply_f32": (I, [P, I, I, I, P, P, P]),
         "dg_rhs_assemble": (I, [P, I, I, P, P, P, P]),
         "dg_vcycle_apply": (I, [P, I, I, I, P, P, P]),
         "dg_coarse_solve": (I, [P, I, I, P, P, P]),
@@ -244,7 +246,10 @@ class Context:
     def operator_apply(self, u, mesh_id=0, level=0):
         nrhs = u.numel() // self._level_dofs(mesh_id, level)
         y = torch.empty_like(u)
-        _check(lib.dg_operator_apply(self._h, mesh_id, level, nrhs, _ptr(u), _ptr(y), _stream()), "operator_apply")
+        f32 = u.dtype == torch.float32
+        fn = lib.dg_operator_apply_f32 if f32 else lib.dg_operator_apply
+        pt = (lambda t: _ptr_t(t, torch.float32)) if f32 else _ptr
+        _check(fn(self._h, mesh_id, level, nrhs, pt(u), pt(y), _stream()), "operator_apply")
         return y
 
     def rhs_assemble(self, rho, g, mesh_id=0):
@@ -256,7 +261,10 @@ class Context:
     def vcycle(self, r, mesh_id=0, level=0):
         nrhs = r.numel() // self._level_dofs(mesh_id, level)
         z = torch.empty_like(r)
-        _check(lib.dg_vcycle_apply(self._h, mesh_id, level, nrhs, _ptr(r), _ptr(z), _stream()), "vcycle_apply")
+        f32 = r.dtype == torch.float32
+        fn = lib.dg_vcycle_apply_f32 if f32 else lib.dg_vcycle_apply
+        pt = (lambda t: _ptr_t(t, torch.float32)) if f32 else _ptr
+        _check(fn(self._h, mesh_id, level, nrhs, pt(r), pt(z), _stream()), "vcycle_apply")
         return z
 
     def coarse_solve(self, r, mesh_id=0):

@@ -1287,6 +1287,37 @@ dg_status dg_vcycle_apply(dg_ctx* ctx, int mesh_id, int level, int nrhs, const d
     });
 }
 
+dg_status dg_operator_apply_f32(dg_ctx* ctx, int mesh_id, int level, int nrhs, const float* u, float* y,
+                                hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (level < 0 || level >= (int)M.lv.size()) throw ArgError("level out of range");
+        if (nrhs < 0 || (nrhs > 0 && (!u || !y))) throw ArgError("bad arguments");
+        const auto& L = M.lv[level];
+        dg::launch_brick<float>(dg::BM_APPLY, L, L.dev32, nrhs, nullptr, u, nullptr, nullptr, nullptr, y, nullptr,
+                                nullptr, 0, 0, 0, stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_vcycle_apply_f32(dg_ctx* ctx, int mesh_id, int level, int nrhs, const float* r, float* z,
+                              hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (level < 0 || level >= (int)M.lv.size()) throw ArgError("level out of range");
+        if (nrhs < 0 || (nrhs > 0 && (!r || !z))) throw ArgError("bad arguments");
+        if (nrhs == 0) return;
+        ensure_state(M, nrhs);
+        ensure_work<float>(M, M.w32, nrhs);
+        g_prof = nullptr;
+        float* out = vcycle<float>(M, M.w32, level, nrhs, nullptr, r, false, false, stream);
+        HIPCHK(hipMemcpyAsync(z, out, sizeof(float) * M.lv[level].ndof * nrhs, hipMemcpyDeviceToDevice, stream));
+        HIPCHK(hipGetLastError());
+    });
+}
+
 dg_status dg_coarse_solve(dg_ctx* ctx, int mesh_id, int nrhs, const double* r, double* z, hipStream_t stream) {
     return run_guarded([&] {
         check_mesh_id(ctx, mesh_id);

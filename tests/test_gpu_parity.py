@@ -64,6 +64,45 @@ def test_operator_apply_all_levels(gpu_lib, case):
             assert np.abs(y[r] - ref).max() <= 1e-12 * np.abs(ref).max(), (level, r)
 
 
+def _t32(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"E{c[0]}p{c[1]}" for c in CASES])
+def test_operator_apply_fp32_all_levels(gpu_lib, case):
+    """The FP32 kernels of the mixed-precision inner solve (tiles, ghosts and coefficients in
+    FP32) against the FP64 oracle, to FP32 rounding: an indexing or coefficient slip gives
+    O(1) relative errors, far above this bar."""
+    mesh = _mesh(case)
+    ctx = _ctx(gpu_lib, [case])
+    nl = ctx.info[0]["n_levels"]
+    rng = np.random.default_rng(21)
+    for level in range(nl):
+        axes, E, p = level_axes(mesh, case[4] or None, level)
+        n = p + 1
+        nrhs = 2
+        u = rng.standard_normal((nrhs, int(np.prod(E)) * n ** 3)).astype(np.float32)
+        y = _n(ctx.operator_apply(_t32(u), level=level)).reshape(nrhs, -1)
+        for r in range(nrhs):
+            ref = layout.to_element_major(sipdg.apply(axes, layout.to_global(u[r].astype(np.float64), E, n)), E, n)
+            assert np.abs(y[r] - ref).max() <= 2e-5 * np.abs(ref).max(), (level, r)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"E{c[0]}p{c[1]}" for c in CASES])
+def test_vcycle_fp32(gpu_lib, case):
+    """One FP32 V-cycle (FP32 smoothing, transfers and restriction epilogue, FP64 coarsest
+    solve) against the oracle's FP64 V-cycle, to FP32 rounding."""
+    mesh = _mesh(case)
+    ctx = _ctx(gpu_lib, [case])
+    H = mg.Hierarchy(mesh.E, mesh.p, mesh.lo, mesh.hi, n_levels=case[4] or None)
+    L0 = H.levels[0]
+    r = np.random.default_rng(22).standard_normal(L0.shape)
+    z = _n(ctx.vcycle(_t32(layout.to_element_major(r, L0.E, L0.n))))
+    ref = layout.to_element_major(H.vcycle(r), L0.E, L0.n)
+    assert np.abs(z - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("case", CASES[:3], ids=[f"E{c[0]}p{c[1]}" for c in CASES[:3]])
 def test_rhs_assembly(gpu_lib, case):
     mesh = _mesh(case)
