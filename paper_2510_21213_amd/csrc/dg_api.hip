@@ -353,15 +353,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
     // rr and the active flags
     dg::launch_dot<T, T>(L0.ndof, nrhs, gate, W.r, W.r, M.partial, M.pstride, s);
     dg::launch_finalize(dg::FIN_RR0, nrhs, st, M.partial, M.pstride, nc, s);
-    if (gate) {
-        // right-hand sides whose outer loop has finished stay inactive
-        read_state(M, gate, nrhs, s);
-        std::vector<dg::RhsState> g(M.st_host, M.st_host + nrhs);
-        read_state(M, st, nrhs, s);
-        for (int i = 0; i < nrhs; ++i)
-            if (!g[i].active) M.st_host[i].active = 0;
-        HIPCHK(hipMemcpyAsync(st, M.st_host, sizeof(dg::RhsState) * nrhs, hipMemcpyHostToDevice, s));
-    }
+    if (gate) dg::launch_gate(nrhs, st, gate, s);  // finished outer loops keep their inner solve idle
     dg::launch_cheb0<T>(L0, ldev<T>(L0), nrhs, st, W.r, W.za[0], M.cheb[0].c0, s);
     dg::launch_fill<T>(W.p0, (T)0, L0.ndof * nrhs, s);
     dg::launch_fill<T>(W.p1, (T)0, L0.ndof * nrhs, s);
@@ -549,21 +541,7 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             dg::launch_fill<float>(W.x, 0.0f, n0 * nrhs, s);
             // inner state on ||r32|| = 1: relative tolerance inner_rtol, loosened for the last
             // refinement step to what the outer tolerance still needs, rtol ||b|| / ||r_k||
-            std::vector<double> tin(nrhs);
-            for (int i = 0; i < nrhs; ++i) {
-                const auto& O = M.st_host[i];
-                const double need = O.rr > 0 ? 0.9 * o.rtol * std::sqrt(O.bb / O.rr) : 1.0;
-                tin[i] = std::min(0.5, std::max(o.inner_rtol, need));
-            }
-            for (int i = 0; i < nrhs; ++i) {
-                dg::RhsState S{};
-                S.tol2 = tin[i] * tin[i];
-                S.maxit = o.max_iter;
-                S.active = 1;
-                S.bb = 1.0;
-                M.st_host[i] = S;
-            }
-            HIPCHK(hipMemcpyAsync(M.st_in, M.st_host, sizeof(dg::RhsState) * nrhs, hipMemcpyHostToDevice, s));
+            dg::launch_inner_init(nrhs, M.st, M.st_in, o.rtol, o.inner_rtol, o.max_iter, s);
             pcg_run<float>(ctx, M, W, nrhs, M.st_in, M.st, it, s);
             for (int i = 0; i < nrhs; ++i) iters[i] += M.st_host[i].iters;
             dg::launch_correct(n0, nrhs, M.st, W.x, v, s);

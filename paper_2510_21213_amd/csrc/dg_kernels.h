@@ -76,6 +76,15 @@ void launch_dot(long long ndof, int nrhs, const RhsState* st, const TA* a, const
 void launch_finalize(int what, int nrhs, RhsState* st, const double* partial, int pstride, int nblk,
                      hipStream_t s);
 
+// st[i].active = 0 wherever gate[i].active == 0 (right-hand sides whose outer loop has finished).
+void launch_gate(int nrhs, RhsState* st, const RhsState* gate, hipStream_t s);
+
+// Inner FP32 state of a refinement step from the outer FP64 state: relative tolerance
+// max(inner_rtol, 0.9 rtol sqrt(bb / rr)) capped at 0.5 (what the outer tolerance still
+// needs), on a right-hand side of norm 1; active where the outer loop is.
+void launch_inner_init(int nrhs, const RhsState* outer, RhsState* inner, double rtol, double inner_rtol, int maxit,
+                       hipStream_t s);
+
 // b = 4 pi M rho + lift(g).  If phi is non-null, rho of right-hand side q is
 // phi[pi[q]] * phi[pj[q]] (pair densities) and rho is ignored.
 void launch_rhs(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const double* rho, const double* phi,

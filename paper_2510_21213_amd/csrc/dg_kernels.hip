@@ -1659,6 +1659,39 @@ void launch_finalize(int what, int nrhs, RhsState* st, const double* partial, in
     hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(256), 0, s, what, st, partial, pstride, nblk);
 }
 
+__global__ __launch_bounds__(256) void k_gate(int nrhs, RhsState* st, const RhsState* gate) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < nrhs && !gate[i].active) st[i].active = 0;
+}
+
+void launch_gate(int nrhs, RhsState* st, const RhsState* gate, hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL(k_gate, dim3((nrhs + 255) / 256), dim3(256), 0, s, nrhs, st, gate);
+}
+
+__global__ __launch_bounds__(256) void k_inner_init(int nrhs, const RhsState* outer, RhsState* inner, double rtol,
+                                                    double inner_rtol, int maxit) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nrhs) return;
+    const RhsState O = outer[i];
+    const double need = O.rr > 0 ? 0.9 * rtol * sqrt(O.bb / O.rr) : 1.0;
+    const double tin = fmin(0.5, fmax(inner_rtol, need));
+    RhsState S{};
+    S.tol2 = tin * tin;
+    S.maxit = maxit;
+    S.active = O.active;
+    S.bb = 1.0;
+    S.scale = 1.0;
+    inner[i] = S;
+}
+
+void launch_inner_init(int nrhs, const RhsState* outer, RhsState* inner, double rtol, double inner_rtol, int maxit,
+                       hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL(k_inner_init, dim3((nrhs + 255) / 256), dim3(256), 0, s, nrhs, outer, inner, rtol, inner_rtol,
+                       maxit);
+}
+
 // ---------------------------------------------------------------------------
 // right-hand side: b = 4 pi M rho + lift(g)
 
