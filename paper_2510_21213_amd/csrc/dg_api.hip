@@ -314,9 +314,10 @@ template <typename T>
 void pcg_iteration(Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, int parity, hipStream_t s) {
     const LevelHost& L0 = M.lv[0];
     const auto* dv = ldev<T>(L0);
-    const int nb = dg::op_blocks<T>(L0), nc = dg::chunks_of(L0.ndof);
+    const int nb_rz = dg::op_blocks<T>(L0, dg::BM_CHEBDOT), nb = dg::op_blocks<T>(L0, dg::BM_PQ);
+    const int nc = dg::chunks_of(L0.ndof);
     T* z = vcycle<T>(M, W, 0, nrhs, st, W.r, true, true, s);
-    dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nb, s);
+    dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nb_rz, s);
     T* pold = parity ? W.p1 : W.p0;
     T* pnew = parity ? W.p0 : W.p1;
     dg::launch_brick<T>(dg::BM_PQ, L0, dv, nrhs, st, z, pold, nullptr, nullptr, W.q, pnew, M.partial, M.pstride, 0.0,
@@ -479,7 +480,7 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
                  hipStream_t s, const std::vector<int>* guess_used = nullptr) {
     const LevelHost& L0 = M.lv[0];
     const long long n0 = L0.ndof;
-    const int nc = dg::chunks_of(n0), nb = dg::op_blocks<double>(L0);
+    const int nc = dg::chunks_of(n0), nb = dg::op_blocks<double>(L0, dg::BM_RESIDDOT);
     const auto& o = ctx->opts;
     ensure_state(M, nrhs);
     std::vector<int> iters(nrhs, 0), outer(nrhs, 0);
@@ -580,7 +581,7 @@ std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho
     if (dg_net_guess(ctx->guess, ctx, mesh_id, nrhs, rho, ctx->g_x0, s) != DG_OK)
         throw ArgError(std::string("learned guess failed: ") + dg_net_last_error());
     ensure_state(M, nrhs);
-    const int nc = dg::chunks_of(n0), nb = dg::op_blocks<double>(L0);
+    const int nc = dg::chunks_of(n0), nb = dg::op_blocks<double>(L0, dg::BM_RESIDDOT);
     init_state(M, M.st, nrhs, 1.0, 1, s);
     dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
     dg::launch_finalize(dg::FIN_BB, nrhs, M.st, M.partial, M.pstride, nc, s);
@@ -682,7 +683,8 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
     HIPCHK(hipMemcpy(M.dcoarse, &M.coarse, sizeof(M.coarse), hipMemcpyHostToDevice));
     int ps = dg::chunks_of(M.lv[0].ndof);
     for (auto& L : M.lv)
-        ps = std::max({ps, dg::bricks_of(L), dg::op_blocks<float>(L), dg::op_blocks<double>(L)});
+        for (int mode : {dg::BM_CHEBDOT, dg::BM_PQ, dg::BM_RESIDDOT})
+            ps = std::max({ps, dg::bricks_of(L), dg::op_blocks<float>(L, mode), dg::op_blocks<double>(L, mode)});
     M.pstride = ps;
     const int NX = mesh.ne[0] * (mesh.p + 1), NY = mesh.ne[1] * (mesh.p + 1), NZ = mesh.ne[2] * (mesh.p + 1);
     M.nface = 2LL * ((long long)NY * NZ + (long long)NX * NZ + (long long)NX * NY);

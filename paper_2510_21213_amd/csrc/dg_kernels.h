@@ -33,10 +33,10 @@ struct KernelCfg {
 
 inline int chunks_of(long long ndof) { return (int)((ndof + 1023) / 1024); }
 inline int bricks_of(const LevelHost& L) { return L.nbr[0] * L.nbr[1] * L.nbr[2]; }
-// Partial-sum slots per right-hand side that launch_brick's dot modes write
-// (its work-groups per right-hand side).
+// Partial-sum slots per right-hand side that launch_brick writes in dot mode
+// `mode` (its work-groups per right-hand side).
 template <typename T>
-int op_blocks(const LevelHost& L);
+int op_blocks(const LevelHost& L, int mode);
 
 template <typename T>
 void launch_brick(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, const T* u,

@@ -949,14 +949,22 @@ static void brick_dispatch(int mode, const BrickArgs<T>& a, int grid, hipStream_
 // or {0, 0} where the brick kernel is used.  Layers per z chunk: enough
 // chunks for a few thousand work-groups at typical batch sizes.
 template <typename T>
-static void slab_shape(int n, int& tx, int& ty, int& zlen) {
+static void slab_shape(int n, int mode, int& tx, int& ty, int& zlen) {
     tx = ty = 0;
     zlen = 4;
     switch (n) {
         case 2: tx = ty = 8; zlen = 2; break;
         case 3: tx = ty = 4; zlen = 4; break;
-        case 5:  // FP64 needs twice the registers: smaller work-groups pack better
-            tx = ty = sizeof(T) == 8 ? 2 : 4;
+        case 5:
+            // FP64 holds twice the registers: 2x2 tiles pack best.  FP32 smoothing steps
+            // run fastest on 4x2 tiles, the steps with two inputs per node (PQ) or the
+            // restriction epilogue on 4x4 (measured)
+            if (sizeof(T) == 8) {
+                tx = ty = 2;
+            } else {
+                tx = 4;
+                ty = (mode == BM_CHEB || mode == BM_CHEBDOT) ? 2 : 4;
+            }
             zlen = 4;
             break;
         default: break;
@@ -968,9 +976,9 @@ struct SlabGeom {
 };
 
 template <typename T>
-static SlabGeom slab_geom(const LevelHost& L) {
+static SlabGeom slab_geom(const LevelHost& L, int mode) {
     SlabGeom g;
-    slab_shape<T>(L.n, g.tx, g.ty, g.zlen);
+    slab_shape<T>(L.n, mode, g.tx, g.ty, g.zlen);
     if (!g.tx) return g;
     g.nt0 = (L.E[0] + g.tx - 1) / g.tx;
     g.nt1 = (L.E[1] + g.ty - 1) / g.ty;
@@ -980,12 +988,12 @@ static SlabGeom slab_geom(const LevelHost& L) {
 }
 
 template <typename T>
-int op_blocks(const LevelHost& L) {
-    const SlabGeom g = slab_geom<T>(L);
+int op_blocks(const LevelHost& L, int mode) {
+    const SlabGeom g = slab_geom<T>(L, mode);
     return g.tx ? g.nt0 * g.nt1 * g.nzc : bricks_of(L);
 }
-template int op_blocks<float>(const LevelHost&);
-template int op_blocks<double>(const LevelHost&);
+template int op_blocks<float>(const LevelHost&, int);
+template int op_blocks<double>(const LevelHost&, int);
 
 template <typename T, int N, int TX, int TY>
 static void slab_dispatch(int mode, const SlabArgs<T>& a, int grid, hipStream_t s) {
@@ -1009,7 +1017,7 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
                         const T* u, const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial,
                         int pstride, double cp, double cr, hipStream_t s, const LevelHost* Lc = nullptr,
                         const LevelDev<T>* devc = nullptr, T* fc = nullptr, T* z1c = nullptr, double c0c = 0) {
-    const SlabGeom g = slab_geom<T>(L);
+    const SlabGeom g = slab_geom<T>(L, mode);
     if (!g.tx) return false;
     if (mode == BM_RESTRICT && L.n != 3 && L.n != 5) return false;
     SlabArgs<T> a;
@@ -1034,6 +1042,7 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
     if (grid == 0) return true;
     if (g.tx == 8 && g.ty == 8 && L.n == 2) slab_dispatch<T, 2, 8, 8>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 4 && L.n == 3) slab_dispatch<T, 3, 4, 4>(mode, a, grid, s);
+    else if (g.tx == 4 && g.ty == 2 && L.n == 5) slab_dispatch<T, 5, 4, 2>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 4 && L.n == 5) slab_dispatch<T, 5, 4, 4>(mode, a, grid, s);
     else if (g.tx == 2 && g.ty == 2 && L.n == 5) slab_dispatch<T, 5, 2, 2>(mode, a, grid, s);
     else return false;
