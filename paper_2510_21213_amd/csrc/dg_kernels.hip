@@ -1358,9 +1358,83 @@ void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHo
     fprintf(stderr, "dg: no restriction kernel for %d -> %d\n", Lf.n, Lc.n);
 }
 
+// Prolongation and correction of a degree step, zf += (P x P x P) zc element by
+// element (the coarse and fine levels share the elements).  A work-group
+// takes EPW consecutive elements (of the packed right-hand sides): their coarse
+// values are staged in LDS with coalesced loads, then one thread per fine node
+// column (i, j) of an element contracts along x and y (NC^2 coarse values per
+// coarse z node) and then along z in registers, and updates its NF nodes.
+template <typename T, int NF, int NC>
+__global__ __launch_bounds__(256) void k_prolong_deg(const TransferDev* __restrict__ trp, long long nelem_rhs,
+                                                     long long nelem, const RhsState* st, const T* __restrict__ zc,
+                                                     T* __restrict__ zf) {
+    constexpr int NF2 = NF * NF, NF3 = NF2 * NF, NC3 = NC * NC * NC;
+    constexpr int EPW = 256 / NF2;
+    __shared__ T sc[EPW * NC3];
+    const TransferDev& tr = *trp;
+    auto Pm = [&](int i, int c) -> T {
+        if constexpr (sizeof(T) == 8)
+            return tr.P[i][c];
+        else
+            return tr.Pf[i][c];
+    };
+    const long long e0 = (long long)blockIdx.x * EPW;
+    const int ne = (int)min((long long)EPW, nelem - e0);
+    for (int q = threadIdx.x; q < ne * NC3; q += 256) sc[q] = zc[e0 * NC3 + q];
+    __syncthreads();
+    const int el = threadIdx.x / NF2, col = threadIdx.x % NF2;
+    if (el >= ne) return;
+    const long long e = e0 + el;
+    if (st && !st[e / nelem_rhs].active) return;
+    const int i = col % NF, j = col / NF;
+    T pi[NC], pj[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+        pi[a] = Pm(i, a);
+        pj[a] = Pm(j, a);
+    }
+    T t[NC];
+    const T* c = sc + el * NC3;
+#pragma unroll
+    for (int cz = 0; cz < NC; ++cz) {
+        T acc = 0;
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+            T u = 0;
+#pragma unroll
+            for (int a = 0; a < NC; ++a) u += pi[a] * c[(cz * NC + b) * NC + a];
+            acc += pj[b] * u;
+        }
+        t[cz] = acc;
+    }
+    T* out = zf + e * NF3 + col;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        T v = 0;
+#pragma unroll
+        for (int cz = 0; cz < NC; ++cz) v += Pm(k, cz) * t[cz];
+        out[k * NF2] += v;
+    }
+}
+
 template <typename T>
 void launch_prolong(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st, const T* zc, T* zf,
                     hipStream_t s) {
+    if (!Lf.hcoarse && Lf.E[0] == Lc.E[0] && Lf.E[1] == Lc.E[1] && Lf.E[2] == Lc.E[2]) {
+        const long long nel = (long long)Lf.E[0] * Lf.E[1] * Lf.E[2];
+        const long long tot = nel * nrhs;
+        if (tot == 0) return;
+#define DG_PD(NF, NC)                                                                                          \
+        if (Lf.n == NF && Lc.n == NC) {                                                                        \
+            constexpr int EPW = 256 / (NF * NF);                                                               \
+            hipLaunchKernelGGL((k_prolong_deg<T, NF, NC>), dim3((unsigned)((tot + EPW - 1) / EPW)), dim3(256), \
+                               0, s, Lf.devtr, nel, tot, st, zc, zf);                                          \
+            return;                                                                                            \
+        }
+        DG_PD(5, 3)
+        DG_PD(3, 2)
+#undef DG_PD
+    }
     TransferArgs<T> a = transfer_args<T>(Lf, Lc, nrhs, st);
     a.z = zc; a.zf = zf;
     const int grid = bricks_of(Lf) * nrhs;

@@ -9,6 +9,10 @@ densities) on the 16^3-element, degree-4 mesh of [-8,8]^3, with seeds
 Every step of the training runs in the library's kernels (solves, network
 forward/backward, A-norm loss, Adam); this script only feeds batches.
 
+With --workload large the molecules follow the 32^3-element recipe instead
+(16-32 atoms in [-8,8]^3 on the degree-4 mesh of [-16,16]^3, 5 levels; seeds
+50000+i, held out 90000+i), and --init starts from existing weights.
+
 Writes the weights (dg_net_save format) and a JSON report with the held-out
 evaluation: mean PCG iterations to 1e-8 with and without the guess, and with
 an untrained network of the same architecture as a control.
@@ -72,19 +76,19 @@ def layer_specs(levels, C, cin, cout):
     return specs
 
 
-def evaluate(mesh, net, mols, rtol=1e-8, precisions=("fp32_ir", "fp64")):
+def evaluate(mesh, net, mols, rtol=1e-8, precisions=("fp32_ir", "fp64"), n_levels=4):
     """Mean iterations over the pairs of the given molecules, with and without the guess."""
     out = {}
     for prec in precisions:
-        out[prec] = evaluate_one(mesh, net, mols, rtol, prec)
+        out[prec] = evaluate_one(mesh, net, mols, rtol, prec, n_levels)
     return out
 
 
-def evaluate_one(mesh, net, mols, rtol, precision):
+def evaluate_one(mesh, net, mols, rtol, precision, n_levels=4):
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
     out = {}
     for label, use in (("none", None), ("net", net)):
-        ctx = binding.Context([m], n_levels=4, rtol=rtol, precision=precision)
+        ctx = binding.Context([m], n_levels=n_levels, rtol=rtol, precision=precision)
         xyz, fxyz = ctx.mesh_coords(0)
         if use is not None:
             ctx.attach_guess(use)
@@ -114,31 +118,46 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", type=int, default=2, help="output gradient (dg_net_train_step): 0, 1 or 2")
     ap.add_argument("--finetune", type=int, default=0, help="final epochs with the plain A-norm gradient")
+    ap.add_argument("--workload", default="exchange8", choices=["exchange8", "large"])
+    ap.add_argument("--init", default=None, help="start from these weights instead of a random initialisation")
     args = ap.parse_args()
     torch.cuda.set_device(0)
-    mesh = configs.cube(16, 4, 8.0)
+    if args.workload == "large":
+        mesh, n_levels = configs.cube(32, 4, 16.0), 5
+        train_mol = lambda i: configs.large_molecule(i).orbitals
+        held_mol = lambda i: configs.large_molecule(i, held_out=True).orbitals
+    else:
+        mesh, n_levels = configs.cube(16, 4, 8.0), 4
+        train_mol = lambda i: molecule(10000 + i)
+        held_mol = lambda i: molecule(90000 + i)
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
-    ctx = binding.Context([m], n_levels=4, rtol=1e-10, precision="fp64")
+    ctx = binding.Context([m], n_levels=n_levels, rtol=1e-10, precision="fp64")
     xyz, fxyz = ctx.mesh_coords(0)
     nd = ctx.info[0]["n_dofs"]
     net = binding.Net(args.levels, args.channels, 125, 27)
     rng = np.random.default_rng(args.seed)
-    net.set_params(he_init(net, rng))
+    if args.init:
+        net.load(args.init)
+    else:
+        net.set_params(he_init(net, rng))
 
     t0 = time.time()
-    X, T = [], []
+    X = T = None
+    n = 0
     for i in range(args.molecules):
-        orb = molecule(10000 + i)
+        orb = train_mol(i)
         rho, g = pair_data(ctx, orb, xyz, fxyz)
         npair = len(orb.pairs())
         v, _ = ctx.solve_batch(rho, g, mesh_ids=[0] * npair)
         x, s = net.prepare_input(rho, npair, nd)
-        X.append(x.reshape(npair, nd))
-        T.append((v.reshape(npair, nd) / s[:, None]).contiguous())
+        if X is None:  # filled in place: no concatenated copy of the data set
+            X = torch.empty((args.molecules * npair, nd), dtype=torch.float32, device="cuda")
+            T = torch.empty((args.molecules * npair, nd), dtype=torch.float64, device="cuda")
+        X[n:n + npair] = x.reshape(npair, nd)
+        T[n:n + npair] = v.reshape(npair, nd) / s[:, None]
+        n += npair
+        del rho, g, v, x
         print(f"data: molecule {i + 1}/{args.molecules} ({time.time() - t0:.0f}s)", flush=True)
-    X = torch.cat(X)
-    T = torch.cat(T)
-    n = X.shape[0]
     print(f"data: {n} pairs in {time.time() - t0:.0f}s", flush=True)
 
     hist = []
@@ -163,12 +182,13 @@ def main():
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)
 
-    held = [molecule(90000 + i) for i in range(args.held_out)]
-    ev = evaluate(mesh, net, held)
+    held = [held_mol(i) for i in range(args.held_out)]
+    ev = evaluate(mesh, net, held, n_levels=n_levels)
     control = binding.Net(args.levels, args.channels, 125, 27)
     control.set_params(he_init(control, np.random.default_rng(12345)))
-    ev_control = evaluate(mesh, control, held)
-    report = {"weights": os.path.basename(args.out), "molecules": args.molecules, "pairs": int(n),
+    ev_control = evaluate(mesh, control, held, n_levels=n_levels)
+    report = {"weights": os.path.basename(args.out), "workload": args.workload, "init": args.init,
+              "molecules": args.molecules, "pairs": int(n),
               "mode": args.mode, "finetune_epochs": args.finetune,
               "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "levels": args.levels,
               "channels": args.channels, "loss_history": hist,
