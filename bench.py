@@ -30,11 +30,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="exchange8", choices=["exchange8", "exchange16", "uneven"],
+    ap.add_argument("--config", default="exchange8", choices=["exchange8", "exchange16", "large", "uneven"],
                     help="uneven: 256 densities over 8^3, 12^3 and 16^3 meshes in one interleaved batch")
     ap.add_argument("--arms", default="fp32_ir+learned,fp32_ir,fp64+learned,fp64")
-    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2510_21213_amd", "weights", "guess_16e_p4.bin"))
-    ap.add_argument("--cpu-sample", type=int, default=2, help="pair solves timed on the oracle (0: skip)")
+    ap.add_argument("--weights", default=None,
+                    help="guess network (default: the weights trained for the workload's mesh)")
+    ap.add_argument("--cpu-sample", type=int, default=12, help="pair solves timed on the oracle (0: skip)")
     ap.add_argument("--check-sample", type=int, default=4, help="pairs compared with the exact solve (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run 3 device-to-device copies of this many MiB (HBM counter calibration)")
@@ -63,7 +64,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    wl = configs.exchange8() if args.config == "exchange8" else configs.exchange16()
+    wl = {"exchange8": configs.exchange8, "exchange16": configs.exchange16,
+          "large": lambda: configs.large_molecule(0, held_out=True)}[args.config]()
+    if args.weights is None:
+        name = "guess_32e_p4.bin" if args.config == "large" else "guess_16e_p4.bin"
+        args.weights = os.path.join(ROOT, "paper_2510_21213_amd", "weights", name)
     mesh = wl.meshes[0]
     orb = wl.orbitals
     norb = orb.norb

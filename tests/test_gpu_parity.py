@@ -227,6 +227,9 @@ def test_uneven_batch_three_meshes_matches_oracle_and_per_mesh_solves(gpu_lib):
         axes, _, _, b = oracle_density_problem(meshes[mid], dens[k])
         assert rel_l2_M(axes, meshes[mid], v[offs[k]:offs[k + 1]], fdm.FDM(axes).solve(b)) <= POT_BAR
         assert st[k]["status"] == 0
+    # the converged potentials as initial guesses (gathered like rho): nothing left to do
+    v2, st2 = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)), mesh_ids=ids, x0=_t(v))
+    assert np.array_equal(_n(v2), v) and all(s["iters"] == 0 and s["guess_used"] == 1 for s in st2)
     for mid in range(3):
         ks = [k for k, m in enumerate(ids) if m == mid]
         vm, sm = ctx.solve_batch(_t(np.concatenate([rho[k] for k in ks])), _t(np.concatenate([g[k] for k in ks])),
