@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--arms", default="fp32_ir+learned,fp32_ir,fp64+learned,fp64")
     ap.add_argument("--weights", default=None,
                     help="guess network (default: the weights trained for the workload's mesh)")
+    ap.add_argument("--lanes", type=int, default=2, choices=[1, 2],
+                    help="solver lanes per mesh: 2 solves a batch as two concurrent halves")
     ap.add_argument("--cpu-sample", type=int, default=12, help="pair solves timed on the oracle (0: skip)")
     ap.add_argument("--check-sample", type=int, default=4, help="pairs compared with the exact solve (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -80,7 +82,7 @@ def main():
     for arm in arms:
         prec, _, learned = arm.partition("+")
         ctx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
-                              precision=prec)
+                              precision=prec, lanes=args.lanes)
         if learned:
             if net is None:
                 net = binding.Net(4, 32, 125, 27)
@@ -109,9 +111,10 @@ def main():
         ctx.profile(False)
         if prof["launches"] < 0:
             # the runtime could not time events recorded inside the captured graph: time the
-            # same steps on eager launches instead (same kernels, same inputs)
+            # same steps on eager launches instead (same kernels, same inputs), on one solver
+            # lane so that every timed launch runs alone (two lanes overlap their launches)
             ectx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
-                                   precision=prec, use_graph=0)
+                                   precision=prec, use_graph=0, lanes=1)
             if learned:
                 ectx.attach_guess(net)
             ectx.exchange(phi, g)
@@ -119,7 +122,7 @@ def main():
             for _ in range(args.steps):
                 ectx.exchange(phi, g)
             prof = ectx.profile_read()
-            prof["source"] = "eager launches (graph events not timeable)"
+            prof["source"] = "eager launches on one solver lane (graph events not timeable)"
             ectx.profile(False)
             ectx.close()
         else:
@@ -180,7 +183,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {npairs} pair-density RHS, {mesh.E[0]}^3 elements p={mesh.p} "
                                f"({first_ctx.info[0]['n_dofs']} DOFs/RHS), {wl.n_levels}-level MG-PCG to {wl.rtol}",
-                   "arm": head_arm, "learned_guess": "learned" in head_arm, "parallelism": "single GPU"},
+                   "arm": head_arm, "learned_guess": "learned" in head_arm, "parallelism": "single GPU",
+                   "solver_lanes": args.lanes},
         "arms": arms_out,
         "speedup_vs_plain_fp64": (head["value"] / results["fp64"]["value"]) if "fp64" in results else None,
         "roofline": roofline,
@@ -206,7 +210,7 @@ def main_uneven(args):
     results = {}
     rho = g = None
     for arm in arms:
-        ctx = binding.Context(meshes, n_levels=wl.n_levels, rtol=wl.rtol, precision=arm)
+        ctx = binding.Context(meshes, n_levels=wl.n_levels, rtol=wl.rtol, precision=arm, lanes=args.lanes)
         if rho is None:
             rs, gs = [], []
             coords = [ctx.mesh_coords(m) for m in range(len(meshes))]

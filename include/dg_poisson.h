@@ -101,6 +101,10 @@ typedef struct {
                             solve on this mesh needed (finished right-hand sides are skipped
                             on the device, so replays past convergence change nothing) */
     int use_graph;       /* 1: replay the PCG iteration as a captured HIP graph */
+    int lanes;           /* solver instances per mesh (1 or 2): with 2, a batch of at least
+                            16 right-hand sides of one mesh is solved as two halves on two
+                            streams at once, so that the latency-bound coarse-level phases of
+                            one half overlap the bandwidth-bound phases of the other */
 } dg_opts;
 
 typedef struct {
@@ -115,7 +119,7 @@ typedef struct dg_ctx dg_ctx;
 
 /* Fill *opts with the defaults: automatic levels, degree 5, ratio 20,
  * safety 1.1, 30 Lanczos steps, eps 1/8, rtol 1e-8, 500 iterations, FP64,
- * inner_rtol 1e-4, max_outer 8, check_every 2, use_graph 1. */
+ * inner_rtol 1e-4, max_outer 8, check_every 2, use_graph 1, lanes 2. */
 void dg_opts_default(dg_opts* opts);
 
 /* Build the level hierarchy, operator tables, coarsest-grid eigendata and

@@ -16,6 +16,7 @@
 #include <exception>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -126,10 +127,16 @@ struct dg_ctx {
         // iterations the k-th PCG run of the last solve needed (per precision): the next
         // solve replays that many before its first host check
         std::vector<int> pred[2];
+        // timing events of eager launches driven by this solver instance
+        std::vector<hipEvent_t> pev;
+        size_t pused = 0;
+        // a second solver instance of a mesh (lane) shares the level tables of the first
+        bool owns_tables = true;
         double *grho = nullptr, *gface = nullptr, *gx0 = nullptr, *gv = nullptr;
         int cap_g = 0;
     };
     std::vector<Mesh> meshes;
+    std::vector<Mesh> twins;       // second solver lane of each mesh (empty with one lane)
     dg_net* guess = nullptr;       // learned initial guess (not owned)
     double* g_x0 = nullptr;        // guess work space
     double* g_rho = nullptr;
@@ -142,6 +149,7 @@ struct dg_ctx {
         long long launches = 0;
         double seconds = 0.0, bytes = 0.0;
         bool failed = false;
+        std::mutex mu;               // solver lanes add their timings from their own threads
     } prof;
     hipEvent_t ev_ready = nullptr;           // multi-mesh batches: inputs assembled
     long long* segtab = nullptr;             // gather / scatter offset tables (device)
@@ -253,6 +261,7 @@ void prof_mark(hipStream_t s) {
 // Called after the stream has been synchronised: add up the timed launches.
 void prof_sum(const std::vector<hipEvent_t>& ev, size_t used) {
     auto& P = *g_prof;
+    std::lock_guard<std::mutex> lock(P.mu);
     for (size_t i = 0; i + 1 < used; i += 2) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) {
@@ -419,16 +428,15 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         }
     } else {
         const int every = std::max(1, ctx->opts.check_every);
-        auto& P = ctx->prof;
         while (it < maxit) {
             if (timed) {
-                P.used = 0;
-                g_sink = {&P.ev, &P.used};
+                M.pused = 0;
+                g_sink = {&M.pev, &M.pused};
             }
             for (int c = 0; c < every && it < maxit; ++c, ++it) pcg_iteration<T>(M, W, nrhs, st, it & 1, s);
             HIPCHK(hipGetLastError());
             read_state(M, st, nrhs, s);
-            if (timed) prof_sum(P.ev, P.used);
+            if (timed) prof_sum(M.pev, M.pused);
             bool any = false;
             for (int i = 0; i < nrhs; ++i) any |= M.st_host[i].active != 0;
             if (!any) break;
@@ -448,6 +456,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         const double per_cycle = (m >= 2 ? 3.0 + 4.0 * (m - 2) : 0.0) + 3.0 + 4.0 * (m - 1);
         long long cycles = 0;
         for (int i = 0; i < nrhs; ++i) cycles += M.st_host[i].iters;
+        std::lock_guard<std::mutex> lock(g_prof->mu);
         g_prof->bytes += per_cycle * (double)cycles * (double)L0.ndof * sizeof(T);
     }
 }
@@ -571,6 +580,92 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             r.status = (r.rel_residual <= o.rtol * 1.01) ? DG_OK : DG_WARN_NOT_CONVERGED;
         }
     }
+}
+
+// One solve on one solver lane: cnt right-hand sides b (already assembled) -> v.
+struct Job {
+    Mesh* M;
+    int cnt;
+    const double* b;
+    const double* x0;
+    double* v;
+    dg_rhs_stats* stats;
+    const std::vector<int>* used;  // learned-guess flags, or null
+};
+
+constexpr int kLaneMin = 16;  // smallest batch of one mesh that is split over two lanes
+
+// Sizes the work space of a lane for cnt right-hand sides (on the calling thread, so
+// that the solves allocate nothing).
+void prepare_lane(dg_ctx* ctx, Mesh& M, int cnt) {
+    const bool fp32 = ctx->opts.precision == DG_PREC_FP32_IR;
+    ensure_b(M, cnt, fp32);
+    ensure_state(M, cnt);
+    if (fp32)
+        ensure_work<float>(M, M.w32, cnt);
+    else
+        ensure_work<double>(M, M.w64, cnt);
+}
+
+// Appends the jobs of one mesh's batch: one job, or two halves on the mesh's two
+// lanes.  `used` (may be null) holds the guess flags of the batch; its halves are
+// kept in `keep`.
+void add_jobs(dg_ctx* ctx, int mesh_id, int cnt, const double* b, const double* x0, double* v, dg_rhs_stats* stats,
+              const std::vector<int>* used, std::vector<Job>& jobs, std::vector<std::vector<int>>& keep) {
+    Mesh& M = ctx->meshes[mesh_id];
+    const long long n0 = M.lv[0].ndof;
+    if (ctx->twins.empty() || cnt < kLaneMin) {
+        prepare_lane(ctx, M, cnt);
+        jobs.push_back({&M, cnt, b, x0, v, stats, used});
+        return;
+    }
+    Mesh& T = ctx->twins[mesh_id];
+    const int h = cnt / 2;
+    const std::vector<int>* u0 = nullptr;
+    const std::vector<int>* u1 = nullptr;
+    if (used) {
+        keep.emplace_back(used->begin(), used->begin() + h);
+        u0 = &keep.back();
+        keep.emplace_back(used->begin() + h, used->end());
+        u1 = &keep.back();
+    }
+    prepare_lane(ctx, M, h);
+    prepare_lane(ctx, T, cnt - h);
+    jobs.push_back({&M, h, b, x0, v, stats, u0});
+    jobs.push_back({&T, cnt - h, b + h * n0, x0 ? x0 + h * n0 : nullptr, v + h * n0, stats ? stats + h : nullptr, u1});
+}
+
+// Runs the jobs: a single one on the caller's stream; several at once, each on its
+// lane's stream from its own host thread (the host waits of one overlap the kernels of
+// the others).  Results do not depend on how the jobs are run.
+void run_jobs(dg_ctx* ctx, std::vector<Job>& jobs, hipStream_t stream) {
+    if (jobs.size() == 1) {
+        auto& J = jobs[0];
+        solve_group(ctx, *J.M, J.cnt, J.b, J.x0, J.v, J.stats, stream, J.used);
+        return;
+    }
+    HIPCHK(hipEventRecord(ctx->ev_ready, stream));
+    dg_ctx::Prof* prof = g_prof;
+    std::vector<std::exception_ptr> err(jobs.size());
+    std::vector<std::thread> th;
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        th.emplace_back([&, k] {
+            try {
+                g_prof = prof;
+                HIPCHK(hipSetDevice(ctx->device));
+                auto& J = jobs[k];
+                HIPCHK(hipStreamWaitEvent(J.M->stream, ctx->ev_ready, 0));
+                solve_group(ctx, *J.M, J.cnt, J.b, J.x0, J.v, J.stats, J.M->stream, J.used);
+                HIPCHK(hipEventRecord(J.M->ev_done, J.M->stream));
+            } catch (...) {
+                err[k] = std::current_exception();
+            }
+        });
+    }
+    for (auto& t : th) t.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+    for (auto& J : jobs) HIPCHK(hipStreamWaitEvent(stream, J.M->ev_done, 0));
 }
 
 std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho, const double* b, hipStream_t s) {
@@ -814,6 +909,7 @@ void dg_opts_default(dg_opts* o) {
     o->inner_rtol = 1e-4;
     o->max_outer = 8;
     o->check_every = 2;
+    o->lanes = 2;
     o->use_graph = 1;
 }
 
@@ -843,7 +939,7 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
         const auto& o = ctx->opts;
         if (o.cheb_degree < 1 || o.cheb_ratio <= 1.0 || o.cheb_safety < 1.0 || o.lanczos_steps < 2 ||
             o.penalty_eps <= 0 || o.rtol <= 0 || o.max_iter < 1 || o.max_outer < 1 || o.inner_rtol <= 0 ||
-            o.inner_rtol >= 1)
+            o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 2)
             throw ArgError("invalid solver options");
         HIPCHK(hipGetDevice(&ctx->device));
         HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
@@ -857,6 +953,24 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
             HIPCHK(hipStreamCreateWithFlags(&ctx->meshes[i].stream, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&ctx->meshes[i].ev_done, hipEventDisableTiming));
         }
+        if (o.lanes == 2) {
+            // the second lane of a mesh: the same (read-only) level tables, its own work space
+            ctx->twins.resize(n_meshes);
+            for (int i = 0; i < n_meshes; ++i) {
+                const Mesh& M = ctx->meshes[i];
+                Mesh& T = ctx->twins[i];
+                T.mesh = M.mesh;
+                T.lv = M.lv;
+                T.cheb = M.cheb;
+                T.coarse = M.coarse;
+                T.dcoarse = M.dcoarse;
+                T.pstride = M.pstride;
+                T.nface = M.nface;
+                T.owns_tables = false;
+                HIPCHK(hipStreamCreateWithFlags(&T.stream, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&T.ev_done, hipEventDisableTiming));
+            }
+        }
         HIPCHK(hipDeviceSynchronize());
         *out = ctx.release();
     });
@@ -865,13 +979,17 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
 void dg_poisson_destroy(dg_ctx* ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
+    for (auto& M : ctx->twins) ctx->meshes.push_back(std::move(M));  // lanes are freed like meshes
+    ctx->twins.clear();
     for (auto& M : ctx->meshes) {
-        for (auto& L : M.lv) {
-            dfree(L.dev64);
-            dfree(L.dev32);
-            dfree(L.devtr);
+        if (M.owns_tables) {
+            for (auto& L : M.lv) {
+                dfree(L.dev64);
+                dfree(L.dev32);
+                dfree(L.devtr);
+            }
+            dfree(M.dcoarse);
         }
-        dfree(M.dcoarse);
         M.w64.release();
         M.w32.release();
         dfree(M.b);
@@ -886,6 +1004,7 @@ void dg_poisson_destroy(dg_ctx* ctx) {
         dfree(M.gv);
         if (M.ev_done) (void)hipEventDestroy(M.ev_done);
         if (M.stream) (void)hipStreamDestroy(M.stream);
+        for (auto e : M.pev) (void)hipEventDestroy(e);
     }
     for (auto e : ctx->prof.ev) (void)hipEventDestroy(e);
     for (auto& M : ctx->meshes) {
@@ -1055,13 +1174,7 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
             Mesh& M = ctx->meshes[P.m];
             const long long n0 = M.lv[0].ndof;
             const int cnt = P.cnt;
-            // every buffer is sized here, on this thread: the solves below allocate nothing
-            ensure_b(M, cnt, fp32);
-            ensure_state(M, cnt);
-            if (fp32)
-                ensure_work<float>(M, M.w32, cnt);
-            else
-                ensure_work<double>(M, M.w64, cnt);
+            ensure_b(M, cnt, fp32);  // the assembled right-hand sides of the whole part
             const bool want_guess = !x0 && ctx->guess;
             if ((!P.contig || want_guess) && M.cap_g < cnt) {
                 dfree(M.grho);
@@ -1106,36 +1219,14 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
                 P.guessed = true;
             }
         }
-        if (parts.size() == 1) {
-            auto& P = parts[0];
-            solve_group(ctx, ctx->meshes[P.m], P.cnt, ctx->meshes[P.m].b, P.x0, P.v, P.stats.data(), stream,
-                        P.guessed ? &P.used : nullptr);
-        } else {
-            // meshes are independent: each is solved on its own stream by its own host
-            // thread, so that the host waits of one overlap the kernels of the others
-            HIPCHK(hipEventRecord(ctx->ev_ready, stream));
-            std::vector<std::exception_ptr> err(parts.size());
-            std::vector<std::thread> th;
-            for (size_t k = 0; k < parts.size(); ++k) {
-                th.emplace_back([&, k] {
-                    try {
-                        HIPCHK(hipSetDevice(ctx->device));
-                        auto& P = parts[k];
-                        Mesh& M = ctx->meshes[P.m];
-                        HIPCHK(hipStreamWaitEvent(M.stream, ctx->ev_ready, 0));
-                        solve_group(ctx, M, P.cnt, M.b, P.x0, P.v, P.stats.data(), M.stream,
-                                    P.guessed ? &P.used : nullptr);
-                        HIPCHK(hipEventRecord(M.ev_done, M.stream));
-                    } catch (...) {
-                        err[k] = std::current_exception();
-                    }
-                });
-            }
-            for (auto& t : th) t.join();
-            for (auto& e : err)
-                if (e) std::rethrow_exception(e);
-            for (auto& P : parts) HIPCHK(hipStreamWaitEvent(stream, ctx->meshes[P.m].ev_done, 0));
-        }
+        // every buffer is sized here, on this thread: the solves allocate nothing
+        std::vector<Job> jobs;
+        std::vector<std::vector<int>> keep;
+        keep.reserve(2 * parts.size());
+        for (auto& P : parts)
+            add_jobs(ctx, P.m, P.cnt, ctx->meshes[P.m].b, P.x0, P.v, P.stats.data(), P.guessed ? &P.used : nullptr,
+                     jobs, keep);
+        run_jobs(ctx, jobs, stream);
         for (auto& P : parts) {
             if (!P.contig) {
                 const long long* t = ctx->segtab + P.tab;
@@ -1190,6 +1281,7 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
         ensure_b(M, npairs, ctx->opts.precision == DG_PREC_FP32_IR);
         dg::launch_rhs(M.lv[0], M.lv[0].dev64, npairs, nullptr, phi, ctx->xpairs, ctx->xpairs + npairs, g_pairs,
                        M.nface, M.b, stream);
+        std::vector<int> used;
         if (ctx->guess) {
             if (ctx->g_cap < n0 * npairs) {
                 dfree(ctx->g_x0);
@@ -1199,11 +1291,16 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
                 ctx->g_cap = n0 * npairs;
             }
             dg::launch_pair_products(n0, npairs, phi, ctx->xpairs, ctx->xpairs + npairs, ctx->g_rho, stream);
-            std::vector<int> used = learned_guess(ctx, M, npairs, ctx->g_rho, M.b, stream);
-            solve_group(ctx, M, npairs, M.b, ctx->g_x0, v, stats, stream, &used);
-        } else {
-            solve_group(ctx, M, npairs, M.b, nullptr, v, stats, stream);
+            used = learned_guess(ctx, M, npairs, ctx->g_rho, M.b, stream);
         }
+        std::vector<dg_rhs_stats> st_all(npairs);
+        std::vector<Job> jobs;
+        std::vector<std::vector<int>> keep;
+        keep.reserve(2);
+        add_jobs(ctx, mesh_id, npairs, M.b, ctx->guess ? ctx->g_x0 : nullptr, v, st_all.data(),
+                 ctx->guess ? &used : nullptr, jobs, keep);
+        run_jobs(ctx, jobs, stream);
+        if (stats) std::copy(st_all.begin(), st_all.end(), stats);
         const int nblk = (int)((n0 + 255) / 256);
         if (ctx->xpart_cap < (long long)npairs * nblk) {
             dfree(ctx->xpart);

@@ -241,6 +241,23 @@ def test_uneven_batch_three_meshes_matches_oracle_and_per_mesh_solves(gpu_lib):
             assert sm[q]["iters"] == st[k]["iters"]
 
 
+def test_two_solver_lanes_match_one_lane_bitwise(gpu_lib):
+    """A batch of 20 right-hand sides of one mesh is split over two concurrent solver lanes
+    (default) or solved as one group (lanes=1): the potentials and iteration counts agree
+    bit for bit, in both precisions."""
+    wl = configs.scaled(4, 4, 20, seed=41)
+    mesh = wl.meshes[0]
+    m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
+    for prec in ("fp64", "fp32_ir"):
+        out = []
+        for lanes in (1, 2):
+            ctx = gpu_lib.Context([m], precision=prec, lanes=lanes)
+            rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+            v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
+            out.append((_n(v), [s["iters"] for s in st]))
+        assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1], prec
+
+
 def test_zero_and_empty_right_hand_sides(gpu_lib):
     mesh = configs.Mesh((4, 4, 4), 2, (-1.0,) * 3, (1.0,) * 3)
     ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)])
