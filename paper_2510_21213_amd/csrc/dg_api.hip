@@ -759,6 +759,16 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
             }
             f.sig = (float)r.sig;
             for (int d = 0; d < 3; ++d) f.scale[d] = (float)r.scale[d];
+            for (int i = 0; i < dg::NMAX / 2; ++i) {
+                for (int l = 0; l < dg::NMAX / 2; ++l) {
+                    f.Pe[i][l] = (float)r.Pe[i][l];
+                    f.Po[i][l] = (float)r.Po[i][l];
+                }
+                f.qe[i] = (float)r.qe[i];
+                f.qo[i] = (float)r.qo[i];
+            }
+            for (int i = 0; i <= dg::NMAX / 2; ++i) f.Bm[i] = (float)r.Bm[i];
+            f.qm = (float)r.qm;
         }
         M.lv.push_back(L);
     }

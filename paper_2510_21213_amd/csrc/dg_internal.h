@@ -47,6 +47,12 @@ struct RefDev {
     T w[NMAX];
     T sig;
     T scale[3];
+    // Even/odd form of the block and of the face coupling (H = n/2 mirrored pairs
+    // (i, p-i)): Pe/Po = (B_il +- B_i,p-l)/2, Bm[i] = B_iH (odd n, i <= H),
+    // qe/qo = (aR_i -+ aL_i)/4, qm = aR_H/2.
+    T Pe[NMAX / 2][NMAX / 2], Po[NMAX / 2][NMAX / 2];
+    T Bm[NMAX / 2 + 1];
+    T qe[NMAX / 2], qo[NMAX / 2], qm;
 };
 
 template <typename T>

@@ -229,6 +229,19 @@ void build_ref(int p, double eps, const double h[3], RefDev<double>& r) {
             v += -0.5 * (eRi * r.aR[j] + r.aR[i] * eRj) + sig * eRi * eRj;
             r.B[i][j] = v;
         }
+    const int H = n / 2;
+    for (int i = 0; i < H; ++i) {
+        for (int l = 0; l < H; ++l) {
+            r.Pe[i][l] = 0.5 * (r.B[i][l] + r.B[i][n - 1 - l]);
+            r.Po[i][l] = 0.5 * (r.B[i][l] - r.B[i][n - 1 - l]);
+        }
+        r.qe[i] = 0.25 * (r.aR[i] - r.aL[i]);
+        r.qo[i] = 0.25 * (r.aR[i] + r.aL[i]);
+    }
+    if (n & 1) {
+        for (int i = 0; i <= H; ++i) r.Bm[i] = r.B[i][H];
+        r.qm = 0.5 * r.aR[H];
+    }
     const double J[3] = {0.5 * h[0], 0.5 * h[1], 0.5 * h[2]};
     r.scale[0] = J[1] * J[2] / J[0];
     r.scale[1] = J[0] * J[2] / J[1];
