@@ -37,11 +37,17 @@ def parse():
                     help="guess network (default: the weights trained for the workload's mesh)")
     ap.add_argument("--lanes", type=int, default=2, choices=[1, 2],
                     help="solver lanes per mesh: 2 solves a batch as two concurrent halves")
+    ap.add_argument("--cheb-degree", type=int, default=None, help="smoothing steps (default: the library's)")
+    ap.add_argument("--cheb-ratio", type=float, default=None, help="smoothing interval ratio (default: the library's)")
+    ap.add_argument("--inner-rtol", type=float, default=None, help="inner FP32 tolerance (default: the library's)")
     ap.add_argument("--cpu-sample", type=int, default=12, help="pair solves timed on the oracle (0: skip)")
     ap.add_argument("--check-sample", type=int, default=4, help="pairs compared with the exact solve (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run 3 device-to-device copies of this many MiB (HBM counter calibration)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    args.solver_opts = {k: v for k, v in (("cheb_degree", args.cheb_degree), ("cheb_ratio", args.cheb_ratio),
+                                          ("inner_rtol", args.inner_rtol)) if v is not None}
+    return args
 
 
 def main():
@@ -82,7 +88,7 @@ def main():
     for arm in arms:
         prec, _, learned = arm.partition("+")
         ctx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
-                              precision=prec, lanes=args.lanes)
+                              precision=prec, lanes=args.lanes, **args.solver_opts)
         if learned:
             if net is None:
                 net = binding.Net(4, 32, 125, 27)
@@ -114,7 +120,7 @@ def main():
             # same steps on eager launches instead (same kernels, same inputs), on one solver
             # lane so that every timed launch runs alone (two lanes overlap their launches)
             ectx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
-                                   precision=prec, use_graph=0, lanes=1)
+                                   precision=prec, use_graph=0, lanes=1, **args.solver_opts)
             if learned:
                 ectx.attach_guess(net)
             ectx.exchange(phi, g)
@@ -210,7 +216,7 @@ def main_uneven(args):
     results = {}
     rho = g = None
     for arm in arms:
-        ctx = binding.Context(meshes, n_levels=wl.n_levels, rtol=wl.rtol, precision=arm, lanes=args.lanes)
+        ctx = binding.Context(meshes, n_levels=wl.n_levels, rtol=wl.rtol, precision=arm, lanes=args.lanes, **args.solver_opts)
         if rho is None:
             rs, gs = [], []
             coords = [ctx.mesh_coords(m) for m in range(len(meshes))]

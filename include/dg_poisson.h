@@ -117,9 +117,9 @@ typedef struct {
 
 typedef struct dg_ctx dg_ctx;
 
-/* Fill *opts with the defaults: automatic levels, degree 5, ratio 20,
+/* Fill *opts with the defaults: automatic levels, degree 6, ratio 60,
  * safety 1.1, 30 Lanczos steps, eps 1/8, rtol 1e-8, 500 iterations, FP64,
- * inner_rtol 1e-4, max_outer 8, check_every 2, use_graph 1, lanes 2. */
+ * inner_rtol 3e-4, max_outer 8, check_every 2, use_graph 1, lanes 2. */
 void dg_opts_default(dg_opts* opts);
 
 /* Build the level hierarchy, operator tables, coarsest-grid eigendata and

@@ -108,7 +108,7 @@ class Level:
 class Hierarchy:
     """Levels, transfers, smoother parameters and the V-cycle."""
 
-    def __init__(self, E, p, lo, hi, n_levels=None, degree=5, ratio=20.0, safety=1.1,
+    def __init__(self, E, p, lo, hi, n_levels=None, degree=6, ratio=60.0, safety=1.1,
                  lanczos_steps=30, max_coarse_nodes=16, eps=_sipdg.PENALTY_EPS):
         self.specs = hierarchy(E, p, n_levels, max_coarse_nodes)
         self.levels = [Level(Es, ps, lo, hi, eps) for Es, ps in self.specs]

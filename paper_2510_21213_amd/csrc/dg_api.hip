@@ -908,15 +908,15 @@ extern "C" {
 void dg_opts_default(dg_opts* o) {
     if (!o) return;
     o->n_levels = 0;
-    o->cheb_degree = 5;
-    o->cheb_ratio = 20.0;
+    o->cheb_degree = 6;
+    o->cheb_ratio = 60.0;
     o->cheb_safety = 1.1;
     o->lanczos_steps = 30;
     o->penalty_eps = 0.125;
     o->rtol = 1e-8;
     o->max_iter = 500;
     o->precision = DG_PREC_FP64;
-    o->inner_rtol = 1e-4;
+    o->inner_rtol = 3e-4;
     o->max_outer = 8;
     o->check_every = 2;
     o->lanes = 2;

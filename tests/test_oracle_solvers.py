@@ -69,7 +69,7 @@ def test_lanczos_brackets_largest_eigenvalue():
     lo, hi = H.lam[0]
     ritz = hi / 1.1
     assert ritz <= lmax * (1 + 1e-12) and ritz >= 0.97 * lmax
-    assert abs(hi / lo - 20.0) < 1e-12
+    assert abs(hi / lo - 60.0) < 1e-12
 
 
 def test_chebyshev_smoother_is_symmetric():
