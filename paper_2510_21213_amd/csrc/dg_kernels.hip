@@ -663,6 +663,9 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr int RS = NX + 2 * N, PS = RS * (NY + 2 * N);  // LDS staging: row and plane strides
     constexpr int OR = NX, OP = OR * NY;                     // LDS x / y terms: row and plane strides
     constexpr int NP = NT / 2;                               // element pairs per axis and layer
+    // first thread of the y pairs: the next wave boundary when the work-group still holds all
+    // y pairs from there, so that no wave computes both an x and a y pair row
+    constexpr int YB = ((NP + 63) / 64) * 64 + NP <= WG ? ((NP + 63) / 64) * 64 : NP;
     constexpr int NH = 2 * (TX + TY);                        // halo elements per layer
     constexpr int HS = (NH + TX * TY - 1) / (TX * TY);       // halo columns per thread
     constexpr uint32_t SZ = sizeof(T);
@@ -754,8 +757,8 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
         hoff[s] = ((uint32_t)((hy * E0 + hx) * N3 + j * N + i)) * SZ;
         hsu[s] = Ye * RS + Xe;
     }
-    // pair role: x pairs for t < NP, y pairs for NP <= t < NT
-    const bool isx = t < NP;
+    // pair role: x pairs for t < NP, y pairs for YB <= t < YB + NP
+    const bool isx = t < NP, isy = t >= YB && t < YB + NP;
     int pb, ob, pe;
     bool pok;
     T psc;
@@ -767,9 +770,9 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
         ob = kr * OP + Yr * OR + 2 * pa * N;
         psc = R.scale[0] * R.w[Yr % N] * R.w[kr];
     } else {
-        const int q = min(t, NT - 1) - NP, pa = q % (TY / 2), col = q / (TY / 2), Xc = col % NX, kr = col / NX;
+        const int q = min(max(t - YB, 0), NP - 1), pa = q % (TY / 2), col = q / (TY / 2), Xc = col % NX, kr = col / NX;
         pe = ty0 + 2 * pa;
-        pok = tact && pe < E1 && tx0 + Xc / N < E0;
+        pok = isy && pe < E1 && tx0 + Xc / N < E0;
         pb = kr * PS + 2 * pa * N * RS + Xc + N;
         ob = N * OP + kr * OP + 2 * pa * N * OR + Xc;
         psc = R.scale[1] * R.w[Xc % N] * R.w[kr];
