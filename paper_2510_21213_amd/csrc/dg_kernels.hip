@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <stdexcept>
 
 #include "dg_kernels.h"
 
@@ -64,6 +65,8 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 constexpr int wg_of(int nt) { return ((nt + 63) / 64) * 64; }
+// element layers per z chunk of the slab kernel, at most (its z loop is unrolled over them)
+constexpr int slab_zmax(int n) { return n == 2 ? 2 : 4; }
 
 template <int N>
 constexpr int be_of() { return N <= 3 ? 4 : (N <= 6 ? 2 : 1); }
@@ -790,14 +793,21 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
 #pragma unroll
     for (int s = 0; s < HS; ++s) load_col<T, N, MODE>(hal[s], ru, ru2, hoff[s], (uint32_t)ezb * lstride, beta);
     if (ezb + 1 < E2) load_col<T, N, MODE>(nxt, ru, ru2, coff, (uint32_t)(ezb + 1) * lstride, beta);
-    T crD[N];  // cr / D for the nodes of an interior layer
+    // cr / D for the nodes of an interior layer, and for the bottom / top node of a boundary layer
+    T crD[N], crD0 = 0, crDN = 0;
     if constexpr (IS_CHEB) {
 #pragma unroll
         for (int k = 0; k < N; ++k) crD[k] = a.cr * recip(P1 * R.w[k] + P2 * R.B[k][k]);
+        crD0 = a.cr * recip(P1 * R.w[0] + P2 * (R.B[0][0] + R.aL[0]));
+        crDN = a.cr * recip(P1 * R.w[N - 1] + P2 * (R.B[N - 1][N - 1] - R.aR[N - 1]));
     }
 
     double dot = 0.0;
-    for (int ez = ezb; ez < eze; ++ez) {
+    constexpr int ZMAX = slab_zmax(N);  // longest chunk (slab_shape)
+#pragma unroll
+    for (int zq = 0; zq < ZMAX; ++zq) {
+        const int ez = ezb + zq;
+        if (ez >= eze) break;
         const uint32_t soff = (uint32_t)ez * lstride;
         // stage this layer
         if (tact) {
@@ -869,7 +879,6 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
             for (int k = 0; k < N; ++k) rr[k] = 0;
         }
         if (colok) {
-            const bool zb = ez == 0 || ez == E2 - 1;
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const T y = zacc[k] * P2 + sxy[k * OP + so_own] + sxy[N * OP + k * OP + so_own];
@@ -882,12 +891,8 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                     if constexpr (MODE == BM_RESIDDOT) dot += (double)r * (double)r;
                 } else if constexpr (IS_CHEB) {
                     T cd = crD[k];
-                    if (zb) {
-                        T bdz = R.B[k][k];
-                        if (ez == 0 && k == 0) bdz += R.aL[0];
-                        if (ez == E2 - 1 && k == N - 1) bdz -= R.aR[N - 1];
-                        cd = a.cr * recip(P1 * R.w[k] + P2 * bdz);
-                    }
+                    if (k == 0 && ez == 0) cd = crD0;
+                    if (k == N - 1 && ez == E2 - 1) cd = crDN;
                     const T uz = cur[k];
                     const T zn = uz + a.cp * (uz - zpcol[k]) + cd * (fcol[k] - y);
                     bstore(zn, ro, coff, so);
@@ -1069,6 +1074,8 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
     a.cr = (T)cr;
     const int grid = g.nt0 * g.nt1 * g.nzc * nrhs;
     if (grid == 0) return true;
+    // the kernel unrolls its z loop over at most slab_zmax(n) layers
+    if (g.zlen > slab_zmax(L.n)) throw std::logic_error("slab chunk longer than the kernel's z loop");
     if (g.tx == 8 && g.ty == 8 && L.n == 2) slab_dispatch<T, 2, 8, 8>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 4 && L.n == 3) slab_dispatch<T, 3, 4, 4>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 2 && L.n == 5) slab_dispatch<T, 5, 4, 2>(mode, a, grid, s);
