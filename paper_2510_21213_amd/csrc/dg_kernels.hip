@@ -990,14 +990,14 @@ static void slab_shape(int n, int mode, int& tx, int& ty, int& zlen) {
         case 2: tx = ty = 8; zlen = 2; break;
         case 3: tx = ty = 4; zlen = 4; break;
         case 5:
-            // FP64 holds twice the registers: 2x2 tiles pack best.  FP32 smoothing steps
-            // run fastest on 4x2 tiles, the steps with two inputs per node (PQ) or the
-            // restriction epilogue on 4x4 (measured)
+            // FP64 holds twice the registers: 2x2 tiles pack best.  FP32 smoothing steps and
+            // the residual-restriction run fastest on 4x2 tiles, the step with two inputs per
+            // node (PQ) on 4x4 (measured)
             if (sizeof(T) == 8) {
                 tx = ty = 2;
             } else {
                 tx = 4;
-                ty = (mode == BM_CHEB || mode == BM_CHEBDOT) ? 2 : 4;
+                ty = (mode == BM_CHEB || mode == BM_CHEBDOT || mode == BM_RESTRICT) ? 2 : 4;
             }
             zlen = 4;
             break;
