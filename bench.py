@@ -30,9 +30,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="exchange8", choices=["exchange8", "exchange16", "large", "uneven"],
-                    help="uneven: 256 densities over 8^3, 12^3 and 16^3 meshes in one interleaved batch")
-    ap.add_argument("--arms", default="fp32_ir+learned,fp32_ir,fp64+learned,fp64")
+    ap.add_argument("--config", default="exchange8", choices=["exchange8", "exchange16", "large", "uneven", "single"],
+                    help="uneven: 256 densities over 8^3, 12^3 and 16^3 meshes in one interleaved batch; "
+                         "single: one two-Gaussian density on 4^3 elements p=3 (latency-bound)")
+    ap.add_argument("--arms", default="fp32_ir+learned,fp32_ir,fp64+learned,fp64",
+                    help="precision fp32_ir or fp64, optionally +learned (trained guess) or +untrained "
+                         "(the same network with random weights, a control)")
     ap.add_argument("--weights", default=None,
                     help="guess network (default: the weights trained for the workload's mesh)")
     ap.add_argument("--lanes", type=int, default=2, choices=[1, 2],
@@ -64,6 +67,8 @@ def main():
     torch.cuda.set_device(0)
     if args.config == "uneven":
         return main_uneven(args)
+    if args.config == "single":
+        return main_single(args)
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -87,13 +92,21 @@ def main():
     net = None
     for arm in arms:
         prec, _, learned = arm.partition("+")
+        if learned not in ("", "learned", "untrained"):
+            raise SystemExit(f"unknown arm {arm}")
         ctx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
                               precision=prec, lanes=args.lanes, **args.solver_opts)
-        if learned:
+        if learned == "learned":
             if net is None:
                 net = binding.Net(4, 32, 125, 27)
                 net.load(args.weights)
             ctx.attach_guess(net)
+        elif learned == "untrained":
+            # control: the same architecture with random (He) weights, as in the training script
+            from paper_2510_21213_amd.train_guess import he_init
+            control = binding.Net(4, 32, 125, 27)
+            control.set_params(he_init(control, np.random.default_rng(12345)))
+            ctx.attach_guess(control)
         if first_ctx is None:
             xyz, fxyz = ctx.mesh_coords(0)
             phi = torch.as_tensor(orb.values(xyz[0], xyz[1], xyz[2]).reshape(-1)).cuda()
@@ -121,8 +134,10 @@ def main():
             # lane so that every timed launch runs alone (two lanes overlap their launches)
             ectx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
                                    precision=prec, use_graph=0, lanes=1, **args.solver_opts)
-            if learned:
+            if learned == "learned":
                 ectx.attach_guess(net)
+            elif learned == "untrained":
+                ectx.attach_guess(control)
             ectx.exchange(phi, g)
             ectx.profile(True)
             for _ in range(args.steps):
@@ -297,6 +312,86 @@ def main_uneven(args):
     print(json.dumps(line))
 
 
+def main_single(args):
+    """One right-hand side on the 4^3-element, p = 3 mesh (4,096 nodes, 2 levels, tolerance 1e-10):
+    the vectors stay in cache, so the solve is bound by launch latency; reported as us per solve."""
+    import numpy as np
+    import torch
+
+    from paper_2510_21213_amd import binding
+    from workloads import configs
+
+    wl = configs.single()
+    mesh = wl.meshes[0]
+    d = wl.batch.densities[0]
+    arms = [a for a in args.arms.split(",") if a and "learned" not in a] or ["fp64"]
+    results = {}
+    for arm in arms:
+        ctx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
+                              precision=arm, **args.solver_opts)
+        xyz, fxyz = ctx.mesh_coords(0)
+        rho = torch.as_tensor(d.density(xyz[0], xyz[1], xyz[2])).cuda()
+        g = torch.as_tensor(d.potential(fxyz[0], fxyz[1], fxyz[2])).cuda()
+        for _ in range(args.warmup):
+            ctx.solve_batch(rho, g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            v, st = ctx.solve_batch(rho, g)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        results[arm] = {"value": 1.0 / dt, "us_per_solve": 1e6 * dt, "iters": st[0]["iters"],
+                        "outer_iters": st[0]["outer_iters"], "rel_residual": st[0]["rel_residual"], "v": v}
+    check = cpu = None
+    if args.check_sample > 0 or args.cpu_sample > 0:
+        from oracle import fdm, layout, mg, pcg, sipdg
+        axes = sipdg.make_axes(mesh.E, mesh.p, mesh.lo, mesh.hi)
+        X, Y, Z = np.broadcast_arrays(*sipdg.node_grid(axes))
+        fx, fy, fz = (layout.boundary_faces_of(A) for A in (X, Y, Z))
+        b = sipdg.rhs(axes, d.density(X, Y, Z), [d.potential(fx[f], fy[f], fz[f]) for f in range(6)])
+        M = sipdg.mass(axes)
+        ref = fdm.FDM(axes).solve(b)
+        cont = d.potential(X, Y, Z)                   # the full-space potential the discretisation approximates
+
+        def err(a, r):
+            return float(np.sqrt(np.sum(M * (a - r) ** 2) / np.sum(M * r ** 2)))
+        check = {arm: {"rel_L2_err_vs_exact": err(layout.to_global(r["v"].cpu().numpy(), mesh.E, mesh.p + 1), ref),
+                       "rel_L2_err_vs_continuum": err(layout.to_global(r["v"].cpu().numpy(), mesh.E, mesh.p + 1), cont)}
+                 for arm, r in results.items()}
+        if args.cpu_sample > 0:
+            H = mg.Hierarchy(mesh.E, mesh.p, mesh.lo, mesh.hi, n_levels=wl.n_levels)
+            pcg.solve(H, b, rtol=wl.rtol)
+            n = 20
+            t0 = time.perf_counter()
+            for _ in range(n):
+                _, it, _, _ = pcg.solve(H, b, rtol=wl.rtol)
+            dt = (time.perf_counter() - t0) / n
+            cpu = {"value": 1.0 / dt, "unit": "RHS/s", "us_per_solve": 1e6 * dt, "cores": _threads(), "kind": "oracle",
+                   "sample": f"{n} solves of the single-Gaussian problem, oracle MG-PCG FP64 to {wl.rtol}, "
+                             f"{it} iterations; set-up excluded"}
+    head_arm = arms[0]
+    head = results[head_arm]
+    line = {
+        "metric": "Poisson RHS solved/sec at 1e-10 rel. residual (single RHS, latency-bound)",
+        "value": head["value"], "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e-3 * head["us_per_solve"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if head_arm.startswith("fp32_ir") else "f64", "data": "synthetic",
+        "config": {"workload": "single: two-Gaussian density, 4^3 elements p=3 (4096 DOFs), 2-level MG-PCG to 1e-10",
+                   "arm": head_arm, "parallelism": "single GPU"},
+        "arms": {a: {k: v for k, v in r.items() if k != "v"} for a, r in results.items()},
+        "roofline": None,
+        "roofline_note": "4,096 nodes per vector stay in cache: bound by launch latency, reported as us per solve",
+        "cpu_baseline": cpu,
+        "check_vs_exact": check,
+    }
+    print(json.dumps(line))
+
+
+def _threads():
+    from threadpoolctl import threadpool_info
+    return max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+
+
 def measured_traffic(profile_name, kernel_source):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None.
 
@@ -353,9 +448,24 @@ def cpu_leg(args, wl, results, phi, g, npairs):
             its.append(it)
         dt = time.perf_counter() - t0
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        # the same solves on one host thread (a shorter sample), and the exact solve (fast diagonalisation)
+        from threadpoolctl import threadpool_limits
+        q1 = bs[:max(1, len(bs) // 6)]
+        with threadpool_limits(1):
+            t1 = time.perf_counter()
+            for b in q1:
+                pcg.solve(H, b, rtol=wl.rtol)
+            dt1 = time.perf_counter() - t1
+        F = fdm.FDM(axes)
+        t2 = time.perf_counter()
+        for b in bs:
+            F.solve(b)
+        dtf = time.perf_counter() - t2
         cpu = {"value": len(qs) / dt, "unit": "RHS/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(qs)} of {npairs} pair solves (pairs {qs}), oracle MG-PCG FP64 to {wl.rtol}, "
-                         f"iterations {its}; set-up excluded"}
+                         f"iterations {its}; set-up excluded",
+               "value_1thread": len(q1) / dt1, "sample_1thread": f"the first {len(q1)} of those solves, one thread",
+               "exact_fdm_value": len(bs) / dtf}
     check = None
     if args.check_sample > 0:
         out = {}
