@@ -479,27 +479,34 @@ void check_mesh_id(const dg_ctx* ctx, int mesh_id) {
     if (mesh_id < 0 || mesh_id >= (int)ctx->meshes.size()) throw ArgError("mesh_id out of range");
 }
 
-// Learned guess for nrhs sources rho of mesh M (b already assembled): writes
-// ctx->g_x0, then zeroes the guesses whose residual is not below ||b||.
-// Returns the per-right-hand-side flags of the guesses kept.
-std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho, const double* b, hipStream_t s);
+// Learned guess for nrhs sources rho of mesh M: writes ctx->g_x0 (the solve's guard
+// later drops a guess whose residual is not below ||b||).
+void learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho, hipStream_t s);
 
 // Solve nrhs problems of one mesh: b (FP64, packed) -> v.  Fills stats.
+// guard: x0 is a learned guess, kept per right-hand side only if its residual is below ||b||
+// (decided on the device from the first FP64 residual of the solve).
 void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* x0, double* v, dg_rhs_stats* stats,
-                 hipStream_t s, const std::vector<int>* guess_used = nullptr) {
+                 hipStream_t s, bool guard = false) {
     const LevelHost& L0 = M.lv[0];
     const long long n0 = L0.ndof;
     const int nc = dg::chunks_of(n0), nb = dg::op_blocks<double>(L0, dg::BM_RESIDDOT);
     const auto& o = ctx->opts;
     ensure_state(M, nrhs);
-    std::vector<int> iters(nrhs, 0), outer(nrhs, 0);
+    std::vector<int> iters(nrhs, 0), outer(nrhs, 0), kept(nrhs, x0 ? 1 : 0);
     if (o.precision == DG_PREC_FP64) {
         ensure_work<double>(M, M.w64, nrhs);
         Work<double>& W = M.w64;
         init_state(M, M.st, nrhs, o.rtol, o.max_iter, s);
         dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
         dg::launch_finalize(dg::FIN_BB, nrhs, M.st, M.partial, M.pstride, nc, s);
-        if (x0) {
+        if (x0 && guard) {
+            dg::launch_copy(x0, W.x, n0 * nrhs, s);
+            dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr, W.r,
+                                     nullptr, M.partial, M.pstride, 0, 0, s);
+            dg::launch_finalize(dg::FIN_TRUE, nrhs, M.st, M.partial, M.pstride, nb, s);
+            dg::launch_guard(nrhs, n0, M.st, b, W.x, W.r, false, s);
+        } else if (x0) {
             dg::launch_copy(x0, W.x, n0 * nrhs, s);
             dg::launch_brick<double>(dg::BM_RESID, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr, W.r,
                                      nullptr, nullptr, 0, 0, 0, s);
@@ -524,6 +531,8 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             if (!again) break;
         }
         for (int i = 0; i < nrhs; ++i) outer[i] = 1;
+        if (x0 && guard)
+            for (int i = 0; i < nrhs; ++i) kept[i] = M.st_host[i].guess;
         HIPCHK(hipMemcpyAsync(v, W.x, sizeof(double) * n0 * nrhs, hipMemcpyDeviceToDevice, s));
     } else {
         ensure_work<float>(M, M.w32, nrhs);
@@ -541,7 +550,10 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, v, nullptr, b, nullptr, M.r64,
                                      nullptr, M.partial, M.pstride, 0, 0, s);
             dg::launch_finalize(dg::FIN_OUTER, nrhs, M.st, M.partial, M.pstride, nb, s);
+            if (it == 0 && x0 && guard) dg::launch_guard(nrhs, n0, M.st, b, v, M.r64, true, s);
             read_state(M, M.st, nrhs, s);
+            if (it == 0 && x0 && guard)
+                for (int i = 0; i < nrhs; ++i) kept[i] = M.st_host[i].guess;
             bool any = false;
             for (int i = 0; i < nrhs; ++i) {
                 any |= M.st_host[i].active != 0;
@@ -575,7 +587,7 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             dg_rhs_stats& r = stats[i];
             r.iters = iters[i];
             r.outer_iters = outer[i];
-            r.guess_used = guess_used ? (*guess_used)[i] : (x0 ? 1 : 0);
+            r.guess_used = kept[i];
             r.rel_residual = S.bb > 0 ? std::sqrt(S.rr / S.bb) : 0.0;
             r.status = (r.rel_residual <= o.rtol * 1.01) ? DG_OK : DG_WARN_NOT_CONVERGED;
         }
@@ -590,7 +602,7 @@ struct Job {
     const double* x0;
     double* v;
     dg_rhs_stats* stats;
-    const std::vector<int>* used;  // learned-guess flags, or null
+    bool guard;  // x0 is a learned guess (guarded in the solve)
 };
 
 constexpr int kLaneMin = 16;  // smallest batch of one mesh that is split over two lanes
@@ -608,31 +620,23 @@ void prepare_lane(dg_ctx* ctx, Mesh& M, int cnt) {
 }
 
 // Appends the jobs of one mesh's batch: one job, or two halves on the mesh's two
-// lanes.  `used` (may be null) holds the guess flags of the batch; its halves are
-// kept in `keep`.
+// lanes.  guard: x0 is a learned guess.
 void add_jobs(dg_ctx* ctx, int mesh_id, int cnt, const double* b, const double* x0, double* v, dg_rhs_stats* stats,
-              const std::vector<int>* used, std::vector<Job>& jobs, std::vector<std::vector<int>>& keep) {
+              bool guard, std::vector<Job>& jobs) {
     Mesh& M = ctx->meshes[mesh_id];
     const long long n0 = M.lv[0].ndof;
     if (ctx->twins.empty() || cnt < kLaneMin) {
         prepare_lane(ctx, M, cnt);
-        jobs.push_back({&M, cnt, b, x0, v, stats, used});
+        jobs.push_back({&M, cnt, b, x0, v, stats, guard});
         return;
     }
     Mesh& T = ctx->twins[mesh_id];
     const int h = cnt / 2;
-    const std::vector<int>* u0 = nullptr;
-    const std::vector<int>* u1 = nullptr;
-    if (used) {
-        keep.emplace_back(used->begin(), used->begin() + h);
-        u0 = &keep.back();
-        keep.emplace_back(used->begin() + h, used->end());
-        u1 = &keep.back();
-    }
     prepare_lane(ctx, M, h);
     prepare_lane(ctx, T, cnt - h);
-    jobs.push_back({&M, h, b, x0, v, stats, u0});
-    jobs.push_back({&T, cnt - h, b + h * n0, x0 ? x0 + h * n0 : nullptr, v + h * n0, stats ? stats + h : nullptr, u1});
+    jobs.push_back({&M, h, b, x0, v, stats, guard});
+    jobs.push_back({&T, cnt - h, b + h * n0, x0 ? x0 + h * n0 : nullptr, v + h * n0, stats ? stats + h : nullptr,
+                    guard});
 }
 
 // Runs the jobs: a single one on the caller's stream; several at once, each on its
@@ -641,7 +645,7 @@ void add_jobs(dg_ctx* ctx, int mesh_id, int cnt, const double* b, const double* 
 void run_jobs(dg_ctx* ctx, std::vector<Job>& jobs, hipStream_t stream) {
     if (jobs.size() == 1) {
         auto& J = jobs[0];
-        solve_group(ctx, *J.M, J.cnt, J.b, J.x0, J.v, J.stats, stream, J.used);
+        solve_group(ctx, *J.M, J.cnt, J.b, J.x0, J.v, J.stats, stream, J.guard);
         return;
     }
     HIPCHK(hipEventRecord(ctx->ev_ready, stream));
@@ -655,7 +659,7 @@ void run_jobs(dg_ctx* ctx, std::vector<Job>& jobs, hipStream_t stream) {
                 HIPCHK(hipSetDevice(ctx->device));
                 auto& J = jobs[k];
                 HIPCHK(hipStreamWaitEvent(J.M->stream, ctx->ev_ready, 0));
-                solve_group(ctx, *J.M, J.cnt, J.b, J.x0, J.v, J.stats, J.M->stream, J.used);
+                solve_group(ctx, *J.M, J.cnt, J.b, J.x0, J.v, J.stats, J.M->stream, J.guard);
                 HIPCHK(hipEventRecord(J.M->ev_done, J.M->stream));
             } catch (...) {
                 err[k] = std::current_exception();
@@ -668,9 +672,8 @@ void run_jobs(dg_ctx* ctx, std::vector<Job>& jobs, hipStream_t stream) {
     for (auto& J : jobs) HIPCHK(hipStreamWaitEvent(stream, J.M->ev_done, 0));
 }
 
-std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho, const double* b, hipStream_t s) {
-    const LevelHost& L0 = M.lv[0];
-    const long long n0 = L0.ndof;
+void learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho, hipStream_t s) {
+    const long long n0 = M.lv[0].ndof;
     if (ctx->g_cap < n0 * nrhs) {
         dfree(ctx->g_x0);
         dfree(ctx->g_rho);
@@ -681,24 +684,6 @@ std::vector<int> learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho
     const int mesh_id = (int)(&M - ctx->meshes.data());
     if (dg_net_guess(ctx->guess, ctx, mesh_id, nrhs, rho, ctx->g_x0, s) != DG_OK)
         throw ArgError(std::string("learned guess failed: ") + dg_net_last_error());
-    ensure_state(M, nrhs);
-    const int nc = dg::chunks_of(n0), nb = dg::op_blocks<double>(L0, dg::BM_RESIDDOT);
-    init_state(M, M.st, nrhs, 1.0, 1, s);
-    dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
-    dg::launch_finalize(dg::FIN_BB, nrhs, M.st, M.partial, M.pstride, nc, s);
-    ensure_b(M, std::max(M.cap_b, nrhs), ctx->opts.precision == DG_PREC_FP32_IR);
-    double* r = ctx->g_rho;  // rho is no longer needed: reuse as residual space
-    dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, ctx->g_x0, nullptr, b, nullptr, r, nullptr,
-                             M.partial, M.pstride, 0, 0, s);
-    dg::launch_finalize(dg::FIN_TRUE, nrhs, M.st, M.partial, M.pstride, nb, s);
-    read_state(M, M.st, nrhs, s);
-    std::vector<int> used(nrhs, 0);
-    for (int i = 0; i < nrhs; ++i) {
-        const auto& S = M.st_host[i];
-        used[i] = (S.bb > 0 && S.rr < S.bb) ? 1 : 0;
-        if (!used[i]) dg::launch_fill<double>(ctx->g_x0 + (long long)i * n0, 0.0, n0, s);
-    }
-    return used;
 }
 
 void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
@@ -1130,7 +1115,7 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
             long long tab = 0;  // offset-table position (non-contiguous parts)
             const double *rho = nullptr, *g = nullptr, *x0 = nullptr;
             double* v = nullptr;
-            std::vector<int> idx, used;
+            std::vector<int> idx;
             std::vector<dg_rhs_stats> stats;
         };
         std::vector<Part> parts;
@@ -1222,8 +1207,7 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
                     ctx->g_rho = dalloc<double>(n0 * cnt);
                     ctx->g_cap = n0 * cnt;
                 }
-                dg::launch_copy(P.rho, ctx->g_rho, n0 * cnt, stream);
-                P.used = learned_guess(ctx, M, cnt, ctx->g_rho, M.b, stream);
+                learned_guess(ctx, M, cnt, P.rho, stream);
                 dg::launch_copy(ctx->g_x0, M.gx0, n0 * cnt, stream);  // the guess buffer is shared by the parts
                 P.x0 = M.gx0;
                 P.guessed = true;
@@ -1231,11 +1215,8 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
         }
         // every buffer is sized here, on this thread: the solves allocate nothing
         std::vector<Job> jobs;
-        std::vector<std::vector<int>> keep;
-        keep.reserve(2 * parts.size());
         for (auto& P : parts)
-            add_jobs(ctx, P.m, P.cnt, ctx->meshes[P.m].b, P.x0, P.v, P.stats.data(), P.guessed ? &P.used : nullptr,
-                     jobs, keep);
+            add_jobs(ctx, P.m, P.cnt, ctx->meshes[P.m].b, P.x0, P.v, P.stats.data(), P.guessed, jobs);
         run_jobs(ctx, jobs, stream);
         for (auto& P : parts) {
             if (!P.contig) {
@@ -1291,7 +1272,6 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
         ensure_b(M, npairs, ctx->opts.precision == DG_PREC_FP32_IR);
         dg::launch_rhs(M.lv[0], M.lv[0].dev64, npairs, nullptr, phi, ctx->xpairs, ctx->xpairs + npairs, g_pairs,
                        M.nface, M.b, stream);
-        std::vector<int> used;
         if (ctx->guess) {
             if (ctx->g_cap < n0 * npairs) {
                 dfree(ctx->g_x0);
@@ -1301,14 +1281,12 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
                 ctx->g_cap = n0 * npairs;
             }
             dg::launch_pair_products(n0, npairs, phi, ctx->xpairs, ctx->xpairs + npairs, ctx->g_rho, stream);
-            used = learned_guess(ctx, M, npairs, ctx->g_rho, M.b, stream);
+            learned_guess(ctx, M, npairs, ctx->g_rho, stream);
         }
         std::vector<dg_rhs_stats> st_all(npairs);
         std::vector<Job> jobs;
-        std::vector<std::vector<int>> keep;
-        keep.reserve(2);
-        add_jobs(ctx, mesh_id, npairs, M.b, ctx->guess ? ctx->g_x0 : nullptr, v, st_all.data(),
-                 ctx->guess ? &used : nullptr, jobs, keep);
+        add_jobs(ctx, mesh_id, npairs, M.b, ctx->guess ? ctx->g_x0 : nullptr, v, st_all.data(), ctx->guess != nullptr,
+                 jobs);
         run_jobs(ctx, jobs, stream);
         if (stats) std::copy(st_all.begin(), st_all.end(), stats);
         const int nblk = (int)((n0 + 255) / 256);

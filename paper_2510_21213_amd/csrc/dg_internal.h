@@ -93,6 +93,7 @@ struct RhsState {
     int iters;      // completed iterations
     int maxit;
     int breakdown;
+    int guess;      // 1 when a supplied initial guess passed the guard (its residual is below ||b||)
 };
 
 // Host description of one level.

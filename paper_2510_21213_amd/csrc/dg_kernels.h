@@ -49,6 +49,10 @@ void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHo
                      int nrhs, const RhsState* st, const T* z, const T* f, T* fc, T* z1c, double c0c, hipStream_t s);
 
 // zf += P zc
+// zf = scale[rhs] * P zc for a degree step (writes every fine node); false when the step
+// between the two levels is not a degree step with a kernel for it (nothing launched)
+bool launch_prolong_set(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const double* zc, double* zf,
+                        const double* scale, hipStream_t s);
 template <typename T>
 void launch_prolong(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st, const T* zc, T* zf,
                     hipStream_t s);
@@ -73,6 +77,11 @@ template <typename TA, typename TB>
 void launch_dot(long long ndof, int nrhs, const RhsState* st, const TA* a, const TB* b, double* partial,
                 int pstride, hipStream_t s);
 
+// Guard of an initial guess, after its FP64 residual r = b - A x and st.rr = ||r||^2: a guess
+// whose residual is not below ||b|| is dropped (x = 0, r = b, rr = bb); st.guess records the
+// decision.  outer: st is the refinement state (FIN_OUTER fields are updated as well).
+void launch_guard(int nrhs, long long n, RhsState* st, const double* b, double* x, double* r, bool outer,
+                  hipStream_t s);
 void launch_finalize(int what, int nrhs, RhsState* st, const double* partial, int pstride, int nblk,
                      hipStream_t s);
 

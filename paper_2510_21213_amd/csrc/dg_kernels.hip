@@ -1400,10 +1400,11 @@ void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHo
 // values are staged in LDS with coalesced loads, then one thread per fine node
 // column (i, j) of an element contracts along x and y (NC^2 coarse values per
 // coarse z node) and then along z in registers, and updates its NF nodes.
-template <typename T, int NF, int NC>
+// SET: zf = scale[rhs] * P zc (every fine node written once) instead of zf += P zc
+template <typename T, int NF, int NC, bool SET = false>
 __global__ __launch_bounds__(256) void k_prolong_deg(const TransferDev* __restrict__ trp, long long nelem_rhs,
                                                      long long nelem, const RhsState* st, const T* __restrict__ zc,
-                                                     T* __restrict__ zf) {
+                                                     T* __restrict__ zf, const double* __restrict__ scale = nullptr) {
     constexpr int NF2 = NF * NF, NF3 = NF2 * NF, NC3 = NC * NC * NC;
     constexpr int EPW = 256 / NF2;
     __shared__ T sc[EPW * NC3];
@@ -1444,13 +1445,36 @@ __global__ __launch_bounds__(256) void k_prolong_deg(const TransferDev* __restri
         t[cz] = acc;
     }
     T* out = zf + e * NF3 + col;
+    const T sc_rhs = SET ? (T)scale[e / nelem_rhs] : (T)0;
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
         T v = 0;
 #pragma unroll
         for (int cz = 0; cz < NC; ++cz) v += Pm(k, cz) * t[cz];
-        out[k * NF2] += v;
+        if constexpr (SET)
+            out[k * NF2] = v * sc_rhs;
+        else
+            out[k * NF2] += v;
     }
+}
+
+bool launch_prolong_set(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const double* zc, double* zf,
+                        const double* scale, hipStream_t s) {
+    if (Lf.hcoarse || Lf.E[0] != Lc.E[0] || Lf.E[1] != Lc.E[1] || Lf.E[2] != Lc.E[2]) return false;
+    const long long nel = (long long)Lf.E[0] * Lf.E[1] * Lf.E[2];
+    const long long tot = nel * nrhs;
+    if (tot == 0) return true;
+#define DG_PS(NF, NC)                                                                                          \
+    if (Lf.n == NF && Lc.n == NC) {                                                                            \
+        constexpr int EPW = 256 / (NF * NF);                                                                   \
+        hipLaunchKernelGGL((k_prolong_deg<double, NF, NC, true>), dim3((unsigned)((tot + EPW - 1) / EPW)),     \
+                           dim3(256), 0, s, Lf.devtr, nel, tot, nullptr, zc, zf, scale);                       \
+        return true;                                                                                           \
+    }
+    DG_PS(5, 3)
+    DG_PS(3, 2)
+#undef DG_PS
+    return false;
 }
 
 template <typename T>
@@ -1771,6 +1795,42 @@ __global__ __launch_bounds__(256) void k_finalize(int what, RhsState* st, const 
             S.active = (s > S.tol2 * S.bb) ? 1 : 0;
             break;
     }
+}
+
+__global__ __launch_bounds__(256) void k_guard_state(int nrhs, RhsState* st, int outer) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nrhs) return;
+    RhsState& S = st[i];
+    S.guess = (S.bb > 0.0 && S.rr < S.bb) ? 1 : 0;
+    if (S.guess) return;
+    S.rr = S.bb;
+    if (outer) {
+        S.scale = sqrt(S.bb);
+        S.active = (S.bb > S.tol2 * S.bb) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_guard_fields(long long n, const RhsState* st, const double* __restrict__ b,
+                                                      double* __restrict__ x, double* __restrict__ r) {
+    const int rhs = blockIdx.y;
+    if (st[rhs].guess) return;
+    const long long base = (long long)rhs * n;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q < n) {
+            x[base + q] = 0.0;
+            r[base + q] = b[base + q];
+        }
+    }
+}
+
+void launch_guard(int nrhs, long long n, RhsState* st, const double* b, double* x, double* r, bool outer,
+                  hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL(k_guard_state, dim3((nrhs + 255) / 256), dim3(256), 0, s, nrhs, st, outer ? 1 : 0);
+    hipLaunchKernelGGL(k_guard_fields, dim3(chunks_of(n), nrhs), dim3(256), 0, s, n, st, b, x, r);
 }
 
 void launch_finalize(int what, int nrhs, RhsState* st, const double* partial, int pstride, int nblk, hipStream_t s) {

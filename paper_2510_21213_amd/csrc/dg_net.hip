@@ -126,6 +126,9 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ x, 
                 const float4 v1 = *reinterpret_cast<const float4*>(xv + ci0 + 4);
                 a[0] = (__bf16)v0.x; a[1] = (__bf16)v0.y; a[2] = (__bf16)v0.z; a[3] = (__bf16)v0.w;
                 a[4] = (__bf16)v1.x; a[5] = (__bf16)v1.y; a[6] = (__bf16)v1.z; a[7] = (__bf16)v1.w;
+            } else if (valid && ci0 + 8 <= Ci) {  // whole chunk in range, rows not 16-byte aligned
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a[q] = (__bf16)xv[ci0 + q];
             } else {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) a[q] = (valid && ci0 + q < Ci) ? (__bf16)xv[ci0 + q] : (__bf16)0.f;
@@ -1136,6 +1139,19 @@ void output_map(const dg::LevelHost& L0, const dg::LevelHost& L1, int B, const f
     dg::launch_prolong<double>(L0, L1, B, nullptr, tmp2, out, s);
 }
 
+// The guess: scale[b] * output_map(y) for sample b, the scale applied by the prolongation
+// itself where the step from level 1 to level 0 is a degree step (one write of the fine field).
+void output_map_scaled(const dg::LevelHost& L0, const dg::LevelHost& L1, int B, const float* y, double* out,
+                       double* tmp1, double* tmp2, const double* scale, hipStream_t s) {
+    const long long n1 = L1.ndof * B;
+    hipLaunchKernelGGL(k_f2d, dim3(nblocks(n1)), dim3(256), 0, s, y, tmp1, n1);
+    launch_continuize(L1, B, tmp1, tmp2, s);
+    if (dg::launch_prolong_set(L0, L1, B, tmp2, out, scale, s)) return;
+    dg::launch_fill<double>(out, 0.0, L0.ndof * B, s);
+    dg::launch_prolong<double>(L0, L1, B, nullptr, tmp2, out, s);
+    hipLaunchKernelGGL(k_scale_samples, dim3(64, B), dim3(256), 0, s, out, scale, L0.ndof);
+}
+
 // Transpose of output_map: gy = C P^T g (C is symmetric).  g: FP64 [B][ndof0].
 void output_map_transpose(const dg::LevelHost& L0, const dg::LevelHost& L1, int B, const double* g, float* gy,
                           double* tmp1, double* tmp2, hipStream_t s) {
@@ -1276,8 +1292,7 @@ dg_status dg_net_guess(dg_net* net, const dg_ctx* ctx, int mesh_id, int batch, c
         hipLaunchKernelGGL(k_scale_of, dim3(batch), dim3(64), 0, stream, net->dpart, nb, n_dofs, net->scale);
         hipLaunchKernelGGL(k_to_input, dim3(nb, batch), dim3(256), 0, stream, rho, net->scale, net->xbuf, n_dofs);
         const float* y = forward(net, batch, ne, net->xbuf, stream);
-        output_map(L0, L1, batch, y, v0, net->w1, net->w2, stream);
-        hipLaunchKernelGGL(k_scale_samples, dim3(nb, batch), dim3(256), 0, stream, v0, net->scale, n_dofs);
+        output_map_scaled(L0, L1, batch, y, v0, net->w1, net->w2, net->scale, stream);
         NCHK(hipGetLastError());
     });
 }
