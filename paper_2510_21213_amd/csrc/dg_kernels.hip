@@ -2068,9 +2068,64 @@ __global__ __launch_bounds__(256) void k_exchange(const LevelDev<double>* __rest
         for (int a = 0; a < norb; ++a) W[(long long)a * ndof + q] = w[a];
 }
 
+// The same for a compile-time orbital count: orbital values and W sums in registers (the
+// run-time count above keeps them in scratch memory), one wave reduction per pair and a
+// single barrier per work-group for all pair partial sums.  Used for 8 orbitals at p = 4;
+// 16 orbitals would need more registers than a lane has.
+template <int N, int NORB>
+__global__ __launch_bounds__(256) void k_exchange_n(const LevelDev<double>* __restrict__ L, long long ndof,
+                                                    const double* __restrict__ phi, const double* __restrict__ v,
+                                                    double* __restrict__ W, double* __restrict__ partial,
+                                                    int pstride) {
+    constexpr int N3 = N * N * N, NPAIR = NORB * (NORB + 1) / 2;
+    __shared__ double red[4][NPAIR];
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool ok = q < ndof;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double ph[NORB], w[NORB];
+    double wq = 0.0;
+    if (ok) {
+        const int l = (int)(q % N3);
+        const int i = l % N, j = (l / N) % N, k = l / (N * N);
+        wq = L->ax[0].m[i] * L->ax[1].m[j] * L->ax[2].m[k];
+    }
+#pragma unroll
+    for (int a = 0; a < NORB; ++a) {
+        ph[a] = ok ? phi[(long long)a * ndof + q] : 0.0;
+        w[a] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < NORB; ++a) {
+#pragma unroll
+        for (int b = a; b < NORB; ++b) {
+            const int pidx = a * NORB - a * (a - 1) / 2 + (b - a);
+            const double vv = ok ? v[(long long)pidx * ndof + q] : 0.0;
+            w[a] += ph[b] * vv;
+            if (b != a) w[b] += ph[a] * vv;
+            double kv = wq * ph[a] * ph[b] * vv;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) kv += __shfl_xor(kv, off, 64);
+            if (lane == 0) red[wave][pidx] = kv;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < NPAIR; p += 256)
+        partial[(long long)p * pstride + blockIdx.x] = (red[0][p] + red[1][p]) + (red[2][p] + red[3][p]);
+    if (ok) {
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) W[(long long)a * ndof + q] = w[a];
+    }
+}
+
 void launch_exchange(const LevelHost& L, const LevelDev<double>* dev, int norb, const double* phi, const double* v,
                      double* W, double* partial, int pstride, hipStream_t s) {
     const unsigned grid = (unsigned)((L.ndof + 255) / 256);
+    if (L.n == 5 && norb == 8) {
+        hipLaunchKernelGGL((k_exchange_n<5, 8>), dim3(grid), dim3(256), 0, s, dev, L.ndof, phi, v, W, partial,
+                           pstride);
+        return;
+    }
+
 #define DG_X(NN)                                                                                                   \
     case NN:                                                                                                       \
         hipLaunchKernelGGL((k_exchange<NN>), dim3(grid), dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, norb, \

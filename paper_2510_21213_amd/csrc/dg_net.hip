@@ -851,7 +851,8 @@ void ensure_buffers(dg_net* net, int B, const int* E) {
 // Forward pass on x [B][Ez][Ey][Ex][Cin]; the output is the activation of "out".
 const float* forward(dg_net* net, int B, const int* E, const float* x, hipStream_t s) {
     ensure_buffers(net, B, E);
-    NCHK(hipMemcpyAsync(net->xin.d, x, sizeof(float) * net->xin.n, hipMemcpyDeviceToDevice, s));
+    // the input is kept for the backward pass (a caller may have written it there already)
+    if (x != net->xin.d) NCHK(hipMemcpyAsync(net->xin.d, x, sizeof(float) * net->xin.n, hipMemcpyDeviceToDevice, s));
     x = net->xin.d;
     const int Lv = net->cfg.levels, C = net->cfg.channels;
     auto A = [&](const std::string& n) { return net->act[layer_index(net, n)].d; };
@@ -1287,11 +1288,13 @@ dg_status dg_net_guess(dg_net* net, const dg_ctx* ctx, int mesh_id, int batch, c
         const int ne[3] = {L0.E[0], L0.E[1], L0.E[2]};
         const long long n_dofs = L0.ndof;
         ensure_field(net, n_dofs * batch, batch);
+        ensure_buffers(net, batch, ne);
+        if (net->xin.n != n_dofs * batch) throw NetError("internal: input buffer size");
         const int nb = 64;
         hipLaunchKernelGGL(k_sumsq, dim3(nb, batch), dim3(256), 0, stream, rho, net->dpart, n_dofs);
         hipLaunchKernelGGL(k_scale_of, dim3(batch), dim3(64), 0, stream, net->dpart, nb, n_dofs, net->scale);
-        hipLaunchKernelGGL(k_to_input, dim3(nb, batch), dim3(256), 0, stream, rho, net->scale, net->xbuf, n_dofs);
-        const float* y = forward(net, batch, ne, net->xbuf, stream);
+        hipLaunchKernelGGL(k_to_input, dim3(nb, batch), dim3(256), 0, stream, rho, net->scale, net->xin.d, n_dofs);
+        const float* y = forward(net, batch, ne, net->xin.d, stream);
         output_map_scaled(L0, L1, batch, y, v0, net->w1, net->w2, net->scale, stream);
         NCHK(hipGetLastError());
     });
