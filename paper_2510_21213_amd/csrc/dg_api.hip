@@ -505,7 +505,7 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr, W.r,
                                      nullptr, M.partial, M.pstride, 0, 0, s);
             dg::launch_finalize(dg::FIN_TRUE, nrhs, M.st, M.partial, M.pstride, nb, s);
-            dg::launch_guard(nrhs, n0, M.st, b, W.x, W.r, false, s);
+            dg::launch_guard(nrhs, n0, M.st, b, W.x, W.r, false, false, s);
         } else if (x0) {
             dg::launch_copy(x0, W.x, n0 * nrhs, s);
             dg::launch_brick<double>(dg::BM_RESID, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr, W.r,
@@ -541,16 +541,18 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
         init_state(M, M.st, nrhs, o.rtol, o.max_iter, s);
         dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
         dg::launch_finalize(dg::FIN_BB, nrhs, M.st, M.partial, M.pstride, nc, s);
-        if (x0)
-            dg::launch_copy(x0, v, n0 * nrhs, s);
-        else
-            dg::launch_fill<double>(v, 0.0, n0 * nrhs, s);
+        if (x0) dg::launch_copy(x0, v, n0 * nrhs, s);
         bool done = false;  // the last outer residual is that of the returned solution
         for (int it = 0; it < o.max_outer; ++it) {
-            dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, v, nullptr, b, nullptr, M.r64,
-                                     nullptr, M.partial, M.pstride, 0, 0, s);
-            dg::launch_finalize(dg::FIN_OUTER, nrhs, M.st, M.partial, M.pstride, nb, s);
-            if (it == 0 && x0 && guard) dg::launch_guard(nrhs, n0, M.st, b, v, M.r64, true, s);
+            if (it == 0 && !x0) {
+                // from x = 0 the first residual is b itself: v = 0, r = b, rr = bb
+                dg::launch_guard(nrhs, n0, M.st, b, v, M.r64, true, true, s);
+            } else {
+                dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, v, nullptr, b, nullptr,
+                                         M.r64, nullptr, M.partial, M.pstride, 0, 0, s);
+                dg::launch_finalize(dg::FIN_OUTER, nrhs, M.st, M.partial, M.pstride, nb, s);
+                if (it == 0 && guard) dg::launch_guard(nrhs, n0, M.st, b, v, M.r64, true, false, s);
+            }
             read_state(M, M.st, nrhs, s);
             if (it == 0 && x0 && guard)
                 for (int i = 0; i < nrhs; ++i) kept[i] = M.st_host[i].guess;

@@ -80,8 +80,9 @@ void launch_dot(long long ndof, int nrhs, const RhsState* st, const TA* a, const
 // Guard of an initial guess, after its FP64 residual r = b - A x and st.rr = ||r||^2: a guess
 // whose residual is not below ||b|| is dropped (x = 0, r = b, rr = bb); st.guess records the
 // decision.  outer: st is the refinement state (FIN_OUTER fields are updated as well).
+// drop_all: every right-hand side starts from x = 0 (no residual needed, st.bb set).
 void launch_guard(int nrhs, long long n, RhsState* st, const double* b, double* x, double* r, bool outer,
-                  hipStream_t s);
+                  bool drop_all, hipStream_t s);
 void launch_finalize(int what, int nrhs, RhsState* st, const double* partial, int pstride, int nblk,
                      hipStream_t s);
 

@@ -1797,11 +1797,11 @@ __global__ __launch_bounds__(256) void k_finalize(int what, RhsState* st, const 
     }
 }
 
-__global__ __launch_bounds__(256) void k_guard_state(int nrhs, RhsState* st, int outer) {
+__global__ __launch_bounds__(256) void k_guard_state(int nrhs, RhsState* st, int outer, int drop_all) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= nrhs) return;
     RhsState& S = st[i];
-    S.guess = (S.bb > 0.0 && S.rr < S.bb) ? 1 : 0;
+    S.guess = (!drop_all && S.bb > 0.0 && S.rr < S.bb) ? 1 : 0;
     if (S.guess) return;
     S.rr = S.bb;
     if (outer) {
@@ -1827,9 +1827,10 @@ __global__ __launch_bounds__(256) void k_guard_fields(long long n, const RhsStat
 }
 
 void launch_guard(int nrhs, long long n, RhsState* st, const double* b, double* x, double* r, bool outer,
-                  hipStream_t s) {
+                  bool drop_all, hipStream_t s) {
     if (nrhs == 0) return;
-    hipLaunchKernelGGL(k_guard_state, dim3((nrhs + 255) / 256), dim3(256), 0, s, nrhs, st, outer ? 1 : 0);
+    hipLaunchKernelGGL(k_guard_state, dim3((nrhs + 255) / 256), dim3(256), 0, s, nrhs, st, outer ? 1 : 0,
+                       drop_all ? 1 : 0);
     hipLaunchKernelGGL(k_guard_fields, dim3(chunks_of(n), nrhs), dim3(256), 0, s, n, st, b, x, r);
 }
 

@@ -171,3 +171,39 @@ def _init(net, rng):
         scale = np.sqrt(2.0 / fan_in) if name != "out" else np.sqrt(1.0 / fan_in)
         out += [scale * rng.standard_normal(k ** 3 * ci * co), np.zeros(co)]
     return np.concatenate(out).astype(np.float32)
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir", "fp64"])
+def test_guard_on_device_with_zero_source_in_the_batch(gpu_lib, precision):
+    """The guard is taken from the solve's first FP64 residual.  A zero source gets a
+    nonzero guess from the network's biases (its residual exceeds ||b|| = 0): it is
+    dropped and the solution is exactly zero; the other sources converge to the exact
+    solve whichever way their guess was judged, and a dropped guess leaves the iteration
+    path of a solve without a guess."""
+    from oracle import fdm
+    wl = configs.scaled(8, 4, 3, seed=52)
+    mesh = wl.meshes[0]
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=1e-11, precision=precision)
+    rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+    nd, nf = len(rho[0]), len(g[0])
+    rho = list(rho[:2]) + [np.zeros(nd)] + list(rho[2:])
+    g = list(g[:2]) + [np.zeros(nf)] + list(g[2:])
+    rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+    net = gpu_lib.Net(3, 8, 125, 27)
+    rng = np.random.default_rng(4)
+    net.set_params((0.05 * rng.standard_normal(net.num_params)).astype(np.float32))
+    ctx.attach_guess(net)
+    v, st = ctx.solve_batch(rho, g)
+    v = v.cpu().numpy().reshape(4, -1)
+    assert st[2]["guess_used"] == 0 and st[2]["status"] == 0 and not np.any(v[2])
+    for k, d in zip((0, 1, 3), wl.batch.densities):
+        axes, _, _, b = oracle_density_problem(mesh, d)
+        assert rel_l2_M(axes, mesh, v[k], fdm.FDM(axes).solve(b)) <= POT_BAR
+        assert st[k]["guess_used"] in (0, 1) and st[k]["status"] == 0
+    net.set_params(np.zeros(net.num_params, dtype=np.float32))   # v0 = 0: dropped everywhere
+    v0, st0 = ctx.solve_batch(rho, g)
+    assert all(s["guess_used"] == 0 for s in st0)
+    ctx.attach_guess(None)
+    v1, st1 = ctx.solve_batch(rho, g)
+    assert [s["iters"] for s in st1] == [s["iters"] for s in st0]
+    assert [s["outer_iters"] for s in st1] == [s["outer_iters"] for s in st0]
