@@ -111,7 +111,8 @@ typedef struct {
     int iters;           /* PCG iterations (summed over inner solves in FP32_IR) */
     int outer_iters;     /* refinement steps (FP32_IR), 1 for FP64 */
     int status;          /* DG_OK or DG_WARN_NOT_CONVERGED */
-    int guess_used;      /* 1 if a caller-supplied initial guess was used */
+    int guess_used;      /* 1 if an initial guess was used: the caller's x0, or a learned guess
+                            that passed the guard (residual below ||b||) */
     double rel_residual; /* ||b - A v||_2 / ||b||_2 recomputed in FP64 at exit */
 } dg_rhs_stats;
 
