@@ -29,7 +29,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=6,
+                    help="untimed steps first: the first calls capture the PCG graphs and learn how many "
+                         "iteration blocks to replay before a host check (about five calls to settle)")
     ap.add_argument("--config", default="exchange8", choices=["exchange8", "exchange16", "large", "uneven", "single"],
                     help="uneven: 256 densities over 8^3, 12^3 and 16^3 meshes in one interleaved batch; "
                          "single: one two-Gaussian density on 4^3 elements p=3 (latency-bound)")
