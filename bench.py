@@ -44,6 +44,8 @@ def parse():
                     help="solver lanes per mesh: 2 solves a batch as two concurrent halves")
     ap.add_argument("--cheb-degree", type=int, default=None, help="smoothing steps (default: the library's)")
     ap.add_argument("--cheb-ratio", type=float, default=None, help="smoothing interval ratio (default: the library's)")
+    ap.add_argument("--cheb-degree-h", type=int, default=None,
+                    help="smoothing steps on the degree-1 coarse levels (default: the library's)")
     ap.add_argument("--inner-rtol", type=float, default=None, help="inner FP32 tolerance (default: the library's)")
     ap.add_argument("--cpu-sample", type=int, default=12, help="pair solves timed on the oracle (0: skip)")
     ap.add_argument("--check-sample", type=int, default=4, help="pairs compared with the exact solve (0: skip)")
@@ -51,7 +53,8 @@ def parse():
                     help="also run 3 device-to-device copies of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     args.solver_opts = {k: v for k, v in (("cheb_degree", args.cheb_degree), ("cheb_ratio", args.cheb_ratio),
-                                          ("inner_rtol", args.inner_rtol)) if v is not None}
+                                          ("cheb_degree_h", args.cheb_degree_h), ("inner_rtol", args.inner_rtol))
+                        if v is not None}
     return args
 
 

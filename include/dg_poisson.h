@@ -105,6 +105,8 @@ typedef struct {
                             16 right-hand sides of one mesh is solved as two halves on two
                             streams at once, so that the latency-bound coarse-level phases of
                             one half overlap the bandwidth-bound phases of the other */
+    int cheb_degree_h;   /* smoothing steps on the degree-1 levels below the finest (the
+                            mesh-coarsening part of the hierarchy); 0 = cheb_degree */
 } dg_opts;
 
 typedef struct {
@@ -120,7 +122,8 @@ typedef struct dg_ctx dg_ctx;
 
 /* Fill *opts with the defaults: automatic levels, degree 6, ratio 60,
  * safety 1.1, 30 Lanczos steps, eps 1/8, rtol 1e-8, 500 iterations, FP64,
- * inner_rtol 3e-4, max_outer 8, check_every 2, use_graph 1, lanes 2. */
+ * inner_rtol 1e-4, max_outer 8, check_every 2, use_graph 1, lanes 2,
+ * cheb_degree_h 10. */
 void dg_opts_default(dg_opts* opts);
 
 /* Build the level hierarchy, operator tables, coarsest-grid eigendata and

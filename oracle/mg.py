@@ -11,7 +11,8 @@ operators and coarsest solver are not stated.  Readings used here:
 * prolongation P is nodal interpolation of the coarse polynomial at the fine
   nodes (degree step: same element; mesh step: parent element), R = P^T;
 * smoother: Chebyshev acceleration of Jacobi, D = diag(A), of ``degree`` steps
-  on [lam_hi/ratio, lam_hi] with lam_hi = safety * (largest Ritz value of
+  (``degree_h`` on the degree-1 levels below the finest, the mesh-coarsening
+  part of the hierarchy) on [lam_hi/ratio, lam_hi] with lam_hi = safety * (largest Ritz value of
   D^{-1/2} A D^{-1/2} after ``lanczos_steps`` Lanczos steps); the same
   polynomial before and after the coarse correction, so V is symmetric;
 * coarsest level: exact fast-diagonalisation solve.
@@ -109,13 +110,15 @@ class Hierarchy:
     """Levels, transfers, smoother parameters and the V-cycle."""
 
     def __init__(self, E, p, lo, hi, n_levels=None, degree=6, ratio=60.0, safety=1.1,
-                 lanczos_steps=30, max_coarse_nodes=16, eps=_sipdg.PENALTY_EPS):
+                 lanczos_steps=30, max_coarse_nodes=16, eps=_sipdg.PENALTY_EPS, degree_h=10):
         self.specs = hierarchy(E, p, n_levels, max_coarse_nodes)
         self.levels = [Level(Es, ps, lo, hi, eps) for Es, ps in self.specs]
         self.P = []
         for lf, lc in zip(self.levels[:-1], self.levels[1:]):
             self.P.append([prolongation_1d(lf.axes[d], lc.axes[d]) for d in range(3)])
         self.degree = degree
+        self.degrees = [degree_h if (l >= 1 and ps == 1 and degree_h > 0) else degree
+                        for l, (_, ps) in enumerate(self.specs)]
         self.coarse = FDM(self.levels[-1].axes)
         self.lam = []
         for L in self.levels[:-1]:
@@ -143,9 +146,10 @@ class Hierarchy:
         rho = 1.0 / sigma1
         r = f - L.A(z)
         d = r / L.D / theta
-        for k in range(self.degree):
+        m = self.degrees[l]
+        for k in range(m):
             z = z + d
-            if k == self.degree - 1:
+            if k == m - 1:
                 break
             r = r - L.A(d)
             rho_new = 1.0 / (2.0 * sigma1 - rho)

@@ -844,7 +844,8 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
         ChebCoef C;
         C.c0 = 1.0 / theta;
         double rho = 1.0 / sigma1;
-        for (int k = 1; k < o.cheb_degree; ++k) {
+        const int degree = (l >= 1 && L.p == 1 && o.cheb_degree_h > 0) ? o.cheb_degree_h : o.cheb_degree;
+        for (int k = 1; k < degree; ++k) {
             const double rn = 1.0 / (2.0 * sigma1 - rho);
             C.cp.push_back(rn * rho);
             C.cr.push_back(2.0 * rn / delta);
@@ -903,11 +904,12 @@ void dg_opts_default(dg_opts* o) {
     o->rtol = 1e-8;
     o->max_iter = 500;
     o->precision = DG_PREC_FP64;
-    o->inner_rtol = 3e-4;
+    o->inner_rtol = 1e-4;
     o->max_outer = 8;
     o->check_every = 2;
     o->lanes = 2;
     o->use_graph = 1;
+    o->cheb_degree_h = 10;
 }
 
 const char* dg_status_string(dg_status s) {
@@ -934,7 +936,7 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
         else
             dg_opts_default(&ctx->opts);
         const auto& o = ctx->opts;
-        if (o.cheb_degree < 1 || o.cheb_ratio <= 1.0 || o.cheb_safety < 1.0 || o.lanczos_steps < 2 ||
+        if (o.cheb_degree < 1 || o.cheb_degree_h < 0 || o.cheb_ratio <= 1.0 || o.cheb_safety < 1.0 || o.lanczos_steps < 2 ||
             o.penalty_eps <= 0 || o.rtol <= 0 || o.max_iter < 1 || o.max_outer < 1 || o.inner_rtol <= 0 ||
             o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 2)
             throw ArgError("invalid solver options");

@@ -9,6 +9,10 @@ import numpy as np
 from oracle import fdm, layout, mg, sipdg
 
 PARITY_RTOL = 1e-11      # residual tolerance at which parity is claimed (oracle study: both bars met)
+# FP32 refinement: a solve that reaches 1e-11 after two refinement steps (one deep FP32
+# correction) was measured with pair-energy errors up to 3e-10 Ha on the exchange8 pairs; at
+# 1e-12 (a third FP64 residual step) both bars hold (<= 1.1e-11 potentials, <= 2e-12 Ha)
+PARITY_RTOL_FP32 = 1e-12
 POT_BAR = 1e-8           # relative M-weighted L2 error of potentials
 ENERGY_BAR = 1e-10       # hartree
 

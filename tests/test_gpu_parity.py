@@ -12,7 +12,7 @@ import pytest
 from oracle import exchange as ox, fdm, layout, mg, pcg, sipdg
 from workloads import configs, gaussians
 
-from _cases import (ENERGY_BAR, PARITY_RTOL, POT_BAR, from_em, gpu_sample, level_axes, oracle_axes,
+from _cases import (ENERGY_BAR, PARITY_RTOL, PARITY_RTOL_FP32, POT_BAR, from_em, gpu_sample, level_axes, oracle_axes,
                     oracle_density_problem, oracle_faces, oracle_grid, rel_l2_M, to_em)
 
 pytestmark = pytest.mark.gpu
@@ -215,7 +215,7 @@ def test_uneven_batch_three_meshes_matches_oracle_and_per_mesh_solves(gpu_lib):
     wl = configs.scaled(4, 4, 7, seed=33)
     ids = [2, 0, 1, 2, 0, 1, 1]
     dens = [wl.batch.densities[k] for k in range(len(ids))]
-    ctx = gpu_lib.Context([(m.E, m.p, m.lo, m.hi) for m in meshes], rtol=PARITY_RTOL, precision="fp32_ir")
+    ctx = gpu_lib.Context([(m.E, m.p, m.lo, m.hi) for m in meshes], rtol=PARITY_RTOL_FP32, precision="fp32_ir")
     rho, g = [], []
     for k, mid in enumerate(ids):
         r_, g_ = gpu_sample(ctx, mid, dens[k])
@@ -317,7 +317,7 @@ def test_exchange_matches_oracle(gpu_lib):
 def test_mixed_precision_refinement_reaches_fp64_accuracy(gpu_lib):
     wl = configs.scaled(6, 4, 2, seed=31)
     mesh = wl.meshes[0]
-    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=PARITY_RTOL, precision="fp32_ir")
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=PARITY_RTOL_FP32, precision="fp32_ir")
     rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
     v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
     v = _n(v).reshape(2, -1)
