@@ -11,7 +11,7 @@ batched solve and the exchange reductions) with all inputs resident in HBM.
 Arms: ``fp32_ir`` (FP32 inner PCG inside FP64 iterative refinement; the
 headline ``value``) and ``fp64`` (plain FP64 MG-PCG; reported beside it).
 
-Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the measurement is of one GPU.
 """
 import argparse
 import json
@@ -61,7 +61,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
+        print(json.dumps({"error": "only one GPU is measured; run with --gpus 1"}))
         sys.exit(2)
     import numpy as np
     import torch

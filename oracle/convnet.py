@@ -1,7 +1,7 @@
 """Reference U-Net for the learned initial guess (test infrastructure only).
 
-The learned part is not in the paper; its network is fixed by this build's
-specification: a 3D U-Net on the element grid of the auxiliary mesh.  The
+The learned part is not in the paper; its network is fixed here as a 3D
+U-Net on the element grid of the auxiliary mesh.  The
 input has one channel per node of an element (the nodal values of rho/s,
 s a per-sample scale), the output one channel per node (the nodal values of
 v/s).  With channels last, the element-major field order of the library is

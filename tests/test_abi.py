@@ -23,7 +23,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("libdgpoisson.so is not built (run __graft_entry__.build())")
+        pytest.fail("libdgpoisson.so is not built (run paper_2510_21213_amd/build.py)")
     return ctypes.CDLL(LIB)
 
 
