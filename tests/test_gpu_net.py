@@ -12,7 +12,7 @@ import pytest
 from oracle import convnet, layout, sipdg
 from workloads import configs
 
-from _cases import POT_BAR, gpu_sample, oracle_density_problem, rel_l2_M
+from _cases import PARITY_RTOL_FP32, POT_BAR, gpu_sample, oracle_density_problem, rel_l2_M
 
 pytestmark = pytest.mark.gpu
 
@@ -207,3 +207,42 @@ def test_guard_on_device_with_zero_source_in_the_batch(gpu_lib, precision):
     v1, st1 = ctx.solve_batch(rho, g)
     assert [s["iters"] for s in st1] == [s["iters"] for s in st0]
     assert [s["outer_iters"] for s in st1] == [s["outer_iters"] for s in st0]
+
+
+def test_guess_in_a_batch_over_two_meshes(gpu_lib):
+    """A learned guess for an interleaved batch over two p = 4 meshes (the network runs once
+    per mesh inside the call): every potential against the exact solve, and bitwise equal to
+    one call per mesh with the same network."""
+    import torch
+    from oracle import fdm
+    m0 = configs.Mesh((4, 4, 4), 4, (-2.0,) * 3, (2.0,) * 3)
+    m1 = configs.Mesh((6, 4, 6), 4, (-3.0, -2.0, -3.0), (3.0, 2.0, 3.0))
+    dens = configs.scaled(4, 4, 5, seed=53).batch.densities
+    ctx = gpu_lib.Context([(m.E, m.p, m.lo, m.hi) for m in (m0, m1)], rtol=PARITY_RTOL_FP32, precision="fp32_ir")
+    net = gpu_lib.Net(3, 8, 125, 27)
+    net.set_params((0.05 * np.random.default_rng(6).standard_normal(net.num_params)).astype(np.float32))
+    ctx.attach_guess(net)
+    ids = [1, 0, 1, 0, 1]
+    samples = [gpu_sample(ctx, mid, dens[k]) for k, mid in enumerate(ids)]
+    v, st = ctx.solve_batch(_t(np.concatenate([s[0] for s in samples])), _t(np.concatenate([s[1] for s in samples])),
+                            mesh_ids=ids)
+    v = v.cpu().numpy()
+    off, parts = 0, {0: [], 1: []}
+    for k, mid in enumerate(ids):
+        mesh = (m0, m1)[mid]
+        n = ctx.info[mid]["n_dofs"]
+        axes, _, _, b = oracle_density_problem(mesh, dens[k])
+        assert rel_l2_M(axes, mesh, v[off:off + n], fdm.FDM(axes).solve(b)) <= POT_BAR
+        assert st[k]["status"] == 0 and st[k]["guess_used"] in (0, 1)
+        parts[mid].append((k, off, n))
+        off += n
+    for mid, ks in parts.items():
+        r = _t(np.concatenate([samples[k][0] for k, _, _ in ks]))
+        g = _t(np.concatenate([samples[k][1] for k, _, _ in ks]))
+        vm, stm = ctx.solve_batch(r, g, mesh_ids=[mid] * len(ks))
+        vm = vm.cpu().numpy()
+        o2 = 0
+        for (k, o, n), s in zip(ks, stm):
+            assert np.array_equal(vm[o2:o2 + n], v[o:o + n])
+            assert s["iters"] == st[k]["iters"] and s["guess_used"] == st[k]["guess_used"]
+            o2 += n
