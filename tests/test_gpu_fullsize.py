@@ -108,3 +108,39 @@ def test_exchange8_parity_tolerance_fp64(gpu_lib, workload, oracle_sample):
 
 def test_exchange8_bench_tolerance_bench_configuration(gpu_lib, workload, oracle_sample):
     _check(gpu_lib, workload, oracle_sample, workload.rtol, BENCH_POT_BAR, BENCH_ENERGY_BAR)
+
+
+def test_trained_guess_saves_iterations_on_a_molecule_outside_its_training_set(gpu_lib, workload):
+    """The benchmark molecule (seed 2) is not among the training molecules (seeds 10000+i):
+    with the trained network every guess passes the guard and the mean iteration count at
+    the benchmark tolerance drops by at least one against the same solver without it."""
+    K_g, _, st_g, _, _ = _solve(gpu_lib, workload, workload.rtol)
+    K_0, _, st_0, _, _ = _solve(gpu_lib, workload, workload.rtol, learned=False)
+    assert all(s["guess_used"] == 1 for s in st_g) and not any(s["guess_used"] for s in st_0)
+    it_g = np.mean([s["iters"] for s in st_g])
+    it_0 = np.mean([s["iters"] for s in st_0])
+    assert it_g <= it_0 - 1.0, (it_g, it_0)
+    assert np.abs(K_g - K_0).max() <= BENCH_ENERGY_BAR
+
+
+def test_large_mesh_five_levels_sampled_sources(gpu_lib):
+    """The 32^3-element, p = 4 mesh with 5 levels (two mesh-coarsening levels below the degree
+    steps), 16 Gaussian-sum sources in one call (two solver lanes), FP32 refinement with the
+    guess network trained for this mesh: two sampled potentials against the oracle's exact
+    solve at the parity tolerance."""
+    from oracle import fdm
+    from _cases import gpu_sample, oracle_density_problem
+    wl = configs.scaled(32, 4, 16, seed=71, n_levels=5)
+    mesh = wl.meshes[0]
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=5, rtol=PARITY_RTOL_FP32, precision="fp32_ir")
+    assert ctx.opts.lanes == 2
+    net = gpu_lib.Net(4, 32, 125, 27)
+    net.load(WEIGHTS.replace("guess_16e_p4", "guess_32e_p4"))
+    ctx.attach_guess(net)
+    rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+    v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
+    assert all(s["status"] == 0 and s["rel_residual"] <= PARITY_RTOL_FP32 for s in st)
+    v = v.cpu().numpy().reshape(16, -1)
+    for k in (3, 12):      # one source of each lane
+        axes, _, _, b = oracle_density_problem(mesh, wl.batch.densities[k])
+        assert rel_l2_M(axes, mesh, v[k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
