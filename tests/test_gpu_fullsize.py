@@ -144,3 +144,29 @@ def test_large_mesh_five_levels_sampled_sources(gpu_lib):
     for k in (3, 12):      # one source of each lane
         axes, _, _, b = oracle_density_problem(mesh, wl.batch.densities[k])
         assert rel_l2_M(axes, mesh, v[k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
+
+
+def test_exchange16_largest_batch_bench_tolerance(gpu_lib):
+    """The largest batch of the workloads: 16 orbitals, 136 pair densities on the 16^3, p = 4
+    mesh in one call (two lanes of 68, FP32 refinement, trained guess) at the benchmark
+    tolerance: sampled pairs against the oracle's exact solve, E_x from the returned energies."""
+    wl = configs.exchange16()
+    mesh, orb = wl.meshes[0], wl.orbitals
+    K, EX, st, v, _ = _solve(gpu_lib, wl, wl.rtol)
+    n = orb.norb
+    assert len(st) == n * (n + 1) // 2 == 136
+    assert all(s["status"] == 0 and s["rel_residual"] <= wl.rtol for s in st)
+    ex = sum(K[ox.pair_index(i, i, n)] for i in range(n)) + \
+        2.0 * sum(K[ox.pair_index(i, j, n)] for i in range(n) for j in range(i + 1, n))
+    assert abs(EX - ex) <= 1e-12 * abs(ex)
+    axes = oracle_axes(mesh)
+    X, Y, Z = oracle_grid(axes)
+    phi = orb.values(X, Y, Z)
+    faces = oracle_faces(axes, lambda a, b, c: orb.pair_potentials(a.reshape(-1), b.reshape(-1), c.reshape(-1)))
+    i, j = 2, 13
+    qs = [ox.pair_index(a, b, n) for a, b in ((i, i), (i, j), (j, j))]
+    fp = [[faces[f][q].reshape(axes[2].N if f < 4 else axes[1].N, -1) for f in range(6)] for q in qs]
+    v_o, _, K_o, _ = ox.exchange(axes, [phi[i], phi[j]], fp, fdm.FDM(axes).solve)
+    for q, vq, Kq in zip(qs, v_o, K_o):
+        assert rel_l2_M(axes, mesh, v[q], vq) <= BENCH_POT_BAR, q
+        assert abs(K[q] - Kq) <= BENCH_ENERGY_BAR, q
