@@ -26,6 +26,8 @@ electronic structure"):
 * ``pcg``       -- V-cycle preconditioned conjugate gradients (Sec. 6.4).
 * ``exchange``  -- pair densities, exchange potentials W_k and pair energies
                    K_ij (Sec. 6.1, eq. fock_poisson).
+* ``boundary``  -- Dirichlet data by quadrature of the source over the grid
+                   (Sec. 6.3): g(r) = sum_q W_q f(x_q)/|r - x_q| at the boundary nodes.
 * ``layout``    -- conversion between the element-major storage order of the
                    library and the global tensor order used here.
 
