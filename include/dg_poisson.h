@@ -154,7 +154,8 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
 /* Exchange step for norb orbitals phi (packed fields [norb][n_dofs]) on one
  * mesh (Sec. 6.1, eq. fock_poisson): for every pair i <= j the pair density
  * rho_ij = phi_i phi_j is the source of one Poisson problem with Dirichlet
- * data g_pairs (packed face vectors, pair order); then
+ * data g_pairs (packed face vectors, pair order; NULL: computed from the pair
+ * densities by quadrature, as dg_boundary_data does); then
  *   W_k  = sum_s phi_s v_ks        (device [norb][n_dofs], the exchange action
  *                                   on u = phi_k at the nodes, positive sign),
  *   K_ij = sum_nodes w rho_ij v_ij (device [npairs], GLL quadrature),
@@ -164,6 +165,20 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
 dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* phi, const double* g_pairs,
                             double* W, double* K_pairs, double* E_x, double* v_pairs,
                             dg_rhs_stats* stats, hipStream_t stream);
+
+/* Dirichlet data by quadrature (Sec. 6.3): the full-space problem -Lap u =
+ * 4 pi f is restated on the mesh box with boundary values equal to the
+ * Coulomb potential of f, evaluated with the quadrature rule of the mesh's
+ * nodal grid (GLL weights, the lumped mass W):
+ *   g_s(r) = sum over the nodes x of W(x) f_s(x) / |r - x|,  r a boundary node.
+ * f: device [nsrc][n_dofs] (packed fields, field order); g: device
+ * [nsrc][n_face] (packed face vectors, face order), written.  The term of a
+ * node at the boundary node itself (closer than 1e-6 of the smallest element
+ * width) is left out: the method has f vanish on the boundary.  FP64
+ * throughout; cost n_face * n_dofs terms per source.  Enqueued on `stream`
+ * (no synchronisation); work space is held by the context.  Errors:
+ * DG_ERR_ARG for nsrc < 0 or null pointers with nsrc > 0. */
+dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g, hipStream_t stream);
 
 /* ---- single steps of the path, exposed for verification and profiling ----
  * All operate on nrhs packed FP64 fields of one mesh at multigrid level

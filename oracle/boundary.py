@@ -33,7 +33,7 @@ def drop_radius(axes):
     return COINCIDENT * min(ax.h for ax in axes)
 
 
-def potential_at(axes, f, points, chunk=16):
+def potential_at(axes, f, points, chunk=None):
     """g at arbitrary points.
 
     f: sources sampled at the nodes, array [..., Z, Y, X] (leading axes are
@@ -47,6 +47,8 @@ def potential_at(axes, f, points, chunk=16):
     pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
     out = np.empty((pts.shape[0], F.shape[1]))
     rmin = drop_radius(axes)
+    if chunk is None:                      # rows per block of the distance matrix (memory only)
+        chunk = int(max(16, min(256, 2e7 // xq.shape[0])))
     for s in range(0, pts.shape[0], chunk):
         d = np.sqrt(np.sum((pts[s:s + chunk, None, :] - xq[None, :, :]) ** 2, axis=-1))    # [c, N]
         K = np.where(d > rmin, 1.0 / np.where(d > rmin, d, 1.0), 0.0)

@@ -63,6 +63,7 @@ def _load():
         "dg_operator_apply_f32": (I, [P, I, I, I, P, P, P]),
         "dg_vcycle_apply_f32": (I, [P, I, I, I, P, P, P]),
         "dg_rhs_assemble": (I, [P, I, I, P, P, P, P]),
+        "dg_boundary_data": (I, [P, I, I, P, P, P]),
         "dg_vcycle_apply": (I, [P, I, I, I, P, P, P]),
         "dg_coarse_solve": (I, [P, I, I, P, P, P]),
         "dg_restrict": (I, [P, I, I, I, P, P, P]),
@@ -213,11 +214,11 @@ class Context:
         return out, [_stats(stats[i]) for i in range(nrhs)]
 
     def exchange(self, phi, g_pairs, mesh_id=0, keep_potentials=False):
-        """Returns (W, K, E_x, stats, v or None)."""
+        """Returns (W, K, E_x, stats, v or None).  g_pairs None: Dirichlet data by quadrature."""
         nd = self.info[mesh_id]["n_dofs"]
         norb = phi.numel() // nd
         npairs = norb * (norb + 1) // 2
-        if g_pairs.numel() != npairs * self.info[mesh_id]["n_face"]:
+        if g_pairs is not None and g_pairs.numel() != npairs * self.info[mesh_id]["n_face"]:
             raise ValueError("g_pairs has the wrong size")
         W = torch.empty(norb * nd, dtype=torch.float64, device=phi.device)
         K = torch.empty(npairs, dtype=torch.float64, device=phi.device)
@@ -258,6 +259,16 @@ class Context:
         b = torch.empty_like(rho)
         _check(lib.dg_rhs_assemble(self._h, mesh_id, nrhs, _ptr(rho), _ptr(g), _ptr(b), _stream()), "rhs_assemble")
         return b
+
+    def boundary_data(self, f, mesh_id=0):
+        """Dirichlet data g (packed face vectors) of the packed sources f by quadrature."""
+        nd, nf = self.info[mesh_id]["n_dofs"], self.info[mesh_id]["n_face"]
+        if f.numel() % nd:
+            raise ValueError("f is not a whole number of fields")
+        nsrc = f.numel() // nd
+        g = torch.empty(nsrc * nf, dtype=torch.float64, device=f.device)
+        _check(lib.dg_boundary_data(self._h, mesh_id, nsrc, _ptr(f), _ptr(g), _stream()), "boundary_data")
+        return g
 
     def vcycle(self, r, mesh_id=0, level=0):
         nrhs = r.numel() // self._level_dofs(mesh_id, level)

@@ -134,6 +134,7 @@ struct dg_ctx {
         bool owns_tables = true;
         double *grho = nullptr, *gface = nullptr, *gx0 = nullptr, *gv = nullptr;
         int cap_g = 0;
+        double* qnodes = nullptr;  // node coordinates per axis (quadrature Dirichlet data), built on first use
     };
     std::vector<Mesh> meshes;
     std::vector<Mesh> twins;       // second solver lane of each mesh (empty with one lane)
@@ -162,6 +163,13 @@ struct dg_ctx {
     long long xpart_cap = 0;
     int* xpairs = nullptr;
     int xpairs_cap = 0;
+    // quadrature Dirichlet data work space: packed source tile, split partial sums, pair data
+    double* qrec = nullptr;
+    long long qrec_cap = 0;
+    double* qpart = nullptr;
+    long long qpart_cap = 0;
+    double* qg = nullptr;
+    long long qg_cap = 0;
 };
 
 namespace {
@@ -477,6 +485,38 @@ void leave(dg_ctx* ctx, hipStream_t user) {
 void check_mesh_id(const dg_ctx* ctx, int mesh_id) {
     if (!ctx) throw ArgError("null context");
     if (mesh_id < 0 || mesh_id >= (int)ctx->meshes.size()) throw ArgError("mesh_id out of range");
+}
+
+void ensure_len(double*& p, long long& cap, long long n) {
+    if (cap >= n) return;
+    dfree(p);
+    p = dalloc<double>(n);
+    cap = n;
+}
+
+// Dirichlet data by quadrature (Sec. 6.3) of nsrc sources of mesh M into g (device
+// [nsrc][n_face]): the sources are the fields f, or with f null the pair products of phi.
+void quad_data(dg_ctx* ctx, Mesh& M, int nsrc, const double* f, const double* phi, const int* pi, const int* pj,
+               double* g, hipStream_t s) {
+    const LevelHost& L0 = M.lv[0];
+    if (!M.qnodes) {
+        std::vector<double> all;
+        for (int d = 0; d < 3; ++d) {
+            dg::AxisDev<double> ax;
+            std::vector<double> nodes;
+            dg::build_axis(M.mesh.ne[d], M.mesh.p, M.mesh.lo[d], M.mesh.hi[d], ctx->opts.penalty_eps, ax, nullptr,
+                           &nodes);
+            all.insert(all.end(), nodes.begin(), nodes.end());
+        }
+        double* d = dalloc<double>((long long)all.size());
+        HIPCHK(hipMemcpy(d, all.data(), sizeof(double) * all.size(), hipMemcpyHostToDevice));
+        M.qnodes = d;
+    }
+    const dg::QuadPlan P = dg::quad_plan(L0, nsrc);
+    if (P.nface != M.nface) throw std::logic_error("quadrature plan: face count mismatch");
+    ensure_len(ctx->qrec, ctx->qrec_cap, P.rec_len);
+    ensure_len(ctx->qpart, ctx->qpart_cap, P.part_len);
+    dg::launch_quad_data(L0, L0.dev64, M.qnodes, P, nsrc, f, phi, pi, pj, ctx->qrec, ctx->qpart, g, s);
 }
 
 // Learned guess for nrhs sources rho of mesh M: writes ctx->g_x0 (the solve's guard
@@ -1001,6 +1041,7 @@ void dg_poisson_destroy(dg_ctx* ctx) {
         dfree(M.gface);
         dfree(M.gx0);
         dfree(M.gv);
+        dfree(M.qnodes);
         if (M.ev_done) (void)hipEventDestroy(M.ev_done);
         if (M.stream) (void)hipStreamDestroy(M.stream);
         for (auto e : M.pev) (void)hipEventDestroy(e);
@@ -1022,6 +1063,9 @@ void dg_poisson_destroy(dg_ctx* ctx) {
     dfree(ctx->xv);
     dfree(ctx->xpart);
     dfree(ctx->xpairs);
+    dfree(ctx->qrec);
+    dfree(ctx->qpart);
+    dfree(ctx->qg);
     delete ctx;
 }
 
@@ -1245,7 +1289,7 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
         check_mesh_id(ctx, mesh_id);
         g_prof = &ctx->prof;
         if (norb < 1 || norb > 32) throw ArgError("norb must be in 1..32");
-        if (!phi || !g_pairs || !W || !K_pairs) throw ArgError("null pointer argument");
+        if (!phi || !W || !K_pairs) throw ArgError("null pointer argument");
         const hipStream_t user = stream;
         stream = enter(ctx, user);
         Mesh& M = ctx->meshes[mesh_id];
@@ -1274,6 +1318,11 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
             v = ctx->xv;
         }
         ensure_b(M, npairs, ctx->opts.precision == DG_PREC_FP32_IR);
+        if (!g_pairs) {
+            ensure_len(ctx->qg, ctx->qg_cap, (long long)npairs * M.nface);
+            quad_data(ctx, M, npairs, nullptr, phi, ctx->xpairs, ctx->xpairs + npairs, ctx->qg, stream);
+            g_pairs = ctx->qg;
+        }
         dg::launch_rhs(M.lv[0], M.lv[0].dev64, npairs, nullptr, phi, ctx->xpairs, ctx->xpairs + npairs, g_pairs,
                        M.nface, M.b, stream);
         if (ctx->guess) {
@@ -1318,6 +1367,16 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
             if (stats[i].status != DG_OK) return DG_WARN_NOT_CONVERGED;
     }
     return st;
+}
+
+dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g, hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        if (nsrc < 0 || (nsrc > 0 && (!f || !g))) throw ArgError("bad arguments");
+        if (nsrc == 0) return;
+        quad_data(ctx, ctx->meshes[mesh_id], nsrc, f, nullptr, nullptr, nullptr, g, stream);
+        HIPCHK(hipGetLastError());
+    });
 }
 
 dg_status dg_operator_apply(dg_ctx* ctx, int mesh_id, int level, int nrhs, const double* u, double* y,

@@ -1,0 +1,230 @@
+// Dirichlet data of the auxiliary-mesh Poisson problem by quadrature (Sec. 6.3).
+//
+// The full-space problem -Lap u = 4 pi f is restated on the mesh domain with
+// Dirichlet data equal to the Coulomb potential of f on the boundary, and that
+// integral is evaluated with the quadrature rule of the mesh's own nodal grid
+// (here the GLL grid, whose weights are the lumped mass W_q):
+//
+//     g(r) = sum_q W_q f(x_q) / |r - x_q|      for every boundary node r.
+//
+// Every boundary node is itself a grid node (and, on an element face, also the
+// node of the neighbouring element at the same place), where the integrand is
+// singular; the method has f vanish there, so terms closer than a millionth of
+// the smallest element width are left out.
+//
+// Work per source: n_face * n_dofs pair terms, a dense FP64 boundary-by-volume
+// sum bound by FP64 vector issue.  The kernels are laid out for that:
+//  * k_quad_pack writes, for a tile of R sources, the records W_q f_s(x_q)
+//    (s in the tile) in lattice order of the grid nodes [Z][Y][X];
+//  * in k_quad each lane owns one boundary node and the R sums of the tile;
+//    all lanes visit the grid nodes in the same order, so the node's x
+//    coordinate and its R weighted values are wave-uniform and are read with
+//    scalar loads into SGPR operands of the FMAs;
+//  * the squared distance is built per lattice row: dy^2 + dz^2 once, then one
+//    FMA per node; 1/|r| is the hardware reciprocal square root refined by one
+//    Newton step;
+//  * only rows on the boundary surface of the lattice (and the first and last
+//    node of the other rows) can hold a coincident node, so only those terms
+//    pay for the distance test;
+//  * the Z planes are split over the grid's y dimension so that a launch fills
+//    the chip; the split partial sums are added in a fixed order by k_quad_sum.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <stdexcept>
+
+#include "dg_internal.h"
+#include "dg_kernels.h"
+
+namespace dg {
+
+namespace {
+
+constexpr int QUAD_RMAX = 48;      // sources per tile (accumulators per lane)
+constexpr int QUAD_WAVES = 8192;   // waves a launch aims for (8 per SIMD)
+
+__global__ __launch_bounds__(256) void k_quad_pack(const LevelDev<double>* __restrict__ dev, int Ex, int Ey, int n,
+                                                   long long ndof, int NX, int NY, int nsrc, int r0, int R,
+                                                   const double* __restrict__ f, const double* __restrict__ phi,
+                                                   const int* __restrict__ pi, const int* __restrict__ pj,
+                                                   double* __restrict__ rec) {
+    const long long q = blockIdx.x * 256LL + threadIdx.x;
+    if (q >= ndof) return;
+    const int n3 = n * n * n;
+    const long long e = q / n3;
+    const int l = (int)(q - e * n3);
+    const int i = l % n, j = (l / n) % n, k = l / (n * n);
+    const int ex = (int)(e % Ex), ey = (int)((e / Ex) % Ey), ez = (int)(e / ((long long)Ex * Ey));
+    const double w = dev->ax[0].m[i] * dev->ax[1].m[j] * dev->ax[2].m[k];
+    const long long G = (ex * n + i) + (long long)NX * ((ey * n + j) + (long long)NY * (ez * n + k));
+    double* out = rec + G * R;
+    for (int r = 0; r < R; ++r) {
+        const int s = r0 + r;
+        double v = 0.0;
+        if (s < nsrc)
+            v = w * (f ? f[(long long)s * ndof + q] : phi[(long long)pi[s] * ndof + q] * phi[(long long)pj[s] * ndof + q]);
+        out[r] = v;
+    }
+}
+
+// 1/|r - x_q| for the lane's boundary node at squared distance d2 + (bx - xq)^2; with MASK,
+// 0 for a node at the boundary node itself.
+template <bool MASK>
+__device__ __forceinline__ double inv_dist(double bx, double d2, double xq, double drop2) {
+    const double dx = bx - xq;
+    const double r2 = fma(dx, dx, d2);
+    double y = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-(r2 * y), y, 1.0);      // Newton step for 1/sqrt: y (1 + e/2)
+    y = fma(0.5 * y, e, y);
+    if (MASK) y = r2 > drop2 ? y : 0.0;
+    return y;
+}
+
+// acc += sum over the row's nodes x0 <= xq < x1 of (W f)_xq / |r - x_q|.  The inverse
+// distances of four nodes are formed together (independent chains, one scalar load of
+// their coordinates), then their R weighted values are read as wave-uniform operands.
+template <int R, bool MASK>
+__device__ __forceinline__ void quad_run(double bx, double d2, const double* __restrict__ xs,
+                                         const double* __restrict__ row, int x0, int x1, double drop2,
+                                         double (&acc)[R]) {
+    int xq = x0;
+    for (; xq + 4 <= x1; xq += 4) {
+        double y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = inv_dist<MASK>(bx, d2, xs[xq + u], drop2);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double* wf = row + (long long)(xq + u) * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = fma(wf[r], y[u], acc[r]);
+        }
+    }
+    for (; xq < x1; ++xq) {
+        const double y = inv_dist<MASK>(bx, d2, xs[xq], drop2);
+        const double* wf = row + (long long)xq * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(wf[r], y, acc[r]);
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_quad(const double* __restrict__ xs, const double* __restrict__ ys,
+                                              const double* __restrict__ zs, int NX, int NY, int NZ, int nface,
+                                              int zper, double drop2, const double* __restrict__ rec,
+                                              double* __restrict__ out, int nsrc, int r0, int direct) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int bb = b < nface ? b : nface - 1;
+    // boundary node -> lattice indices (face order x-, x+ [Z][Y]; y-, y+ [Z][X]; z-, z+ [Y][X])
+    int X, Y, Z;
+    const int fx = NZ * NY, fy = NZ * NX, fz = NY * NX;
+    if (bb < 2 * fx) {
+        const int side = bb >= fx, rem = bb - side * fx;
+        Z = rem / NY; Y = rem % NY; X = side ? NX - 1 : 0;
+    } else if (bb < 2 * fx + 2 * fy) {
+        const int t = bb - 2 * fx, side = t >= fy, rem = t - side * fy;
+        Z = rem / NX; X = rem % NX; Y = side ? NY - 1 : 0;
+    } else {
+        const int t = bb - 2 * fx - 2 * fy, side = t >= fz, rem = t - side * fz;
+        Y = rem / NX; X = rem % NX; Z = side ? NZ - 1 : 0;
+    }
+    const double bx = xs[X], by = ys[Y], bz = zs[Z];
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    const int z0 = blockIdx.y * zper, z1 = min(NZ, z0 + zper);
+    for (int zq = z0; zq < z1; ++zq) {
+        const double dz = bz - zs[zq];
+        const double dz2 = dz * dz;
+        const bool zedge = zq == 0 || zq == NZ - 1;
+        for (int yq = 0; yq < NY; ++yq) {
+            const double dy = by - ys[yq];
+            const double d2 = fma(dy, dy, dz2);
+            const double* row = rec + ((long long)zq * NY + yq) * NX * R;
+            // a row on the lattice's boundary surface is tested node by node; any other row
+            // only at its two end nodes (x faces).  Three consecutive ranges, no branches,
+            // so that one set of accumulators serves all of them.
+            const bool edge = zedge || yq == 0 || yq == NY - 1;
+            const int m1 = edge ? NX : 1, u1 = edge ? NX : NX - 1;
+            quad_run<R, true>(bx, d2, xs, row, 0, m1, drop2, acc);
+            quad_run<R, false>(bx, d2, xs, row, m1, u1, drop2, acc);
+            quad_run<R, true>(bx, d2, xs, row, u1, NX, drop2, acc);
+        }
+    }
+    if (b >= nface) return;
+    // direct: out is g [nsrc][nface]; else the split's partial sums [split][R][nface]
+    double* o = direct ? out + (long long)r0 * nface + b : out + (long long)blockIdx.y * R * nface + b;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r0 + r < nsrc) o[(long long)r * nface] = acc[r];
+}
+
+__global__ __launch_bounds__(256) void k_quad_sum(const double* __restrict__ part, int S, int R, int nface,
+                                                  int nsrc, int r0, double* __restrict__ g) {
+    const long long t = blockIdx.x * 256LL + threadIdx.x;
+    const int nr = min(R, nsrc - r0);
+    if (t >= (long long)nr * nface) return;
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) acc += part[(long long)s * R * nface + t];
+    g[(long long)r0 * nface + t] = acc;
+}
+
+template <int R>
+void launch_quad_r(dim3 grid, const double* nodes, int NX, int NY, int NZ, int nface, int zper, double drop2,
+                   const double* rec, double* out, int nsrc, int r0, int direct, hipStream_t s) {
+    hipLaunchKernelGGL(k_quad<R>, grid, dim3(256), 0, s, nodes, nodes + NX, nodes + NX + NY, NX, NY, NZ, nface, zper,
+                       drop2, rec, out, nsrc, r0, direct);
+}
+
+}  // namespace
+
+QuadPlan quad_plan(const LevelHost& L, int nsrc) {
+    QuadPlan P{};
+    const long long NX = (long long)L.E[0] * L.n, NY = (long long)L.E[1] * L.n, NZ = (long long)L.E[2] * L.n;
+    P.nface = 2 * (NZ * NY + NZ * NX + NY * NX);
+    P.ntile = std::max(1, (nsrc + QUAD_RMAX - 1) / QUAD_RMAX);
+    const int per = (nsrc + P.ntile - 1) / P.ntile;
+    P.R = std::max(4, (per + 3) / 4 * 4);
+    const long long blocks = (P.nface + 255) / 256;
+    const long long want = (QUAD_WAVES + 4 * blocks - 1) / (4 * blocks);
+    const int S0 = (int)std::max(1LL, std::min(NZ, want));
+    P.zper = (int)((NZ + S0 - 1) / S0);
+    P.S = (int)((NZ + P.zper - 1) / P.zper);
+    P.rec_len = L.ndof * P.R;
+    P.part_len = P.S > 1 ? (long long)P.S * P.R * P.nface : 0;
+    return P;
+}
+
+void launch_quad_data(const LevelHost& L, const LevelDev<double>* dev, const double* nodes, const QuadPlan& P,
+                      int nsrc, const double* f, const double* phi, const int* pi, const int* pj, double* rec,
+                      double* part, double* g, hipStream_t s) {
+    if (nsrc <= 0) return;
+    const int NX = L.E[0] * L.n, NY = L.E[1] * L.n, NZ = L.E[2] * L.n;
+    if (P.nface != 2 * ((long long)NZ * NY + (long long)NZ * NX + (long long)NY * NX) || P.nface > (1LL << 30) ||
+        P.R < 4 || P.R > QUAD_RMAX || P.R % 4 || (P.S > 1 && !part) || (long long)P.S * P.zper < NZ)
+        throw std::logic_error("quadrature plan does not fit the mesh");
+    const double hmin = std::min({L.h[0], L.h[1], L.h[2]});
+    const double drop2 = (1e-6 * hmin) * (1e-6 * hmin);
+    const int nface = (int)P.nface;
+    const dim3 grid((unsigned)((nface + 255) / 256), (unsigned)P.S);
+    for (int r0 = 0; r0 < nsrc; r0 += P.R) {
+        hipLaunchKernelGGL(k_quad_pack, dim3((unsigned)((L.ndof + 255) / 256)), dim3(256), 0, s, dev, L.E[0], L.E[1],
+                           L.n, L.ndof, NX, NY, nsrc, r0, P.R, f, phi, pi, pj, rec);
+        const int direct = P.S == 1;
+        double* out = direct ? g : part;
+        switch (P.R) {
+#define QUAD_CASE(RR) \
+    case RR: launch_quad_r<RR>(grid, nodes, NX, NY, NZ, nface, P.zper, drop2, rec, out, nsrc, r0, direct, s); break;
+            QUAD_CASE(4) QUAD_CASE(8) QUAD_CASE(12) QUAD_CASE(16) QUAD_CASE(20) QUAD_CASE(24)
+            QUAD_CASE(28) QUAD_CASE(32) QUAD_CASE(36) QUAD_CASE(40) QUAD_CASE(44) QUAD_CASE(48)
+#undef QUAD_CASE
+            default: throw std::logic_error("no quadrature kernel for this tile");
+        }
+        if (!direct) {
+            const long long cnt = (long long)std::min(P.R, nsrc - r0) * nface;
+            hipLaunchKernelGGL(k_quad_sum, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, part, P.S, P.R,
+                               nface, nsrc, r0, g);
+        }
+    }
+}
+
+}  // namespace dg

@@ -127,4 +127,18 @@ void launch_segcopy(const double* src, const long long* soff, double* dst, const
 // K[q] = sum of partial[q][0..nblk-1] (fixed order).
 void launch_sum_partials(int nq, const double* partial, int pstride, int nblk, double* K, hipStream_t s);
 
+// Dirichlet data by quadrature (dg_boundary.hip): g[s][b] = sum_q W_q f_s(x_q) / |r_b - x_q| over the
+// finest level's nodes, for nsrc sources f (packed fields) or, with f null, the pair products
+// phi[pi[s]] phi[pj[s]].  Sources go in tiles of R; each tile is packed into rec (rec_len
+// doubles) and its Z planes are split S ways (partial sums in part, part_len doubles).
+struct QuadPlan {
+    int R, ntile, S, zper;
+    long long nface, rec_len, part_len;
+};
+QuadPlan quad_plan(const LevelHost& L, int nsrc);
+// nodes: the node coordinates per axis, x[NX] then y[NY] then z[NZ] (device).
+void launch_quad_data(const LevelHost& L, const LevelDev<double>* dev, const double* nodes, const QuadPlan& P,
+                      int nsrc, const double* f, const double* phi, const int* pi, const int* pj, double* rec,
+                      double* part, double* g, hipStream_t s);
+
 }  // namespace dg
