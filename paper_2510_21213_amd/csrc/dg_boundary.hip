@@ -21,13 +21,15 @@
 //    coordinate and its R weighted values are wave-uniform and are read with
 //    scalar loads into SGPR operands of the FMAs;
 //  * the squared distance is built per lattice row: dy^2 + dz^2 once, then one
-//    FMA per node; 1/|r| is the hardware reciprocal square root refined by one
-//    Newton step;
+//    FMA per node; 1/|r| is the hardware reciprocal square root refined by the
+//    first two terms of its error series;
 //  * only rows on the boundary surface of the lattice (and the first and last
 //    node of the other rows) can hold a coincident node, so only those terms
 //    pay for the distance test;
-//  * the Z planes are split over the grid's y dimension so that a launch fills
-//    the chip; the split partial sums are added in a fixed order by k_quad_sum.
+//  * the Z planes are split into parts so that a launch holds several rounds of
+//    resident waves; the parts' partial sums are added in a fixed order by
+//    k_quad_sum.  Work-groups are ordered so that each XCD takes the boundary
+//    tiles of one part at a time: they stream the same records through its L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,7 +43,12 @@ namespace dg {
 namespace {
 
 constexpr int QUAD_RMAX = 48;      // sources per tile (accumulators per lane)
-constexpr int QUAD_WAVES = 8192;   // waves a launch aims for (8 per SIMD)
+// waves a launch aims for: 32 per SIMD, several rounds of the waves that fit at once (the loop
+// waits on scalar loads, so waves queued behind the resident ones keep the SIMDs fed; measured
+// on the 36 pair densities of 16^3 elements, p = 4: 8 per SIMD 44.3 ms, 16 38.2, 32 36.9, 64 38.4)
+constexpr int QUAD_WAVES = 32768;
+constexpr int QUAD_BLOCK = 256;    // threads per workgroup (its waves read the same records)
+constexpr int QUAD_NB = 1;         // boundary nodes per lane (each scalar-loaded value feeds QUAD_NB FMAs)
 
 __global__ __launch_bounds__(256) void k_quad_pack(const LevelDev<double>* __restrict__ dev, int Ex, int Ey, int n,
                                                    long long ndof, int NX, int NY, int nsrc, int r0, int R,
@@ -73,49 +80,66 @@ template <bool MASK>
 __device__ __forceinline__ double inv_dist(double bx, double d2, double xq, double drop2) {
     const double dx = bx - xq;
     const double r2 = fma(dx, dx, d2);
+    // the hardware estimate is good to about 5e-8; with e = 1 - r2 y^2 the exact value is
+    // y (1 - e)^(-1/2) = y (1 + e/2 + 3e^2/8 + ...), so two terms of the series leave O(e^3)
     double y = __builtin_amdgcn_rsq(r2);
-    const double e = fma(-(r2 * y), y, 1.0);      // Newton step for 1/sqrt: y (1 + e/2)
-    y = fma(0.5 * y, e, y);
+    const double e = fma(-(r2 * y), y, 1.0);
+    y = fma(y * e, fma(0.375, e, 0.5), y);
     if (MASK) y = r2 > drop2 ? y : 0.0;
     return y;
 }
 
-// acc += sum over the row's nodes x0 <= xq < x1 of (W f)_xq / |r - x_q|.  The inverse
-// distances of four nodes are formed together (independent chains, one scalar load of
-// their coordinates), then their R weighted values are read as wave-uniform operands.
-template <int R, bool MASK>
-__device__ __forceinline__ void quad_run(double bx, double d2, const double* __restrict__ xs,
-                                         const double* __restrict__ row, int x0, int x1, double drop2,
-                                         double (&acc)[R]) {
+// acc += sum over the row's nodes x0 <= xq < x1 of (W f)_xq / |r - x_q| for the lane's NB
+// boundary nodes.  The inverse distances of a few nodes are formed together (independent
+// chains, one scalar load of their coordinates), then their R weighted values are read as
+// wave-uniform operands.
+template <int R, int NB, bool MASK>
+__device__ __forceinline__ void quad_run(const double (&bx)[NB], const double (&d2)[NB],
+                                         const double* __restrict__ xs, const double* __restrict__ row, int x0,
+                                         int x1, double drop2, double (&acc)[NB][R]) {
+    constexpr int U = NB == 1 ? 4 : 2;
     int xq = x0;
-    for (; xq + 4 <= x1; xq += 4) {
-        double y[4];
+    for (; xq + U <= x1; xq += U) {
+        double y[U][NB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] = inv_dist<MASK>(bx, d2, xs[xq + u], drop2);
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+            for (int k = 0; k < NB; ++k) y[u][k] = inv_dist<MASK>(bx[k], d2[k], xs[xq + u], drop2);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
             const double* wf = row + (long long)(xq + u) * R;
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = fma(wf[r], y[u], acc[r]);
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < NB; ++k) acc[k][r] = fma(wf[r], y[u][k], acc[k][r]);
         }
     }
     for (; xq < x1; ++xq) {
-        const double y = inv_dist<MASK>(bx, d2, xs[xq], drop2);
+        double y[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) y[k] = inv_dist<MASK>(bx[k], d2[k], xs[xq], drop2);
         const double* wf = row + (long long)xq * R;
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fma(wf[r], y, acc[r]);
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) acc[k][r] = fma(wf[r], y[k], acc[k][r]);
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(256) void k_quad(const double* __restrict__ xs, const double* __restrict__ ys,
-                                              const double* __restrict__ zs, int NX, int NY, int NZ, int nface,
-                                              int zper, double drop2, const double* __restrict__ rec,
-                                              double* __restrict__ out, int nsrc, int r0, int direct) {
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    const int bb = b < nface ? b : nface - 1;
-    // boundary node -> lattice indices (face order x-, x+ [Z][Y]; y-, y+ [Z][X]; z-, z+ [Y][X])
-    int X, Y, Z;
+// Work-groups are dispatched to the eight XCDs round robin (w % 8).  Give XCD x a contiguous
+// range of the logical work-group order, in which consecutive work-groups are the boundary
+// tiles of one part of the lattice: the tiles in flight on an XCD then stream the same
+// records through its L2.
+__device__ __forceinline__ int quad_xcd_remap(int w, int G) {
+    constexpr int NXCD = 8;
+    if (G < NXCD) return w;
+    const int x = w % NXCD, slot = w / NXCD;
+    const int base = G / NXCD, rem = G % NXCD;
+    return x * base + min(x, rem) + slot;
+}
+
+// boundary node -> lattice indices (face order x-, x+ [Z][Y]; y-, y+ [Z][X]; z-, z+ [Y][X])
+__device__ __forceinline__ void face_node(int bb, int NX, int NY, int NZ, int& X, int& Y, int& Z) {
     const int fx = NZ * NY, fy = NZ * NX, fz = NY * NX;
     if (bb < 2 * fx) {
         const int side = bb >= fx, rem = bb - side * fx;
@@ -127,35 +151,67 @@ __global__ __launch_bounds__(256) void k_quad(const double* __restrict__ xs, con
         const int t = bb - 2 * fx - 2 * fy, side = t >= fz, rem = t - side * fz;
         Y = rem / NX; X = rem % NX; Z = side ? NZ - 1 : 0;
     }
-    const double bx = xs[X], by = ys[Y], bz = zs[Z];
-    double acc[R];
+}
+
+template <int R>
+__global__ __launch_bounds__(QUAD_BLOCK) void k_quad(const double* __restrict__ xs, const double* __restrict__ ys,
+                                              const double* __restrict__ zs, int NX, int NY, int NZ, int nface,
+                                              int zper, int ntb, double drop2, const double* __restrict__ rec,
+                                              double* __restrict__ out, int nsrc, int r0, int direct) {
+    constexpr int NB = QUAD_NB;
+    // logical work-group: boundary tile (fastest) and part of the lattice
+    const int w = quad_xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = w % ntb, part = w / ntb;
+    int bnode[NB];
+    double bx[NB], by[NB], bz[NB];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    const int z0 = blockIdx.y * zper, z1 = min(NZ, z0 + zper);
+    for (int k = 0; k < NB; ++k) {
+        bnode[k] = tile * (QUAD_BLOCK * NB) + k * QUAD_BLOCK + threadIdx.x;
+        int X, Y, Z;
+        face_node(bnode[k] < nface ? bnode[k] : nface - 1, NX, NY, NZ, X, Y, Z);
+        bx[k] = xs[X]; by[k] = ys[Y]; bz[k] = zs[Z];
+    }
+    double acc[NB][R];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[k][r] = 0.0;
+    const int z0 = part * zper, z1 = min(NZ, z0 + zper);
     for (int zq = z0; zq < z1; ++zq) {
-        const double dz = bz - zs[zq];
-        const double dz2 = dz * dz;
+        double dz2[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const double dz = bz[k] - zs[zq];
+            dz2[k] = dz * dz;
+        }
         const bool zedge = zq == 0 || zq == NZ - 1;
         for (int yq = 0; yq < NY; ++yq) {
-            const double dy = by - ys[yq];
-            const double d2 = fma(dy, dy, dz2);
+            double d2[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const double dy = by[k] - ys[yq];
+                d2[k] = fma(dy, dy, dz2[k]);
+            }
             const double* row = rec + ((long long)zq * NY + yq) * NX * R;
             // a row on the lattice's boundary surface is tested node by node; any other row
             // only at its two end nodes (x faces).  Three consecutive ranges, no branches,
             // so that one set of accumulators serves all of them.
             const bool edge = zedge || yq == 0 || yq == NY - 1;
             const int m1 = edge ? NX : 1, u1 = edge ? NX : NX - 1;
-            quad_run<R, true>(bx, d2, xs, row, 0, m1, drop2, acc);
-            quad_run<R, false>(bx, d2, xs, row, m1, u1, drop2, acc);
-            quad_run<R, true>(bx, d2, xs, row, u1, NX, drop2, acc);
+            quad_run<R, NB, true>(bx, d2, xs, row, 0, m1, drop2, acc);
+            quad_run<R, NB, false>(bx, d2, xs, row, m1, u1, drop2, acc);
+            quad_run<R, NB, true>(bx, d2, xs, row, u1, NX, drop2, acc);
         }
     }
-    if (b >= nface) return;
     // direct: out is g [nsrc][nface]; else the split's partial sums [split][R][nface]
-    double* o = direct ? out + (long long)r0 * nface + b : out + (long long)blockIdx.y * R * nface + b;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (r0 + r < nsrc) o[(long long)r * nface] = acc[r];
+    for (int k = 0; k < NB; ++k) {
+        if (bnode[k] >= nface) continue;
+        double* o = direct ? out + (long long)r0 * nface + bnode[k] : out + (long long)part * R * nface + bnode[k];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r0 + r < nsrc) o[(long long)r * nface] = acc[k][r];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_quad_sum(const double* __restrict__ part, int S, int R, int nface,
@@ -169,10 +225,10 @@ __global__ __launch_bounds__(256) void k_quad_sum(const double* __restrict__ par
 }
 
 template <int R>
-void launch_quad_r(dim3 grid, const double* nodes, int NX, int NY, int NZ, int nface, int zper, double drop2,
+void launch_quad_r(int ntb, int S, const double* nodes, int NX, int NY, int NZ, int nface, int zper, double drop2,
                    const double* rec, double* out, int nsrc, int r0, int direct, hipStream_t s) {
-    hipLaunchKernelGGL(k_quad<R>, grid, dim3(256), 0, s, nodes, nodes + NX, nodes + NX + NY, NX, NY, NZ, nface, zper,
-                       drop2, rec, out, nsrc, r0, direct);
+    hipLaunchKernelGGL(k_quad<R>, dim3((unsigned)(ntb * S)), dim3(QUAD_BLOCK), 0, s, nodes, nodes + NX,
+                       nodes + NX + NY, NX, NY, NZ, nface, zper, ntb, drop2, rec, out, nsrc, r0, direct);
 }
 
 }  // namespace
@@ -184,8 +240,8 @@ QuadPlan quad_plan(const LevelHost& L, int nsrc) {
     P.ntile = std::max(1, (nsrc + QUAD_RMAX - 1) / QUAD_RMAX);
     const int per = (nsrc + P.ntile - 1) / P.ntile;
     P.R = std::max(4, (per + 3) / 4 * 4);
-    const long long blocks = (P.nface + 255) / 256;
-    const long long want = (QUAD_WAVES + 4 * blocks - 1) / (4 * blocks);
+    const long long wpb = QUAD_BLOCK / 64, blocks = (P.nface + QUAD_BLOCK * QUAD_NB - 1) / (QUAD_BLOCK * QUAD_NB);
+    const long long want = (QUAD_WAVES + wpb * blocks - 1) / (wpb * blocks);
     const int S0 = (int)std::max(1LL, std::min(NZ, want));
     P.zper = (int)((NZ + S0 - 1) / S0);
     P.S = (int)((NZ + P.zper - 1) / P.zper);
@@ -205,7 +261,8 @@ void launch_quad_data(const LevelHost& L, const LevelDev<double>* dev, const dou
     const double hmin = std::min({L.h[0], L.h[1], L.h[2]});
     const double drop2 = (1e-6 * hmin) * (1e-6 * hmin);
     const int nface = (int)P.nface;
-    const dim3 grid((unsigned)((nface + 255) / 256), (unsigned)P.S);
+    const int ntb = (nface + QUAD_BLOCK * QUAD_NB - 1) / (QUAD_BLOCK * QUAD_NB);
+    if ((long long)ntb * P.S >= (1LL << 31)) throw std::logic_error("quadrature grid too large");
     for (int r0 = 0; r0 < nsrc; r0 += P.R) {
         hipLaunchKernelGGL(k_quad_pack, dim3((unsigned)((L.ndof + 255) / 256)), dim3(256), 0, s, dev, L.E[0], L.E[1],
                            L.n, L.ndof, NX, NY, nsrc, r0, P.R, f, phi, pi, pj, rec);
@@ -213,7 +270,7 @@ void launch_quad_data(const LevelHost& L, const LevelDev<double>* dev, const dou
         double* out = direct ? g : part;
         switch (P.R) {
 #define QUAD_CASE(RR) \
-    case RR: launch_quad_r<RR>(grid, nodes, NX, NY, NZ, nface, P.zper, drop2, rec, out, nsrc, r0, direct, s); break;
+    case RR: launch_quad_r<RR>(ntb, P.S, nodes, NX, NY, NZ, nface, P.zper, drop2, rec, out, nsrc, r0, direct, s); break;
             QUAD_CASE(4) QUAD_CASE(8) QUAD_CASE(12) QUAD_CASE(16) QUAD_CASE(20) QUAD_CASE(24)
             QUAD_CASE(28) QUAD_CASE(32) QUAD_CASE(36) QUAD_CASE(40) QUAD_CASE(44) QUAD_CASE(48)
 #undef QUAD_CASE
