@@ -90,14 +90,16 @@ __device__ __forceinline__ double inv_dist(double bx, double d2, double xq, doub
 }
 
 // acc += sum over the row's nodes x0 <= xq < x1 of (W f)_xq / |r - x_q| for the lane's NB
-// boundary nodes.  The inverse distances of a few nodes are formed together (independent
-// chains, one scalar load of their coordinates), then their R weighted values are read as
-// wave-uniform operands.
+// boundary nodes.  The inverse distances of U nodes are formed together (independent chains,
+// one scalar load of their coordinates), then their R weighted values are read as
+// wave-uniform operands.  U = 8 for wide tiles (36 sources of 16^3 elements, p = 4: U = 4
+// 36.4 ms, 6 34.4, 8 33.6, 16 47.5 with 3 waves per SIMD); narrow tiles keep 4, and so does
+// the widest (48 accumulators: with U = 8 it would drop to 3 waves per SIMD).
 template <int R, int NB, bool MASK>
 __device__ __forceinline__ void quad_run(const double (&bx)[NB], const double (&d2)[NB],
                                          const double* __restrict__ xs, const double* __restrict__ row, int x0,
                                          int x1, double drop2, double (&acc)[NB][R]) {
-    constexpr int U = NB == 1 ? 4 : 2;
+    constexpr int U = NB == 1 ? (R >= 24 && R <= 40 ? 8 : 4) : 2;
     int xq = x0;
     for (; xq + U <= x1; xq += U) {
         double y[U][NB];
