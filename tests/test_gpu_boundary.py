@@ -40,11 +40,12 @@ def _mesh(E, p, lo, hi):
 
 
 @pytest.mark.parametrize("E,p,nsrc", [((3, 4, 5), 3, 1), ((3, 4, 5), 3, 7), ((2, 3, 2), 4, 52), ((2, 2, 1), 7, 3),
-                                       ((8, 8, 8), 1, 5)])
+                                       ((8, 8, 8), 1, 5), ((3, 2, 2), 4, 36), ((2, 2, 3), 3, 96)])
 def test_boundary_data_matches_oracle(gpu_lib, E, p, nsrc):
     """Ragged face counts (not a multiple of the 256-node block), one and several source
-    tiles (52 sources: two tiles of 28), a single element along z (every node of it on the
-    z faces) and degree 1 (half the nodes of each row on an element face)."""
+    tiles (52 sources: two tiles of 28; 96: two of the widest tile, 48), the 36-source tile
+    of the exchange workload, a single element along z (every node of it on the z faces) and
+    degree 1 (half the nodes of each row on an element face)."""
     lo, hi = [-3.0, -2.5, -4.0], [3.5, 2.0, 3.0]
     mesh = _mesh(E, p, lo, hi)
     ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=2 if p == 1 else 0)
