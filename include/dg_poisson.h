@@ -43,8 +43,12 @@
  *
  * Errors
  *   Functions return a dg_status; no C++ exception crosses the ABI.
- *   DG_ERR_ARG for bad sizes, indices or null pointers; DG_ERR_HIP when a HIP
- *   runtime call fails (dg_last_error() gives the message);
+ *   DG_ERR_ARG for bad sizes, indices or null pointers, and from the solves
+ *   (dg_poisson_solve_batch, dg_exchange_apply) when a source, its Dirichlet
+ *   data or a caller's initial guess holds a NaN or Inf: such a right-hand side
+ *   does no iterations, the others are solved, and the outputs of the call are
+ *   then not to be used; DG_ERR_HIP when a HIP runtime call fails
+ *   (dg_last_error() gives the message);
  *   DG_WARN_NOT_CONVERGED when a right-hand side missed its tolerance within
  *   max_iter (its stats entry says which).
  */

@@ -623,6 +623,17 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
         }
     }
     HIPCHK(hipGetLastError());
+    // A NaN or Inf in a source, its Dirichlet data or a caller's initial guess leaves ||b||^2 or
+    // the residual non-finite.  Such a right-hand side never became active (every comparison
+    // with NaN is false), so it cost no iterations; the call reports an argument error.
+    for (int i = 0; i < nrhs; ++i) {
+        const auto& S = M.st_host[i];
+        if (!std::isfinite(S.bb) || !std::isfinite(S.rr)) {
+            HIPCHK(hipStreamSynchronize(s));
+            throw ArgError("non-finite value (NaN or Inf) in the source, Dirichlet data or initial guess of a "
+                           "right-hand side");
+        }
+    }
     if (stats) {
         for (int i = 0; i < nrhs; ++i) {
             const auto& S = M.st_host[i];

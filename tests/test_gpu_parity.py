@@ -278,6 +278,34 @@ def test_invalid_arguments_are_rejected(gpu_lib):
     assert code == -1
 
 
+def test_non_finite_inputs_are_rejected(gpu_lib):
+    """A NaN or Inf in a source, its Dirichlet data or a caller's initial guess is reported as
+    an argument error, in both precisions and over two solver lanes (20 right-hand sides); the
+    context solves normally afterwards."""
+    wl = configs.scaled(4, 2, 20, seed=43)
+    mesh = wl.meshes[0]
+    for prec in ("fp64", "fp32_ir"):
+        ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], precision=prec)
+        assert ctx.opts.lanes == 2
+        rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+        rho, g = np.concatenate(rho), np.concatenate(g)
+        nd, nf = ctx.info[0]["n_dofs"], ctx.info[0]["n_face"]
+        bad = rho.copy()
+        bad[5 * nd + 17] = np.nan
+        with pytest.raises(gpu_lib.DgError, match="non-finite"):
+            ctx.solve_batch(_t(bad), _t(g))
+        bad = g.copy()
+        bad[13 * nf + 3] = np.inf
+        with pytest.raises(gpu_lib.DgError, match="non-finite"):
+            ctx.solve_batch(_t(rho), _t(bad))
+        x0 = np.zeros_like(rho)
+        x0[2 * nd] = np.nan
+        with pytest.raises(gpu_lib.DgError, match="non-finite"):
+            ctx.solve_batch(_t(rho), _t(g), x0=_t(x0))
+        v, st = ctx.solve_batch(_t(rho), _t(g))
+        assert all(s["status"] == 0 for s in st) and np.all(np.isfinite(_n(v))), prec
+
+
 def _small_exchange_case():
     prims = gaussians.Primitives([0.6, 1.4, 0.9, 0.45, 2.0],
                                  [[0.4, 0, 0], [0.4, 0, 0], [-0.5, 0.2, 0.1], [-0.5, 0.2, 0.1], [0.1, -0.6, 0.3]])
