@@ -98,7 +98,8 @@ typedef struct {
     dg_precision precision;
     double inner_rtol;   /* FP32_IR: relative tolerance of each inner solve (loosened for the last
                             step to 0.9 rtol ||b|| / ||r_k|| when that is larger) */
-    int max_outer;       /* FP32_IR: refinement steps */
+    int max_outer;       /* FP32_IR: refinement steps; a right-hand side still above rtol after
+                            them is finished by FP64 PCG from its current iterate */
     int check_every;     /* PCG iterations per replay block (graph: rounded up to even) and
                             between host convergence checks; with a graph the first check
                             waits for as many iterations as the same PCG run of the previous
@@ -115,8 +116,12 @@ typedef struct {
 
 typedef struct {
     int iters;           /* PCG iterations (summed over inner solves in FP32_IR) */
-    int outer_iters;     /* refinement steps (FP32_IR), 1 for FP64 */
-    int status;          /* DG_OK or DG_WARN_NOT_CONVERGED */
+    int outer_iters;     /* refinement steps (FP32_IR), 1 for FP64; one more when the FP64
+                            fallback finished the right-hand side (see max_outer) */
+    int status;          /* DG_OK, DG_WARN_NOT_CONVERGED, or DG_ERR_BREAKDOWN when the last FP64
+                            PCG pass stopped on a non-positive p.Ap or r.z short of the
+                            tolerance (after up to three restarts from the current iterate);
+                            a solve returns the worst of its right-hand sides' statuses */
     int guess_used;      /* 1 if an initial guess was used: the caller's x0, or a learned guess
                             that passed the guard (residual below ||b||) */
     double rel_residual; /* ||b - A v||_2 / ||b||_2 recomputed in FP64 at exit */

@@ -621,6 +621,39 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             dg::launch_finalize(dg::FIN_TRUE, nrhs, M.st, M.partial, M.pstride, nb, s);
             read_state(M, M.st, nrhs, s);
         }
+        // Fallback: right-hand sides still above the tolerance after max_outer refinement steps
+        // (an inner solve that stalls or breaks down) are finished by FP64 PCG from the current
+        // iterate; converged ones stay inactive in it.  M.r64 holds b - A v of the current v.
+        std::vector<char> miss(nrhs, 0);
+        bool any_miss = false;
+        for (int i = 0; i < nrhs; ++i) {
+            const auto& S = M.st_host[i];
+            miss[i] = std::isfinite(S.bb) && std::isfinite(S.rr) && S.bb > 0 && S.rr > S.tol2 * S.bb * 1.0201 &&
+                      iters[i] < o.max_iter;
+            any_miss |= miss[i] != 0;
+        }
+        if (any_miss) {
+            ensure_work<double>(M, M.w64, nrhs);  // sized when the fallback first happens
+            Work<double>& W = M.w64;
+            dg::launch_copy(v, W.x, n0 * nrhs, s);
+            dg::launch_copy(M.r64, W.r, n0 * nrhs, s);
+            for (int i = 0; i < nrhs; ++i) outer[i] += miss[i];
+            for (int restart = 0; restart < 3; ++restart) {
+                pcg_run<double>(ctx, M, W, nrhs, M.st, nullptr, restart, s);
+                for (int i = 0; i < nrhs; ++i) iters[i] += M.st_host[i].iters;
+                dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr,
+                                         W.r, nullptr, M.partial, M.pstride, 0, 0, s);
+                dg::launch_finalize(dg::FIN_TRUE, nrhs, M.st, M.partial, M.pstride, nb, s);
+                read_state(M, M.st, nrhs, s);
+                bool again = false;
+                for (int i = 0; i < nrhs; ++i) {
+                    const auto& S = M.st_host[i];
+                    again |= S.bb > 0 && S.rr > S.tol2 * S.bb * 1.0201 && iters[i] < o.max_iter && !S.breakdown;
+                }
+                if (!again) break;
+            }
+            HIPCHK(hipMemcpyAsync(v, W.x, sizeof(double) * n0 * nrhs, hipMemcpyDeviceToDevice, s));
+        }
     }
     HIPCHK(hipGetLastError());
     // A NaN or Inf in a source, its Dirichlet data or a caller's initial guess leaves ||b||^2 or
@@ -642,7 +675,8 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             r.outer_iters = outer[i];
             r.guess_used = kept[i];
             r.rel_residual = S.bb > 0 ? std::sqrt(S.rr / S.bb) : 0.0;
-            r.status = (r.rel_residual <= o.rtol * 1.01) ? DG_OK : DG_WARN_NOT_CONVERGED;
+            // breakdown: the last FP64 PCG pass stopped on a non-positive p.Ap or r.z
+            r.status = (r.rel_residual <= o.rtol * 1.01) ? DG_OK : S.breakdown ? DG_ERR_BREAKDOWN : DG_WARN_NOT_CONVERGED;
         }
     }
 }
@@ -1149,6 +1183,18 @@ dg_status dg_mesh_coords(const dg_ctx* ctx, int mesh_id, double* xyz, double* fx
     });
 }
 
+// Status of a call whose right-hand sides all ran: a breakdown that the FP64 restarts could not
+// cure first, then a missed tolerance.
+static dg_status worst_status(const dg_rhs_stats* stats, int n) {
+    if (!stats) return DG_OK;
+    dg_status w = DG_OK;
+    for (int i = 0; i < n; ++i) {
+        if (stats[i].status == DG_ERR_BREAKDOWN) return DG_ERR_BREAKDOWN;
+        if (stats[i].status != DG_OK) w = DG_WARN_NOT_CONVERGED;
+    }
+    return w;
+}
+
 dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, const double* rho, const double* g,
                                  const double* x0, double* v, dg_rhs_stats* stats, hipStream_t stream) {
     dg_status st = run_guarded([&] {
@@ -1272,7 +1318,8 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
                 P.guessed = true;
             }
         }
-        // every buffer is sized here, on this thread: the solves allocate nothing
+        // every buffer is sized here, on this thread: the solves allocate nothing (but for the
+        // FP64 fallback of a mixed-precision solve, sized when it first happens)
         std::vector<Job> jobs;
         for (auto& P : parts)
             add_jobs(ctx, P.m, P.cnt, ctx->meshes[P.m].b, P.x0, P.v, P.stats.data(), P.guessed, jobs);
@@ -1288,10 +1335,7 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
         HIPCHK(hipStreamSynchronize(stream));
         leave(ctx, user);
     });
-    if (st == DG_OK && stats)
-        for (int i = 0; i < nrhs; ++i)
-            if (stats[i].status != DG_OK) return DG_WARN_NOT_CONVERGED;
-    return st;
+    return st == DG_OK ? worst_status(stats, nrhs) : st;
 }
 
 dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* phi, const double* g_pairs, double* W,
@@ -1372,12 +1416,7 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
             for (int j = i; j < norb; ++j, ++q) ex += (i == j ? 1.0 : 2.0) * K[q];
         if (E_x) *E_x = ex;
     });
-    if (st == DG_OK && stats) {
-        const int npairs = norb * (norb + 1) / 2;
-        for (int i = 0; i < npairs; ++i)
-            if (stats[i].status != DG_OK) return DG_WARN_NOT_CONVERGED;
-    }
-    return st;
+    return st == DG_OK ? worst_status(stats, norb * (norb + 1) / 2) : st;
 }
 
 dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g, hipStream_t stream) {

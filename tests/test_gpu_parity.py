@@ -306,6 +306,28 @@ def test_non_finite_inputs_are_rejected(gpu_lib):
         assert all(s["status"] == 0 for s in st) and np.all(np.isfinite(_n(v))), prec
 
 
+def test_mixed_precision_falls_back_to_fp64(gpu_lib):
+    """With a single refinement step the FP32 inner solves (to 1e-4) cannot reach 1e-11: the
+    FP64 fallback finishes every right-hand side from its current iterate (one more outer
+    step counted), and the potentials agree with the plain FP64 solver's."""
+    wl = configs.scaled(4, 4, 20, seed=47)
+    mesh = wl.meshes[0]
+    m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
+    ctx = gpu_lib.Context([m], precision="fp32_ir", max_outer=1, rtol=1e-11)
+    rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+    rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+    v, st = ctx.solve_batch(rho, g)
+    assert all(s["status"] == 0 and s["rel_residual"] <= 1e-11 and s["outer_iters"] == 2 for s in st)
+    ref = gpu_lib.Context([m], precision="fp64", rtol=1e-11)
+    v64, _ = ref.solve_batch(rho, g)
+    v, v64 = _n(v), _n(v64)
+    assert np.max(np.abs(v - v64)) <= 1e-8 * np.max(np.abs(v64))
+    # with the default number of steps no right-hand side needs the fallback
+    ctx8 = gpu_lib.Context([m], precision="fp32_ir", rtol=1e-11)
+    _, st8 = ctx8.solve_batch(rho, g)
+    assert all(s["status"] == 0 and s["outer_iters"] <= 8 for s in st8)
+
+
 def _small_exchange_case():
     prims = gaussians.Primitives([0.6, 1.4, 0.9, 0.45, 2.0],
                                  [[0.4, 0, 0], [0.4, 0, 0], [-0.5, 0.2, 0.1], [-0.5, 0.2, 0.1], [0.1, -0.6, 0.3]])
