@@ -381,6 +381,7 @@ def main_single(args):
                 _, it, _, _ = pcg.solve(H, b, rtol=wl.rtol)
             dt = (time.perf_counter() - t0) / n
             cpu = {"value": 1.0 / dt, "unit": "RHS/s", "us_per_solve": 1e6 * dt, "cores": _threads(), "kind": "oracle",
+                   **_host(),
                    "sample": f"{n} solves of the single-Gaussian problem, oracle MG-PCG FP64 to {wl.rtol}, "
                              f"{it} iterations; set-up excluded"}
     head_arm = arms[0]
@@ -472,7 +473,7 @@ def main_quadrature(args):
         go = boundary.potential_at(axes, fo, pts[idx])
         dt_o = time.perf_counter() - t0
         per_rhs = dt_o * (nface / len(idx)) / npairs
-        cpu = {"value": 1.0 / per_rhs, "unit": "RHS/s", "cores": _threads(), "kind": "oracle",
+        cpu = {"value": 1.0 / per_rhs, "unit": "RHS/s", "cores": _threads(), "kind": "oracle", **_host(),
                "sample": f"oracle direct sum for all {npairs} pair densities at {len(idx)} of the {nface} "
                          f"boundary nodes ({dt_o:.1f} s), scaled to whole boundary-data sets per second"}
         check = {"max_rel_diff_vs_oracle": float(max(np.abs(g_h[q, idx] - go[q]).max() / np.abs(go[q]).max()
@@ -507,6 +508,19 @@ def main_quadrature(args):
         "check_vs_oracle": check,
     }
     print(json.dumps(line))
+
+
+def _host():
+    """The host the oracle ran on: logical CPUs and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"host_cpus": os.cpu_count(), "host_cpu_model": model}
 
 
 def _threads():
@@ -583,7 +597,7 @@ def cpu_leg(args, wl, results, phi, g, npairs):
         for b in bs:
             F.solve(b)
         dtf = time.perf_counter() - t2
-        cpu = {"value": len(qs) / dt, "unit": "RHS/s", "cores": threads, "kind": "oracle",
+        cpu = {"value": len(qs) / dt, "unit": "RHS/s", "cores": threads, "kind": "oracle", **_host(),
                "sample": f"{len(qs)} of {npairs} pair solves (pairs {qs}), oracle MG-PCG FP64 to {wl.rtol}, "
                          f"iterations {its}; set-up excluded",
                "value_1thread": len(q1) / dt1, "sample_1thread": f"the first {len(q1)} of those solves, one thread",
