@@ -189,6 +189,29 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
  * DG_ERR_ARG for nsrc < 0 or null pointers with nsrc > 0. */
 dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g, hipStream_t stream);
 
+/* Work-group tiles of the operator kernels (host only; no GPU needed).
+ * The operator steps of the path run as a slab kernel on nodes-per-edge n = 2,
+ * 3 and 5 (degrees 1, 2, 4): a work-group owns tx x ty elements of the x-y
+ * plane and zlen element layers along z.  dg_tile_set chooses the tile of one
+ * step (DG_STEP_*) for one arithmetic (fp_bytes 4: FP32, 8: FP64) and one n,
+ * for every context set up afterwards (contexts set up before keep theirs).
+ * Compiled shapes: n = 2: 8x8, zlen 1..2; n = 3: 4x4, zlen 1..4; n = 5: 4x2,
+ * 4x4 or 2x2, zlen 1..4; anything else returns DG_ERR_ARG.  dg_tile_get
+ * reports the current choice (host outputs).  The built-in defaults are
+ * measured choices for gfx950; the package's tuning script times the
+ * alternatives on a workload and writes a table that its binding applies. */
+typedef enum {
+    DG_STEP_APPLY = 0,     /* y = A u */
+    DG_STEP_RESID = 1,     /* r = f - A u */
+    DG_STEP_CHEB = 2,      /* Chebyshev smoothing step */
+    DG_STEP_CHEBDOT = 3,   /* the same with partial sums of f.z (last post-smoothing step) */
+    DG_STEP_PQ = 4,        /* p = z + beta p; q = A p; partial sums of p.q */
+    DG_STEP_RESIDDOT = 5,  /* r = f - A u with partial sums of r.r */
+    DG_STEP_RESTRICT = 6   /* r = f - A u restricted to the next coarser degree */
+} dg_step;
+dg_status dg_tile_set(int fp_bytes, int n, int step, int tx, int ty, int zlen);
+dg_status dg_tile_get(int fp_bytes, int n, int step, int* tx, int* ty, int* zlen);
+
 /* ---- single steps of the path, exposed for verification and profiling ----
  * All operate on nrhs packed FP64 fields of one mesh at multigrid level
  * `level` (0 = finest).  They return after enqueueing (no synchronisation). */

@@ -64,6 +64,8 @@ def _load():
         "dg_vcycle_apply_f32": (I, [P, I, I, I, P, P, P]),
         "dg_rhs_assemble": (I, [P, I, I, P, P, P, P]),
         "dg_boundary_data": (I, [P, I, I, P, P, P]),
+        "dg_tile_set": (I, [I, I, I, I, I, I]),
+        "dg_tile_get": (I, [I, I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "dg_vcycle_apply": (I, [P, I, I, I, P, P, P]),
         "dg_coarse_solve": (I, [P, I, I, P, P, P]),
         "dg_restrict": (I, [P, I, I, I, P, P, P]),
@@ -96,6 +98,38 @@ def _load():
 
 
 lib = _load()
+
+STEPS = {"APPLY": 0, "RESID": 1, "CHEB": 2, "CHEBDOT": 3, "PQ": 4, "RESIDDOT": 5, "RESTRICT": 6}
+TILE_TABLE = os.path.join(_HERE, "tiles_gfx950.json")
+
+
+def tile_set(fp_bytes, n, step, tx, ty, zlen):
+    """Work-group tile of one operator step for contexts set up afterwards (dg_tile_set)."""
+    code = lib.dg_tile_set(int(fp_bytes), int(n), STEPS[step] if isinstance(step, str) else int(step),
+                           int(tx), int(ty), int(zlen))
+    if code != 0:
+        raise DgError(f"tile_set: {lib.dg_last_error().decode()}")
+
+
+def tile_get(fp_bytes, n, step):
+    tx, ty, z = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    code = lib.dg_tile_get(int(fp_bytes), int(n), STEPS[step] if isinstance(step, str) else int(step),
+                           ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(z))
+    if code != 0:
+        raise DgError(f"tile_get: {lib.dg_last_error().decode()}")
+    return tx.value, ty.value, z.value
+
+
+def apply_tile_table(path=TILE_TABLE):
+    """Apply a tile table written by tune_tiles.py (a list of {fp_bytes, n, step, tx, ty, zlen})."""
+    import json
+    with open(path) as f:
+        for t in json.load(f)["tiles"]:
+            tile_set(t["fp_bytes"], t["n"], t["step"], t["tx"], t["ty"], t["zlen"])
+
+
+if os.path.exists(TILE_TABLE) and not os.environ.get("DG_POISSON_NO_TILE_TABLE"):
+    apply_tile_table()
 
 
 def status_string(code):

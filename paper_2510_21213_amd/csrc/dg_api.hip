@@ -798,6 +798,7 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
         L.ndof = (long long)E[0] * E[1] * E[2] * L.n * L.n * L.n;
         L.be = dg::brick_edge(L.n);
         for (int d = 0; d < 3; ++d) L.nbr[d] = (E[d] + L.be - 1) / L.be;
+        dg::assign_tiles(L);
         for (int d = 0; d < 3; ++d) {
             dg::build_axis(E[d], p, mesh.lo[d], mesh.hi[d], o.penalty_eps, L.d64.ax[d], nullptr, nullptr);
             auto& a = L.d64.ax[d];
@@ -1426,6 +1427,18 @@ dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, 
         if (nsrc == 0) return;
         quad_data(ctx, ctx->meshes[mesh_id], nsrc, f, nullptr, nullptr, nullptr, g, stream);
         HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_tile_set(int fp_bytes, int n, int step, int tx, int ty, int zlen) {
+    return run_guarded([&] {
+        if (!dg::tile_set(fp_bytes, n, step, tx, ty, zlen)) throw ArgError("no operator kernel for this tile");
+    });
+}
+
+dg_status dg_tile_get(int fp_bytes, int n, int step, int* tx, int* ty, int* zlen) {
+    return run_guarded([&] {
+        if (!dg::tile_get(fp_bytes, n, step, tx, ty, zlen)) throw ArgError("bad tile query");
     });
 }
 

@@ -113,6 +113,9 @@ struct LevelHost {
     TransferDev* devtr = nullptr;
     int nbr[3];      // bricks per axis
     int be;          // elements per brick edge
+    // slab-kernel tile per arithmetic (0 FP32, 1 FP64) and operator step (BrickMode):
+    // {tx, ty, zlen}; tx = 0 selects the brick kernel.  Fixed when the level is set up.
+    int tile[2][7][3];
 };
 
 // Host-side numerics (dg_setup.cpp).

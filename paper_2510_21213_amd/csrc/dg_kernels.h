@@ -33,6 +33,12 @@ struct KernelCfg {
 
 inline int chunks_of(long long ndof) { return (int)((ndof + 1023) / 1024); }
 inline int bricks_of(const LevelHost& L) { return L.nbr[0] * L.nbr[1] * L.nbr[2]; }
+// Slab-kernel tiles.  tile_set/tile_get edit the process-wide table from which assign_tiles
+// fills a level when it is set up (false: a shape with no compiled kernel, or bad arguments).
+bool tile_set(int fp_bytes, int n, int mode, int tx, int ty, int zlen);
+bool tile_get(int fp_bytes, int n, int mode, int* tx, int* ty, int* zlen);
+void assign_tiles(LevelHost& L);
+
 // Partial-sum slots per right-hand side that launch_brick writes in dot mode
 // `mode` (its work-groups per right-hand side).
 template <typename T>

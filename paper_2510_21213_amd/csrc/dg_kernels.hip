@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <stdexcept>
 
 #include "dg_kernels.h"
@@ -803,7 +804,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     }
 
     double dot = 0.0;
-    constexpr int ZMAX = slab_zmax(N);  // longest chunk (slab_shape)
+    constexpr int ZMAX = slab_zmax(N);  // longest chunk (tile_compiled)
 #pragma unroll
     for (int zq = 0; zq < ZMAX; ++zq) {
         const int ez = ezb + zq;
@@ -981,9 +982,9 @@ static void brick_dispatch(int mode, const BrickArgs<T>& a, int grid, hipStream_
 
 // Tile of the slab kernel for (precision, nodes per edge): TX x TY elements,
 // or {0, 0} where the brick kernel is used.  Layers per z chunk: enough
-// chunks for a few thousand work-groups at typical batch sizes.
-template <typename T>
-static void slab_shape(int n, int mode, int& tx, int& ty, int& zlen) {
+// chunks for a few thousand work-groups at typical batch sizes.  These are the
+// built-in defaults; tile_set overrides them for levels set up afterwards.
+static void default_tile(int fp64, int n, int mode, int& tx, int& ty, int& zlen) {
     tx = ty = 0;
     zlen = 4;
     switch (n) {
@@ -993,7 +994,7 @@ static void slab_shape(int n, int mode, int& tx, int& ty, int& zlen) {
             // FP64 holds twice the registers: 2x2 tiles pack best.  FP32 smoothing steps and
             // the residual-restriction run fastest on 4x2 tiles, the step with two inputs per
             // node (PQ) on 4x4 (measured)
-            if (sizeof(T) == 8) {
+            if (fp64) {
                 tx = ty = 2;
             } else {
                 tx = 4;
@@ -1005,6 +1006,67 @@ static void slab_shape(int n, int mode, int& tx, int& ty, int& zlen) {
     }
 }
 
+// The shapes launch_slab has kernels for.
+static bool tile_compiled(int n, int tx, int ty, int zlen) {
+    if (zlen < 1 || zlen > slab_zmax(n)) return false;
+    switch (n) {
+        case 2: return tx == 8 && ty == 8;
+        case 3: return tx == 4 && ty == 4;
+        case 5: return (tx == 4 && ty == 2) || (tx == 4 && ty == 4) || (tx == 2 && ty == 2);
+        default: return false;
+    }
+}
+
+namespace {
+struct TileTable {
+    std::mutex mu;
+    bool set[2][8][7] = {};
+    int v[2][8][7][3] = {};
+};
+TileTable& tile_table() {
+    static TileTable t;
+    return t;
+}
+}  // namespace
+
+bool tile_set(int fp_bytes, int n, int mode, int tx, int ty, int zlen) {
+    if ((fp_bytes != 4 && fp_bytes != 8) || n < 2 || n > 8 || mode < 0 || mode > BM_RESTRICT) return false;
+    if (!tile_compiled(n, tx, ty, zlen)) return false;
+    auto& t = tile_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    const int f = fp_bytes == 8;
+    t.set[f][n - 1][mode] = true;
+    t.v[f][n - 1][mode][0] = tx;
+    t.v[f][n - 1][mode][1] = ty;
+    t.v[f][n - 1][mode][2] = zlen;
+    return true;
+}
+
+bool tile_get(int fp_bytes, int n, int mode, int* tx, int* ty, int* zlen) {
+    if ((fp_bytes != 4 && fp_bytes != 8) || n < 2 || n > 8 || mode < 0 || mode > BM_RESTRICT) return false;
+    auto& t = tile_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    const int f = fp_bytes == 8;
+    int x, y, z;
+    if (t.set[f][n - 1][mode]) {
+        x = t.v[f][n - 1][mode][0]; y = t.v[f][n - 1][mode][1]; z = t.v[f][n - 1][mode][2];
+    } else {
+        default_tile(f, n, mode, x, y, z);
+    }
+    if (tx) *tx = x;
+    if (ty) *ty = y;
+    if (zlen) *zlen = z;
+    return true;
+}
+
+void assign_tiles(LevelHost& L) {
+    for (int f = 0; f < 2; ++f)
+        for (int m = 0; m <= BM_RESTRICT; ++m) {
+            int* t = L.tile[f][m];
+            if (L.n < 2 || L.n > 8 || !tile_get(f ? 8 : 4, L.n, m, &t[0], &t[1], &t[2])) t[0] = t[1] = 0, t[2] = 4;
+        }
+}
+
 struct SlabGeom {
     int tx, ty, nt0, nt1, zlen, nzc;
 };
@@ -1012,7 +1074,10 @@ struct SlabGeom {
 template <typename T>
 static SlabGeom slab_geom(const LevelHost& L, int mode) {
     SlabGeom g;
-    slab_shape<T>(L.n, mode, g.tx, g.ty, g.zlen);
+    const int* t = L.tile[sizeof(T) == 8][mode];
+    g.tx = t[0];
+    g.ty = t[1];
+    g.zlen = t[2];
     if (!g.tx) return g;
     g.nt0 = (L.E[0] + g.tx - 1) / g.tx;
     g.nt1 = (L.E[1] + g.ty - 1) / g.ty;

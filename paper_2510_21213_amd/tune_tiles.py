@@ -1,0 +1,127 @@
+#!/usr/bin/env python
+"""Pick the operator kernels' work-group tiles by timing the exchange step on the GPU.
+
+The operator steps run as a slab kernel whose work-group owns tx x ty elements of the x-y plane
+and zlen element layers (dg_tile_set lists the compiled shapes).  The steps are grouped (the
+FP32 smoothing steps and restriction of the degree-4 level; its other FP32 steps; its FP64
+steps; the degree-2 and degree-1 levels in each arithmetic) and every compiled tile of a group
+is tried in turn, coordinate descent from the current table, with the exchange step of the
+8-orbital workload (36 pair densities, 16^3 elements, p = 4) timed end to end: the mixed arm
+with the trained guess for FP32 tiles, the plain FP64 arm for FP64 tiles.  A tile replaces the
+current one only when its median step time is lower by more than the noise margin.  Writes the
+table (tiles_gfx950.json next to this file by default), which the binding applies on import.
+
+    python paper_2510_21213_amd/tune_tiles.py [--steps 8] [--warmup 4] [--margin 0.02]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_2510_21213_amd import binding  # noqa: E402
+from workloads import configs  # noqa: E402
+
+ALL = list(binding.STEPS)
+SHAPES5 = [(4, 2), (4, 4), (2, 2)]
+GROUPS = [
+    # name, fp_bytes, n, steps, shapes, zlens, arm timed
+    ("fp32 degree-4 smoothing and restriction", 4, 5, ["CHEB", "CHEBDOT", "RESTRICT"], SHAPES5, [1, 2, 3, 4],
+     "fp32_ir+learned"),
+    ("fp32 degree-4 other steps", 4, 5, ["APPLY", "RESID", "PQ", "RESIDDOT"], SHAPES5, [1, 2, 3, 4],
+     "fp32_ir+learned"),
+    ("fp32 degree-2", 4, 3, ALL, [(4, 4)], [1, 2, 3, 4], "fp32_ir+learned"),
+    ("fp32 degree-1", 4, 2, ALL, [(8, 8)], [1, 2], "fp32_ir+learned"),
+    ("fp64 degree-4", 8, 5, ALL, SHAPES5, [1, 2, 3, 4], "fp64"),
+    ("fp64 degree-2", 8, 3, ALL, [(4, 4)], [1, 2, 3, 4], "fp64"),
+    ("fp64 degree-1", 8, 2, ALL, [(8, 8)], [1, 2], "fp64"),
+]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--margin", type=float, default=0.02, help="relative gain a new tile must show")
+    ap.add_argument("--out", default=binding.TILE_TABLE)
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    wl = configs.exchange8()
+    mesh, orb = wl.meshes[0], wl.orbitals
+    m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
+    net = binding.Net(4, 32, 125, 27)
+    net.load(os.path.join(ROOT, "paper_2510_21213_amd", "weights", "guess_16e_p4.bin"))
+    probe = binding.Context([m], n_levels=wl.n_levels)
+    xyz, fxyz = probe.mesh_coords(0)
+    probe.close()
+    phi = torch.as_tensor(orb.values(xyz[0], xyz[1], xyz[2]).reshape(-1)).cuda()
+    g = torch.as_tensor(orb.pair_potentials(fxyz[0], fxyz[1], fxyz[2]).reshape(-1)).cuda()
+
+    def measure(arm):
+        prec = "fp32_ir" if arm.startswith("fp32_ir") else "fp64"
+        ctx = binding.Context([m], n_levels=wl.n_levels, rtol=wl.rtol, precision=prec)
+        if "learned" in arm:
+            ctx.attach_guess(net)
+        for _ in range(args.warmup):
+            ctx.exchange(phi, g)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            ctx.exchange(phi, g)
+            ts.append(time.perf_counter() - t0)
+        ctx.close()
+        return float(np.median(ts))
+
+    def set_group(fp, n, steps, tile):
+        for st in steps:
+            binding.tile_set(fp, n, st, *tile)
+
+    trials = []
+    t_start = time.time()
+    for name, fp, n, steps, shapes, zlens, arm in GROUPS:
+        current = {st: binding.tile_get(fp, n, st) for st in steps}
+        base = measure(arm)
+        best, best_t = None, base
+        for tx, ty in shapes:
+            for z in zlens:
+                tile = (tx, ty, z)
+                if all(current[st] == tile for st in steps):
+                    continue
+                set_group(fp, n, steps, tile)
+                t = measure(arm)
+                trials.append({"group": name, "tile": list(tile), "ms": 1e3 * t, "current_ms": 1e3 * base})
+                print(f"{name}: tile {tile} {1e3 * t:.2f} ms (current {1e3 * base:.2f} ms) "
+                      f"[{time.time() - t_start:.0f}s]", flush=True)
+                if t < best_t:
+                    best, best_t = tile, t
+        for st in steps:
+            binding.tile_set(fp, n, st, *current[st])
+        if best is not None and best_t < base * (1.0 - args.margin):
+            set_group(fp, n, steps, best)
+            print(f"{name}: chose {best} ({1e3 * best_t:.2f} ms against {1e3 * base:.2f} ms)", flush=True)
+        else:
+            print(f"{name}: kept the current tiles", flush=True)
+
+    tiles = []
+    for fp in (4, 8):
+        for n in (2, 3, 5):
+            for st in ALL:
+                tx, ty, z = binding.tile_get(fp, n, st)
+                tiles.append({"fp_bytes": fp, "n": n, "step": st, "tx": tx, "ty": ty, "zlen": z})
+    report = {"arch": "gfx950", "workload": "exchange8: 36 pair densities, 16^3 elements, p = 4, 4 levels, 1e-8",
+              "timing": f"median of {args.steps} exchange steps after {args.warmup} warm-up steps",
+              "margin": args.margin, "tiles": tiles, "trials": trials, "seconds": time.time() - t_start}
+    with open(args.out, "w") as f:
+        json.dump(report, f, indent=1)
+    print(f"wrote {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -58,3 +58,21 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu(lib):
     rc = binding.lib.dg_poisson_setup(None, 0, ctypes.byref(opts), ctypes.byref(h))
     assert rc == -1
     assert b"mesh" in binding.lib.dg_last_error()
+
+
+def test_tile_table_host_calls(lib):
+    """dg_tile_set / dg_tile_get need no GPU: a compiled tile round-trips, shapes without a
+    kernel and bad arguments are rejected, and degrees without slab kernels report tx = 0."""
+    from paper_2510_21213_amd import binding
+    orig = binding.tile_get(4, 5, "CHEB")
+    assert orig[0] in (2, 4) and 1 <= orig[2] <= 4
+    try:
+        binding.tile_set(4, 5, "CHEB", 2, 2, 3)
+        assert binding.tile_get(4, 5, "CHEB") == (2, 2, 3)
+    finally:
+        binding.tile_set(4, 5, "CHEB", *orig)
+    for bad in [(4, 5, "CHEB", 8, 8, 2), (4, 3, "PQ", 4, 4, 5), (2, 5, "PQ", 4, 4, 2), (8, 2, "APPLY", 8, 8, 3),
+                (8, 4, "APPLY", 4, 4, 2)]:
+        with pytest.raises(binding.DgError):
+            binding.tile_set(*bad)
+    assert binding.tile_get(8, 4, "APPLY")[0] == 0
