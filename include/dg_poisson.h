@@ -154,7 +154,8 @@ dg_status dg_mesh_coords(const dg_ctx* ctx, int mesh_id, double* xyz, double* fx
 
 /* Solve nrhs Poisson problems.  mesh_id (host [nrhs]) names each problem's
  * mesh.  rho: sources at the nodes (packed fields); g: Dirichlet data (packed
- * face vectors); x0: initial guesses (packed fields) or NULL for zero;
+ * face vectors), or NULL: computed from rho by quadrature, as dg_boundary_data
+ * does; x0: initial guesses (packed fields) or NULL for zero;
  * v: solutions (packed fields).  stats: host [nrhs] or NULL. */
 dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, const double* rho,
                                  const double* g, const double* x0, double* v,

@@ -230,14 +230,14 @@ class Context:
 
     # ---- solves
     def solve_batch(self, rho, g, mesh_ids=None, x0=None, out=None):
-        """Solve the packed batch; returns (v, stats list of dicts)."""
+        """Solve the packed batch; returns (v, stats list of dicts).  g None: Dirichlet data by quadrature."""
         nrhs = len(mesh_ids) if mesh_ids is not None else (rho.numel() // self.info[0]["n_dofs"] if rho.numel() else 0)
         if mesh_ids is None:
             mesh_ids = [0] * nrhs
         ids = (ctypes.c_int * max(1, nrhs))(*mesh_ids)
         nd = sum(self.info[m]["n_dofs"] for m in mesh_ids)
         nf = sum(self.info[m]["n_face"] for m in mesh_ids)
-        if rho.numel() != nd or g.numel() != nf:
+        if rho.numel() != nd or (g is not None and g.numel() != nf):
             raise ValueError("rho/g sizes do not match the meshes")
         if out is None:
             out = torch.empty(nd, dtype=torch.float64, device=rho.device)

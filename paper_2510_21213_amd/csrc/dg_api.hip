@@ -1203,7 +1203,7 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
         g_prof = &ctx->prof;
         if (nrhs < 0) throw ArgError("nrhs must be >= 0");
         if (nrhs == 0) return;
-        if (!mesh_id || !rho || !g || !v) throw ArgError("null pointer argument");
+        if (!mesh_id || !rho || !v) throw ArgError("null pointer argument");
         for (int i = 0; i < nrhs; ++i) check_mesh_id(ctx, mesh_id[i]);
         const hipStream_t user = stream;
         stream = enter(ctx, user);
@@ -1277,7 +1277,7 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
             const int cnt = P.cnt;
             ensure_b(M, cnt, fp32);  // the assembled right-hand sides of the whole part
             const bool want_guess = !x0 && ctx->guess;
-            if ((!P.contig || want_guess) && M.cap_g < cnt) {
+            if ((!P.contig || want_guess || !g) && M.cap_g < cnt) {
                 dfree(M.grho);
                 dfree(M.gface);
                 dfree(M.gx0);
@@ -1291,18 +1291,23 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
             if (P.contig) {
                 const int i0 = P.idx.front();
                 P.rho = rho + off[i0];
-                P.g = g + foff[i0];
+                P.g = g ? g + foff[i0] : nullptr;
                 P.x0 = x0 ? x0 + off[i0] : nullptr;
                 P.v = v + off[i0];
             } else {
                 const long long* t = ctx->segtab + P.tab;
                 dg::launch_segcopy(rho, t, M.grho, t + cnt, n0, cnt, stream);
-                dg::launch_segcopy(g, t + 2 * cnt, M.gface, t + 3 * cnt, M.nface, cnt, stream);
+                if (g) dg::launch_segcopy(g, t + 2 * cnt, M.gface, t + 3 * cnt, M.nface, cnt, stream);
                 if (x0) dg::launch_segcopy(x0, t, M.gx0, t + cnt, n0, cnt, stream);
                 P.rho = M.grho;
                 P.g = M.gface;
                 P.x0 = x0 ? M.gx0 : nullptr;
                 P.v = M.gv;
+            }
+            if (!g) {
+                // no Dirichlet data given: computed from the sources by quadrature (Sec. 6.3)
+                quad_data(ctx, M, cnt, P.rho, nullptr, nullptr, nullptr, M.gface, stream);
+                P.g = M.gface;
             }
             dg::launch_rhs(M.lv[0], M.lv[0].dev64, cnt, P.rho, nullptr, nullptr, nullptr, P.g, M.nface, M.b, stream);
             if (want_guess) {

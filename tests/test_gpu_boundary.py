@@ -8,7 +8,7 @@ orders, so they agree to rounding: 1e-12 of the largest value of each source.
 import numpy as np
 import pytest
 
-from oracle import boundary, fdm, layout
+from oracle import boundary, fdm, layout, sipdg
 from oracle import exchange as ox
 from workloads import configs
 from workloads.gaussians import GaussianDensity
@@ -129,3 +129,34 @@ def test_exchange_with_quadrature_data(gpu_lib):
     for q, vq, Kq in zip([ox.pair_index(a, b, n) for a, b in ((i, i), (i, j), (j, j))], v_o, K_o):
         assert rel_l2_M(axes, mesh, v[q], vq) <= POT_BAR, q
         assert abs(K[q] - Kq) <= ENERGY_BAR, q
+
+
+def test_solve_batch_with_quadrature_data(gpu_lib):
+    """dg_poisson_solve_batch with no Dirichlet data computes it by quadrature for every mesh of
+    an interleaved two-mesh batch: the same potentials, bit for bit, as with the data computed
+    first by dg_boundary_data, and a sampled potential against the oracle's exact solve with
+    the oracle's own quadrature data at the parity tolerance."""
+    m0 = configs.Mesh((4, 4, 4), 4, (-4.0,) * 3, (4.0,) * 3)
+    m1 = configs.Mesh((3, 4, 5), 3, (-3.0, -3.5, -4.0), (3.0, 3.5, 4.5))
+    ctx = gpu_lib.Context([(m.E, m.p, m.lo, m.hi) for m in (m0, m1)], rtol=PARITY_RTOL)
+    ids = [0, 1, 1, 0, 1]
+    rhos = []
+    for k, mid in enumerate(ids):
+        xyz, _ = ctx.mesh_coords(mid)
+        rhos.append(_sources(xyz[0], xyz[1], xyz[2], k))
+    rho = _t(np.concatenate(rhos))
+    v, st = ctx.solve_batch(rho, None, mesh_ids=ids)
+    assert all(s["status"] == 0 and s["rel_residual"] <= PARITY_RTOL for s in st)
+    g = np.concatenate([ctx.boundary_data(_t(rhos[k]), mesh_id=mid).cpu().numpy() for k, mid in enumerate(ids)])
+    v2, _ = ctx.solve_batch(rho, _t(g), mesh_ids=ids)
+    v, v2 = v.cpu().numpy(), v2.cpu().numpy()
+    assert np.array_equal(v, v2)
+    axes = oracle_axes(m1)
+    X, Y, Z = oracle_grid(axes)
+    f = _sources(X, Y, Z, 2)
+    faces = layout.split_faces(boundary.potential_at(axes, f, boundary.boundary_points(axes)),
+                               [a.E for a in axes], axes[0].n)
+    ref = fdm.FDM(axes).solve(sipdg.rhs(axes, f, faces))
+    n0, n1 = ctx.info[0]["n_dofs"], ctx.info[1]["n_dofs"]
+    off = n0 + n1                       # right-hand side 2: after one field of each mesh
+    assert rel_l2_M(axes, m1, v[off:off + n1], ref) <= POT_BAR
