@@ -241,7 +241,7 @@ QuadPlan quad_plan(const LevelHost& L, int nsrc) {
     P.nface = 2 * (NZ * NY + NZ * NX + NY * NX);
     P.ntile = std::max(1, (nsrc + QUAD_RMAX - 1) / QUAD_RMAX);
     const int per = (nsrc + P.ntile - 1) / P.ntile;
-    P.R = std::max(4, (per + 3) / 4 * 4);
+    P.R = per < 4 ? per : (per + 3) / 4 * 4;  // 1-3 sources (a single density) unpadded
     const long long wpb = QUAD_BLOCK / 64, blocks = (P.nface + QUAD_BLOCK * QUAD_NB - 1) / (QUAD_BLOCK * QUAD_NB);
     const long long want = (QUAD_WAVES + wpb * blocks - 1) / (wpb * blocks);
     const int S0 = (int)std::max(1LL, std::min(NZ, want));
@@ -258,7 +258,7 @@ void launch_quad_data(const LevelHost& L, const LevelDev<double>* dev, const dou
     if (nsrc <= 0) return;
     const int NX = L.E[0] * L.n, NY = L.E[1] * L.n, NZ = L.E[2] * L.n;
     if (P.nface != 2 * ((long long)NZ * NY + (long long)NZ * NX + (long long)NY * NX) || P.nface > (1LL << 30) ||
-        P.R < 4 || P.R > QUAD_RMAX || P.R % 4 || (P.S > 1 && !part) || (long long)P.S * P.zper < NZ)
+        P.R < 1 || P.R > QUAD_RMAX || (P.R > 3 && P.R % 4) || (P.S > 1 && !part) || (long long)P.S * P.zper < NZ)
         throw std::logic_error("quadrature plan does not fit the mesh");
     const double hmin = std::min({L.h[0], L.h[1], L.h[2]});
     const double drop2 = (1e-6 * hmin) * (1e-6 * hmin);
@@ -273,7 +273,7 @@ void launch_quad_data(const LevelHost& L, const LevelDev<double>* dev, const dou
         switch (P.R) {
 #define QUAD_CASE(RR) \
     case RR: launch_quad_r<RR>(ntb, P.S, nodes, NX, NY, NZ, nface, P.zper, drop2, rec, out, nsrc, r0, direct, s); break;
-            QUAD_CASE(4) QUAD_CASE(8) QUAD_CASE(12) QUAD_CASE(16) QUAD_CASE(20) QUAD_CASE(24)
+            QUAD_CASE(1) QUAD_CASE(2) QUAD_CASE(3) QUAD_CASE(4) QUAD_CASE(8) QUAD_CASE(12) QUAD_CASE(16) QUAD_CASE(20) QUAD_CASE(24)
             QUAD_CASE(28) QUAD_CASE(32) QUAD_CASE(36) QUAD_CASE(40) QUAD_CASE(44) QUAD_CASE(48)
 #undef QUAD_CASE
             default: throw std::logic_error("no quadrature kernel for this tile");

@@ -40,10 +40,10 @@ def _mesh(E, p, lo, hi):
 
 
 @pytest.mark.parametrize("E,p,nsrc", [((3, 4, 5), 3, 1), ((3, 4, 5), 3, 7), ((2, 3, 2), 4, 52), ((2, 2, 1), 7, 3),
-                                       ((8, 8, 8), 1, 5), ((3, 2, 2), 4, 36), ((2, 2, 3), 3, 96)])
+                                       ((8, 8, 8), 1, 5), ((3, 2, 2), 4, 36), ((2, 2, 3), 3, 96), ((2, 3, 2), 4, 2)])
 def test_boundary_data_matches_oracle(gpu_lib, E, p, nsrc):
     """Ragged face counts (not a multiple of the 256-node block), one and several source
-    tiles (52 sources: two tiles of 28; 96: two of the widest tile, 48), the 36-source tile
+    tiles (1, 2 and 3 sources unpadded; 52: two tiles of 28; 96: two of the widest, 48), the 36-source tile
     of the exchange workload, a single element along z (every node of it on the z faces) and
     degree 1 (half the nodes of each row on an element face)."""
     lo, hi = [-3.0, -2.5, -4.0], [3.5, 2.0, 3.0]
