@@ -309,6 +309,38 @@ def test_every_compiled_tile_gives_the_same_operator(gpu_lib):
             gpu_lib.tile_set(fp, 5, st, *t)
 
 
+def test_full_solves_agree_on_every_compiled_tile(gpu_lib):
+    """Full solves with every step of the degree-4 level on another compiled tile (both
+    arithmetics, FP64 and mixed precision, two solver lanes) reach the same potentials as with
+    the default tiles: only the order of the partial dot products changes."""
+    wl = configs.scaled(4, 4, 18, seed=53)
+    mesh = wl.meshes[0]
+    m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
+    steps = list(gpu_lib.STEPS)
+    saved = {(fp, st): gpu_lib.tile_get(fp, 5, st) for fp in (4, 8) for st in steps}
+
+    def solve(prec):
+        ctx = gpu_lib.Context([m], precision=prec, rtol=1e-11)
+        rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+        v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
+        assert all(s["status"] == 0 for s in st)
+        ctx.close()
+        return _n(v)
+
+    ref = {prec: solve(prec) for prec in ("fp64", "fp32_ir")}
+    try:
+        for tile in ((4, 2, 4), (4, 4, 2), (2, 2, 3)):
+            for fp in (4, 8):
+                for st in steps:
+                    gpu_lib.tile_set(fp, 5, st, *tile)
+            for prec in ("fp64", "fp32_ir"):
+                v = solve(prec)
+                assert np.max(np.abs(v - ref[prec])) <= 1e-8 * np.max(np.abs(ref[prec])), (tile, prec)
+    finally:
+        for (fp, st), t in saved.items():
+            gpu_lib.tile_set(fp, 5, st, *t)
+
+
 def test_non_finite_inputs_are_rejected(gpu_lib):
     """A NaN or Inf in a source, its Dirichlet data or a caller's initial guess is reported as
     an argument error, in both precisions and over two solver lanes (20 right-hand sides); the
