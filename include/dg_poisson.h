@@ -50,7 +50,9 @@
  *   then not to be used; DG_ERR_HIP when a HIP runtime call fails
  *   (dg_last_error() gives the message);
  *   DG_WARN_NOT_CONVERGED when a right-hand side missed its tolerance within
- *   max_iter (its stats entry says which).
+ *   max_iter (its stats entry says which); DG_ERR_BREAKDOWN when the last FP64
+ *   PCG pass of a right-hand side stopped on a non-positive p.Ap or r.z short
+ *   of its tolerance (after restarts and, in FP32_IR, the FP64 fallback).
  */
 #ifndef DG_POISSON_H
 #define DG_POISSON_H
