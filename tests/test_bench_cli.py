@@ -1,0 +1,33 @@
+"""The benchmark's command-line contract, on the CPU: one GPU only, and the committed
+rocprofv3 summaries that its roofline figures read."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_committed_counter_summaries_parse():
+    """Each summary carries one traffic line naming the source hash it was taken on and a
+    positive byte count; the benchmark reports it only while that hash matches the source
+    (a kernel edited since reads null until the counters are taken again)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    for profile, source in (("cheb_step_exchange8.md", "dg_kernels.hip"),
+                            ("boundary_quadrature_exchange8.md", "dg_boundary.hip")):
+        lines = [l for l in open(os.path.join(ROOT, "profiles", profile)) if l.startswith("traffic-json:")]
+        assert len(lines) == 1, profile
+        rec = json.loads(lines[0].split(":", 1)[1])
+        assert len(rec["kernel_source_sha256_16"]) == 16 and rec["traffic_bytes_per_launch"] > 0
+        t = bench.measured_traffic(profile, source)
+        assert t is None or t == rec["traffic_bytes_per_launch"]
+    assert bench._host()["host_cpus"] >= 1
