@@ -31,11 +31,11 @@ class FDM:
         sx, sy, sz = self.S
         Qx, Qy, Qz = self.Q
         t = np.asarray(b, dtype=np.float64) * (sz[:, None, None] * sy[None, :, None] * sx[None, None, :])
-        t = np.einsum("Xa,zyX->zya", Qx, t)
-        t = np.einsum("Yb,zYx->zbx", Qy, t)
-        t = np.einsum("Zc,Zyx->cyx", Qz, t)
+        t = np.einsum("Xa,zyX->zya", Qx, t, optimize=True)
+        t = np.einsum("Yb,zYx->zbx", Qy, t, optimize=True)
+        t = np.einsum("Zc,Zyx->cyx", Qz, t, optimize=True)
         t = t / self.denom
-        t = np.einsum("Xa,zya->zyX", Qx, t)
-        t = np.einsum("Yb,zbx->zYx", Qy, t)
-        t = np.einsum("Zc,cyx->Zyx", Qz, t)
+        t = np.einsum("Xa,zya->zyX", Qx, t, optimize=True)
+        t = np.einsum("Yb,zbx->zYx", Qy, t, optimize=True)
+        t = np.einsum("Zc,cyx->Zyx", Qz, t, optimize=True)
         return t * (sz[:, None, None] * sy[None, :, None] * sx[None, None, :])
