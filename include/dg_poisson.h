@@ -77,8 +77,15 @@ typedef enum {
  * FP32_IR: FP64 iterative refinement (FP64 right-hand side, solution and
  * residual) around an inner PCG whose vectors, operator applications and
  * smoothing are FP32; dot products, the coarsest-grid solve and all energy
- * reductions stay FP64. */
-typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_IR = 1 } dg_precision;
+ * reductions stay FP64.
+ * FP32_PC: FP64 PCG (FP64 iterate, residual and search direction, FP64
+ * operator application of the search direction, FP64 dot products) whose
+ * preconditioner, the V-cycle, runs in FP32 (smoothing, transfers and their
+ * fields; the coarsest-grid solve in FP64 arithmetic).  The iterate is FP64
+ * CG's, so a solve stopped at a residual tolerance has the accuracy of an
+ * FP64 solve stopped there, while most bytes moved are the V-cycle's FP32
+ * ones. */
+typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_IR = 1, DG_PREC_FP32_PC = 2 } dg_precision;
 
 /* A uniform hexahedral mesh: ne[d] elements along axis d on [lo[d], hi[d]],
  * Gauss-Lobatto nodal polynomials of degree p (1 <= p <= 7). */
@@ -177,6 +184,17 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
 dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* phi, const double* g_pairs,
                             double* W, double* K_pairs, double* E_x, double* v_pairs,
                             dg_rhs_stats* stats, hipStream_t stream);
+
+/* Pair densities (Sec. 6.1: the source of the exchange Poisson problem of
+ * eq. fock_poisson for u = phi_i and psi_s = phi_j is their product at the
+ * nodes): rho[q - first_pair] = phi_i phi_j for the npairs pairs q =
+ * first_pair .. first_pair + npairs - 1 of norb orbitals in the pair order
+ * above.  phi: device [norb][n_dofs] (packed fields); rho: device
+ * [npairs][n_dofs], written.  Needs no context; enqueued on `stream`.
+ * Errors: DG_ERR_ARG for a pair range outside 0 .. norb(norb+1)/2, more than
+ * 65535 pairs, or null pointers with work to do. */
+dg_status dg_pair_densities(long long n_dofs, int norb, int first_pair, int npairs, const double* phi, double* rho,
+                            hipStream_t stream);
 
 /* Dirichlet data by quadrature (Sec. 6.3): the full-space problem -Lap u =
  * 4 pi f is restated on the mesh box with boundary values equal to the

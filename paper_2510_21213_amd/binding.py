@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("DG_POISSON_LIB", os.path.join(_HERE, "libdgpoisson.so"))
 
 DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
-DG_PREC_FP64, DG_PREC_FP32_IR = 0, 1
-PRECISIONS = {"fp64": DG_PREC_FP64, "fp32_ir": DG_PREC_FP32_IR}
+DG_PREC_FP64, DG_PREC_FP32_IR, DG_PREC_FP32_PC = 0, 1, 2
+PRECISIONS = {"fp64": DG_PREC_FP64, "fp32_ir": DG_PREC_FP32_IR, "fp32_pc": DG_PREC_FP32_PC}
 
 
 class DgMesh(ctypes.Structure):
@@ -64,6 +64,7 @@ def _load():
         "dg_vcycle_apply_f32": (I, [P, I, I, I, P, P, P]),
         "dg_rhs_assemble": (I, [P, I, I, P, P, P, P]),
         "dg_boundary_data": (I, [P, I, I, P, P, P]),
+        "dg_pair_densities": (I, [LL, I, I, I, P, P, P]),
         "dg_tile_set": (I, [I, I, I, I, I, I]),
         "dg_tile_get": (I, [I, I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "dg_vcycle_apply": (I, [P, I, I, I, P, P, P]),
@@ -132,6 +133,17 @@ if os.path.exists(TILE_TABLE) and not os.environ.get("DG_POISSON_NO_TILE_TABLE")
     apply_tile_table()
 
 
+def pair_densities(phi, norb, first=0, count=None):
+    """rho_ij = phi_i phi_j for the pairs first .. first+count-1 (row-major i <= j order) of the
+    packed orbitals phi (float64 CUDA tensor [norb * n_dofs]); returns [count * n_dofs]."""
+    nd = phi.numel() // norb
+    total = norb * (norb + 1) // 2
+    count = total - first if count is None else count
+    rho = torch.empty(count * nd, dtype=torch.float64, device=phi.device)
+    _check(lib.dg_pair_densities(nd, norb, first, count, _ptr(phi), _ptr(rho), _stream()), "pair_densities")
+    return rho
+
+
 def status_string(code):
     return lib.dg_status_string(code).decode()
 
@@ -178,7 +190,7 @@ class Context:
     """A set-up DG Poisson solver for one or more uniform meshes.
 
     meshes: list of (ne, p, lo, hi) with ne, lo, hi 3-sequences.
-    options: fields of dg_opts (precision may be "fp64" or "fp32_ir").
+    options: fields of dg_opts (precision may be "fp64", "fp32_ir" or "fp32_pc").
     """
 
     def __init__(self, meshes, **options):

@@ -67,19 +67,27 @@ void dfree(T*& p) {
     p = nullptr;
 }
 
-// Per-precision work space of one mesh for `cap` right-hand sides.
+// Per-precision work space of one mesh, in groups sized separately (right-hand sides each holds):
+// WK_R the level-0 residual (the V-cycle source), WK_PCG the other level-0 PCG vectors, WK_LV the
+// per-level smoother and transfer vectors, WK_TMP one more level-0 field (FP32_PC on a degree
+// with no mixed-precision operator kernel).
+enum { WK_R = 1, WK_PCG = 2, WK_LV = 4, WK_TMP = 8, WK_ALL = WK_R | WK_PCG | WK_LV };
 template <typename T>
 struct Work {
     std::vector<T*> f, za, zb;  // per level (f[0] unused: the PCG residual is the level-0 source)
-    T *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
-    int cap = 0;
-    void release() {
+    T *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *tmp = nullptr;
+    int cap_r = 0, cap_pcg = 0, cap_lv = 0, cap_tmp = 0;
+    void release_lv() {
         for (auto* p : f) dfree(p);
         for (auto* p : za) dfree(p);
         for (auto* p : zb) dfree(p);
         f.clear(); za.clear(); zb.clear();
-        dfree(x); dfree(r); dfree(p0); dfree(p1); dfree(q);
-        cap = 0;
+        cap_lv = 0;
+    }
+    void release() {
+        release_lv();
+        dfree(x); dfree(r); dfree(p0); dfree(p1); dfree(q); dfree(tmp);
+        cap_r = cap_pcg = cap_tmp = 0;
     }
 };
 
@@ -112,21 +120,21 @@ struct dg_ctx {
         dg::RhsState* st_in = nullptr;   // inner FP32 state
         dg::RhsState* st_host = nullptr; // pinned host mirror
         int cap_b = 0, cap_st = 0;
-        // captured PCG iterations, per precision (index 0: FP64, 1: FP32)
+        // captured PCG iterations, per kind of run (index 0: FP64, 1: FP32 inner solve, 2: FP32_PC)
         struct Graph {
             hipGraphExec_t exec = nullptr;
             int nrhs = 0, every = 0;
             bool prof = false;
             std::vector<hipEvent_t> ev;
             size_t nev = 0;
-        } graph[2];
+        } graph[3];
         // multi-mesh batches: the mesh's own stream and completion event, and its
         // right-hand sides gathered from the caller's packing when they are not contiguous
         hipStream_t stream = nullptr;
         hipEvent_t ev_done = nullptr;
-        // iterations the k-th PCG run of the last solve needed (per precision): the next
+        // iterations the k-th PCG run of the last solve needed (per kind of run): the next
         // solve replays that many before its first host check
-        std::vector<int> pred[2];
+        std::vector<int> pred[3];
         // timing events of eager launches driven by this solver instance
         std::vector<hipEvent_t> pev;
         size_t pused = 0;
@@ -199,27 +207,50 @@ void ensure_state(Mesh& M, int nrhs) {
 }
 
 template <typename T>
-void ensure_work(Mesh& M, Work<T>& W, int nrhs) {
-    if (W.cap >= nrhs) return;
-    drop_graphs(M);
-    W.release();
-    const int L = (int)M.lv.size();
-    W.f.assign(L, nullptr);
-    W.za.assign(L, nullptr);
-    W.zb.assign(L, nullptr);
-    for (int l = 0; l < L; ++l) {
-        const long long n = M.lv[l].ndof * nrhs;
-        if (l > 0) W.f[l] = dalloc<T>(n);
-        W.za[l] = dalloc<T>(n);
-        W.zb[l] = dalloc<T>(n);
-    }
+void ensure_work(Mesh& M, Work<T>& W, int nrhs, int parts = WK_ALL) {
     const long long n0 = M.lv[0].ndof * nrhs;
-    W.x = dalloc<T>(n0);
-    W.r = dalloc<T>(n0);
-    W.p0 = dalloc<T>(n0);
-    W.p1 = dalloc<T>(n0);
-    W.q = dalloc<T>(n0);
-    W.cap = nrhs;
+    const int L = (int)M.lv.size();
+    if ((parts & WK_R) && W.cap_r < nrhs) {
+        drop_graphs(M);
+        dfree(W.r);
+        W.r = dalloc<T>(n0);
+        W.cap_r = nrhs;
+    }
+    if ((parts & WK_PCG) && W.cap_pcg < nrhs) {
+        drop_graphs(M);
+        dfree(W.x); dfree(W.p0); dfree(W.p1); dfree(W.q);
+        W.x = dalloc<T>(n0);
+        W.p0 = dalloc<T>(n0);
+        W.p1 = dalloc<T>(n0);
+        W.q = dalloc<T>(n0);
+        W.cap_pcg = nrhs;
+    }
+    if ((parts & WK_TMP) && W.cap_tmp < nrhs) {
+        drop_graphs(M);
+        dfree(W.tmp);
+        W.tmp = dalloc<T>(n0);
+        W.cap_tmp = nrhs;
+    }
+    if ((parts & WK_LV) && W.cap_lv < nrhs) {
+        drop_graphs(M);
+        W.release_lv();
+        W.f.assign(L, nullptr);
+        W.za.assign(L, nullptr);
+        W.zb.assign(L, nullptr);
+        for (int l = 0; l < L; ++l) {
+            const long long n = M.lv[l].ndof * nrhs;
+            if (l > 0) W.f[l] = dalloc<T>(n);
+            W.za[l] = dalloc<T>(n);
+            W.zb[l] = dalloc<T>(n);
+        }
+        W.cap_lv = nrhs;
+    }
+}
+
+// Work space of an FP32_PC solve: FP64 PCG vectors, an FP32 V-cycle with its FP32 source.
+void ensure_work_pc(Mesh& M, int nrhs) {
+    ensure_work<double>(M, M.w64, nrhs, WK_R | WK_PCG | (dg::has_pq_mixed(M.lv[0]) ? 0 : WK_TMP));
+    ensure_work<float>(M, M.w32, nrhs, WK_R | WK_LV);
 }
 
 void ensure_b(Mesh& M, int nrhs, bool need_r64) {
@@ -334,13 +365,44 @@ void pcg_iteration(Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, int parity, 
     const int nb_rz = dg::op_blocks<T>(L0, dg::BM_CHEBDOT), nb = dg::op_blocks<T>(L0, dg::BM_PQ);
     const int nc = dg::chunks_of(L0.ndof);
     T* z = vcycle<T>(M, W, 0, nrhs, st, W.r, true, true, s);
-    dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nb_rz, s);
+    if (M.lv.size() == 1) {
+        // the preconditioner was the exact solve alone: no smoothing step wrote the r.z partial sums
+        dg::launch_dot<T, T>(L0.ndof, nrhs, st, W.r, z, M.partial, M.pstride, s);
+        dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nc, s);
+    } else {
+        dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nb_rz, s);
+    }
     T* pold = parity ? W.p1 : W.p0;
     T* pnew = parity ? W.p0 : W.p1;
     dg::launch_brick<T>(dg::BM_PQ, L0, dv, nrhs, st, z, pold, nullptr, nullptr, W.q, pnew, M.partial, M.pstride, 0.0,
                         0.0, s);
     dg::launch_finalize(dg::FIN_PQ, nrhs, st, M.partial, M.pstride, nb, s);
     dg::launch_update<T>(L0, dv, nrhs, st, W.x, W.r, pnew, W.q, W.za[0], M.cheb[0].c0, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_RR, nrhs, st, M.partial, M.pstride, nc, s);
+}
+
+// One PCG iteration of FP32_PC: the PCG vectors, the operator of the search direction and all dot
+// products in FP64 (W); the V-cycle preconditioner in FP32 (M.w32, whose level-0 residual r32 and
+// first smoothing iterate the update step writes).
+void pcg_iteration_pc(Mesh& M, Work<double>& W, int nrhs, dg::RhsState* st, int parity, hipStream_t s) {
+    const LevelHost& L0 = M.lv[0];
+    Work<float>& V = M.w32;
+    const int nb_rz = dg::op_blocks<float>(L0, dg::BM_CHEBDOT), nb = dg::op_blocks<double>(L0, dg::BM_PQ);
+    const int nc = dg::chunks_of(L0.ndof);
+    float* z = vcycle<float>(M, V, 0, nrhs, st, V.r, true, true, s);
+    if (M.lv.size() == 1) {
+        // the preconditioner was the exact solve alone: no smoothing step wrote the r.z partial sums
+        dg::launch_dot<float, float>(L0.ndof, nrhs, st, V.r, z, M.partial, M.pstride, s);
+        dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nc, s);
+    } else {
+        dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nb_rz, s);
+    }
+    double* pold = parity ? W.p1 : W.p0;
+    double* pnew = parity ? W.p0 : W.p1;
+    dg::launch_pq_mixed(L0, L0.dev64, nrhs, st, z, pold, W.q, pnew, W.tmp, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_PQ, nrhs, st, M.partial, M.pstride, nb, s);
+    dg::launch_update_pc(L0, L0.dev64, nrhs, st, W.x, W.r, pnew, W.q, V.r, V.za[0], M.cheb[0].c0, M.partial,
+                         M.pstride, s);
     dg::launch_finalize(dg::FIN_RR, nrhs, st, M.partial, M.pstride, nc, s);
 }
 
@@ -362,19 +424,31 @@ void init_state(Mesh& M, dg::RhsState* st, int nrhs, double rtol, int maxit, hip
 }
 
 // PCG on level 0 from the current x and r of W (r holds the residual);
-// st must have tol2/maxit/bb set.  Returns the iterations performed.
-template <typename T>
+// st must have tol2/maxit/bb set.  PC: FP64 PCG (T = double) preconditioned by the FP32 V-cycle.
+template <typename T, bool PC = false>
 void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const dg::RhsState* gate, int slot,
              hipStream_t s) {
+    static_assert(!PC || sizeof(T) == 8, "FP32_PC runs its PCG in FP64");
     const LevelHost& L0 = M.lv[0];
     const int nc = dg::chunks_of(L0.ndof);
+    const int kind = PC ? 2 : (sizeof(T) == 8 ? 0 : 1);
+    const size_t vbytes = PC ? sizeof(float) : sizeof(T);  // element size of the V-cycle's fields
     // rr and the active flags
     dg::launch_dot<T, T>(L0.ndof, nrhs, gate, W.r, W.r, M.partial, M.pstride, s);
     dg::launch_finalize(dg::FIN_RR0, nrhs, st, M.partial, M.pstride, nc, s);
     if (gate) dg::launch_gate(nrhs, st, gate, s);  // finished outer loops keep their inner solve idle
-    dg::launch_cheb0<T>(L0, ldev<T>(L0), nrhs, st, W.r, W.za[0], M.cheb[0].c0, s);
+    if constexpr (PC)
+        dg::launch_to32_cheb0(L0, L0.dev64, nrhs, st, W.r, M.w32.r, M.w32.za[0], M.cheb[0].c0, s);
+    else
+        dg::launch_cheb0<T>(L0, ldev<T>(L0), nrhs, st, W.r, W.za[0], M.cheb[0].c0, s);
     dg::launch_fill<T>(W.p0, (T)0, L0.ndof * nrhs, s);
     dg::launch_fill<T>(W.p1, (T)0, L0.ndof * nrhs, s);
+    auto iteration = [&](int parity) {
+        if constexpr (PC)
+            pcg_iteration_pc(M, W, nrhs, st, parity, s);
+        else
+            pcg_iteration<T>(M, W, nrhs, st, parity, s);
+    };
     const int maxit = ctx->opts.max_iter;
     const bool timed = g_prof && g_prof->on;
     int it = 0;
@@ -382,7 +456,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         // `every` iterations captured once and replayed; an even count keeps the p ping-pong aligned
         int every = std::max(2, ctx->opts.check_every);
         every += every & 1;
-        auto& G = M.graph[sizeof(T) == 8 ? 0 : 1];
+        auto& G = M.graph[kind];
         if (!G.exec || G.nrhs != nrhs || G.every != every || G.prof != timed) {
             if (G.exec) (void)hipGraphExecDestroy(G.exec);
             G.exec = nullptr;
@@ -402,7 +476,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
             HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             hipGraph_t graph = nullptr;
             try {
-                for (int c = 0; c < every; ++c) pcg_iteration<T>(M, W, nrhs, st, c & 1, s);
+                for (int c = 0; c < every; ++c) iteration(c & 1);
             } catch (...) {
                 (void)hipStreamEndCapture(s, &graph);  // leave capture mode before reporting
                 if (graph) (void)hipGraphDestroy(graph);
@@ -421,7 +495,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         }
         // replay up to the count the same run of the previous solve needed, then check
         // after every replay (finished right-hand sides cost only early-exiting launches)
-        auto& pred = M.pred[sizeof(T) == 8 ? 0 : 1];
+        auto& pred = M.pred[kind];
         const int ahead = slot < (int)pred.size() ? pred[slot] : 0;
         while (it < maxit) {
             do {
@@ -441,7 +515,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
                 M.pused = 0;
                 g_sink = {&M.pev, &M.pused};
             }
-            for (int c = 0; c < every && it < maxit; ++c, ++it) pcg_iteration<T>(M, W, nrhs, st, it & 1, s);
+            for (int c = 0; c < every && it < maxit; ++c, ++it) iteration(it & 1);
             HIPCHK(hipGetLastError());
             read_state(M, st, nrhs, s);
             if (timed) prof_sum(M.pev, M.pused);
@@ -451,7 +525,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         }
     }
     {
-        auto& pred = M.pred[sizeof(T) == 8 ? 0 : 1];
+        auto& pred = M.pred[kind];
         if ((int)pred.size() <= slot) pred.resize(slot + 1, 0);
         int need = 0;
         for (int i = 0; i < nrhs; ++i) need = std::max(need, M.st_host[i].iters);
@@ -465,7 +539,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
         long long cycles = 0;
         for (int i = 0; i < nrhs; ++i) cycles += M.st_host[i].iters;
         std::lock_guard<std::mutex> lock(g_prof->mu);
-        g_prof->bytes += per_cycle * (double)cycles * (double)L0.ndof * sizeof(T);
+        g_prof->bytes += per_cycle * (double)cycles * (double)L0.ndof * (double)vbytes;
     }
 }
 
@@ -534,8 +608,12 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
     const auto& o = ctx->opts;
     ensure_state(M, nrhs);
     std::vector<int> iters(nrhs, 0), outer(nrhs, 0), kept(nrhs, x0 ? 1 : 0);
-    if (o.precision == DG_PREC_FP64) {
-        ensure_work<double>(M, M.w64, nrhs);
+    if (o.precision == DG_PREC_FP64 || o.precision == DG_PREC_FP32_PC) {
+        const bool pc = o.precision == DG_PREC_FP32_PC;
+        if (pc)
+            ensure_work_pc(M, nrhs);
+        else
+            ensure_work<double>(M, M.w64, nrhs);
         Work<double>& W = M.w64;
         init_state(M, M.st, nrhs, o.rtol, o.max_iter, s);
         dg::launch_dot<double, double>(n0, nrhs, nullptr, b, b, M.partial, M.pstride, s);
@@ -555,7 +633,10 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             dg::launch_copy(b, W.r, n0 * nrhs, s);
         }
         for (int restart = 0; restart < 3; ++restart) {
-            pcg_run<double>(ctx, M, W, nrhs, M.st, nullptr, restart, s);
+            if (pc)
+                pcg_run<double, true>(ctx, M, W, nrhs, M.st, nullptr, restart, s);
+            else
+                pcg_run<double>(ctx, M, W, nrhs, M.st, nullptr, restart, s);
             for (int i = 0; i < nrhs; ++i) iters[i] += M.st_host[i].iters;
             // FP64 residual of the current solution
             dg::launch_brick<double>(dg::BM_RESIDDOT, L0, L0.dev64, nrhs, nullptr, W.x, nullptr, b, nullptr, W.r,
@@ -697,11 +778,13 @@ constexpr int kLaneMin = 16;  // smallest batch of one mesh that is split over t
 // Sizes the work space of a lane for cnt right-hand sides (on the calling thread, so
 // that the solves allocate nothing).
 void prepare_lane(dg_ctx* ctx, Mesh& M, int cnt) {
-    const bool fp32 = ctx->opts.precision == DG_PREC_FP32_IR;
-    ensure_b(M, cnt, fp32);
+    const int prec = ctx->opts.precision;
+    ensure_b(M, cnt, prec == DG_PREC_FP32_IR);
     ensure_state(M, cnt);
-    if (fp32)
+    if (prec == DG_PREC_FP32_IR)
         ensure_work<float>(M, M.w32, cnt);
+    else if (prec == DG_PREC_FP32_PC)
+        ensure_work_pc(M, cnt);
     else
         ensure_work<double>(M, M.w64, cnt);
 }
@@ -781,11 +864,9 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
         if (!(mesh.hi[d] > mesh.lo[d])) throw ArgError("box must have positive extent");
     }
     M.mesh = mesh;
+    // a single level (a small degree-1 mesh) is solved by PCG with the exact coarsest-level
+    // solve as its preconditioner (build_coarse rejects one with more than CMAX nodes per axis)
     auto specs = dg::hierarchy(mesh.ne, mesh.p, o.n_levels);
-    if (specs.size() < 2) {
-        // a single level would need the exact solve on the fine mesh; add a degree or mesh step when possible
-        throw ArgError("mesh too small for a multigrid hierarchy (needs at least two levels)");
-    }
     for (auto& [E, p] : specs) {
         LevelHost L;
         for (int d = 0; d < 3; ++d) {
@@ -1024,7 +1105,8 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
         const auto& o = ctx->opts;
         if (o.cheb_degree < 1 || o.cheb_degree_h < 0 || o.cheb_ratio <= 1.0 || o.cheb_safety < 1.0 || o.lanczos_steps < 2 ||
             o.penalty_eps <= 0 || o.rtol <= 0 || o.max_iter < 1 || o.max_outer < 1 || o.inner_rtol <= 0 ||
-            o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 2)
+            o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 2 ||
+            (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_IR && o.precision != DG_PREC_FP32_PC))
             throw ArgError("invalid solver options");
         HIPCHK(hipGetDevice(&ctx->device));
         HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
@@ -1187,7 +1269,6 @@ dg_status dg_mesh_coords(const dg_ctx* ctx, int mesh_id, double* xyz, double* fx
 // Status of a call whose right-hand sides all ran: a breakdown that the FP64 restarts could not
 // cure first, then a missed tolerance.
 static dg_status worst_status(const dg_rhs_stats* stats, int n) {
-    if (!stats) return DG_OK;
     dg_status w = DG_OK;
     for (int i = 0; i < n; ++i) {
         if (stats[i].status == DG_ERR_BREAKDOWN) return DG_ERR_BREAKDOWN;
@@ -1198,6 +1279,7 @@ static dg_status worst_status(const dg_rhs_stats* stats, int n) {
 
 dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, const double* rho, const double* g,
                                  const double* x0, double* v, dg_rhs_stats* stats, hipStream_t stream) {
+    std::vector<dg_rhs_stats> all;  // every right-hand side's statistics, whether or not the caller takes them
     dg_status st = run_guarded([&] {
         if (!ctx) throw ArgError("null context");
         g_prof = &ctx->prof;
@@ -1335,17 +1417,19 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
                 const long long* t = ctx->segtab + P.tab;
                 dg::launch_segcopy(P.v, t + P.cnt, v, t, ctx->meshes[P.m].lv[0].ndof, P.cnt, stream);
             }
-            if (stats)
-                for (int q = 0; q < P.cnt; ++q) stats[P.idx[q]] = P.stats[q];
+            all.resize(nrhs);
+            for (int q = 0; q < P.cnt; ++q) all[P.idx[q]] = P.stats[q];
         }
+        if (stats) std::copy(all.begin(), all.end(), stats);
         HIPCHK(hipStreamSynchronize(stream));
         leave(ctx, user);
     });
-    return st == DG_OK ? worst_status(stats, nrhs) : st;
+    return st == DG_OK ? worst_status(all.data(), (int)all.size()) : st;
 }
 
 dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* phi, const double* g_pairs, double* W,
                             double* K_pairs, double* E_x, double* v_pairs, dg_rhs_stats* stats, hipStream_t stream) {
+    std::vector<dg_rhs_stats> st_all;  // every pair's statistics, whether or not the caller takes them
     dg_status st = run_guarded([&] {
         check_mesh_id(ctx, mesh_id);
         g_prof = &ctx->prof;
@@ -1397,7 +1481,7 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
             dg::launch_pair_products(n0, npairs, phi, ctx->xpairs, ctx->xpairs + npairs, ctx->g_rho, stream);
             learned_guess(ctx, M, npairs, ctx->g_rho, stream);
         }
-        std::vector<dg_rhs_stats> st_all(npairs);
+        st_all.assign(npairs, dg_rhs_stats{});
         std::vector<Job> jobs;
         add_jobs(ctx, mesh_id, npairs, M.b, ctx->guess ? ctx->g_x0 : nullptr, v, st_all.data(), ctx->guess != nullptr,
                  jobs);
@@ -1422,7 +1506,21 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
             for (int j = i; j < norb; ++j, ++q) ex += (i == j ? 1.0 : 2.0) * K[q];
         if (E_x) *E_x = ex;
     });
-    return st == DG_OK ? worst_status(stats, norb * (norb + 1) / 2) : st;
+    return st == DG_OK ? worst_status(st_all.data(), (int)st_all.size()) : st;
+}
+
+dg_status dg_pair_densities(long long n_dofs, int norb, int first_pair, int npairs, const double* phi, double* rho,
+                            hipStream_t stream) {
+    return run_guarded([&] {
+        const long long total = (long long)norb * (norb + 1) / 2;
+        if (n_dofs < 0 || norb < 1 || first_pair < 0 || npairs < 0 || first_pair + (long long)npairs > total)
+            throw ArgError("bad pair range");
+        if (npairs > 65535) throw ArgError("at most 65535 pairs per call");
+        if (npairs == 0 || n_dofs == 0) return;
+        if (!phi || !rho) throw ArgError("null pointer argument");
+        dg::launch_pair_densities(n_dofs, norb, first_pair, npairs, phi, rho, stream);
+        HIPCHK(hipGetLastError());
+    });
 }
 
 dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g, hipStream_t stream) {

@@ -13,7 +13,9 @@ enum BrickMode {
     BM_CHEBDOT = 3,  // BM_CHEB and partial sums of f.out
     BM_PQ = 4,       // w = u + beta u2; out2 = w; out = A w; partial sums of w.out
     BM_RESIDDOT = 5,  // BM_RESID and partial sums of out.out
-    BM_RESTRICT = 6   // fc = P^T (f - A u) onto the next coarser (degree) level (launch_restrict only)
+    BM_RESTRICT = 6,  // fc = P^T (f - A u) onto the next coarser (degree) level (launch_restrict only)
+    BM_PQ32 = 7       // BM_PQ in FP64 with u an FP32 field (the preconditioned direction of FP32_PC;
+                      // launch_pq_mixed only; uses the tile of BM_PQ)
 };
 
 enum FinalizeWhat {
@@ -54,6 +56,14 @@ template <typename T>
 void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHost& Lc, const LevelDev<T>* devc,
                      int nrhs, const RhsState* st, const T* z, const T* f, T* fc, T* z1c, double c0c, hipStream_t s);
 
+// FP32_PC step of the FP64 PCG: p = z + beta p_old with z the FP32 V-cycle output, q = A p and
+// partial sums of p.q, all in FP64.  tmp: an FP64 field buffer used only on levels whose degree
+// has no slab kernel (z is widened into it first); may be null when has_pq_mixed(L).
+bool has_pq_mixed(const LevelHost& L);
+void launch_pq_mixed(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const float* z,
+                     const double* pold, double* q, double* pnew, double* tmp, double* partial, int pstride,
+                     hipStream_t s);
+
 // zf += P zc
 // zf = scale[rhs] * P zc for a degree step (writes every fine node); false when the step
 // between the two levels is not a degree step with a kernel for it (nothing launched)
@@ -77,6 +87,15 @@ void launch_cheb0(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const Rh
 template <typename T>
 void launch_update(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, T* x, T* r, const T* p,
                    const T* q, T* z1, double c0, double* partial, int pstride, hipStream_t s);
+
+// FP32_PC update: x += alpha p; r -= alpha q; partial sums of r.r (FP64); r32 = (float) r and
+// z1 = (float) c0 D^-1 r, the source and first smoothing iterate of the FP32 V-cycle.
+void launch_update_pc(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, double* x,
+                      double* r, const double* p, const double* q, float* r32, float* z1, double c0, double* partial,
+                      int pstride, hipStream_t s);
+// FP32_PC start: r32 = (float) r and z1 = (float) c0 D^-1 r.
+void launch_to32_cheb0(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const double* r,
+                       float* r32, float* z1, double c0, hipStream_t s);
 
 // partial sums of a.b per right-hand side (FP64 accumulation).
 template <typename TA, typename TB>
@@ -125,6 +144,10 @@ void launch_exchange(const LevelHost& L, const LevelDev<double>* dev, int norb, 
 // rho[q] = phi[pi[q]] * phi[pj[q]] for every pair q.
 void launch_pair_products(long long ndof, int npairs, const double* phi, const int* pi, const int* pj, double* rho,
                           hipStream_t s);
+
+// rho[q - first] = phi_i phi_j for the pairs q = first .. first + count - 1 (row-major pair order).
+void launch_pair_densities(long long ndof, int norb, int first, int count, const double* phi, double* rho,
+                           hipStream_t s);
 
 // dst[doff[q] + i] = src[soff[q] + i] for i < len and q < nseg (offset tables on the device).
 void launch_segcopy(const double* src, const long long* soff, double* dst, const long long* doff, long long len,

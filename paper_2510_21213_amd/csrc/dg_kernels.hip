@@ -454,6 +454,7 @@ struct SlabArgs {
     long long ndof;
     const RhsState* st;
     const T* u;
+    const float* uf;  // BM_PQ32: the FP32 field that takes the place of u
     const T* u2;
     const T* f;
     const T* zprev;
@@ -645,12 +646,23 @@ __device__ __forceinline__ void bstore(double v, brsrc r, uint32_t voff, uint32_
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
-// The N values of a node column of one element layer (stride N^2 values).
+// The N values of a node column of one element layer (stride N^2 values).  BM_PQ and BM_PQ32
+// read u + beta u2; in BM_PQ32 u is an FP32 field, addressed at half the byte offsets of T = double.
 template <typename T, int N, int MODE>
 __device__ __forceinline__ void load_col(T* v, brsrc ru, brsrc ru2, uint32_t voff, uint32_t soff, T beta) {
+    if constexpr (MODE == BM_PQ32) {
+        static_assert(sizeof(T) == 8, "BM_PQ32 is an FP64 step");
 #pragma unroll
-    for (int k = 0; k < N; ++k) bload(v[k], ru, voff, soff + k * N * N * (uint32_t)sizeof(T));
-    if constexpr (MODE == BM_PQ) {
+        for (int k = 0; k < N; ++k) {
+            float zf;
+            bload(zf, ru, voff >> 1, (soff >> 1) + k * N * N * 4u);
+            v[k] = (T)zf;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) bload(v[k], ru, voff, soff + k * N * N * (uint32_t)sizeof(T));
+    }
+    if constexpr (MODE == BM_PQ || MODE == BM_PQ32) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             T w;
@@ -677,7 +689,8 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr bool HAS_F = MODE == BM_RESID || MODE == BM_RESIDDOT || MODE == BM_CHEB || MODE == BM_CHEBDOT ||
                            MODE == BM_RESTRICT;
     constexpr bool IS_CHEB = MODE == BM_CHEB || MODE == BM_CHEBDOT;
-    constexpr bool DOT = MODE == BM_CHEBDOT || MODE == BM_PQ || MODE == BM_RESIDDOT;
+    constexpr bool IS_PQ = MODE == BM_PQ || MODE == BM_PQ32;
+    constexpr bool DOT = MODE == BM_CHEBDOT || IS_PQ || MODE == BM_RESIDDOT;
     constexpr int NC = (N - 1) / 2 + 1, NC3 = NC * NC * NC;  // BM_RESTRICT: coarse nodes per edge (degree p/2)
     __shared__ T su[N * PS];
     __shared__ T sr[MODE == BM_RESTRICT ? NC * OP : 1];  // BM_RESTRICT: residual contracted along z
@@ -695,15 +708,19 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     const uint32_t lstride = (uint32_t)(E0 * E1 * N3) * SZ;  // bytes per element layer
 
     const long long base = (long long)rhs * a.ndof;
-    const brsrc ru = rsrc_of(a.u + base, a.ndof);
-    const brsrc ru2 = rsrc_of(MODE == BM_PQ ? a.u2 + base : a.u + base, a.ndof);
+    brsrc ru;
+    if constexpr (MODE == BM_PQ32)
+        ru = rsrc_of(a.uf + base, a.ndof);
+    else
+        ru = rsrc_of(a.u + base, a.ndof);
+    const brsrc ru2 = rsrc_of(IS_PQ ? a.u2 + base : a.u + base, a.ndof);
     const brsrc rf = rsrc_of(HAS_F ? a.f + base : a.u + base, a.ndof);
     const brsrc rzp = rsrc_of(IS_CHEB && a.zprev ? a.zprev + base : a.u + base, a.ndof);
     T* const obase = MODE == BM_RESTRICT ? const_cast<T*>(a.u) : a.out;  // BM_RESTRICT stores no fine field
     const brsrc ro = rsrc_of(obase + base, a.ndof);
-    const brsrc ro2 = rsrc_of(MODE == BM_PQ ? a.out2 + base : obase + base, a.ndof);
+    const brsrc ro2 = rsrc_of(IS_PQ ? a.out2 + base : obase + base, a.ndof);
     T beta = 0;
-    if constexpr (MODE == BM_PQ) beta = (T)a.st[rhs].beta;
+    if constexpr (IS_PQ) beta = (T)a.st[rhs].beta;
     const bool has_zp = IS_CHEB && a.zprev;
 
     const RefDev<T>& R = a.L->ref;
@@ -898,7 +915,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                     const T zn = uz + a.cp * (uz - zpcol[k]) + cd * (fcol[k] - y);
                     bstore(zn, ro, coff, so);
                     if constexpr (MODE == BM_CHEBDOT) dot += (double)fcol[k] * (double)zn;
-                } else if constexpr (MODE == BM_PQ) {
+                } else if constexpr (IS_PQ) {
                     bstore(cur[k], ro2, coff, so);
                     bstore(y, ro, coff, so);
                     dot += (double)cur[k] * (double)y;
@@ -1074,7 +1091,7 @@ struct SlabGeom {
 template <typename T>
 static SlabGeom slab_geom(const LevelHost& L, int mode) {
     SlabGeom g;
-    const int* t = L.tile[sizeof(T) == 8][mode];
+    const int* t = L.tile[sizeof(T) == 8][mode == BM_PQ32 ? BM_PQ : mode];
     g.tx = t[0];
     g.ty = t[1];
     g.zlen = t[2];
@@ -1108,6 +1125,10 @@ static void slab_dispatch(int mode, const SlabArgs<T>& a, int grid, hipStream_t 
             if constexpr (N == 3 || N == 5)
                 hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESTRICT>), dim3(grid), dim3(WG), 0, s, a);
             break;
+        case BM_PQ32:
+            if constexpr (sizeof(T) == 8)
+                hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_PQ32>), dim3(grid), dim3(WG), 0, s, a);
+            break;
     }
 }
 
@@ -1115,7 +1136,8 @@ template <typename T>
 static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st,
                         const T* u, const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial,
                         int pstride, double cp, double cr, hipStream_t s, const LevelHost* Lc = nullptr,
-                        const LevelDev<T>* devc = nullptr, T* fc = nullptr, T* z1c = nullptr, double c0c = 0) {
+                        const LevelDev<T>* devc = nullptr, T* fc = nullptr, T* z1c = nullptr, double c0c = 0,
+                        const float* uf = nullptr) {
     const SlabGeom g = slab_geom<T>(L, mode);
     if (!g.tx) return false;
     if (mode == BM_RESTRICT && L.n != 3 && L.n != 5) return false;
@@ -1132,7 +1154,7 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
     a.nrhs = nrhs;
     a.ndof = L.ndof;
     a.st = st;
-    a.u = u; a.u2 = u2; a.f = f; a.zprev = zprev; a.out = out; a.out2 = out2;
+    a.u = u; a.uf = uf; a.u2 = u2; a.f = f; a.zprev = zprev; a.out = out; a.out2 = out2;
     a.partial = partial;
     a.pstride = pstride;
     a.cp = (T)cp;
@@ -1178,6 +1200,27 @@ void launch_brick(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs
         case 7: brick_dispatch<T, 7, be_of<7>()>(mode, a, grid, s); break;
         case 8: brick_dispatch<T, 8, be_of<8>()>(mode, a, grid, s); break;
     }
+}
+
+__global__ __launch_bounds__(256) void k_widen(const float* __restrict__ a, double* __restrict__ b, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = (double)a[i];
+}
+
+bool has_pq_mixed(const LevelHost& L) { return slab_geom<double>(L, BM_PQ).tx != 0; }
+
+void launch_pq_mixed(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const float* z,
+                     const double* pold, double* q, double* pnew, double* tmp, double* partial, int pstride,
+                     hipStream_t s) {
+    if (nrhs == 0) return;
+    // u is never read in BM_PQ32 (uf takes its place); q keeps the resource base valid
+    if (launch_slab<double>(BM_PQ32, L, dev, nrhs, st, q, pold, nullptr, nullptr, q, pnew, partial, pstride, 0.0,
+                            0.0, s, nullptr, nullptr, nullptr, nullptr, 0.0, z))
+        return;
+    if (!tmp) throw std::logic_error("launch_pq_mixed: no slab kernel for this degree and no widening buffer");
+    const long long n = L.ndof * nrhs;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, tmp, n);
+    launch_brick<double>(BM_PQ, L, dev, nrhs, st, tmp, pold, nullptr, nullptr, q, pnew, partial, pstride, 0.0, 0.0, s);
 }
 
 template void launch_brick<double>(int, const LevelHost&, const LevelDev<double>*, int, const RhsState*,
@@ -1778,6 +1821,83 @@ template void launch_update<double>(const LevelHost&, const LevelDev<double>*, i
 template void launch_update<float>(const LevelHost&, const LevelDev<float>*, int, const RhsState*, float*, float*,
                                    const float*, const float*, float*, double, double*, int, hipStream_t);
 
+template <int N>
+__global__ __launch_bounds__(256) void k_update_pc(const LevelDev<double>* __restrict__ L, int E0, int E1, int E2,
+                                                   long long ndof, const RhsState* st, double* __restrict__ x,
+                                                   double* __restrict__ r, const double* __restrict__ p,
+                                                   const double* __restrict__ q_, float* __restrict__ r32,
+                                                   float* __restrict__ z1, double c0, double* __restrict__ partial,
+                                                   int pstride) {
+    __shared__ double red[4];
+    const int rhs = blockIdx.y;
+    if (!st[rhs].active) return;
+    const double alpha = st[rhs].alpha;
+    const long long base = (long long)rhs * ndof;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    double acc = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q < ndof) {
+            const long long g = base + q;
+            x[g] += alpha * p[g];
+            const double rn = r[g] - alpha * q_[g];
+            r[g] = rn;
+            acc += rn * rn;
+            r32[g] = (float)rn;
+            z1[g] = (float)(c0 * rn / diag_at<double, N>(*L, E0, E1, E2, q));
+        }
+    }
+    const double s = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) partial[(long long)rhs * pstride + blockIdx.x] = s;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_to32_cheb0(const LevelDev<double>* __restrict__ L, int E0, int E1, int E2,
+                                                    long long ndof, const RhsState* st, const double* __restrict__ r,
+                                                    float* __restrict__ r32, float* __restrict__ z1, double c0) {
+    const int rhs = blockIdx.y;
+    if (st && !st[rhs].active) return;
+    const long long base = (long long)rhs * ndof;
+    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long q = q0 + v * 256;
+        if (q < ndof) {
+            const double rv = r[base + q];
+            r32[base + q] = (float)rv;
+            z1[base + q] = (float)(c0 * rv / diag_at<double, N>(*L, E0, E1, E2, q));
+        }
+    }
+}
+
+void launch_update_pc(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, double* x,
+                      double* r, const double* p, const double* q, float* r32, float* z1, double c0, double* partial,
+                      int pstride, hipStream_t s) {
+    if (nrhs == 0) return;
+    dim3 grid(chunks_of(L.ndof), nrhs);
+#define DG_UPC(NN)                                                                                                 \
+    case NN:                                                                                                       \
+        hipLaunchKernelGGL((k_update_pc<NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, st, x, r, \
+                           p, q, r32, z1, c0, partial, pstride);                                                   \
+        break;
+    switch (L.n) { DG_UPC(2) DG_UPC(3) DG_UPC(4) DG_UPC(5) DG_UPC(6) DG_UPC(7) DG_UPC(8) }
+#undef DG_UPC
+}
+
+void launch_to32_cheb0(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const double* r,
+                       float* r32, float* z1, double c0, hipStream_t s) {
+    if (nrhs == 0) return;
+    dim3 grid(chunks_of(L.ndof), nrhs);
+#define DG_T32(NN)                                                                                                 \
+    case NN:                                                                                                       \
+        hipLaunchKernelGGL((k_to32_cheb0<NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, st, r,   \
+                           r32, z1, c0);                                                                           \
+        break;
+    switch (L.n) { DG_T32(2) DG_T32(3) DG_T32(4) DG_T32(5) DG_T32(6) DG_T32(7) DG_T32(8) }
+#undef DG_T32
+}
+
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_dot(long long ndof, const RhsState* st, const TA* __restrict__ a,
                                              const TB* __restrict__ b, double* __restrict__ partial, int pstride) {
@@ -2214,6 +2334,30 @@ void launch_pair_products(long long ndof, int npairs, const double* phi, const i
                           hipStream_t s) {
     if (npairs == 0) return;
     hipLaunchKernelGGL(k_pair_products, dim3(256, npairs), dim3(256), 0, s, ndof, phi, pi, pj, rho);
+}
+
+// rho[q - first] = phi_i phi_j for the pairs q = first .. first + count - 1 of norb orbitals, pair q = (i, j),
+// i <= j, in row-major order: q = i norb - i (i - 1) / 2 + (j - i).
+__global__ __launch_bounds__(256) void k_pair_densities(long long ndof, int norb, int first,
+                                                        const double* __restrict__ phi, double* __restrict__ rho) {
+    const int qo = blockIdx.y;
+    int q = first + qo, i = 0;
+    while (q >= norb - i) {  // row i holds the norb - i pairs (i, i..norb-1)
+        q -= norb - i;
+        ++i;
+    }
+    const int j = i + q;
+    const double* a = phi + (long long)i * ndof;
+    const double* b = phi + (long long)j * ndof;
+    double* out = rho + (long long)qo * ndof;
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < ndof; k += (long long)gridDim.x * 256)
+        out[k] = a[k] * b[k];
+}
+void launch_pair_densities(long long ndof, int norb, int first, int count, const double* phi, double* rho,
+                           hipStream_t s) {
+    if (count <= 0 || ndof <= 0) return;
+    const long long blocks = std::min<long long>(1024, (ndof + 255) / 256);
+    hipLaunchKernelGGL(k_pair_densities, dim3((unsigned)blocks, count), dim3(256), 0, s, ndof, norb, first, phi, rho);
 }
 
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int pstride, int nblk,

@@ -1,16 +1,19 @@
-"""Full-size parity in the benchmark's launch configuration.
+"""Full-size parity in the benchmark's launch configurations, every right-hand side checked.
 
-The exchange workload of 8 orbitals on the 16^3-element, p = 4 mesh (36 pair
-densities, 512,000 nodes each) is solved the way the benchmark times it: FP32
-inner solves inside FP64 refinement, the trained initial-guess network, two
-solver lanes, captured graphs.  The oracle solves a sample of the pair
-problems exactly (fast diagonalisation), one by one.  At the parity tolerance
-(1e-12 for FP32 refinement, 1e-11 for the plain FP64 solver) the sampled
-potentials and pair energies meet the parity bars; at the
-benchmark's tolerance 1e-8 their error stays within what such a residual
-leaves (an oracle study on these pairs found potential errors up to 9.7e-8
-and pair-energy errors up to 2.4e-8 Ha, the first-order part coming from the
-Dirichlet lift).
+The exchange workloads on the 16^3-element, p = 4 mesh (512,000 nodes per
+pair density) are solved the way the benchmark times them: two solver lanes,
+captured graphs, the trained initial-guess network where the arm uses it.
+The oracle solves every pair problem exactly (fast diagonalisation) and forms
+W_k, K_ij and E_x from those potentials.
+
+Bars (the parity bars of the method): relative M-weighted L2 error of every
+potential and of every W_k <= 1e-8, every pair energy and E_x within 1e-10
+Ha.  They are met at the benchmark's operating tolerance (residual 1e-10) by
+the FP64 solver and by FP32_PC (FP64 CG preconditioned by the FP32 V-cycle),
+and at 1e-12 by FP32 iterative refinement.  At the metric's residual 1e-8
+the two CG arms have equal accuracy (their potentials differ from each other
+by far less than from the exact solve), and the error stays within what such
+a residual leaves.
 """
 import os
 
@@ -20,14 +23,13 @@ import pytest
 from oracle import exchange as ox, fdm
 from workloads import configs
 
-from _cases import (ENERGY_BAR, PARITY_RTOL, PARITY_RTOL_FP32, POT_BAR, oracle_axes, oracle_faces, oracle_grid,
+from _cases import (ENERGY_BAR, OPERATING_RTOL, PARITY_RTOL_FP32, POT_BAR, oracle_axes, oracle_faces, oracle_grid,
                     rel_l2_M)
 
 pytestmark = pytest.mark.gpu
 
 WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2510_21213_amd", "weights", "guess_16e_p4.bin")
-SAMPLE = [(0, 5), (3, 7)]      # orbital pairs (i, j): the pairs ii, ij and jj are checked
-BENCH_POT_BAR = 3e-7           # at residual 1e-8 (observed <= 9.7e-8)
+BENCH_POT_BAR = 3e-7           # at residual 1e-8 (oracle study on the exchange8 pairs: <= 9.7e-8)
 BENCH_ENERGY_BAR = 1e-7        # hartree, at residual 1e-8 (observed <= 2.4e-8)
 
 
@@ -36,34 +38,32 @@ def _t(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
+def _oracle_exchange(wl):
+    """The oracle's exchange step on every pair of the workload, at its own nodes."""
+    mesh, orb = wl.meshes[0], wl.orbitals
+    axes = oracle_axes(mesh)
+    X, Y, Z = oracle_grid(axes)
+    phi = list(orb.values(X, Y, Z))
+    faces = oracle_faces(axes, lambda a, b, c: orb.pair_potentials(a.reshape(-1), b.reshape(-1), c.reshape(-1)))
+    fp = [[faces[f][q].reshape(axes[2].N if f < 4 else axes[1].N, -1) for f in range(6)]
+          for q in range(len(orb.pairs()))]
+    v, W, K, EX = ox.exchange(axes, phi, fp, fdm.FDM(axes).solve)
+    return axes, v, W, K, EX
+
+
 @pytest.fixture(scope="module")
 def workload():
     return configs.exchange8()
 
 
 @pytest.fixture(scope="module")
-def oracle_sample(workload):
-    """Oracle potentials and pair energies of the sampled pairs (its own nodes and inputs)."""
-    mesh, orb = workload.meshes[0], workload.orbitals
-    axes = oracle_axes(mesh)
-    X, Y, Z = oracle_grid(axes)
-    phi = orb.values(X, Y, Z)
-    faces = oracle_faces(axes, lambda a, b, c: orb.pair_potentials(a.reshape(-1), b.reshape(-1), c.reshape(-1)))
-    F = fdm.FDM(axes)
-    out = {}
-    for i, j in SAMPLE:
-        # the oracle's exchange on the two orbitals i, j: pairs (i,i), (i,j), (j,j)
-        qs = [ox.pair_index(a, b, orb.norb) for a, b in ((i, i), (i, j), (j, j))]
-        fp = [[faces[f][q].reshape(axes[2].N if f < 4 else axes[1].N, -1) for f in range(6)] for q in qs]
-        v, _, K, _ = ox.exchange(axes, [phi[i], phi[j]], fp, F.solve)
-        for q, vq, Kq in zip(qs, v, K):
-            out[q] = (vq, Kq)
-    return axes, out
+def oracle_all(workload):
+    return _oracle_exchange(workload)
 
 
-def _solve(gpu_lib, workload, rtol, precision="fp32_ir", learned=True):
-    mesh, orb = workload.meshes[0], workload.orbitals
-    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=workload.n_levels, rtol=rtol,
+def _solve(gpu_lib, wl, rtol, precision, learned):
+    mesh, orb = wl.meshes[0], wl.orbitals
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=rtol,
                           precision=precision)
     assert ctx.opts.lanes == 2 and ctx.opts.use_graph == 1
     net = None
@@ -77,45 +77,84 @@ def _solve(gpu_lib, workload, rtol, precision="fp32_ir", learned=True):
     ctx.exchange(phi, g)                          # warm: the timed configuration replays graphs
     W, K, EX, st, v = ctx.exchange(phi, g, keep_potentials=True)
     npairs = orb.norb * (orb.norb + 1) // 2
-    return K.cpu().numpy(), EX, st, v.cpu().numpy().reshape(npairs, -1), net
+    out = (W.cpu().numpy().reshape(orb.norb, -1), K.cpu().numpy(), EX, st, v.cpu().numpy().reshape(npairs, -1))
+    ctx.close()
+    return out
 
 
-def _check(gpu_lib, workload, oracle_sample, rtol, pot_bar, energy_bar, precision="fp32_ir", learned=True):
-    mesh, orb = workload.meshes[0], workload.orbitals
-    K, EX, st, v, _ = _solve(gpu_lib, workload, rtol, precision, learned)
+def _errors(wl, oracle, got):
+    """Per-pair potential errors, pair-energy errors, W_k errors and the E_x error."""
+    mesh = wl.meshes[0]
+    axes, v_o, W_o, K_o, EX_o = oracle
+    W, K, EX, st, v = got
+    ev = [rel_l2_M(axes, mesh, v[q], v_o[q]) for q in range(len(v_o))]
+    eK = np.abs(K - K_o)
+    eW = [rel_l2_M(axes, mesh, W[k], W_o[k]) for k in range(len(W_o))]
+    return np.array(ev), eK, np.array(eW), abs(EX - EX_o)
+
+
+def _check_all(wl, oracle, got, rtol, pot_bar, energy_bar):
+    W, K, EX, st, v = got
+    n = wl.orbitals.norb
     assert all(s["status"] == 0 and s["rel_residual"] <= rtol for s in st)
-    assert all(s["guess_used"] in (0, 1) for s in st)
-    assert any(s["guess_used"] for s in st) if learned else not any(s["guess_used"] for s in st)
-    # E_x is the ordered-pair sum of the returned pair energies
-    n = orb.norb
     ex = sum(K[ox.pair_index(i, i, n)] for i in range(n)) + \
         2.0 * sum(K[ox.pair_index(i, j, n)] for i in range(n) for j in range(i + 1, n))
     assert abs(EX - ex) <= 1e-12 * abs(ex)
-    axes, ref = oracle_sample
-    for q, (vq, Kq) in ref.items():
-        assert rel_l2_M(axes, mesh, v[q], vq) <= pot_bar, q
-        assert abs(K[q] - Kq) <= energy_bar, q
+    ev, eK, eW, eX = _errors(wl, oracle, got)
+    print(f"max errors: potential {ev.max():.2e}, K {eK.max():.2e} Ha, W {eW.max():.2e}, E_x {eX:.2e} Ha")
+    assert ev.max() <= pot_bar, (int(ev.argmax()), ev.max())
+    assert eK.max() <= energy_bar, (int(eK.argmax()), eK.max())
+    assert eW.max() <= pot_bar, eW.max()
+    assert eX <= energy_bar, eX
+    return ev, eK
 
 
-def test_exchange8_parity_tolerance_bench_configuration(gpu_lib, workload, oracle_sample):
-    _check(gpu_lib, workload, oracle_sample, PARITY_RTOL_FP32, POT_BAR, ENERGY_BAR)
+@pytest.mark.parametrize("arm", ["fp32_pc+learned", "fp32_pc", "fp64+learned", "fp64"])
+def test_exchange8_every_pair_at_operating_tolerance(gpu_lib, workload, oracle_all, arm):
+    """Every one of the 36 pair potentials, every pair energy, every W_k and E_x of the
+    exchange8 step meet the parity bars at the benchmark's operating tolerance, in every arm
+    the benchmark compares."""
+    prec, _, learned = arm.partition("+")
+    got = _solve(gpu_lib, workload, OPERATING_RTOL, prec, learned == "learned")
+    _check_all(workload, oracle_all, got, OPERATING_RTOL, POT_BAR, ENERGY_BAR)
+    if learned:
+        assert all(s["guess_used"] in (0, 1) for s in got[3]) and any(s["guess_used"] for s in got[3])
 
 
-def test_exchange8_parity_tolerance_fp64(gpu_lib, workload, oracle_sample):
-    """The plain FP64 solver (no guess) meets both bars at the oracle's parity tolerance."""
-    _check(gpu_lib, workload, oracle_sample, PARITY_RTOL, POT_BAR, ENERGY_BAR, precision="fp64", learned=False)
+def test_exchange8_every_pair_fp32_refinement_at_parity_tolerance(gpu_lib, workload, oracle_all):
+    """FP32 inner solves inside FP64 refinement (with the trained guess) meet the bars on every
+    pair at residual 1e-12 (its refinement leaves more error in the smooth modes per unit of
+    residual than FP64 CG)."""
+    got = _solve(gpu_lib, workload, PARITY_RTOL_FP32, "fp32_ir", True)
+    _check_all(workload, oracle_all, got, PARITY_RTOL_FP32, POT_BAR, ENERGY_BAR)
 
 
-def test_exchange8_bench_tolerance_bench_configuration(gpu_lib, workload, oracle_sample):
-    _check(gpu_lib, workload, oracle_sample, workload.rtol, BENCH_POT_BAR, BENCH_ENERGY_BAR)
+def test_exchange8_equal_accuracy_at_metric_residual(gpu_lib, workload, oracle_all):
+    """At the metric's residual 1e-8 FP32_PC and plain FP64 have the same accuracy: on every pair
+    their potentials differ from each other by less than a tenth of the FP64 potential's error
+    against the exact solve, and both stay within what a 1e-8 residual leaves."""
+    mesh = workload.meshes[0]
+    axes = oracle_all[0]
+    g64 = _solve(gpu_lib, workload, workload.rtol, "fp64", False)
+    gpc = _solve(gpu_lib, workload, workload.rtol, "fp32_pc", False)
+    ev64, eK64 = _check_all(workload, oracle_all, g64, workload.rtol, BENCH_POT_BAR, BENCH_ENERGY_BAR)
+    evpc, eKpc = _check_all(workload, oracle_all, gpc, workload.rtol, BENCH_POT_BAR, BENCH_ENERGY_BAR)
+    from _cases import from_em
+    from oracle import sipdg
+    Mw = sipdg.mass(axes)
+    for q in range(len(ev64)):
+        a, b = from_em(gpc[4][q], mesh), from_em(g64[4][q], mesh)
+        d = float(np.sqrt(np.sum(Mw * (a - b) ** 2) / np.sum(Mw * b ** 2)))
+        assert d <= 0.1 * ev64[q], (q, d, ev64[q])
+    assert [s["iters"] for s in gpc[3]] == [s["iters"] for s in g64[3]]
 
 
 def test_trained_guess_saves_iterations_on_a_molecule_outside_its_training_set(gpu_lib, workload):
     """The benchmark molecule (seed 2) is not among the training molecules (seeds 10000+i):
     with the trained network every guess passes the guard and the mean iteration count at
-    the benchmark tolerance drops by at least one against the same solver without it."""
-    K_g, _, st_g, _, _ = _solve(gpu_lib, workload, workload.rtol)
-    K_0, _, st_0, _, _ = _solve(gpu_lib, workload, workload.rtol, learned=False)
+    the metric's tolerance drops by at least one against the same solver without it."""
+    _, K_g, _, st_g, _ = _solve(gpu_lib, workload, workload.rtol, "fp32_pc", True)
+    _, K_0, _, st_0, _ = _solve(gpu_lib, workload, workload.rtol, "fp32_pc", False)
     assert all(s["guess_used"] == 1 for s in st_g) and not any(s["guess_used"] for s in st_0)
     it_g = np.mean([s["iters"] for s in st_g])
     it_0 = np.mean([s["iters"] for s in st_0])
@@ -123,50 +162,80 @@ def test_trained_guess_saves_iterations_on_a_molecule_outside_its_training_set(g
     assert np.abs(K_g - K_0).max() <= BENCH_ENERGY_BAR
 
 
-def test_large_mesh_five_levels_sampled_sources(gpu_lib):
-    """The 32^3-element, p = 4 mesh with 5 levels (two mesh-coarsening levels below the degree
-    steps), 16 Gaussian-sum sources in one call (two solver lanes), FP32 refinement with the
-    guess network trained for this mesh: two sampled potentials against the oracle's exact
-    solve at the parity tolerance."""
-    from oracle import fdm
-    from _cases import gpu_sample, oracle_density_problem
-    wl = configs.scaled(32, 4, 16, seed=71, n_levels=5)
-    mesh = wl.meshes[0]
-    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=5, rtol=PARITY_RTOL_FP32, precision="fp32_ir")
-    assert ctx.opts.lanes == 2
+def test_exchange16_every_pair_at_operating_tolerance(gpu_lib):
+    """The largest exchange batch: 16 orbitals, all 136 pair densities on the 16^3, p = 4 mesh
+    in one call (two lanes of 68, FP32_PC, trained guess): every potential, pair energy, W_k and
+    E_x against the oracle's exact solves at the operating tolerance."""
+    wl = configs.exchange16()
+    got = _solve(gpu_lib, wl, OPERATING_RTOL, "fp32_pc", True)
+    assert len(got[3]) == 136
+    _check_all(wl, _oracle_exchange(wl), got, OPERATING_RTOL, POT_BAR, ENERGY_BAR)
+
+
+def test_uneven_batch_sampled_per_mesh(gpu_lib):
+    """The uneven batch: 256 Gaussian-sum densities over the 8^3, 12^3 and 16^3 meshes (p = 4)
+    interleaved in one call, FP32_PC at the operating tolerance: every residual below it, and
+    four potentials of each mesh (first, last and two between, in the caller's order) against
+    the exact solve."""
+    from _cases import oracle_density_problem
+    wl = configs.uneven()
+    ids = [int(m) for m in wl.batch.mesh_ids]
+    ctx = gpu_lib.Context([(m.E, m.p, m.lo, m.hi) for m in wl.meshes], n_levels=wl.n_levels,
+                          rtol=OPERATING_RTOL, precision="fp32_pc")
+    coords = [ctx.mesh_coords(m) for m in range(3)]
+    rho, g = [], []
+    for k, mid in enumerate(ids):
+        xyz, fxyz = coords[mid]
+        rho.append(wl.batch.densities[k].density(xyz[0], xyz[1], xyz[2]))
+        g.append(wl.batch.densities[k].potential(fxyz[0], fxyz[1], fxyz[2]))
+    v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)), mesh_ids=ids)
+    assert all(s["status"] == 0 and s["rel_residual"] <= OPERATING_RTOL for s in st)
+    v = v.cpu().numpy()
+    offs = np.cumsum([0] + [ctx.info[m]["n_dofs"] for m in ids])
+    for mid in range(3):
+        ks = [k for k in range(len(ids)) if ids[k] == mid]
+        for k in (ks[0], ks[len(ks) // 3], ks[2 * len(ks) // 3], ks[-1]):
+            mesh = wl.meshes[mid]
+            axes, _, _, b = oracle_density_problem(mesh, wl.batch.densities[k])
+            assert rel_l2_M(axes, mesh, v[offs[k]:offs[k + 1]], fdm.FDM(axes).solve(b)) <= POT_BAR, (mid, k)
+
+
+def test_large_heldout_molecule_every_pair_at_operating_tolerance(gpu_lib):
+    """The 32^3-element, p = 4 mesh with 5 levels (4,096,000 nodes per right-hand side): the 36
+    pair densities of the first held-out molecule (seed 90000, outside the network's training
+    set) solved as the benchmark's headline arm does (FP32_PC, the guess network trained for this
+    mesh, two lanes) at the operating tolerance; every potential and pair energy against the
+    oracle's exact solve.  Inputs are the closed forms evaluated with torch (on the GPU for the
+    library's nodes, on the host for the oracle's)."""
+    import torch
+    from oracle import sipdg
+    wl = configs.large_molecule(0, held_out=True)
+    mesh, orb = wl.meshes[0], wl.orbitals
+    npairs = len(orb.pairs())
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=OPERATING_RTOL,
+                          precision="fp32_pc")
     net = gpu_lib.Net(4, 32, 125, 27)
     net.load(WEIGHTS.replace("guess_16e_p4", "guess_32e_p4"))
     ctx.attach_guess(net)
-    rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
-    v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
-    assert all(s["status"] == 0 and s["rel_residual"] <= PARITY_RTOL_FP32 for s in st)
-    v = v.cpu().numpy().reshape(16, -1)
-    for k in (3, 12):      # one source of each lane
-        axes, _, _, b = oracle_density_problem(mesh, wl.batch.densities[k])
-        assert rel_l2_M(axes, mesh, v[k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
-
-
-def test_exchange16_largest_batch_bench_tolerance(gpu_lib):
-    """The largest batch of the workloads: 16 orbitals, 136 pair densities on the 16^3, p = 4
-    mesh in one call (two lanes of 68, FP32 refinement, trained guess) at the benchmark
-    tolerance: sampled pairs against the oracle's exact solve, E_x from the returned energies."""
-    wl = configs.exchange16()
-    mesh, orb = wl.meshes[0], wl.orbitals
-    K, EX, st, v, _ = _solve(gpu_lib, wl, wl.rtol)
-    n = orb.norb
-    assert len(st) == n * (n + 1) // 2 == 136
-    assert all(s["status"] == 0 and s["rel_residual"] <= wl.rtol for s in st)
-    ex = sum(K[ox.pair_index(i, i, n)] for i in range(n)) + \
-        2.0 * sum(K[ox.pair_index(i, j, n)] for i in range(n) for j in range(i + 1, n))
-    assert abs(EX - ex) <= 1e-12 * abs(ex)
+    xyz, fxyz = ctx.mesh_coords(0)
+    phi = orb.values_torch(*xyz, device="cuda").reshape(-1).contiguous()
+    g = orb.pair_potentials_torch(*fxyz, device="cuda").reshape(-1).contiguous()
+    _, K, _, st, v = ctx.exchange(phi, g, keep_potentials=True)
+    assert all(s["status"] == 0 and s["rel_residual"] <= OPERATING_RTOL for s in st)
+    assert np.mean([s["guess_used"] for s in st]) > 0.5
+    K = K.cpu().numpy()
+    v = v.cpu().numpy().reshape(npairs, -1)
+    del phi, g
+    torch.cuda.empty_cache()
     axes = oracle_axes(mesh)
     X, Y, Z = oracle_grid(axes)
-    phi = orb.values(X, Y, Z)
-    faces = oracle_faces(axes, lambda a, b, c: orb.pair_potentials(a.reshape(-1), b.reshape(-1), c.reshape(-1)))
-    i, j = 2, 13
-    qs = [ox.pair_index(a, b, n) for a, b in ((i, i), (i, j), (j, j))]
-    fp = [[faces[f][q].reshape(axes[2].N if f < 4 else axes[1].N, -1) for f in range(6)] for q in qs]
-    v_o, _, K_o, _ = ox.exchange(axes, [phi[i], phi[j]], fp, fdm.FDM(axes).solve)
-    for q, vq, Kq in zip(qs, v_o, K_o):
-        assert rel_l2_M(axes, mesh, v[q], vq) <= BENCH_POT_BAR, q
-        assert abs(K[q] - Kq) <= BENCH_ENERGY_BAR, q
+    phi_o = orb.values_torch(X, Y, Z).numpy().reshape((orb.norb,) + X.shape)
+    faces = oracle_faces(axes, lambda a, b, c: orb.pair_potentials_torch(a, b, c).numpy())
+    F = fdm.FDM(axes)
+    Mw = sipdg.mass(axes)
+    for q, (i, j) in enumerate(orb.pairs()):
+        rho = phi_o[i] * phi_o[j]
+        ref = F.solve(sipdg.rhs(axes, rho, [faces[f][q].reshape(axes[2].N if f < 4 else axes[1].N, -1)
+                                             for f in range(6)]))
+        assert rel_l2_M(axes, mesh, v[q], ref) <= POT_BAR, q
+        assert abs(K[q] - float(np.sum(Mw * rho * ref))) <= ENERGY_BAR, q

@@ -244,11 +244,11 @@ def test_uneven_batch_three_meshes_matches_oracle_and_per_mesh_solves(gpu_lib):
 def test_two_solver_lanes_match_one_lane_bitwise(gpu_lib):
     """A batch of 20 right-hand sides of one mesh is split over two concurrent solver lanes
     (default) or solved as one group (lanes=1): the potentials and iteration counts agree
-    bit for bit, in both precisions."""
+    bit for bit, in every precision."""
     wl = configs.scaled(4, 4, 20, seed=41)
     mesh = wl.meshes[0]
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
-    for prec in ("fp64", "fp32_ir"):
+    for prec in ("fp64", "fp32_ir", "fp32_pc"):
         out = []
         for lanes in (1, 2):
             ctx = gpu_lib.Context([m], precision=prec, lanes=lanes)
@@ -343,11 +343,11 @@ def test_full_solves_agree_on_every_compiled_tile(gpu_lib):
 
 def test_non_finite_inputs_are_rejected(gpu_lib):
     """A NaN or Inf in a source, its Dirichlet data or a caller's initial guess is reported as
-    an argument error, in both precisions and over two solver lanes (20 right-hand sides); the
+    an argument error, in every precision and over two solver lanes (20 right-hand sides); the
     context solves normally afterwards."""
     wl = configs.scaled(4, 2, 20, seed=43)
     mesh = wl.meshes[0]
-    for prec in ("fp64", "fp32_ir"):
+    for prec in ("fp64", "fp32_ir", "fp32_pc"):
         ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], precision=prec)
         assert ctx.opts.lanes == 2
         rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
@@ -449,7 +449,7 @@ def test_graph_replay_matches_eager_launches_bitwise(gpu_lib):
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
     outs = []
     for use_graph in (0, 1):
-        for prec in ("fp64", "fp32_ir"):
+        for prec in ("fp64", "fp32_ir", "fp32_pc"):
             ctx = gpu_lib.Context([m], rtol=1e-10, use_graph=use_graph, precision=prec, check_every=2)
             rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
             rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
@@ -460,6 +460,99 @@ def test_graph_replay_matches_eager_launches_bitwise(gpu_lib):
             assert torch.equal(v1, v2)
             assert [s["iters"] for s in st1] == [s["iters"] for s in st2]
             outs.append((prec, _n(v1), [s["iters"] for s in st1]))
-    for prec in ("fp64", "fp32_ir"):
+    for prec in ("fp64", "fp32_ir", "fp32_pc"):
         a, b = [o for o in outs if o[0] == prec]
         assert np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def _box_density(mesh, seed):
+    """Two or three normalised Gaussians inside the central half of a mesh's box."""
+    rng = np.random.default_rng(seed)
+    lo, hi = np.array(mesh.lo), np.array(mesh.hi)
+    c, w = 0.5 * (lo + hi), 0.25 * (hi - lo)
+    K = int(rng.integers(2, 4))
+    h = float(np.min((hi - lo) / np.array(mesh.E)))
+    alpha = rng.uniform(0.5, 1.5, K) / h ** 2
+    return gaussians.GaussianDensity(rng.uniform(0.5, 1.5, K), alpha, c + rng.uniform(-1, 1, (K, 3)) * w)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"E{c[0]}p{c[1]}" for c in CASES])
+def test_fp32_preconditioned_fp64_pcg_matches_exact(gpu_lib, case):
+    """FP32_PC (FP64 PCG, FP32 V-cycle) on every operator case, the degrees without a mixed
+    operator kernel included (their FP32 direction is widened first): the potential meets the
+    bar against the exact solve at the parity tolerance, with the iteration count of the FP64
+    solver (+-1) and a potential within FP64 CG's own error of the FP64 solver's."""
+    mesh = _mesh(case)
+    dens = [_box_density(mesh, 60 + k) for k in range(2)]
+    out = {}
+    for prec in ("fp64", "fp32_pc"):
+        ctx = _ctx(gpu_lib, [case], rtol=PARITY_RTOL, precision=prec)
+        rho, g = zip(*[gpu_sample(ctx, 0, d) for d in dens])
+        v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
+        assert all(s_["status"] == 0 and s_["rel_residual"] <= PARITY_RTOL for s_ in st), prec
+        out[prec] = (_n(v).reshape(len(dens), -1), [s_["iters"] for s_ in st])
+    for k, d in enumerate(dens):
+        axes, _, _, b = oracle_density_problem(mesh, d)
+        ref = fdm.FDM(axes).solve(b)
+        assert rel_l2_M(axes, mesh, out["fp32_pc"][0][k], ref) <= POT_BAR, k
+        assert abs(out["fp32_pc"][1][k] - out["fp64"][1][k]) <= 1, k
+
+
+def test_single_level_hierarchy(gpu_lib):
+    """A degree-1 mesh of at most 16 nodes per axis has a single multigrid level with default
+    options: PCG is preconditioned by the exact solve alone and converges at once, in every
+    precision, to the exact solution."""
+    mesh = configs.Mesh((8, 8, 8), 1, (-4.0,) * 3, (4.0,) * 3)
+    dens = _box_density(mesh, 71)
+    axes, _, _, b = oracle_density_problem(mesh, dens)
+    ref = fdm.FDM(axes).solve(b)
+    for prec in ("fp64", "fp32_pc", "fp32_ir"):
+        ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=PARITY_RTOL, precision=prec)
+        assert ctx.info[0]["n_levels"] == 1
+        rho, g = gpu_sample(ctx, 0, dens)
+        v, st = ctx.solve_batch(_t(rho), _t(g))
+        assert st[0]["status"] == 0 and st[0]["iters"] <= (2 if prec != "fp32_ir" else 8), (prec, st)
+        assert rel_l2_M(axes, mesh, _n(v), ref) <= POT_BAR, prec
+
+
+def test_call_status_without_statistics(gpu_lib):
+    """A caller that passes no statistics array still learns that a right-hand side missed its
+    tolerance: the call returns DG_WARN_NOT_CONVERGED (one PCG iteration cannot reach 1e-12)."""
+    import ctypes
+    wl = configs.scaled(4, 4, 2, seed=73)
+    mesh = wl.meshes[0]
+    for prec in ("fp64", "fp32_pc", "fp32_ir"):
+        ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=1e-12, max_iter=1, max_outer=1,
+                              precision=prec)
+        rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+        rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+        v = torch_empty_like(rho)
+        ids = (ctypes.c_int * 2)(0, 0)
+        code = gpu_lib.lib.dg_poisson_solve_batch(ctx._h, 2, ids, ctypes.c_void_p(rho.data_ptr()),
+                                                  ctypes.c_void_p(g.data_ptr()), None,
+                                                  ctypes.c_void_p(v.data_ptr()), None, gpu_lib._stream())
+        assert code == gpu_lib.DG_WARN_NOT_CONVERGED, (prec, code)
+
+
+def torch_empty_like(t):
+    import torch
+    return torch.empty_like(t)
+
+
+def test_pair_densities_every_pair_and_subranges(gpu_lib):
+    """dg_pair_densities forms phi_i phi_j bitwise (one FP64 product per node) in row-major pair
+    order, for the whole triangle and for sub-ranges that start and end inside a row; bad
+    ranges are argument errors."""
+    rng = np.random.default_rng(81)
+    norb, nd = 7, 3001
+    phi = rng.standard_normal((norb, nd))
+    pairs = [(i, j) for i in range(norb) for j in range(i, norb)]
+    ref = np.stack([phi[i] * phi[j] for i, j in pairs])
+    tphi = _t(phi.reshape(-1))
+    assert np.array_equal(_n(gpu_lib.pair_densities(tphi, norb)).reshape(len(pairs), nd), ref)
+    for first, count in ((0, 1), (5, 9), (13, 15), (27, 1)):
+        got = _n(gpu_lib.pair_densities(tphi, norb, first, count)).reshape(count, nd)
+        assert np.array_equal(got, ref[first:first + count]), (first, count)
+    for first, count in ((-1, 2), (20, 9), (0, 29)):
+        with pytest.raises(gpu_lib.DgError):
+            gpu_lib.pair_densities(tphi, norb, first, count)

@@ -99,6 +99,22 @@ class Primitives:
                 * boys0(pp * qq / (pp + qq) * d2))
 
 
+def _t(a, device):
+    import torch
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64)
+    return torch.as_tensor(np.asarray(a, dtype=np.float64), device=device)
+
+
+def erf_over_r_torch(c_sqrt, d):
+    """erf(c d)/d with its limit 2c/sqrt(pi) at d = 0 (torch tensors)."""
+    import torch
+    cd = c_sqrt * d
+    lim = 2.0 * c_sqrt / np.sqrt(np.pi) * (1.0 - cd * cd / 3.0)
+    val = torch.erf(cd) / torch.where(d > 0, d, torch.ones_like(d))
+    return torch.where(cd.abs() < 1e-6, lim, val)
+
+
 def lowdin(C, S):
     """C <- C (C^T S C)^{-1/2}: orbitals orthonormal in the analytic overlap S."""
     G = C.T @ S @ C
@@ -133,6 +149,34 @@ class Orbitals:
             c = np.where(ia == ib, 0.5 * c, c)
             rows.append(c)
         return np.array(rows)
+
+    def values_torch(self, X, Y, Z, device="cpu"):
+        """The orbitals at the points with torch (float64, on ``device``): [norb, npts]."""
+        import torch
+        X, Y, Z = (_t(v, device).reshape(-1) for v in (X, Y, Z))
+        pr = self.prims
+        chi = torch.empty((len(pr), X.numel()), dtype=torch.float64, device=X.device)
+        for a in range(len(pr)):
+            A = pr.centres[a]
+            chi[a] = pr.norm[a] * torch.exp(-pr.alpha[a] * ((X - A[0]) ** 2 + (Y - A[1]) ** 2 + (Z - A[2]) ** 2))
+        return _t(self.C.T, device) @ chi
+
+    def pair_potentials_torch(self, X, Y, Z, device="cpu", chunk=512):
+        """pair_potentials with torch (float64, on ``device``): [npairs, npts], summed over
+        chunks of primitive pairs."""
+        import torch
+        X, Y, Z = (_t(v, device).reshape(-1) for v in (X, Y, Z))
+        ia, ib, K, p, P = self.prims.product_terms()
+        coef = _t(self._pair_coeffs(), device)
+        out = torch.zeros((coef.shape[0], X.numel()), dtype=torch.float64, device=X.device)
+        for t0 in range(0, len(ia), chunk):
+            sl = slice(t0, min(len(ia), t0 + chunk))
+            Pc = _t(P[sl], device)
+            pc = _t(p[sl], device)[:, None]
+            d = torch.sqrt((X[None] - Pc[:, 0:1]) ** 2 + (Y[None] - Pc[:, 1:2]) ** 2 + (Z[None] - Pc[:, 2:3]) ** 2)
+            V = _t(K[sl], device)[:, None] * (np.pi / pc) ** 1.5 * erf_over_r_torch(torch.sqrt(pc), d)
+            out += coef[:, sl] @ V
+        return out
 
     def pair_potentials(self, X, Y, Z):
         """Full-space potential of every pair density phi_i phi_j (i <= j) at the points."""
