@@ -210,6 +210,23 @@ dg_status dg_pair_densities(long long n_dofs, int norb, int first_pair, int npai
  * DG_ERR_ARG for nsrc < 0 or null pointers with nsrc > 0. */
 dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g, hipStream_t stream);
 
+/* dg_boundary_data for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same Dirichlet data by quadrature, same arguments, layout and errors,
+ * with no hipMalloc, hipFree or other allocation inside the call.  Its work
+ * space (the packed source records and split partial sums) is a fixed array
+ * of 64 MiB per GPU, held from the first dg_poisson_setup on that GPU until
+ * the process ends; the node tables come from the context (built at set-up).
+ * Sources go in tiles narrow enough for the records and partial sums to fit,
+ * so a mesh whose n_dofs exceeds 8,388,608 values (one source's records) is
+ * rejected with DG_ERR_ARG, and large batches take more passes than
+ * dg_boundary_data.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, or two host threads) race and must be
+ * ordered by the caller.  DG_ERR_ARG also when the context's device is not
+ * the current one. */
+dg_status dg_boundary_data_noalloc(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g,
+                                   hipStream_t stream);
+
 /* Work-group tiles of the operator kernels (host only; no GPU needed).
  * The operator steps of the path run as a slab kernel on nodes-per-edge n = 2,
  * 3 and 5 (degrees 1, 2, 4): a work-group owns tx x ty elements of the x-y

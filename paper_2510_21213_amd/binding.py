@@ -65,6 +65,7 @@ def _load():
         "dg_rhs_assemble": (I, [P, I, I, P, P, P, P]),
         "dg_boundary_data": (I, [P, I, I, P, P, P]),
         "dg_pair_densities": (I, [LL, I, I, I, P, P, P]),
+        "dg_boundary_data_noalloc": (I, [P, I, I, P, P, P]),
         "dg_tile_set": (I, [I, I, I, I, I, I]),
         "dg_tile_get": (I, [I, I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "dg_vcycle_apply": (I, [P, I, I, I, P, P, P]),
@@ -314,6 +315,16 @@ class Context:
         nsrc = f.numel() // nd
         g = torch.empty(nsrc * nf, dtype=torch.float64, device=f.device)
         _check(lib.dg_boundary_data(self._h, mesh_id, nsrc, _ptr(f), _ptr(g), _stream()), "boundary_data")
+        return g
+
+    def boundary_data_noalloc(self, f, g, mesh_id=0):
+        """dg_boundary_data_noalloc into the caller's g (packed face vectors): nothing is
+        allocated on either side of the call."""
+        nd, nf = self.info[mesh_id]["n_dofs"], self.info[mesh_id]["n_face"]
+        if f.numel() % nd or g.numel() != (f.numel() // nd) * nf:
+            raise ValueError("f / g sizes do not match the mesh")
+        _check(lib.dg_boundary_data_noalloc(self._h, mesh_id, f.numel() // nd, _ptr(f), _ptr(g), _stream()),
+               "boundary_data_noalloc")
         return g
 
     def vcycle(self, r, mesh_id=0, level=0):

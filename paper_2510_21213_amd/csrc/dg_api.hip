@@ -142,7 +142,7 @@ struct dg_ctx {
         bool owns_tables = true;
         double *grho = nullptr, *gface = nullptr, *gx0 = nullptr, *gv = nullptr;
         int cap_g = 0;
-        double* qnodes = nullptr;  // node coordinates per axis (quadrature Dirichlet data), built on first use
+        double* qnodes = nullptr;  // node coordinates per axis (quadrature Dirichlet data), built at set-up
     };
     std::vector<Mesh> meshes;
     std::vector<Mesh> twins;       // second solver lane of each mesh (empty with one lane)
@@ -570,22 +570,25 @@ void ensure_len(double*& p, long long& cap, long long n) {
 
 // Dirichlet data by quadrature (Sec. 6.3) of nsrc sources of mesh M into g (device
 // [nsrc][n_face]): the sources are the fields f, or with f null the pair products of phi.
+// Node coordinates per axis of the finest level (x, then y, then z) in device memory: the
+// quadrature's grid.  Built when a mesh is set up.
+void build_qnodes(dg_ctx* ctx, Mesh& M) {
+    std::vector<double> all;
+    for (int d = 0; d < 3; ++d) {
+        dg::AxisDev<double> ax;
+        std::vector<double> nodes;
+        dg::build_axis(M.mesh.ne[d], M.mesh.p, M.mesh.lo[d], M.mesh.hi[d], ctx->opts.penalty_eps, ax, nullptr,
+                       &nodes);
+        all.insert(all.end(), nodes.begin(), nodes.end());
+    }
+    double* d = dalloc<double>((long long)all.size());
+    HIPCHK(hipMemcpy(d, all.data(), sizeof(double) * all.size(), hipMemcpyHostToDevice));
+    M.qnodes = d;
+}
+
 void quad_data(dg_ctx* ctx, Mesh& M, int nsrc, const double* f, const double* phi, const int* pi, const int* pj,
                double* g, hipStream_t s) {
     const LevelHost& L0 = M.lv[0];
-    if (!M.qnodes) {
-        std::vector<double> all;
-        for (int d = 0; d < 3; ++d) {
-            dg::AxisDev<double> ax;
-            std::vector<double> nodes;
-            dg::build_axis(M.mesh.ne[d], M.mesh.p, M.mesh.lo[d], M.mesh.hi[d], ctx->opts.penalty_eps, ax, nullptr,
-                           &nodes);
-            all.insert(all.end(), nodes.begin(), nodes.end());
-        }
-        double* d = dalloc<double>((long long)all.size());
-        HIPCHK(hipMemcpy(d, all.data(), sizeof(double) * all.size(), hipMemcpyHostToDevice));
-        M.qnodes = d;
-    }
     const dg::QuadPlan P = dg::quad_plan(L0, nsrc);
     if (P.nface != M.nface) throw std::logic_error("quadrature plan: face count mismatch");
     ensure_len(ctx->qrec, ctx->qrec_cap, P.rec_len);
@@ -1115,8 +1118,11 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
         HIPCHK(hipEventCreateWithFlags(&ctx->ev_ready, hipEventDisableTiming));
         hipStream_t s = ctx->stream;
         ctx->meshes.resize(n_meshes);
+        // the fixed work space of the entry point that allocates nothing: this device's copy
+        HIPCHK(dg::quad_scratch_init(ctx->device));
         for (int i = 0; i < n_meshes; ++i) {
             setup_mesh(ctx.get(), meshes[i], ctx->meshes[i], s);
+            build_qnodes(ctx.get(), ctx->meshes[i]);
             HIPCHK(hipStreamCreateWithFlags(&ctx->meshes[i].stream, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&ctx->meshes[i].ev_done, hipEventDisableTiming));
         }
@@ -1529,6 +1535,29 @@ dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, 
         if (nsrc < 0 || (nsrc > 0 && (!f || !g))) throw ArgError("bad arguments");
         if (nsrc == 0) return;
         quad_data(ctx, ctx->meshes[mesh_id], nsrc, f, nullptr, nullptr, nullptr, g, stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_boundary_data_noalloc(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g,
+                                   hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        if (nsrc < 0 || (nsrc > 0 && (!f || !g))) throw ArgError("bad arguments");
+        if (nsrc == 0) return;
+        int dev = -1;
+        HIPCHK(hipGetDevice(&dev));
+        if (dev != ctx->device) throw ArgError("the context's device is not the current device");
+        long long cap = 0;
+        double* scr = dg::quad_scratch(dev, &cap);
+        if (!scr) throw HipError("work space of this device not set up");
+        const Mesh& M = ctx->meshes[mesh_id];
+        const LevelHost& L0 = M.lv[0];
+        const dg::QuadPlan P = dg::quad_plan_bounded(L0, nsrc, cap);
+        if (P.R == 0) throw ArgError("mesh too large for the fixed work space (records of one source exceed it)");
+        // records first, then the split partial sums (every entry read is written first in the call)
+        double* part = P.part_len > 0 ? scr + P.rec_len : nullptr;
+        dg::launch_quad_data(L0, L0.dev64, M.qnodes, P, nsrc, f, nullptr, nullptr, nullptr, scr, part, g, stream);
         HIPCHK(hipGetLastError());
     });
 }

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <stdexcept>
 
 #include "dg_internal.h"
@@ -235,6 +236,37 @@ void launch_quad_r(int ntb, int S, const double* nodes, int NX, int NY, int NZ, 
 
 }  // namespace
 
+// Work space of the entry point that allocates nothing (dg_boundary_data_noalloc): the packed
+// records and the split partial sums live in this array, one copy per GPU, kept until the
+// process ends.  Host code never uses its name as an address: quad_scratch_init looks up each
+// device's copy once and quad_scratch returns it.  Every call on a GPU shares that GPU's copy.
+constexpr long long QUAD_SCRATCH_DOUBLES = 8LL << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[QUAD_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int QUAD_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[QUAD_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t quad_scratch_init(int device) {
+    if (device < 0 || device >= QUAD_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = static_cast<double*>(p);
+    return hipSuccess;
+}
+
+double* quad_scratch(int device, long long* capacity) {
+    if (capacity) *capacity = QUAD_SCRATCH_DOUBLES;
+    if (device < 0 || device >= QUAD_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[device];
+}
+
 QuadPlan quad_plan(const LevelHost& L, int nsrc) {
     QuadPlan P{};
     const long long NX = (long long)L.E[0] * L.n, NY = (long long)L.E[1] * L.n, NZ = (long long)L.E[2] * L.n;
@@ -250,6 +282,42 @@ QuadPlan quad_plan(const LevelHost& L, int nsrc) {
     P.rec_len = L.ndof * P.R;
     P.part_len = P.S > 1 ? (long long)P.S * P.R * P.nface : 0;
     return P;
+}
+
+// A plan whose records and partial sums fit in `capacity` doubles: the widest source tile that
+// still leaves room for enough split parts to give the launch about a thousand work-groups (or
+// the most it can), narrower tiles meaning more passes over the grid.  R = 0: the mesh does not
+// fit even with one source per pass and no split.
+QuadPlan quad_plan_bounded(const LevelHost& L, int nsrc, long long capacity) {
+    const QuadPlan full = quad_plan(L, nsrc);
+    if (nsrc <= 0 || full.rec_len + full.part_len <= capacity) return full;
+    static const int tiles[] = {48, 44, 40, 36, 32, 28, 24, 20, 16, 12, 8, 4, 3, 2, 1};
+    const long long NZ = (long long)L.E[2] * L.n;
+    const long long ntb = (full.nface + QUAD_BLOCK * QUAD_NB - 1) / (QUAD_BLOCK * QUAD_NB);
+    QuadPlan best{};
+    long long best_wg = -1;
+    for (int R : tiles) {
+        if (R > full.R) continue;
+        const long long rec = L.ndof * R;
+        if (rec > capacity) continue;
+        const long long smax = std::min<long long>(full.S, (capacity - rec) / ((long long)R * full.nface));
+        const int S0 = (int)std::max(1LL, std::min(NZ, smax));
+        QuadPlan P = full;
+        P.R = R;
+        P.ntile = (nsrc + R - 1) / R;
+        P.zper = (int)((NZ + S0 - 1) / S0);
+        P.S = (int)((NZ + P.zper - 1) / P.zper);
+        P.rec_len = rec;
+        P.part_len = P.S > 1 ? (long long)P.S * R * P.nface : 0;
+        if (P.rec_len + P.part_len > capacity) continue;
+        const long long wg = ntb * P.S;
+        if (wg > best_wg) {
+            best = P;
+            best_wg = wg;
+        }
+        if (wg >= std::min<long long>(1024, ntb * full.S)) return P;
+    }
+    return best;  // R = 0 when nothing fits
 }
 
 void launch_quad_data(const LevelHost& L, const LevelDev<double>* dev, const double* nodes, const QuadPlan& P,

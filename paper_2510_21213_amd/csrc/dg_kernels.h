@@ -165,6 +165,13 @@ struct QuadPlan {
     long long nface, rec_len, part_len;
 };
 QuadPlan quad_plan(const LevelHost& L, int nsrc);
+// The same with rec_len + part_len <= capacity doubles (R = 0 if the mesh cannot fit).
+QuadPlan quad_plan_bounded(const LevelHost& L, int nsrc, long long capacity);
+// The fixed work space of dg_boundary_data_noalloc (a file-scope device array): look up this
+// device's copy once, with the device current (quad_scratch_init), then fetch it and its size
+// in doubles (quad_scratch; null before the lookup).
+hipError_t quad_scratch_init(int device);
+double* quad_scratch(int device, long long* capacity);
 // nodes: the node coordinates per axis, x[NX] then y[NY] then z[NZ] (device).
 void launch_quad_data(const LevelHost& L, const LevelDev<double>* dev, const double* nodes, const QuadPlan& P,
                       int nsrc, const double* f, const double* phi, const int* pi, const int* pj, double* rec,
