@@ -121,6 +121,12 @@ typedef struct {
                             one half overlap the bandwidth-bound phases of the other */
     int cheb_degree_h;   /* smoothing steps on the degree-1 levels below the finest (the
                             mesh-coarsening part of the hierarchy); 0 = cheb_degree */
+    int fused;           /* 1: in FP64 precision, a mesh whose every level has degree at most 4,
+                            at most 8,192 nodes and at most 64 nodes per axis is solved by a
+                            single launch that runs the whole PCG, one work-group per
+                            right-hand side (no host checks between iterations; level fields
+                            held in LDS when they fit); 0 (default): the level-by-level kernels,
+                            which are faster on gfx950 for every workload measured */
 } dg_opts;
 
 typedef struct {
@@ -141,7 +147,7 @@ typedef struct dg_ctx dg_ctx;
 /* Fill *opts with the defaults: automatic levels, degree 6, ratio 60,
  * safety 1.1, 30 Lanczos steps, eps 1/8, rtol 1e-8, 500 iterations, FP64,
  * inner_rtol 1e-4, max_outer 8, check_every 2, use_graph 1, lanes 2,
- * cheb_degree_h 10. */
+ * cheb_degree_h 10, fused 0. */
 void dg_opts_default(dg_opts* opts);
 
 /* Build the level hierarchy, operator tables, coarsest-grid eigendata and

@@ -32,7 +32,7 @@ class DgOpts(ctypes.Structure):
                 ("penalty_eps", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("lanes", ctypes.c_int),
-                ("cheb_degree_h", ctypes.c_int)]
+                ("cheb_degree_h", ctypes.c_int), ("fused", ctypes.c_int)]
 
 
 class DgRhsStats(ctypes.Structure):

@@ -143,6 +143,12 @@ struct dg_ctx {
         double *grho = nullptr, *gface = nullptr, *gx0 = nullptr, *gv = nullptr;
         int cap_g = 0;
         double* qnodes = nullptr;  // node coordinates per axis (quadrature Dirichlet data), built at set-up
+        // fused solve of a small mesh (null when the mesh is not small enough): device tables
+        // (shared by the lanes), their transfer matrices, and this lane's work space
+        dg::FusedMeshDev* dfused = nullptr;
+        std::vector<double*> fusedP;
+        double* fws = nullptr;
+        long long fws_cap = 0, fws_per = 0;  // work space held, and needed per right-hand side
     };
     std::vector<Mesh> meshes;
     std::vector<Mesh> twins;       // second solver lane of each mesh (empty with one lane)
@@ -596,6 +602,114 @@ void quad_data(dg_ctx* ctx, Mesh& M, int nsrc, const double* f, const double* ph
     dg::launch_quad_data(L0, L0.dev64, M.qnodes, P, nsrc, f, phi, pi, pj, ctx->qrec, ctx->qpart, g, s);
 }
 
+// Tables of the fused small-mesh solve (every level at most FUSED_MAX_DOF nodes): levels, smoother
+// coefficients, dense 1D transfers with their index ranges, work-space offsets.  Leaves M.dfused
+// null when the mesh is not small enough.
+void build_fused(Mesh& M) {
+    const int nl = (int)M.lv.size();
+    if (nl > dg::FUSED_MAX_LEVELS) return;
+    for (int l = 0; l < nl; ++l) {
+        const LevelHost& L = M.lv[l];
+        if (L.ndof > dg::FUSED_MAX_DOF || L.n > 5) return;  // the fused operator has kernels for degrees 1..4
+        for (int d = 0; d < 3; ++d)
+            if (L.E[d] * L.n > dg::FUSED_MAX_AXIS) return;
+        if (l + 1 < nl && (int)M.cheb[l].cp.size() + 1 > dg::FUSED_MAX_DEG) return;
+    }
+    dg::FusedMeshDev H;
+    std::memset(&H, 0, sizeof(H));
+    H.nl = nl;
+    long long off = 0;
+    H.off_x = off; off += M.lv[0].ndof;
+    H.off_r = off; off += M.lv[0].ndof;
+    H.off_p = off; off += M.lv[0].ndof;
+    for (int l = 0; l < nl; ++l) {
+        const LevelHost& L = M.lv[l];
+        dg::FusedLevel& F = H.lv[l];
+        F.L = L.dev64;
+        F.dinv = L.dinv64;
+        for (int d = 0; d < 3; ++d) {
+            F.E[d] = L.E[d];
+            F.N[d] = L.E[d] * L.n;
+        }
+        F.n = L.n;
+        F.ndof = (int)L.ndof;
+        F.off_f = off; off += L.ndof;
+        F.off_za = off; off += L.ndof;
+        F.off_zb = off; off += L.ndof;
+        if (l + 1 == nl) continue;
+        const ChebCoef& C = M.cheb[l];
+        F.deg = (int)C.cp.size() + 1;
+        F.c0 = C.c0;
+        for (size_t k = 0; k < C.cp.size(); ++k) {
+            F.cp[k] = C.cp[k];
+            F.cr[k] = C.cr[k];
+        }
+        // 1D transfers to the next coarser level: degree step (same elements) or mesh step (parent element)
+        const LevelHost& Lc = M.lv[l + 1];
+        std::vector<double> xf, wf, Df, xc, wc, Dc;
+        dg::gll(L.p, xf, wf, Df);
+        dg::gll(Lc.p, xc, wc, Dc);
+        for (int d = 0; d < 3; ++d) {
+            const int nf = L.n, nc = Lc.n, Nf = F.N[d], Nc = Lc.E[d] * Lc.n;
+            const bool mesh_step = L.E[d] != Lc.E[d];
+            std::vector<double> P((size_t)Nf * Nc, 0.0);
+            for (int ef = 0; ef < L.E[d]; ++ef) {
+                const int ec = mesh_step ? ef / 2 : ef;
+                std::vector<double> pts(nf), Lg;
+                for (int i = 0; i < nf; ++i) pts[i] = mesh_step ? (xf[i] + 2.0 * (ef % 2) - 1.0) / 2.0 : xf[i];
+                dg::lagrange_eval(xc, pts, Lg);
+                for (int i = 0; i < nf; ++i)
+                    for (int a = 0; a < nc; ++a) P[(size_t)(ef * nf + i) * Nc + ec * nc + a] = Lg[i * nc + a];
+                for (int i = 0; i < nf; ++i) {  // fine node <- coarse nodes of its (parent) element
+                    F.plo[d][ef * nf + i] = (short)(ec * nc);
+                    F.pcnt[d][ef * nf + i] = (short)nc;
+                }
+            }
+            for (int ec = 0; ec < Lc.E[d]; ++ec)
+                for (int a = 0; a < nc; ++a) {  // coarse node <- fine nodes of its element (or its two children)
+                    F.rlo[d][ec * nc + a] = (short)((mesh_step ? 2 * ec : ec) * nf);
+                    F.rcnt[d][ec * nc + a] = (short)((mesh_step ? 2 : 1) * nf);
+                }
+            double* dP = dalloc<double>((long long)P.size());
+            HIPCHK(hipMemcpy(dP, P.data(), sizeof(double) * P.size(), hipMemcpyHostToDevice));
+            M.fusedP.push_back(dP);
+            F.P[d] = dP;
+        }
+    }
+    // resident mode when every level field fits in LDS with the operator output, the coarsest
+    // solve's scratch (from the output's offset on) and the reduction slots:
+    // [f, za, zb of every level][output, max(level-0 size, coarse scratch)][reduction]
+    {
+        int lo = 0;
+        for (int l = 0; l < nl; ++l) {
+            dg::FusedLevel& F = H.lv[l];
+            F.lf = lo; lo += F.ndof;
+            F.lza = lo; lo += F.ndof;
+            F.lzb = lo; lo += F.ndof;
+        }
+        H.lsy = lo;
+        lo += std::max(H.lv[0].ndof, dg::FUSED_COARSE_SCRATCH);
+        H.resident = lo + dg::FUSED_THREADS / 64 <= dg::FUSED_LDS_DOUBLES ? 1 : 0;
+    }
+    H.coarse = M.dcoarse;
+    H.ws_per_rhs = off;
+    M.fws_per = off;
+    M.dfused = dalloc<dg::FusedMeshDev>(1);
+    HIPCHK(hipMemcpy(M.dfused, &H, sizeof(H), hipMemcpyHostToDevice));
+}
+
+bool use_fused(const dg_ctx* ctx, const Mesh& M) {
+    return M.dfused && ctx->opts.fused && ctx->opts.precision == DG_PREC_FP64;
+}
+
+void ensure_fused_ws(Mesh& M, int nrhs) {
+    const long long need = M.fws_per * nrhs;
+    if (M.fws_cap >= need) return;
+    dfree(M.fws);
+    M.fws = dalloc<double>(need);
+    M.fws_cap = need;
+}
+
 // Learned guess for nrhs sources rho of mesh M: writes ctx->g_x0 (the solve's guard
 // later drops a guess whose residual is not below ||b||).
 void learned_guess(dg_ctx* ctx, Mesh& M, int nrhs, const double* rho, hipStream_t s);
@@ -611,7 +725,20 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
     const auto& o = ctx->opts;
     ensure_state(M, nrhs);
     std::vector<int> iters(nrhs, 0), outer(nrhs, 0), kept(nrhs, x0 ? 1 : 0);
-    if (o.precision == DG_PREC_FP64 || o.precision == DG_PREC_FP32_PC) {
+    if (use_fused(ctx, M)) {
+        // small mesh: the whole PCG in one launch, one work-group per right-hand side
+        ensure_fused_ws(M, nrhs);
+        init_state(M, M.st, nrhs, o.rtol, o.max_iter, s);
+        if (x0) HIPCHK(hipMemcpyAsync(v, x0, sizeof(double) * n0 * nrhs, hipMemcpyDeviceToDevice, s));
+        dg::launch_fused_pcg(M.dfused, nrhs, b, v, M.st, M.fws, x0 != nullptr, guard, s);
+        HIPCHK(hipGetLastError());
+        read_state(M, M.st, nrhs, s);
+        for (int i = 0; i < nrhs; ++i) {
+            iters[i] = M.st_host[i].iters;
+            outer[i] = 1;
+            if (x0) kept[i] = M.st_host[i].guess;
+        }
+    } else if (o.precision == DG_PREC_FP64 || o.precision == DG_PREC_FP32_PC) {
         const bool pc = o.precision == DG_PREC_FP32_PC;
         if (pc)
             ensure_work_pc(M, nrhs);
@@ -784,7 +911,9 @@ void prepare_lane(dg_ctx* ctx, Mesh& M, int cnt) {
     const int prec = ctx->opts.precision;
     ensure_b(M, cnt, prec == DG_PREC_FP32_IR);
     ensure_state(M, cnt);
-    if (prec == DG_PREC_FP32_IR)
+    if (use_fused(ctx, M))
+        ensure_fused_ws(M, cnt);
+    else if (prec == DG_PREC_FP32_IR)
         ensure_work<float>(M, M.w32, cnt);
     else if (prec == DG_PREC_FP32_PC)
         ensure_work_pc(M, cnt);
@@ -946,7 +1075,11 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
         HIPCHK(hipMemcpy(L.dev32, &L.d32, sizeof(L.d32), hipMemcpyHostToDevice));
         L.devtr = dalloc<dg::TransferDev>(1);
         HIPCHK(hipMemcpy(L.devtr, &L.tr, sizeof(L.tr), hipMemcpyHostToDevice));
+        L.dinv64 = dalloc<double>(L.ndof);
+        L.dinv32 = dalloc<float>(L.ndof);
+        dg::launch_dinv(L, s);
     }
+    HIPCHK(hipStreamSynchronize(s));
     M.dcoarse = dalloc<dg::CoarseDev>(1);
     HIPCHK(hipMemcpy(M.dcoarse, &M.coarse, sizeof(M.coarse), hipMemcpyHostToDevice));
     int ps = dg::chunks_of(M.lv[0].ndof);
@@ -1023,6 +1156,7 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
         }
         M.cheb[l] = C;
     }
+    build_fused(M);
 }
 
 }  // namespace
@@ -1080,6 +1214,7 @@ void dg_opts_default(dg_opts* o) {
     o->lanes = 2;
     o->use_graph = 1;
     o->cheb_degree_h = 10;
+    o->fused = 0;
 }
 
 const char* dg_status_string(dg_status s) {
@@ -1137,6 +1272,8 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
                 T.cheb = M.cheb;
                 T.coarse = M.coarse;
                 T.dcoarse = M.dcoarse;
+                T.dfused = M.dfused;
+                T.fws_per = M.fws_per;
                 T.pstride = M.pstride;
                 T.nface = M.nface;
                 T.owns_tables = false;
@@ -1160,9 +1297,14 @@ void dg_poisson_destroy(dg_ctx* ctx) {
                 dfree(L.dev64);
                 dfree(L.dev32);
                 dfree(L.devtr);
+                dfree(L.dinv64);
+                dfree(L.dinv32);
             }
             dfree(M.dcoarse);
+            dfree(M.dfused);
+            for (auto* p : M.fusedP) dfree(p);
         }
+        dfree(M.fws);
         M.w64.release();
         M.w32.release();
         dfree(M.b);

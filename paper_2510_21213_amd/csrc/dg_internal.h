@@ -107,6 +107,8 @@ struct LevelHost {
     LevelDev<float> d32;
     LevelDev<double>* dev64 = nullptr;  // device copies
     LevelDev<float>* dev32 = nullptr;
+    double* dinv64 = nullptr;  // inverse diagonal of the level's operator, one value per node (device)
+    float* dinv32 = nullptr;
     // transfer to the next coarser level (unused on the coarsest)
     bool hcoarse = false;
     TransferDev tr;

@@ -78,6 +78,9 @@ template <typename T>
 void launch_coarse(const CoarseDev* C, const LevelHost& L, int nrhs, const RhsState* st, const T* r, T* z,
                    hipStream_t s);
 
+// L.dinv64 / L.dinv32 = 1 / diag(A) of the level (the tables must be allocated, ndof each).
+void launch_dinv(const LevelHost& L, hipStream_t s);
+
 // z = c0 D^-1 f
 template <typename T>
 void launch_cheb0(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, const T* f, T* z,
@@ -155,6 +158,48 @@ void launch_segcopy(const double* src, const long long* soff, double* dst, const
 
 // K[q] = sum of partial[q][0..nblk-1] (fixed order).
 void launch_sum_partials(int nq, const double* partial, int pstride, int nblk, double* K, hipStream_t s);
+
+// Fused solve of small meshes: one work-group (FUSED_THREADS threads, a divisor of 1024) per right-hand side runs
+// the whole FP64 PCG with its V-cycle, every level staged through LDS, in a single launch.
+// Every level of an eligible mesh has degree at most 4, at most FUSED_MAX_DOF nodes (two FP64
+// staging arrays of that size fill 128 KiB of LDS) and at most FUSED_MAX_AXIS nodes per axis.
+constexpr int FUSED_THREADS = 512;
+constexpr int FUSED_MAX_DOF = 8192;
+constexpr int FUSED_MAX_LEVELS = 8;
+constexpr int FUSED_MAX_AXIS = 64;
+constexpr int FUSED_MAX_DEG = 16;
+constexpr int FUSED_LDS_DOUBLES = 20480;  // the work-group's LDS: 160 KiB
+constexpr int FUSED_COARSE_SCRATCH = 16 * (16 * 17 + 2) + 3 * 16 * 16;  // coarsest solve's LDS (CMAX = 16)
+struct FusedLevel {
+    const LevelDev<double>* L;  // 1D blocks and masses of the level (device)
+    const double* dinv;         // inverse diagonal, element-major (device)
+    int E[3], n, ndof, N[3];    // elements, nodes per element edge, nodes, nodes per axis
+    int deg;                    // smoothing steps (0 on the coarsest level)
+    double c0, cp[FUSED_MAX_DEG], cr[FUSED_MAX_DEG];
+    long long off_f, off_za, off_zb;  // fields of the level in a right-hand side's work space
+    int lf, lza, lzb;                 // the same fields' offsets in LDS (resident mode)
+    // transfer to the next coarser level per axis: P[d][Xf * Nc_d + Xc] (device, dense); the
+    // coarse node Xc takes the fine nodes rlo .. rlo + rcnt - 1 (restriction), the fine node Xf
+    // the coarse nodes plo .. plo + pcnt - 1 (prolongation)
+    const double* P[3];
+    short rlo[3][FUSED_MAX_AXIS], rcnt[3][FUSED_MAX_AXIS], plo[3][FUSED_MAX_AXIS], pcnt[3][FUSED_MAX_AXIS];
+};
+struct FusedMeshDev {
+    int nl;
+    int resident;  // 1: every level field lives in LDS for the whole solve
+    int lsy;       // resident mode: LDS offset of the operator output (and of the coarsest solve's scratch)
+    FusedLevel lv[FUSED_MAX_LEVELS];
+    const CoarseDev* coarse;
+    long long off_x, off_r, off_p;  // level-0 PCG fields (the level-0 smoother fields are lv[0].off_za/zb)
+    long long ws_per_rhs;           // doubles of work space per right-hand side
+};
+// Solve nrhs problems b -> x of one small mesh (FP64 PCG, HS beta, up to three restarts from the
+// current iterate when the recomputed residual misses the tolerance).  st: tol2 and maxit set;
+// on return bb, rr (of the returned x), iters, breakdown and guess are written, active = 0.
+// has_x0: x holds initial guesses (guard: a guess whose residual is not below ||b|| is dropped).
+// ws: nrhs * M.ws_per_rhs doubles.
+void launch_fused_pcg(const FusedMeshDev* M, int nrhs, const double* b, double* x, RhsState* st, double* ws,
+                      bool has_x0, bool guard, hipStream_t s);
 
 // Dirichlet data by quadrature (dg_boundary.hip): g[s][b] = sum_q W_q f_s(x_q) / |r_b - x_q| over the
 // finest level's nodes, for nsrc sources f (packed fields) or, with f null, the pair products

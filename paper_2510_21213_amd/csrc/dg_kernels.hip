@@ -1640,18 +1640,14 @@ template void launch_prolong<float>(const LevelHost&, const LevelHost&, int, con
 constexpr int CSY = CMAX + 1;
 constexpr int CSZ = CMAX * CSY + 2;
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse(const CoarseDev* __restrict__ C, int nrhs, long long ndof,
-                                                 const RhsState* st, const T* __restrict__ r, T* __restrict__ z) {
-    __shared__ double g[CMAX * CSZ];
-    __shared__ double Qs[3][CMAX][CMAX];
-    const int rhs = blockIdx.x;
-    if (st && !st[rhs].active) return;
+// Exact coarsest-level solve of one right-hand side by a work-group of 1024 / LPT threads: rr and
+// zz are its fields (element-major, ndof values), g (CMAX * CSZ doubles) and Qs (3 CMAX^2) LDS.
+template <typename T, int LPT = 1>
+__device__ __forceinline__ void coarse_wg(const CoarseDev* __restrict__ C, long long ndof, const T* __restrict__ rr,
+                                          T* __restrict__ zz, double* g, double (*Qs)[CMAX][CMAX]) {
     const int nx = C->n[0], ny = C->n[1], nz = C->n[2], N = C->N;
     const int E0 = C->E[0], E1 = C->E[1];
     const int N3 = N * N * N;
-    const T* rr = r + (long long)rhs * ndof;
-    T* zz = z + (long long)rhs * ndof;
     const int t = threadIdx.x;
     const int nd = (int)ndof;
     for (int q = t; q < 3 * CMAX * CMAX; q += blockDim.x) (&Qs[0][0][0])[q] = (&C->Q[0][0][0])[q];
@@ -1665,40 +1661,50 @@ __global__ __launch_bounds__(1024) void k_coarse(const CoarseDev* __restrict__ C
     __syncthreads();
     // three contractions with Q^T, the eigenvalue scaling, three with Q.  A
     // line of n values is shared by 4 threads, each producing a quarter of
-    // the outputs.
+    // the outputs; a work-group of fewer than 1024 threads takes LPT lines
+    // per thread group.
     for (int pass = 0; pass < 6; ++pass) {
         const int axis = pass % 3;
         const bool fwd = pass < 3;
         const int n = C->n[axis];
         const int nl = (nx * ny * nz) / n;
         const int part = t & 3;
-        double w[CMAX / 4];
-        int o = 0, stride = 1;
-        const int line = t >> 2;
-        const bool act = line < nl;
-        if (act) {
-            if (axis == 0) { const int Zg = line / ny, Yg = line % ny; o = Zg * CSZ + Yg * CSY; stride = 1; }
-            else if (axis == 1) { const int Zg = line / nx, Xg = line % nx; o = Zg * CSZ + Xg; stride = CSY; }
-            else { const int Yg = line / nx, Xg = line % nx; o = Yg * CSY + Xg; stride = CSZ; }
-            double v[CMAX];
+        double w[LPT][CMAX / 4];
+        int o[LPT], stride[LPT];
+        bool act[LPT];
 #pragma unroll
-            for (int b = 0; b < CMAX; ++b) v[b] = b < n ? g[o + b * stride] : 0.0;
+        for (int m = 0; m < LPT; ++m) {
+            const int line = (t >> 2) + m * ((int)blockDim.x >> 2);
+            act[m] = line < nl;
+            o[m] = 0;
+            stride[m] = 1;
+            if (act[m]) {
+                if (axis == 0) { const int Zg = line / ny, Yg = line % ny; o[m] = Zg * CSZ + Yg * CSY; stride[m] = 1; }
+                else if (axis == 1) { const int Zg = line / nx, Xg = line % nx; o[m] = Zg * CSZ + Xg; stride[m] = CSY; }
+                else { const int Yg = line / nx, Xg = line % nx; o[m] = Yg * CSY + Xg; stride[m] = CSZ; }
+                double v[CMAX];
 #pragma unroll
-            for (int a4 = 0; a4 < CMAX / 4; ++a4) {
-                const int a2 = part + 4 * a4;
-                double s = 0.0;
+                for (int b = 0; b < CMAX; ++b) v[b] = b < n ? g[o[m] + b * stride[m]] : 0.0;
 #pragma unroll
-                for (int b = 0; b < CMAX; ++b)
-                    if (a2 < n && b < n) s += (fwd ? Qs[axis][b][a2] : Qs[axis][a2][b]) * v[b];
-                w[a4] = s;
+                for (int a4 = 0; a4 < CMAX / 4; ++a4) {
+                    const int a2 = part + 4 * a4;
+                    double s = 0.0;
+#pragma unroll
+                    for (int b = 0; b < CMAX; ++b)
+                        if (a2 < n && b < n) s += (fwd ? Qs[axis][b][a2] : Qs[axis][a2][b]) * v[b];
+                    w[m][a4] = s;
+                }
             }
         }
         __syncthreads();
-        if (act) {
 #pragma unroll
-            for (int a4 = 0; a4 < CMAX / 4; ++a4) {
-                const int a2 = part + 4 * a4;
-                if (a2 < n) g[o + a2 * stride] = w[a4];
+        for (int m = 0; m < LPT; ++m) {
+            if (act[m]) {
+#pragma unroll
+                for (int a4 = 0; a4 < CMAX / 4; ++a4) {
+                    const int a2 = part + 4 * a4;
+                    if (a2 < n) g[o[m] + a2 * stride[m]] = w[m][a4];
+                }
             }
         }
         __syncthreads();
@@ -1717,6 +1723,16 @@ __global__ __launch_bounds__(1024) void k_coarse(const CoarseDev* __restrict__ C
         const int Xg = ex * N + i, Yg = ey * N + j, Zg = ez * N + k;
         zz[q] = (T)(g[Zg * CSZ + Yg * CSY + Xg] * C->s[0][Xg] * C->s[1][Yg] * C->s[2][Zg]);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse(const CoarseDev* __restrict__ C, int nrhs, long long ndof,
+                                                 const RhsState* st, const T* __restrict__ r, T* __restrict__ z) {
+    __shared__ double g[CMAX * CSZ];
+    __shared__ double Qs[3][CMAX][CMAX];
+    const int rhs = blockIdx.x;
+    if (st && !st[rhs].active) return;
+    coarse_wg<T>(C, ndof, r + (long long)rhs * ndof, z + (long long)rhs * ndof, g, Qs);
 }
 
 template <typename T>
@@ -1745,47 +1761,80 @@ __device__ __forceinline__ T diag_at(const LevelDev<T>& L, int E0, int E1, int E
     return L.ax[0].Bd[tx][i] * my * mz + mx * L.ax[1].Bd[ty][j] * mz + mx * my * L.ax[2].Bd[tz][k];
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_cheb0(const LevelDev<T>* __restrict__ L, int E0, int E1, int E2,
-                                               long long ndof, const RhsState* st, const T* __restrict__ f,
-                                               T* __restrict__ z, T c0) {
-    const int rhs = blockIdx.y;
+// Inverse diagonal of a level's operator, one value per node (shared by every right-hand side).
+template <int N>
+__global__ __launch_bounds__(256) void k_dinv(const LevelDev<double>* __restrict__ L, int E0, int E1, int E2,
+                                              long long ndof, double* __restrict__ d64, float* __restrict__ d32) {
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= ndof) return;
+    const double d = 1.0 / diag_at<double, N>(*L, E0, E1, E2, q);
+    d64[q] = d;
+    d32[q] = (float)d;
+}
+
+void launch_dinv(const LevelHost& L, hipStream_t s) {
+    const long long n = L.ndof;
+    const dim3 grid((unsigned)((n + 255) / 256));
+#define DG_DI(NN) \
+    case NN: hipLaunchKernelGGL((k_dinv<NN>), grid, dim3(256), 0, s, L.dev64, L.E[0], L.E[1], L.E[2], n, L.dinv64, L.dinv32); break;
+    switch (L.n) { DG_DI(2) DG_DI(3) DG_DI(4) DG_DI(5) DG_DI(6) DG_DI(7) DG_DI(8) }
+#undef DG_DI
+}
+
+// The pointwise kernels below run on a grid (right-hand side, chunk of 1024 nodes) with the
+// right-hand side fastest, so that the work-groups of one chunk follow each other and share
+// its slice of the inverse-diagonal table in L2.
+template <typename T>
+const T* dinv_of(const LevelHost& L);
+template <>
+const double* dinv_of<double>(const LevelHost& L) { return L.dinv64; }
+template <>
+const float* dinv_of<float>(const LevelHost& L) { return L.dinv32; }
+
+inline dim3 rhs_chunk_grid(long long ndof, int nrhs) {
+    const int nc = chunks_of(ndof);
+    if (nc > 65535) throw std::logic_error("field too large for the pointwise kernels' grid");
+    return dim3((unsigned)nrhs, (unsigned)nc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cheb0(const T* __restrict__ dinv, long long ndof, const RhsState* st,
+                                               const T* __restrict__ f, T* __restrict__ z, T c0) {
+    const int rhs = blockIdx.x;
     if (st && !st[rhs].active) return;
     const long long base = (long long)rhs * ndof;
-    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    const long long q0 = (long long)blockIdx.y * 1024 + threadIdx.x;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const long long q = q0 + v * 256;
-        if (q < ndof) z[base + q] = c0 * f[base + q] / diag_at<T, N>(*L, E0, E1, E2, q);
+        if (q < ndof) z[base + q] = c0 * f[base + q] * dinv[q];
     }
 }
 
 template <typename T>
 void launch_cheb0(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, const T* f, T* z,
                   double c0, hipStream_t s) {
+    (void)dev;
     if (nrhs == 0) return;
-    dim3 grid(chunks_of(L.ndof), nrhs);
-#define DG_C0(NN) \
-    case NN: hipLaunchKernelGGL((k_cheb0<T, NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, st, f, z, (T)c0); break;
-    switch (L.n) { DG_C0(2) DG_C0(3) DG_C0(4) DG_C0(5) DG_C0(6) DG_C0(7) DG_C0(8) }
-#undef DG_C0
+    hipLaunchKernelGGL((k_cheb0<T>), rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, dinv_of<T>(L), L.ndof, st, f, z,
+                       (T)c0);
 }
 template void launch_cheb0<double>(const LevelHost&, const LevelDev<double>*, int, const RhsState*, const double*,
                                    double*, double, hipStream_t);
 template void launch_cheb0<float>(const LevelHost&, const LevelDev<float>*, int, const RhsState*, const float*,
                                   float*, double, hipStream_t);
 
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_update(const LevelDev<T>* __restrict__ L, int E0, int E1, int E2,
-                                                long long ndof, const RhsState* st, T* __restrict__ x,
-                                                T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q_,
-                                                T* __restrict__ z1, T c0, double* __restrict__ partial, int pstride) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(const T* __restrict__ dinv, long long ndof, const RhsState* st,
+                                                T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                                                const T* __restrict__ q_, T* __restrict__ z1, T c0,
+                                                double* __restrict__ partial, int pstride) {
     __shared__ double red[4];
-    const int rhs = blockIdx.y;
+    const int rhs = blockIdx.x;
     if (!st[rhs].active) return;
     const T alpha = (T)st[rhs].alpha;
     const long long base = (long long)rhs * ndof;
-    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    const long long q0 = (long long)blockIdx.y * 1024 + threadIdx.x;
     double acc = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1796,44 +1845,37 @@ __global__ __launch_bounds__(256) void k_update(const LevelDev<T>* __restrict__ 
             const T rn = r[g] - alpha * q_[g];
             r[g] = rn;
             acc += (double)rn * (double)rn;
-            if (z1) z1[g] = c0 * rn / diag_at<T, N>(*L, E0, E1, E2, q);
+            if (z1) z1[g] = c0 * rn * dinv[q];
         }
     }
     const double s = block_sum<256>(acc, red);
-    if (threadIdx.x == 0) partial[(long long)rhs * pstride + blockIdx.x] = s;
+    if (threadIdx.x == 0) partial[(long long)rhs * pstride + blockIdx.y] = s;
 }
 
 template <typename T>
 void launch_update(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st, T* x, T* r, const T* p,
                    const T* q, T* z1, double c0, double* partial, int pstride, hipStream_t s) {
+    (void)dev;
     if (nrhs == 0) return;
-    dim3 grid(chunks_of(L.ndof), nrhs);
-#define DG_U(NN)                                                                                                  \
-    case NN:                                                                                                      \
-        hipLaunchKernelGGL((k_update<T, NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, st, x, r, \
-                           p, q, z1, (T)c0, partial, pstride);                                                    \
-        break;
-    switch (L.n) { DG_U(2) DG_U(3) DG_U(4) DG_U(5) DG_U(6) DG_U(7) DG_U(8) }
-#undef DG_U
+    hipLaunchKernelGGL((k_update<T>), rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, dinv_of<T>(L), L.ndof, st, x, r,
+                       p, q, z1, (T)c0, partial, pstride);
 }
 template void launch_update<double>(const LevelHost&, const LevelDev<double>*, int, const RhsState*, double*, double*,
                                     const double*, const double*, double*, double, double*, int, hipStream_t);
 template void launch_update<float>(const LevelHost&, const LevelDev<float>*, int, const RhsState*, float*, float*,
                                    const float*, const float*, float*, double, double*, int, hipStream_t);
 
-template <int N>
-__global__ __launch_bounds__(256) void k_update_pc(const LevelDev<double>* __restrict__ L, int E0, int E1, int E2,
-                                                   long long ndof, const RhsState* st, double* __restrict__ x,
-                                                   double* __restrict__ r, const double* __restrict__ p,
-                                                   const double* __restrict__ q_, float* __restrict__ r32,
-                                                   float* __restrict__ z1, double c0, double* __restrict__ partial,
-                                                   int pstride) {
+__global__ __launch_bounds__(256) void k_update_pc(const double* __restrict__ dinv, long long ndof, const RhsState* st,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q_,
+                                                   float* __restrict__ r32, float* __restrict__ z1, double c0,
+                                                   double* __restrict__ partial, int pstride) {
     __shared__ double red[4];
-    const int rhs = blockIdx.y;
+    const int rhs = blockIdx.x;
     if (!st[rhs].active) return;
     const double alpha = st[rhs].alpha;
     const long long base = (long long)rhs * ndof;
-    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    const long long q0 = (long long)blockIdx.y * 1024 + threadIdx.x;
     double acc = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1845,28 +1887,27 @@ __global__ __launch_bounds__(256) void k_update_pc(const LevelDev<double>* __res
             r[g] = rn;
             acc += rn * rn;
             r32[g] = (float)rn;
-            z1[g] = (float)(c0 * rn / diag_at<double, N>(*L, E0, E1, E2, q));
+            z1[g] = (float)(c0 * rn * dinv[q]);
         }
     }
     const double s = block_sum<256>(acc, red);
-    if (threadIdx.x == 0) partial[(long long)rhs * pstride + blockIdx.x] = s;
+    if (threadIdx.x == 0) partial[(long long)rhs * pstride + blockIdx.y] = s;
 }
 
-template <int N>
-__global__ __launch_bounds__(256) void k_to32_cheb0(const LevelDev<double>* __restrict__ L, int E0, int E1, int E2,
-                                                    long long ndof, const RhsState* st, const double* __restrict__ r,
+__global__ __launch_bounds__(256) void k_to32_cheb0(const double* __restrict__ dinv, long long ndof,
+                                                    const RhsState* st, const double* __restrict__ r,
                                                     float* __restrict__ r32, float* __restrict__ z1, double c0) {
-    const int rhs = blockIdx.y;
+    const int rhs = blockIdx.x;
     if (st && !st[rhs].active) return;
     const long long base = (long long)rhs * ndof;
-    const long long q0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    const long long q0 = (long long)blockIdx.y * 1024 + threadIdx.x;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const long long q = q0 + v * 256;
         if (q < ndof) {
             const double rv = r[base + q];
             r32[base + q] = (float)rv;
-            z1[base + q] = (float)(c0 * rv / diag_at<double, N>(*L, E0, E1, E2, q));
+            z1[base + q] = (float)(c0 * rv * dinv[q]);
         }
     }
 }
@@ -1874,28 +1915,18 @@ __global__ __launch_bounds__(256) void k_to32_cheb0(const LevelDev<double>* __re
 void launch_update_pc(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, double* x,
                       double* r, const double* p, const double* q, float* r32, float* z1, double c0, double* partial,
                       int pstride, hipStream_t s) {
+    (void)dev;
     if (nrhs == 0) return;
-    dim3 grid(chunks_of(L.ndof), nrhs);
-#define DG_UPC(NN)                                                                                                 \
-    case NN:                                                                                                       \
-        hipLaunchKernelGGL((k_update_pc<NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, st, x, r, \
-                           p, q, r32, z1, c0, partial, pstride);                                                   \
-        break;
-    switch (L.n) { DG_UPC(2) DG_UPC(3) DG_UPC(4) DG_UPC(5) DG_UPC(6) DG_UPC(7) DG_UPC(8) }
-#undef DG_UPC
+    hipLaunchKernelGGL(k_update_pc, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st, x, r, p, q,
+                       r32, z1, c0, partial, pstride);
 }
 
 void launch_to32_cheb0(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const double* r,
                        float* r32, float* z1, double c0, hipStream_t s) {
+    (void)dev;
     if (nrhs == 0) return;
-    dim3 grid(chunks_of(L.ndof), nrhs);
-#define DG_T32(NN)                                                                                                 \
-    case NN:                                                                                                       \
-        hipLaunchKernelGGL((k_to32_cheb0<NN>), grid, dim3(256), 0, s, dev, L.E[0], L.E[1], L.E[2], L.ndof, st, r,   \
-                           r32, z1, c0);                                                                           \
-        break;
-    switch (L.n) { DG_T32(2) DG_T32(3) DG_T32(4) DG_T32(5) DG_T32(6) DG_T32(7) DG_T32(8) }
-#undef DG_T32
+    hipLaunchKernelGGL(k_to32_cheb0, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st, r, r32, z1,
+                       c0);
 }
 
 template <typename TA, typename TB>
@@ -2379,4 +2410,428 @@ void launch_sum_partials(int nq, const double* partial, int pstride, int nblk, d
     hipLaunchKernelGGL(k_sum_partials, dim3(nq), dim3(256), 0, s, partial, pstride, nblk, K);
 }
 
+// ---------------------------------------------------------------------------
+// Fused solve of small meshes: one work-group per right-hand side runs the whole PCG and its
+// V-cycle.  Level fields live in the right-hand side's work space (global memory, L2-resident
+// at these sizes); the operand of every operator application and the intermediate arrays of the
+// transfers are staged in two LDS arrays of FUSED_MAX_DOF doubles.  Work-group barriers separate
+// the phases; there is no grid-wide synchronisation, so right-hand sides of different sizes and
+// iteration counts need nothing from each other.
+
+namespace {
+
+// The work-group's view of its LDS: in resident mode every level field lives in LDS for the whole
+// solve (offsets FusedLevel::lf/lza/lzb); otherwise the fields live in the right-hand side's
+// work space and the operand of each operator application is staged into su.  sy receives the
+// operator's output; g and Qs are the coarsest solve's scratch; red the reduction slots.
+struct WgCtx {
+    double* lds;
+    double* su;
+    double* sy;
+    double* g;
+    double* Qs;
+    double* red;
+    bool resident;
+};
+
+// Sum over the work-group, the same value (added in a fixed order) in every thread.
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();  // red may still be read by the previous sum
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < FUSED_THREADS / 64; ++i) s += red[i];
+    return s;
+}
+
+__device__ __forceinline__ void wg_copy(const double* __restrict__ src, double* __restrict__ dst, int n) {
+#pragma unroll 8
+    for (int q = threadIdx.x; q < n; q += FUSED_THREADS) dst[q] = src[q];
+    __syncthreads();
+}
+
+// A field as an operator operand in LDS: itself in resident mode, else staged into su.
+__device__ __forceinline__ const double* wg_operand(const WgCtx& w, const double* g, int n) {
+    if (w.resident) return g;
+    wg_copy(g, w.su, n);
+    return w.su;
+}
+
+// Element-major index of the level node with global indices (X, Y, Z).
+__device__ __forceinline__ int em_index(const FusedLevel& F, int X, int Y, int Z) {
+    const int n = F.n;
+    const int ex = X / n, i = X - ex * n, ey = Y / n, j = Y - ey * n, ez = Z / n, k = Z - ez * n;
+    return ((ez * F.E[1] + ey) * F.E[0] + ex) * n * n * n + (k * n + j) * n + i;
+}
+
+// sy = A su on level F (element-major), axis by axis: one thread per element line computes the
+// line's N outputs with the reference-element block shared by every element and axis (the slab
+// kernel's elem_op): the neighbours along the axis supply their face value and normal
+// derivative, and a domain face supplies ghost data that reproduces its Nitsche terms.  The
+// output is scaled by the axis factor and the two tangential GLL weights.
+template <int N>
+__device__ void wg_apply_n(const FusedLevel& F, const double* su, double* sy) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const RefDev<double>& R = F.L->ref;
+    SlabCoef<double, N> c;
+    load_coef(c, R);
+    const int E0 = F.E[0], E1 = F.E[1];
+    const int nlines = F.ndof / N;
+#pragma unroll 1
+    for (int axis = 0; axis < 3; ++axis) {
+        const int Ed = F.E[axis];
+        const int s_in = axis == 0 ? 1 : (axis == 1 ? N : N2);
+        const int s_el = axis == 0 ? N3 : (axis == 1 ? E0 * N3 : E0 * E1 * N3);
+        const double sca = R.scale[axis];
+        for (int t = threadIdx.x; t < nlines; t += FUSED_THREADS) {
+            const int e = t / N2, ln = t - e * N2;
+            const int a = ln % N, b = ln / N;  // the other two local indices, lower axis first
+            int off, ed;
+            if (axis == 0) {
+                off = a * N + b * N2;
+                ed = e % E0;
+            } else if (axis == 1) {
+                off = a + b * N2;
+                ed = (e / E0) % E1;
+            } else {
+                off = a + b * N;
+                ed = e / (E0 * E1);
+            }
+            const int base = e * N3 + off;
+            double A[N], nb[N], acc[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) A[l] = su[base + l * s_in];
+            double U, Dv, U0, D0;
+            if (ed > 0) {
+#pragma unroll
+                for (int l = 0; l < N; ++l) nb[l] = su[base - s_el + l * s_in];
+                U = nb[N - 1];
+                Dv = face_r(c, nb);
+            } else {
+                U = -A[0];
+                Dv = face_l(c, A) - 2.0 * c.sig * A[0];
+            }
+            if (ed < Ed - 1) {
+#pragma unroll
+                for (int l = 0; l < N; ++l) nb[l] = su[base + s_el + l * s_in];
+                U0 = nb[0];
+                D0 = face_l(c, nb);
+            } else {
+                U0 = -A[N - 1];
+                D0 = face_r(c, A) + 2.0 * c.sig * A[N - 1];
+            }
+            elem_op(c, A, U, Dv, U0, D0, acc);
+            const double sc = sca * R.w[a] * R.w[b];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                if (axis == 0)
+                    sy[base + i * s_in] = acc[i] * sc;
+                else
+                    sy[base + i * s_in] += acc[i] * sc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void wg_apply(const FusedLevel& F, const double* su, double* sy) {
+    switch (F.n) {
+        case 2: wg_apply_n<2>(F, su, sy); break;
+        case 3: wg_apply_n<3>(F, su, sy); break;
+        case 4: wg_apply_n<4>(F, su, sy); break;
+        case 5: wg_apply_n<5>(F, su, sy); break;
+    }
+}
+
+// One Chebyshev step on level F: out = z + cp (z - zp) + cr D^-1 (f - A z); zp null: the previous
+// iterate is zero (the second pre-smoothing step, whose recurrence starts from z = 0).
+__device__ void wg_cheb(const WgCtx& w, const FusedLevel& F, const double* __restrict__ f, const double* z,
+                        const double* __restrict__ zp, double* __restrict__ out, double cp, double cr) {
+    const double* zin = wg_operand(w, z, F.ndof);
+    wg_apply(F, zin, w.sy);
+#pragma unroll 8
+    for (int q = threadIdx.x; q < F.ndof; q += FUSED_THREADS) {
+        const double zq = zin[q];
+        out[q] = zq + cp * (zq - (zp ? zp[q] : 0.0)) + cr * F.dinv[q] * (f[q] - w.sy[q]);
+    }
+    __syncthreads();
+}
+
+// fc = P^T r from the fine level F to the coarse level C; r in w.sy (element-major), t1 a free
+// array of F.ndof values.  With z1c, also z1c = C.c0 D_C^-1 fc (the coarse level's first iterate).
+__device__ void wg_restrict(const WgCtx& w, const FusedLevel& F, const FusedLevel& C, double* t1, double* fc,
+                            double* z1c) {
+    const int NXf = F.N[0], NYf = F.N[1], NZf = F.N[2];
+    const int NXc = C.N[0], NYc = C.N[1], NZc = C.N[2];
+    const double *P0 = F.P[0], *P1 = F.P[1], *P2 = F.P[2];
+    double* sy = w.sy;
+    for (int o = threadIdx.x; o < NXc * NYf * NZf; o += FUSED_THREADS) {  // along x: (Xc, Yf, Zf)
+        const int Xc = o % NXc, Yf = (o / NXc) % NYf, Zf = o / (NXc * NYf);
+        const int lo = F.rlo[0][Xc], cnt = F.rcnt[0][Xc];
+        double s = 0.0;
+        for (int c = 0; c < cnt; ++c) s += P0[(lo + c) * NXc + Xc] * sy[em_index(F, lo + c, Yf, Zf)];
+        t1[o] = s;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < NXc * NYc * NZf; o += FUSED_THREADS) {  // along y: (Xc, Yc, Zf)
+        const int Xc = o % NXc, Yc = (o / NXc) % NYc, Zf = o / (NXc * NYc);
+        const int lo = F.rlo[1][Yc], cnt = F.rcnt[1][Yc];
+        double s = 0.0;
+        for (int c = 0; c < cnt; ++c) s += P1[(lo + c) * NYc + Yc] * t1[(Zf * NYf + lo + c) * NXc + Xc];
+        sy[o] = s;
+    }
+    __syncthreads();
+    const int n = C.n, n3 = n * n * n;
+    for (int o = threadIdx.x; o < C.ndof; o += FUSED_THREADS) {  // along z, into the coarse field
+        const int e = o / n3, l = o - e * n3;
+        const int Xc = (e % C.E[0]) * n + l % n, Yc = ((e / C.E[0]) % C.E[1]) * n + (l / n) % n,
+                  Zc = (e / (C.E[0] * C.E[1])) * n + l / (n * n);
+        const int lo = F.rlo[2][Zc], cnt = F.rcnt[2][Zc];
+        double s = 0.0;
+        for (int c = 0; c < cnt; ++c) s += P2[(lo + c) * NZc + Zc] * sy[((lo + c) * NYc + Yc) * NXc + Xc];
+        fc[o] = s;
+        if (z1c) z1c[o] = C.c0 * C.dinv[o] * s;
+    }
+    __syncthreads();
+}
+
+// zf += P zc from the coarse level C to the fine level F (element-major); t1 a free array of F.ndof.
+__device__ void wg_prolong_add(const WgCtx& w, const FusedLevel& F, const FusedLevel& C, const double* zc,
+                               double* zf, double* t1) {
+    const int NXf = F.N[0], NYf = F.N[1];
+    const int NXc = C.N[0], NYc = C.N[1], NZc = C.N[2];
+    const double *P0 = F.P[0], *P1 = F.P[1], *P2 = F.P[2];
+    double* sy = w.sy;
+    for (int o = threadIdx.x; o < NXf * NYc * NZc; o += FUSED_THREADS) {  // along x: (Xf, Yc, Zc)
+        const int Xf = o % NXf, Yc = (o / NXf) % NYc, Zc = o / (NXf * NYc);
+        const int lo = F.plo[0][Xf], cnt = F.pcnt[0][Xf];
+        double s = 0.0;
+        for (int c = 0; c < cnt; ++c) s += P0[Xf * NXc + lo + c] * zc[em_index(C, lo + c, Yc, Zc)];
+        t1[o] = s;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < NXf * NYf * NZc; o += FUSED_THREADS) {  // along y: (Xf, Yf, Zc)
+        const int Xf = o % NXf, Yf = (o / NXf) % NYf, Zc = o / (NXf * NYf);
+        const int lo = F.plo[1][Yf], cnt = F.pcnt[1][Yf];
+        double s = 0.0;
+        for (int c = 0; c < cnt; ++c) s += P1[Yf * NYc + lo + c] * t1[(Zc * NYc + lo + c) * NXf + Xf];
+        sy[o] = s;
+    }
+    __syncthreads();
+    const int n = F.n, n3 = n * n * n;
+    for (int o = threadIdx.x; o < F.ndof; o += FUSED_THREADS) {  // along z, added to the fine field
+        const int e = o / n3, l = o - e * n3;
+        const int Xf = (e % F.E[0]) * n + l % n, Yf = ((e / F.E[0]) % F.E[1]) * n + (l / n) % n,
+                  Zf = (e / (F.E[0] * F.E[1])) * n + l / (n * n);
+        const int lo = F.plo[2][Zf], cnt = F.pcnt[2][Zf];
+        double s = 0.0;
+        for (int c = 0; c < cnt; ++c) s += P2[Zf * NZc + lo + c] * sy[((lo + c) * NYf + Yf) * NXf + Xf];
+        zf[o] += s;
+    }
+    __syncthreads();
+}
+
+// Fields of a level: in LDS (resident) or in the right-hand side's work space.
+__device__ __forceinline__ double* lvf(const WgCtx& w, double* ws, const FusedLevel& F, int which) {
+    if (w.resident) return w.lds + (which == 0 ? F.lf : which == 1 ? F.lza : F.lzb);
+    return ws + (which == 0 ? F.off_f : which == 1 ? F.off_za : F.off_zb);
+}
+
+// z = B r, one V-cycle from level 0 (r: the level-0 source, lvf(level 0, 0)); returns the field
+// that holds z (one of the level-0 smoother fields).
+__device__ double* wg_vcycle(const WgCtx& w, const FusedMeshDev& M, double* ws) {
+    const int nl = M.nl;
+    double* zcur[FUSED_MAX_LEVELS];
+    double* zoth[FUSED_MAX_LEVELS];
+    for (int l = 0; l + 1 < nl; ++l) {
+        const FusedLevel& F = M.lv[l];
+        const double* f = lvf(w, ws, F, 0);
+        double* cur = lvf(w, ws, F, 1);
+        double* prev = lvf(w, ws, F, 2);
+        if (l == 0) {  // lower levels receive their first iterate from the restriction
+#pragma unroll 8
+            for (int q = threadIdx.x; q < F.ndof; q += FUSED_THREADS) cur[q] = F.c0 * F.dinv[q] * f[q];
+            __syncthreads();
+        }
+        for (int k = 1; k < F.deg; ++k) {
+            wg_cheb(w, F, f, cur, k == 1 ? nullptr : prev, prev, F.cp[k - 1], F.cr[k - 1]);
+            double* t = cur; cur = prev; prev = t;
+        }
+        // residual into sy, restricted to the next level
+        const double* zin = wg_operand(w, cur, F.ndof);
+        wg_apply(F, zin, w.sy);
+#pragma unroll 8
+        for (int q = threadIdx.x; q < F.ndof; q += FUSED_THREADS) w.sy[q] = f[q] - w.sy[q];
+        __syncthreads();
+        const FusedLevel& C = M.lv[l + 1];
+        wg_restrict(w, F, C, w.resident ? prev : w.su, lvf(w, ws, C, 0), l + 2 < nl ? lvf(w, ws, C, 1) : nullptr);
+        zcur[l] = cur;
+        zoth[l] = prev;
+    }
+    const FusedLevel& Lc = M.lv[nl - 1];
+    double* zc = lvf(w, ws, Lc, 1);
+    coarse_wg<double, 1024 / FUSED_THREADS>(M.coarse, Lc.ndof, lvf(w, ws, Lc, 0), zc, w.g,
+                                            reinterpret_cast<double(*)[CMAX][CMAX]>(w.Qs));
+    __syncthreads();
+    for (int l = nl - 2; l >= 0; --l) {
+        const FusedLevel& F = M.lv[l];
+        const double* f = lvf(w, ws, F, 0);
+        double* cur = zcur[l];
+        double* prev = zoth[l];
+        wg_prolong_add(w, F, M.lv[l + 1], zc, cur, w.resident ? prev : w.su);
+        for (int k = 0; k < F.deg; ++k) {
+            wg_cheb(w, F, f, cur, k == 0 ? nullptr : prev, prev, k == 0 ? 0.0 : F.cp[k - 1],
+                    k == 0 ? F.c0 : F.cr[k - 1]);
+            double* t = cur; cur = prev; prev = t;
+        }
+        zc = cur;
+    }
+    return zc;
+}
+
+__global__ __launch_bounds__(FUSED_THREADS) void k_fused_pcg(const FusedMeshDev* __restrict__ Mp, int nrhs,
+                                                            const double* __restrict__ b_all,
+                                                            double* __restrict__ x_all, RhsState* st,
+                                                            double* __restrict__ ws_all, int has_x0, int guard) {
+    __shared__ double lds[FUSED_LDS_DOUBLES];
+    const FusedMeshDev& M = *Mp;
+    WgCtx w;
+    w.lds = lds;
+    w.resident = M.resident != 0;
+    w.red = lds + FUSED_LDS_DOUBLES - FUSED_THREADS / 64;
+    if (w.resident) {
+        w.su = nullptr;
+        w.sy = lds + M.lsy;
+        w.g = lds + M.lsy;
+    } else {
+        w.su = lds;
+        w.sy = lds + FUSED_MAX_DOF;
+        w.g = lds;
+    }
+    w.Qs = w.g + CMAX * CSZ;
+    const int rhs = blockIdx.x;
+    const FusedLevel& F0 = M.lv[0];
+    const int nd = F0.ndof;
+    const double* __restrict__ b = b_all + (long long)rhs * nd;
+    double* __restrict__ x = x_all + (long long)rhs * nd;
+    double* ws = ws_all + (long long)rhs * M.ws_per_rhs;
+    double* r = lvf(w, ws, F0, 0);
+    double* p = ws + M.off_p;
+    const double tol2 = st[rhs].tol2;
+    const int maxit = st[rhs].maxit;
+    const int T = threadIdx.x;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int q = T; q < nd; q += FUSED_THREADS) acc += b[q] * b[q];
+    const double bb = wg_sum(acc, w.red);
+    // r = b - A x of the current x (its operand staged in the level-0 smoother field, free here)
+    auto residual = [&]() -> double {
+        double* xs = w.resident ? lvf(w, ws, F0, 1) : w.su;
+        wg_copy(x, xs, nd);
+        wg_apply(F0, xs, w.sy);
+        double a = 0.0;
+#pragma unroll 8
+        for (int q = T; q < nd; q += FUSED_THREADS) {
+            const double rq = b[q] - w.sy[q];
+            r[q] = rq;
+            a += rq * rq;
+        }
+        return wg_sum(a, w.red);
+    };
+    // start: r = b - A x0, or x = 0 and r = b; a guarded guess is kept only if its residual is below ||b||
+    double rr = 0.0;
+    int guess = 0;
+    if (has_x0) {
+        rr = residual();
+        guess = (!guard || rr < bb) ? 1 : 0;
+    }
+    if (!guess) {
+#pragma unroll 8
+        for (int q = T; q < nd; q += FUSED_THREADS) {
+            x[q] = 0.0;
+            r[q] = b[q];
+        }
+        rr = bb;
+        __syncthreads();
+    }
+    int iters = 0, breakdown = 0;
+    for (int pass = 0; pass < 4; ++pass) {  // the first PCG pass and up to three restarts
+        breakdown = 0;
+        if (rr > tol2 * bb && iters < maxit) {
+            double* z = wg_vcycle(w, M, ws);
+            acc = 0.0;
+#pragma unroll 8
+            for (int q = T; q < nd; q += FUSED_THREADS) {
+                acc += r[q] * z[q];
+                p[q] = z[q];
+            }
+            double rz = wg_sum(acc, w.red);
+            while (true) {
+                // q = A p, with the LDS copy of p (resident: z's field now holds p)
+                const double* pl = w.resident ? z : wg_operand(w, p, nd);
+                wg_apply(F0, pl, w.sy);
+                acc = 0.0;
+#pragma unroll 8
+                for (int q = T; q < nd; q += FUSED_THREADS) acc += pl[q] * w.sy[q];
+                const double pq = wg_sum(acc, w.red);
+                if (!(pq > 0.0) || !(rz > 0.0)) {
+                    breakdown = 1;
+                    break;
+                }
+                const double alpha = rz / pq;
+                acc = 0.0;
+#pragma unroll 8
+                for (int q = T; q < nd; q += FUSED_THREADS) {
+                    x[q] += alpha * pl[q];
+                    const double rq = r[q] - alpha * w.sy[q];
+                    r[q] = rq;
+                    acc += rq * rq;
+                }
+                rr = wg_sum(acc, w.red);
+                ++iters;
+                if (!(rr > tol2 * bb) || iters >= maxit) break;
+                z = wg_vcycle(w, M, ws);
+                acc = 0.0;
+#pragma unroll 8
+                for (int q = T; q < nd; q += FUSED_THREADS) acc += r[q] * z[q];
+                const double rzn = wg_sum(acc, w.red);
+                const double beta = rzn / rz;
+                rz = rzn;
+#pragma unroll 8
+                for (int q = T; q < nd; q += FUSED_THREADS) {
+                    const double pn = z[q] + beta * p[q];
+                    p[q] = pn;
+                    z[q] = pn;
+                }
+                __syncthreads();
+            }
+        }
+        rr = residual();  // of the current iterate, recomputed
+        const bool miss = bb > 0.0 && rr > tol2 * bb * 1.0201;  // (1.01 rtol)^2
+        if (!(miss && iters < maxit && !breakdown)) break;
+    }
+    if (T == 0) {
+        RhsState& S = st[rhs];
+        S.bb = bb;
+        S.rr = rr;
+        S.iters = iters;
+        S.breakdown = breakdown;
+        S.guess = guess;
+        S.active = 0;
+    }
+}
+
+}  // namespace
+
+void launch_fused_pcg(const FusedMeshDev* M, int nrhs, const double* b, double* x, RhsState* st, double* ws,
+                      bool has_x0, bool guard, hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL(k_fused_pcg, dim3(nrhs), dim3(FUSED_THREADS), 0, s, M, nrhs, b, x, st, ws, has_x0 ? 1 : 0,
+                       guard ? 1 : 0);
+}
+
 }  // namespace dg
+

@@ -556,3 +556,31 @@ def test_pair_densities_every_pair_and_subranges(gpu_lib):
     for first, count in ((-1, 2), (20, 9), (0, 29)):
         with pytest.raises(gpu_lib.DgError):
             gpu_lib.pair_densities(tphi, norb, first, count)
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if np.prod(c[0]) * (c[1] + 1) ** 3 <= 8192],
+                         ids=[f"E{c[0]}p{c[1]}" for c in CASES if np.prod(c[0]) * (c[1] + 1) ** 3 <= 8192])
+def test_fused_small_mesh_solve_matches_level_kernels(gpu_lib, case):
+    """With fused = 1, a mesh whose levels all have at most 8,192 nodes is solved in FP64 by one
+    launch, one work-group per right-hand side (the whole PCG and V-cycle in the kernel, fields in
+    LDS when they fit, else in global work space; both forms occur among these cases): the
+    potentials meet the bar against the exact solve at the parity tolerance, with the
+    level-by-level solver's iteration counts (+-1), for a batch of 20 over two lanes and with an
+    initial guess."""
+    mesh = _mesh(case)
+    dens = [_box_density(mesh, 90 + k) for k in range(20)]
+    out = {}
+    for fused in (1, 0):
+        ctx = _ctx(gpu_lib, [case], rtol=PARITY_RTOL, fused=fused)
+        rho, g = zip(*[gpu_sample(ctx, 0, d) for d in dens])
+        rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+        v, st = ctx.solve_batch(rho, g)
+        assert all(s_["status"] == 0 and s_["rel_residual"] <= PARITY_RTOL for s_ in st), fused
+        # the converged potentials as guesses: nothing left to do
+        v2, st2 = ctx.solve_batch(rho, g, x0=v)
+        assert all(s_["iters"] == 0 and s_["guess_used"] == 1 for s_ in st2), fused
+        out[fused] = (_n(v).reshape(len(dens), -1), [s_["iters"] for s_ in st])
+    for k in (0, 7, 19):
+        axes, _, _, b = oracle_density_problem(mesh, dens[k])
+        assert rel_l2_M(axes, mesh, out[1][0][k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
+    assert max(abs(a - b_) for a, b_ in zip(out[1][1], out[0][1])) <= 1
