@@ -39,6 +39,9 @@ METRIC = "Poisson RHS solved/sec at 1e-8 rel. residual: learned+mixed vs plain F
 OPERATING_RTOL = 1e-11
 POT_BAR, ENERGY_BAR = 1e-8, 1e-10
 HELDOUT_RHS = 128
+# arithmetic each precision mode computes in (the "dtype" field of the JSON line)
+DTYPE_OF = {"fp64": "f64", "fp32_ir": "f64 refinement + f32 inner PCG", "fp32_pc": "f64 CG + f32 V-cycle",
+            "bf16_pc": "f64 flexible CG + f32 V-cycle, bf16 matrix-core x/y contractions in level-0 smoothing"}
 
 
 def parse():
@@ -56,7 +59,7 @@ def parse():
                          "single: one two-Gaussian density on 4^3 elements p=3 (latency-bound); "
                          "quadrature: the exchange8 step with its Dirichlet data computed by quadrature")
     ap.add_argument("--arms", default="fp32_pc+learned,fp32_pc,fp64+learned,fp64,fp32_pc+untrained",
-                    help="precision fp32_pc, fp32_ir or fp64, optionally +learned (trained guess) or "
+                    help="precision fp32_pc, bf16_pc, fp32_ir or fp64, optionally +learned (trained guess) or "
                          "+untrained (the same network with random weights, a control); the first is the headline")
     ap.add_argument("--rtol", type=float, default=OPERATING_RTOL, help="FP64 relative residual of every arm")
     ap.add_argument("--metric-rtol", type=float, default=1e-8,
@@ -277,8 +280,7 @@ def main_pairs(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32_pc": "f64 CG + f32 V-cycle", "fp32_ir": "f64 refinement + f32 inner PCG",
-                  "fp64": "f64"}[prec],
+        "dtype": DTYPE_OF[prec],
         "data": "synthetic",
         "config": {"workload": workload_name(W, info, args.rtol), "arm": head_arm, "rtol": args.rtol,
                    "equal_accuracy": "every arm stops at the same FP64 relative residual; cpu leg checks "
@@ -553,7 +555,7 @@ def main_uneven(args):
         "metric": "Poisson RHS solved/sec (uneven batch over three meshes)",
         "value": head["value"], "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if head_arm == "fp64" else "f64+f32", "data": "synthetic",
+        "dtype": DTYPE_OF[head_arm.split("+")[0]], "data": "synthetic",
         "config": {"workload": f"uneven: 256 Gaussian-sum densities over 8^3, 12^3, 16^3 elements p=4 "
                                f"(86/85/85, interleaved), 4-level MG-PCG to {args.rtol:g}", "arm": head_arm,
                    "parallelism": "single GPU"},
@@ -651,7 +653,7 @@ def main_single(args):
         "metric": "Poisson RHS solved/sec at 1e-10 rel. residual (single RHS, latency-bound)",
         "value": head["value"], "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e-3 * head["us_per_solve"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if head_arm == "fp64" else "f64+f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": DTYPE_OF[head_arm.split("+")[0]], "data": "synthetic",
         "config": {"workload": "single: two-Gaussian density, 4^3 elements p=3 (4096 DOFs), 2-level MG-PCG to 1e-10",
                    "arm": head_arm, "parallelism": "single GPU"},
         "arms": results,
@@ -769,7 +771,7 @@ def main_quadrature(args):
         "metric": "Poisson RHS solved/sec, Dirichlet data by quadrature on the GPU",
         "value": npairs / dt_q, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * dt_q, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 data, " + ("f64" if prec == "fp64" else "f64+f32") + " solve", "data": "synthetic",
+        "dtype": "f64 data, " + DTYPE_OF[prec] + " solve", "data": "synthetic",
         "config": {"workload": f"quadrature: exchange8 step, {npairs} pair-density RHS, {mesh.E[0]}^3 elements "
                                f"p={mesh.p} ({ndof} DOFs, {nface} boundary nodes per RHS), Dirichlet data by "
                                f"quadrature, residual {args.rtol:g}", "arm": arm, "parallelism": "single GPU"},

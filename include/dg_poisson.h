@@ -84,8 +84,13 @@ typedef enum {
  * fields; the coarsest-grid solve in FP64 arithmetic).  The iterate is FP64
  * CG's, so a solve stopped at a residual tolerance has the accuracy of an
  * FP64 solve stopped there, while most bytes moved are the V-cycle's FP32
- * ones. */
-typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_IR = 1, DG_PREC_FP32_PC = 2 } dg_precision;
+ * ones.
+ * BF16_PC: FP32_PC whose finest-level smoothing steps compute their x and y
+ * line contractions on the matrix cores with BF16 operands and FP32
+ * accumulation (degree-4 meshes; other degrees run the FP32 kernels).  The
+ * preconditioner is then no longer exactly symmetric, so the FP64 CG takes
+ * the flexible (Polak-Ribiere) beta. */
+typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_IR = 1, DG_PREC_FP32_PC = 2, DG_PREC_BF16_PC = 3 } dg_precision;
 
 /* A uniform hexahedral mesh: ne[d] elements along axis d on [lo[d], hi[d]],
  * Gauss-Lobatto nodal polynomials of degree p (1 <= p <= 7). */
@@ -277,6 +282,13 @@ dg_status dg_operator_apply_f32(dg_ctx* ctx, int mesh_id, int level, int nrhs, c
                                 hipStream_t stream);
 dg_status dg_vcycle_apply_f32(dg_ctx* ctx, int mesh_id, int level, int nrhs, const float* r, float* z,
                               hipStream_t stream);
+/* y = A u with FP32 fields and the x and y line contractions on the matrix
+ * cores (BF16 operands, FP32 accumulation; the z contraction in FP32 on the
+ * vector units), as the smoothing steps of DG_PREC_BF16_PC run it.  Only
+ * levels of degree 4; DG_ERR_ARG for others.  Layout, ownership and errors
+ * as dg_operator_apply_f32. */
+dg_status dg_operator_apply_mfma(dg_ctx* ctx, int mesh_id, int level, int nrhs, const float* u, float* y,
+                                 hipStream_t stream);
 /* Coarsest-level exact solve z = A^{-1} r (fast diagonalisation). */
 dg_status dg_coarse_solve(dg_ctx* ctx, int mesh_id, int nrhs, const double* r, double* z, hipStream_t stream);
 /* Transfers between `level` and `level`+1: rc = P^T r (restriction of a

@@ -17,8 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("DG_POISSON_LIB", os.path.join(_HERE, "libdgpoisson.so"))
 
 DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
-DG_PREC_FP64, DG_PREC_FP32_IR, DG_PREC_FP32_PC = 0, 1, 2
-PRECISIONS = {"fp64": DG_PREC_FP64, "fp32_ir": DG_PREC_FP32_IR, "fp32_pc": DG_PREC_FP32_PC}
+DG_PREC_FP64, DG_PREC_FP32_IR, DG_PREC_FP32_PC, DG_PREC_BF16_PC = 0, 1, 2, 3
+PRECISIONS = {"fp64": DG_PREC_FP64, "fp32_ir": DG_PREC_FP32_IR, "fp32_pc": DG_PREC_FP32_PC,
+              "bf16_pc": DG_PREC_BF16_PC}
 
 
 class DgMesh(ctypes.Structure):
@@ -61,6 +62,7 @@ def _load():
         "dg_exchange_apply": (I, [P, I, I, P, P, P, P, P, P, P, P]),
         "dg_operator_apply": (I, [P, I, I, I, P, P, P]),
         "dg_operator_apply_f32": (I, [P, I, I, I, P, P, P]),
+        "dg_operator_apply_mfma": (I, [P, I, I, I, P, P, P]),
         "dg_vcycle_apply_f32": (I, [P, I, I, I, P, P, P]),
         "dg_rhs_assemble": (I, [P, I, I, P, P, P, P]),
         "dg_boundary_data": (I, [P, I, I, P, P, P]),
@@ -191,7 +193,7 @@ class Context:
     """A set-up DG Poisson solver for one or more uniform meshes.
 
     meshes: list of (ne, p, lo, hi) with ne, lo, hi 3-sequences.
-    options: fields of dg_opts (precision may be "fp64", "fp32_ir" or "fp32_pc").
+    options: fields of dg_opts (precision may be "fp64", "fp32_ir", "fp32_pc" or "bf16_pc").
     """
 
     def __init__(self, meshes, **options):
@@ -299,6 +301,14 @@ class Context:
         fn = lib.dg_operator_apply_f32 if f32 else lib.dg_operator_apply
         pt = (lambda t: _ptr_t(t, torch.float32)) if f32 else _ptr
         _check(fn(self._h, mesh_id, level, nrhs, pt(u), pt(y), _stream()), "operator_apply")
+        return y
+
+    def operator_apply_mfma(self, u, mesh_id=0, level=0):
+        """y = A u (FP32 fields) with the x and y contractions on the matrix cores (BF16 operands)."""
+        nrhs = u.numel() // self._level_dofs(mesh_id, level)
+        y = torch.empty_like(u)
+        _check(lib.dg_operator_apply_mfma(self._h, mesh_id, level, nrhs, _ptr_t(u, torch.float32),
+                                          _ptr_t(y, torch.float32), _stream()), "operator_apply_mfma")
         return y
 
     def rhs_assemble(self, rho, g, mesh_id=0):

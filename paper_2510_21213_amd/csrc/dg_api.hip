@@ -120,21 +120,21 @@ struct dg_ctx {
         dg::RhsState* st_in = nullptr;   // inner FP32 state
         dg::RhsState* st_host = nullptr; // pinned host mirror
         int cap_b = 0, cap_st = 0;
-        // captured PCG iterations, per kind of run (index 0: FP64, 1: FP32 inner solve, 2: FP32_PC)
+        // captured PCG iterations, per kind of run (index 0: FP64, 1: FP32 inner solve, 2: FP32_PC, 3: BF16_PC)
         struct Graph {
             hipGraphExec_t exec = nullptr;
             int nrhs = 0, every = 0;
             bool prof = false;
             std::vector<hipEvent_t> ev;
             size_t nev = 0;
-        } graph[3];
+        } graph[4];
         // multi-mesh batches: the mesh's own stream and completion event, and its
         // right-hand sides gathered from the caller's packing when they are not contiguous
         hipStream_t stream = nullptr;
         hipEvent_t ev_done = nullptr;
         // iterations the k-th PCG run of the last solve needed (per kind of run): the next
         // solve replays that many before its first host check
-        std::vector<int> pred[3];
+        std::vector<int> pred[4];
         // timing events of eager launches driven by this solver instance
         std::vector<hipEvent_t> pev;
         size_t pused = 0;
@@ -253,10 +253,11 @@ void ensure_work(Mesh& M, Work<T>& W, int nrhs, int parts = WK_ALL) {
     }
 }
 
-// Work space of an FP32_PC solve: FP64 PCG vectors, an FP32 V-cycle with its FP32 source.
-void ensure_work_pc(Mesh& M, int nrhs) {
+// Work space of an FP32_PC or BF16_PC solve: FP64 PCG vectors, an FP32 V-cycle with its FP32 source
+// (flexible: two of them, the current and the previous).
+void ensure_work_pc(Mesh& M, int nrhs, bool flex = false) {
     ensure_work<double>(M, M.w64, nrhs, WK_R | WK_PCG | (dg::has_pq_mixed(M.lv[0]) ? 0 : WK_TMP));
-    ensure_work<float>(M, M.w32, nrhs, WK_R | WK_LV);
+    ensure_work<float>(M, M.w32, nrhs, WK_R | WK_LV | (flex ? WK_TMP : 0));
 }
 
 void ensure_b(Mesh& M, int nrhs, bool need_r64) {
@@ -320,9 +321,11 @@ void prof_sum(const std::vector<hipEvent_t>& ev, size_t used) {
     }
 }
 
+// mf: the level-0 smoothing steps take their x and y contractions on the matrix cores (FP32
+// fields only, where the level has such a kernel).
 template <typename T>
 T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T* f, bool z1_ready, bool dot,
-          hipStream_t s) {
+          hipStream_t s, bool mf = false) {
     const bool timed = l == 0 && g_prof && g_prof->on;
     const int L = (int)M.lv.size();
     const LevelHost& Lv = M.lv[l];
@@ -336,10 +339,18 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
     if (!z1_ready) dg::launch_cheb0<T>(Lv, dv, nrhs, st, f, W.za[l], C.c0, s);
     T* cur = W.za[l];
     T* prev = W.zb[l];
+    const bool mf0 = mf && l == 0;
+    // one smoothing step: on the matrix cores where asked for and available, else the FP32/FP64 kernel
+    auto step = [&](int mode, const T* u, const T* zp, T* out, double cp, double cr) {
+        if constexpr (sizeof(T) == 4) {
+            if (mf0 && dg::launch_brick_mf(mode, Lv, dv, nrhs, st, u, f, zp, out, M.partial, M.pstride, cp, cr, s))
+                return;
+        }
+        dg::launch_brick<T>(mode, Lv, dv, nrhs, st, u, nullptr, f, zp, out, nullptr, M.partial, M.pstride, cp, cr, s);
+    };
     for (int k = 1; k < m; ++k) {
         if (timed) prof_mark(s);
-        dg::launch_brick<T>(dg::BM_CHEB, Lv, dv, nrhs, st, cur, nullptr, f, k == 1 ? nullptr : prev, prev, nullptr,
-                            nullptr, 0, C.cp[k - 1], C.cr[k - 1], s);
+        step(dg::BM_CHEB, cur, k == 1 ? nullptr : prev, prev, C.cp[k - 1], C.cr[k - 1]);
         if (timed) prof_mark(s);
         std::swap(cur, prev);
     }
@@ -355,8 +366,7 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
         const double cp = k == 0 ? 0.0 : C.cp[k - 1];
         const double cr = k == 0 ? C.c0 : C.cr[k - 1];
         if (timed) prof_mark(s);
-        dg::launch_brick<T>(mode, Lv, dv, nrhs, st, cur, nullptr, f, k == 0 ? nullptr : prev, prev, nullptr,
-                            M.partial, M.pstride, cp, cr, s);
+        step(mode, cur, k == 0 ? nullptr : prev, prev, cp, cr);
         if (timed) prof_mark(s);
         std::swap(cur, prev);
     }
@@ -390,24 +400,34 @@ void pcg_iteration(Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, int parity, 
 // One PCG iteration of FP32_PC: the PCG vectors, the operator of the search direction and all dot
 // products in FP64 (W); the V-cycle preconditioner in FP32 (M.w32, whose level-0 residual r32 and
 // first smoothing iterate the update step writes).
-void pcg_iteration_pc(Mesh& M, Work<double>& W, int nrhs, dg::RhsState* st, int parity, hipStream_t s) {
+// flex (BF16_PC): the smoothing steps of level 0 on the matrix cores, and the flexible (Polak-Ribiere)
+// beta, for which the FP32 residual alternates between two buffers so that the previous one is
+// still there for z.r_old.
+void pcg_iteration_pc(Mesh& M, Work<double>& W, int nrhs, dg::RhsState* st, int parity, hipStream_t s,
+                      bool flex = false) {
     const LevelHost& L0 = M.lv[0];
     Work<float>& V = M.w32;
     const int nb_rz = dg::op_blocks<float>(L0, dg::BM_CHEBDOT), nb = dg::op_blocks<double>(L0, dg::BM_PQ);
     const int nc = dg::chunks_of(L0.ndof);
-    float* z = vcycle<float>(M, V, 0, nrhs, st, V.r, true, true, s);
+    float* rcur = (flex && parity) ? V.tmp : V.r;
+    float* rnext = flex ? (parity ? V.r : V.tmp) : V.r;
+    float* z = vcycle<float>(M, V, 0, nrhs, st, rcur, true, true, s, flex);
     if (M.lv.size() == 1) {
         // the preconditioner was the exact solve alone: no smoothing step wrote the r.z partial sums
-        dg::launch_dot<float, float>(L0.ndof, nrhs, st, V.r, z, M.partial, M.pstride, s);
+        dg::launch_dot<float, float>(L0.ndof, nrhs, st, rcur, z, M.partial, M.pstride, s);
         dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nc, s);
     } else {
         dg::launch_finalize(dg::FIN_RZ, nrhs, st, M.partial, M.pstride, nb_rz, s);
+    }
+    if (flex) {
+        dg::launch_dot<float, float>(L0.ndof, nrhs, st, rnext, z, M.partial, M.pstride, s);  // z . r_old
+        dg::launch_finalize(dg::FIN_FLEX, nrhs, st, M.partial, M.pstride, nc, s);
     }
     double* pold = parity ? W.p1 : W.p0;
     double* pnew = parity ? W.p0 : W.p1;
     dg::launch_pq_mixed(L0, L0.dev64, nrhs, st, z, pold, W.q, pnew, W.tmp, M.partial, M.pstride, s);
     dg::launch_finalize(dg::FIN_PQ, nrhs, st, M.partial, M.pstride, nb, s);
-    dg::launch_update_pc(L0, L0.dev64, nrhs, st, W.x, W.r, pnew, W.q, V.r, V.za[0], M.cheb[0].c0, M.partial,
+    dg::launch_update_pc(L0, L0.dev64, nrhs, st, W.x, W.r, pnew, W.q, rnext, V.za[0], M.cheb[0].c0, M.partial,
                          M.pstride, s);
     dg::launch_finalize(dg::FIN_RR, nrhs, st, M.partial, M.pstride, nc, s);
 }
@@ -437,7 +457,8 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
     static_assert(!PC || sizeof(T) == 8, "FP32_PC runs its PCG in FP64");
     const LevelHost& L0 = M.lv[0];
     const int nc = dg::chunks_of(L0.ndof);
-    const int kind = PC ? 2 : (sizeof(T) == 8 ? 0 : 1);
+    const bool flex = PC && ctx->opts.precision == DG_PREC_BF16_PC;
+    const int kind = PC ? (flex ? 3 : 2) : (sizeof(T) == 8 ? 0 : 1);
     const size_t vbytes = PC ? sizeof(float) : sizeof(T);  // element size of the V-cycle's fields
     // rr and the active flags
     dg::launch_dot<T, T>(L0.ndof, nrhs, gate, W.r, W.r, M.partial, M.pstride, s);
@@ -451,7 +472,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
     dg::launch_fill<T>(W.p1, (T)0, L0.ndof * nrhs, s);
     auto iteration = [&](int parity) {
         if constexpr (PC)
-            pcg_iteration_pc(M, W, nrhs, st, parity, s);
+            pcg_iteration_pc(M, W, nrhs, st, parity, s, flex);
         else
             pcg_iteration<T>(M, W, nrhs, st, parity, s);
     };
@@ -738,10 +759,10 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
             outer[i] = 1;
             if (x0) kept[i] = M.st_host[i].guess;
         }
-    } else if (o.precision == DG_PREC_FP64 || o.precision == DG_PREC_FP32_PC) {
-        const bool pc = o.precision == DG_PREC_FP32_PC;
+    } else if (o.precision == DG_PREC_FP64 || o.precision == DG_PREC_FP32_PC || o.precision == DG_PREC_BF16_PC) {
+        const bool pc = o.precision != DG_PREC_FP64;
         if (pc)
-            ensure_work_pc(M, nrhs);
+            ensure_work_pc(M, nrhs, o.precision == DG_PREC_BF16_PC);
         else
             ensure_work<double>(M, M.w64, nrhs);
         Work<double>& W = M.w64;
@@ -915,8 +936,8 @@ void prepare_lane(dg_ctx* ctx, Mesh& M, int cnt) {
         ensure_fused_ws(M, cnt);
     else if (prec == DG_PREC_FP32_IR)
         ensure_work<float>(M, M.w32, cnt);
-    else if (prec == DG_PREC_FP32_PC)
-        ensure_work_pc(M, cnt);
+    else if (prec == DG_PREC_FP32_PC || prec == DG_PREC_BF16_PC)
+        ensure_work_pc(M, cnt, prec == DG_PREC_BF16_PC);
     else
         ensure_work<double>(M, M.w64, cnt);
 }
@@ -1244,7 +1265,8 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
         if (o.cheb_degree < 1 || o.cheb_degree_h < 0 || o.cheb_ratio <= 1.0 || o.cheb_safety < 1.0 || o.lanczos_steps < 2 ||
             o.penalty_eps <= 0 || o.rtol <= 0 || o.max_iter < 1 || o.max_outer < 1 || o.inner_rtol <= 0 ||
             o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 2 ||
-            (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_IR && o.precision != DG_PREC_FP32_PC))
+            (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_IR && o.precision != DG_PREC_FP32_PC &&
+             o.precision != DG_PREC_BF16_PC))
             throw ArgError("invalid solver options");
         HIPCHK(hipGetDevice(&ctx->device));
         HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
@@ -1768,6 +1790,22 @@ dg_status dg_operator_apply_f32(dg_ctx* ctx, int mesh_id, int level, int nrhs, c
         const auto& L = M.lv[level];
         dg::launch_brick<float>(dg::BM_APPLY, L, L.dev32, nrhs, nullptr, u, nullptr, nullptr, nullptr, y, nullptr,
                                 nullptr, 0, 0, 0, stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_operator_apply_mfma(dg_ctx* ctx, int mesh_id, int level, int nrhs, const float* u, float* y,
+                                 hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        auto& M = ctx->meshes[mesh_id];
+        if (level < 0 || level >= (int)M.lv.size()) throw ArgError("level out of range");
+        if (nrhs < 0 || (nrhs > 0 && (!u || !y))) throw ArgError("bad arguments");
+        if (nrhs == 0) return;
+        const auto& L = M.lv[level];
+        if (!dg::launch_brick_mf(dg::BM_APPLY, L, L.dev32, nrhs, nullptr, u, nullptr, nullptr, y, nullptr, 0, 0, 0,
+                                 stream))
+            throw ArgError("no matrix-core operator kernel for this level (degree 4 only)");
         HIPCHK(hipGetLastError());
     });
 }

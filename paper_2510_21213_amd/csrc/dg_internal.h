@@ -84,6 +84,7 @@ struct RhsState {
     double bb;      // ||b||^2
     double rz;      // r.z of this iteration
     double rz_old;  // r.z of the previous iteration
+    double rz_prev; // flexible CG: r.z of the iteration before (the denominator of Polak-Ribiere beta)
     double pq;      // p.Ap
     double rr;      // r.r
     double alpha, beta;

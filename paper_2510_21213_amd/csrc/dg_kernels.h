@@ -25,7 +25,8 @@ enum FinalizeWhat {
     FIN_PQ = 3,    // alpha = rz/s (breakdown if s <= 0)
     FIN_RR = 4,    // rr = s; iters++; active = rr > tol2 bb and iters < maxit
     FIN_TRUE = 5,  // rr_true = s (FP64 residual of the returned solution)
-    FIN_OUTER = 6  // outer refinement: rr = s; scale = sqrt(s); active = rr > tol2 bb
+    FIN_OUTER = 6, // outer refinement: rr = s; scale = sqrt(s); active = rr > tol2 bb
+    FIN_FLEX = 7   // flexible CG after FIN_RZ, s = z.r_old: beta = (rz - s) / rz_prev (0 on the first iteration)
 };
 
 struct KernelCfg {
@@ -55,6 +56,13 @@ void launch_brick(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs
 template <typename T>
 void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHost& Lc, const LevelDev<T>* devc,
                      int nrhs, const RhsState* st, const T* z, const T* f, T* fc, T* z1c, double c0c, hipStream_t s);
+
+// The FP32 operator step with its x and y line contractions on the matrix cores (BF16 operands,
+// FP32 accumulation; modes BM_APPLY, BM_CHEB, BM_CHEBDOT).  False (nothing launched) where the
+// level has no such kernel (degree 4 on 4 x 2 tiles only).
+bool launch_brick_mf(int mode, const LevelHost& L, const LevelDev<float>* dev, int nrhs, const RhsState* st,
+                     const float* u, const float* f, const float* zprev, float* out, double* partial, int pstride,
+                     double cp, double cr, hipStream_t s);
 
 // FP32_PC step of the FP64 PCG: p = z + beta p_old with z the FP32 V-cycle output, q = A p and
 // partial sums of p.q, all in FP64.  tmp: an FP64 field buffer used only on levels whose degree

@@ -470,6 +470,7 @@ struct SlabArgs {
     T* z1c;
     long long ndofc;
     T c0c;
+    const T* dinvc;  // BM_RESTRICT: inverse diagonal of the coarse level (its first smoothing iterate)
 };
 
 // Coefficients of the interior block in the even/odd form of RefDev (symmetric
@@ -672,7 +673,149 @@ __device__ __forceinline__ void load_col(T* v, brsrc ru, brsrc ru2, uint32_t vof
     }
 }
 
-template <typename T, int N, int TX, int TY, int MODE>
+// ---- x and y terms on the matrix cores (BF16 operands, FP32 accumulation) ----------------
+// For one axis, the element line's N outputs are one matrix-vector product with the 15-vector of
+// the line and its two neighbour lines along the axis: acc = [C_L | B | C_R] (left, own, right),
+// the reference-element form of elem_op (C_L and C_R carry the face couplings, rank 2 each).
+// Sixteen lines make the columns of one v_mfma_f32_16x16x16_bf16 (K = 16 >= 3N = 15); the same
+// 16 x 16 matrix (rows >= N and column 15 zero) serves every line of the level and both axes.
+// Lines next to a domain face read ghost neighbour lines (mf_ghosts) that reproduce the Nitsche
+// terms through the same couplings.
+typedef short mf_s4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ short mf_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+// Entry (i, k) of [C_L | B | C_R] in reference units.
+template <int N>
+__device__ __forceinline__ float mf_coef(const RefDev<float>& R, int i, int k) {
+    if (i >= N || k >= 3 * N) return 0.f;
+    const int blk = k / N, l = k - blk * N;
+    const float aRi = -R.aL[N - 1 - i];
+    if (blk == 1) return R.B[i][l];
+    if (blk == 0) {  // left neighbour: U = its value at the right end, Dv = aR . its line
+        const float aRl = -R.aL[N - 1 - l];
+        float v = (l == N - 1) ? -0.5f * R.aL[i] : 0.f;
+        if (i == 0) v += 0.5f * aRl - (l == N - 1 ? R.sig : 0.f);
+        return v;
+    }
+    // right neighbour: U0 = its value at the left end, D0 = aL . its line
+    float v = (l == 0) ? 0.5f * aRi : 0.f;
+    if (i == N - 1) v -= 0.5f * R.aL[l] + (l == 0 ? R.sig : 0.f);
+    return v;
+}
+
+// Ghost neighbour lines of the element lines next to a domain face, written into the staging
+// rows: a line g with g at the far end and one more entry chosen so that the couplings of the
+// line see the ghost value U and derivative D of the Nitsche form (elem_op's ghost data).
+template <int N, int TX, int TY>
+__device__ __forceinline__ void mf_ghosts(const SlabCoef<float, N>& c, float* su, int tx0, int ty0, int E0,
+                                          int E1) {
+    constexpr int NX = TX * N, NY = TY * N, RS = NX + 2 * N, PS = RS * (NY + 2 * N);
+    const int nvx = min(TX, E0 - tx0), nvy = min(TY, E1 - ty0);  // valid elements of the tile per axis
+    const bool lx = tx0 == 0, rx = tx0 + TX >= E0, ly = ty0 == 0, ry = ty0 + TY >= E1;
+    const int t = threadIdx.x;
+    // tasks: x rows (NY * N) and y columns (NX * N), each on its left and right side
+    const int nx_tasks = 2 * NY * N, ny_tasks = 2 * NX * N;
+    for (int q = t; q < nx_tasks + ny_tasks; q += blockDim.x) {
+        int base, stride, first, side, ok;
+        if (q < nx_tasks) {
+            side = q & 1;
+            const int row = q >> 1, Yr = row % NY, kr = row / NY;
+            ok = (side ? rx : lx) && (Yr / N) < nvy;
+            base = kr * PS + (Yr + N) * RS;
+            stride = 1;
+            first = side ? N + (nvx - 1) * N : N;  // the boundary element's line
+        } else {
+            const int q2 = q - nx_tasks;
+            side = q2 & 1;
+            const int col = q2 >> 1, Xc = col % NX, kr = col / NX;
+            ok = (side ? ry : ly) && (Xc / N) < nvx;
+            base = kr * PS + Xc + N;
+            stride = RS;
+            first = side ? N + (nvy - 1) * N : N;
+        }
+        if (!ok) continue;
+        float A[N];
+#pragma unroll
+        for (int l = 0; l < N; ++l) A[l] = su[base + (first + l) * stride];
+        float g[N];
+#pragma unroll
+        for (int l = 0; l < N; ++l) g[l] = 0.f;
+        if (!side) {  // left ghost: U = -A_0, Dv = aL.A - 2 sig A_0; g = (g0, 0, ..., 0, U)
+            const float U = -A[0], Dv = face_l(c, A) - 2.f * c.sig * A[0];
+            g[N - 1] = U;
+            g[0] = -(Dv + c.aL[0] * U) / c.aL[N - 1];
+        } else {      // right ghost: U0 = -A_p, D0 = aR.A + 2 sig A_p; g = (U0, 0, ..., 0, gp)
+            const float U0 = -A[N - 1], D0 = face_r(c, A) + 2.f * c.sig * A[N - 1];
+            g[0] = U0;
+            g[N - 1] = (D0 - c.aL[0] * U0) / c.aL[N - 1];
+        }
+        const int gpos = side ? first + N : first - N;
+#pragma unroll
+        for (int l = 0; l < N; ++l) su[base + (gpos + l) * stride] = g[l];
+    }
+}
+
+// x and y terms of the layer staged in su into sxy (same layout as pair_row's output), on the
+// matrix cores.  Lines of elements outside the mesh produce values nobody reads.
+template <int N, int TX, int TY>
+__device__ __forceinline__ void mf_xy_terms(const RefDev<float>& R, const mf_s4& Aop, const float* su, float* sxy) {
+    constexpr int NX = TX * N, NY = TY * N, RS = NX + 2 * N, PS = RS * (NY + 2 * N), OR = NX, OP = OR * NY;
+    constexpr int NLX = NY * N * TX, NLY = NX * N * TY;       // element lines per axis in the layer
+    constexpr int NBX = (NLX + 15) / 16, NBY = (NLY + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int n = lane & 15, kq = (lane >> 4) * 4;           // column of B, first of its 4 K rows
+    for (int blk = wave; blk < NBX + NBY; blk += nwaves) {
+        const bool xa = blk < NBX;
+        const int lam = (xa ? blk : blk - NBX) * 16 + n;    // this lane's line
+        const int nlines = xa ? NLX : NLY;
+        const bool lv = lam < nlines;
+        int base = 0, stride = 1, obase = 0, ostride = 1;
+        float sc = 0.f;
+        if (lv) {
+            if (xa) {  // x line: row (Yr, kr), element e
+                const int row = lam / TX, e = lam % TX, Yr = row % NY, kr = row / NY;
+                base = kr * PS + (Yr + N) * RS + e * N;
+                stride = 1;
+                obase = kr * OP + Yr * OR + e * N;
+                ostride = 1;
+                sc = R.scale[0] * R.w[Yr % N] * R.w[kr];
+            } else {   // y line: column (Xc, kr), element e
+                const int col = lam / TY, e = lam % TY, Xc = col % NX, kr = col / NX;
+                base = kr * PS + e * N * RS + Xc + N;
+                stride = RS;
+                obase = N * OP + kr * OP + e * N * OR + Xc;
+                ostride = OR;
+                sc = R.scale[1] * R.w[Xc % N] * R.w[kr];
+            }
+        }
+        mf_s4 b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = kq + j;
+            b[j] = (lv && k < 3 * N) ? mf_bf16(su[base + k * stride]) : (short)0;
+        }
+        mf_f4 d = {0.f, 0.f, 0.f, 0.f};
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Aop, b, d, 0, 0, 0);
+        // d[j] = output node kq + j of line n: lines are this lane's column, so swap the roles:
+        // lane (n, kq) holds rows kq..kq+3 of column n
+        if (lv) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = kq + j;
+                if (i < N) sxy[obase + i * ostride] = d[j] * sc;
+            }
+        }
+    }
+}
+
+template <typename T, int N, int TX, int TY, int MODE, bool MF = false>
 __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr int NX = TX * N, NY = TY * N, NT = NX * NY, N2 = N * N, N3 = N2 * N;
     constexpr int WG = wg_of(NT);
@@ -726,6 +869,13 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     const RefDev<T>& R = a.L->ref;
     SlabCoef<T, N> c;
     load_coef(c, R);
+    mf_s4 mfA = {0, 0, 0, 0};
+    if constexpr (MF) {
+        static_assert(sizeof(T) == 4 && 3 * N <= 16, "matrix-core x/y terms: FP32 fields, at most 5 nodes per edge");
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mfA[j] = mf_bf16(mf_coef<N>(R, lane & 15, (lane >> 4) * 4 + j));
+    }
 
     const int t = threadIdx.x;
     const bool tact = t < NT;
@@ -860,12 +1010,20 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
             }
         }
         __syncthreads();
-        // x and y terms of element pairs
-        if (pok) {
-            if (isx)
-                pair_row<T, N, 1, 1>(c, su, pb, sxy, ob, pe, E0, psc);
-            else
-                pair_row<T, N, RS, OR>(c, su, pb, sxy, ob, pe, E1, psc);
+        // x and y terms of element pairs (MF: of element lines, on the matrix cores)
+        if constexpr (MF) {
+            if (tx0 == 0 || ty0 == 0 || tx0 + TX >= E0 || ty0 + TY >= E1) {  // uniform in the work-group
+                mf_ghosts<N, TX, TY>(c, su, tx0, ty0, E0, E1);
+                __syncthreads();
+            }
+            mf_xy_terms<N, TX, TY>(R, mfA, su, sxy);
+        } else {
+            if (pok) {
+                if (isx)
+                    pair_row<T, N, 1, 1>(c, su, pb, sxy, ob, pe, E0, psc);
+                else
+                    pair_row<T, N, RS, OR>(c, su, pb, sxy, ob, pe, E1, psc);
+            }
         }
         // z term of the column
         T zacc[N];
@@ -962,14 +1120,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                 const long long idx =
                     (long long)rhs * a.ndofc + ((long long)(ez * E1 + eyo) * E0 + exo) * NC3 + loc;
                 a.fc[idx] = s;
-                if (a.z1c) {
-                    const LevelDev<T>& Lc = *a.Lc;
-                    const int cx = etype(exo, E0), cy = etype(eyo, E1), czt = etype(ez, E2);
-                    const T mx = Lc.ax[0].m[ca], my = Lc.ax[1].m[cb], mz = Lc.ax[2].m[cz];
-                    const T D = Lc.ax[0].Bd[cx][ca] * my * mz + mx * Lc.ax[1].Bd[cy][cb] * mz +
-                                mx * my * Lc.ax[2].Bd[czt][cz];
-                    a.z1c[idx] = a.c0c * s / D;
-                }
+                if (a.z1c) a.z1c[idx] = a.c0c * s * a.dinvc[idx - (long long)rhs * a.ndofc];
             }
         }
 #pragma unroll
@@ -1137,9 +1288,21 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
                         const T* u, const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial,
                         int pstride, double cp, double cr, hipStream_t s, const LevelHost* Lc = nullptr,
                         const LevelDev<T>* devc = nullptr, T* fc = nullptr, T* z1c = nullptr, double c0c = 0,
-                        const float* uf = nullptr) {
-    const SlabGeom g = slab_geom<T>(L, mode);
+                        const float* uf = nullptr, bool mf = false) {
+    SlabGeom g = slab_geom<T>(L, mode);
+    if (mf && mode == BM_APPLY && L.n == 5) {  // no partial sums: the smoothing steps' 4 x 2 tile, 4 layers
+        g.tx = 4;
+        g.ty = 2;
+        g.nt0 = (L.E[0] + 3) / 4;
+        g.nt1 = (L.E[1] + 1) / 2;
+        g.zlen = std::min(4, L.E[2]);
+        g.nzc = (L.E[2] + g.zlen - 1) / g.zlen;
+    }
     if (!g.tx) return false;
+    // the matrix-core form exists for FP32 fields of degree 4 on 4 x 2 tiles
+    if (mf && !(sizeof(T) == 4 && L.n == 5 && g.tx == 4 && g.ty == 2 &&
+                (mode == BM_APPLY || mode == BM_CHEB || mode == BM_CHEBDOT)))
+        return false;
     if (mode == BM_RESTRICT && L.n != 3 && L.n != 5) return false;
     SlabArgs<T> a;
     a.Lc = devc;
@@ -1147,6 +1310,10 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
     a.fc = fc;
     a.z1c = z1c;
     a.ndofc = Lc ? Lc->ndof : 0;
+    if constexpr (sizeof(T) == 8)
+        a.dinvc = Lc ? Lc->dinv64 : nullptr;
+    else
+        a.dinvc = Lc ? Lc->dinv32 : nullptr;
     a.c0c = (T)c0c;
     a.L = dev;
     a.E0 = L.E[0]; a.E1 = L.E[1]; a.E2 = L.E[2];
@@ -1163,6 +1330,17 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
     if (grid == 0) return true;
     // the kernel unrolls its z loop over at most slab_zmax(n) layers
     if (g.zlen > slab_zmax(L.n)) throw std::logic_error("slab chunk longer than the kernel's z loop");
+    if constexpr (sizeof(T) == 4) {
+        if (mf) {
+            constexpr int WG = wg_of(4 * 2 * 5 * 5);
+            switch (mode) {
+                case BM_APPLY: hipLaunchKernelGGL((k_slab<float, 5, 4, 2, BM_APPLY, true>), dim3(grid), dim3(WG), 0, s, a); break;
+                case BM_CHEB: hipLaunchKernelGGL((k_slab<float, 5, 4, 2, BM_CHEB, true>), dim3(grid), dim3(WG), 0, s, a); break;
+                case BM_CHEBDOT: hipLaunchKernelGGL((k_slab<float, 5, 4, 2, BM_CHEBDOT, true>), dim3(grid), dim3(WG), 0, s, a); break;
+            }
+            return true;
+        }
+    }
     if (g.tx == 8 && g.ty == 8 && L.n == 2) slab_dispatch<T, 2, 8, 8>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 4 && L.n == 3) slab_dispatch<T, 3, 4, 4>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 2 && L.n == 5) slab_dispatch<T, 5, 4, 2>(mode, a, grid, s);
@@ -1200,6 +1378,13 @@ void launch_brick(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs
         case 7: brick_dispatch<T, 7, be_of<7>()>(mode, a, grid, s); break;
         case 8: brick_dispatch<T, 8, be_of<8>()>(mode, a, grid, s); break;
     }
+}
+
+bool launch_brick_mf(int mode, const LevelHost& L, const LevelDev<float>* dev, int nrhs, const RhsState* st,
+                     const float* u, const float* f, const float* zprev, float* out, double* partial, int pstride,
+                     double cp, double cr, hipStream_t s) {
+    return launch_slab<float>(mode, L, dev, nrhs, st, u, nullptr, f, zprev, out, nullptr, partial, pstride, cp, cr, s,
+                              nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, true);
 }
 
 __global__ __launch_bounds__(256) void k_widen(const float* __restrict__ a, double* __restrict__ b, long long n) {
@@ -1964,7 +2149,7 @@ __global__ __launch_bounds__(256) void k_finalize(int what, RhsState* st, const 
     __shared__ double red[256];
     const int rhs = blockIdx.x;
     RhsState& S = st[rhs];
-    const bool gated = (what == FIN_RZ || what == FIN_PQ || what == FIN_RR);
+    const bool gated = (what == FIN_RZ || what == FIN_PQ || what == FIN_RR || what == FIN_FLEX);
     if (gated && !S.active) return;
     double acc = 0.0;
     const double* p = partial + (long long)rhs * pstride;
@@ -1987,8 +2172,12 @@ __global__ __launch_bounds__(256) void k_finalize(int what, RhsState* st, const 
             break;
         case FIN_RZ:
             S.beta = (S.iters == 0) ? 0.0 : s / S.rz_old;
+            S.rz_prev = S.rz_old;
             S.rz = s;
             S.rz_old = s;
+            break;
+        case FIN_FLEX:
+            S.beta = (S.iters == 0) ? 0.0 : (S.rz - s) / S.rz_prev;
             break;
         case FIN_PQ:
             S.pq = s;

@@ -11,7 +11,10 @@ forward/backward, A-norm loss, Adam); this script only feeds batches.
 
 With --workload large the molecules follow the 32^3-element recipe instead
 (16-32 atoms in [-8,8]^3 on the degree-4 mesh of [-16,16]^3, 5 levels; seeds
-50000+i, held out 90000+i), and --init starts from existing weights.
+50000+i, held out 90000+i), and --init starts from existing weights.  With
+--stream K the training set is generated on the GPU K molecules at a time and
+discarded after one pass (556 molecules, 20,016 pairs per epoch, would need
+about a terabyte stored).
 
 Writes the weights (dg_net_save format) and a JSON report with the held-out
 evaluation: mean PCG iterations to 1e-8 with and without the guess, and with
@@ -46,10 +49,11 @@ def molecule(seed, n_atoms=8, norb=8):
 
 
 def pair_data(ctx, orb, xyz, fxyz):
-    """Pair densities (device, packed) and their Dirichlet data (device, packed)."""
-    phi = torch.as_tensor(orb.values(xyz[0], xyz[1], xyz[2])).cuda()
-    rho = torch.stack([phi[i] * phi[j] for i, j in orb.pairs()]).reshape(-1).contiguous()
-    g = torch.as_tensor(orb.pair_potentials(fxyz[0], fxyz[1], fxyz[2]).reshape(-1)).cuda()
+    """Pair densities (device, packed, formed by the library's pair-density kernel) and their
+    closed-form Dirichlet data (device, packed); the orbitals are evaluated on the GPU."""
+    phi = orb.values_torch(*xyz, device="cuda").reshape(-1).contiguous()
+    rho = binding.pair_densities(phi, orb.norb)
+    g = orb.pair_potentials_torch(*fxyz, device="cuda").reshape(-1).contiguous()
     return rho, g
 
 
@@ -120,6 +124,14 @@ def main():
     ap.add_argument("--finetune", type=int, default=0, help="final epochs with the plain A-norm gradient")
     ap.add_argument("--workload", default="exchange8", choices=["exchange8", "large"])
     ap.add_argument("--init", default=None, help="start from these weights instead of a random initialisation")
+    ap.add_argument("--stream", type=int, default=0, metavar="MOLS",
+                    help="stream the training set: generate MOLS molecules at a time, train on their pairs "
+                         "once, discard them (the set is never stored; every epoch regenerates it)")
+    ap.add_argument("--target-precision", default="fp64", choices=["fp64", "fp32_pc"],
+                    help="arithmetic of the solves that make the targets (FP32_PC has FP64 CG's accuracy)")
+    ap.add_argument("--target-rtol", type=float, default=1e-10)
+    ap.add_argument("--eval-rtol", default="1e-8", help="comma-separated tolerances of the held-out evaluation")
+    ap.add_argument("--eval-precisions", default="fp32_ir,fp64")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     if args.workload == "large":
@@ -131,7 +143,7 @@ def main():
         train_mol = lambda i: molecule(10000 + i)
         held_mol = lambda i: molecule(90000 + i)
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
-    ctx = binding.Context([m], n_levels=n_levels, rtol=1e-10, precision="fp64")
+    ctx = binding.Context([m], n_levels=n_levels, rtol=args.target_rtol, precision=args.target_precision)
     xyz, fxyz = ctx.mesh_coords(0)
     nd = ctx.info[0]["n_dofs"]
     net = binding.Net(args.levels, args.channels, 125, 27)
@@ -140,6 +152,8 @@ def main():
         net.load(args.init)
     else:
         net.set_params(he_init(net, rng))
+    if args.stream > 0:
+        return train_streamed(args, mesh, n_levels, ctx, net, train_mol, held_mol, rng, xyz, fxyz, nd)
 
     t0 = time.time()
     X = T = None
@@ -195,6 +209,76 @@ def main():
               "held_out": {"molecules": args.held_out, "seeds": "90000+i", "trained": ev,
                            "untrained_control": {p: ev_control[p]["net"] for p in ev_control}},
               "train_seconds": time.time() - t1}
+    with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
+        json.dump(report, f, indent=1)
+    print(json.dumps(report["held_out"]))
+
+
+def train_streamed(args, mesh, n_levels, ctx, net, train_mol, held_mol, rng, xyz, fxyz, nd):
+    """Training on a set that is generated on the GPU chunk by chunk and never stored: per chunk
+    of args.stream molecules, the pair densities, their Dirichlet data and the target potentials
+    (solved by the library), then one pass of mini-batches over the chunk's pairs, shuffled."""
+    total = args.epochs * args.molecules * 36 // args.batch
+    step = 0
+    hist = []
+    t1 = time.time()
+    npairs_seen = 0
+    for ep in range(args.epochs):
+        mode = 0 if ep >= args.epochs - args.finetune else args.mode
+        losses = []
+        for c0 in range(0, args.molecules, args.stream):
+            rhos, gs = [], []
+            for i in range(c0, min(args.molecules, c0 + args.stream)):
+                rho, g = pair_data(ctx, train_mol(i), xyz, fxyz)
+                rhos.append(rho)
+                gs.append(g)
+            rho, g = torch.cat(rhos), torch.cat(gs)
+            del rhos, gs
+            n = rho.numel() // nd
+            v, st = ctx.solve_batch(rho, g)
+            x, s = net.prepare_input(rho, n, nd)
+            T = (v.reshape(n, nd) / s[:, None]).contiguous()
+            X = x.reshape(n, nd)
+            del rho, g, v, x
+            perm = torch.as_tensor(rng.permutation(n), device="cuda")
+            for k in range(n // args.batch):
+                idx = perm[k * args.batch:(k + 1) * args.batch]
+                lr = args.lr * 0.5 * (1 + np.cos(np.pi * min(step, total) / total))  # cosine decay
+                loss = net.train_step(ctx, X[idx].reshape(-1).contiguous(), T[idx].reshape(-1).contiguous(),
+                                      args.batch, float(lr), mode=mode)
+                losses.append(loss)
+                step += 1
+            npairs_seen += n
+            del X, T
+            torch.cuda.empty_cache()
+            print(f"epoch {ep + 1}/{args.epochs}, molecules {c0}-{min(args.molecules, c0 + args.stream) - 1}: "
+                  f"mean loss {np.mean(losses[-max(1, n // args.batch):]):.4e} ({time.time() - t1:.0f}s)", flush=True)
+        hist.append(float(np.mean(losses)))
+        print(f"epoch {ep + 1}/{args.epochs}: mean relative A-norm loss {hist[-1]:.4e} ({time.time() - t1:.0f}s)",
+              flush=True)
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        net.save(args.out)
+    train_s = time.time() - t1
+    held = [held_mol(i) for i in range(args.held_out)]
+    ev, ev_control = {}, {}
+    control = binding.Net(args.levels, args.channels, 125, 27)
+    control.set_params(he_init(control, np.random.default_rng(12345)))
+    for rt in [float(t) for t in args.eval_rtol.split(",")]:
+        ev[f"{rt:g}"] = evaluate(mesh, net, held, rtol=rt, precisions=args.eval_precisions.split(","),
+                                 n_levels=n_levels)
+        ev_control[f"{rt:g}"] = {p: v["net"] for p, v in evaluate(mesh, control, held, rtol=rt,
+                                                                   precisions=args.eval_precisions.split(","),
+                                                                   n_levels=n_levels).items()}
+    report = {"weights": os.path.basename(args.out), "workload": args.workload, "init": args.init,
+              "molecules": args.molecules, "pairs_per_epoch": args.molecules * 36, "pairs_seen": npairs_seen,
+              "streamed": f"{args.stream} molecules at a time, regenerated every epoch, never stored",
+              "targets": f"{args.target_precision} MG-PCG to {args.target_rtol:g}",
+              "mode": args.mode, "finetune_epochs": args.finetune,
+              "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "levels": args.levels,
+              "channels": args.channels, "loss_history": hist,
+              "held_out": {"molecules": args.held_out, "seeds": "90000+i", "trained": ev,
+                           "untrained_control": ev_control},
+              "train_seconds": train_s}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(report, f, indent=1)
     print(json.dumps(report["held_out"]))

@@ -248,7 +248,7 @@ def test_two_solver_lanes_match_one_lane_bitwise(gpu_lib):
     wl = configs.scaled(4, 4, 20, seed=41)
     mesh = wl.meshes[0]
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
-    for prec in ("fp64", "fp32_ir", "fp32_pc"):
+    for prec in ("fp64", "fp32_ir", "fp32_pc", "bf16_pc"):
         out = []
         for lanes in (1, 2):
             ctx = gpu_lib.Context([m], precision=prec, lanes=lanes)
@@ -449,7 +449,7 @@ def test_graph_replay_matches_eager_launches_bitwise(gpu_lib):
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
     outs = []
     for use_graph in (0, 1):
-        for prec in ("fp64", "fp32_ir", "fp32_pc"):
+        for prec in ("fp64", "fp32_ir", "fp32_pc", "bf16_pc"):
             ctx = gpu_lib.Context([m], rtol=1e-10, use_graph=use_graph, precision=prec, check_every=2)
             rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
             rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
@@ -460,7 +460,7 @@ def test_graph_replay_matches_eager_launches_bitwise(gpu_lib):
             assert torch.equal(v1, v2)
             assert [s["iters"] for s in st1] == [s["iters"] for s in st2]
             outs.append((prec, _n(v1), [s["iters"] for s in st1]))
-    for prec in ("fp64", "fp32_ir", "fp32_pc"):
+    for prec in ("fp64", "fp32_ir", "fp32_pc", "bf16_pc"):
         a, b = [o for o in outs if o[0] == prec]
         assert np.array_equal(a[1], b[1]) and a[2] == b[2]
 
@@ -584,3 +584,56 @@ def test_fused_small_mesh_solve_matches_level_kernels(gpu_lib, case):
         axes, _, _, b = oracle_density_problem(mesh, dens[k])
         assert rel_l2_M(axes, mesh, out[1][0][k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
     assert max(abs(a - b_) for a, b_ in zip(out[1][1], out[0][1])) <= 1
+
+
+MF_CASES = [
+    ((4, 6, 2), 4, (-2.0, -3.0, -1.0), (2.0, 3.0, 1.0), 0),      # whole 4 x 2 tiles, every tile at a face
+    ((10, 6, 2), 4, (-5.0, -3.0, -1.0), (5.0, 3.0, 1.0), 0),     # interior tiles, ragged tiles at the x face
+]
+
+
+@pytest.mark.parametrize("case", MF_CASES, ids=[f"E{c[0]}" for c in MF_CASES])
+def test_matrix_core_operator_matches_oracle(gpu_lib, case):
+    """The degree-4 operator with its x and y line contractions on the matrix cores (BF16 operands,
+    FP32 accumulation; ghost lines at the domain faces) against the oracle's FP64 apply: each x or
+    y output sums at most 15 products whose two BF16 factors are each rounded to 2^-9 relative, so
+    its error is below 4e-3 of the sum of the absolute products; for random inputs that sum stays
+    within a few times max|y|, and the bar is 2e-2 max|y|.  The same inputs through the FP32
+    vector-unit kernel stay at FP32 rounding (2e-5), so the difference is the BF16 rounding alone."""
+    mesh = _mesh(case)
+    ctx = _ctx(gpu_lib, [case])
+    axes = oracle_axes(mesh)
+    u = np.random.default_rng(17).standard_normal((axes[2].N, axes[1].N, axes[0].N))
+    ref = layout.to_element_major(sipdg.apply(axes, u), mesh.E, mesh.p + 1)
+    import torch
+    ut = torch.as_tensor(layout.to_element_major(u, mesh.E, mesh.p + 1), dtype=torch.float32).cuda()
+    y_mf = ctx.operator_apply_mfma(ut).double().cpu().numpy()
+    y_32 = ctx.operator_apply(ut).double().cpu().numpy()
+    scale = np.abs(ref).max()
+    err_mf = np.abs(y_mf - ref).max() / scale
+    err_32 = np.abs(y_32 - ref).max() / scale
+    print(f"matrix-core operator: rel. max error {err_mf:.2e} (FP32 vector units {err_32:.2e})")
+    assert err_32 <= 2e-5
+    assert 1e-5 < err_mf <= 2e-2
+    # levels without a matrix-core kernel are refused
+    with pytest.raises(gpu_lib.DgError):
+        ctx.operator_apply_mfma(torch.zeros(ctx._level_dofs(0, 1), dtype=torch.float32, device="cuda"), level=1)
+
+
+def test_bf16_preconditioned_fp64_pcg_matches_exact(gpu_lib):
+    """BF16_PC (FP64 flexible CG, the finest-level smoothing steps on the matrix cores) reaches the
+    parity tolerance and the exact solution, with at most a few more iterations than FP64."""
+    wl = configs.scaled(8, 4, 6, seed=57)
+    mesh = wl.meshes[0]
+    out = {}
+    for prec in ("fp64", "bf16_pc"):
+        ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=PARITY_RTOL, precision=prec)
+        rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
+        v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
+        assert all(s_["status"] == 0 and s_["rel_residual"] <= PARITY_RTOL for s_ in st), prec
+        out[prec] = (_n(v).reshape(6, -1), [s_["iters"] for s_ in st])
+    print("iterations fp64", out["fp64"][1], "bf16_pc", out["bf16_pc"][1])
+    for k in (0, 5):
+        axes, _, _, b = oracle_density_problem(mesh, wl.batch.densities[k])
+        assert rel_l2_M(axes, mesh, out["bf16_pc"][0][k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
+    assert max(a - b_ for a, b_ in zip(out["bf16_pc"][1], out["fp64"][1])) <= 4
