@@ -331,6 +331,7 @@ def measure_roofline(W, arm, args, inputs, net_cache):
     if prof["launches"] <= 0 or prof["seconds"] <= 0:
         return None
     achieved = prof["bytes"] / prof["seconds"] / 1e9
+    copy_gbs = copy_bandwidth()
     fp = "float" if prec != "fp64" else "double"
     traffic_file = {"heldout32": "cheb_step_heldout32.md", "exchange8": "cheb_step_exchange8.md"}.get(W.name)
     return {
@@ -346,7 +347,33 @@ def measure_roofline(W, arm, args, inputs, net_cache):
         "launches": prof["launches"],
         "timing_source": "HIP events on the solver's stream around each launch, eager launches on one lane, "
                          "a separate pass after the timed steps",
+        "copy_gbs": copy_gbs,
+        "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
+        "copy_note": "device-to-device copy of 2 GiB (read + write bytes over its duration), timed in the same "
+                     "process: the streaming rate this GPU reaches with the runtime's own copy kernel",
     }
+
+
+def copy_bandwidth(mib=2048, reps=5):
+    """Bytes read plus written per second by a device-to-device copy of mib MiB (best of reps), GB/s."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        dt = e0.elapsed_time(e1) * 1e-3
+        best = dt if best is None else min(best, dt)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / best / 1e9
 
 
 def measured_traffic(profile_name, kernel_source, prec):
