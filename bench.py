@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--cheb-degree-h", type=int, default=None,
                     help="smoothing steps on the degree-1 coarse levels (default: the library's)")
     ap.add_argument("--inner-rtol", type=float, default=None, help="inner FP32 tolerance of fp32_ir")
+    ap.add_argument("--fused", type=int, default=None, choices=[0, 1, 2],
+                    help="FP64 small-mesh solve in one launch: 1 one work-group per RHS, 2 group-persistent")
+    ap.add_argument("--fused-wgs", type=int, default=None, help="work-groups per RHS of the group-persistent solve")
     ap.add_argument("--profile-solves", type=int, default=2,
                     help="eager solves of the headline arm that time the dominant kernel (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=1, help="pair solves timed on the oracle (0: skip)")
@@ -83,7 +86,8 @@ def parse():
                     help="also run 3 device-to-device copies of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     args.solver_opts = {k: v for k, v in (("cheb_degree", args.cheb_degree), ("cheb_ratio", args.cheb_ratio),
-                                          ("cheb_degree_h", args.cheb_degree_h), ("inner_rtol", args.inner_rtol))
+                                          ("cheb_degree_h", args.cheb_degree_h), ("inner_rtol", args.inner_rtol),
+                                          ("fused", args.fused), ("fused_wgs", args.fused_wgs))
                         if v is not None}
     return args
 
@@ -651,11 +655,18 @@ def main_single(args):
     wl = configs.single()
     mesh = wl.meshes[0]
     d = wl.batch.densities[0]
+    # arms: a precision, optionally +fused (one work-group per RHS runs the whole FP64 solve) or
+    # +group (the group-persistent launch: fused_wgs work-groups per RHS, group barriers)
     arms = [a for a in args.arms.split(",") if a and "learned" not in a and "untrained" not in a] or ["fp64"]
     results, pots = {}, {}
     for arm in arms:
+        opts = dict(args.solver_opts)
+        if arm.endswith("+fused"):
+            opts["fused"] = 1
+        elif arm.endswith("+group"):
+            opts["fused"] = 2
         ctx = binding.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol,
-                              precision=arm, **args.solver_opts)
+                              precision=arm.split("+")[0], **opts)
         xyz, fxyz = ctx.mesh_coords(0)
         rho = torch.as_tensor(d.density(xyz[0], xyz[1], xyz[2])).cuda()
         g = torch.as_tensor(d.potential(fxyz[0], fxyz[1], fxyz[2])).cuda()
@@ -668,7 +679,9 @@ def main_single(args):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         results[arm] = {"value": 1.0 / dt, "us_per_solve": 1e6 * dt, "iters": st[0]["iters"],
-                        "outer_iters": st[0]["outer_iters"], "rel_residual": st[0]["rel_residual"]}
+                        "outer_iters": st[0]["outer_iters"], "rel_residual": st[0]["rel_residual"],
+                        "fused": opts.get("fused", 0), "fused_wgs": opts.get("fused_wgs", 0),
+                        "fused_fallbacks": ctx.fused_fallbacks()}
         pots[arm] = v
         ctx.close()
     check = cpu = None

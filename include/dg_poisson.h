@@ -126,12 +126,22 @@ typedef struct {
                             one half overlap the bandwidth-bound phases of the other */
     int cheb_degree_h;   /* smoothing steps on the degree-1 levels below the finest (the
                             mesh-coarsening part of the hierarchy); 0 = cheb_degree */
-    int fused;           /* 1: in FP64 precision, a mesh whose every level has degree at most 4,
-                            at most 8,192 nodes and at most 64 nodes per axis is solved by a
-                            single launch that runs the whole PCG, one work-group per
-                            right-hand side (no host checks between iterations; level fields
-                            held in LDS when they fit); 0 (default): the level-by-level kernels,
-                            which are faster on gfx950 for every workload measured */
+    int fused;           /* fused small-mesh solve, FP64 precision only (other precisions ignore it):
+                            1: a mesh whose every level has degree at most 4, at most 8,192 nodes
+                            and at most 128 nodes per axis is solved by a single launch that runs
+                            the whole PCG, one work-group per right-hand side (level fields held
+                            in LDS when they fit); 2: group-persistent launch, the same solve
+                            with fused_wgs work-groups per right-hand side, persistent for the
+                            whole solve, the phases separated by a barrier of the group (no
+                            grid-wide barrier; any level size, degree at most 4, coarsest level
+                            at most 16 nodes per axis); a group whose barrier gives up waiting
+                            (see fused_spin) leaves the call to solve the batch again with the
+                            level kernels; 0 (default): the level-by-level kernels */
+    int fused_wgs;       /* fused = 2: work-groups per right-hand side, 1..32; 0 = automatic
+                            (about four finest-level nodes per thread, at most 16) */
+    long long fused_spin; /* fused = 2: polls before a group barrier gives up; 0 = default
+                            (2,000,000, about a second); negative: give up at the first poll
+                            that finds the group incomplete (tests the fallback) */
 } dg_opts;
 
 typedef struct {
@@ -152,7 +162,7 @@ typedef struct dg_ctx dg_ctx;
 /* Fill *opts with the defaults: automatic levels, degree 6, ratio 60,
  * safety 1.1, 30 Lanczos steps, eps 1/8, rtol 1e-8, 500 iterations, FP64,
  * inner_rtol 1e-4, max_outer 8, check_every 2, use_graph 1, lanes 2,
- * cheb_degree_h 10, fused 0. */
+ * cheb_degree_h 10, fused 0, fused_wgs 0, fused_spin 0. */
 void dg_opts_default(dg_opts* opts);
 
 /* Build the level hierarchy, operator tables, coarsest-grid eigendata and
@@ -304,6 +314,10 @@ dg_status dg_prolong_add(dg_ctx* ctx, int mesh_id, int level, int nrhs, const do
  * time them), their summed duration in seconds and their algorithmic bytes:
  * every vector the step reads or writes counted once per right-hand side
  * still iterating (host outputs). */
+/* Number of group-persistent solves (dg_opts.fused = 2) of this context whose group barrier gave
+ * up waiting and that were therefore solved again by the level kernels. */
+dg_status dg_fused_fallbacks(const dg_ctx* ctx, long long* count);
+
 dg_status dg_profile_enable(dg_ctx* ctx, int enable);
 dg_status dg_profile_read(const dg_ctx* ctx, long long* launches, double* seconds, double* bytes);
 

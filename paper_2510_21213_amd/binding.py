@@ -33,7 +33,8 @@ class DgOpts(ctypes.Structure):
                 ("penalty_eps", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("lanes", ctypes.c_int),
-                ("cheb_degree_h", ctypes.c_int), ("fused", ctypes.c_int)]
+                ("cheb_degree_h", ctypes.c_int), ("fused", ctypes.c_int), ("fused_wgs", ctypes.c_int),
+                ("fused_spin", ctypes.c_longlong)]
 
 
 class DgRhsStats(ctypes.Structure):
@@ -76,6 +77,7 @@ def _load():
         "dg_prolong_add": (I, [P, I, I, I, P, P, P]),
         "dg_level_info": (I, [P, I, I, P, P, P, P]),
         "dg_profile_enable": (I, [P, I]),
+        "dg_fused_fallbacks": (I, [P, ctypes.POINTER(LL)]),
         "dg_net_create": (I, [P, ctypes.POINTER(P)]),
         "dg_net_destroy": (None, [P]),
         "dg_net_last_error": (ctypes.c_char_p, []),
@@ -283,6 +285,12 @@ class Context:
         """Use a trained Net for the initial guess of later solves (None to stop)."""
         _check(lib.dg_poisson_attach_guess(self._h, net._h if net is not None else None), "attach_guess")
         self._guess = net
+
+    def fused_fallbacks(self):
+        """Group-persistent solves (fused=2) that fell back to the level kernels."""
+        n = ctypes.c_longlong()
+        _check(lib.dg_fused_fallbacks(self._h, ctypes.byref(n)), "fused_fallbacks")
+        return n.value
 
     # ---- timing of the finest-level Chebyshev step
     def profile(self, enable=True):

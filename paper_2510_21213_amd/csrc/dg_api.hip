@@ -16,6 +16,7 @@
 #include <exception>
 #include <functional>
 #include <memory>
+#include <atomic>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -149,10 +150,15 @@ struct dg_ctx {
         std::vector<double*> fusedP;
         double* fws = nullptr;
         long long fws_cap = 0, fws_per = 0;  // work space held, and needed per right-hand side
+        bool fused_lds_ok = false;           // every level fits the one-work-group kernel's LDS staging
+        long long fws_group = 0;             // work space per right-hand side of the group-persistent solve
+        unsigned* gsync = nullptr;           // its barrier counters (2 per right-hand side)
+        int gsync_cap = 0;
     };
     std::vector<Mesh> meshes;
     std::vector<Mesh> twins;       // second solver lane of each mesh (empty with one lane)
     dg_net* guess = nullptr;       // learned initial guess (not owned)
+    std::atomic<long long> fused_fallbacks{0};  // group-persistent solves that fell back to the level kernels
     double* g_x0 = nullptr;        // guess work space
     double* g_rho = nullptr;
     long long g_cap = 0;
@@ -629,13 +635,18 @@ void quad_data(dg_ctx* ctx, Mesh& M, int nsrc, const double* f, const double* ph
 void build_fused(Mesh& M) {
     const int nl = (int)M.lv.size();
     if (nl > dg::FUSED_MAX_LEVELS) return;
+    bool lds_ok = true;
     for (int l = 0; l < nl; ++l) {
         const LevelHost& L = M.lv[l];
-        if (L.ndof > dg::FUSED_MAX_DOF || L.n > 5) return;  // the fused operator has kernels for degrees 1..4
+        if (L.n > 5) return;  // the fused operator has kernels for degrees 1..4
+        if (L.ndof > dg::FUSED_MAX_DOF) lds_ok = false;
         for (int d = 0; d < 3; ++d)
             if (L.E[d] * L.n > dg::FUSED_MAX_AXIS) return;
         if (l + 1 < nl && (int)M.cheb[l].cp.size() + 1 > dg::FUSED_MAX_DEG) return;
     }
+    if (M.lv.back().E[0] * M.lv.back().n > dg::CMAX || M.lv.back().E[1] * M.lv.back().n > dg::CMAX ||
+        M.lv.back().E[2] * M.lv.back().n > dg::CMAX)
+        return;  // the coarsest solve's tables hold at most CMAX nodes per axis
     dg::FusedMeshDev H;
     std::memset(&H, 0, sizeof(H));
     H.nl = nl;
@@ -715,20 +726,53 @@ void build_fused(Mesh& M) {
     H.coarse = M.dcoarse;
     H.ws_per_rhs = off;
     M.fws_per = off;
+    H.lds_ok = lds_ok ? 1 : 0;
+    M.fused_lds_ok = lds_ok;
+    // group-persistent solve: q, the restriction's residual (largest level below the coarsest, or
+    // level 0), two coarsest-level scratch arrays, two sets of reduction slots
+    {
+        long long big = 0;
+        for (int l = 0; l < nl; ++l) big = std::max(big, M.lv[l].ndof);
+        H.off_q = off; off += M.lv[0].ndof;
+        H.off_t = off; off += big;
+        H.off_g1 = off; off += M.lv[nl - 1].ndof;
+        H.off_g2 = off; off += M.lv[nl - 1].ndof;
+        H.off_red = off; off += 2 * dg::GROUP_MAX_K;
+        H.ws_group = off;
+        M.fws_group = off;
+    }
     M.dfused = dalloc<dg::FusedMeshDev>(1);
     HIPCHK(hipMemcpy(M.dfused, &H, sizeof(H), hipMemcpyHostToDevice));
 }
 
+// fused = 1: one work-group per right-hand side (levels within its LDS staging); fused = 2: the
+// group-persistent solve.
 bool use_fused(const dg_ctx* ctx, const Mesh& M) {
-    return M.dfused && ctx->opts.fused && ctx->opts.precision == DG_PREC_FP64;
+    if (!M.dfused || ctx->opts.precision != DG_PREC_FP64) return false;
+    return (ctx->opts.fused == 1 && M.fused_lds_ok) || ctx->opts.fused == 2;
 }
 
-void ensure_fused_ws(Mesh& M, int nrhs) {
-    const long long need = M.fws_per * nrhs;
-    if (M.fws_cap >= need) return;
-    dfree(M.fws);
-    M.fws = dalloc<double>(need);
-    M.fws_cap = need;
+// Work-groups per right-hand side of the group-persistent solve: the option, else about 4
+// level-0 nodes per thread, at most 16.
+int group_wgs(const dg_ctx* ctx, const Mesh& M) {
+    if (ctx->opts.fused_wgs > 0) return std::min(ctx->opts.fused_wgs, dg::GROUP_MAX_K);
+    const long long per = 4LL * dg::GROUP_THREADS;
+    return (int)std::max(1LL, std::min(16LL, (M.lv[0].ndof + per - 1) / per));
+}
+
+void ensure_fused_ws(const dg_ctx* ctx, Mesh& M, int nrhs) {
+    const bool group = ctx->opts.fused == 2;
+    const long long need = (group ? M.fws_group : M.fws_per) * nrhs;
+    if (M.fws_cap < need) {
+        dfree(M.fws);
+        M.fws = dalloc<double>(need);
+        M.fws_cap = need;
+    }
+    if (group && M.gsync_cap < nrhs) {
+        dfree(M.gsync);
+        M.gsync = dalloc<unsigned>(2LL * nrhs);
+        M.gsync_cap = nrhs;
+    }
 }
 
 // Learned guess for nrhs sources rho of mesh M: writes ctx->g_x0 (the solve's guard
@@ -746,19 +790,36 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
     const auto& o = ctx->opts;
     ensure_state(M, nrhs);
     std::vector<int> iters(nrhs, 0), outer(nrhs, 0), kept(nrhs, x0 ? 1 : 0);
+    bool fused_done = false;
     if (use_fused(ctx, M)) {
-        // small mesh: the whole PCG in one launch, one work-group per right-hand side
-        ensure_fused_ws(M, nrhs);
+        // small mesh: the whole PCG in one launch, one work-group (fused = 1) or a group of
+        // work-groups (fused = 2) per right-hand side
+        ensure_fused_ws(ctx, M, nrhs);
         init_state(M, M.st, nrhs, o.rtol, o.max_iter, s);
         if (x0) HIPCHK(hipMemcpyAsync(v, x0, sizeof(double) * n0 * nrhs, hipMemcpyDeviceToDevice, s));
-        dg::launch_fused_pcg(M.dfused, nrhs, b, v, M.st, M.fws, x0 != nullptr, guard, s);
+        if (o.fused == 2)
+            dg::launch_group_pcg(M.dfused, group_wgs(ctx, M), nrhs, b, v, M.st, M.fws, M.gsync, x0 != nullptr, guard,
+                                 o.fused_spin > 0 ? o.fused_spin : (o.fused_spin < 0 ? 0LL : 2000000LL), s);
+        else
+            dg::launch_fused_pcg(M.dfused, nrhs, b, v, M.st, M.fws, x0 != nullptr, guard, s);
         HIPCHK(hipGetLastError());
         read_state(M, M.st, nrhs, s);
-        for (int i = 0; i < nrhs; ++i) {
-            iters[i] = M.st_host[i].iters;
-            outer[i] = 1;
-            if (x0) kept[i] = M.st_host[i].guess;
+        // a group barrier that gave up leaves its right-hand side unsolved: the batch is solved
+        // again by the level kernels below (the caller's initial guesses are still in x0)
+        fused_done = true;
+        for (int i = 0; i < nrhs; ++i) fused_done &= M.st_host[i].breakdown != dg::GROUP_SYNC_FAILED;
+        if (fused_done) {
+            for (int i = 0; i < nrhs; ++i) {
+                iters[i] = M.st_host[i].iters;
+                outer[i] = 1;
+                if (x0) kept[i] = M.st_host[i].guess;
+            }
+        } else {
+            ctx->fused_fallbacks += 1;
+            init_state(M, M.st, nrhs, o.rtol, o.max_iter, s);
         }
+    }
+    if (fused_done) {
     } else if (o.precision == DG_PREC_FP64 || o.precision == DG_PREC_FP32_PC || o.precision == DG_PREC_BF16_PC) {
         const bool pc = o.precision != DG_PREC_FP64;
         if (pc)
@@ -933,7 +994,7 @@ void prepare_lane(dg_ctx* ctx, Mesh& M, int cnt) {
     ensure_b(M, cnt, prec == DG_PREC_FP32_IR);
     ensure_state(M, cnt);
     if (use_fused(ctx, M))
-        ensure_fused_ws(M, cnt);
+        ensure_fused_ws(ctx, M, cnt);
     else if (prec == DG_PREC_FP32_IR)
         ensure_work<float>(M, M.w32, cnt);
     else if (prec == DG_PREC_FP32_PC || prec == DG_PREC_BF16_PC)
@@ -1236,6 +1297,8 @@ void dg_opts_default(dg_opts* o) {
     o->use_graph = 1;
     o->cheb_degree_h = 10;
     o->fused = 0;
+    o->fused_wgs = 0;
+    o->fused_spin = 0;
 }
 
 const char* dg_status_string(dg_status s) {
@@ -1296,6 +1359,8 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
                 T.dcoarse = M.dcoarse;
                 T.dfused = M.dfused;
                 T.fws_per = M.fws_per;
+                T.fused_lds_ok = M.fused_lds_ok;
+                T.fws_group = M.fws_group;
                 T.pstride = M.pstride;
                 T.nface = M.nface;
                 T.owns_tables = false;
@@ -1327,6 +1392,7 @@ void dg_poisson_destroy(dg_ctx* ctx) {
             for (auto* p : M.fusedP) dfree(p);
         }
         dfree(M.fws);
+        dfree(M.gsync);
         M.w64.release();
         M.w32.release();
         dfree(M.b);
@@ -1867,6 +1933,13 @@ dg_status dg_poisson_attach_guess(dg_ctx* ctx, dg_net* net) {
     return run_guarded([&] {
         if (!ctx) throw ArgError("null context");
         ctx->guess = net;
+    });
+}
+
+dg_status dg_fused_fallbacks(const dg_ctx* ctx, long long* count) {
+    return run_guarded([&] {
+        if (!ctx || !count) throw ArgError("null argument");
+        *count = ctx->fused_fallbacks.load();
     });
 }
 

@@ -171,10 +171,12 @@ void launch_sum_partials(int nq, const double* partial, int pstride, int nblk, d
 // the whole FP64 PCG with its V-cycle, every level staged through LDS, in a single launch.
 // Every level of an eligible mesh has degree at most 4, at most FUSED_MAX_DOF nodes (two FP64
 // staging arrays of that size fill 128 KiB of LDS) and at most FUSED_MAX_AXIS nodes per axis.
+// The group-persistent variant (launch_group_pcg) reads the same tables with no limit on the
+// nodes of a level.
 constexpr int FUSED_THREADS = 512;
 constexpr int FUSED_MAX_DOF = 8192;
 constexpr int FUSED_MAX_LEVELS = 8;
-constexpr int FUSED_MAX_AXIS = 64;
+constexpr int FUSED_MAX_AXIS = 128;
 constexpr int FUSED_MAX_DEG = 16;
 constexpr int FUSED_LDS_DOUBLES = 20480;  // the work-group's LDS: 160 KiB
 constexpr int FUSED_COARSE_SCRATCH = 16 * (16 * 17 + 2) + 3 * 16 * 16;  // coarsest solve's LDS (CMAX = 16)
@@ -196,10 +198,15 @@ struct FusedMeshDev {
     int nl;
     int resident;  // 1: every level field lives in LDS for the whole solve
     int lsy;       // resident mode: LDS offset of the operator output (and of the coarsest solve's scratch)
+    int lds_ok;    // 1: every level fits the one-work-group kernel's LDS staging (FUSED_MAX_DOF)
     FusedLevel lv[FUSED_MAX_LEVELS];
     const CoarseDev* coarse;
     long long off_x, off_r, off_p;  // level-0 PCG fields (the level-0 smoother fields are lv[0].off_za/zb)
     long long ws_per_rhs;           // doubles of work space per right-hand side
+    // group-persistent solve: after the fields above, q = A p (level 0), the residual handed to a
+    // restriction (largest level), two coarsest-level scratch arrays and the group's reduction slots
+    long long off_q, off_t, off_g1, off_g2, off_red;
+    long long ws_group;             // doubles of work space per right-hand side in that solve
 };
 // Solve nrhs problems b -> x of one small mesh (FP64 PCG, HS beta, up to three restarts from the
 // current iterate when the recomputed residual misses the tolerance).  st: tol2 and maxit set;
@@ -208,6 +215,19 @@ struct FusedMeshDev {
 // ws: nrhs * M.ws_per_rhs doubles.
 void launch_fused_pcg(const FusedMeshDev* M, int nrhs, const double* b, double* x, RhsState* st, double* ws,
                       bool has_x0, bool guard, hipStream_t s);
+
+// Group-persistent fused solve: the same solve with K work-groups (GROUP_THREADS threads each) per
+// right-hand side, persistent for the whole solve, every phase spread over the group and the phases
+// separated by a group barrier (an arrival counter per right-hand side; no grid-wide barrier).  The
+// group's work-groups run on one XCD.  A barrier that waits more than `spin` polls gives up: the
+// right-hand side then returns with st.breakdown = GROUP_SYNC_FAILED (its outputs are not to be
+// used) and the caller solves it again with the level kernels.  ws: nrhs * M.ws_group doubles;
+// sync: 2 * nrhs counters (zeroed here, before the launch).
+constexpr int GROUP_THREADS = 256;
+constexpr int GROUP_MAX_K = 32;
+constexpr int GROUP_SYNC_FAILED = 3;
+void launch_group_pcg(const FusedMeshDev* M, int K, int nrhs, const double* b, double* x, RhsState* st, double* ws,
+                      unsigned* sync, bool has_x0, bool guard, long long spin, hipStream_t s);
 
 // Dirichlet data by quadrature (dg_boundary.hip): g[s][b] = sum_q W_q f_s(x_q) / |r_b - x_q| over the
 // finest level's nodes, for nsrc sources f (packed fields) or, with f null, the pair products

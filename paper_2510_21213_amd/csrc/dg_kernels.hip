@@ -2385,6 +2385,7 @@ void launch_fill(T* x, T v, long long n, hipStream_t s) {
 }
 template void launch_fill<double>(double*, double, long long, hipStream_t);
 template void launch_fill<float>(float*, float, long long, hipStream_t);
+template void launch_fill<unsigned>(unsigned*, unsigned, long long, hipStream_t);
 
 __global__ __launch_bounds__(256) void k_segcopy(const double* __restrict__ src, const long long* __restrict__ soff,
                                                   double* __restrict__ dst, const long long* __restrict__ doff,
@@ -3022,5 +3023,579 @@ void launch_fused_pcg(const FusedMeshDev* M, int nrhs, const double* b, double* 
                        guard ? 1 : 0);
 }
 
-}  // namespace dg
+// ---------------------------------------------------------------------------
+// Group-persistent fused solve.  A group of K work-groups owns one right-hand side for the whole
+// FP64 PCG: every phase (a smoothing step, a residual, a transfer, a step of the coarsest solve, a
+// PCG vector update) is spread over the group's K * GROUP_THREADS threads, and a group barrier
+// separates the phases.  Level fields live in the right-hand side's work space (global memory;
+// small meshes stay in L2).  The operator is evaluated per node: the node's three element lines
+// and the face value (and, on the line's end nodes, the face derivative) of the neighbouring
+// elements along each axis.  Groups need nothing from each other, so the launch has no
+// grid-wide barrier, and right-hand sides of one launch converge independently.
+//
+// Group barrier: thread 0 of each work-group adds one arrival to the right-hand side's counter
+// (release at agent scope) and polls it until all K work-groups of the group have arrived at
+// this barrier (counter >= barriers passed * K), then acquires.  The poll is bounded: past
+// `spin` polls, or when another work-group of the group has given up, it sets the group's
+// give-up flag and the work-groups leave the kernel (every wave ends); the right-hand side
+// reports GROUP_SYNC_FAILED.  Measured on gfx950, a barrier over 8 work-groups costs about
+// 1.3 us and one over 256 about 8 us (arrivals at one counter are serialised), against about
+// 1.8 us between two kernels replayed from a graph: small groups are what pays.
 
+namespace {
+
+struct GroupArgs {
+    const FusedMeshDev* M;
+    int nrhs, K;
+    const double* b;
+    double* x;
+    RhsState* st;
+    double* ws;
+    unsigned* sync;
+    int has_x0, guard;
+    long long spin;
+};
+
+struct GCtx {
+    int gi, gs;          // this thread's index within the group, threads in the group
+    int rank, K;
+    unsigned* cnt;       // the group's arrival counter
+    unsigned* fail;      // the group's give-up flag
+    unsigned passed;     // barriers passed (thread 0)
+    long long spin;
+    int nsum;            // group sums taken (alternates the two slot sets)
+    double* slots;       // 2 * K doubles of the right-hand side's work space
+    double* red;         // LDS: one value per wave
+    double* lds;         // LDS: GROUP_LDS_DOUBLES, the staged operand of an operator phase
+    int* ok;             // LDS: the barrier's outcome for the work-group
+};
+
+__device__ bool g_bar(GCtx& c) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(c.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = ++c.passed * (unsigned)c.K;
+        long long n = 0;
+        while (__hip_atomic_load(c.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++n > c.spin || __hip_atomic_load(c.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                __hip_atomic_store(c.fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *c.ok = ok;
+    }
+    __syncthreads();
+    return *c.ok != 0;
+}
+
+// Sum of v over the group, taken at a barrier: the work-group's sum goes to its slot, and after
+// the barrier every thread adds the K slots in slot order (the same value in every thread of the
+// group).  Two slot sets alternate, so a work-group that runs ahead cannot overwrite slots that
+// another still reads (a barrier separates any two sums that share a set).
+__device__ bool g_sum(GCtx& c, double v, double& out) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    double* set = c.slots + (c.nsum & 1) * c.K;
+    ++c.nsum;
+    if ((threadIdx.x & 63) == 0) c.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < GROUP_THREADS / 64; ++w) s += c.red[w];
+        set[c.rank] = s;
+    }
+    if (!g_bar(c)) return false;
+    double s = 0.0;
+    for (int r = 0; r < c.K; ++r) s += set[r];
+    out = s;
+    return true;
+}
+
+// (A u) at node q of level F: the sum over the three axes of the node's row of the element-line
+// form (interior block B, the coupling to the neighbours' face values U and U0 and, on the line's
+// first and last node, to their face derivatives; ghost data on a domain face, as elem_op), times
+// the axis scale and the GLL weights of the other two local indices.
+template <int N>
+__device__ __forceinline__ double g_apply_node(const FusedLevel& F, const RefDev<double>& R,
+                                               const double* __restrict__ u, int q) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const int e = q / N3, loc = q - e * N3;
+    const int li[3] = {loc % N, (loc / N) % N, loc / N2};
+    const int E0 = F.E[0], E1 = F.E[1];
+    const int ei[3] = {e % E0, (e / E0) % E1, e / (E0 * E1)};
+    const int s_in[3] = {1, N, N2};
+    const int s_el[3] = {N3, E0 * N3, E0 * E1 * N3};
+    double sum = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int i = li[d];
+        const int base = q - i * s_in[d];
+        double A[N];
+#pragma unroll
+        for (int l = 0; l < N; ++l) A[l] = u[base + l * s_in[d]];
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) acc += R.B[i][l] * A[l];
+        double U, U0;
+        if (ei[d] > 0) {
+            const int nb = base - s_el[d];
+            U = u[nb + (N - 1) * s_in[d]];
+            if (i == 0) {
+                double Dv = 0.0;
+#pragma unroll
+                for (int l = 0; l < N; ++l) Dv += R.aR[l] * u[nb + l * s_in[d]];
+                acc += 0.5 * Dv - R.sig * U;
+            }
+        } else {
+            U = -A[0];
+            if (i == 0) {
+                double Dv = -2.0 * R.sig * A[0];
+#pragma unroll
+                for (int l = 0; l < N; ++l) Dv += R.aL[l] * A[l];
+                acc += 0.5 * Dv - R.sig * U;
+            }
+        }
+        if (ei[d] < F.E[d] - 1) {
+            const int nb = base + s_el[d];
+            U0 = u[nb];
+            if (i == N - 1) {
+                double D0 = 0.0;
+#pragma unroll
+                for (int l = 0; l < N; ++l) D0 += R.aL[l] * u[nb + l * s_in[d]];
+                acc -= 0.5 * D0 + R.sig * U0;
+            }
+        } else {
+            U0 = -A[N - 1];
+            if (i == N - 1) {
+                double D0 = 2.0 * R.sig * A[N - 1];
+#pragma unroll
+                for (int l = 0; l < N; ++l) D0 += R.aR[l] * A[l];
+                acc -= 0.5 * D0 + R.sig * U0;
+            }
+        }
+        acc += 0.5 * (R.aR[i] * U0 - R.aL[i] * U);
+        const int a = d == 0 ? li[1] : li[0], b2 = d == 2 ? li[1] : li[2];
+        sum += acc * R.scale[d] * R.w[a] * R.w[b2];
+    }
+    return sum;
+}
+
+// The operand of an operator phase: copied whole into the work-group's LDS when the level fits
+// (each work-group reads the field once, coalesced, instead of every node gathering its lines
+// from L2), else read in place.  The caller's group barrier orders the copy against the next
+// phase's.
+constexpr int GROUP_LDS_DOUBLES = 8192;
+__device__ __forceinline__ const double* g_stage(const double* __restrict__ u, int n, double* lds) {
+    if (n > GROUP_LDS_DOUBLES) return u;
+#pragma unroll 4
+    for (int q = threadIdx.x; q < n; q += GROUP_THREADS) lds[q] = u[q];
+    __syncthreads();
+    return lds;
+}
+
+// out = z + cp (z - zp) + cr D^-1 (f - A z) on the nodes of this thread (zp null: zero).
+// Returns this thread's part of dotv . out when dotv is given.
+template <int N>
+__device__ __noinline__ double g_cheb(int gi, int gs, const FusedLevel& F, const RefDev<double>& R, const double* __restrict__ f,
+                         const double* __restrict__ z, const double* __restrict__ zp, double* __restrict__ out,
+                         double cp, double cr, const double* __restrict__ dotv, double* lds) {
+    const double* zs = g_stage(z, F.ndof, lds);
+    double acc = 0.0;
+    for (int q = gi; q < F.ndof; q += gs) {
+        const double zq = zs[q];
+        const double o = zq + cp * (zq - (zp ? zp[q] : 0.0)) + cr * F.dinv[q] * (f[q] - g_apply_node<N>(F, R, zs, q));
+        out[q] = o;
+        if (dotv) acc += dotv[q] * o;
+    }
+    return acc;
+}
+
+// out = f - A u; optionally z1 = c0 D^-1 out.  Returns this thread's part of out . out.
+template <int N>
+__device__ __noinline__ double g_resid(int gi, int gs, const FusedLevel& F, const RefDev<double>& R, const double* __restrict__ f,
+                          const double* __restrict__ u, double* __restrict__ out, double* __restrict__ z1,
+                          double* lds) {
+    const double* us = g_stage(u, F.ndof, lds);
+    double acc = 0.0;
+    for (int q = gi; q < F.ndof; q += gs) {
+        const double rq = f[q] - g_apply_node<N>(F, R, us, q);
+        out[q] = rq;
+        if (z1) z1[q] = F.c0 * F.dinv[q] * rq;
+        acc += rq * rq;
+    }
+    return acc;
+}
+
+// out = A u.  Returns this thread's part of u . out.
+template <int N>
+__device__ __noinline__ double g_apply(int gi, int gs, const FusedLevel& F, const RefDev<double>& R, const double* __restrict__ u,
+                          double* __restrict__ out, double* lds) {
+    const double* us = g_stage(u, F.ndof, lds);
+    double acc = 0.0;
+    for (int q = gi; q < F.ndof; q += gs) {
+        const double y = g_apply_node<N>(F, R, us, q);
+        out[q] = y;
+        acc += us[q] * y;
+    }
+    return acc;
+}
+
+#define DG_GN(F, CALL)                 \
+    switch ((F).n) {                   \
+        case 2: { constexpr int NN = 2; CALL; } break; \
+        case 3: { constexpr int NN = 3; CALL; } break; \
+        case 4: { constexpr int NN = 4; CALL; } break; \
+        default: { constexpr int NN = 5; CALL; } break; \
+    }
+
+// fc = P^T t from level F to level C (each coarse node gathers the fine nodes of its element, or of
+// its two children per axis, with the tensor product of the 1D weights); optionally
+// z1c = C.c0 D_C^-1 fc.
+__device__ __noinline__ void g_restrict(int gi, int gs, const FusedLevel& F, const FusedLevel& C, const double* __restrict__ t,
+                           double* __restrict__ fc, double* __restrict__ z1c) {
+    const int n = C.n, n3 = n * n * n;
+    const int NXc = C.N[0], NYc = C.N[1], NZc = C.N[2];
+    for (int o = gi; o < C.ndof; o += gs) {
+        const int e = o / n3, l = o - e * n3;
+        const int Xc = (e % C.E[0]) * n + l % n, Yc = ((e / C.E[0]) % C.E[1]) * n + (l / n) % n,
+                  Zc = (e / (C.E[0] * C.E[1])) * n + l / (n * n);
+        const int x0 = F.rlo[0][Xc], xn = F.rcnt[0][Xc];
+        const int y0 = F.rlo[1][Yc], yn = F.rcnt[1][Yc];
+        const int z0 = F.rlo[2][Zc], zn = F.rcnt[2][Zc];
+        double s = 0.0;
+        for (int cz = 0; cz < zn; ++cz) {
+            const double wz = F.P[2][(z0 + cz) * NZc + Zc];
+            for (int cy = 0; cy < yn; ++cy) {
+                const double wyz = wz * F.P[1][(y0 + cy) * NYc + Yc];
+                double sx = 0.0;
+                for (int cx = 0; cx < xn; ++cx)
+                    sx += F.P[0][(x0 + cx) * NXc + Xc] * t[em_index(F, x0 + cx, y0 + cy, z0 + cz)];
+                s += wyz * sx;
+            }
+        }
+        fc[o] = s;
+        if (z1c) z1c[o] = C.c0 * C.dinv[o] * s;
+    }
+}
+
+// zf += P zc from level C to level F (each fine node gathers the coarse nodes of its (parent) element).
+__device__ __noinline__ void g_prolong_add(int gi, int gs, const FusedLevel& F, const FusedLevel& C, const double* __restrict__ zc,
+                              double* __restrict__ zf) {
+    const int n = F.n, n3 = n * n * n;
+    const int NXc = C.N[0], NYc = C.N[1], NZc = C.N[2];
+    for (int q = gi; q < F.ndof; q += gs) {
+        const int e = q / n3, l = q - e * n3;
+        const int Xf = (e % F.E[0]) * n + l % n, Yf = ((e / F.E[0]) % F.E[1]) * n + (l / n) % n,
+                  Zf = (e / (F.E[0] * F.E[1])) * n + l / (n * n);
+        const int x0 = F.plo[0][Xf], xn = F.pcnt[0][Xf];
+        const int y0 = F.plo[1][Yf], yn = F.pcnt[1][Yf];
+        const int z0 = F.plo[2][Zf], zn = F.pcnt[2][Zf];
+        double s = 0.0;
+        for (int cz = 0; cz < zn; ++cz) {
+            const double wz = F.P[2][Zf * NZc + z0 + cz];
+            for (int cy = 0; cy < yn; ++cy) {
+                const double wyz = wz * F.P[1][Yf * NYc + y0 + cy];
+                double sx = 0.0;
+                for (int cx = 0; cx < xn; ++cx) sx += F.P[0][Xf * NXc + x0 + cx] * zc[em_index(C, x0 + cx, y0 + cy, z0 + cz)];
+                s += wyz * sx;
+            }
+        }
+        zf[q] += s;
+    }
+}
+
+// The coarsest solve's eigendata staged in LDS once per work-group.
+struct GCoarse {
+    double Q[3][CMAX][CMAX];
+    double lam[3][CMAX];
+    double s[3][CMAX];
+};
+
+// Exact solve on the coarsest level C in three group phases: g1 = (Q^T (x) Q^T along x and y) S r,
+// then per z line the contraction with Q^T, the division by the eigenvalue sums and the
+// contraction with Q, then z = S (Q (x) Q along x and y) g2 (element-major).  g1, g2: lexicographic
+// scratch, X fastest.
+__device__ __noinline__ void g_coarse_fwd(int gi, int gs, const FusedLevel& C, const GCoarse& Cs,
+                                          const double* __restrict__ r, double* __restrict__ g1) {
+    const int nx = C.N[0], ny = C.N[1], nz = C.N[2];
+    const int nxy = nx * ny, nall = nxy * nz;
+    for (int o = gi; o < nall; o += gs) {
+        const int Xo = o % nx, Yo = (o / nx) % ny, Z = o / nxy;
+        double s = 0.0;
+        for (int Y = 0; Y < ny; ++Y) {
+            double sx = 0.0;
+            for (int X = 0; X < nx; ++X) sx += Cs.Q[0][X][Xo] * Cs.s[0][X] * r[em_index(C, X, Y, Z)];
+            s += Cs.Q[1][Y][Yo] * Cs.s[1][Y] * sx;
+        }
+        g1[o] = s * Cs.s[2][Z];
+    }
+}
+
+__device__ __noinline__ void g_coarse_z(int gi, int gs, const FusedLevel& C, const GCoarse& Cs,
+                                        const double* __restrict__ g1, double* __restrict__ g2) {
+    const int nx = C.N[0], ny = C.N[1], nz = C.N[2];
+    const int nxy = nx * ny;
+    for (int o = gi; o < nxy; o += gs) {
+        const int Xo = o % nx, Yo = o / nx;
+        double v[CMAX];
+#pragma unroll
+        for (int k = 0; k < CMAX; ++k) {
+            double s = 0.0;
+            if (k < nz) {
+                for (int Z = 0; Z < nz; ++Z) s += Cs.Q[2][Z][k] * g1[Z * nxy + o];
+                s /= (Cs.lam[0][Xo] + Cs.lam[1][Yo] + Cs.lam[2][k]);
+            }
+            v[k] = s;
+        }
+        for (int Z = 0; Z < nz; ++Z) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < CMAX; ++k)
+                if (k < nz) s += Cs.Q[2][Z][k] * v[k];
+            g2[Z * nxy + o] = s;
+        }
+    }
+}
+
+__device__ __noinline__ void g_coarse_back(int gi, int gs, const FusedLevel& C, const GCoarse& Cs,
+                                           const double* __restrict__ g2, double* __restrict__ z) {
+    const int nx = C.N[0], ny = C.N[1], nz = C.N[2];
+    const int nxy = nx * ny, nall = nxy * nz;
+    for (int o = gi; o < nall; o += gs) {
+        const int X = o % nx, Y = (o / nx) % ny, Z = o / nxy;
+        double s = 0.0;
+        for (int Yo = 0; Yo < ny; ++Yo) {
+            double sx = 0.0;
+            for (int Xo = 0; Xo < nx; ++Xo) sx += Cs.Q[0][X][Xo] * g2[Z * nxy + Yo * nx + Xo];
+            s += Cs.Q[1][Y][Yo] * sx;
+        }
+        z[em_index(C, X, Y, Z)] = s * Cs.s[0][X] * Cs.s[1][Y] * Cs.s[2][Z];
+    }
+}
+
+// Exact solve on the coarsest level C in three group phases: g1 = (Q^T (x) Q^T along x and y) S r,
+// then per z line the contraction with Q^T, the division by the eigenvalue sums and the
+// contraction with Q, then z = S (Q (x) Q along x and y) g2 (element-major).  g1, g2: lexicographic
+// scratch, X fastest.
+__device__ bool g_coarse(GCtx& c, const FusedLevel& C, const GCoarse& Cs, const double* __restrict__ r,
+                         double* __restrict__ z, double* __restrict__ g1, double* __restrict__ g2) {
+    g_coarse_fwd(c.gi, c.gs, C, Cs, r, g1);
+    if (!g_bar(c)) return false;
+    g_coarse_z(c.gi, c.gs, C, Cs, g1, g2);
+    if (!g_bar(c)) return false;
+    g_coarse_back(c.gi, c.gs, C, Cs, g2, z);
+    return g_bar(c);
+}
+
+__device__ __forceinline__ double* g_field(double* ws, const FusedLevel& F, int which) {
+    return ws + (which == 0 ? F.off_f : which == 1 ? F.off_za : F.off_zb);
+}
+
+// z = B r, one V-cycle from level 0 whose first smoothing iterate is already in lv[0]'s za; the
+// last smoothing step also sums r . z (rz).  Returns the field that holds z, or null when a
+// barrier gave up.
+__device__ double* g_vcycle(GCtx& c, const FusedMeshDev& M, const RefDev<double>* Rs, const GCoarse& Cs, double* ws,
+                            const double* r, double& rz) {
+    const int nl = M.nl;
+    double* t = ws + M.off_t;
+    for (int l = 0; l + 1 < nl; ++l) {
+        const FusedLevel& F = M.lv[l];
+        const double* f = l == 0 ? r : g_field(ws, F, 0);
+        double* cur = g_field(ws, F, 1);
+        double* prev = g_field(ws, F, 2);
+        for (int k = 1; k < F.deg; ++k) {
+            DG_GN(F, g_cheb<NN>(c.gi, c.gs, F, Rs[l], f, cur, k == 1 ? nullptr : prev, prev, F.cp[k - 1], F.cr[k - 1],
+                                nullptr, c.lds))
+            if (!g_bar(c)) return nullptr;
+            double* sw = cur; cur = prev; prev = sw;
+        }
+        DG_GN(F, g_resid<NN>(c.gi, c.gs, F, Rs[l], f, cur, t, nullptr, c.lds))
+        if (!g_bar(c)) return nullptr;
+        const FusedLevel& C = M.lv[l + 1];
+        g_restrict(c.gi, c.gs, F, C, t, g_field(ws, C, 0), l + 2 < nl ? g_field(ws, C, 1) : nullptr);
+        if (!g_bar(c)) return nullptr;
+    }
+    const FusedLevel& Lc = M.lv[nl - 1];
+    double* zc = g_field(ws, Lc, 1);
+    if (!g_coarse(c, Lc, Cs, g_field(ws, Lc, 0), zc, ws + M.off_g1, ws + M.off_g2)) return nullptr;
+    if (nl == 1) {  // a single level: the exact solve is the preconditioner (its source is r)
+        double part = 0.0;
+        for (int q = c.gi; q < Lc.ndof; q += c.gs) part += r[q] * zc[q];
+        if (!g_sum(c, part, rz)) return nullptr;
+        return zc;
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+        const FusedLevel& F = M.lv[l];
+        const double* f = l == 0 ? r : g_field(ws, F, 0);
+        // the pre-smoothing left its iterate in za after an even number of swaps, else in zb
+        const bool odd = ((F.deg - 1) & 1) != 0;
+        double* cur = g_field(ws, F, odd ? 2 : 1);
+        double* prev = g_field(ws, F, odd ? 1 : 2);
+        g_prolong_add(c.gi, c.gs, F, M.lv[l + 1], zc, cur);
+        if (!g_bar(c)) return nullptr;
+        for (int k = 0; k < F.deg; ++k) {
+            const bool last = l == 0 && k == F.deg - 1;
+            double part = 0.0;
+            DG_GN(F, part = g_cheb<NN>(c.gi, c.gs, F, Rs[l], f, cur, k == 0 ? nullptr : prev, prev,
+                                        k == 0 ? 0.0 : F.cp[k - 1], k == 0 ? F.c0 : F.cr[k - 1], last ? r : nullptr, c.lds))
+            if (last) {
+                if (!g_sum(c, part, rz)) return nullptr;
+            } else if (!g_bar(c)) {
+                return nullptr;
+            }
+            double* sw = cur; cur = prev; prev = sw;
+        }
+        zc = cur;
+    }
+    return zc;
+}
+
+__global__ __launch_bounds__(GROUP_THREADS) void k_group_pcg(GroupArgs a) {
+    __shared__ double red[GROUP_THREADS / 64];
+    __shared__ int ok;
+    __shared__ GCoarse Cs;
+    __shared__ RefDev<double> Rs[FUSED_MAX_LEVELS];  // reference-element tables of every level
+    __shared__ double ulds[GROUP_LDS_DOUBLES];
+    const int b = blockIdx.x, xcd = b % 8, j = b / 8;
+    const int rank = j % a.K, rhs = (j / a.K) * 8 + xcd;  // the group's work-groups share one XCD
+    if (rhs >= a.nrhs) return;
+    const FusedMeshDev& M = *a.M;
+    GCtx c;
+    c.rank = rank;
+    c.K = a.K;
+    c.gi = rank * GROUP_THREADS + (int)threadIdx.x;
+    c.gs = a.K * GROUP_THREADS;
+    c.cnt = a.sync + 2 * rhs;
+    c.fail = a.sync + 2 * rhs + 1;
+    c.passed = 0;
+    c.spin = a.spin;
+    c.nsum = 0;
+    c.red = red;
+    c.lds = ulds;
+    c.ok = &ok;
+    double* ws = a.ws + (long long)rhs * M.ws_group;
+    c.slots = ws + M.off_red;
+    {
+        const CoarseDev& CD = *M.coarse;
+        for (int q = threadIdx.x; q < 3 * CMAX * CMAX; q += GROUP_THREADS) (&Cs.Q[0][0][0])[q] = (&CD.Q[0][0][0])[q];
+        for (int q = threadIdx.x; q < 3 * CMAX; q += GROUP_THREADS) {
+            (&Cs.lam[0][0])[q] = (&CD.lam[0][0])[q];
+            (&Cs.s[0][0])[q] = (&CD.s[0][0])[q];
+        }
+        constexpr int RW = (int)(sizeof(RefDev<double>) / sizeof(double));
+        static_assert(sizeof(RefDev<double>) % sizeof(double) == 0, "RefDev<double> is a table of doubles");
+        for (int q = threadIdx.x; q < M.nl * RW; q += GROUP_THREADS)
+            reinterpret_cast<double*>(&Rs[q / RW])[q % RW] = reinterpret_cast<const double*>(&M.lv[q / RW].L->ref)[q % RW];
+    }
+    const FusedLevel& F0 = M.lv[0];
+    const int nd = F0.ndof;
+    const double* __restrict__ bv = a.b + (long long)rhs * nd;
+    double* __restrict__ x = a.x + (long long)rhs * nd;
+    double* r = g_field(ws, F0, 0);  // the level-0 source slot holds the residual
+    double* p = ws + M.off_p;
+    double* q = ws + M.off_q;
+    double* z1 = g_field(ws, F0, 1);
+    const double tol2 = a.st[rhs].tol2;
+    const int maxit = a.st[rhs].maxit;
+    bool live = true;
+    int iters = 0, breakdown = 0, guess = 0;
+    double bb = 0.0, rr = 0.0;
+    do {  // one pass; `break` leaves it when a barrier gave up (live = false)
+        double acc = 0.0;
+        for (int i = c.gi; i < nd; i += c.gs) acc += bv[i] * bv[i];
+        if (!(live = g_sum(c, acc, bb))) break;
+        if (a.has_x0) {
+            DG_GN(F0, acc = g_resid<NN>(c.gi, c.gs, F0, Rs[0], bv, x, r, z1, c.lds))
+            if (!(live = g_sum(c, acc, rr))) break;
+            guess = (!a.guard || rr < bb) ? 1 : 0;
+        }
+        if (!guess) {
+            for (int i = c.gi; i < nd; i += c.gs) {
+                x[i] = 0.0;
+                r[i] = bv[i];
+                z1[i] = F0.c0 * F0.dinv[i] * bv[i];
+            }
+            if (!(live = g_bar(c))) break;
+            rr = bb;
+        }
+        for (int pass = 0; pass < 4 && live; ++pass) {  // the first PCG pass and up to three restarts
+            breakdown = 0;
+            if (rr > tol2 * bb && iters < maxit) {
+                double rz = 0.0;
+                double* z = g_vcycle(c, M, Rs, Cs, ws, r, rz);
+                if (!(live = z != nullptr)) break;
+                for (int i = c.gi; i < nd; i += c.gs) p[i] = z[i];
+                if (!(live = g_bar(c))) break;
+                while (true) {
+                    double pq = 0.0;
+                    DG_GN(F0, acc = g_apply<NN>(c.gi, c.gs, F0, Rs[0], p, q, c.lds))
+                    if (!(live = g_sum(c, acc, pq))) break;
+                    if (!(pq > 0.0) || !(rz > 0.0)) {
+                        breakdown = 1;
+                        break;
+                    }
+                    const double alpha = rz / pq;
+                    acc = 0.0;
+                    for (int i = c.gi; i < nd; i += c.gs) {
+                        x[i] += alpha * p[i];
+                        const double ri = r[i] - alpha * q[i];
+                        r[i] = ri;
+                        z1[i] = F0.c0 * F0.dinv[i] * ri;
+                        acc += ri * ri;
+                    }
+                    if (!(live = g_sum(c, acc, rr))) break;
+                    ++iters;
+                    if (!(rr > tol2 * bb) || iters >= maxit) break;
+                    double rzn = 0.0;
+                    z = g_vcycle(c, M, Rs, Cs, ws, r, rzn);
+                    if (!(live = z != nullptr)) break;
+                    const double beta = rzn / rz;
+                    rz = rzn;
+                    for (int i = c.gi; i < nd; i += c.gs) p[i] = z[i] + beta * p[i];
+                    if (!(live = g_bar(c))) break;
+                }
+                if (!live) break;
+            }
+            // residual of the current iterate, recomputed (and the next pass's first smoothing iterate)
+            DG_GN(F0, acc = g_resid<NN>(c.gi, c.gs, F0, Rs[0], bv, x, r, z1, c.lds))
+            if (!(live = g_sum(c, acc, rr))) break;
+            const bool miss = bb > 0.0 && rr > tol2 * bb * 1.0201;  // (1.01 rtol)^2
+            if (!(miss && iters < maxit && !breakdown)) break;
+        }
+    } while (false);
+    if (threadIdx.x == 0 && (rank == 0 || !live)) {
+        RhsState& S = a.st[rhs];
+        S.active = 0;
+        if (!live) {
+            S.breakdown = GROUP_SYNC_FAILED;
+        } else {
+            S.bb = bb;
+            S.rr = rr;
+            S.iters = iters;
+            S.breakdown = breakdown;
+            S.guess = guess;
+        }
+    }
+}
+
+#undef DG_GN
+
+}  // namespace
+
+void launch_group_pcg(const FusedMeshDev* M, int K, int nrhs, const double* b, double* x, RhsState* st, double* ws,
+                      unsigned* sync, bool has_x0, bool guard, long long spin, hipStream_t s) {
+    if (nrhs == 0) return;
+    if (K < 1 || K > GROUP_MAX_K) throw std::runtime_error("group-persistent solve: bad work-group count");
+    launch_fill<unsigned>(sync, 0u, 2LL * nrhs, s);
+    GroupArgs a{M, nrhs, K, b, x, st, ws, sync, has_x0 ? 1 : 0, guard ? 1 : 0, spin};
+    const dim3 grid((unsigned)(((nrhs + 7) / 8) * 8 * K));
+    hipLaunchKernelGGL(k_group_pcg, grid, dim3(GROUP_THREADS), 0, s, a);
+}
+
+}  // namespace dg

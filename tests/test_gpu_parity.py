@@ -586,6 +586,70 @@ def test_fused_small_mesh_solve_matches_level_kernels(gpu_lib, case):
     assert max(abs(a - b_) for a, b_ in zip(out[1][1], out[0][1])) <= 1
 
 
+GROUP_CASES = [c for c in CASES if c[1] <= 4] + [
+    ((4, 4, 4), 1, (-2.0, -2.0, -2.0), (2.0, 2.0, 2.0), 0),    # one level: the exact solve preconditions
+]
+
+
+@pytest.mark.parametrize("K", [1, 4])
+@pytest.mark.parametrize("case", GROUP_CASES, ids=[f"E{c[0]}p{c[1]}" for c in GROUP_CASES])
+def test_group_persistent_solve_matches_exact(gpu_lib, case, K):
+    """With fused = 2 the whole FP64 PCG runs in one launch, a group of K work-groups per
+    right-hand side separated by group barriers (operator evaluated per node, transfers by
+    gather, coarsest solve in three group phases): the potentials meet the bar against the exact
+    solve at the parity tolerance, with the level-by-level solver's iteration counts (+-1), for a
+    batch of 20 over two lanes, and converged potentials given back as guesses need no iteration."""
+    mesh = _mesh(case)
+    dens = [_box_density(mesh, 190 + k) for k in range(20)]
+    out = {}
+    for fused in (2, 0):
+        ctx = _ctx(gpu_lib, [case], rtol=PARITY_RTOL, fused=fused, fused_wgs=K)
+        rho, g = zip(*[gpu_sample(ctx, 0, d) for d in dens])
+        rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+        v, st = ctx.solve_batch(rho, g)
+        assert all(s_["status"] == 0 and s_["rel_residual"] <= PARITY_RTOL for s_ in st), fused
+        v2, st2 = ctx.solve_batch(rho, g, x0=v)
+        assert all(s_["iters"] == 0 and s_["guess_used"] == 1 for s_ in st2), fused
+        assert ctx.fused_fallbacks() == 0
+        out[fused] = (_n(v).reshape(len(dens), -1), [s_["iters"] for s_ in st])
+    for k in (0, 11, 19):
+        axes, _, _, b = oracle_density_problem(mesh, dens[k])
+        assert rel_l2_M(axes, mesh, out[2][0][k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
+    assert max(abs(a - b_) for a, b_ in zip(out[2][1], out[0][1])) <= 1
+
+
+def test_group_persistent_single_gaussian(gpu_lib):
+    """The single-Gaussian workload (4^3 elements, p = 3, two levels) by the group-persistent
+    solve with the automatic group size, against the exact solve."""
+    wl = configs.single()
+    mesh, dens = wl.meshes[0], wl.batch.densities[0]
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=wl.rtol, fused=2)
+    rho, g = gpu_sample(ctx, 0, dens)
+    v, st = ctx.solve_batch(_t(rho), _t(g))
+    assert st[0]["status"] == 0 and st[0]["rel_residual"] <= wl.rtol
+    axes, _, _, b = oracle_density_problem(mesh, dens)
+    assert rel_l2_M(axes, mesh, _n(v), fdm.FDM(axes).solve(b)) <= POT_BAR
+    assert ctx.fused_fallbacks() == 0
+
+
+def test_group_persistent_fallback_when_a_barrier_gives_up(gpu_lib):
+    """fused_spin < 0 makes every group barrier give up at its first incomplete poll (every wave
+    still leaves the kernel); the call then solves the batch again with the level kernels, so the
+    results still meet the bar and the context counts the fallback."""
+    case = GROUP_CASES[0]
+    mesh = _mesh(case)
+    dens = [_box_density(mesh, 290 + k) for k in range(6)]
+    ctx = _ctx(gpu_lib, [case], rtol=PARITY_RTOL, fused=2, fused_wgs=4, fused_spin=-1)
+    rho, g = zip(*[gpu_sample(ctx, 0, d) for d in dens])
+    v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
+    assert all(s_["status"] == 0 and s_["rel_residual"] <= PARITY_RTOL for s_ in st)
+    assert ctx.fused_fallbacks() >= 1
+    v = _n(v).reshape(len(dens), -1)
+    for k in (0, 5):
+        axes, _, _, b = oracle_density_problem(mesh, dens[k])
+        assert rel_l2_M(axes, mesh, v[k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
+
+
 MF_CASES = [
     ((4, 6, 2), 4, (-2.0, -3.0, -1.0), (2.0, 3.0, 1.0), 0),      # whole 4 x 2 tiles, every tile at a face
     ((10, 6, 2), 4, (-5.0, -3.0, -1.0), (5.0, 3.0, 1.0), 0),     # interior tiles, ragged tiles at the x face
