@@ -154,6 +154,8 @@ struct dg_ctx {
         long long fws_group = 0;             // work space per right-hand side of the group-persistent solve
         unsigned* gsync = nullptr;           // its barrier counters (2 per right-hand side)
         int gsync_cap = 0;
+        double* cscr = nullptr;              // scratch of the coarsest solve (2 fields per right-hand side)
+        int cscr_cap = 0;
     };
     std::vector<Mesh> meshes;
     std::vector<Mesh> twins;       // second solver lane of each mesh (empty with one lane)
@@ -218,6 +220,14 @@ void ensure_state(Mesh& M, int nrhs) {
     M.cap_st = nrhs;
 }
 
+void ensure_cscr(Mesh& M, int nrhs) {
+    if (M.cscr_cap >= nrhs) return;
+    drop_graphs(M);
+    dfree(M.cscr);
+    M.cscr = dalloc<double>(2LL * nrhs * M.lv.back().ndof);
+    M.cscr_cap = nrhs;
+}
+
 template <typename T>
 void ensure_work(Mesh& M, Work<T>& W, int nrhs, int parts = WK_ALL) {
     const long long n0 = M.lv[0].ndof * nrhs;
@@ -256,6 +266,7 @@ void ensure_work(Mesh& M, Work<T>& W, int nrhs, int parts = WK_ALL) {
             W.zb[l] = dalloc<T>(n);
         }
         W.cap_lv = nrhs;
+        ensure_cscr(M, nrhs);
     }
 }
 
@@ -336,7 +347,7 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
     const int L = (int)M.lv.size();
     const LevelHost& Lv = M.lv[l];
     if (l == L - 1) {
-        dg::launch_coarse<T>(M.dcoarse, Lv, nrhs, st, f, W.za[l], s);
+        dg::launch_coarse<T>(M.dcoarse, Lv, nrhs, st, f, W.za[l], M.cscr_cap >= nrhs ? M.cscr : nullptr, s);
         return W.za[l];
     }
     const ChebCoef& C = M.cheb[l];
@@ -1393,6 +1404,7 @@ void dg_poisson_destroy(dg_ctx* ctx) {
         }
         dfree(M.fws);
         dfree(M.gsync);
+        dfree(M.cscr);
         M.w64.release();
         M.w32.release();
         dfree(M.b);
@@ -1898,7 +1910,8 @@ dg_status dg_coarse_solve(dg_ctx* ctx, int mesh_id, int nrhs, const double* r, d
         check_mesh_id(ctx, mesh_id);
         auto& M = ctx->meshes[mesh_id];
         if (nrhs < 0 || (nrhs > 0 && (!r || !z))) throw ArgError("bad arguments");
-        dg::launch_coarse<double>(M.dcoarse, M.lv.back(), nrhs, nullptr, r, z, stream);
+        ensure_cscr(M, nrhs);
+        dg::launch_coarse<double>(M.dcoarse, M.lv.back(), nrhs, nullptr, r, z, M.cscr, stream);
         HIPCHK(hipGetLastError());
     });
 }

@@ -81,10 +81,12 @@ template <typename T>
 void launch_prolong(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st, const T* zc, T* zf,
                     hipStream_t s);
 
-// z = A^-1 r on the coarsest level (FP64 arithmetic for any storage type).
+// z = A^-1 r on the coarsest level (FP64 arithmetic for any storage type).  scratch: 2 * nrhs *
+// L.ndof doubles, which spreads the solve over many work-groups in three launches; null: one
+// work-group per right-hand side.
 template <typename T>
 void launch_coarse(const CoarseDev* C, const LevelHost& L, int nrhs, const RhsState* st, const T* r, T* z,
-                   hipStream_t s);
+                   double* scratch, hipStream_t s);
 
 // L.dinv64 / L.dinv32 = 1 / diag(A) of the level (the tables must be allocated, ndof each).
 void launch_dinv(const LevelHost& L, hipStream_t s);

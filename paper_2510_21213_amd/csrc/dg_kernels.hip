@@ -1920,16 +1920,117 @@ __global__ __launch_bounds__(1024) void k_coarse(const CoarseDev* __restrict__ C
     coarse_wg<T>(C, ndof, r + (long long)rhs * ndof, z + (long long)rhs * ndof, g, Qs);
 }
 
+// The same exact solve spread over many work-groups, in three launches (each a barrier-free
+// phase): per z plane the x and y contractions with Q^T of S r; per group of 16 z lines the z
+// contraction with Q^T, the division by the eigenvalue sums and the z contraction with Q; per z
+// plane the x and y contractions with Q and the scaling by S back into element order.  g1, g2:
+// FP64 scratch, nrhs lexicographic fields of the level (X fastest).  At most CMAX nodes per axis,
+// so a z plane (at most 256 nodes) is one work-group.
+__device__ __forceinline__ int coarse_em(const CoarseDev& C, int X, int Y, int Z) {
+    const int N = C.N;
+    const int ex = X / N, i = X - ex * N, ey = Y / N, j = Y - ey * N, ez = Z / N, k = Z - ez * N;
+    return ((ez * C.E[1] + ey) * C.E[0] + ex) * N * N * N + (k * N + j) * N + i;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_xy_fwd(const CoarseDev* __restrict__ Cp, long long ndof,
+                                                       const RhsState* st, const T* __restrict__ r,
+                                                       double* __restrict__ g1) {
+    __shared__ double sp[CMAX * CMAX], tp[CMAX * CMAX];
+    const int rhs = blockIdx.y, Z = blockIdx.x, t = threadIdx.x;
+    if (st && !st[rhs].active) return;
+    const CoarseDev& C = *Cp;
+    const int nx = C.n[0], ny = C.n[1], nxy = nx * ny;
+    const T* rr = r + (long long)rhs * ndof;
+    if (t < nxy) {
+        const int X = t % nx, Y = t / nx;
+        sp[t] = (double)rr[coarse_em(C, X, Y, Z)] * C.s[0][X] * C.s[1][Y];
+    }
+    __syncthreads();
+    if (t < nxy) {  // (Y, Xo): along x
+        const int Xo = t % nx, Y = t / nx;
+        double a = 0.0;
+        for (int X = 0; X < nx; ++X) a += C.Q[0][X][Xo] * sp[Y * nx + X];
+        tp[t] = a;
+    }
+    __syncthreads();
+    if (t < nxy) {  // (Yo, Xo): along y
+        const int Xo = t % nx, Yo = t / nx;
+        double a = 0.0;
+        for (int Y = 0; Y < ny; ++Y) a += C.Q[1][Y][Yo] * tp[Y * nx + Xo];
+        g1[(long long)rhs * ndof + (long long)Z * nxy + t] = a * C.s[2][Z];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_coarse_z(const CoarseDev* __restrict__ Cp, long long ndof, const RhsState* st,
+                                                  const double* __restrict__ g1, double* __restrict__ g2) {
+    __shared__ double sv[16][CMAX + 1];
+    const int rhs = blockIdx.y, t = threadIdx.x;
+    if (st && !st[rhs].active) return;
+    const CoarseDev& C = *Cp;
+    const int nx = C.n[0], nxy = nx * C.n[1], nz = C.n[2];
+    const int ln = t / 16, k = t % 16, line = blockIdx.x * 16 + ln;  // 16 z lines of 16 entries
+    const bool ok = line < nxy && k < nz;
+    const double* a1 = g1 + (long long)rhs * ndof;
+    double v = 0.0;
+    if (ok) {
+        for (int Z = 0; Z < nz; ++Z) v += C.Q[2][Z][k] * a1[(long long)Z * nxy + line];
+        v /= (C.lam[0][line % nx] + C.lam[1][line / nx] + C.lam[2][k]);
+    }
+    sv[ln][k] = v;
+    __syncthreads();
+    if (ok) {
+        double w = 0.0;
+        for (int c = 0; c < nz; ++c) w += C.Q[2][k][c] * sv[ln][c];
+        g2[(long long)rhs * ndof + (long long)k * nxy + line] = w;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_xy_back(const CoarseDev* __restrict__ Cp, long long ndof,
+                                                        const RhsState* st, const double* __restrict__ g2,
+                                                        T* __restrict__ z) {
+    __shared__ double sp[CMAX * CMAX], tp[CMAX * CMAX];
+    const int rhs = blockIdx.y, Z = blockIdx.x, t = threadIdx.x;
+    if (st && !st[rhs].active) return;
+    const CoarseDev& C = *Cp;
+    const int nx = C.n[0], ny = C.n[1], nxy = nx * ny;
+    if (t < nxy) sp[t] = g2[(long long)rhs * ndof + (long long)Z * nxy + t];
+    __syncthreads();
+    if (t < nxy) {  // (Yo, X): along x
+        const int X = t % nx, Yo = t / nx;
+        double a = 0.0;
+        for (int Xo = 0; Xo < nx; ++Xo) a += C.Q[0][X][Xo] * sp[Yo * nx + Xo];
+        tp[t] = a;
+    }
+    __syncthreads();
+    if (t < nxy) {  // (Y, X): along y, scaled, into element order
+        const int X = t % nx, Y = t / nx;
+        double a = 0.0;
+        for (int Yo = 0; Yo < ny; ++Yo) a += C.Q[1][Y][Yo] * tp[Yo * nx + X];
+        z[(long long)rhs * ndof + coarse_em(C, X, Y, Z)] = (T)(a * C.s[0][X] * C.s[1][Y] * C.s[2][Z]);
+    }
+}
+
 template <typename T>
 void launch_coarse(const CoarseDev* C, const LevelHost& L, int nrhs, const RhsState* st, const T* r, T* z,
-                   hipStream_t s) {
+                   double* scratch, hipStream_t s) {
     if (nrhs == 0) return;
-    hipLaunchKernelGGL((k_coarse<T>), dim3(nrhs), dim3(1024), 0, s, C, nrhs, L.ndof, st, r, z);
+    const int nx = L.E[0] * L.n, ny = L.E[1] * L.n, nz = L.E[2] * L.n;
+    if (!scratch || nx > CMAX || ny > CMAX || nz > CMAX) {  // one work-group per right-hand side
+        hipLaunchKernelGGL((k_coarse<T>), dim3(nrhs), dim3(1024), 0, s, C, nrhs, L.ndof, st, r, z);
+        return;
+    }
+    double* g1 = scratch;
+    double* g2 = scratch + (long long)nrhs * L.ndof;
+    hipLaunchKernelGGL((k_coarse_xy_fwd<T>), dim3(nz, nrhs), dim3(256), 0, s, C, L.ndof, st, r, g1);
+    hipLaunchKernelGGL(k_coarse_z, dim3((nx * ny + 15) / 16, nrhs), dim3(256), 0, s, C, L.ndof, st, g1, g2);
+    hipLaunchKernelGGL((k_coarse_xy_back<T>), dim3(nz, nrhs), dim3(256), 0, s, C, L.ndof, st, g2, z);
 }
 template void launch_coarse<double>(const CoarseDev*, const LevelHost&, int, const RhsState*, const double*, double*,
-                                    hipStream_t);
+                                    double*, hipStream_t);
 template void launch_coarse<float>(const CoarseDev*, const LevelHost&, int, const RhsState*, const float*, float*,
-                                   hipStream_t);
+                                   double*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // pointwise kernels: grid (chunks, nrhs), 256 threads x 4 values per chunk
