@@ -13,13 +13,16 @@
 // and for the left neighbour (value up and derivative dp at its right end)
 //     y_e += e_L ( dp/2 - sigma up) - d_L (up/2).
 //
-// Tiling.  A work-group owns a brick of BE^3 elements (NB = BE*N nodes per
-// edge) of one right-hand side.  The brick is staged in LDS; the x and y
-// axis terms are computed by one thread per brick row, the z term by one
-// thread per brick column that keeps its column in registers.  Neighbour
-// elements outside the brick are read straight from global memory (they are
-// the face halo; the L2 of the XCD serves them).  Work-group indices are
-// remapped so that each XCD receives a contiguous range of bricks.
+// Tiling.  The operator kernels of degrees 1, 2 and 4 (every level of the benchmark
+// hierarchies) are slab kernels (k_slab): a work-group owns a TX x TY tile of elements in the
+// x-y plane of one right-hand side and marches along z through a chunk of element layers; per
+// layer it stages the tile and its ring of x/y neighbour elements in LDS, computes the x and y
+// terms of element pairs in two thread halves at once and the z term of each node column in
+// registers (the previous and next layers supply the z neighbours, so no z halo is read), and
+// applies the step's epilogue (Chebyshev update, residual, search direction, restriction).  The
+// other degrees (3, 5, 6, 7) use the earlier brick kernel (k_brick): a BE^3-element brick staged
+// in LDS, neighbour lines outside it read from global memory.  Work-group indices are remapped
+// so that each XCD receives a contiguous range of tiles.
 //
 // Reductions are deterministic: every work-group writes one partial sum to a
 // fixed slot and a second kernel adds the slots in a fixed order.
