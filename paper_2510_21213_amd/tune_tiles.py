@@ -5,13 +5,16 @@ The operator steps run as a slab kernel whose work-group owns tx x ty elements o
 and zlen element layers (dg_tile_set lists the compiled shapes).  The steps are grouped (the
 FP32 smoothing steps and restriction of the degree-4 level; its other FP32 steps; its FP64
 steps; the degree-2 and degree-1 levels in each arithmetic) and every compiled tile of a group
-is tried in turn, coordinate descent from the current table, with the exchange step of the
-8-orbital workload (36 pair densities, 16^3 elements, p = 4) timed end to end: the mixed arm
-with the trained guess for FP32 tiles, the plain FP64 arm for FP64 tiles.  A tile replaces the
-current one only when its median step time is lower by more than the noise margin.  Writes the
-table (tiles_gfx950.json next to this file by default), which the binding applies on import.
+is tried in turn, coordinate descent from the current table, with an exchange step timed end to
+end.  Workload exchange8 (36 pair densities of 8 orbitals, 16^3 elements, p = 4): the FP32
+refinement arm with the trained guess for FP32 tiles, the plain FP64 arm for FP64 tiles.
+Workload large (the 36 pair densities of the first held-out molecule on 32^3 elements, p = 4,
+5 levels): the FP32_PC arm with its trained guess for every group it runs (its V-cycle is FP32,
+its search-direction and residual steps FP64).  A tile replaces the current one only when its
+median step time is lower by more than the noise margin.  Writes the table (tiles_gfx950.json
+next to this file by default), which the binding applies on import.
 
-    python paper_2510_21213_amd/tune_tiles.py [--steps 8] [--warmup 4] [--margin 0.02]
+    python paper_2510_21213_amd/tune_tiles.py [--workload large] [--steps 8] [--warmup 4] [--margin 0.02]
 """
 import argparse
 import json
@@ -50,22 +53,31 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--margin", type=float, default=0.02, help="relative gain a new tile must show")
     ap.add_argument("--out", default=binding.TILE_TABLE)
+    ap.add_argument("--workload", default="exchange8", choices=["exchange8", "large"])
+    ap.add_argument("--rtol", type=float, default=None, help="residual of the timed solves (default: the workload's)")
     args = ap.parse_args()
     torch.cuda.set_device(0)
-    wl = configs.exchange8()
+    large = args.workload == "large"
+    wl = configs.large_molecule(0, held_out=True) if large else configs.exchange8()
+    rtol = args.rtol or (1e-11 if large else wl.rtol)
     mesh, orb = wl.meshes[0], wl.orbitals
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
     net = binding.Net(4, 32, 125, 27)
-    net.load(os.path.join(ROOT, "paper_2510_21213_amd", "weights", "guess_16e_p4.bin"))
+    net.load(os.path.join(ROOT, "paper_2510_21213_amd", "weights",
+                          "guess_32e_p4.bin" if large else "guess_16e_p4.bin"))
     probe = binding.Context([m], n_levels=wl.n_levels)
     xyz, fxyz = probe.mesh_coords(0)
     probe.close()
-    phi = torch.as_tensor(orb.values(xyz[0], xyz[1], xyz[2]).reshape(-1)).cuda()
-    g = torch.as_tensor(orb.pair_potentials(fxyz[0], fxyz[1], fxyz[2]).reshape(-1)).cuda()
+    phi = orb.values_torch(*xyz, device="cuda").reshape(-1).contiguous()
+    g = orb.pair_potentials_torch(*fxyz, device="cuda").reshape(-1).contiguous()
+    groups = GROUPS
+    if large:  # the FP32_PC arm: FP32 V-cycle steps and the FP64 degree-4 steps
+        groups = [(nm, fp, n, st, sh, zl, "fp32_pc+learned") for nm, fp, n, st, sh, zl, _ in GROUPS
+                  if fp == 4 or n == 5]
 
     def measure(arm):
-        prec = "fp32_ir" if arm.startswith("fp32_ir") else "fp64"
-        ctx = binding.Context([m], n_levels=wl.n_levels, rtol=wl.rtol, precision=prec)
+        prec = arm.split("+")[0]
+        ctx = binding.Context([m], n_levels=wl.n_levels, rtol=rtol, precision=prec)
         if "learned" in arm:
             ctx.attach_guess(net)
         for _ in range(args.warmup):
@@ -85,7 +97,7 @@ def main():
 
     trials = []
     t_start = time.time()
-    for name, fp, n, steps, shapes, zlens, arm in GROUPS:
+    for name, fp, n, steps, shapes, zlens, arm in groups:
         current = {st: binding.tile_get(fp, n, st) for st in steps}
         base = measure(arm)
         best, best_t = None, base
@@ -115,7 +127,9 @@ def main():
             for st in ALL:
                 tx, ty, z = binding.tile_get(fp, n, st)
                 tiles.append({"fp_bytes": fp, "n": n, "step": st, "tx": tx, "ty": ty, "zlen": z})
-    report = {"arch": "gfx950", "workload": "exchange8: 36 pair densities, 16^3 elements, p = 4, 4 levels, 1e-8",
+    wname = ("large: 36 pair densities of the first held-out molecule, 32^3 elements, p = 4, 5 levels, fp32_pc"
+             if large else "exchange8: 36 pair densities, 16^3 elements, p = 4, 4 levels")
+    report = {"arch": "gfx950", "workload": f"{wname}, residual {rtol:g}",
               "timing": f"median of {args.steps} exchange steps after {args.warmup} warm-up steps",
               "margin": args.margin, "tiles": tiles, "trials": trials, "seconds": time.time() - t_start}
     with open(args.out, "w") as f:
