@@ -28,6 +28,10 @@ electronic structure"):
                    K_ij (Sec. 6.1, eq. fock_poisson).
 * ``boundary``  -- Dirichlet data by quadrature of the source over the grid
                    (Sec. 6.3): g(r) = sum_q W_q f(x_q)/|r - x_q| at the boundary nodes.
+* ``consumers`` -- the Hartree and exchange actions projected on a basis by the
+                   grid's quadrature (Sec. 6.1) and the adaptively compressed
+                   exchange built from the exchange action on the occupied
+                   orbitals (Sec. 7.2).
 * ``layout``    -- conversion between the element-major storage order of the
                    library and the global tensor order used here.
 
