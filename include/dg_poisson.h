@@ -248,6 +248,47 @@ dg_status dg_boundary_data(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, 
 dg_status dg_boundary_data_noalloc(dg_ctx* ctx, int mesh_id, int nsrc, const double* f, double* g,
                                    hipStream_t stream);
 
+/* ---- Consumers of the potentials: actions projected on a basis, compressed exchange ----
+ * Functions on the grid are element-major fields of the mesh's finest level, packed one after
+ * another ([count][n_dofs], device).  Integrals use the grid's quadrature rule (Sec. 6.1:
+ * each factor evaluated at the nodes, weights = the lumped GLL mass).  Outputs are row-major
+ * device matrices.  Work is enqueued on `stream` (no synchronisation unless stated). */
+
+/* Hartree action on vectors u_a projected on basis functions phi_i (Sec. 6.1, the action of
+ * eq. hartreecoulomb on an orbital): out[i*nu + a] = sum over nodes of w phi_i u_a vH, where vH
+ * is a potential on the same grid (e.g. the solution of a Hartree problem from
+ * dg_poisson_solve_batch).  nbasis, nu >= 1.  DG_ERR_ARG on bad sizes or null pointers. */
+dg_status dg_hartree_action(dg_ctx* ctx, int mesh_id, int nbasis, const double* phi, int nu, const double* u,
+                            const double* vH, double* out, hipStream_t stream);
+
+/* Exchange action on vectors u_a projected on basis functions phi_i (Sec. 6.1, eq.
+ * fock_exchange and eq. fock_poisson): for every pair (a, s) with an occupied orbital psi_s the
+ * problem -Lap v_as = 4 pi u_a psi_s is solved on the grid as dg_poisson_solve_batch does (the
+ * context's precision, tolerance, lanes and attached learned guess); W_a = sum_s psi_s v_as
+ * (positive sign; the Hartree-Fock prefactor is the caller's) and out[i*nu + a] = sum over nodes
+ * of w phi_i W_a.  g_pairs: Dirichlet data [nu*nocc][n_face] with pair (a, s) at a*nocc + s, or
+ * NULL (computed by quadrature of u_a psi_s, as dg_boundary_data).  W: device [nu][n_dofs]
+ * receiving W_a, or NULL.  stats: host [nu*nocc] or NULL.  1 <= nocc <= 64, nu*nocc <= 4096.
+ * Returns after synchronising the stream, with the solve's worst status (dg_poisson_solve_batch). */
+dg_status dg_exchange_action(dg_ctx* ctx, int mesh_id, int nbasis, const double* phi, int nu, const double* u,
+                             int nocc, const double* psi, const double* g_pairs, double* out, double* W,
+                             dg_rhs_stats* stats, hipStream_t stream);
+
+/* Adaptively compressed exchange (Sec. 7.2, the construction the paper cites): from the occupied
+ * orbitals psi_k and W_k, the exchange action on them (dg_exchange_apply's W, or
+ * dg_exchange_action's W with u = psi), M_kl = (psi_k, W_l) (quadrature), its symmetric part
+ * factored M = L L^T (Cholesky), and xi = L^-1 W: xi_k = sum_{j<=k} (L^-1)_kj W_j, device
+ * [nocc][n_dofs].  The compressed operator sum_k xi_k (xi_k, .) equals the exchange operator on
+ * the span of the psi_k.  1 <= nocc <= 64.  Synchronises the stream; DG_ERR_BREAKDOWN when M is
+ * not positive definite (xi then not to be used). */
+dg_status dg_ace_build(dg_ctx* ctx, int mesh_id, int nocc, const double* psi, const double* W, double* xi,
+                       hipStream_t stream);
+
+/* The compressed exchange applied to vectors u_a and projected on phi_i:
+ * out[i*nu + a] = sum_k (phi_i, xi_k) (xi_k, u_a), inner products by quadrature. */
+dg_status dg_ace_action(dg_ctx* ctx, int mesh_id, int nbasis, const double* phi, int nu, const double* u, int nocc,
+                        const double* xi, double* out, hipStream_t stream);
+
 /* Work-group tiles of the operator kernels (host only; no GPU needed).
  * The operator steps of the path run as a slab kernel on nodes-per-edge n = 2,
  * 3 and 5 (degrees 1, 2, 4): a work-group owns tx x ty elements of the x-y

@@ -78,6 +78,10 @@ def _load():
         "dg_level_info": (I, [P, I, I, P, P, P, P]),
         "dg_profile_enable": (I, [P, I]),
         "dg_fused_fallbacks": (I, [P, ctypes.POINTER(LL)]),
+        "dg_hartree_action": (I, [P, I, I, P, I, P, P, P, P]),
+        "dg_exchange_action": (I, [P, I, I, P, I, P, I, P, P, P, P, P, P]),
+        "dg_ace_build": (I, [P, I, I, P, P, P, P]),
+        "dg_ace_action": (I, [P, I, I, P, I, P, I, P, P, P]),
         "dg_net_create": (I, [P, ctypes.POINTER(P)]),
         "dg_net_destroy": (None, [P]),
         "dg_net_last_error": (ctypes.c_char_p, []),
@@ -280,6 +284,47 @@ class Context:
                                      ctypes.byref(ex), _ptr(v), stats, _stream())
         _check(code, "exchange_apply", allow_warn=True)
         return W, K, ex.value, [_stats(stats[i]) for i in range(npairs)], v
+
+    # ---- consumers: actions projected on a basis, compressed exchange
+    def _count(self, t, mesh_id):
+        nd = self.info[mesh_id]["n_dofs"]
+        if t.numel() % nd:
+            raise ValueError("field stack is not a whole number of fields")
+        return t.numel() // nd
+
+    def hartree_action(self, phi, u, vH, mesh_id=0):
+        """[nbasis, nu] matrix of (phi_i, u_a vH) by the grid's quadrature (dg_hartree_action)."""
+        nb, nu = self._count(phi, mesh_id), self._count(u, mesh_id)
+        out = torch.empty(nb * nu, dtype=torch.float64, device=phi.device)
+        _check(lib.dg_hartree_action(self._h, mesh_id, nb, _ptr(phi), nu, _ptr(u), _ptr(vH), _ptr(out), _stream()),
+               "hartree_action")
+        return out.view(nb, nu)
+
+    def exchange_action(self, phi, u, psi, g_pairs=None, mesh_id=0, keep_w=False):
+        """([nbasis, nu] matrix of (phi_i, K u_a), W or None, stats) (dg_exchange_action)."""
+        nb, nu, no = self._count(phi, mesh_id), self._count(u, mesh_id), self._count(psi, mesh_id)
+        out = torch.empty(nb * nu, dtype=torch.float64, device=phi.device)
+        W = torch.empty(nu * self.info[mesh_id]["n_dofs"], dtype=torch.float64, device=phi.device) if keep_w else None
+        stats = (DgRhsStats * (nu * no))()
+        code = lib.dg_exchange_action(self._h, mesh_id, nb, _ptr(phi), nu, _ptr(u), no, _ptr(psi), _ptr(g_pairs),
+                                      _ptr(out), _ptr(W), stats, _stream())
+        _check(code, "exchange_action", allow_warn=True)
+        return out.view(nb, nu), W, [_stats(stats[i]) for i in range(nu * no)]
+
+    def ace_build(self, psi, W, mesh_id=0):
+        """The compressed exchange vectors xi [nocc * n_dofs] (dg_ace_build)."""
+        no = self._count(psi, mesh_id)
+        xi = torch.empty_like(psi)
+        _check(lib.dg_ace_build(self._h, mesh_id, no, _ptr(psi), _ptr(W), _ptr(xi), _stream()), "ace_build")
+        return xi
+
+    def ace_action(self, phi, u, xi, mesh_id=0):
+        """[nbasis, nu] matrix of sum_k (phi_i, xi_k)(xi_k, u_a) (dg_ace_action)."""
+        nb, nu, no = self._count(phi, mesh_id), self._count(u, mesh_id), self._count(xi, mesh_id)
+        out = torch.empty(nb * nu, dtype=torch.float64, device=phi.device)
+        _check(lib.dg_ace_action(self._h, mesh_id, nb, _ptr(phi), nu, _ptr(u), no, _ptr(xi), _ptr(out), _stream()),
+               "ace_action")
+        return out.view(nb, nu)
 
     def attach_guess(self, net):
         """Use a trained Net for the initial guess of later solves (None to stop)."""

@@ -192,6 +192,18 @@ struct dg_ctx {
     long long qpart_cap = 0;
     double* qg = nullptr;
     long long qg_cap = 0;
+    // consumers (projections, exchange action, compressed exchange): work space
+    double* cpart = nullptr;   // projection partial sums
+    long long cpart_cap = 0;
+    double* crho = nullptr;    // pair sources u_a psi_s
+    long long crho_cap = 0;
+    double* cv = nullptr;      // their potentials
+    long long cv_cap = 0;
+    double* cW = nullptr;      // W_a when the caller does not take it
+    long long cW_cap = 0;
+    double* csmall = nullptr;  // small matrices (M, L^-1, ACE factors)
+    long long csmall_cap = 0;
+    int* cflag = nullptr;
 };
 
 namespace {
@@ -1442,6 +1454,12 @@ void dg_poisson_destroy(dg_ctx* ctx) {
     dfree(ctx->qrec);
     dfree(ctx->qpart);
     dfree(ctx->qg);
+    dfree(ctx->cpart);
+    dfree(ctx->crho);
+    dfree(ctx->cv);
+    dfree(ctx->cW);
+    dfree(ctx->csmall);
+    dfree(ctx->cflag);
     delete ctx;
 }
 
@@ -1755,6 +1773,119 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
         if (E_x) *E_x = ex;
     });
     return st == DG_OK ? worst_status(st_all.data(), (int)st_all.size()) : st;
+}
+
+// ---- consumers of the potentials (Sec. 6.1, Sec. 7.2)
+
+namespace {
+
+// out = quadrature projection (phi_i, f u_a) on the mesh's finest level, on stream s.
+void project(dg_ctx* ctx, Mesh& M, int nbasis, const double* phi, int nu, const double* u, const double* f,
+             double* out, hipStream_t s) {
+    ensure_len(ctx->cpart, ctx->cpart_cap, (long long)nbasis * nu * dg::project_chunks(M.lv[0].ndof));
+    dg::launch_project(M.lv[0], nbasis, phi, nu, u, f, ctx->cpart, out, s);
+}
+
+}  // namespace
+
+dg_status dg_hartree_action(dg_ctx* ctx, int mesh_id, int nbasis, const double* phi, int nu, const double* u,
+                            const double* vH, double* out, hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        if (nbasis < 1 || nu < 1 || (long long)nbasis * nu > (1LL << 24)) throw ArgError("bad nbasis or nu");
+        if (!phi || !u || !vH || !out) throw ArgError("null pointer argument");
+        const hipStream_t user = stream;
+        stream = enter(ctx, user);
+        project(ctx, ctx->meshes[mesh_id], nbasis, phi, nu, u, vH, out, stream);
+        HIPCHK(hipGetLastError());
+        leave(ctx, user);
+    });
+}
+
+dg_status dg_exchange_action(dg_ctx* ctx, int mesh_id, int nbasis, const double* phi, int nu, const double* u,
+                             int nocc, const double* psi, const double* g_pairs, double* out, double* W,
+                             dg_rhs_stats* stats, hipStream_t stream) {
+    std::vector<dg_rhs_stats> all;
+    dg_status solve_status = DG_OK;
+    dg_status st = run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        if (nbasis < 1 || nu < 1 || nocc < 1 || nocc > 64 || nu * nocc > 4096 || (long long)nbasis * nu > (1LL << 24))
+            throw ArgError("bad nbasis, nu or nocc");
+        if (!phi || !u || !psi || !out) throw ArgError("null pointer argument");
+        const hipStream_t user = stream;
+        stream = enter(ctx, user);
+        Mesh& M = ctx->meshes[mesh_id];
+        const long long n0 = M.lv[0].ndof;
+        const int npairs = nu * nocc;
+        ensure_len(ctx->crho, ctx->crho_cap, n0 * npairs);
+        ensure_len(ctx->cv, ctx->cv_cap, n0 * npairs);
+        dg::launch_cross_products(n0, nu, nocc, u, psi, ctx->crho, stream);
+        // the pair problems, solved as one batch of the mesh (quadrature data when none is given)
+        std::vector<int> ids(npairs, mesh_id);
+        all.assign(npairs, dg_rhs_stats{});
+        solve_status = dg_poisson_solve_batch(ctx, npairs, ids.data(), ctx->crho, g_pairs, nullptr, ctx->cv,
+                                              all.data(), stream);
+        if (solve_status < 0) throw std::runtime_error(std::string("pair solves: ") + g_err);
+        double* w = W;
+        if (!w) {
+            ensure_len(ctx->cW, ctx->cW_cap, n0 * nu);
+            w = ctx->cW;
+        }
+        dg::launch_cross_w(n0, nu, nocc, psi, ctx->cv, w, stream);
+        project(ctx, M, nbasis, phi, nu, w, nullptr, out, stream);
+        HIPCHK(hipStreamSynchronize(stream));
+        HIPCHK(hipGetLastError());
+        leave(ctx, user);
+        if (stats) std::copy(all.begin(), all.end(), stats);
+    });
+    return st == DG_OK ? solve_status : st;
+}
+
+dg_status dg_ace_build(dg_ctx* ctx, int mesh_id, int nocc, const double* psi, const double* W, double* xi,
+                       hipStream_t stream) {
+    int bad = 0;
+    dg_status st = run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        if (nocc < 1 || nocc > 64) throw ArgError("nocc must be in 1..64");
+        if (!psi || !W || !xi) throw ArgError("null pointer argument");
+        const hipStream_t user = stream;
+        stream = enter(ctx, user);
+        Mesh& M = ctx->meshes[mesh_id];
+        ensure_len(ctx->csmall, ctx->csmall_cap, 2LL * nocc * nocc);
+        if (!ctx->cflag) ctx->cflag = dalloc<int>(1);
+        double* Mm = ctx->csmall;
+        double* T = ctx->csmall + (long long)nocc * nocc;
+        project(ctx, M, nocc, psi, nocc, W, nullptr, Mm, stream);  // M_kl = (psi_k, W_l)
+        dg::launch_ace_factor(nocc, Mm, T, ctx->cflag, stream);
+        dg::launch_ace_combine(M.lv[0].ndof, nocc, T, W, xi, stream);
+        HIPCHK(hipMemcpyAsync(&bad, ctx->cflag, sizeof(int), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        HIPCHK(hipGetLastError());
+        leave(ctx, user);
+        if (bad) set_err("exchange overlap matrix (psi_k, W_l) is not positive definite");
+    });
+    return st == DG_OK && bad ? DG_ERR_BREAKDOWN : st;
+}
+
+dg_status dg_ace_action(dg_ctx* ctx, int mesh_id, int nbasis, const double* phi, int nu, const double* u, int nocc,
+                        const double* xi, double* out, hipStream_t stream) {
+    return run_guarded([&] {
+        check_mesh_id(ctx, mesh_id);
+        if (nbasis < 1 || nu < 1 || nocc < 1 || nocc > 64 || (long long)nbasis * nu > (1LL << 24))
+            throw ArgError("bad nbasis, nu or nocc");
+        if (!phi || !u || !xi || !out) throw ArgError("null pointer argument");
+        const hipStream_t user = stream;
+        stream = enter(ctx, user);
+        Mesh& M = ctx->meshes[mesh_id];
+        ensure_len(ctx->csmall, ctx->csmall_cap, (long long)nocc * (nbasis + nu));
+        double* A = ctx->csmall;                         // (phi_i, xi_k)   [nbasis][nocc]
+        double* B = ctx->csmall + (long long)nbasis * nocc;  // (xi_k, u_a) [nocc][nu]
+        project(ctx, M, nbasis, phi, nocc, xi, nullptr, A, stream);
+        project(ctx, M, nocc, xi, nu, u, nullptr, B, stream);
+        dg::launch_small_gemm(nbasis, nocc, nu, A, B, out, stream);
+        HIPCHK(hipGetLastError());
+        leave(ctx, user);
+    });
 }
 
 dg_status dg_pair_densities(long long n_dofs, int norb, int first_pair, int npairs, const double* phi, double* rho,

@@ -231,6 +231,26 @@ constexpr int GROUP_SYNC_FAILED = 3;
 void launch_group_pcg(const FusedMeshDev* M, int K, int nrhs, const double* b, double* x, RhsState* st, double* ws,
                       unsigned* sync, bool has_x0, bool guard, long long spin, hipStream_t s);
 
+// Consumers of the grid potentials (dg_consumers.hip).  Quadrature weight of a node: the product
+// of the level's three 1D lumped masses.
+// out[i * nu + a] = sum_q w_q f_q phi_i(q) u_a(q) over the nodes of level L (f null: 1), fields
+// packed [nbasis][ndof] and [nu][ndof]; partial: nbasis * nu * project_chunks(L.ndof) doubles.
+int project_chunks(long long ndof);
+void launch_project(const LevelHost& L, int nbasis, const double* phi, int nu, const double* u, const double* f,
+                    double* partial, double* out, hipStream_t s);
+// rho[a * nocc + s] = u_a psi_s
+void launch_cross_products(long long ndof, int nu, int nocc, const double* u, const double* psi, double* rho,
+                           hipStream_t s);
+// W[a] = sum_s psi_s v[a * nocc + s]
+void launch_cross_w(long long ndof, int nu, int nocc, const double* psi, const double* v, double* W, hipStream_t s);
+// One work-group: T = L^-1 for the Cholesky factor L of the symmetric part of M (n x n, n <= 64);
+// flag[0] = 1 when M is not positive definite.
+void launch_ace_factor(int n, const double* M, double* T, int* flag, hipStream_t s);
+// xi[k] = sum_{j <= k} T[k][j] W[j]
+void launch_ace_combine(long long ndof, int n, const double* T, const double* W, double* xi, hipStream_t s);
+// C = A B for small row-major matrices (ni x nk) (nk x na)
+void launch_small_gemm(int ni, int nk, int na, const double* A, const double* B, double* C, hipStream_t s);
+
 // Dirichlet data by quadrature (dg_boundary.hip): g[s][b] = sum_q W_q f_s(x_q) / |r_b - x_q| over the
 // finest level's nodes, for nsrc sources f (packed fields) or, with f null, the pair products
 // phi[pi[s]] phi[pj[s]].  Sources go in tiles of R; each tile is packed into rec (rec_len
