@@ -19,47 +19,57 @@ namespace dg {
 namespace {
 
 constexpr int PJ_THREADS = 256;
-constexpr int PJ_NODES = 16;  // nodes per thread per chunk: a chunk is 4,096 nodes
-
-// Weight of node q (element-major) on the level: the product of the three 1D lumped masses.
-__device__ __forceinline__ double node_weight(const LevelDev<double>& L, int n, long long q) {
-    const int n3 = n * n * n;
-    const int l = (int)(q % n3);
-    return L.ax[0].m[l % n] * L.ax[1].m[(l / n) % n] * L.ax[2].m[l / (n * n)];
-}
+constexpr int PJ_NODES = 32;  // nodes per thread per chunk: a chunk is 8,192 nodes
+constexpr int PJ_MAXN3 = 512;  // nodes per element (degree <= 7)
 
 // partial[(i * nu + a) * nchunk + c] = sum over the nodes q of chunk c of w_q f_q phi_i(q) u_a(q),
 // for the TI x TA block of (i, a) of this work-group (f null: 1).  Work-groups of one chunk are
-// consecutive, so the chunk's u and f come from L2 after the first.
+// consecutive, so the chunk's u and f come from L2 after the first.  The weight of a node depends
+// only on its local index in the element (the three 1D lumped masses of a uniform mesh), staged
+// in LDS per work-group.  Indices within one field are 32-bit (a field has < 2^31 nodes).
 template <int TI, int TA>
-__global__ __launch_bounds__(PJ_THREADS) void k_project(const LevelDev<double>* __restrict__ Lp, int n,
-                                                        long long ndof, int nbasis, const double* __restrict__ phi,
-                                                        int nu, const double* __restrict__ u,
-                                                        const double* __restrict__ f, int nchunk,
-                                                        double* __restrict__ partial) {
+__global__ __launch_bounds__(PJ_THREADS) void k_project(const LevelDev<double>* __restrict__ Lp, int n, int ndof,
+                                                        int nbasis, const double* __restrict__ phi, int nu,
+                                                        const double* __restrict__ u, const double* __restrict__ f,
+                                                        int nchunk, double* __restrict__ partial) {
     __shared__ double red[PJ_THREADS / 64][TI * TA];
+    __shared__ double wloc[PJ_MAXN3];
     const int nti = (nbasis + TI - 1) / TI, nta = (nu + TA - 1) / TA;
     const int b = blockIdx.x;
     const int ti = b % nti, ta = (b / nti) % nta, c = b / (nti * nta);
     const int i0 = ti * TI, a0 = ta * TA;
-    const LevelDev<double>& L = *Lp;
+    const int n3 = n * n * n;
+    {
+        const LevelDev<double>& L = *Lp;
+        for (int l = threadIdx.x; l < n3; l += PJ_THREADS)
+            wloc[l] = L.ax[0].m[l % n] * L.ax[1].m[(l / n) % n] * L.ax[2].m[l / (n * n)];
+    }
+    __syncthreads();
+    const double* __restrict__ prow[TI];
+    const double* __restrict__ urow[TA];
+#pragma unroll
+    for (int r = 0; r < TI; ++r) prow[r] = phi + (long long)min(i0 + r, nbasis - 1) * ndof;
+#pragma unroll
+    for (int k = 0; k < TA; ++k) urow[k] = u + (long long)min(a0 + k, nu - 1) * ndof;
     double acc[TI][TA];
 #pragma unroll
     for (int r = 0; r < TI; ++r)
 #pragma unroll
         for (int k = 0; k < TA; ++k) acc[r][k] = 0.0;
-    const long long q0 = (long long)c * PJ_THREADS * PJ_NODES;
+    const int q0 = c * PJ_THREADS * PJ_NODES + (int)threadIdx.x;
+#pragma unroll 4
     for (int m = 0; m < PJ_NODES; ++m) {
-        const long long q = q0 + (long long)m * PJ_THREADS + threadIdx.x;
-        if (q >= ndof) break;
-        double wq = node_weight(L, n, q);
-        if (f) wq *= f[q];
+        const int q = q0 + m * PJ_THREADS;
+        const bool ok = q < ndof;
+        const int qq = ok ? q : 0;
+        double wq = ok ? wloc[qq % n3] : 0.0;
+        if (f) wq *= f[qq];
         double uv[TA];
 #pragma unroll
-        for (int k = 0; k < TA; ++k) uv[k] = (a0 + k < nu) ? wq * u[(long long)(a0 + k) * ndof + q] : 0.0;
+        for (int k = 0; k < TA; ++k) uv[k] = wq * urow[k][qq];
 #pragma unroll
         for (int r = 0; r < TI; ++r) {
-            const double pv = (i0 + r < nbasis) ? phi[(long long)(i0 + r) * ndof + q] : 0.0;
+            const double pv = prow[r][qq];
 #pragma unroll
             for (int k = 0; k < TA; ++k) acc[r][k] += pv * uv[k];
         }
@@ -196,7 +206,8 @@ void launch_project(const LevelHost& L, int nbasis, const double* phi, int nu, c
     const long long nti = (nbasis + TI - 1) / TI, nta = (nu + TA - 1) / TA;
     const long long grid = nti * nta * nchunk;
     if (grid > 0x7fffffffLL) throw std::runtime_error("projection grid too large");
-    hipLaunchKernelGGL((k_project<TI, TA>), dim3((unsigned)grid), dim3(PJ_THREADS), 0, s, L.dev64, L.n, L.ndof,
+    if (L.ndof >= 0x7fffffffLL || L.n * L.n * L.n > PJ_MAXN3) throw std::runtime_error("projection: field too large");
+    hipLaunchKernelGGL((k_project<TI, TA>), dim3((unsigned)grid), dim3(PJ_THREADS), 0, s, L.dev64, L.n, (int)L.ndof,
                        nbasis, phi, nu, u, f, nchunk, partial);
     launch_sum_partials(nbasis * nu, partial, nchunk, nchunk, out, s);
 }
