@@ -399,6 +399,11 @@ dg_status dg_net_set_params(dg_net* net, const float* params, long long n);
 dg_status dg_net_get_params(const dg_net* net, float* params, long long n);
 /* y = net(x) for `batch` tensors on an ne[0] x ne[1] x ne[2] element grid (device). */
 dg_status dg_net_forward(dg_net* net, int batch, const int* ne, const float* x, float* y, hipStream_t stream);
+/* y = net(x) as the guess evaluates it: convolutions on the matrix cores (BF16 operands, FP32
+ * accumulation) with BF16 activations between layers (each layer's output rounded to nearest
+ * even), the last layer's output in FP32; x is rounded to BF16 first.  Leaves the training
+ * state alone (a backward needs dg_net_forward). */
+dg_status dg_net_infer(dg_net* net, int batch, const int* ne, const float* x, float* y, hipStream_t stream);
 /* Gradient of sum(y * dy) for the last forward; grad (device, may be NULL) receives it. */
 dg_status dg_net_backward(dg_net* net, const float* dy, float* grad, hipStream_t stream);
 /* Forward convolutions on the matrix cores with BF16 operands and FP32
@@ -421,7 +426,8 @@ dg_status dg_net_train_step(dg_net* net, dg_ctx* ctx, int mesh_id, int batch, co
  * FP64 packed fields).  The network's output is a field on multigrid level 1
  * (one channel per node of that level's element); C averages every node
  * shared by neighbouring elements over its copies (continuous field), P is
- * the level-1 to level-0 interpolation of the V-cycle. */
+ * the level-1 to level-0 interpolation of the V-cycle.  With the matrix-core path on (the
+ * default) the network is evaluated as dg_net_infer does: BF16 activations. */
 dg_status dg_net_guess(dg_net* net, const dg_ctx* ctx, int mesh_id, int batch, const double* rho, double* v0,
                        hipStream_t stream);
 /* Flat binary weight file: "DGNET001", 4 ints of configuration, count, floats. */

@@ -90,6 +90,7 @@ def _load():
         "dg_net_get_params": (I, [P, P, LL]),
         "dg_net_forward": (I, [P, I, P, P, P, P]),
         "dg_net_backward": (I, [P, P, P, P]),
+        "dg_net_infer": (I, [P, I, P, P, P, P]),
         "dg_net_adam": (I, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),
         "dg_net_prepare_input": (I, [P, I, LL, P, P, P, P]),
         "dg_net_train_step": (I, [P, P, I, I, P, P, ctypes.c_float, I, ctypes.POINTER(D), P]),
@@ -479,6 +480,14 @@ class Net:
         y = torch.empty(batch * ne[0] * ne[1] * ne[2] * self.out_channels, dtype=torch.float32, device=x.device)
         _ncheck(lib.dg_net_forward(self._h, batch, ne_c, _ptr_t(x, torch.float32), _ptr_t(y, torch.float32),
                                    _stream()), "net_forward")
+        return y
+
+    def infer(self, x, ne, batch):
+        """The guess's forward: matrix cores with BF16 activations (dg_net_infer)."""
+        ne_c = (ctypes.c_int * 3)(*ne)
+        y = torch.empty(batch * ne[0] * ne[1] * ne[2] * self.out_channels, dtype=torch.float32, device=x.device)
+        _ncheck(lib.dg_net_infer(self._h, batch, ne_c, _ptr_t(x, torch.float32), _ptr_t(y, torch.float32),
+                                 _stream()), "net_infer")
         return y
 
     def backward(self, dy):

@@ -93,9 +93,21 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ x, c
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int KS, int STRIDE, int NB>
-__global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ x, const __bf16* __restrict__ Wt,
-                                                   const float* __restrict__ bias, float* __restrict__ y, int D, int H,
+// Eight consecutive channels of one voxel as BF16 operands (RNE conversion of FP32 activations;
+// BF16 activations as they are).  p is 16-byte aligned.
+__device__ __forceinline__ bf16x8 load8_bf16(const float* p) {
+    const float4 v0 = *reinterpret_cast<const float4*>(p);
+    const float4 v1 = *reinterpret_cast<const float4*>(p + 4);
+    bf16x8 a;
+    a[0] = (__bf16)v0.x; a[1] = (__bf16)v0.y; a[2] = (__bf16)v0.z; a[3] = (__bf16)v0.w;
+    a[4] = (__bf16)v1.x; a[5] = (__bf16)v1.y; a[6] = (__bf16)v1.z; a[7] = (__bf16)v1.w;
+    return a;
+}
+__device__ __forceinline__ bf16x8 load8_bf16(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+template <int KS, int STRIDE, int NB, typename TX = float, typename TY = float>
+__global__ __launch_bounds__(256) void k_conv_mfma(const TX* __restrict__ x, const __bf16* __restrict__ Wt,
+                                                   const float* __restrict__ bias, TY* __restrict__ y, int D, int H,
                                                    int Wd, int Ci, int CiP, int Do, int Ho, int Wo, int Co,
                                                    int relu) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -111,21 +123,18 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ x, 
     f32x4 acc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const float* xb = x + (long long)b * D * H * Wd * Ci;
+    const TX* xb = x + (long long)b * D * H * Wd * Ci;
     const bool vec = (Ci % 8) == 0;
     for (int t = 0; t < KS * KS * KS; ++t) {
         const int dz = t / (KS * KS), dy = (t / KS) % KS, dx = t % KS;
         const int iz = oz * STRIDE - PAD + dz, iy = oy * STRIDE - PAD + dy, ix = ox * STRIDE - PAD + dx;
         const bool valid = ov && iz >= 0 && iz < D && iy >= 0 && iy < H && ix >= 0 && ix < Wd;
-        const float* xv = xb + (long long)((valid ? (iz * H + iy) * Wd + ix : 0)) * Ci;
+        const TX* xv = xb + (long long)((valid ? (iz * H + iy) * Wd + ix : 0)) * Ci;
         for (int cc = 0; cc < CiP; cc += 32) {
             const int ci0 = cc + 8 * kb;
             bf16x8 a;
             if (vec && valid && ci0 + 8 <= Ci) {
-                const float4 v0 = *reinterpret_cast<const float4*>(xv + ci0);
-                const float4 v1 = *reinterpret_cast<const float4*>(xv + ci0 + 4);
-                a[0] = (__bf16)v0.x; a[1] = (__bf16)v0.y; a[2] = (__bf16)v0.z; a[3] = (__bf16)v0.w;
-                a[4] = (__bf16)v1.x; a[5] = (__bf16)v1.y; a[6] = (__bf16)v1.z; a[7] = (__bf16)v1.w;
+                a = load8_bf16(xv + ci0);
             } else if (valid && ci0 + 8 <= Ci) {  // whole chunk in range, rows not 16-byte aligned
 #pragma unroll
                 for (int q = 0; q < 8; ++q) a[q] = (__bf16)xv[ci0 + q];
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ x, 
             const int o2 = vox0 + 4 * kb + r;
             if (o2 < nvo) {
                 const float v = acc[nb][r] + bco;
-                y[((long long)b * nvo + o2) * Co + co] = relu ? fmaxf(v, 0.f) : v;
+                y[((long long)b * nvo + o2) * Co + co] = (TY)(relu ? fmaxf(v, 0.f) : v);
             }
         }
     }
@@ -190,9 +199,9 @@ __host__ __device__ inline ConvBox conv_box(int v0, int v1, int H, int W) {
     return b;
 }
 
-template <int NB>
-__global__ __launch_bounds__(256) void k_conv3_lds(const float* __restrict__ x, const __bf16* __restrict__ Wt,
-                                                   const float* __restrict__ bias, float* __restrict__ y, int D, int H,
+template <int NB, typename TX = float, typename TY = float>
+__global__ __launch_bounds__(256) void k_conv3_lds(const TX* __restrict__ x, const __bf16* __restrict__ Wt,
+                                                   const float* __restrict__ bias, TY* __restrict__ y, int D, int H,
                                                    int Wd, int Ci, int CiP, int Co, int relu) {
     extern __shared__ __attribute__((aligned(16))) unsigned char conv_lds[];
     bf16x8* sx = reinterpret_cast<bf16x8*>(conv_lds);  // [box voxel][4 groups of 8 channels]
@@ -216,7 +225,7 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const float* __restrict__ x, 
     for (int q = 0; q < CV_MB; ++q)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[q][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const float* xb = x + (long long)b * nvo * Ci;
+    const TX* xb = x + (long long)b * nvo * Ci;
     const bool vec = (Ci % 8) == 0;
     for (int cc = 0; cc < CiP; cc += 32) {
         if (cc) __syncthreads();  // the previous chunk's reads are done
@@ -226,12 +235,9 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const float* __restrict__ x, 
             const int ci0 = cc + 8 * g;
             bf16x8 a;
             const bool inside = ix >= 0 && ix < Wd && iy >= 0 && iy < H && iz >= 0 && iz < D;
-            const float* xv = xb + (long long)((inside ? (iz * H + iy) * Wd + ix : 0)) * Ci;
+            const TX* xv = xb + (long long)((inside ? (iz * H + iy) * Wd + ix : 0)) * Ci;
             if (inside && vec && ci0 + 8 <= Ci) {
-                const float4 p0 = *reinterpret_cast<const float4*>(xv + ci0);
-                const float4 p1 = *reinterpret_cast<const float4*>(xv + ci0 + 4);
-                a[0] = (__bf16)p0.x; a[1] = (__bf16)p0.y; a[2] = (__bf16)p0.z; a[3] = (__bf16)p0.w;
-                a[4] = (__bf16)p1.x; a[5] = (__bf16)p1.y; a[6] = (__bf16)p1.z; a[7] = (__bf16)p1.w;
+                a = load8_bf16(xv + ci0);
             } else {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) a[q] = (inside && ci0 + q < Ci) ? (__bf16)xv[ci0 + q] : (__bf16)0.f;
@@ -268,7 +274,7 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const float* __restrict__ x, 
                 const int o2 = vb + 4 * kb + r;
                 if (o2 < v1) {
                     const float v = acc[q][nb][r] + bco;
-                    y[((long long)b * nvo + o2) * Co + co] = relu ? fmaxf(v, 0.f) : v;
+                    y[((long long)b * nvo + o2) * Co + co] = (TY)(relu ? fmaxf(v, 0.f) : v);
                 }
             }
         }
@@ -410,7 +416,8 @@ __global__ __launch_bounds__(256) void k_relu_mask(float* __restrict__ g, const 
 }
 
 // nearest x2 upsampling of [B][d][h][w][C] to [B][D][H][W][C] (D <= 2d ...)
-__global__ __launch_bounds__(256) void k_upsample(const float* __restrict__ s, float* __restrict__ u, int B, int d,
+template <typename T>
+__global__ __launch_bounds__(256) void k_upsample(const T* __restrict__ s, T* __restrict__ u, int B, int d,
                                                   int h, int w, int D, int H, int W, int C) {
     const long long n = (long long)B * D * H * W * C;
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -440,8 +447,9 @@ __global__ __launch_bounds__(256) void k_upsample_bwd(const float* __restrict__ 
 }
 
 // cat[v][0:C1] = a[v], cat[v][C1:C1+C2] = b[v]  and the reverse split (add into ga, gb when acc)
-__global__ __launch_bounds__(256) void k_concat(const float* __restrict__ a, const float* __restrict__ b,
-                                                float* __restrict__ cat, long long nv, int C1, int C2) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_concat(const T* __restrict__ a, const T* __restrict__ b,
+                                                T* __restrict__ cat, long long nv, int C1, int C2) {
     const int C = C1 + C2;
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= nv * C) return;
@@ -507,12 +515,17 @@ __global__ void k_scale_of(const double* __restrict__ part, int nblk, long long 
     const double r = sqrt(s / (double)n);
     scale[b] = r > 0.0 ? r : 1.0;
 }
+template <typename T>
 __global__ __launch_bounds__(256) void k_to_input(const double* __restrict__ a, const double* __restrict__ scale,
-                                                  float* __restrict__ x, long long n) {
+                                                  T* __restrict__ x, long long n) {
     const int b = blockIdx.y;
     const double inv = 1.0 / scale[b];
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-        x[(long long)b * n + i] = (float)(a[(long long)b * n + i] * inv);
+        x[(long long)b * n + i] = (T)(float)(a[(long long)b * n + i] * inv);
+}
+__global__ __launch_bounds__(256) void k_f2bf(const float* __restrict__ a, __bf16* __restrict__ b, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = (__bf16)a[i];
 }
 __global__ __launch_bounds__(256) void k_from_output(const float* __restrict__ y, const double* __restrict__ scale,
                                                      double* __restrict__ v, long long n) {
@@ -641,6 +654,14 @@ struct dg_net {
         long long n = 0;
     };
     std::vector<Buf> act;   // per layer output
+    // inference with BF16 activations (the guess): per layer output and decoder inputs, and the
+    // input; allocated with the FP32 set, on first use
+    struct Buf16 {
+        __bf16* d = nullptr;
+        long long n = 0;
+    };
+    std::vector<Buf16> act16, aux16;
+    Buf16 xin16;
     std::vector<Buf> aux;   // upsampled / concatenated inputs
     std::vector<Buf> grd;   // gradient work buffers
     std::vector<std::array<int, 3>> dims;  // spatial dims per level
@@ -708,7 +729,8 @@ void refresh_bf16(dg_net* net, hipStream_t s) {
     net->wt_dirty = false;
 }
 
-void conv_forward_mfma(const dg_net* net, int li, const float* x, float* y, int B, const int* din, const int* dout,
+template <typename TX, typename TY>
+void conv_forward_mfma(const dg_net* net, int li, const TX* x, TY* y, int B, const int* din, const int* dout,
                        int relu, hipStream_t s) {
     const auto& L = net->layers[li];
     const int CiP = pad_to(L.ci, 32), NB = pad_to(L.co, 16) / 16;
@@ -716,7 +738,7 @@ void conv_forward_mfma(const dg_net* net, int li, const float* x, float* y, int 
     dim3 grid((nvo + 63) / 64, B);
     const __bf16* Wt = net->wt + net->wtoff[li];
     const float* b = net->p + L.boff;
-#define CM(KS, ST, NBV) hipLaunchKernelGGL((k_conv_mfma<KS, ST, NBV>), grid, dim3(256), 0, s, x, Wt, b, y, din[0], din[1], din[2], L.ci, CiP, dout[0], dout[1], dout[2], L.co, relu)
+#define CM(KS, ST, NBV) hipLaunchKernelGGL((k_conv_mfma<KS, ST, NBV, TX, TY>), grid, dim3(256), 0, s, x, Wt, b, y, din[0], din[1], din[2], L.ci, CiP, dout[0], dout[1], dout[2], L.co, relu)
 #define CMN(KS, ST) switch (NB) { case 1: CM(KS, ST, 1); break; case 2: CM(KS, ST, 2); break; case 4: CM(KS, ST, 4); break; default: throw NetError("unsupported channel count for the matrix-core path"); }
     if (L.k == 1) { CMN(1, 1) }
     else if (L.s == 1) {
@@ -729,7 +751,7 @@ void conv_forward_mfma(const dg_net* net, int li, const float* x, float* y, int 
         const size_t lds = (size_t)maxbox * 64;
         if (lds > 64 * 1024) throw NetError("convolution input box too large for LDS");
         dim3 g3((nvo + CV_VPW - 1) / CV_VPW, B);
-#define C3(NBV) hipLaunchKernelGGL((k_conv3_lds<NBV>), g3, dim3(256), lds, s, x, Wt, b, y, din[0], din[1], din[2], L.ci, CiP, L.co, relu)
+#define C3(NBV) hipLaunchKernelGGL((k_conv3_lds<NBV, TX, TY>), g3, dim3(256), lds, s, x, Wt, b, y, din[0], din[1], din[2], L.ci, CiP, L.co, relu)
         switch (NB) {
             case 1: C3(1); break;
             case 2: C3(2); break;
@@ -789,6 +811,12 @@ void ensure_buffers(dg_net* net, int B, const int* E) {
     for (auto& b : net->act) nfree(b.d);
     for (auto& b : net->aux) nfree(b.d);
     for (auto& b : net->grd) nfree(b.d);
+    for (auto& b : net->act16) nfree(b.d);
+    for (auto& b : net->aux16) nfree(b.d);
+    net->act16.clear();
+    net->aux16.clear();
+    nfree(net->xin16.d);
+    net->xin16.n = 0;  // input16 allocates it again for the new grid
     const int Lv = net->cfg.levels, C = net->cfg.channels;
     net->dims.assign(Lv, {0, 0, 0});
     net->dims[0] = {E[2], E[1], E[0]};  // z, y, x
@@ -882,17 +910,82 @@ const float* forward(dg_net* net, int B, const int* E, const float* x, hipStream
     for (int l = Lv - 2; l >= 0; --l) {
         const std::string up = "up" + std::to_string(l), mg = "merge" + std::to_string(l);
         const long long nu = net->aux[2 * l].n;
-        hipLaunchKernelGGL(k_upsample, dim3(nblocks(nu)), dim3(256), 0, s, d, net->aux[2 * l].d, B, D(l + 1)[0],
+        hipLaunchKernelGGL(k_upsample<float>, dim3(nblocks(nu)), dim3(256), 0, s, d, net->aux[2 * l].d, B, D(l + 1)[0],
                            D(l + 1)[1], D(l + 1)[2], D(l)[0], D(l)[1], D(l)[2], C);
         run(up, net->aux[2 * l].d, A(up), D(l), D(l), 1);
         const long long nv = (long long)B * D(l)[0] * D(l)[1] * D(l)[2];
-        hipLaunchKernelGGL(k_concat, dim3(nblocks(nv * 2 * C)), dim3(256), 0, s, A(up),
+        hipLaunchKernelGGL(k_concat<float>, dim3(nblocks(nv * 2 * C)), dim3(256), 0, s, A(up),
                            A("enc" + std::to_string(l) + "b"), net->aux[2 * l + 1].d, nv, C, C);
         run(mg, net->aux[2 * l + 1].d, A(mg), D(l), D(l), 1);
         d = A(mg);
     }
     run("out", d, A("out"), D(0), D(0), 0);
     return A("out");
+}
+
+// Inference forward on the matrix cores with BF16 activations: every layer reads and writes BF16
+// (the convolutions accumulate in FP32 and round their output to nearest even), except the last,
+// whose FP32 output is the activation of "out".  The input x16 is BF16 (net->xin16).  The FP32
+// activations of the training forward are not touched, so a backward pass still needs forward().
+const float* forward16(dg_net* net, int B, const int* E, const __bf16* x16, hipStream_t s) {
+    ensure_buffers(net, B, E);
+    const int Lv = net->cfg.levels, C = net->cfg.channels;
+    if (net->act16.empty()) {
+        net->act16.assign(net->layers.size(), {});
+        for (size_t i = 0; i < net->layers.size(); ++i) {
+            net->act16[i].n = net->act[i].n;
+            net->act16[i].d = nalloc<__bf16>(net->act16[i].n);
+        }
+        net->aux16.assign(net->aux.size(), {});
+        for (size_t i = 0; i < net->aux.size(); ++i) {
+            net->aux16[i].n = net->aux[i].n;
+            net->aux16[i].d = nalloc<__bf16>(net->aux16[i].n);
+        }
+    }
+    if (net->wt_dirty) refresh_bf16(net, s);
+    auto A = [&](const std::string& n) { return net->act16[layer_index(net, n)].d; };
+    auto D = [&](int l) { return net->dims[l].data(); };
+    auto run = [&](const std::string& n, const __bf16* in, __bf16* out, const int* din, const int* dout, int relu) {
+        conv_forward_mfma<__bf16, __bf16>(net, layer_index(net, n), in, out, B, din, dout, relu, s);
+    };
+    run("in", x16, A("in"), D(0), D(0), 1);
+    const __bf16* h = A("in");
+    for (int l = 0; l < Lv; ++l) {
+        const std::string a = "enc" + std::to_string(l) + "a", b = "enc" + std::to_string(l) + "b";
+        run(a, h, A(a), D(l), D(l), 1);
+        run(b, A(a), A(b), D(l), D(l), 1);
+        if (l < Lv - 1) {
+            const std::string dn = "down" + std::to_string(l);
+            run(dn, A(b), A(dn), D(l), D(l + 1), 1);
+            h = A(dn);
+        }
+    }
+    const __bf16* d = A("enc" + std::to_string(Lv - 1) + "b");
+    for (int l = Lv - 2; l >= 0; --l) {
+        const std::string up = "up" + std::to_string(l), mg = "merge" + std::to_string(l);
+        const long long nu = net->aux16[2 * l].n;
+        hipLaunchKernelGGL(k_upsample<__bf16>, dim3(nblocks(nu)), dim3(256), 0, s, d, net->aux16[2 * l].d, B,
+                           D(l + 1)[0], D(l + 1)[1], D(l + 1)[2], D(l)[0], D(l)[1], D(l)[2], C);
+        run(up, net->aux16[2 * l].d, A(up), D(l), D(l), 1);
+        const long long nv = (long long)B * D(l)[0] * D(l)[1] * D(l)[2];
+        hipLaunchKernelGGL(k_concat<__bf16>, dim3(nblocks(nv * 2 * C)), dim3(256), 0, s, A(up),
+                           A("enc" + std::to_string(l) + "b"), net->aux16[2 * l + 1].d, nv, C, C);
+        run(mg, net->aux16[2 * l + 1].d, A(mg), D(l), D(l), 1);
+        d = A(mg);
+    }
+    float* out = net->act[layer_index(net, "out")].d;
+    conv_forward_mfma<__bf16, float>(net, layer_index(net, "out"), d, out, B, D(0), D(0), 0, s);
+    return out;
+}
+
+__bf16* input16(dg_net* net, long long n) {
+    if (!net->xin16.d || net->xin16.n < n) {
+        NCHK(hipDeviceSynchronize());
+        nfree(net->xin16.d);
+        net->xin16.d = nalloc<__bf16>(n);
+        net->xin16.n = n;
+    }
+    return net->xin16.d;
 }
 
 // Backward pass for upstream gradient dy of the output; fills net->g.
@@ -917,7 +1010,7 @@ void backward(dg_net* net, const float* dy, hipStream_t s) {
         hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, g2, A(up), nv(l) * C);
         // input of up_l is upsample(d_{l+1}); recompute it into g3 for the weight gradient
         const float* dsrc = (l + 1 == Lv - 1) ? A("enc" + std::to_string(l + 1) + "b") : A("merge" + std::to_string(l + 1));
-        hipLaunchKernelGGL(k_upsample, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, dsrc, g3, B, D(l + 1)[0],
+        hipLaunchKernelGGL(k_upsample<float>, dim3(nblocks(nv(l) * C)), dim3(256), 0, s, dsrc, g3, B, D(l + 1)[0],
                            D(l + 1)[1], D(l + 1)[2], D(l)[0], D(l)[1], D(l)[2], C);
         conv_backward(net, Ly(up), g3, g2, g1, B, D(l), D(l), s);  // g1 = grad of the upsampled tensor
         hipLaunchKernelGGL(k_upsample_bwd, dim3(nblocks(nv(l + 1) * C)), dim3(256), 0, s, g1, g0, B, D(l + 1)[0],
@@ -996,6 +1089,9 @@ void dg_net_destroy(dg_net* net) {
     for (auto& b : net->act) nfree(b.d);
     for (auto& b : net->aux) nfree(b.d);
     for (auto& b : net->grd) nfree(b.d);
+    for (auto& b : net->act16) nfree(b.d);
+    for (auto& b : net->aux16) nfree(b.d);
+    nfree(net->xin16.d);
     nfree(net->xin.d);
     nfree(net->wt);
     nfree(net->p); nfree(net->g); nfree(net->m); nfree(net->v); nfree(net->part);
@@ -1030,6 +1126,20 @@ dg_status dg_net_forward(dg_net* net, int batch, const int* ne, const float* x, 
         const float* out = forward(net, batch, ne, x, stream);
         const long long n = (long long)batch * ne[0] * ne[1] * ne[2] * net->cfg.out_channels;
         NCHK(hipMemcpyAsync(y, out, sizeof(float) * n, hipMemcpyDeviceToDevice, stream));
+        NCHK(hipGetLastError());
+    });
+}
+
+dg_status dg_net_infer(dg_net* net, int batch, const int* ne, const float* x, float* y, hipStream_t stream) {
+    return net_guard([&] {
+        if (!net || !ne || !x || !y || batch < 1 || ne[0] < 1 || ne[1] < 1 || ne[2] < 1) throw NetError("bad arguments");
+        const long long nx = (long long)batch * ne[0] * ne[1] * ne[2] * net->cfg.in_channels;
+        ensure_buffers(net, batch, ne);  // first: a new grid frees the BF16 input buffer
+        __bf16* x16 = input16(net, nx);
+        hipLaunchKernelGGL(k_f2bf, dim3(nblocks(nx)), dim3(256), 0, stream, x, x16, nx);
+        const float* out = forward16(net, batch, ne, x16, stream);
+        const long long ny = (long long)batch * ne[0] * ne[1] * ne[2] * net->cfg.out_channels;
+        NCHK(hipMemcpyAsync(y, out, sizeof(float) * ny, hipMemcpyDeviceToDevice, stream));
         NCHK(hipGetLastError());
     });
 }
@@ -1211,7 +1321,7 @@ dg_status dg_net_prepare_input(dg_net* net, int batch, long long n_dofs, const d
         const int nb = 64;
         hipLaunchKernelGGL(k_sumsq, dim3(nb, batch), dim3(256), 0, stream, rho, net->dpart, n_dofs);
         hipLaunchKernelGGL(k_scale_of, dim3(batch), dim3(64), 0, stream, net->dpart, nb, n_dofs, scale);
-        hipLaunchKernelGGL(k_to_input, dim3(nb, batch), dim3(256), 0, stream, rho, scale, x, n_dofs);
+        hipLaunchKernelGGL(k_to_input<float>, dim3(nb, batch), dim3(256), 0, stream, rho, scale, x, n_dofs);
         NCHK(hipGetLastError());
     });
 }
@@ -1293,8 +1403,16 @@ dg_status dg_net_guess(dg_net* net, const dg_ctx* ctx, int mesh_id, int batch, c
         const int nb = 64;
         hipLaunchKernelGGL(k_sumsq, dim3(nb, batch), dim3(256), 0, stream, rho, net->dpart, n_dofs);
         hipLaunchKernelGGL(k_scale_of, dim3(batch), dim3(64), 0, stream, net->dpart, nb, n_dofs, net->scale);
-        hipLaunchKernelGGL(k_to_input, dim3(nb, batch), dim3(256), 0, stream, rho, net->scale, net->xin.d, n_dofs);
-        const float* y = forward(net, batch, ne, net->xin.d, stream);
+        const float* y;
+        if (net->bf16) {  // matrix cores with BF16 activations
+            __bf16* x16 = input16(net, n_dofs * batch);
+            hipLaunchKernelGGL(k_to_input<__bf16>, dim3(nb, batch), dim3(256), 0, stream, rho, net->scale, x16, n_dofs);
+            y = forward16(net, batch, ne, x16, stream);
+        } else {          // FP32 vector path
+            hipLaunchKernelGGL(k_to_input<float>, dim3(nb, batch), dim3(256), 0, stream, rho, net->scale, net->xin.d,
+                               n_dofs);
+            y = forward(net, batch, ne, net->xin.d, stream);
+        }
         output_map_scaled(L0, L1, batch, y, v0, net->w1, net->w2, net->scale, stream);
         NCHK(hipGetLastError());
     });

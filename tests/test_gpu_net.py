@@ -51,6 +51,29 @@ def test_forward_backward_match_oracle(gpu_lib, levels, E):
     assert np.abs(g - g_ref).max() <= 2e-4 * np.abs(g_ref).max()
 
 
+@pytest.mark.parametrize("levels,E,C,cin", [(3, (6, 4, 5), 8, 27), (4, (8, 8, 8), 32, 125), (2, (5, 3, 4), 16, 64)])
+def test_inference_with_bf16_activations(gpu_lib, levels, E, C, cin):
+    """The guess's forward stores every activation in BF16 (half the bytes of FP32).  The
+    matrix-core convolutions round their FP32 operands to BF16 (nearest even) on load, so rounding
+    them once when they are stored gives the same operands: the output equals the FP32-activation
+    matrix-core forward bit for bit, and stays within the BF16 bound of the oracle network."""
+    specs = convnet.layer_specs(levels, C, cin, 27)
+    n = convnet.param_count(specs)
+    rng = np.random.default_rng(100 + levels)
+    params = (0.3 * rng.standard_normal(n) / np.sqrt(C)).astype(np.float32)
+    net = gpu_lib.Net(levels, C, cin, 27)
+    net.set_params(params)
+    net.set_bf16(True)
+    B = 2
+    x = rng.standard_normal((B, E[2], E[1], E[0], cin)).astype(np.float32)
+    y16 = net.infer(_t(x, np.float32), E, B).cpu().numpy()
+    yb = net.forward(_t(x, np.float32), E, B).cpu().numpy()
+    assert np.array_equal(y16, yb)
+    y_ref, _ = convnet.forward(params.astype(np.float64), specs, levels, x.astype(np.float64))
+    y16 = y16.reshape(y_ref.shape)
+    assert np.abs(y16 - y_ref).max() <= 3e-2 * np.abs(y_ref).max()
+
+
 def _continuize_1d(E, n):
     """1D averaging of the two copies of every node shared by neighbouring elements."""
     N = E * n
