@@ -41,7 +41,8 @@ POT_BAR, ENERGY_BAR = 1e-8, 1e-10
 HELDOUT_RHS = 128
 # arithmetic each precision mode computes in (the "dtype" field of the JSON line)
 DTYPE_OF = {"fp64": "f64", "fp32_ir": "f64 refinement + f32 inner PCG", "fp32_pc": "f64 CG + f32 V-cycle",
-            "bf16_pc": "f64 flexible CG + f32 V-cycle, bf16 matrix-core x/y contractions in level-0 smoothing"}
+            "bf16_pc": "f64 flexible CG + f32 V-cycle, bf16 matrix-core x/y contractions in level-0 smoothing",
+            "bf16f_pc": "f64 CG + f32-arithmetic V-cycle with bf16 finest-level fields"}
 
 
 def parse():
@@ -61,7 +62,7 @@ def parse():
                          "consumers: Hartree/exchange actions projected on a 256-function basis and the "
                          "compressed exchange on the exchange8 mesh")
     ap.add_argument("--arms", default="fp32_pc+learned,fp32_pc,fp64+learned,fp64,fp32_pc+untrained",
-                    help="precision fp32_pc, bf16_pc, fp32_ir or fp64, optionally +learned (trained guess) or "
+                    help="precision fp32_pc, bf16f_pc, bf16_pc, fp32_ir or fp64, optionally +learned (trained guess) or "
                          "+untrained (the same network with random weights, a control); the first is the headline")
     ap.add_argument("--rtol", type=float, default=OPERATING_RTOL, help="FP64 relative residual of every arm")
     ap.add_argument("--metric-rtol", type=float, default=1e-8,
@@ -341,6 +342,8 @@ def measure_roofline(W, arm, args, inputs, net_cache):
     achieved = prof["bytes"] / prof["seconds"] / 1e9
     copy_gbs = copy_bandwidth()
     fp = "float" if prec != "fp64" else "double"
+    if prec == "bf16f_pc":
+        fp = "float, ..., __bf16"  # FP32 arithmetic on BF16 fields
     traffic_file = {"heldout32": "cheb_step_heldout32.md", "exchange8": "cheb_step_exchange8.md"}.get(W.name)
     return {
         "bound": "hbm",
@@ -350,7 +353,7 @@ def measure_roofline(W, arm, args, inputs, net_cache):
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
         "algorithmic_bytes_per_launch": prof["bytes"] / prof["launches"],
         "bytes_counted": "per step and right-hand side still iterating: read z, f (and z_prev after the first "
-                         "step), write z': 3 or 4 fields of the finest level",
+                         "step), write z': 3 or 4 fields of the finest level, at the size of their storage type",
         "avg_launch_us": 1e6 * prof["seconds"] / prof["launches"],
         "launches": prof["launches"],
         "timing_source": "HIP events on the solver's stream around each launch, eager launches on one lane, "

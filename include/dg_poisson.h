@@ -89,8 +89,20 @@ typedef enum {
  * line contractions on the matrix cores with BF16 operands and FP32
  * accumulation (degree-4 meshes; other degrees run the FP32 kernels).  The
  * preconditioner is then no longer exactly symmetric, so the FP64 CG takes
- * the flexible (Polak-Ribiere) beta. */
-typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_IR = 1, DG_PREC_FP32_PC = 2, DG_PREC_BF16_PC = 3 } dg_precision;
+ * the flexible (Polak-Ribiere) beta.
+ * BF16F_PC: FP32_PC whose finest-level V-cycle fields (its source, the residual handed over by the
+ * CG update, and the smoother iterates) are stored in BF16 (rounded to nearest even), read into
+ * FP32 arithmetic: half the bytes of the level that carries most of the V-cycle's traffic.  The
+ * coarser levels, the coarsest solve and the whole CG (iterate, residual, direction, dots) are
+ * as in FP32_PC, so a solve stopped at a residual keeps the FP64 solver's accuracy.  Degree-4
+ * finest levels whose next level is their degree-2 step; other hierarchies run as FP32_PC. */
+typedef enum {
+    DG_PREC_FP64 = 0,
+    DG_PREC_FP32_IR = 1,
+    DG_PREC_FP32_PC = 2,
+    DG_PREC_BF16_PC = 3,
+    DG_PREC_BF16F_PC = 4
+} dg_precision;
 
 /* A uniform hexahedral mesh: ne[d] elements along axis d on [lo[d], hi[d]],
  * Gauss-Lobatto nodal polynomials of degree p (1 <= p <= 7). */

@@ -17,9 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("DG_POISSON_LIB", os.path.join(_HERE, "libdgpoisson.so"))
 
 DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
-DG_PREC_FP64, DG_PREC_FP32_IR, DG_PREC_FP32_PC, DG_PREC_BF16_PC = 0, 1, 2, 3
+DG_PREC_FP64, DG_PREC_FP32_IR, DG_PREC_FP32_PC, DG_PREC_BF16_PC, DG_PREC_BF16F_PC = 0, 1, 2, 3, 4
 PRECISIONS = {"fp64": DG_PREC_FP64, "fp32_ir": DG_PREC_FP32_IR, "fp32_pc": DG_PREC_FP32_PC,
-              "bf16_pc": DG_PREC_BF16_PC}
+              "bf16_pc": DG_PREC_BF16_PC, "bf16f_pc": DG_PREC_BF16F_PC}
 
 
 class DgMesh(ctypes.Structure):

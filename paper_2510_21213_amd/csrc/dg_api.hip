@@ -121,21 +121,22 @@ struct dg_ctx {
         dg::RhsState* st_in = nullptr;   // inner FP32 state
         dg::RhsState* st_host = nullptr; // pinned host mirror
         int cap_b = 0, cap_st = 0;
-        // captured PCG iterations, per kind of run (index 0: FP64, 1: FP32 inner solve, 2: FP32_PC, 3: BF16_PC)
+        // captured PCG iterations, per kind of run (index 0: FP64, 1: FP32 inner solve, 2: FP32_PC, 3: BF16_PC,
+        // 4: BF16F_PC)
         struct Graph {
             hipGraphExec_t exec = nullptr;
             int nrhs = 0, every = 0;
             bool prof = false;
             std::vector<hipEvent_t> ev;
             size_t nev = 0;
-        } graph[4];
+        } graph[5];
         // multi-mesh batches: the mesh's own stream and completion event, and its
         // right-hand sides gathered from the caller's packing when they are not contiguous
         hipStream_t stream = nullptr;
         hipEvent_t ev_done = nullptr;
         // iterations the k-th PCG run of the last solve needed (per kind of run): the next
         // solve replays that many before its first host check
-        std::vector<int> pred[4];
+        std::vector<int> pred[5];
         // timing events of eager launches driven by this solver instance
         std::vector<hipEvent_t> pev;
         size_t pused = 0;
@@ -350,11 +351,23 @@ void prof_sum(const std::vector<hipEvent_t>& ev, size_t used) {
     }
 }
 
+// BF16F_PC keeps the finest level's V-cycle fields in BF16 where the kernels exist for it: a
+// degree-4 finest level with a coarser level below that is its degree-2 step (on other
+// hierarchies the mode runs as FP32_PC).
+bool lp_fields(const dg_ctx* ctx, const Mesh& M) {
+    if (ctx->opts.precision != DG_PREC_BF16F_PC || M.lv.size() < 2) return false;
+    const LevelHost& L0 = M.lv[0];
+    const LevelHost& L1 = M.lv[1];
+    return L0.n == 5 && L1.n == 3 && !L0.hcoarse && L0.E[0] == L1.E[0] && L0.E[1] == L1.E[1] && L0.E[2] == L1.E[2] &&
+           dg::has_pq_mixed(L0);
+}
+
 // mf: the level-0 smoothing steps take their x and y contractions on the matrix cores (FP32
-// fields only, where the level has such a kernel).
+// fields only, where the level has such a kernel).  lp: the level-0 fields (source, smoother
+// iterates) hold BF16 values (FP32 arithmetic; levels below stay FP32); see lp_fields().
 template <typename T>
 T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T* f, bool z1_ready, bool dot,
-          hipStream_t s, bool mf = false) {
+          hipStream_t s, bool mf = false, bool lp = false) {
     const bool timed = l == 0 && g_prof && g_prof->on;
     const int L = (int)M.lv.size();
     const LevelHost& Lv = M.lv[l];
@@ -369,9 +382,15 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
     T* cur = W.za[l];
     T* prev = W.zb[l];
     const bool mf0 = mf && l == 0;
+    const bool lp0 = lp && l == 0;
     // one smoothing step: on the matrix cores where asked for and available, else the FP32/FP64 kernel
     auto step = [&](int mode, const T* u, const T* zp, T* out, double cp, double cr) {
         if constexpr (sizeof(T) == 4) {
+            if (lp0) {
+                if (!dg::launch_brick_lp(mode, Lv, dv, nrhs, st, u, f, zp, out, M.partial, M.pstride, cp, cr, s))
+                    throw std::logic_error("internal: no BF16-field smoothing kernel for level 0");
+                return;
+            }
             if (mf0 && dg::launch_brick_mf(mode, Lv, dv, nrhs, st, u, f, zp, out, M.partial, M.pstride, cp, cr, s))
                 return;
         }
@@ -385,10 +404,31 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
     }
     const LevelHost& Lc = M.lv[l + 1];
     const bool coarse_is_last = (l + 1 == L - 1);
-    dg::launch_restrict<T>(Lv, dv, Lc, ldev<T>(Lc), nrhs, st, cur, f, W.f[l + 1],
-                           coarse_is_last ? nullptr : W.za[l + 1], coarse_is_last ? 0.0 : M.cheb[l + 1].c0, s);
+    if constexpr (sizeof(T) == 4) {
+        if (lp0) {
+            if (!dg::launch_restrict_lp(Lv, dv, Lc, ldev<T>(Lc), nrhs, st, cur, f, W.f[l + 1],
+                                        coarse_is_last ? nullptr : W.za[l + 1], coarse_is_last ? 0.0 : M.cheb[l + 1].c0,
+                                        s))
+                throw std::logic_error("internal: no BF16-field restriction kernel for level 0");
+        } else {
+            dg::launch_restrict<T>(Lv, dv, Lc, ldev<T>(Lc), nrhs, st, cur, f, W.f[l + 1],
+                                   coarse_is_last ? nullptr : W.za[l + 1], coarse_is_last ? 0.0 : M.cheb[l + 1].c0, s);
+        }
+    } else {
+        dg::launch_restrict<T>(Lv, dv, Lc, ldev<T>(Lc), nrhs, st, cur, f, W.f[l + 1],
+                               coarse_is_last ? nullptr : W.za[l + 1], coarse_is_last ? 0.0 : M.cheb[l + 1].c0, s);
+    }
     T* zc = vcycle<T>(M, W, l + 1, nrhs, st, W.f[l + 1], !coarse_is_last, false, s);
-    dg::launch_prolong<T>(Lv, Lc, nrhs, st, zc, cur, s);
+    if constexpr (sizeof(T) == 4) {
+        if (lp0) {
+            if (!dg::launch_prolong_lp(Lv, Lc, nrhs, st, zc, cur, s))
+                throw std::logic_error("internal: no BF16-field prolongation kernel for level 0");
+        } else {
+            dg::launch_prolong<T>(Lv, Lc, nrhs, st, zc, cur, s);
+        }
+    } else {
+        dg::launch_prolong<T>(Lv, Lc, nrhs, st, zc, cur, s);
+    }
     for (int k = 0; k < m; ++k) {
         const bool last = (k == m - 1);
         const int mode = (dot && last) ? dg::BM_CHEBDOT : dg::BM_CHEB;
@@ -433,14 +473,14 @@ void pcg_iteration(Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, int parity, 
 // beta, for which the FP32 residual alternates between two buffers so that the previous one is
 // still there for z.r_old.
 void pcg_iteration_pc(Mesh& M, Work<double>& W, int nrhs, dg::RhsState* st, int parity, hipStream_t s,
-                      bool flex = false) {
+                      bool flex = false, bool lp = false) {
     const LevelHost& L0 = M.lv[0];
     Work<float>& V = M.w32;
     const int nb_rz = dg::op_blocks<float>(L0, dg::BM_CHEBDOT), nb = dg::op_blocks<double>(L0, dg::BM_PQ);
     const int nc = dg::chunks_of(L0.ndof);
     float* rcur = (flex && parity) ? V.tmp : V.r;
     float* rnext = flex ? (parity ? V.r : V.tmp) : V.r;
-    float* z = vcycle<float>(M, V, 0, nrhs, st, rcur, true, true, s, flex);
+    float* z = vcycle<float>(M, V, 0, nrhs, st, rcur, true, true, s, flex, lp);
     if (M.lv.size() == 1) {
         // the preconditioner was the exact solve alone: no smoothing step wrote the r.z partial sums
         dg::launch_dot<float, float>(L0.ndof, nrhs, st, rcur, z, M.partial, M.pstride, s);
@@ -454,10 +494,10 @@ void pcg_iteration_pc(Mesh& M, Work<double>& W, int nrhs, dg::RhsState* st, int 
     }
     double* pold = parity ? W.p1 : W.p0;
     double* pnew = parity ? W.p0 : W.p1;
-    dg::launch_pq_mixed(L0, L0.dev64, nrhs, st, z, pold, W.q, pnew, W.tmp, M.partial, M.pstride, s);
+    dg::launch_pq_mixed(L0, L0.dev64, nrhs, st, z, pold, W.q, pnew, W.tmp, M.partial, M.pstride, s, lp);
     dg::launch_finalize(dg::FIN_PQ, nrhs, st, M.partial, M.pstride, nb, s);
     dg::launch_update_pc(L0, L0.dev64, nrhs, st, W.x, W.r, pnew, W.q, rnext, V.za[0], M.cheb[0].c0, M.partial,
-                         M.pstride, s);
+                         M.pstride, s, lp);
     dg::launch_finalize(dg::FIN_RR, nrhs, st, M.partial, M.pstride, nc, s);
 }
 
@@ -487,21 +527,23 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
     const LevelHost& L0 = M.lv[0];
     const int nc = dg::chunks_of(L0.ndof);
     const bool flex = PC && ctx->opts.precision == DG_PREC_BF16_PC;
-    const int kind = PC ? (flex ? 3 : 2) : (sizeof(T) == 8 ? 0 : 1);
-    const size_t vbytes = PC ? sizeof(float) : sizeof(T);  // element size of the V-cycle's fields
+    const bool lp = PC && lp_fields(ctx, M);
+    const int kind = PC ? (lp ? 4 : flex ? 3 : 2) : (sizeof(T) == 8 ? 0 : 1);
+    // element size of the V-cycle's level-0 fields
+    const size_t vbytes = PC ? (lp ? sizeof(__bf16) : sizeof(float)) : sizeof(T);
     // rr and the active flags
     dg::launch_dot<T, T>(L0.ndof, nrhs, gate, W.r, W.r, M.partial, M.pstride, s);
     dg::launch_finalize(dg::FIN_RR0, nrhs, st, M.partial, M.pstride, nc, s);
     if (gate) dg::launch_gate(nrhs, st, gate, s);  // finished outer loops keep their inner solve idle
     if constexpr (PC)
-        dg::launch_to32_cheb0(L0, L0.dev64, nrhs, st, W.r, M.w32.r, M.w32.za[0], M.cheb[0].c0, s);
+        dg::launch_to32_cheb0(L0, L0.dev64, nrhs, st, W.r, M.w32.r, M.w32.za[0], M.cheb[0].c0, s, lp);
     else
         dg::launch_cheb0<T>(L0, ldev<T>(L0), nrhs, st, W.r, W.za[0], M.cheb[0].c0, s);
     dg::launch_fill<T>(W.p0, (T)0, L0.ndof * nrhs, s);
     dg::launch_fill<T>(W.p1, (T)0, L0.ndof * nrhs, s);
     auto iteration = [&](int parity) {
         if constexpr (PC)
-            pcg_iteration_pc(M, W, nrhs, st, parity, s, flex);
+            pcg_iteration_pc(M, W, nrhs, st, parity, s, flex, lp);
         else
             pcg_iteration<T>(M, W, nrhs, st, parity, s);
     };
@@ -843,7 +885,8 @@ void solve_group(dg_ctx* ctx, Mesh& M, int nrhs, const double* b, const double* 
         }
     }
     if (fused_done) {
-    } else if (o.precision == DG_PREC_FP64 || o.precision == DG_PREC_FP32_PC || o.precision == DG_PREC_BF16_PC) {
+    } else if (o.precision == DG_PREC_FP64 || o.precision == DG_PREC_FP32_PC || o.precision == DG_PREC_BF16_PC ||
+               o.precision == DG_PREC_BF16F_PC) {
         const bool pc = o.precision != DG_PREC_FP64;
         if (pc)
             ensure_work_pc(M, nrhs, o.precision == DG_PREC_BF16_PC);
@@ -1020,7 +1063,7 @@ void prepare_lane(dg_ctx* ctx, Mesh& M, int cnt) {
         ensure_fused_ws(ctx, M, cnt);
     else if (prec == DG_PREC_FP32_IR)
         ensure_work<float>(M, M.w32, cnt);
-    else if (prec == DG_PREC_FP32_PC || prec == DG_PREC_BF16_PC)
+    else if (prec == DG_PREC_FP32_PC || prec == DG_PREC_BF16_PC || prec == DG_PREC_BF16F_PC)
         ensure_work_pc(M, cnt, prec == DG_PREC_BF16_PC);
     else
         ensure_work<double>(M, M.w64, cnt);
@@ -1352,7 +1395,7 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
             o.penalty_eps <= 0 || o.rtol <= 0 || o.max_iter < 1 || o.max_outer < 1 || o.inner_rtol <= 0 ||
             o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 2 ||
             (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_IR && o.precision != DG_PREC_FP32_PC &&
-             o.precision != DG_PREC_BF16_PC))
+             o.precision != DG_PREC_BF16_PC && o.precision != DG_PREC_BF16F_PC))
             throw ArgError("invalid solver options");
         HIPCHK(hipGetDevice(&ctx->device));
         HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));

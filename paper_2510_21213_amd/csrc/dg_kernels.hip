@@ -33,6 +33,7 @@
 #include <cstdio>
 #include <mutex>
 #include <stdexcept>
+#include <type_traits>
 
 #include "dg_kernels.h"
 
@@ -457,7 +458,7 @@ struct SlabArgs {
     long long ndof;
     const RhsState* st;
     const T* u;
-    const float* uf;  // BM_PQ32: the FP32 field that takes the place of u
+    const void* uf;   // BM_PQ32: the FP32 (or BF16) field that takes the place of u
     const T* u2;
     const T* f;
     const T* zprev;
@@ -649,28 +650,55 @@ __device__ __forceinline__ void bstore(double v, brsrc r, uint32_t voff, uint32_
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
+// Field element of storage type S as the compute type T: FP32/FP64 fields as they are; BF16 fields
+// widened on load (exact) and rounded to nearest even on store.
+template <typename S, typename T>
+__device__ __forceinline__ void fload(T& v, brsrc r, uint32_t voff, uint32_t soff) {
+    if constexpr (std::is_same<S, __bf16>::value) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        v = (T)__uint_as_float((uint32_t)h << 16);
+    } else {
+        bload(v, r, voff, soff);
+    }
+}
+// (The FP32 -> BF16 conversion is the hardware's, v_cvt_pk_bf16_f32 on gfx950: round to nearest even.)
+template <typename S, typename T>
+__device__ __forceinline__ void fstore(T v, brsrc r, uint32_t voff, uint32_t soff) {
+    if constexpr (std::is_same<S, __bf16>::value) {
+        const __bf16 h = (__bf16)(float)v;
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, voff, soff, 0);
+    } else {
+        bstore(v, r, voff, soff);
+    }
+}
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
+__device__ __forceinline__ float from_bf16(__bf16 h) {
+    return __uint_as_float((uint32_t)__builtin_bit_cast(unsigned short, h) << 16);
+}
 
-// The N values of a node column of one element layer (stride N^2 values).  BM_PQ and BM_PQ32
-// read u + beta u2; in BM_PQ32 u is an FP32 field, addressed at half the byte offsets of T = double.
-template <typename T, int N, int MODE>
+// The N values of a node column of one element layer (stride N^2 values), fields of storage type
+// S.  BM_PQ and BM_PQ32 read u + beta u2; in BM_PQ32 u is the V-cycle output, a field of type ZP
+// (FP32 or BF16), addressed at sizeof(ZP) / sizeof(T) of the byte offsets of T = double.
+template <typename T, int N, int MODE, typename S = T, typename ZP = float>
 __device__ __forceinline__ void load_col(T* v, brsrc ru, brsrc ru2, uint32_t voff, uint32_t soff, T beta) {
     if constexpr (MODE == BM_PQ32) {
-        static_assert(sizeof(T) == 8, "BM_PQ32 is an FP64 step");
+        static_assert(sizeof(T) == 8 && sizeof(S) == 8, "BM_PQ32 is an FP64 step");
+        constexpr uint32_t R = sizeof(T) / sizeof(ZP);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             float zf;
-            bload(zf, ru, voff >> 1, (soff >> 1) + k * N * N * 4u);
+            fload<ZP>(zf, ru, voff / R, soff / R + k * N * N * (uint32_t)sizeof(ZP));
             v[k] = (T)zf;
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < N; ++k) bload(v[k], ru, voff, soff + k * N * N * (uint32_t)sizeof(T));
+        for (int k = 0; k < N; ++k) fload<S>(v[k], ru, voff, soff + k * N * N * (uint32_t)sizeof(S));
     }
     if constexpr (MODE == BM_PQ || MODE == BM_PQ32) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             T w;
-            bload(w, ru2, voff, soff + k * N * N * (uint32_t)sizeof(T));
+            fload<S>(w, ru2, voff, soff + k * N * N * (uint32_t)sizeof(S));
             v[k] += beta * w;
         }
     }
@@ -818,7 +846,9 @@ __device__ __forceinline__ void mf_xy_terms(const RefDev<float>& R, const mf_s4&
     }
 }
 
-template <typename T, int N, int TX, int TY, int MODE, bool MF = false>
+// S: storage type of the fields u, u2, f, zprev, out, out2 (T, or BF16 for FP32 arithmetic; the
+// pointers of SlabArgs<T> then address BF16 data); ZP: type of the BM_PQ32 input uf.
+template <typename T, int N, int TX, int TY, int MODE, bool MF = false, typename S = T, typename ZP = float>
 __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr int NX = TX * N, NY = TY * N, NT = NX * NY, N2 = N * N, N3 = N2 * N;
     constexpr int WG = wg_of(NT);
@@ -830,7 +860,7 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr int YB = ((NP + 63) / 64) * 64 + NP <= WG ? ((NP + 63) / 64) * 64 : NP;
     constexpr int NH = 2 * (TX + TY);                        // halo elements per layer
     constexpr int HS = (NH + TX * TY - 1) / (TX * TY);       // halo columns per thread
-    constexpr uint32_t SZ = sizeof(T);
+    constexpr uint32_t SZ = sizeof(S);
     static_assert(TX % 2 == 0 && TY % 2 == 0, "tiles hold whole element pairs");
     constexpr bool HAS_F = MODE == BM_RESID || MODE == BM_RESIDDOT || MODE == BM_CHEB || MODE == BM_CHEBDOT ||
                            MODE == BM_RESTRICT;
@@ -854,17 +884,19 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     const uint32_t lstride = (uint32_t)(E0 * E1 * N3) * SZ;  // bytes per element layer
 
     const long long base = (long long)rhs * a.ndof;
+    const S* const uS = reinterpret_cast<const S*>(a.u);
     brsrc ru;
     if constexpr (MODE == BM_PQ32)
-        ru = rsrc_of(a.uf + base, a.ndof);
+        ru = rsrc_of(reinterpret_cast<const ZP*>(a.uf) + base, a.ndof);
     else
-        ru = rsrc_of(a.u + base, a.ndof);
-    const brsrc ru2 = rsrc_of(IS_PQ ? a.u2 + base : a.u + base, a.ndof);
-    const brsrc rf = rsrc_of(HAS_F ? a.f + base : a.u + base, a.ndof);
-    const brsrc rzp = rsrc_of(IS_CHEB && a.zprev ? a.zprev + base : a.u + base, a.ndof);
-    T* const obase = MODE == BM_RESTRICT ? const_cast<T*>(a.u) : a.out;  // BM_RESTRICT stores no fine field
+        ru = rsrc_of(uS + base, a.ndof);
+    const brsrc ru2 = rsrc_of(IS_PQ ? reinterpret_cast<const S*>(a.u2) + base : uS + base, a.ndof);
+    const brsrc rf = rsrc_of(HAS_F ? reinterpret_cast<const S*>(a.f) + base : uS + base, a.ndof);
+    const brsrc rzp = rsrc_of(IS_CHEB && a.zprev ? reinterpret_cast<const S*>(a.zprev) + base : uS + base, a.ndof);
+    // BM_RESTRICT stores no fine field
+    S* const obase = MODE == BM_RESTRICT ? const_cast<S*>(uS) : reinterpret_cast<S*>(a.out);
     const brsrc ro = rsrc_of(obase + base, a.ndof);
-    const brsrc ro2 = rsrc_of(IS_PQ ? a.out2 + base : obase + base, a.ndof);
+    const brsrc ro2 = rsrc_of(IS_PQ ? reinterpret_cast<S*>(a.out2) + base : obase + base, a.ndof);
     T beta = 0;
     if constexpr (IS_PQ) beta = (T)a.st[rhs].beta;
     const bool has_zp = IS_CHEB && a.zprev;
@@ -956,14 +988,14 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     T cur[N], nxt[N], nx2[N], hal[HS][N];
     T prevU = 0, prevD = 0;
     if (ezb > 0) {
-        load_col<T, N, MODE>(nx2, ru, ru2, coff, (uint32_t)(ezb - 1) * lstride, beta);
+        load_col<T, N, MODE, S, ZP>(nx2, ru, ru2, coff, (uint32_t)(ezb - 1) * lstride, beta);
         prevU = nx2[N - 1];
         prevD = face_r(c, nx2);
     }
-    load_col<T, N, MODE>(cur, ru, ru2, coff, (uint32_t)ezb * lstride, beta);
+    load_col<T, N, MODE, S, ZP>(cur, ru, ru2, coff, (uint32_t)ezb * lstride, beta);
 #pragma unroll
-    for (int s = 0; s < HS; ++s) load_col<T, N, MODE>(hal[s], ru, ru2, hoff[s], (uint32_t)ezb * lstride, beta);
-    if (ezb + 1 < E2) load_col<T, N, MODE>(nxt, ru, ru2, coff, (uint32_t)(ezb + 1) * lstride, beta);
+    for (int s = 0; s < HS; ++s) load_col<T, N, MODE, S, ZP>(hal[s], ru, ru2, hoff[s], (uint32_t)ezb * lstride, beta);
+    if (ezb + 1 < E2) load_col<T, N, MODE, S, ZP>(nxt, ru, ru2, coff, (uint32_t)(ezb + 1) * lstride, beta);
     // cr / D for the nodes of an interior layer, and for the bottom / top node of a boundary layer
     T crD[N], crD0 = 0, crDN = 0;
     if constexpr (IS_CHEB) {
@@ -995,18 +1027,18 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
         // loads for later layers and for this layer's epilogue
         if (ez + 1 < eze) {
 #pragma unroll
-            for (int s = 0; s < HS; ++s) load_col<T, N, MODE>(hal[s], ru, ru2, hoff[s], soff + lstride, beta);
+            for (int s = 0; s < HS; ++s) load_col<T, N, MODE, S, ZP>(hal[s], ru, ru2, hoff[s], soff + lstride, beta);
         }
-        if (ez + 1 < eze && ez + 2 < E2) load_col<T, N, MODE>(nx2, ru, ru2, coff, soff + 2 * lstride, beta);
+        if (ez + 1 < eze && ez + 2 < E2) load_col<T, N, MODE, S, ZP>(nx2, ru, ru2, coff, soff + 2 * lstride, beta);
         T fcol[N], zpcol[N];
         if constexpr (HAS_F) {
 #pragma unroll
-            for (int k = 0; k < N; ++k) bload(fcol[k], rf, coff, soff + k * N2 * SZ);
+            for (int k = 0; k < N; ++k) fload<S>(fcol[k], rf, coff, soff + k * N2 * SZ);
         }
         if constexpr (IS_CHEB) {
             if (has_zp) {
 #pragma unroll
-                for (int k = 0; k < N; ++k) bload(zpcol[k], rzp, coff, soff + k * N2 * SZ);
+                for (int k = 0; k < N; ++k) fload<S>(zpcol[k], rzp, coff, soff + k * N2 * SZ);
             } else {
 #pragma unroll
                 for (int k = 0; k < N; ++k) zpcol[k] = 0;
@@ -1063,10 +1095,10 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                 const T y = zacc[k] * P2 + sxy[k * OP + so_own] + sxy[N * OP + k * OP + so_own];
                 const uint32_t so = soff + k * N2 * SZ;
                 if constexpr (MODE == BM_APPLY) {
-                    bstore(y, ro, coff, so);
+                    fstore<S>(y, ro, coff, so);
                 } else if constexpr (MODE == BM_RESID || MODE == BM_RESIDDOT) {
                     const T r = fcol[k] - y;
-                    bstore(r, ro, coff, so);
+                    fstore<S>(r, ro, coff, so);
                     if constexpr (MODE == BM_RESIDDOT) dot += (double)r * (double)r;
                 } else if constexpr (IS_CHEB) {
                     T cd = crD[k];
@@ -1074,11 +1106,11 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                     if (k == N - 1 && ez == E2 - 1) cd = crDN;
                     const T uz = cur[k];
                     const T zn = uz + a.cp * (uz - zpcol[k]) + cd * (fcol[k] - y);
-                    bstore(zn, ro, coff, so);
+                    fstore<S>(zn, ro, coff, so);
                     if constexpr (MODE == BM_CHEBDOT) dot += (double)fcol[k] * (double)zn;
                 } else if constexpr (IS_PQ) {
-                    bstore(cur[k], ro2, coff, so);
-                    bstore(y, ro, coff, so);
+                    fstore<S>(cur[k], ro2, coff, so);
+                    fstore<S>(y, ro, coff, so);
                     dot += (double)cur[k] * (double)y;
                 } else if constexpr (MODE == BM_RESTRICT) {
                     rr[k] = fcol[k] - y;
@@ -1286,12 +1318,35 @@ static void slab_dispatch(int mode, const SlabArgs<T>& a, int grid, hipStream_t 
     }
 }
 
+// The BF16-field forms: FP32 arithmetic on BF16 fields (smoothing, smoothing with f.z, restriction),
+// or the FP64 search-direction step reading a BF16 V-cycle output.
+template <typename T, int N, int TX, int TY>
+static void slab_dispatch_lp(int mode, const SlabArgs<T>& a, int grid, hipStream_t s) {
+    constexpr int WG = wg_of(TX * TY * N * N);
+    if constexpr (sizeof(T) == 4) {
+        switch (mode) {
+            case BM_CHEB:
+                hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_CHEB, false, __bf16>), dim3(grid), dim3(WG), 0, s, a);
+                break;
+            case BM_CHEBDOT:
+                hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_CHEBDOT, false, __bf16>), dim3(grid), dim3(WG), 0, s, a);
+                break;
+            case BM_RESTRICT:
+                hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESTRICT, false, __bf16>), dim3(grid), dim3(WG), 0, s, a);
+                break;
+        }
+    } else {
+        if (mode == BM_PQ32)
+            hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_PQ32, false, T, __bf16>), dim3(grid), dim3(WG), 0, s, a);
+    }
+}
+
 template <typename T>
 static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, int nrhs, const RhsState* st,
                         const T* u, const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial,
                         int pstride, double cp, double cr, hipStream_t s, const LevelHost* Lc = nullptr,
                         const LevelDev<T>* devc = nullptr, T* fc = nullptr, T* z1c = nullptr, double c0c = 0,
-                        const float* uf = nullptr, bool mf = false) {
+                        const void* uf = nullptr, bool mf = false, bool lp = false) {
     SlabGeom g = slab_geom<T>(L, mode);
     if (mf && mode == BM_APPLY && L.n == 5) {  // no partial sums: the smoothing steps' 4 x 2 tile, 4 layers
         g.tx = 4;
@@ -1344,6 +1399,19 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
             return true;
         }
     }
+    if (lp) {  // BF16 fields: FP32 smoothing and restriction steps, or the FP64 BM_PQ32 step, of degree 4
+        if (L.n != 5) return false;
+        if constexpr (sizeof(T) == 4) {
+            if (mode != BM_CHEB && mode != BM_CHEBDOT && mode != BM_RESTRICT) return false;
+        } else {
+            if (mode != BM_PQ32) return false;
+        }
+        if (g.tx == 4 && g.ty == 2) slab_dispatch_lp<T, 5, 4, 2>(mode, a, grid, s);
+        else if (g.tx == 4 && g.ty == 4) slab_dispatch_lp<T, 5, 4, 4>(mode, a, grid, s);
+        else if (g.tx == 2 && g.ty == 2) slab_dispatch_lp<T, 5, 2, 2>(mode, a, grid, s);
+        else return false;
+        return true;
+    }
     if (g.tx == 8 && g.ty == 8 && L.n == 2) slab_dispatch<T, 2, 8, 8>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 4 && L.n == 3) slab_dispatch<T, 3, 4, 4>(mode, a, grid, s);
     else if (g.tx == 4 && g.ty == 2 && L.n == 5) slab_dispatch<T, 5, 4, 2>(mode, a, grid, s);
@@ -1390,6 +1458,21 @@ bool launch_brick_mf(int mode, const LevelHost& L, const LevelDev<float>* dev, i
                               nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, true);
 }
 
+bool launch_brick_lp(int mode, const LevelHost& L, const LevelDev<float>* dev, int nrhs, const RhsState* st,
+                     const float* u, const float* f, const float* zprev, float* out, double* partial, int pstride,
+                     double cp, double cr, hipStream_t s) {
+    return launch_slab<float>(mode, L, dev, nrhs, st, u, nullptr, f, zprev, out, nullptr, partial, pstride, cp, cr, s,
+                              nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, false, true);
+}
+
+bool launch_restrict_lp(const LevelHost& Lf, const LevelDev<float>* devf, const LevelHost& Lc,
+                        const LevelDev<float>* devc, int nrhs, const RhsState* st, const float* z, const float* f,
+                        float* fc, float* z1c, double c0c, hipStream_t s) {
+    if (!z || Lf.hcoarse || Lc.n != (Lf.n - 1) / 2 + 1) return false;
+    return launch_slab<float>(BM_RESTRICT, Lf, devf, nrhs, st, z, nullptr, f, nullptr, nullptr, nullptr, nullptr, 0,
+                              0, 0, s, &Lc, devc, fc, z1c, c0c, nullptr, false, true);
+}
+
 __global__ __launch_bounds__(256) void k_widen(const float* __restrict__ a, double* __restrict__ b, long long n) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i < n) b[i] = (double)a[i];
@@ -1399,8 +1482,14 @@ bool has_pq_mixed(const LevelHost& L) { return slab_geom<double>(L, BM_PQ).tx !=
 
 void launch_pq_mixed(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const float* z,
                      const double* pold, double* q, double* pnew, double* tmp, double* partial, int pstride,
-                     hipStream_t s) {
+                     hipStream_t s, bool zbf16) {
     if (nrhs == 0) return;
+    if (zbf16) {  // z holds BF16 values
+        if (!launch_slab<double>(BM_PQ32, L, dev, nrhs, st, q, pold, nullptr, nullptr, q, pnew, partial, pstride, 0.0,
+                                 0.0, s, nullptr, nullptr, nullptr, nullptr, 0.0, z, false, true))
+            throw std::logic_error("launch_pq_mixed: no BF16-input kernel for this level");
+        return;
+    }
     // u is never read in BM_PQ32 (uf takes its place); q keeps the resource base valid
     if (launch_slab<double>(BM_PQ32, L, dev, nrhs, st, q, pold, nullptr, nullptr, q, pnew, partial, pstride, 0.0,
                             0.0, s, nullptr, nullptr, nullptr, nullptr, 0.0, z))
@@ -1696,11 +1785,12 @@ void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHo
 // values are staged in LDS with coalesced loads, then one thread per fine node
 // column (i, j) of an element contracts along x and y (NC^2 coarse values per
 // coarse z node) and then along z in registers, and updates its NF nodes.
-// SET: zf = scale[rhs] * P zc (every fine node written once) instead of zf += P zc
-template <typename T, int NF, int NC, bool SET = false>
+// SET: zf = scale[rhs] * P zc (every fine node written once) instead of zf += P zc.
+// SF: storage type of zf (T, or BF16 under FP32 arithmetic: read, add, round to nearest even).
+template <typename T, int NF, int NC, bool SET = false, typename SF = T>
 __global__ __launch_bounds__(256) void k_prolong_deg(const TransferDev* __restrict__ trp, long long nelem_rhs,
                                                      long long nelem, const RhsState* st, const T* __restrict__ zc,
-                                                     T* __restrict__ zf, const double* __restrict__ scale = nullptr) {
+                                                     SF* __restrict__ zf, const double* __restrict__ scale = nullptr) {
     constexpr int NF2 = NF * NF, NF3 = NF2 * NF, NC3 = NC * NC * NC;
     constexpr int EPW = 256 / NF2;
     __shared__ T sc[EPW * NC3];
@@ -1740,17 +1830,21 @@ __global__ __launch_bounds__(256) void k_prolong_deg(const TransferDev* __restri
         }
         t[cz] = acc;
     }
-    T* out = zf + e * NF3 + col;
+    SF* out = zf + e * NF3 + col;
     const T sc_rhs = SET ? (T)scale[e / nelem_rhs] : (T)0;
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
         T v = 0;
 #pragma unroll
         for (int cz = 0; cz < NC; ++cz) v += Pm(k, cz) * t[cz];
-        if constexpr (SET)
+        if constexpr (std::is_same<SF, __bf16>::value) {
+            static_assert(!SET && sizeof(T) == 4, "BF16 fine fields: FP32 correction only");
+            out[k * NF2] = to_bf16(from_bf16(out[k * NF2]) + v);
+        } else if constexpr (SET) {
             out[k * NF2] = v * sc_rhs;
-        else
+        } else {
             out[k * NF2] += v;
+        }
     }
 }
 
@@ -1771,6 +1865,19 @@ bool launch_prolong_set(const LevelHost& Lf, const LevelHost& Lc, int nrhs, cons
     DG_PS(3, 2)
 #undef DG_PS
     return false;
+}
+
+bool launch_prolong_lp(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st, const float* zc,
+                       float* zf, hipStream_t s) {
+    if (Lf.hcoarse || Lf.E[0] != Lc.E[0] || Lf.E[1] != Lc.E[1] || Lf.E[2] != Lc.E[2]) return false;
+    if (!(Lf.n == 5 && Lc.n == 3)) return false;
+    const long long nel = (long long)Lf.E[0] * Lf.E[1] * Lf.E[2];
+    const long long tot = nel * nrhs;
+    if (tot == 0) return true;
+    constexpr int EPW = 256 / 25;
+    hipLaunchKernelGGL((k_prolong_deg<float, 5, 3, false, __bf16>), dim3((unsigned)((tot + EPW - 1) / EPW)), dim3(256),
+                       0, s, Lf.devtr, nel, tot, st, zc, reinterpret_cast<__bf16*>(zf), nullptr);
+    return true;
 }
 
 template <typename T>
@@ -2154,10 +2261,11 @@ template void launch_update<double>(const LevelHost&, const LevelDev<double>*, i
 template void launch_update<float>(const LevelHost&, const LevelDev<float>*, int, const RhsState*, float*, float*,
                                    const float*, const float*, float*, double, double*, int, hipStream_t);
 
+template <typename TO>
 __global__ __launch_bounds__(256) void k_update_pc(const double* __restrict__ dinv, long long ndof, const RhsState* st,
                                                    double* __restrict__ x, double* __restrict__ r,
                                                    const double* __restrict__ p, const double* __restrict__ q_,
-                                                   float* __restrict__ r32, float* __restrict__ z1, double c0,
+                                                   TO* __restrict__ r32, TO* __restrict__ z1, double c0,
                                                    double* __restrict__ partial, int pstride) {
     __shared__ double red[4];
     const int rhs = blockIdx.x;
@@ -2175,17 +2283,23 @@ __global__ __launch_bounds__(256) void k_update_pc(const double* __restrict__ di
             const double rn = r[g] - alpha * q_[g];
             r[g] = rn;
             acc += rn * rn;
-            r32[g] = (float)rn;
-            z1[g] = (float)(c0 * rn * dinv[q]);
+            if constexpr (std::is_same<TO, __bf16>::value) {
+                r32[g] = to_bf16((float)rn);
+                z1[g] = to_bf16((float)(c0 * rn * dinv[q]));
+            } else {
+                r32[g] = (float)rn;
+                z1[g] = (float)(c0 * rn * dinv[q]);
+            }
         }
     }
     const double s = block_sum<256>(acc, red);
     if (threadIdx.x == 0) partial[(long long)rhs * pstride + blockIdx.y] = s;
 }
 
+template <typename TO>
 __global__ __launch_bounds__(256) void k_to32_cheb0(const double* __restrict__ dinv, long long ndof,
                                                     const RhsState* st, const double* __restrict__ r,
-                                                    float* __restrict__ r32, float* __restrict__ z1, double c0) {
+                                                    TO* __restrict__ r32, TO* __restrict__ z1, double c0) {
     const int rhs = blockIdx.x;
     if (st && !st[rhs].active) return;
     const long long base = (long long)rhs * ndof;
@@ -2195,27 +2309,40 @@ __global__ __launch_bounds__(256) void k_to32_cheb0(const double* __restrict__ d
         const long long q = q0 + v * 256;
         if (q < ndof) {
             const double rv = r[base + q];
-            r32[base + q] = (float)rv;
-            z1[base + q] = (float)(c0 * rv * dinv[q]);
+            if constexpr (std::is_same<TO, __bf16>::value) {
+                r32[base + q] = to_bf16((float)rv);
+                z1[base + q] = to_bf16((float)(c0 * rv * dinv[q]));
+            } else {
+                r32[base + q] = (float)rv;
+                z1[base + q] = (float)(c0 * rv * dinv[q]);
+            }
         }
     }
 }
 
 void launch_update_pc(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, double* x,
                       double* r, const double* p, const double* q, float* r32, float* z1, double c0, double* partial,
-                      int pstride, hipStream_t s) {
+                      int pstride, hipStream_t s, bool bf16) {
     (void)dev;
     if (nrhs == 0) return;
-    hipLaunchKernelGGL(k_update_pc, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st, x, r, p, q,
-                       r32, z1, c0, partial, pstride);
+    if (bf16)
+        hipLaunchKernelGGL(k_update_pc<__bf16>, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st, x,
+                           r, p, q, reinterpret_cast<__bf16*>(r32), reinterpret_cast<__bf16*>(z1), c0, partial, pstride);
+    else
+        hipLaunchKernelGGL(k_update_pc<float>, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st, x,
+                           r, p, q, r32, z1, c0, partial, pstride);
 }
 
 void launch_to32_cheb0(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const double* r,
-                       float* r32, float* z1, double c0, hipStream_t s) {
+                       float* r32, float* z1, double c0, hipStream_t s, bool bf16) {
     (void)dev;
     if (nrhs == 0) return;
-    hipLaunchKernelGGL(k_to32_cheb0, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st, r, r32, z1,
-                       c0);
+    if (bf16)
+        hipLaunchKernelGGL(k_to32_cheb0<__bf16>, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st,
+                           r, reinterpret_cast<__bf16*>(r32), reinterpret_cast<__bf16*>(z1), c0);
+    else
+        hipLaunchKernelGGL(k_to32_cheb0<float>, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st,
+                           r, r32, z1, c0);
 }
 
 template <typename TA, typename TB>

@@ -55,6 +55,7 @@ def main():
     ap.add_argument("--out", default=binding.TILE_TABLE)
     ap.add_argument("--workload", default="exchange8", choices=["exchange8", "large"])
     ap.add_argument("--rtol", type=float, default=None, help="residual of the timed solves (default: the workload's)")
+    ap.add_argument("--arm", default="fp32_pc+learned", help="arm timed on the large workload")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     large = args.workload == "large"
@@ -72,8 +73,7 @@ def main():
     g = orb.pair_potentials_torch(*fxyz, device="cuda").reshape(-1).contiguous()
     groups = GROUPS
     if large:  # the FP32_PC arm: FP32 V-cycle steps and the FP64 degree-4 steps
-        groups = [(nm, fp, n, st, sh, zl, "fp32_pc+learned") for nm, fp, n, st, sh, zl, _ in GROUPS
-                  if fp == 4 or n == 5]
+        groups = [(nm, fp, n, st, sh, zl, args.arm) for nm, fp, n, st, sh, zl, _ in GROUPS if fp == 4 or n == 5]
 
     def measure(arm):
         prec = arm.split("+")[0]
@@ -127,7 +127,7 @@ def main():
             for st in ALL:
                 tx, ty, z = binding.tile_get(fp, n, st)
                 tiles.append({"fp_bytes": fp, "n": n, "step": st, "tx": tx, "ty": ty, "zlen": z})
-    wname = ("large: 36 pair densities of the first held-out molecule, 32^3 elements, p = 4, 5 levels, fp32_pc"
+    wname = (f"large: 36 pair densities of the first held-out molecule, 32^3 elements, p = 4, 5 levels, {args.arm}"
              if large else "exchange8: 36 pair densities, 16^3 elements, p = 4, 4 levels")
     report = {"arch": "gfx950", "workload": f"{wname}, residual {rtol:g}",
               "timing": f"median of {args.steps} exchange steps after {args.warmup} warm-up steps",

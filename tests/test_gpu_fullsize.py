@@ -110,7 +110,7 @@ def _check_all(wl, oracle, got, rtol, pot_bar, energy_bar, ex_bar=None):
     return ev, eK
 
 
-@pytest.mark.parametrize("arm", ["fp32_pc+learned", "fp32_pc", "fp64+learned", "fp64", "bf16_pc"])
+@pytest.mark.parametrize("arm", ["fp32_pc+learned", "fp32_pc", "fp64+learned", "fp64", "bf16_pc", "bf16f_pc+learned"])
 def test_exchange8_every_pair_at_operating_tolerance(gpu_lib, workload, oracle_all, arm):
     """Every one of the 36 pair potentials, every pair energy, every W_k and E_x of the
     exchange8 step meet the parity bars at the benchmark's operating tolerance, in every arm

@@ -498,6 +498,37 @@ def test_fp32_preconditioned_fp64_pcg_matches_exact(gpu_lib, case):
         assert abs(out["fp32_pc"][1][k] - out["fp64"][1][k]) <= 1, k
 
 
+P4_CASES = [
+    ((4, 6, 2), 4, (-2.0, -3.0, -1.0), (2.0, 3.0, 1.0), 0),      # every 4 x 2 tile at a face, 2-level
+    ((10, 6, 4), 4, (-5.0, -3.0, -2.0), (5.0, 3.0, 2.0), 0),     # interior and ragged tiles, 3 levels
+    ((8, 8, 8), 4, (-4.0, -4.0, -4.0), (4.0, 4.0, 4.0), 0),      # 4 levels (degree steps, then mesh steps)
+]
+
+
+@pytest.mark.parametrize("case", P4_CASES, ids=[f"E{c[0]}" for c in P4_CASES])
+def test_bf16_field_vcycle_pcg_matches_exact(gpu_lib, case):
+    """BF16F_PC: FP64 CG preconditioned by the V-cycle whose finest-level fields (source, smoother
+    iterates) are stored in BF16: the potentials meet the bar against the exact solve at the
+    parity tolerance, with FP32_PC's iteration count (+-1); the mode also runs in an interleaved
+    batch over two lanes and a second call from the converged potentials does no iteration."""
+    mesh = _mesh(case)
+    dens = [_box_density(mesh, 160 + k) for k in range(20)]
+    out = {}
+    for prec in ("fp32_pc", "bf16f_pc"):
+        ctx = _ctx(gpu_lib, [case], rtol=PARITY_RTOL, precision=prec)
+        rho, g = zip(*[gpu_sample(ctx, 0, d) for d in dens])
+        rho, g = _t(np.concatenate(rho)), _t(np.concatenate(g))
+        v, st = ctx.solve_batch(rho, g)
+        assert all(s_["status"] == 0 and s_["rel_residual"] <= PARITY_RTOL for s_ in st), prec
+        v2, st2 = ctx.solve_batch(rho, g, x0=v)
+        assert all(s_["iters"] == 0 and s_["guess_used"] == 1 for s_ in st2), prec
+        out[prec] = (_n(v).reshape(len(dens), -1), [s_["iters"] for s_ in st])
+    for k in (0, 9, 19):
+        axes, _, _, b = oracle_density_problem(mesh, dens[k])
+        assert rel_l2_M(axes, mesh, out["bf16f_pc"][0][k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
+    assert max(abs(a - b_) for a, b_ in zip(out["bf16f_pc"][1], out["fp32_pc"][1])) <= 1
+
+
 def test_single_level_hierarchy(gpu_lib):
     """A degree-1 mesh of at most 16 nodes per axis has a single multigrid level with default
     options: PCG is preconditioned by the exact solve alone and converges at once, in every
@@ -506,7 +537,7 @@ def test_single_level_hierarchy(gpu_lib):
     dens = _box_density(mesh, 71)
     axes, _, _, b = oracle_density_problem(mesh, dens)
     ref = fdm.FDM(axes).solve(b)
-    for prec in ("fp64", "fp32_pc", "fp32_ir"):
+    for prec in ("fp64", "fp32_pc", "fp32_ir", "bf16f_pc"):
         ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], rtol=PARITY_RTOL, precision=prec)
         assert ctx.info[0]["n_levels"] == 1
         rho, g = gpu_sample(ctx, 0, dens)
