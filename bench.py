@@ -61,13 +61,13 @@ def parse():
                          "quadrature: the exchange8 step with its Dirichlet data computed by quadrature; "
                          "consumers: Hartree/exchange actions projected on a 256-function basis and the "
                          "compressed exchange on the exchange8 mesh")
-    ap.add_argument("--arms", default="fp32_pc+learned,fp32_pc,fp64+learned,fp64,fp32_pc+untrained",
+    ap.add_argument("--arms", default="bf16f_pc+learned,fp32_pc+learned,fp32_pc,fp64+learned,fp64,bf16f_pc+untrained",
                     help="precision fp32_pc, bf16f_pc, bf16_pc, fp32_ir or fp64, optionally +learned (trained guess) or "
                          "+untrained (the same network with random weights, a control); the first is the headline")
     ap.add_argument("--rtol", type=float, default=OPERATING_RTOL, help="FP64 relative residual of every arm")
     ap.add_argument("--metric-rtol", type=float, default=1e-8,
                     help="second comparison at this residual (0: skip)")
-    ap.add_argument("--metric-arms", default="fp32_pc+learned,fp64")
+    ap.add_argument("--metric-arms", default="bf16f_pc+learned,fp64")
     ap.add_argument("--weights", default=None,
                     help="guess network (default: the weights trained for the workload's mesh)")
     ap.add_argument("--lanes", type=int, default=2, choices=[1, 2],
