@@ -42,7 +42,7 @@ HELDOUT_RHS = 128
 # arithmetic each precision mode computes in (the "dtype" field of the JSON line)
 DTYPE_OF = {"fp64": "f64", "fp32_ir": "f64 refinement + f32 inner PCG", "fp32_pc": "f64 CG + f32 V-cycle",
             "bf16_pc": "f64 flexible CG + f32 V-cycle, bf16 matrix-core x/y contractions in level-0 smoothing",
-            "bf16f_pc": "f64 CG + f32-arithmetic V-cycle with bf16 finest-level fields"}
+            "bf16f_pc": "f64 CG (f32-stored search direction) + f32-arithmetic V-cycle with bf16 fields on its two finest levels"}
 
 
 def parse():

@@ -90,12 +90,13 @@ typedef enum {
  * accumulation (degree-4 meshes; other degrees run the FP32 kernels).  The
  * preconditioner is then no longer exactly symmetric, so the FP64 CG takes
  * the flexible (Polak-Ribiere) beta.
- * BF16F_PC: FP32_PC whose finest-level V-cycle fields (its source, the residual handed over by the
- * CG update, and the smoother iterates) are stored in BF16 (rounded to nearest even), read into
- * FP32 arithmetic: half the bytes of the level that carries most of the V-cycle's traffic.  The
- * coarser levels, the coarsest solve and the whole CG (iterate, residual, direction, dots) are
- * as in FP32_PC, so a solve stopped at a residual keeps the FP64 solver's accuracy.  Degree-4
- * finest levels whose next level is their degree-2 step; other hierarchies run as FP32_PC. */
+ * BF16F_PC: FP32_PC whose V-cycle fields on the finest level (its source, the residual handed
+ * over by the CG update, and the smoother iterates) and on the finest level's degree-2 step (when
+ * that is not the coarsest level) are stored in BF16 (rounded to nearest even), read into FP32
+ * arithmetic, and whose search direction p is stored in FP32 (rounded before q = A p is formed
+ * from it, so q is the FP64 product of the stored direction).  Iterate, residual, q and every dot
+ * stay FP64, so a solve stopped at a residual keeps the FP64 solver's accuracy.  Degree-4 finest
+ * levels whose next level is their degree-2 step; other hierarchies run as FP32_PC. */
 typedef enum {
     DG_PREC_FP64 = 0,
     DG_PREC_FP32_IR = 1,

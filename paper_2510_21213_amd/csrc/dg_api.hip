@@ -351,23 +351,26 @@ void prof_sum(const std::vector<hipEvent_t>& ev, size_t used) {
     }
 }
 
-// BF16F_PC keeps the finest level's V-cycle fields in BF16 where the kernels exist for it: a
-// degree-4 finest level with a coarser level below that is its degree-2 step (on other
-// hierarchies the mode runs as FP32_PC).
-bool lp_fields(const dg_ctx* ctx, const Mesh& M) {
-    if (ctx->opts.precision != DG_PREC_BF16F_PC || M.lv.size() < 2) return false;
-    const LevelHost& L0 = M.lv[0];
-    const LevelHost& L1 = M.lv[1];
-    return L0.n == 5 && L1.n == 3 && !L0.hcoarse && L0.E[0] == L1.E[0] && L0.E[1] == L1.E[1] && L0.E[2] == L1.E[2] &&
-           dg::has_pq_mixed(L0);
+// The number of finest levels whose V-cycle fields BF16F_PC keeps in BF16, where the kernels exist
+// for them: a degree-4 finest level whose next level is its degree-2 step (1), and that level too
+// when it is not the coarsest and its own next level is its degree-1 step (2).  0: the mode runs
+// as FP32_PC on this hierarchy.
+int lp_fields(const dg_ctx* ctx, const Mesh& M) {
+    if (ctx->opts.precision != DG_PREC_BF16F_PC || M.lv.size() < 2) return 0;
+    auto degree_step = [](const LevelHost& F, const LevelHost& C, int nf, int nc) {
+        return F.n == nf && C.n == nc && !F.hcoarse && F.E[0] == C.E[0] && F.E[1] == C.E[1] && F.E[2] == C.E[2];
+    };
+    if (!degree_step(M.lv[0], M.lv[1], 5, 3) || !dg::has_pq_mixed(M.lv[0])) return 0;
+    return M.lv.size() >= 3 && degree_step(M.lv[1], M.lv[2], 3, 2) ? 2 : 1;
 }
 
 // mf: the level-0 smoothing steps take their x and y contractions on the matrix cores (FP32
-// fields only, where the level has such a kernel).  lp: the level-0 fields (source, smoother
-// iterates) hold BF16 values (FP32 arithmetic; levels below stay FP32); see lp_fields().
+// fields only, where the level has such a kernel).  lpn: the fields (source, smoother iterates) of
+// levels below lpn hold BF16 values (FP32 arithmetic; the levels below them stay FP32); see
+// lp_fields().
 template <typename T>
 T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T* f, bool z1_ready, bool dot,
-          hipStream_t s, bool mf = false, bool lp = false) {
+          hipStream_t s, bool mf = false, int lpn = 0) {
     const bool timed = l == 0 && g_prof && g_prof->on;
     const int L = (int)M.lv.size();
     const LevelHost& Lv = M.lv[l];
@@ -382,13 +385,13 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
     T* cur = W.za[l];
     T* prev = W.zb[l];
     const bool mf0 = mf && l == 0;
-    const bool lp0 = lp && l == 0;
+    const bool lpl = l < lpn, lpc = l + 1 < lpn;  // BF16 fields on this level, on the next
     // one smoothing step: on the matrix cores where asked for and available, else the FP32/FP64 kernel
     auto step = [&](int mode, const T* u, const T* zp, T* out, double cp, double cr) {
         if constexpr (sizeof(T) == 4) {
-            if (lp0) {
+            if (lpl) {
                 if (!dg::launch_brick_lp(mode, Lv, dv, nrhs, st, u, f, zp, out, M.partial, M.pstride, cp, cr, s))
-                    throw std::logic_error("internal: no BF16-field smoothing kernel for level 0");
+                    throw std::logic_error("internal: no BF16-field smoothing kernel for this level");
                 return;
             }
             if (mf0 && dg::launch_brick_mf(mode, Lv, dv, nrhs, st, u, f, zp, out, M.partial, M.pstride, cp, cr, s))
@@ -405,11 +408,11 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
     const LevelHost& Lc = M.lv[l + 1];
     const bool coarse_is_last = (l + 1 == L - 1);
     if constexpr (sizeof(T) == 4) {
-        if (lp0) {
+        if (lpl) {
             if (!dg::launch_restrict_lp(Lv, dv, Lc, ldev<T>(Lc), nrhs, st, cur, f, W.f[l + 1],
                                         coarse_is_last ? nullptr : W.za[l + 1], coarse_is_last ? 0.0 : M.cheb[l + 1].c0,
-                                        s))
-                throw std::logic_error("internal: no BF16-field restriction kernel for level 0");
+                                        s, lpc))
+                throw std::logic_error("internal: no BF16-field restriction kernel for this level");
         } else {
             dg::launch_restrict<T>(Lv, dv, Lc, ldev<T>(Lc), nrhs, st, cur, f, W.f[l + 1],
                                    coarse_is_last ? nullptr : W.za[l + 1], coarse_is_last ? 0.0 : M.cheb[l + 1].c0, s);
@@ -418,11 +421,11 @@ T* vcycle(Mesh& M, Work<T>& W, int l, int nrhs, const dg::RhsState* st, const T*
         dg::launch_restrict<T>(Lv, dv, Lc, ldev<T>(Lc), nrhs, st, cur, f, W.f[l + 1],
                                coarse_is_last ? nullptr : W.za[l + 1], coarse_is_last ? 0.0 : M.cheb[l + 1].c0, s);
     }
-    T* zc = vcycle<T>(M, W, l + 1, nrhs, st, W.f[l + 1], !coarse_is_last, false, s);
+    T* zc = vcycle<T>(M, W, l + 1, nrhs, st, W.f[l + 1], !coarse_is_last, false, s, false, lpn);
     if constexpr (sizeof(T) == 4) {
-        if (lp0) {
-            if (!dg::launch_prolong_lp(Lv, Lc, nrhs, st, zc, cur, s))
-                throw std::logic_error("internal: no BF16-field prolongation kernel for level 0");
+        if (lpl) {
+            if (!dg::launch_prolong_lp(Lv, Lc, nrhs, st, zc, cur, s, lpc))
+                throw std::logic_error("internal: no BF16-field prolongation kernel for this level");
         } else {
             dg::launch_prolong<T>(Lv, Lc, nrhs, st, zc, cur, s);
         }
@@ -473,14 +476,15 @@ void pcg_iteration(Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, int parity, 
 // beta, for which the FP32 residual alternates between two buffers so that the previous one is
 // still there for z.r_old.
 void pcg_iteration_pc(Mesh& M, Work<double>& W, int nrhs, dg::RhsState* st, int parity, hipStream_t s,
-                      bool flex = false, bool lp = false) {
+                      bool flex = false, int lpn = 0) {
+    const bool lp = lpn > 0;
     const LevelHost& L0 = M.lv[0];
     Work<float>& V = M.w32;
     const int nb_rz = dg::op_blocks<float>(L0, dg::BM_CHEBDOT), nb = dg::op_blocks<double>(L0, dg::BM_PQ);
     const int nc = dg::chunks_of(L0.ndof);
     float* rcur = (flex && parity) ? V.tmp : V.r;
     float* rnext = flex ? (parity ? V.r : V.tmp) : V.r;
-    float* z = vcycle<float>(M, V, 0, nrhs, st, rcur, true, true, s, flex, lp);
+    float* z = vcycle<float>(M, V, 0, nrhs, st, rcur, true, true, s, flex, lpn);
     if (M.lv.size() == 1) {
         // the preconditioner was the exact solve alone: no smoothing step wrote the r.z partial sums
         dg::launch_dot<float, float>(L0.ndof, nrhs, st, rcur, z, M.partial, M.pstride, s);
@@ -492,6 +496,7 @@ void pcg_iteration_pc(Mesh& M, Work<double>& W, int nrhs, dg::RhsState* st, int 
         dg::launch_dot<float, float>(L0.ndof, nrhs, st, rnext, z, M.partial, M.pstride, s);  // z . r_old
         dg::launch_finalize(dg::FIN_FLEX, nrhs, st, M.partial, M.pstride, nc, s);
     }
+    // lp: the search direction is kept in FP32 in the first half of these FP64 buffers
     double* pold = parity ? W.p1 : W.p0;
     double* pnew = parity ? W.p0 : W.p1;
     dg::launch_pq_mixed(L0, L0.dev64, nrhs, st, z, pold, W.q, pnew, W.tmp, M.partial, M.pstride, s, lp);
@@ -527,7 +532,8 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
     const LevelHost& L0 = M.lv[0];
     const int nc = dg::chunks_of(L0.ndof);
     const bool flex = PC && ctx->opts.precision == DG_PREC_BF16_PC;
-    const bool lp = PC && lp_fields(ctx, M);
+    const int lpn = PC ? lp_fields(ctx, M) : 0;
+    const bool lp = lpn > 0;
     const int kind = PC ? (lp ? 4 : flex ? 3 : 2) : (sizeof(T) == 8 ? 0 : 1);
     // element size of the V-cycle's level-0 fields
     const size_t vbytes = PC ? (lp ? sizeof(__bf16) : sizeof(float)) : sizeof(T);
@@ -543,7 +549,7 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
     dg::launch_fill<T>(W.p1, (T)0, L0.ndof * nrhs, s);
     auto iteration = [&](int parity) {
         if constexpr (PC)
-            pcg_iteration_pc(M, W, nrhs, st, parity, s, flex, lp);
+            pcg_iteration_pc(M, W, nrhs, st, parity, s, flex, lpn);
         else
             pcg_iteration<T>(M, W, nrhs, st, parity, s);
     };

@@ -68,23 +68,26 @@ bool launch_brick_mf(int mode, const LevelHost& L, const LevelDev<float>* dev, i
 // partial sums of p.q, all in FP64.  tmp: an FP64 field buffer used only on levels whose degree
 // has no slab kernel (z is widened into it first); may be null when has_pq_mixed(L).
 bool has_pq_mixed(const LevelHost& L);
-// zbf16: z holds BF16 values (the BF16-field V-cycle); degree-4 levels only.
+// zbf16: z holds BF16 values (the BF16-field V-cycle); degree-4 levels only.  The search direction
+// is then stored in FP32 (pold and pnew address FP32 values; the new direction is rounded to FP32
+// before q = A p is formed from it).
 void launch_pq_mixed(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const float* z,
                      const double* pold, double* q, double* pnew, double* tmp, double* partial, int pstride,
                      hipStream_t s, bool zbf16 = false);
-// BF16-field forms of the level-0 V-cycle steps (FP32 arithmetic, fields stored as BF16 at the
-// addresses the float pointers give): a smoothing step (BM_CHEB, BM_CHEBDOT), the residual
-// restriction of a degree step, and the prolongation-correction of a degree step into a BF16
-// fine field.  False where the level has no such kernel (degree 4 and its 4 -> 2 step only);
-// nothing is launched then.
+// BF16-field forms of the V-cycle steps of the finest levels (FP32 arithmetic, fields stored as
+// BF16 at the addresses the float pointers give): a smoothing step (BM_CHEB; BM_CHEBDOT on degree
+// 4), the residual restriction of a degree step (coarse_bf16: its coarse outputs fc and z1c are
+// BF16 too; degree 4 only), and the prolongation-correction of a degree step into a BF16 fine field
+// (coarse_bf16: zc holds BF16 values; degree 4 only).  Degree 4 with its 4 -> 2 step, and degree 2
+// with its 2 -> 1 step into FP32 coarse fields; false elsewhere, and nothing is launched then.
 bool launch_brick_lp(int mode, const LevelHost& L, const LevelDev<float>* dev, int nrhs, const RhsState* st,
                      const float* u, const float* f, const float* zprev, float* out, double* partial, int pstride,
                      double cp, double cr, hipStream_t s);
 bool launch_restrict_lp(const LevelHost& Lf, const LevelDev<float>* devf, const LevelHost& Lc,
                         const LevelDev<float>* devc, int nrhs, const RhsState* st, const float* z, const float* f,
-                        float* fc, float* z1c, double c0c, hipStream_t s);
+                        float* fc, float* z1c, double c0c, hipStream_t s, bool coarse_bf16 = false);
 bool launch_prolong_lp(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st, const float* zc,
-                       float* zf, hipStream_t s);
+                       float* zf, hipStream_t s, bool coarse_bf16 = false);
 
 // zf += P zc
 // zf = scale[rhs] * P zc for a degree step (writes every fine node); false when the step
@@ -116,7 +119,8 @@ void launch_update(const LevelHost& L, const LevelDev<T>* dev, int nrhs, const R
                    const T* q, T* z1, double c0, double* partial, int pstride, hipStream_t s);
 
 // FP32_PC update: x += alpha p; r -= alpha q; partial sums of r.r (FP64); r32 = (float) r and
-// z1 = (float) c0 D^-1 r, the source and first smoothing iterate of the FP32 V-cycle.
+// z1 = (float) c0 D^-1 r, the source and first smoothing iterate of the FP32 V-cycle.  bf16: r32
+// and z1 are BF16 fields and p holds FP32 values (the BF16-field V-cycle's search direction).
 void launch_update_pc(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, double* x,
                       double* r, const double* p, const double* q, float* r32, float* z1, double c0, double* partial,
                       int pstride, hipStream_t s, bool bf16 = false);

@@ -650,13 +650,18 @@ __device__ __forceinline__ void bstore(double v, brsrc r, uint32_t voff, uint32_
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
-// Field element of storage type S as the compute type T: FP32/FP64 fields as they are; BF16 fields
-// widened on load (exact) and rounded to nearest even on store.
+// Field element of storage type S as the compute type T: fields of the compute type as they are;
+// BF16 fields widened on load (exact) and rounded to nearest even on store; FP32 fields of an FP64
+// computation widened on load and rounded to nearest on store.
 template <typename S, typename T>
 __device__ __forceinline__ void fload(T& v, brsrc r, uint32_t voff, uint32_t soff) {
     if constexpr (std::is_same<S, __bf16>::value) {
         const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
         v = (T)__uint_as_float((uint32_t)h << 16);
+    } else if constexpr (sizeof(S) != sizeof(T)) {
+        S w;
+        bload(w, r, voff, soff);
+        v = (T)w;
     } else {
         bload(v, r, voff, soff);
     }
@@ -667,6 +672,8 @@ __device__ __forceinline__ void fstore(T v, brsrc r, uint32_t voff, uint32_t sof
     if constexpr (std::is_same<S, __bf16>::value) {
         const __bf16 h = (__bf16)(float)v;
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, voff, soff, 0);
+    } else if constexpr (sizeof(S) != sizeof(T)) {
+        bstore((S)v, r, voff, soff);
     } else {
         bstore(v, r, voff, soff);
     }
@@ -678,8 +685,11 @@ __device__ __forceinline__ float from_bf16(__bf16 h) {
 
 // The N values of a node column of one element layer (stride N^2 values), fields of storage type
 // S.  BM_PQ and BM_PQ32 read u + beta u2; in BM_PQ32 u is the V-cycle output, a field of type ZP
-// (FP32 or BF16), addressed at sizeof(ZP) / sizeof(T) of the byte offsets of T = double.
-template <typename T, int N, int MODE, typename S = T, typename ZP = float>
+// (FP32 or BF16), addressed at sizeof(ZP) / sizeof(T) of the byte offsets of T = double, and u2
+// the search direction, stored as SP (FP64, or FP32 when the direction is kept in single
+// precision: the new direction is then rounded to SP here, before it is used, so that q = A p is
+// the product of exactly the direction that is stored).
+template <typename T, int N, int MODE, typename S = T, typename ZP = float, typename SP = S>
 __device__ __forceinline__ void load_col(T* v, brsrc ru, brsrc ru2, uint32_t voff, uint32_t soff, T beta) {
     if constexpr (MODE == BM_PQ32) {
         static_assert(sizeof(T) == 8 && sizeof(S) == 8, "BM_PQ32 is an FP64 step");
@@ -694,12 +704,21 @@ __device__ __forceinline__ void load_col(T* v, brsrc ru, brsrc ru2, uint32_t vof
 #pragma unroll
         for (int k = 0; k < N; ++k) fload<S>(v[k], ru, voff, soff + k * N * N * (uint32_t)sizeof(S));
     }
-    if constexpr (MODE == BM_PQ || MODE == BM_PQ32) {
+    if constexpr (MODE == BM_PQ) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             T w;
             fload<S>(w, ru2, voff, soff + k * N * N * (uint32_t)sizeof(S));
             v[k] += beta * w;
+        }
+    } else if constexpr (MODE == BM_PQ32) {
+        constexpr uint32_t R2 = sizeof(T) / sizeof(SP);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            T w;
+            fload<SP>(w, ru2, voff / R2, soff / R2 + k * N * N * (uint32_t)sizeof(SP));
+            v[k] += beta * w;
+            if constexpr (sizeof(SP) == 4) v[k] = (T)(float)v[k];
         }
     }
 }
@@ -847,8 +866,11 @@ __device__ __forceinline__ void mf_xy_terms(const RefDev<float>& R, const mf_s4&
 }
 
 // S: storage type of the fields u, u2, f, zprev, out, out2 (T, or BF16 for FP32 arithmetic; the
-// pointers of SlabArgs<T> then address BF16 data); ZP: type of the BM_PQ32 input uf.
-template <typename T, int N, int TX, int TY, int MODE, bool MF = false, typename S = T, typename ZP = float>
+// pointers of SlabArgs<T> then address BF16 data); ZP: type of the BM_PQ32 input uf; SP: storage
+// type of the BM_PQ32 search direction (u2 in, out2 out); SC: storage type of the BM_RESTRICT
+// outputs fc and z1c (the coarse level's source and first smoothing iterate).
+template <typename T, int N, int TX, int TY, int MODE, bool MF = false, typename S = T, typename ZP = float,
+          typename SP = S, typename SC = T>
 __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     constexpr int NX = TX * N, NY = TY * N, NT = NX * NY, N2 = N * N, N3 = N2 * N;
     constexpr int WG = wg_of(NT);
@@ -890,13 +912,21 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
         ru = rsrc_of(reinterpret_cast<const ZP*>(a.uf) + base, a.ndof);
     else
         ru = rsrc_of(uS + base, a.ndof);
-    const brsrc ru2 = rsrc_of(IS_PQ ? reinterpret_cast<const S*>(a.u2) + base : uS + base, a.ndof);
+    brsrc ru2;
+    if constexpr (MODE == BM_PQ32)
+        ru2 = rsrc_of(reinterpret_cast<const SP*>(a.u2) + base, a.ndof);
+    else
+        ru2 = rsrc_of(IS_PQ ? reinterpret_cast<const S*>(a.u2) + base : uS + base, a.ndof);
     const brsrc rf = rsrc_of(HAS_F ? reinterpret_cast<const S*>(a.f) + base : uS + base, a.ndof);
     const brsrc rzp = rsrc_of(IS_CHEB && a.zprev ? reinterpret_cast<const S*>(a.zprev) + base : uS + base, a.ndof);
     // BM_RESTRICT stores no fine field
     S* const obase = MODE == BM_RESTRICT ? const_cast<S*>(uS) : reinterpret_cast<S*>(a.out);
     const brsrc ro = rsrc_of(obase + base, a.ndof);
-    const brsrc ro2 = rsrc_of(IS_PQ ? reinterpret_cast<S*>(a.out2) + base : obase + base, a.ndof);
+    brsrc ro2;
+    if constexpr (MODE == BM_PQ32)
+        ro2 = rsrc_of(reinterpret_cast<SP*>(a.out2) + base, a.ndof);
+    else
+        ro2 = rsrc_of(IS_PQ ? reinterpret_cast<S*>(a.out2) + base : obase + base, a.ndof);
     T beta = 0;
     if constexpr (IS_PQ) beta = (T)a.st[rhs].beta;
     const bool has_zp = IS_CHEB && a.zprev;
@@ -988,14 +1018,14 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
     T cur[N], nxt[N], nx2[N], hal[HS][N];
     T prevU = 0, prevD = 0;
     if (ezb > 0) {
-        load_col<T, N, MODE, S, ZP>(nx2, ru, ru2, coff, (uint32_t)(ezb - 1) * lstride, beta);
+        load_col<T, N, MODE, S, ZP, SP>(nx2, ru, ru2, coff, (uint32_t)(ezb - 1) * lstride, beta);
         prevU = nx2[N - 1];
         prevD = face_r(c, nx2);
     }
-    load_col<T, N, MODE, S, ZP>(cur, ru, ru2, coff, (uint32_t)ezb * lstride, beta);
+    load_col<T, N, MODE, S, ZP, SP>(cur, ru, ru2, coff, (uint32_t)ezb * lstride, beta);
 #pragma unroll
-    for (int s = 0; s < HS; ++s) load_col<T, N, MODE, S, ZP>(hal[s], ru, ru2, hoff[s], (uint32_t)ezb * lstride, beta);
-    if (ezb + 1 < E2) load_col<T, N, MODE, S, ZP>(nxt, ru, ru2, coff, (uint32_t)(ezb + 1) * lstride, beta);
+    for (int s = 0; s < HS; ++s) load_col<T, N, MODE, S, ZP, SP>(hal[s], ru, ru2, hoff[s], (uint32_t)ezb * lstride, beta);
+    if (ezb + 1 < E2) load_col<T, N, MODE, S, ZP, SP>(nxt, ru, ru2, coff, (uint32_t)(ezb + 1) * lstride, beta);
     // cr / D for the nodes of an interior layer, and for the bottom / top node of a boundary layer
     T crD[N], crD0 = 0, crDN = 0;
     if constexpr (IS_CHEB) {
@@ -1027,9 +1057,9 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
         // loads for later layers and for this layer's epilogue
         if (ez + 1 < eze) {
 #pragma unroll
-            for (int s = 0; s < HS; ++s) load_col<T, N, MODE, S, ZP>(hal[s], ru, ru2, hoff[s], soff + lstride, beta);
+            for (int s = 0; s < HS; ++s) load_col<T, N, MODE, S, ZP, SP>(hal[s], ru, ru2, hoff[s], soff + lstride, beta);
         }
-        if (ez + 1 < eze && ez + 2 < E2) load_col<T, N, MODE, S, ZP>(nx2, ru, ru2, coff, soff + 2 * lstride, beta);
+        if (ez + 1 < eze && ez + 2 < E2) load_col<T, N, MODE, S, ZP, SP>(nx2, ru, ru2, coff, soff + 2 * lstride, beta);
         T fcol[N], zpcol[N];
         if constexpr (HAS_F) {
 #pragma unroll
@@ -1108,6 +1138,11 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                     const T zn = uz + a.cp * (uz - zpcol[k]) + cd * (fcol[k] - y);
                     fstore<S>(zn, ro, coff, so);
                     if constexpr (MODE == BM_CHEBDOT) dot += (double)fcol[k] * (double)zn;
+                } else if constexpr (MODE == BM_PQ32) {
+                    constexpr uint32_t R2 = sizeof(T) / sizeof(SP);
+                    fstore<SP>(cur[k], ro2, coff / R2, so / R2);
+                    fstore<S>(y, ro, coff, so);
+                    dot += (double)cur[k] * (double)y;
                 } else if constexpr (IS_PQ) {
                     fstore<S>(cur[k], ro2, coff, so);
                     fstore<S>(y, ro, coff, so);
@@ -1154,8 +1189,16 @@ __global__ __launch_bounds__(wg_of(TX* TY* N* N)) void k_slab(SlabArgs<T> a) {
                 }
                 const long long idx =
                     (long long)rhs * a.ndofc + ((long long)(ez * E1 + eyo) * E0 + exo) * NC3 + loc;
-                a.fc[idx] = s;
-                if (a.z1c) a.z1c[idx] = a.c0c * s * a.dinvc[idx - (long long)rhs * a.ndofc];
+                if constexpr (std::is_same<SC, __bf16>::value) {
+                    static_assert(sizeof(T) == 4, "BF16 coarse fields: FP32 arithmetic only");
+                    reinterpret_cast<__bf16*>(a.fc)[idx] = to_bf16(s);
+                    if (a.z1c)
+                        reinterpret_cast<__bf16*>(a.z1c)[idx] =
+                            to_bf16(a.c0c * s * a.dinvc[idx - (long long)rhs * a.ndofc]);
+                } else {
+                    a.fc[idx] = s;
+                    if (a.z1c) a.z1c[idx] = a.c0c * s * a.dinvc[idx - (long long)rhs * a.ndofc];
+                }
             }
         }
 #pragma unroll
@@ -1318,10 +1361,12 @@ static void slab_dispatch(int mode, const SlabArgs<T>& a, int grid, hipStream_t 
     }
 }
 
-// The BF16-field forms: FP32 arithmetic on BF16 fields (smoothing, smoothing with f.z, restriction),
-// or the FP64 search-direction step reading a BF16 V-cycle output.
+// The BF16-field forms: FP32 arithmetic on BF16 fields (smoothing, smoothing with f.z, restriction,
+// whose coarse outputs are BF16 too when lpc), or the FP64 search-direction step reading a BF16
+// V-cycle output.  Degree 4 has every form; degree 2 (the level below a degree-4 finest level)
+// smoothing and a restriction into FP32 coarse fields.
 template <typename T, int N, int TX, int TY>
-static void slab_dispatch_lp(int mode, const SlabArgs<T>& a, int grid, hipStream_t s) {
+static void slab_dispatch_lp(int mode, const SlabArgs<T>& a, int grid, hipStream_t s, bool lpc) {
     constexpr int WG = wg_of(TX * TY * N * N);
     if constexpr (sizeof(T) == 4) {
         switch (mode) {
@@ -1329,15 +1374,27 @@ static void slab_dispatch_lp(int mode, const SlabArgs<T>& a, int grid, hipStream
                 hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_CHEB, false, __bf16>), dim3(grid), dim3(WG), 0, s, a);
                 break;
             case BM_CHEBDOT:
-                hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_CHEBDOT, false, __bf16>), dim3(grid), dim3(WG), 0, s, a);
+                if constexpr (N == 5)
+                    hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_CHEBDOT, false, __bf16>), dim3(grid), dim3(WG), 0, s,
+                                       a);
                 break;
             case BM_RESTRICT:
-                hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESTRICT, false, __bf16>), dim3(grid), dim3(WG), 0, s, a);
+                if constexpr (N == 5) {
+                    if (lpc)
+                        hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESTRICT, false, __bf16, float, __bf16, __bf16>),
+                                           dim3(grid), dim3(WG), 0, s, a);
+                    else
+                        hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESTRICT, false, __bf16>), dim3(grid), dim3(WG), 0,
+                                           s, a);
+                } else {
+                    hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_RESTRICT, false, __bf16>), dim3(grid), dim3(WG), 0, s,
+                                       a);
+                }
                 break;
         }
     } else {
         if (mode == BM_PQ32)
-            hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_PQ32, false, T, __bf16>), dim3(grid), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((k_slab<T, N, TX, TY, BM_PQ32, false, T, __bf16, float>), dim3(grid), dim3(WG), 0, s, a);
     }
 }
 
@@ -1346,7 +1403,7 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
                         const T* u, const T* u2, const T* f, const T* zprev, T* out, T* out2, double* partial,
                         int pstride, double cp, double cr, hipStream_t s, const LevelHost* Lc = nullptr,
                         const LevelDev<T>* devc = nullptr, T* fc = nullptr, T* z1c = nullptr, double c0c = 0,
-                        const void* uf = nullptr, bool mf = false, bool lp = false) {
+                        const void* uf = nullptr, bool mf = false, bool lp = false, bool lpc = false) {
     SlabGeom g = slab_geom<T>(L, mode);
     if (mf && mode == BM_APPLY && L.n == 5) {  // no partial sums: the smoothing steps' 4 x 2 tile, 4 layers
         g.tx = 4;
@@ -1399,16 +1456,26 @@ static bool launch_slab(int mode, const LevelHost& L, const LevelDev<T>* dev, in
             return true;
         }
     }
-    if (lp) {  // BF16 fields: FP32 smoothing and restriction steps, or the FP64 BM_PQ32 step, of degree 4
-        if (L.n != 5) return false;
+    if (lp) {  // BF16 fields: FP32 smoothing and restriction steps (degree 4 and 2), or the FP64 BM_PQ32 step
         if constexpr (sizeof(T) == 4) {
-            if (mode != BM_CHEB && mode != BM_CHEBDOT && mode != BM_RESTRICT) return false;
+            if (L.n == 5) {
+                if (mode != BM_CHEB && mode != BM_CHEBDOT && mode != BM_RESTRICT) return false;
+            } else if (L.n == 3) {
+                if (mode != BM_CHEB && !(mode == BM_RESTRICT && !lpc)) return false;
+            } else {
+                return false;
+            }
         } else {
-            if (mode != BM_PQ32) return false;
+            if (mode != BM_PQ32 || L.n != 5) return false;
         }
-        if (g.tx == 4 && g.ty == 2) slab_dispatch_lp<T, 5, 4, 2>(mode, a, grid, s);
-        else if (g.tx == 4 && g.ty == 4) slab_dispatch_lp<T, 5, 4, 4>(mode, a, grid, s);
-        else if (g.tx == 2 && g.ty == 2) slab_dispatch_lp<T, 5, 2, 2>(mode, a, grid, s);
+        if (L.n == 3) {
+            if (g.tx == 4 && g.ty == 4) slab_dispatch_lp<T, 3, 4, 4>(mode, a, grid, s, lpc);
+            else return false;
+            return true;
+        }
+        if (g.tx == 4 && g.ty == 2) slab_dispatch_lp<T, 5, 4, 2>(mode, a, grid, s, lpc);
+        else if (g.tx == 4 && g.ty == 4) slab_dispatch_lp<T, 5, 4, 4>(mode, a, grid, s, lpc);
+        else if (g.tx == 2 && g.ty == 2) slab_dispatch_lp<T, 5, 2, 2>(mode, a, grid, s, lpc);
         else return false;
         return true;
     }
@@ -1467,10 +1534,10 @@ bool launch_brick_lp(int mode, const LevelHost& L, const LevelDev<float>* dev, i
 
 bool launch_restrict_lp(const LevelHost& Lf, const LevelDev<float>* devf, const LevelHost& Lc,
                         const LevelDev<float>* devc, int nrhs, const RhsState* st, const float* z, const float* f,
-                        float* fc, float* z1c, double c0c, hipStream_t s) {
+                        float* fc, float* z1c, double c0c, hipStream_t s, bool coarse_bf16) {
     if (!z || Lf.hcoarse || Lc.n != (Lf.n - 1) / 2 + 1) return false;
     return launch_slab<float>(BM_RESTRICT, Lf, devf, nrhs, st, z, nullptr, f, nullptr, nullptr, nullptr, nullptr, 0,
-                              0, 0, s, &Lc, devc, fc, z1c, c0c, nullptr, false, true);
+                              0, 0, s, &Lc, devc, fc, z1c, c0c, nullptr, false, true, coarse_bf16);
 }
 
 __global__ __launch_bounds__(256) void k_widen(const float* __restrict__ a, double* __restrict__ b, long long n) {
@@ -1786,10 +1853,11 @@ void launch_restrict(const LevelHost& Lf, const LevelDev<T>* devf, const LevelHo
 // column (i, j) of an element contracts along x and y (NC^2 coarse values per
 // coarse z node) and then along z in registers, and updates its NF nodes.
 // SET: zf = scale[rhs] * P zc (every fine node written once) instead of zf += P zc.
-// SF: storage type of zf (T, or BF16 under FP32 arithmetic: read, add, round to nearest even).
-template <typename T, int NF, int NC, bool SET = false, typename SF = T>
+// SF: storage type of zf (T, or BF16 under FP32 arithmetic: read, add, round to nearest even); SZ:
+// storage type of zc (T, or BF16 widened on load).
+template <typename T, int NF, int NC, bool SET = false, typename SF = T, typename SZ = T>
 __global__ __launch_bounds__(256) void k_prolong_deg(const TransferDev* __restrict__ trp, long long nelem_rhs,
-                                                     long long nelem, const RhsState* st, const T* __restrict__ zc,
+                                                     long long nelem, const RhsState* st, const SZ* __restrict__ zc,
                                                      SF* __restrict__ zf, const double* __restrict__ scale = nullptr) {
     constexpr int NF2 = NF * NF, NF3 = NF2 * NF, NC3 = NC * NC * NC;
     constexpr int EPW = 256 / NF2;
@@ -1803,7 +1871,12 @@ __global__ __launch_bounds__(256) void k_prolong_deg(const TransferDev* __restri
     };
     const long long e0 = (long long)blockIdx.x * EPW;
     const int ne = (int)min((long long)EPW, nelem - e0);
-    for (int q = threadIdx.x; q < ne * NC3; q += 256) sc[q] = zc[e0 * NC3 + q];
+    for (int q = threadIdx.x; q < ne * NC3; q += 256) {
+        if constexpr (std::is_same<SZ, __bf16>::value)
+            sc[q] = from_bf16(zc[e0 * NC3 + q]);
+        else
+            sc[q] = zc[e0 * NC3 + q];
+    }
     __syncthreads();
     const int el = threadIdx.x / NF2, col = threadIdx.x % NF2;
     if (el >= ne) return;
@@ -1868,15 +1941,28 @@ bool launch_prolong_set(const LevelHost& Lf, const LevelHost& Lc, int nrhs, cons
 }
 
 bool launch_prolong_lp(const LevelHost& Lf, const LevelHost& Lc, int nrhs, const RhsState* st, const float* zc,
-                       float* zf, hipStream_t s) {
+                       float* zf, hipStream_t s, bool coarse_bf16) {
     if (Lf.hcoarse || Lf.E[0] != Lc.E[0] || Lf.E[1] != Lc.E[1] || Lf.E[2] != Lc.E[2]) return false;
-    if (!(Lf.n == 5 && Lc.n == 3)) return false;
+    const bool d42 = Lf.n == 5 && Lc.n == 3, d21 = Lf.n == 3 && Lc.n == 2 && !coarse_bf16;
+    if (!d42 && !d21) return false;
     const long long nel = (long long)Lf.E[0] * Lf.E[1] * Lf.E[2];
     const long long tot = nel * nrhs;
     if (tot == 0) return true;
+    __bf16* zfb = reinterpret_cast<__bf16*>(zf);
+    if (d21) {
+        constexpr int EPW = 256 / 9;
+        hipLaunchKernelGGL((k_prolong_deg<float, 3, 2, false, __bf16>), dim3((unsigned)((tot + EPW - 1) / EPW)),
+                           dim3(256), 0, s, Lf.devtr, nel, tot, st, zc, zfb, nullptr);
+        return true;
+    }
     constexpr int EPW = 256 / 25;
-    hipLaunchKernelGGL((k_prolong_deg<float, 5, 3, false, __bf16>), dim3((unsigned)((tot + EPW - 1) / EPW)), dim3(256),
-                       0, s, Lf.devtr, nel, tot, st, zc, reinterpret_cast<__bf16*>(zf), nullptr);
+    const unsigned grid = (unsigned)((tot + EPW - 1) / EPW);
+    if (coarse_bf16)
+        hipLaunchKernelGGL((k_prolong_deg<float, 5, 3, false, __bf16, __bf16>), dim3(grid), dim3(256), 0, s, Lf.devtr,
+                           nel, tot, st, reinterpret_cast<const __bf16*>(zc), zfb, nullptr);
+    else
+        hipLaunchKernelGGL((k_prolong_deg<float, 5, 3, false, __bf16>), dim3(grid), dim3(256), 0, s, Lf.devtr, nel,
+                           tot, st, zc, zfb, nullptr);
     return true;
 }
 
@@ -2261,10 +2347,10 @@ template void launch_update<double>(const LevelHost&, const LevelDev<double>*, i
 template void launch_update<float>(const LevelHost&, const LevelDev<float>*, int, const RhsState*, float*, float*,
                                    const float*, const float*, float*, double, double*, int, hipStream_t);
 
-template <typename TO>
+template <typename TO, typename TP>
 __global__ __launch_bounds__(256) void k_update_pc(const double* __restrict__ dinv, long long ndof, const RhsState* st,
                                                    double* __restrict__ x, double* __restrict__ r,
-                                                   const double* __restrict__ p, const double* __restrict__ q_,
+                                                   const TP* __restrict__ p, const double* __restrict__ q_,
                                                    TO* __restrict__ r32, TO* __restrict__ z1, double c0,
                                                    double* __restrict__ partial, int pstride) {
     __shared__ double red[4];
@@ -2279,7 +2365,7 @@ __global__ __launch_bounds__(256) void k_update_pc(const double* __restrict__ di
         const long long q = q0 + v * 256;
         if (q < ndof) {
             const long long g = base + q;
-            x[g] += alpha * p[g];
+            x[g] += alpha * (double)p[g];
             const double rn = r[g] - alpha * q_[g];
             r[g] = rn;
             acc += rn * rn;
@@ -2325,12 +2411,13 @@ void launch_update_pc(const LevelHost& L, const LevelDev<double>* dev, int nrhs,
                       int pstride, hipStream_t s, bool bf16) {
     (void)dev;
     if (nrhs == 0) return;
-    if (bf16)
-        hipLaunchKernelGGL(k_update_pc<__bf16>, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st, x,
-                           r, p, q, reinterpret_cast<__bf16*>(r32), reinterpret_cast<__bf16*>(z1), c0, partial, pstride);
+    if (bf16)  // BF16 fields; the search direction is stored in FP32 (the BF16-input BM_PQ32 step writes it)
+        hipLaunchKernelGGL((k_update_pc<__bf16, float>), rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof,
+                           st, x, r, reinterpret_cast<const float*>(p), q, reinterpret_cast<__bf16*>(r32),
+                           reinterpret_cast<__bf16*>(z1), c0, partial, pstride);
     else
-        hipLaunchKernelGGL(k_update_pc<float>, rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof, st, x,
-                           r, p, q, r32, z1, c0, partial, pstride);
+        hipLaunchKernelGGL((k_update_pc<float, double>), rhs_chunk_grid(L.ndof, nrhs), dim3(256), 0, s, L.dinv64, L.ndof,
+                           st, x, r, p, q, r32, z1, c0, partial, pstride);
 }
 
 void launch_to32_cheb0(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const RhsState* st, const double* r,

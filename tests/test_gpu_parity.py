@@ -499,18 +499,22 @@ def test_fp32_preconditioned_fp64_pcg_matches_exact(gpu_lib, case):
 
 
 P4_CASES = [
-    ((4, 6, 2), 4, (-2.0, -3.0, -1.0), (2.0, 3.0, 1.0), 0),      # every 4 x 2 tile at a face, 2-level
-    ((10, 6, 4), 4, (-5.0, -3.0, -2.0), (5.0, 3.0, 2.0), 0),     # interior and ragged tiles, 3 levels
-    ((8, 8, 8), 4, (-4.0, -4.0, -4.0), (4.0, 4.0, 4.0), 0),      # 4 levels (degree steps, then mesh steps)
+    ((4, 6, 2), 4, (-2.0, -3.0, -1.0), (2.0, 3.0, 1.0), 0),      # every 4 x 2 tile at a face, 2 levels:
+                                                                 # BF16 fields on the finest level only
+    ((10, 6, 4), 4, (-5.0, -3.0, -2.0), (5.0, 3.0, 2.0), 0),     # interior and ragged tiles, 3 levels: BF16
+                                                                 # on the degree-2 level, restricted into the
+                                                                 # coarsest
+    ((8, 8, 8), 4, (-4.0, -4.0, -4.0), (4.0, 4.0, 4.0), 0),      # 4 levels (degree steps, then a mesh step)
 ]
 
 
 @pytest.mark.parametrize("case", P4_CASES, ids=[f"E{c[0]}" for c in P4_CASES])
 def test_bf16_field_vcycle_pcg_matches_exact(gpu_lib, case):
-    """BF16F_PC: FP64 CG preconditioned by the V-cycle whose finest-level fields (source, smoother
-    iterates) are stored in BF16: the potentials meet the bar against the exact solve at the
-    parity tolerance, with FP32_PC's iteration count (+-1); the mode also runs in an interleaved
-    batch over two lanes and a second call from the converged potentials does no iteration."""
+    """BF16F_PC: FP64 CG (search direction stored in FP32) preconditioned by the V-cycle whose
+    fields (source, smoother iterates) on the finest level and, below it, on its degree-2 step are
+    stored in BF16: the potentials meet the bar against the exact solve at the parity tolerance,
+    with FP32_PC's iteration count (+-1); the mode also runs in an interleaved batch over two lanes
+    and a second call from the converged potentials does no iteration."""
     mesh = _mesh(case)
     dens = [_box_density(mesh, 160 + k) for k in range(20)]
     out = {}
