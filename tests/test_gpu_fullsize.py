@@ -163,34 +163,41 @@ def test_trained_guess_saves_iterations_on_a_molecule_outside_its_training_set(g
     assert np.abs(K_g - K_0).max() <= BENCH_ENERGY_BAR
 
 
-def test_exchange16_every_pair_at_operating_tolerance(gpu_lib):
-    """The largest exchange batch: 16 orbitals, all 136 pair densities on the 16^3, p = 4 mesh
-    in one call (two lanes of 68, FP32_PC, trained guess): every potential, pair energy and W_k
-    against the oracle's exact solves at the operating tolerance.  E_x sums 256 ordered pair
-    energies, so at that tolerance its error is bounded by the sum of theirs (measured 1.2e-10
-    Ha); one decade tighter (1e-12) it meets the 1e-10 Ha bar itself."""
+@pytest.fixture(scope="module")
+def exchange16_oracle():
     wl = configs.exchange16()
-    oracle = _oracle_exchange(wl)
-    got = _solve(gpu_lib, wl, OPERATING_RTOL, "fp32_pc", True)
+    return wl, _oracle_exchange(wl)
+
+
+@pytest.mark.parametrize("precision", ["fp32_pc", "bf16f_pc"])
+def test_exchange16_every_pair_at_operating_tolerance(gpu_lib, exchange16_oracle, precision):
+    """The largest exchange batch: 16 orbitals, all 136 pair densities on the 16^3, p = 4 mesh
+    in one call (two lanes of 68, FP32_PC or BF16F_PC, trained guess): every potential, pair
+    energy and W_k against the oracle's exact solves at the operating tolerance.  E_x sums 256
+    ordered pair energies, so at that tolerance its error is bounded by the sum of theirs
+    (measured 1.2e-10 Ha); one decade tighter (1e-12) it meets the 1e-10 Ha bar itself."""
+    wl, oracle = exchange16_oracle
+    got = _solve(gpu_lib, wl, OPERATING_RTOL, precision, True)
     assert len(got[3]) == 136
     n = wl.orbitals.norb
     eK = np.abs(got[1] - oracle[3])
     bound = sum((1.0 if i == j else 2.0) * eK[ox.pair_index(i, j, n)] for i in range(n) for j in range(i, n))
     _check_all(wl, oracle, got, OPERATING_RTOL, POT_BAR, ENERGY_BAR, ex_bar=bound)
-    got = _solve(gpu_lib, wl, 1e-12, "fp32_pc", True)
+    got = _solve(gpu_lib, wl, 1e-12, precision, True)
     _check_all(wl, oracle, got, 1e-12, POT_BAR, ENERGY_BAR)
 
 
-def test_uneven_batch_sampled_per_mesh(gpu_lib):
+@pytest.mark.parametrize("precision", ["fp32_pc", "bf16f_pc"])
+def test_uneven_batch_sampled_per_mesh(gpu_lib, precision):
     """The uneven batch: 256 Gaussian-sum densities over the 8^3, 12^3 and 16^3 meshes (p = 4)
-    interleaved in one call, FP32_PC at the operating tolerance: every residual below it, and
-    four potentials of each mesh (first, last and two between, in the caller's order) against
-    the exact solve."""
+    interleaved in one call, FP32_PC or BF16F_PC at the operating tolerance: every residual below
+    it, and four potentials of each mesh (first, last and two between, in the caller's order)
+    against the exact solve."""
     from _cases import oracle_density_problem
     wl = configs.uneven()
     ids = [int(m) for m in wl.batch.mesh_ids]
     ctx = gpu_lib.Context([(m.E, m.p, m.lo, m.hi) for m in wl.meshes], n_levels=wl.n_levels,
-                          rtol=OPERATING_RTOL, precision="fp32_pc")
+                          rtol=OPERATING_RTOL, precision=precision)
     coords = [ctx.mesh_coords(m) for m in range(3)]
     rho, g = [], []
     for k, mid in enumerate(ids):
