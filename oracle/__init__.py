@@ -15,7 +15,10 @@ electronic structure"):
                    with the penalty of eq. (pen_poly), on a uniform hexahedral
                    auxiliary mesh, as a Kronecker sum (Sec. 3.4-3.5), with
                    Dirichlet data imposed weakly (Sec. 6.3); right-hand side
-                   4*pi*rho sampled at the nodes (Sec. 6.1).
+                   4*pi*rho sampled at the nodes (Sec. 6.1).  Node family GLL
+                   (the library's default) or GL (the nodes Sec. 6.2 names: no
+                   node on a face, exact diagonal mass); ``face_points`` gives
+                   where Dirichlet data are sampled.
 * ``assemble``  -- an independent element-by-element assembly of the same
                    bilinear form from 3D volume and face quadrature, used to pin
                    the Kronecker-sum construction on tiny meshes.
@@ -27,7 +30,7 @@ electronic structure"):
 * ``exchange``  -- pair densities, exchange potentials W_k and pair energies
                    K_ij (Sec. 6.1, eq. fock_poisson).
 * ``boundary``  -- Dirichlet data by quadrature of the source over the grid
-                   (Sec. 6.3): g(r) = sum_q W_q f(x_q)/|r - x_q| at the boundary nodes.
+                   (Sec. 6.3): g(r) = sum_q W_q f(x_q)/|r - x_q| at the face points.
 * ``consumers`` -- the Hartree and exchange actions projected on a basis by the
                    grid's quadrature (Sec. 6.1) and the adaptively compressed
                    exchange built from the exchange action on the occupied

@@ -6,8 +6,9 @@ grad(phi_a).grad(phi_b); for every interior face the terms
 -[[phi_a]].{grad phi_b} - {grad phi_a}.[[phi_b]] + sigma [[phi_a]].[[phi_b]]
 with the vector jump of eq. (jump_operator) and full 3D gradients; and for
 boundary faces the Nitsche terms with [[phi]] = phi n and {grad phi} = grad phi.
-Integrals use the tensor GLL rule of the element and of the face (the nodal
-points define the quadrature, Sec. 6.1).  Nothing here uses the Kronecker-sum
+Integrals use the tensor rule of the node family (GLL or GL) on the element and
+on the face (the nodal points define the quadrature, Sec. 6.1); face traces are
+the basis functions evaluated on the face.  Nothing here uses the Kronecker-sum
 form, so agreement with ``sipdg.dense_matrix`` pins that construction.
 
 Only for tiny meshes (dense matrices).  Test infrastructure only.
@@ -34,14 +35,14 @@ def _basis_at(xi, pts_ref):
     return _nodes.lagrange_eval(xi, pts_ref), _nodes.lagrange_derivative(xi, pts_ref)
 
 
-def assemble(E, p, lo, hi, f=None, faces=None, eps=PENALTY_EPS):
+def assemble(E, p, lo, hi, f=None, faces=None, eps=PENALTY_EPS, family="gll"):
     """Dense A (and b if f, faces given) in flattened [Z, Y, X] order.
 
     f: callable f(x, y, z) or None;  faces: callable g(x, y, z) giving the
     Dirichlet value at boundary points, or None.
     """
     n = p + 1
-    xi, w, _ = _nodes.gll(p)
+    xi, w, _ = _nodes.gll(p) if family == "gll" else _nodes.gl(p)
     h = [(hi[d] - lo[d]) / E[d] for d in range(3)]
     J = [hd / 2.0 for hd in h]
     NX, NY, NZ = E[0] * n, E[1] * n, E[2] * n

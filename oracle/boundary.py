@@ -57,9 +57,10 @@ def potential_at(axes, f, points, chunk=None):
 
 
 def boundary_points(axes):
-    """The boundary nodes in face order (x-, x+, y-, y+, z-, z+), array [n_face, 3]."""
-    X, Y, Z = np.broadcast_arrays(*sipdg.node_grid(axes))
-    fx, fy, fz = (layout.boundary_faces_of(A) for A in (X, Y, Z))
+    """The face points (the boundary nodes for GLL) in face order (x-, x+, y-, y+, z-, z+),
+    array [n_face, 3]."""
+    fp = sipdg.face_points(axes)
+    fx, fy, fz = ([fp[f][c] for f in range(6)] for c in range(3))
     return np.stack([layout.join_faces(fx), layout.join_faces(fy), layout.join_faces(fz)], axis=1)
 
 

@@ -96,9 +96,9 @@ def lanczos_max(apply_sym, v0, steps):
 
 
 class Level:
-    def __init__(self, E, p, lo, hi, eps=_sipdg.PENALTY_EPS):
+    def __init__(self, E, p, lo, hi, eps=_sipdg.PENALTY_EPS, family="gll"):
         self.E, self.p, self.n = tuple(E), p, p + 1
-        self.axes = _sipdg.make_axes(E, p, lo, hi, eps)
+        self.axes = _sipdg.make_axes(E, p, lo, hi, eps, family)
         self.D = _sipdg.diagonal(self.axes)
         self.shape = self.D.shape
 
@@ -110,9 +110,9 @@ class Hierarchy:
     """Levels, transfers, smoother parameters and the V-cycle."""
 
     def __init__(self, E, p, lo, hi, n_levels=None, degree=6, ratio=60.0, safety=1.1,
-                 lanczos_steps=30, max_coarse_nodes=16, eps=_sipdg.PENALTY_EPS, degree_h=10):
+                 lanczos_steps=30, max_coarse_nodes=16, eps=_sipdg.PENALTY_EPS, degree_h=10, family="gll"):
         self.specs = hierarchy(E, p, n_levels, max_coarse_nodes)
-        self.levels = [Level(Es, ps, lo, hi, eps) for Es, ps in self.specs]
+        self.levels = [Level(Es, ps, lo, hi, eps, family) for Es, ps in self.specs]
         self.P = []
         for lf, lc in zip(self.levels[:-1], self.levels[1:]):
             self.P.append([prolongation_1d(lf.axes[d], lc.axes[d]) for d in range(3)])

@@ -14,7 +14,12 @@ interior-penalty boundary terms (Nitsche), which keep the matrix symmetric
 positive definite; a boundary face uses its own element's width in sigma.
 
 Quadrature: the nodal points define the quadrature rule (Sec. 6.1), so volume
-and face integrals use GLL collocation; the mass is diagonal.  With that rule
+and face integrals use collocation at the nodes; the mass is diagonal.  Two node
+families: Gauss-Lobatto-Legendre (``family="gll"``, the default: the end points
+are nodes, so face values are node values; the mass is lumped) and Gauss-Legendre
+(``family="gl"``, the family Sec. 6.2 names: no node on a face, face values and
+derivatives are interpolated, and the (p+1)-point rule integrates every product
+that appears exactly, so the diagonal mass is the exact one).  With either rule
 the 3D matrix is exactly the Kronecker sum (Sec. 3.5)
     A = A1_x (x) M1_y (x) M1_z + M1_x (x) A1_y (x) M1_z + M1_x (x) M1_y (x) A1_z.
 
@@ -40,19 +45,27 @@ class Axis1D:
 
     Attributes (all FP64, global 1D node index X = e*(p+1) + i):
       x      node coordinates, length E*(p+1)
-      m      lumped GLL mass  J*omega_i            (diagonal of M1)
+      m      mass at the nodes  J*omega_i            (diagonal of M1)
       A      1D SIPDG matrix with Nitsche Dirichlet faces (dense)
       liftL  right-hand-side vector multiplying the left boundary value
       liftR  right-hand-side vector multiplying the right boundary value
+      eL, eR values of the element's basis functions at its left / right end
+      dL, dR their derivatives there (physical units)
     """
 
-    def __init__(self, E, p, a, b, eps=PENALTY_EPS):
+    def __init__(self, E, p, a, b, eps=PENALTY_EPS, family="gll"):
         self.E, self.p, self.a, self.b = int(E), int(p), float(a), float(b)
         n = p + 1
         self.n = n
+        self.family = family
         self.h = (self.b - self.a) / E
         J = self.h / 2.0
-        xi, w, Dh = _nodes.gll(p)
+        if family == "gll":
+            xi, w, Dh = _nodes.gll(p)
+        elif family == "gl":
+            xi, w, Dh = _nodes.gl(p)
+        else:
+            raise ValueError(f"unknown node family {family!r}")
         self.xi, self.w, self.Dhat = xi, w, Dh
         self.sigma = penalty(p, self.h, eps)
         N = E * n
@@ -62,16 +75,17 @@ class Axis1D:
         Kloc = Dh.T @ np.diag(w) @ Dh / J              # int_e l_i' l_j' dx
         for e in range(E):
             A[e * n:(e + 1) * n, e * n:(e + 1) * n] += Kloc
-        dL = Dh[0, :] / J                              # u -> u'(left end of element)
-        dR = Dh[p, :] / J                              # u -> u'(right end of element)
+        # traces: u -> u(left end), u(right end), u'(left end), u'(right end) of an element
+        eL = _nodes.lagrange_eval(xi, -1.0)[0]
+        eR = _nodes.lagrange_eval(xi, 1.0)[0]
+        dL = _nodes.lagrange_derivative(xi, -1.0)[0] / J
+        dR = _nodes.lagrange_derivative(xi, 1.0)[0] / J
 
         def vec(e, local):
             v = np.zeros(N)
             v[e * n:(e + 1) * n] = local
             return v
 
-        eL = np.zeros(n); eL[0] = 1.0
-        eR = np.zeros(n); eR[p] = 1.0
         s = self.sigma
         for e in range(E - 1):
             # face between e (minus side, normal +1) and e+1 (plus side, normal -1)
@@ -87,16 +101,16 @@ class Axis1D:
         # lift: int_face g (sigma v - d_n v)
         self.liftL = s * jl - gl_
         self.liftR = s * jr - gr_
-        self.dL, self.dR = dL, dR
+        self.eL, self.eR, self.dL, self.dR = eL, eR, dL, dR
 
     @property
     def N(self):
         return self.E * self.n
 
 
-def make_axes(E, p, lo, hi, eps=PENALTY_EPS):
+def make_axes(E, p, lo, hi, eps=PENALTY_EPS, family="gll"):
     """Three Axis1D objects (x, y, z) for an Ex*Ey*Ez mesh on the box [lo, hi]."""
-    return [Axis1D(E[d], p, lo[d], hi[d], eps) for d in range(3)]
+    return [Axis1D(E[d], p, lo[d], hi[d], eps, family) for d in range(3)]
 
 
 def apply(axes, u):
@@ -136,9 +150,10 @@ def rhs(axes, f, faces):
     """b = 4 pi M f + sum over the six faces of (lift (x) M1 (x) M1) g.
 
     ``f`` is the source sampled at the nodes, array [Z, Y, X]; ``faces`` is the
-    list [gxm, gxp, gym, gyp, gzm, gzp] of Dirichlet values at the boundary
-    nodes (x faces indexed [Z, Y], y faces [Z, X], z faces [Y, X]).  Edge and
-    corner nodes receive one term from each face they lie on.
+    list [gxm, gxp, gym, gyp, gzm, gzp] of Dirichlet values at the face points
+    (``face_points``: the boundary nodes for GLL; for GL the tangential nodes on
+    the boundary plane), x faces indexed [Z, Y], y faces [Z, X], z faces [Y, X].
+    With GLL, edge and corner nodes receive one term from each face they lie on.
     """
     ax, ay, az = axes
     b = 4.0 * np.pi * mass(axes) * np.asarray(f, dtype=np.float64)
@@ -159,3 +174,24 @@ def node_grid(axes):
     """Coordinate arrays X, Y, Z broadcastable to [Z, Y, X]."""
     ax, ay, az = axes
     return ax.x[None, None, :], ay.x[None, :, None], az.x[:, None, None]
+
+
+def face_points(axes):
+    """Coordinates of the face points where Dirichlet data are given, in face order
+    (x-, x+, y-, y+, z-, z+): lists [X, Y, Z] of arrays shaped like the face (x faces [Z, Y],
+    y faces [Z, X], z faces [Y, X]).  The tangential coordinates are the nodes of the other two
+    axes and the normal coordinate is the boundary plane (for GLL these are the boundary nodes)."""
+    ax, ay, az = axes
+    out = []
+    for d, (lo_, hi_) in enumerate(((ax.a, ax.b), (ay.a, ay.b), (az.a, az.b))):
+        for v in (lo_, hi_):
+            if d == 0:
+                Zg, Yg = np.meshgrid(az.x, ay.x, indexing="ij")
+                out.append([np.full(Zg.shape, v), Yg, Zg])
+            elif d == 1:
+                Zg, Xg = np.meshgrid(az.x, ax.x, indexing="ij")
+                out.append([Xg, np.full(Zg.shape, v), Zg])
+            else:
+                Yg, Xg = np.meshgrid(ay.x, ax.x, indexing="ij")
+                out.append([Xg, Yg, np.full(Yg.shape, v)])
+    return out
