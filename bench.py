@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--fused", type=int, default=None, choices=[0, 1, 2],
                     help="FP64 small-mesh solve in one launch: 1 one work-group per RHS, 2 group-persistent")
     ap.add_argument("--fused-wgs", type=int, default=None, help="work-groups per RHS of the group-persistent solve")
+    ap.add_argument("--node-family", default=None, choices=["gll", "gl"],
+                    help="element nodes: gll (default) or gl (Gauss-Legendre: general operator kernels, no learned "
+                         "guess; the oracle legs are skipped)")
     ap.add_argument("--profile-solves", type=int, default=2,
                     help="eager solves of the headline arm that time the dominant kernel (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=1, help="pair solves timed on the oracle (0: skip)")
@@ -90,8 +93,12 @@ def parse():
     args = ap.parse_args()
     args.solver_opts = {k: v for k, v in (("cheb_degree", args.cheb_degree), ("cheb_ratio", args.cheb_ratio),
                                           ("cheb_degree_h", args.cheb_degree_h), ("inner_rtol", args.inner_rtol),
-                                          ("fused", args.fused), ("fused_wgs", args.fused_wgs))
+                                          ("fused", args.fused), ("fused_wgs", args.fused_wgs),
+                                          ("node_family", args.node_family))
                         if v is not None}
+    if args.node_family == "gl":
+        # the CPU legs compare with the oracle's Gauss-Lobatto solve; the GL parity lives in the tests
+        args.check, args.cpu_sample, args.profile_solves, args.metric_rtol = 0, 0, 0, 0
     return args
 
 

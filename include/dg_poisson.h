@@ -106,7 +106,7 @@ typedef enum {
 } dg_precision;
 
 /* A uniform hexahedral mesh: ne[d] elements along axis d on [lo[d], hi[d]],
- * Gauss-Lobatto nodal polynomials of degree p (1 <= p <= 7). */
+ * nodal polynomials of degree p (1 <= p <= 7) on the node family of dg_opts.node_family. */
 typedef struct {
     int ne[3];
     int p;
@@ -155,6 +155,16 @@ typedef struct {
     long long fused_spin; /* fused = 2: polls before a group barrier gives up; 0 = default
                             (2,000,000, about a second); negative: give up at the first poll
                             that finds the group incomplete (tests the fallback) */
+    int node_family;     /* nodes of every element, which also define the quadrature (Sec. 6.1,
+                            Sec. 6.2): 0 (default) Gauss-Lobatto-Legendre, the end points are
+                            nodes and face values are node values; 1 Gauss-Legendre, the family
+                            Sec. 6.2 names: no node on a face, face values and derivatives are
+                            interpolated, the diagonal mass is exact.  Gauss-Legendre meshes run
+                            on the general (brick) operator kernels in every precision (BF16F_PC
+                            and BF16_PC then run as FP32_PC), take Dirichlet data from the caller
+                            at the face points dg_mesh_coords gives (no quadrature data), no
+                            learned guess and no fused solve (DG_ERR_ARG); point-Jacobi smoothing
+                            sees less of their operator, so they need more iterations. */
 } dg_opts;
 
 typedef struct {

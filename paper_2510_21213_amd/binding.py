@@ -20,6 +20,7 @@ DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
 DG_PREC_FP64, DG_PREC_FP32_IR, DG_PREC_FP32_PC, DG_PREC_BF16_PC, DG_PREC_BF16F_PC = 0, 1, 2, 3, 4
 PRECISIONS = {"fp64": DG_PREC_FP64, "fp32_ir": DG_PREC_FP32_IR, "fp32_pc": DG_PREC_FP32_PC,
               "bf16_pc": DG_PREC_BF16_PC, "bf16f_pc": DG_PREC_BF16F_PC}
+NODE_FAMILIES = {"gll": 0, "gl": 1}   # dg_opts.node_family
 
 
 class DgMesh(ctypes.Structure):
@@ -34,7 +35,7 @@ class DgOpts(ctypes.Structure):
                 ("precision", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("lanes", ctypes.c_int),
                 ("cheb_degree_h", ctypes.c_int), ("fused", ctypes.c_int), ("fused_wgs", ctypes.c_int),
-                ("fused_spin", ctypes.c_longlong)]
+                ("fused_spin", ctypes.c_longlong), ("node_family", ctypes.c_int)]
 
 
 class DgRhsStats(ctypes.Structure):
@@ -164,6 +165,8 @@ def default_opts(**kw):
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = PRECISIONS[v]
+        if k == "node_family" and isinstance(v, str):
+            v = NODE_FAMILIES[v]
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

@@ -682,7 +682,7 @@ void build_qnodes(dg_ctx* ctx, Mesh& M) {
         dg::AxisDev<double> ax;
         std::vector<double> nodes;
         dg::build_axis(M.mesh.ne[d], M.mesh.p, M.mesh.lo[d], M.mesh.hi[d], ctx->opts.penalty_eps, ax, nullptr,
-                       &nodes);
+                       &nodes, ctx->opts.node_family);
         all.insert(all.end(), nodes.begin(), nodes.end());
     }
     double* d = dalloc<double>((long long)all.size());
@@ -693,6 +693,8 @@ void build_qnodes(dg_ctx* ctx, Mesh& M) {
 void quad_data(dg_ctx* ctx, Mesh& M, int nsrc, const double* f, const double* phi, const int* pi, const int* pj,
                double* g, hipStream_t s) {
     const LevelHost& L0 = M.lv[0];
+    if (L0.family != 0)
+        throw ArgError("Dirichlet data by quadrature need Gauss-Lobatto nodes (pass g at the face points)");
     const dg::QuadPlan P = dg::quad_plan(L0, nsrc);
     if (P.nface != M.nface) throw std::logic_error("quadrature plan: face count mismatch");
     ensure_len(ctx->qrec, ctx->qrec_cap, P.rec_len);
@@ -705,7 +707,7 @@ void quad_data(dg_ctx* ctx, Mesh& M, int nsrc, const double* f, const double* ph
 // null when the mesh is not small enough.
 void build_fused(Mesh& M) {
     const int nl = (int)M.lv.size();
-    if (nl > dg::FUSED_MAX_LEVELS) return;
+    if (nl > dg::FUSED_MAX_LEVELS || M.lv[0].family != 0) return;
     bool lds_ok = true;
     for (int l = 0; l < nl; ++l) {
         const LevelHost& L = M.lv[l];
@@ -1164,10 +1166,14 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
         L.n = p + 1;
         L.ndof = (long long)E[0] * E[1] * E[2] * L.n * L.n * L.n;
         L.be = dg::brick_edge(L.n);
+        L.family = o.node_family;
         for (int d = 0; d < 3; ++d) L.nbr[d] = (E[d] + L.be - 1) / L.be;
         dg::assign_tiles(L);
+        if (L.family != 0)  // the slab kernels take face values at the end nodes: GL runs on the bricks
+            for (int f = 0; f < 2; ++f)
+                for (int m = 0; m <= dg::BM_RESTRICT; ++m) L.tile[f][m][0] = 0;
         for (int d = 0; d < 3; ++d) {
-            dg::build_axis(E[d], p, mesh.lo[d], mesh.hi[d], o.penalty_eps, L.d64.ax[d], nullptr, nullptr);
+            dg::build_axis(E[d], p, mesh.lo[d], mesh.hi[d], o.penalty_eps, L.d64.ax[d], nullptr, nullptr, L.family);
             auto& a = L.d64.ax[d];
             auto& f = L.d32.ax[d];
             std::memset(&f, 0, sizeof(f));
@@ -1179,12 +1185,15 @@ void setup_mesh(dg_ctx* ctx, const dg_mesh& mesh, Mesh& M, hipStream_t s) {
             for (int i = 0; i < dg::NMAX; ++i) {
                 f.dL[i] = (float)a.dL[i];
                 f.dR[i] = (float)a.dR[i];
+                f.eL[i] = (float)a.eL[i];
+                f.eR[i] = (float)a.eR[i];
                 f.m[i] = (float)a.m[i];
                 f.liftL[i] = (float)a.liftL[i];
                 f.liftR[i] = (float)a.liftR[i];
             }
             f.sigma = (float)a.sigma;
             f.E = a.E;
+            f.gl = a.gl;
         }
         dg::build_ref(p, o.penalty_eps, L.h, L.d64.ref);
         {
@@ -1371,6 +1380,7 @@ void dg_opts_default(dg_opts* o) {
     o->fused = 0;
     o->fused_wgs = 0;
     o->fused_spin = 0;
+    o->node_family = 0;
 }
 
 const char* dg_status_string(dg_status s) {
@@ -1401,8 +1411,10 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
             o.penalty_eps <= 0 || o.rtol <= 0 || o.max_iter < 1 || o.max_outer < 1 || o.inner_rtol <= 0 ||
             o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 2 ||
             (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_IR && o.precision != DG_PREC_FP32_PC &&
-             o.precision != DG_PREC_BF16_PC && o.precision != DG_PREC_BF16F_PC))
+             o.precision != DG_PREC_BF16_PC && o.precision != DG_PREC_BF16F_PC) ||
+            o.node_family < 0 || o.node_family > 1)
             throw ArgError("invalid solver options");
+        if (o.node_family != 0 && o.fused != 0) throw ArgError("the fused solves need Gauss-Lobatto nodes");
         HIPCHK(hipGetDevice(&ctx->device));
         HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
@@ -1544,7 +1556,8 @@ dg_status dg_mesh_coords(const dg_ctx* ctx, int mesh_id, double* xyz, double* fx
         std::vector<double> nodes[3];
         for (int d = 0; d < 3; ++d) {
             dg::AxisDev<double> ax;
-            dg::build_axis(m.ne[d], m.p, m.lo[d], m.hi[d], ctx->opts.penalty_eps, ax, nullptr, &nodes[d]);
+            dg::build_axis(m.ne[d], m.p, m.lo[d], m.hi[d], ctx->opts.penalty_eps, ax, nullptr, &nodes[d],
+                           ctx->opts.node_family);
         }
         const long long ndof = M.lv[0].ndof;
         if (xyz) {
@@ -1975,6 +1988,8 @@ dg_status dg_boundary_data_noalloc(dg_ctx* ctx, int mesh_id, int nsrc, const dou
         if (!scr) throw HipError("work space of this device not set up");
         const Mesh& M = ctx->meshes[mesh_id];
         const LevelHost& L0 = M.lv[0];
+        if (L0.family != 0)
+            throw ArgError("Dirichlet data by quadrature need Gauss-Lobatto nodes (pass g at the face points)");
         const dg::QuadPlan P = dg::quad_plan_bounded(L0, nsrc, cap);
         if (P.R == 0) throw ArgError("mesh too large for the fixed work space (records of one source exceed it)");
         // records first, then the split partial sums (every entry read is written first in the call)
@@ -2125,6 +2140,8 @@ dg_status dg_prolong_add(dg_ctx* ctx, int mesh_id, int level, int nrhs, const do
 dg_status dg_poisson_attach_guess(dg_ctx* ctx, dg_net* net) {
     return run_guarded([&] {
         if (!ctx) throw ArgError("null context");
+        if (net && ctx->opts.node_family != 0)
+            throw ArgError("the guess network works on Gauss-Lobatto element values");
         ctx->guess = net;
     });
 }

@@ -26,12 +26,14 @@ struct AxisDev {
     T Bd[4][NMAX];       // diagonal of B
     T dL[NMAX];          // u -> u'(left end of the element)
     T dR[NMAX];          // u -> u'(right end of the element)
-    T m[NMAX];           // lumped GLL mass J*w
+    T eL[NMAX];          // u -> u(left end of the element): the first node for GLL
+    T eR[NMAX];          // u -> u(right end of the element): the last node for GLL
+    T m[NMAX];           // mass at the nodes J*w (lumped for GLL, exact for GL)
     T liftL[NMAX];       // boundary lift of the left boundary element
     T liftR[NMAX];       // boundary lift of the right boundary element
     T sigma;             // penalty of this level along this axis
     int E;               // elements along this axis
-    int pad;
+    int gl;              // 1: Gauss-Legendre nodes (face values by eL / eR), 0: Gauss-Lobatto
 };
 
 // Reference-element form of a level's interior 1D block, shared by the three
@@ -101,6 +103,7 @@ struct RhsState {
 struct LevelHost {
     int E[3];
     int p, n;
+    int family = 0;  // node family (dg_opts.node_family)
     double h[3], lo[3];
     long long ndof;
     double lam_lo = 0, lam_hi = 0;
@@ -123,10 +126,14 @@ struct LevelHost {
 
 // Host-side numerics (dg_setup.cpp).
 void gll(int p, std::vector<double>& xi, std::vector<double>& w, std::vector<double>& D);
+void gl(int p, std::vector<double>& xi, std::vector<double>& w, std::vector<double>& D);
+// the nodes, weights and derivative matrix of a node family (0 GLL, 1 GL)
+void node_rule(int p, int family, std::vector<double>& xi, std::vector<double>& w, std::vector<double>& D);
 void lagrange_eval(const std::vector<double>& nodes, const std::vector<double>& x, std::vector<double>& L);
+void lagrange_deriv(const std::vector<double>& nodes, const std::vector<double>& x, std::vector<double>& G);
 void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V);
 void build_axis(int E, int p, double lo, double hi, double eps, AxisDev<double>& ax, std::vector<double>* dense,
-                std::vector<double>* nodes);
+                std::vector<double>* nodes, int family = 0);
 void build_ref(int p, double eps, const double h[3], RefDev<double>& r);
 int brick_edge(int n);
 std::vector<std::pair<std::array<int, 3>, int>> hierarchy(const int E[3], int p, int n_levels);

@@ -79,6 +79,9 @@ constexpr int be_of() { return N <= 3 ? 4 : (N <= 6 ? 2 : 1); }
 // One axis of the operator over a brick row of NB = BE*N values (elements
 // e0 .. e0+BE-1).  hl*: face value / derivative of element e0-1 at its right
 // end; hr*: of element e0+BE at its left end (only read when they exist).
+// Face values are the end nodes on Gauss-Lobatto axes; on Gauss-Legendre axes
+// (A.gl) they are the traces eR . line and eL . line, and the jump terms reach
+// every node of the line through eL and eR.
 template <typename T, int N, int BE>
 __device__ __forceinline__ void axis_row(const AxisDev<T>& A, int e0, int E, const T* row, T hlu, T hld, T hru,
                                          T hrd, T* out) {
@@ -100,32 +103,56 @@ __device__ __forceinline__ void axis_row(const AxisDev<T>& A, int e0, int E, con
             if (e > 0) {
                 T up, dp;
                 if (b > 0) {
-                    up = row[b * N - 1];
                     dp = 0;
 #pragma unroll
                     for (int l = 0; l < N; ++l) dp += A.dR[l] * row[(b - 1) * N + l];
+                    if (A.gl) {
+                        up = 0;
+#pragma unroll
+                        for (int l = 0; l < N; ++l) up += A.eR[l] * row[(b - 1) * N + l];
+                    } else {
+                        up = row[b * N - 1];
+                    }
                 } else {
                     up = hlu;
                     dp = hld;
                 }
-                acc[0] += half * dp - sg * up;
+                if (A.gl) {
+                    const T c = half * dp - sg * up;
 #pragma unroll
-                for (int i = 0; i < N; ++i) acc[i] -= half * A.dL[i] * up;
+                    for (int i = 0; i < N; ++i) acc[i] += A.eL[i] * c - half * A.dL[i] * up;
+                } else {
+                    acc[0] += half * dp - sg * up;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) acc[i] -= half * A.dL[i] * up;
+                }
             }
             if (e < E - 1) {
                 T u0, d0;
                 if (b < BE - 1) {
-                    u0 = row[(b + 1) * N];
                     d0 = 0;
 #pragma unroll
                     for (int l = 0; l < N; ++l) d0 += A.dL[l] * row[(b + 1) * N + l];
+                    if (A.gl) {
+                        u0 = 0;
+#pragma unroll
+                        for (int l = 0; l < N; ++l) u0 += A.eL[l] * row[(b + 1) * N + l];
+                    } else {
+                        u0 = row[(b + 1) * N];
+                    }
                 } else {
                     u0 = hru;
                     d0 = hrd;
                 }
-                acc[N - 1] += -half * d0 - sg * u0;
+                if (A.gl) {
+                    const T c = -half * d0 - sg * u0;
 #pragma unroll
-                for (int i = 0; i < N; ++i) acc[i] += half * A.dR[i] * u0;
+                    for (int i = 0; i < N; ++i) acc[i] += A.eR[i] * c + half * A.dR[i] * u0;
+                } else {
+                    acc[N - 1] += -half * d0 - sg * u0;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) acc[i] += half * A.dR[i] * u0;
+                }
             }
 #pragma unroll
             for (int i = 0; i < N; ++i) out[b * N + i] = acc[i];
@@ -258,14 +285,24 @@ __device__ __forceinline__ void brick_load(int E0, int E1, int E2, int ex0, int 
 template <typename T, int N>
 __device__ __forceinline__ void halo_reduce(const AxisDev<T>& A, const T* hl, const T* hr, T& hlu, T& hld, T& hru,
                                             T& hrd) {
-    hlu = hl[N - 1];
-    hru = hr[0];
     hld = 0;
     hrd = 0;
 #pragma unroll
     for (int l = 0; l < N; ++l) {
         hld += A.dR[l] * hl[l];
         hrd += A.dL[l] * hr[l];
+    }
+    if (A.gl) {
+        hlu = 0;
+        hru = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            hlu += A.eR[l] * hl[l];
+            hru += A.eL[l] * hr[l];
+        }
+    } else {
+        hlu = hl[N - 1];
+        hru = hr[0];
     }
 }
 

@@ -61,6 +61,56 @@ void gll(int p, std::vector<double>& xi, std::vector<double>& w, std::vector<dou
     D[p * n + p] = p * (p + 1.0) / 4.0;
 }
 
+// Gauss-Legendre nodes (the roots of P_{p+1}, by Newton's method from the usual cosine
+// estimates), weights 2 / ((1 - x^2) P_{p+1}'(x)^2) and the derivative matrix D[i][j] = l_j'(x_i).
+void gl(int p, std::vector<double>& xi, std::vector<double>& w, std::vector<double>& D) {
+    const int n = p + 1;
+    xi.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double x = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(n, x, P, dP);
+            const double dx = P / dP;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        xi[i] = x;
+    }
+    std::sort(xi.begin(), xi.end());
+    for (int i = 0; i < n; ++i) {
+        double P, dP;
+        legendre(n, xi[i], P, dP);
+        w[i] = 2.0 / ((1.0 - xi[i] * xi[i]) * dP * dP);
+    }
+    std::vector<double> G;
+    lagrange_deriv(xi, xi, G);
+    D = G;
+}
+
+void node_rule(int p, int family, std::vector<double>& xi, std::vector<double>& w, std::vector<double>& D) {
+    if (family == 1)
+        gl(p, xi, w, D);
+    else
+        gll(p, xi, w, D);
+}
+
+// G[a*n + j] = l_j'(x_a): the product rule on the product formula of the Lagrange basis.
+void lagrange_deriv(const std::vector<double>& nodes, const std::vector<double>& x, std::vector<double>& G) {
+    const int n = (int)nodes.size(), m = (int)x.size();
+    G.assign((size_t)m * n, 0.0);
+    for (int a = 0; a < m; ++a)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                if (k == j) continue;
+                double term = 1.0 / (nodes[j] - nodes[k]);
+                for (int q = 0; q < n; ++q)
+                    if (q != j && q != k) term *= (x[a] - nodes[q]) / (nodes[j] - nodes[q]);
+                G[a * n + j] += term;
+            }
+}
+
 // L[a*n + j] = l_j(x_a), Lagrange basis on `nodes`, product formula.
 void lagrange_eval(const std::vector<double>& nodes, const std::vector<double>& x, std::vector<double>& L) {
     const int n = (int)nodes.size(), m = (int)x.size();
@@ -135,12 +185,14 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
 // Element block for position type t (bit 0: left boundary, bit 1: right
 // boundary): local stiffness plus the own-element parts of the face terms of
 // eq. (sip_bilinear); boundary faces carry the symmetric Nitsche terms.
-// Optionally returns the dense 1D matrix and the node coordinates.
+// Optionally returns the dense 1D matrix and the node coordinates.  The face terms use the
+// element's traces: eL, eR (the values at its ends) and dL, dR (the derivatives there); for GLL
+// eL and eR pick the end nodes, for GL they are the Lagrange basis evaluated at -1 and +1.
 void build_axis(int E, int p, double lo, double hi, double eps, AxisDev<double>& ax, std::vector<double>* dense,
-                std::vector<double>* nodes) {
+                std::vector<double>* nodes, int family) {
     const int n = p + 1;
     std::vector<double> xi, w, D;
-    gll(p, xi, w, D);
+    node_rule(p, family, xi, w, D);
     const double h = (hi - lo) / E, J = 0.5 * h;
     const double sigma = (p + 1.0) * (p + 1.0) / (eps * h);
     std::memset(&ax, 0, sizeof(ax));
@@ -153,17 +205,32 @@ void build_axis(int E, int p, double lo, double hi, double eps, AxisDev<double>&
             for (int q = 0; q < n; ++q) s += D[q * n + i] * w[q] * D[q * n + j];
             K[i][j] = s / J;
         }
-    for (int l = 0; l < n; ++l) {
-        ax.dL[l] = D[0 * n + l] / J;
-        ax.dR[l] = D[p * n + l] / J;
-        ax.m[l] = J * w[l];
+    ax.gl = family == 1;
+    if (family == 1) {
+        std::vector<double> ends = {-1.0, 1.0}, Le, Ge;
+        lagrange_eval(xi, ends, Le);
+        lagrange_deriv(xi, ends, Ge);
+        for (int l = 0; l < n; ++l) {
+            ax.eL[l] = Le[l];
+            ax.eR[l] = Le[n + l];
+            ax.dL[l] = Ge[l] / J;
+            ax.dR[l] = Ge[n + l] / J;
+        }
+    } else {
+        for (int l = 0; l < n; ++l) {
+            ax.eL[l] = (l == 0);
+            ax.eR[l] = (l == p);
+            ax.dL[l] = D[0 * n + l] / J;
+            ax.dR[l] = D[p * n + l] / J;
+        }
     }
+    for (int l = 0; l < n; ++l) ax.m[l] = J * w[l];
     for (int t = 0; t < 4; ++t) {
         const bool lb = t & 1, rb = t & 2;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 double v = K[i][j];
-                const double eLi = (i == 0), eLj = (j == 0), eRi = (i == p), eRj = (j == p);
+                const double eLi = ax.eL[i], eLj = ax.eL[j], eRi = ax.eR[i], eRj = ax.eR[j];
                 if (lb)  // Nitsche, left boundary: j = e_L, g = -d_L
                     v += eLi * ax.dL[j] + ax.dL[i] * eLj + sigma * eLi * eLj;
                 else     // interior face on the left, this element on its plus side
@@ -177,8 +244,8 @@ void build_axis(int E, int p, double lo, double hi, double eps, AxisDev<double>&
         for (int i = 0; i < n; ++i) ax.Bd[t][i] = ax.B[t][i][i];
     }
     for (int i = 0; i < n; ++i) {
-        ax.liftL[i] = sigma * (i == 0) + ax.dL[i];
-        ax.liftR[i] = sigma * (i == p) - ax.dR[i];
+        ax.liftL[i] = sigma * ax.eL[i] + ax.dL[i];
+        ax.liftR[i] = sigma * ax.eR[i] - ax.dR[i];
     }
     if (dense) {
         const int N = E * n;
@@ -191,7 +258,7 @@ void build_axis(int E, int p, double lo, double hi, double eps, AxisDev<double>&
             if (e + 1 < E) {  // coupling to the right neighbour: -1/2 e_R d_L^T + 1/2 d_R e_L^T - sigma e_R e_L^T
                 for (int i = 0; i < n; ++i)
                     for (int j = 0; j < n; ++j) {
-                        double v = -0.5 * (i == p) * ax.dL[j] + 0.5 * ax.dR[i] * (j == 0) - sigma * (i == p) * (j == 0);
+                        double v = -0.5 * ax.eR[i] * ax.dL[j] + 0.5 * ax.dR[i] * ax.eL[j] - sigma * ax.eR[i] * ax.eL[j];
                         A[(size_t)(e * n + i) * N + (e + 1) * n + j] += v;
                         A[(size_t)((e + 1) * n + j) * N + e * n + i] += v;
                     }
@@ -278,8 +345,8 @@ std::vector<std::pair<std::array<int, 3>, int>> hierarchy(const int E[3], int p,
 void build_transfer(const LevelHost& fine, const LevelHost& coarse, TransferDev& tr) {
     std::memset(&tr, 0, sizeof(tr));
     std::vector<double> xf, wf, Df, xc, wc, Dc;
-    gll(fine.p, xf, wf, Df);
-    gll(coarse.p, xc, wc, Dc);
+    node_rule(fine.p, fine.family, xf, wf, Df);
+    node_rule(coarse.p, coarse.family, xc, wc, Dc);
     const int nf = fine.n, nc = coarse.n, be = fine.be;
     const bool hc = fine.E[0] != coarse.E[0];
     for (int b = 0; b < be; ++b) {
@@ -307,7 +374,7 @@ void build_coarse(const LevelHost& L, double eps, CoarseDev& c) {
     for (int d = 0; d < 3; ++d) {
         AxisDev<double> ax;
         std::vector<double> A;
-        build_axis(L.E[d], L.p, L.lo[d], L.lo[d] + L.h[d] * L.E[d], eps, ax, &A, nullptr);
+        build_axis(L.E[d], L.p, L.lo[d], L.lo[d] + L.h[d] * L.E[d], eps, ax, &A, nullptr, L.family);
         const int n = L.E[d] * L.n;
         if (n > CMAX) throw std::runtime_error("coarsest level too large for the exact solve");
         c.n[d] = n;

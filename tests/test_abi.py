@@ -46,6 +46,7 @@ def test_host_only_entry_points(lib):
     from paper_2510_21213_amd import binding
     o = binding.default_opts()
     assert o.cheb_degree == 6 and o.cheb_degree_h == 10 and o.cheb_ratio == 60.0 and abs(o.penalty_eps - 0.125) < 1e-15 and o.rtol == 1e-8
+    assert o.node_family == 0 and binding.default_opts(node_family="gl").node_family == 1
     with pytest.raises(KeyError):
         binding.default_opts(nonexistent=1)
 
