@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--metric-arms", default="bf16f_pc+learned,fp64")
     ap.add_argument("--weights", default=None,
                     help="guess network (default: the weights trained for the workload's mesh)")
-    ap.add_argument("--lanes", type=int, default=2, choices=[1, 2],
+    ap.add_argument("--lanes", type=int, default=2, choices=[1, 2, 3, 4],
                     help="solver lanes per mesh: 2 solves a batch as two concurrent halves")
     ap.add_argument("--cheb-degree", type=int, default=None, help="smoothing steps (default: the library's)")
     ap.add_argument("--cheb-ratio", type=float, default=None, help="smoothing interval ratio (default: the library's)")

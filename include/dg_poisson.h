@@ -133,10 +133,11 @@ typedef struct {
                             solve on this mesh needed (finished right-hand sides are skipped
                             on the device, so replays past convergence change nothing) */
     int use_graph;       /* 1: replay the PCG iteration as a captured HIP graph */
-    int lanes;           /* solver instances per mesh (1 or 2): with 2, a batch of at least
-                            16 right-hand sides of one mesh is solved as two halves on two
+    int lanes;           /* solver instances per mesh (1 to 4): with more than one, a batch of
+                            at least 16 right-hand sides of one mesh is solved as that many
+                            consecutive parts (at least 8 right-hand sides each) on as many
                             streams at once, so that the latency-bound coarse-level phases of
-                            one half overlap the bandwidth-bound phases of the other */
+                            one part overlap the bandwidth-bound phases of the others */
     int cheb_degree_h;   /* smoothing steps on the degree-1 levels below the finest (the
                             mesh-coarsening part of the hierarchy); 0 = cheb_degree */
     int fused;           /* fused small-mesh solve, FP64 precision only (other precisions ignore it):

@@ -159,7 +159,8 @@ struct dg_ctx {
         int cscr_cap = 0;
     };
     std::vector<Mesh> meshes;
-    std::vector<Mesh> twins;       // second solver lane of each mesh (empty with one lane)
+    std::vector<Mesh> twins;       // further solver lanes: lane k >= 1 of mesh i at (k - 1) * n_meshes + i
+                                   // (empty with one lane)
     dg_net* guess = nullptr;       // learned initial guess (not owned)
     std::atomic<long long> fused_fallbacks{0};  // group-persistent solves that fell back to the level kernels
     double* g_x0 = nullptr;        // guess work space
@@ -1059,7 +1060,8 @@ struct Job {
     bool guard;  // x0 is a learned guess (guarded in the solve)
 };
 
-constexpr int kLaneMin = 16;  // smallest batch of one mesh that is split over two lanes
+constexpr int kLaneMin = 16;  // smallest batch of one mesh that is split over lanes
+constexpr int kLaneRhs = 8;   // fewest right-hand sides a lane takes
 
 // Sizes the work space of a lane for cnt right-hand sides (on the calling thread, so
 // that the solves allocate nothing).
@@ -1077,24 +1079,29 @@ void prepare_lane(dg_ctx* ctx, Mesh& M, int cnt) {
         ensure_work<double>(M, M.w64, cnt);
 }
 
-// Appends the jobs of one mesh's batch: one job, or two halves on the mesh's two
-// lanes.  guard: x0 is a learned guess.
+// Appends the jobs of one mesh's batch: one job, or consecutive parts of nearly equal size on
+// the mesh's lanes (as many lanes as the options give, each taking at least kLaneRhs right-hand
+// sides).  guard: x0 is a learned guess.
 void add_jobs(dg_ctx* ctx, int mesh_id, int cnt, const double* b, const double* x0, double* v, dg_rhs_stats* stats,
               bool guard, std::vector<Job>& jobs) {
     Mesh& M = ctx->meshes[mesh_id];
     const long long n0 = M.lv[0].ndof;
-    if (ctx->twins.empty() || cnt < kLaneMin) {
+    const int nm = (int)ctx->meshes.size();
+    const int nl = std::min(ctx->opts.lanes, std::max(1, cnt / kLaneRhs));
+    if (ctx->twins.empty() || cnt < kLaneMin || nl < 2) {
         prepare_lane(ctx, M, cnt);
         jobs.push_back({&M, cnt, b, x0, v, stats, guard});
         return;
     }
-    Mesh& T = ctx->twins[mesh_id];
-    const int h = cnt / 2;
-    prepare_lane(ctx, M, h);
-    prepare_lane(ctx, T, cnt - h);
-    jobs.push_back({&M, h, b, x0, v, stats, guard});
-    jobs.push_back({&T, cnt - h, b + h * n0, x0 ? x0 + h * n0 : nullptr, v + h * n0, stats ? stats + h : nullptr,
-                    guard});
+    int first = 0;
+    for (int k = 0; k < nl; ++k) {
+        const int part = cnt / nl + (k >= nl - cnt % nl ? 1 : 0);  // the later lanes take the remainder
+        Mesh& T = k == 0 ? M : ctx->twins[(size_t)(k - 1) * nm + mesh_id];
+        prepare_lane(ctx, T, part);
+        jobs.push_back({&T, part, b + first * n0, x0 ? x0 + first * n0 : nullptr, v + first * n0,
+                        stats ? stats + first : nullptr, guard});
+        first += part;
+    }
 }
 
 // Runs the jobs: a single one on the caller's stream; several at once, each on its
@@ -1409,7 +1416,7 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
         const auto& o = ctx->opts;
         if (o.cheb_degree < 1 || o.cheb_degree_h < 0 || o.cheb_ratio <= 1.0 || o.cheb_safety < 1.0 || o.lanczos_steps < 2 ||
             o.penalty_eps <= 0 || o.rtol <= 0 || o.max_iter < 1 || o.max_outer < 1 || o.inner_rtol <= 0 ||
-            o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 2 ||
+            o.inner_rtol >= 1 || o.lanes < 1 || o.lanes > 4 ||
             (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_IR && o.precision != DG_PREC_FP32_PC &&
              o.precision != DG_PREC_BF16_PC && o.precision != DG_PREC_BF16F_PC) ||
             o.node_family < 0 || o.node_family > 1)
@@ -1430,12 +1437,12 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
             HIPCHK(hipStreamCreateWithFlags(&ctx->meshes[i].stream, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&ctx->meshes[i].ev_done, hipEventDisableTiming));
         }
-        if (o.lanes == 2) {
-            // the second lane of a mesh: the same (read-only) level tables, its own work space
-            ctx->twins.resize(n_meshes);
-            for (int i = 0; i < n_meshes; ++i) {
-                const Mesh& M = ctx->meshes[i];
-                Mesh& T = ctx->twins[i];
+        if (o.lanes >= 2) {
+            // the further lanes of a mesh: the same (read-only) level tables, their own work space
+            ctx->twins.resize((size_t)(o.lanes - 1) * n_meshes);
+            for (size_t q = 0; q < ctx->twins.size(); ++q) {
+                const Mesh& M = ctx->meshes[q % n_meshes];
+                Mesh& T = ctx->twins[q];
                 T.mesh = M.mesh;
                 T.lv = M.lv;
                 T.cheb = M.cheb;

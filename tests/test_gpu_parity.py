@@ -241,21 +241,23 @@ def test_uneven_batch_three_meshes_matches_oracle_and_per_mesh_solves(gpu_lib):
             assert sm[q]["iters"] == st[k]["iters"]
 
 
-def test_two_solver_lanes_match_one_lane_bitwise(gpu_lib):
-    """A batch of 20 right-hand sides of one mesh is split over two concurrent solver lanes
-    (default) or solved as one group (lanes=1): the potentials and iteration counts agree
-    bit for bit, in every precision."""
-    wl = configs.scaled(4, 4, 20, seed=41)
+def test_solver_lanes_match_one_lane_bitwise(gpu_lib):
+    """A batch of 36 right-hand sides of one mesh is split over 2 (default), 3 or 4 concurrent
+    solver lanes (parts of 18, 12 and 9) or solved as one group (lanes=1): the potentials and
+    iteration counts agree bit for bit, in every precision."""
+    wl = configs.scaled(4, 4, 36, seed=41)
     mesh = wl.meshes[0]
     m = (mesh.E, mesh.p, mesh.lo, mesh.hi)
-    for prec in ("fp64", "fp32_ir", "fp32_pc", "bf16_pc"):
+    for prec in ("fp64", "fp32_ir", "fp32_pc", "bf16_pc", "bf16f_pc"):
         out = []
-        for lanes in (1, 2):
+        for lanes in (1, 2, 3, 4):
             ctx = gpu_lib.Context([m], precision=prec, lanes=lanes)
             rho, g = zip(*[gpu_sample(ctx, 0, d) for d in wl.batch.densities])
             v, st = ctx.solve_batch(_t(np.concatenate(rho)), _t(np.concatenate(g)))
             out.append((_n(v), [s["iters"] for s in st]))
-        assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1], prec
+            ctx.close()
+        for k in range(1, 4):
+            assert np.array_equal(out[0][0], out[k][0]) and out[0][1] == out[k][1], (prec, k + 1)
 
 
 def test_zero_and_empty_right_hand_sides(gpu_lib):
