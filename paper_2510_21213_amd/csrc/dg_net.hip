@@ -2,15 +2,17 @@
 // HIP forward, backward and Adam kernels, and its use as the PCG initial
 // guess.
 //
-// Tensors are channels-last [batch][z][y][x][channel] in FP32.  One channel
-// per node of an element, so an element-major field of the library is the
+// Tensors are channels-last [batch][z][y][x][channel]: FP32 in training, BF16
+// between the layers of the inference forward (the guess).  One channel per
+// node of an element, so an element-major field of the library is the
 // network's input or output tensor as it is.  Architecture, parameter order
 // and loss are fixed in include/dg_poisson.h (dg_net_*).
 //
-// Kernels: direct convolution (3x3x3 stride 1 or 2, 1x1x1) with the weights
-// of the work-group's output-channel group read by uniform (scalar) loads,
-// fused bias and ReLU; gradient with respect to the input by the same loop
-// over the taps that touch an input voxel; gradient with respect to the
+// Kernels: forward convolutions on the matrix cores (implicit GEMM with BF16
+// operands and FP32 accumulation; the 3x3x3 stride-1 layers stage their input
+// box in LDS) and a direct FP32 form (weights read by uniform loads), both with
+// fused bias and ReLU; gradient with respect to the input by the
+// loop over the taps that touch an input voxel; gradient with respect to the
 // weights by LDS-tiled partial sums over voxel chunks followed by a
 // fixed-order reduction (deterministic).
 #include <hip/hip_runtime.h>
