@@ -358,6 +358,10 @@ def measure_roofline(W, arm, args, inputs, net_cache):
         "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
         "traffic": measured_traffic(traffic_file, "dg_kernels.hip", prec) if traffic_file else None,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
+        "valu_busy": measured_traffic(traffic_file, "dg_kernels.hip", prec, "valu_busy") if traffic_file else None,
+        "valu_busy_note": "fraction of the isolated launch the vector ALUs issue (SQ_ACTIVE_INST_VALU x 4 cycles / "
+                          "1024 SIMDs at 2.4 GHz, committed counter summary): the step is bound by issue and "
+                          "barrier latency when this is high while frac is low",
         "algorithmic_bytes_per_launch": prof["bytes"] / prof["launches"],
         "bytes_counted": "per step and right-hand side still iterating: read z, f (and z_prev after the first "
                          "step), write z': 3 or 4 fields of the finest level, at the size of their storage type",
@@ -394,8 +398,9 @@ def copy_bandwidth(mib=2048, reps=5):
     return 2.0 * n * 8 / best / 1e9
 
 
-def measured_traffic(profile_name, kernel_source, prec):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None.
+def measured_traffic(profile_name, kernel_source, prec, key="traffic_bytes_per_launch"):
+    """HBM bytes per launch (or another field of the record, `key`) from the committed rocprofv3
+    counter summary, or None.
 
     None when the summary is missing, was taken for another arithmetic, or on a different kernel source.
     """
@@ -409,7 +414,7 @@ def measured_traffic(profile_name, kernel_source, prec):
         if line.startswith("traffic-json:"):
             rec = json.loads(line.split(":", 1)[1])
             if rec.get("kernel_source_sha256_16") == digest and rec.get("precision", prec) == prec:
-                return rec["traffic_bytes_per_launch"]
+                return rec.get(key)
     return None
 
 
