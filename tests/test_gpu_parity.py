@@ -533,6 +533,8 @@ def test_bf16_field_vcycle_pcg_matches_exact(gpu_lib, case):
         axes, _, _, b = oracle_density_problem(mesh, dens[k])
         assert rel_l2_M(axes, mesh, out["bf16f_pc"][0][k], fdm.FDM(axes).solve(b)) <= POT_BAR, k
     assert max(abs(a - b_) for a, b_ in zip(out["bf16f_pc"][1], out["fp32_pc"][1])) <= 1
+    # the BF16 fields were used (the mode did not fall back to FP32_PC): the potentials differ
+    assert not np.array_equal(out["bf16f_pc"][0], out["fp32_pc"][0])
 
 
 def test_single_level_hierarchy(gpu_lib):
