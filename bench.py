@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--fused", type=int, default=None, choices=[0, 1, 2],
                     help="FP64 small-mesh solve in one launch: 1 one work-group per RHS, 2 group-persistent")
     ap.add_argument("--fused-wgs", type=int, default=None, help="work-groups per RHS of the group-persistent solve")
+    ap.add_argument("--learned-cgc", type=int, default=None,
+                    help="PCG iterations that take the learned coarse-grid correction (FP64 arms with +learned, "
+                         "--lanes 1)")
     ap.add_argument("--node-family", default=None, choices=["gll", "gl"],
                     help="element nodes: gll (default) or gl (Gauss-Legendre: general operator kernels, no learned "
                          "guess; the oracle legs are skipped)")
@@ -94,7 +97,7 @@ def parse():
     args.solver_opts = {k: v for k, v in (("cheb_degree", args.cheb_degree), ("cheb_ratio", args.cheb_ratio),
                                           ("cheb_degree_h", args.cheb_degree_h), ("inner_rtol", args.inner_rtol),
                                           ("fused", args.fused), ("fused_wgs", args.fused_wgs),
-                                          ("node_family", args.node_family))
+                                          ("node_family", args.node_family), ("learned_cgc", args.learned_cgc))
                         if v is not None}
     if args.node_family == "gl":
         # the CPU legs compare with the oracle's Gauss-Lobatto solve; the GL parity lives in the tests

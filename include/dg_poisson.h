@@ -166,6 +166,15 @@ typedef struct {
                             at the face points dg_mesh_coords gives (no quadrature data), no
                             learned guess and no fused solve (DG_ERR_ARG); point-Jacobi smoothing
                             sees less of their operator, so they need more iterations. */
+    int learned_cgc;     /* learned coarse-grid correction: the first learned_cgc PCG iterations
+                            (rounded up to even) are preconditioned by z = g c + V(r - g A c), where
+                            c is the attached guess network's prediction of A^-1 r (the residual
+                            given to it as the density r / (4 pi M), its degree-2 output prolonged
+                            to the finest level), g = c.r / c.Ac its Galerkin multiple (0 if c.Ac
+                            is not positive) and V the V-cycle; those steps restart the direction
+                            (beta = 0), the later ones are plain PCG.  FP64 precision, one solver
+                            lane, no fused solve (DG_ERR_ARG at set-up otherwise); a solve without
+                            an attached network is DG_ERR_ARG.  0 (default): off. */
 } dg_opts;
 
 typedef struct {

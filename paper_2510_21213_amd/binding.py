@@ -35,7 +35,7 @@ class DgOpts(ctypes.Structure):
                 ("precision", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("lanes", ctypes.c_int),
                 ("cheb_degree_h", ctypes.c_int), ("fused", ctypes.c_int), ("fused_wgs", ctypes.c_int),
-                ("fused_spin", ctypes.c_longlong), ("node_family", ctypes.c_int)]
+                ("fused_spin", ctypes.c_longlong), ("node_family", ctypes.c_int), ("learned_cgc", ctypes.c_int)]
 
 
 class DgRhsStats(ctypes.Structure):

@@ -157,6 +157,9 @@ struct dg_ctx {
         int gsync_cap = 0;
         double* cscr = nullptr;              // scratch of the coarsest solve (2 fields per right-hand side)
         int cscr_cap = 0;
+        double* lc_rho = nullptr;            // learned coarse-grid correction: the residual as a density,
+        double* lc_c = nullptr;              // and the network's correction (finest-level fields)
+        long long lc_cap = 0;
     };
     std::vector<Mesh> meshes;
     std::vector<Mesh> twins;       // further solver lanes: lane k >= 1 of mesh i at (k - 1) * n_meshes + i
@@ -470,6 +473,52 @@ void pcg_iteration(Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, int parity, 
     dg::launch_finalize(dg::FIN_RR, nrhs, st, M.partial, M.pstride, nc, s);
 }
 
+// One FP64 PCG iteration preconditioned by the learned coarse-grid correction followed by the
+// V-cycle: c = N(r) (the guess network fed the residual as the density r / (4 pi M), its level-1
+// output prolonged to the finest level) spans a one-dimensional coarse space, corrected by its
+// Galerkin multiple gamma = c.r / c.Ac, then z = gamma c + V(r - gamma A c); the direction
+// restarts (beta = 0), since this preconditioner is not a fixed linear map.  One solver lane (the
+// network's buffers are shared).
+void pcg_iteration_lcgc(dg_ctx* ctx, Mesh& M, Work<double>& W, int nrhs, dg::RhsState* st, int parity,
+                        hipStream_t s) {
+    const LevelHost& L0 = M.lv[0];
+    const auto* dv = L0.dev64;
+    const int nb = dg::op_blocks<double>(L0, dg::BM_PQ), nc = dg::chunks_of(L0.ndof);
+    const long long n = L0.ndof * nrhs;
+    if (M.lc_cap < n) {
+        dfree(M.lc_rho);
+        dfree(M.lc_c);
+        M.lc_rho = dalloc<double>(n);
+        M.lc_c = dalloc<double>(n);
+        M.lc_cap = n;
+    }
+    const int mesh_id = (int)(&M - ctx->meshes.data());
+    dg::launch_source_of(L0, dv, nrhs, W.r, M.lc_rho, s);
+    if (dg_net_guess(ctx->guess, ctx, mesh_id, nrhs, M.lc_rho, M.lc_c, s) != DG_OK)
+        throw ArgError(std::string("learned coarse-grid correction failed: ") + dg_net_last_error());
+    // A c into q (free until the search-direction step); the Galerkin multiple gamma = c.r / c.Ac
+    // of c (the best one in the energy norm: a useless c gets gamma = 0, and z falls back to V(r));
+    // then q = r - gamma A c and z = gamma c + V(q)
+    dg::launch_brick<double>(dg::BM_APPLY, L0, dv, nrhs, st, M.lc_c, nullptr, nullptr, nullptr, W.q, nullptr,
+                             M.partial, M.pstride, 0.0, 0.0, s);
+    dg::launch_dot<double, double>(L0.ndof, nrhs, st, M.lc_c, W.r, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_CR, nrhs, st, M.partial, M.pstride, nc, s);
+    dg::launch_dot<double, double>(L0.ndof, nrhs, st, M.lc_c, W.q, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_CAC, nrhs, st, M.partial, M.pstride, nc, s);
+    dg::launch_lcgc_scale(L0.ndof, nrhs, st, W.r, M.lc_c, W.q, s);
+    double* z = vcycle<double>(M, W, 0, nrhs, st, W.q, false, false, s);
+    dg::launch_axpby(n, 1.0, M.lc_c, 1.0, z, s);
+    dg::launch_dot<double, double>(L0.ndof, nrhs, st, W.r, z, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_RZ0, nrhs, st, M.partial, M.pstride, nc, s);
+    double* pold = parity ? W.p1 : W.p0;
+    double* pnew = parity ? W.p0 : W.p1;
+    dg::launch_brick<double>(dg::BM_PQ, L0, dv, nrhs, st, z, pold, nullptr, nullptr, W.q, pnew, M.partial, M.pstride,
+                             0.0, 0.0, s);
+    dg::launch_finalize(dg::FIN_PQ, nrhs, st, M.partial, M.pstride, nb, s);
+    dg::launch_update<double>(L0, dv, nrhs, st, W.x, W.r, pnew, W.q, W.za[0], M.cheb[0].c0, M.partial, M.pstride, s);
+    dg::launch_finalize(dg::FIN_RR, nrhs, st, M.partial, M.pstride, nc, s);
+}
+
 // One PCG iteration of FP32_PC: the PCG vectors, the operator of the search direction and all dot
 // products in FP64 (W); the V-cycle preconditioner in FP32 (M.w32, whose level-0 residual r32 and
 // first smoothing iterate the update step writes).
@@ -557,6 +606,15 @@ void pcg_run(dg_ctx* ctx, Mesh& M, Work<T>& W, int nrhs, dg::RhsState* st, const
     const int maxit = ctx->opts.max_iter;
     const bool timed = g_prof && g_prof->on;
     int it = 0;
+    if constexpr (!PC && sizeof(T) == 8) {
+        // the leading iterations with the learned coarse-grid correction (an even count keeps the
+        // p ping-pong of the captured iterations aligned), on eager launches
+        const int K = (ctx->opts.learned_cgc + 1) / 2 * 2;
+        if (K > 0 && ctx->opts.precision == DG_PREC_FP64 && ctx->guess && !gate) {
+            for (; it < K && it < maxit; ++it) pcg_iteration_lcgc(ctx, M, W, nrhs, st, it & 1, s);
+            HIPCHK(hipGetLastError());
+        }
+    }
     if (ctx->opts.use_graph) {
         // `every` iterations captured once and replayed; an even count keeps the p ping-pong aligned
         int every = std::max(2, ctx->opts.check_every);
@@ -1388,6 +1446,7 @@ void dg_opts_default(dg_opts* o) {
     o->fused_wgs = 0;
     o->fused_spin = 0;
     o->node_family = 0;
+    o->learned_cgc = 0;
 }
 
 const char* dg_status_string(dg_status s) {
@@ -1422,6 +1481,8 @@ dg_status dg_poisson_setup(const dg_mesh* meshes, int n_meshes, const dg_opts* o
             o.node_family < 0 || o.node_family > 1)
             throw ArgError("invalid solver options");
         if (o.node_family != 0 && o.fused != 0) throw ArgError("the fused solves need Gauss-Lobatto nodes");
+        if (o.learned_cgc < 0 || (o.learned_cgc > 0 && (o.precision != DG_PREC_FP64 || o.lanes != 1 || o.fused != 0)))
+            throw ArgError("the learned coarse-grid correction runs in FP64 precision on one solver lane, unfused");
         HIPCHK(hipGetDevice(&ctx->device));
         HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
@@ -1485,6 +1546,8 @@ void dg_poisson_destroy(dg_ctx* ctx) {
         dfree(M.fws);
         dfree(M.gsync);
         dfree(M.cscr);
+        dfree(M.lc_rho);
+        dfree(M.lc_c);
         M.w64.release();
         M.w32.release();
         dfree(M.b);
@@ -1617,6 +1680,8 @@ dg_status dg_poisson_solve_batch(dg_ctx* ctx, int nrhs, const int* mesh_id, cons
     std::vector<dg_rhs_stats> all;  // every right-hand side's statistics, whether or not the caller takes them
     dg_status st = run_guarded([&] {
         if (!ctx) throw ArgError("null context");
+        if (ctx->opts.learned_cgc > 0 && !ctx->guess)
+            throw ArgError("the learned coarse-grid correction needs an attached guess network");
         g_prof = &ctx->prof;
         if (nrhs < 0) throw ArgError("nrhs must be >= 0");
         if (nrhs == 0) return;
@@ -1768,6 +1833,8 @@ dg_status dg_exchange_apply(dg_ctx* ctx, int mesh_id, int norb, const double* ph
     dg_status st = run_guarded([&] {
         check_mesh_id(ctx, mesh_id);
         g_prof = &ctx->prof;
+        if (ctx->opts.learned_cgc > 0 && !ctx->guess)
+            throw ArgError("the learned coarse-grid correction needs an attached guess network");
         if (norb < 1 || norb > 32) throw ArgError("norb must be in 1..32");
         if (!phi || !W || !K_pairs) throw ArgError("null pointer argument");
         const hipStream_t user = stream;

@@ -92,6 +92,7 @@ struct RhsState {
     double alpha, beta;
     double tol2;    // (rtol)^2
     double scale;   // iterative refinement: ||r_outer||
+    double cr, cac; // learned coarse-grid correction: c.r and c.Ac of the network's correction c
     int active;     // 1 while iterating
     int iters;      // completed iterations
     int maxit;

@@ -26,7 +26,10 @@ enum FinalizeWhat {
     FIN_RR = 4,    // rr = s; iters++; active = rr > tol2 bb and iters < maxit
     FIN_TRUE = 5,  // rr_true = s (FP64 residual of the returned solution)
     FIN_OUTER = 6, // outer refinement: rr = s; scale = sqrt(s); active = rr > tol2 bb
-    FIN_FLEX = 7   // flexible CG after FIN_RZ, s = z.r_old: beta = (rz - s) / rz_prev (0 on the first iteration)
+    FIN_FLEX = 7,  // flexible CG after FIN_RZ, s = z.r_old: beta = (rz - s) / rz_prev (0 on the first iteration)
+    FIN_RZ0 = 8,   // as FIN_RZ with beta = 0 (a restarted step: the direction is the preconditioned residual)
+    FIN_CR = 9,    // cr = s (c.r of the learned correction)
+    FIN_CAC = 10   // cac = s (c.Ac of the learned correction)
 };
 
 struct KernelCfg {
@@ -168,6 +171,14 @@ void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 void launch_dscale(const LevelHost& L, const LevelDev<double>* dev, const double* x, double* y, hipStream_t s);
 // y = a x + b y  (single vector)
 void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t s);
+// rho = r / (4 pi M) for nrhs fields of the level: the source whose right-hand side, without a boundary
+// lift, is r (the learned coarse-grid correction hands a residual to the guess network as a density).
+void launch_source_of(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const double* r, double* rho,
+                      hipStream_t s);
+// The learned correction's Galerkin step, per active right-hand side: gamma = c.r / c.Ac (0 unless
+// c.Ac > 0, from the state's cr and cac), c <- gamma c, and q <- r - gamma q (q holds A c on entry).
+void launch_lcgc_scale(long long ndof, int nrhs, const RhsState* st, const double* r, double* c, double* q,
+                       hipStream_t s);
 
 // Exchange: W_k = sum_s phi_s v_ks; partial sums of w rho_ij v_ij per pair.
 void launch_exchange(const LevelHost& L, const LevelDev<double>* dev, int norb, const double* phi, const double* v,

@@ -2504,7 +2504,8 @@ __global__ __launch_bounds__(256) void k_finalize(int what, RhsState* st, const 
     __shared__ double red[256];
     const int rhs = blockIdx.x;
     RhsState& S = st[rhs];
-    const bool gated = (what == FIN_RZ || what == FIN_PQ || what == FIN_RR || what == FIN_FLEX);
+    const bool gated = (what == FIN_RZ || what == FIN_PQ || what == FIN_RR || what == FIN_FLEX || what == FIN_RZ0 ||
+                        what == FIN_CR || what == FIN_CAC);
     if (gated && !S.active) return;
     double acc = 0.0;
     const double* p = partial + (long long)rhs * pstride;
@@ -2534,6 +2535,14 @@ __global__ __launch_bounds__(256) void k_finalize(int what, RhsState* st, const 
         case FIN_FLEX:
             S.beta = (S.iters == 0) ? 0.0 : (S.rz - s) / S.rz_prev;
             break;
+        case FIN_RZ0:
+            S.beta = 0.0;
+            S.rz_prev = S.rz_old;
+            S.rz = s;
+            S.rz_old = s;
+            break;
+        case FIN_CR: S.cr = s; break;
+        case FIN_CAC: S.cac = s; break;
         case FIN_PQ:
             S.pq = s;
             if (!(s > 0.0) || !(S.rz > 0.0)) {
@@ -2788,6 +2797,49 @@ __global__ __launch_bounds__(256) void k_axpby(long long n, double a, const doub
 void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, x, b, y);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_source_of(const LevelDev<double>* __restrict__ L, long long ndof, long long n,
+                                                   const double* __restrict__ r, double* __restrict__ rho) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int l = (int)((i % ndof) % (N * N * N));  // node within its element (the mass is element-local)
+    const double m = L->ax[0].m[l % N] * L->ax[1].m[(l / N) % N] * L->ax[2].m[l / (N * N)];
+    rho[i] = r[i] / (4.0 * M_PI * m);
+}
+__global__ __launch_bounds__(256) void k_lcgc_scale(long long ndof, const RhsState* st, const double* __restrict__ r,
+                                                    double* __restrict__ c, double* __restrict__ q) {
+    const int rhs = blockIdx.x;
+    if (!st[rhs].active) return;
+    const double cac = st[rhs].cac;
+    const double g = cac > 0.0 ? st[rhs].cr / cac : 0.0;
+    const long long base = (long long)rhs * ndof;
+    const long long q0 = (long long)blockIdx.y * 1024 + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long i = q0 + v * 256;
+        if (i < ndof) {
+            c[base + i] *= g;
+            q[base + i] = r[base + i] - g * q[base + i];
+        }
+    }
+}
+void launch_lcgc_scale(long long ndof, int nrhs, const RhsState* st, const double* r, double* c, double* q,
+                       hipStream_t s) {
+    if (nrhs == 0) return;
+    hipLaunchKernelGGL(k_lcgc_scale, rhs_chunk_grid(ndof, nrhs), dim3(256), 0, s, ndof, st, r, c, q);
+}
+
+void launch_source_of(const LevelHost& L, const LevelDev<double>* dev, int nrhs, const double* r, double* rho,
+                      hipStream_t s) {
+    const long long n = L.ndof * nrhs;
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+#define DG_SO(NN) \
+    case NN: hipLaunchKernelGGL((k_source_of<NN>), dim3(grid), dim3(256), 0, s, dev, L.ndof, n, r, rho); break;
+    switch (L.n) { DG_SO(2) DG_SO(3) DG_SO(4) DG_SO(5) DG_SO(6) DG_SO(7) DG_SO(8) }
+#undef DG_SO
 }
 
 // ---------------------------------------------------------------------------

@@ -122,6 +122,53 @@ def test_exchange8_every_pair_at_operating_tolerance(gpu_lib, workload, oracle_a
         assert all(s["guess_used"] in (0, 1) for s in got[3]) and any(s["guess_used"] for s in got[3])
 
 
+def _solve_lcgc(gpu_lib, wl, steps):
+    """FP64 exchange step on one lane with the trained network as the initial guess and, in the
+    first `steps` PCG iterations, as the learned coarse-grid correction."""
+    mesh, orb = wl.meshes[0], wl.orbitals
+    ctx = gpu_lib.Context([(mesh.E, mesh.p, mesh.lo, mesh.hi)], n_levels=wl.n_levels, rtol=OPERATING_RTOL,
+                          precision="fp64", lanes=1, learned_cgc=steps)
+    net = gpu_lib.Net(4, 32, 125, 27)
+    net.load(WEIGHTS)
+    ctx.attach_guess(net)
+    xyz, fxyz = ctx.mesh_coords(0)
+    phi = _t(orb.values(xyz[0], xyz[1], xyz[2]).reshape(-1))
+    g = _t(orb.pair_potentials(fxyz[0], fxyz[1], fxyz[2]).reshape(-1))
+    W, K, EX, st, v = ctx.exchange(phi, g, keep_potentials=True)
+    npairs = orb.norb * (orb.norb + 1) // 2
+    out = (W.cpu().numpy().reshape(orb.norb, -1), K.cpu().numpy(), EX, st, v.cpu().numpy().reshape(npairs, -1))
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("steps", [2, 4])
+def test_learned_coarse_grid_correction_meets_the_bars(gpu_lib, workload, oracle_all, steps):
+    """FP64 PCG whose first iterations are preconditioned by the learned coarse-grid correction
+    (z = c + V(r - A c), c the network's prediction of A^-1 r): every pair potential, W_k, pair
+    energy and E_x against the oracle's exact solve at the operating tolerance, like the plain
+    FP64 solve with the same guess; the iteration counts of both are printed."""
+    got = _solve_lcgc(gpu_lib, workload, steps)
+    _check_all(workload, oracle_all, got, OPERATING_RTOL, POT_BAR, ENERGY_BAR)
+    base = _solve_lcgc(gpu_lib, workload, 0)
+    it_c = np.mean([s["iters"] for s in got[3]])
+    it_0 = np.mean([s["iters"] for s in base[3]])
+    print(f"mean PCG iterations: learned correction in {steps} steps {it_c:.2f}, without {it_0:.2f}")
+
+
+def test_learned_coarse_grid_correction_options_are_checked(gpu_lib, workload):
+    mesh = workload.meshes[0]
+    m = [(mesh.E, mesh.p, mesh.lo, mesh.hi)]
+    for bad in ({"precision": "fp32_pc", "lanes": 1}, {"precision": "fp64", "lanes": 2}, {"learned_cgc": -1}):
+        opts = dict(precision="fp64", lanes=1, learned_cgc=2)
+        opts.update(bad)
+        with pytest.raises(gpu_lib.DgError, match="invalid argument"):
+            gpu_lib.Context(m, **opts)
+    ctx = gpu_lib.Context(m, precision="fp64", lanes=1, learned_cgc=2)
+    nd, nf = ctx.info[0]["n_dofs"], ctx.info[0]["n_face"]
+    with pytest.raises(gpu_lib.DgError, match="guess network"):
+        ctx.solve_batch(_t(np.ones(nd)), _t(np.zeros(nf)))
+
+
 def test_exchange8_every_pair_fp32_refinement_at_parity_tolerance(gpu_lib, workload, oracle_all):
     """FP32 inner solves inside FP64 refinement (with the trained guess) meet the bars on every
     pair at residual 1e-12 (its refinement leaves more error in the smooth modes per unit of
