@@ -36,3 +36,14 @@ def test_committed_counter_summaries_parse():
             checked += 1
     assert checked >= 1
     assert bench._host()["host_cpus"] >= 1
+
+
+def test_headline_counters_match_the_current_kernel_source():
+    """The headline arm's smoothing step has committed counters for the kernel source as it is:
+    the bench's roofline then reports their traffic and the vector units' issue fraction."""
+    sys.path.insert(0, ROOT)
+    import bench
+    t = bench.measured_traffic("cheb_step_heldout32.md", "dg_kernels.hip", "bf16f_pc")
+    v = bench.measured_traffic("cheb_step_heldout32.md", "dg_kernels.hip", "bf16f_pc", "valu_busy")
+    assert t is not None and t > 0
+    assert v is not None and 0 < v <= 1
