@@ -471,6 +471,79 @@ dg_status dg_net_load(dg_net* net, const char* path);
  * side by right-hand side; stats.guess_used says which were kept. */
 dg_status dg_poisson_attach_guess(dg_ctx* ctx, dg_net* net);
 
+/* ---------------------------------------------------------------------------------------------
+ * Adaptive octree auxiliary mesh (Sec. 6.2), its SIPDG Poisson problem with hanging faces
+ * (Sec. 6.3) and MG-PCG over the refinement hierarchy (Sec. 6.4).
+ *
+ * Construction: a uniform box of ne[0] x ne[1] x ne[2] base elements (1 to 8 per axis) with
+ * degree-q Gauss-Legendre nodes (q = 1..4); a cell of edge lengths L_d (L = max) is halved along
+ * every axis with L_d >= L/2 (2, 4 or 8 children) and replaced by its children when the GL
+ * integrals of the density on the cell and on its children differ by more than delta_q
+ * (indicator Q of Sec. 6.2; the paper uses 1e-8); children are tested in turn, generation by
+ * generation, at most max_depth times below a base element (0..8).  Elements (the leaves) are in
+ * depth-first order: base elements z, y, x lexicographic with x fastest, the children of a cell
+ * in z, y, x lexicographic order of their half along each split axis; each element's (q+1)^3
+ * nodes [k][j][i], x fastest.  Fields: element-major FP64, right-hand side after right-hand
+ * side.
+ *
+ * Discretisation: the SIPDG form of eq. sip_bilinear with penalty eq. pen_poly ((q+1)^2 /
+ * (eps h), h the smaller width of the two elements along the normal); a hanging face is
+ * integrated piece by piece (the intersections of the two sides' faces) with the piece's own
+ * (q+1)^2-point GL rule; Nitsche terms carry the Dirichlet data g on the domain boundary.
+ * Multigrid: degree steps q -> q/2 -> .. -> 1 on the leaves, then the tree cut at generation
+ * G-1, .., 0 at degree 1; exact fast-diagonalisation solve on the base mesh; Chebyshev-Jacobi
+ * smoothing with the dg_opts parameters.  FP64 only. */
+typedef struct dg_octree dg_octree;
+
+/* The density: out[i] = rho(x[i], y[i], z[i]) for i < n (host arrays).  Called on the host
+ * during dg_octree_create, once per generation with the GL points of every cell tested in it
+ * and of its would-be children. */
+typedef void (*dg_density_fn)(long long n, const double* x, const double* y, const double* z, double* out,
+                              void* user);
+
+typedef struct {
+    int ne[3];              /* base elements per axis, 1..8 */
+    double lo[3], hi[3];    /* the box */
+    int q;                  /* degree, 1..4 */
+    double delta_q;         /* refinement tolerance (> 0) */
+    int max_depth;          /* refinements below a base element, 0..8 */
+    long long max_elements; /* refinement beyond this many elements is DG_ERR_ARG */
+} dg_octree_desc;
+
+/* Build the mesh (rho may be NULL: no refinement), its levels and smoother bounds on the current
+ * device.  opts NULL: dg_opts_default; precision must be DG_PREC_FP64.  DG_ERR_ARG on bad sizes,
+ * options, a density that is not finite, or more than max_elements elements. */
+dg_status dg_octree_create(const dg_octree_desc* desc, dg_density_fn rho, void* user, const dg_opts* opts,
+                           dg_octree** out);
+void dg_octree_destroy(dg_octree* octree);
+/* Elements, finest-level nodes (= n_elements (q+1)^3), Dirichlet points, multigrid levels, and
+ * the deepest generation; any pointer may be NULL. */
+dg_status dg_octree_info(const dg_octree* octree, long long* n_elements, long long* n_dofs, long long* n_boundary,
+                         int* n_levels, int* max_generation);
+/* Elements and degree of a multigrid level (0 finest) and its smoother interval. */
+dg_status dg_octree_level_info(const dg_octree* octree, int level, long long* n_elements, int* q, double* lam_lo,
+                               double* lam_hi);
+/* Host arrays: lohi[6e .. 6e+5] = (x, y, z) of the lower, then the upper corner of element e;
+ * generation[e] its refinement generation (either may be NULL). */
+dg_status dg_octree_elements(const dg_octree* octree, double* lohi, int* generation);
+/* Host arrays of n_dofs: the node coordinates, element-major. */
+dg_status dg_octree_nodes(const dg_octree* octree, double* x, double* y, double* z);
+/* Host arrays of n_boundary: the Dirichlet points, (q+1)^2 per boundary face of an element, in
+ * element order, then face order x-, x+, y-, y+, z-, z+, each face [t2][t1] (t1 < t2 its
+ * tangential axes, t1 fastest). */
+dg_status dg_octree_boundary_points(const dg_octree* octree, double* x, double* y, double* z);
+/* b = 4 pi M f + Nitsche lift of g (eq. hartree_poisson / fock_poisson on the auxiliary mesh):
+ * device arrays f, b [nrhs][n_dofs] and g [nrhs][n_boundary]. */
+dg_status dg_octree_rhs(dg_octree* octree, int nrhs, const double* f, const double* g, double* b, void* stream);
+/* y = A u on multigrid level `level` (device arrays [nrhs][level nodes]). */
+dg_status dg_octree_apply(dg_octree* octree, int level, int nrhs, const double* u, double* y, void* stream);
+/* z = V r, one V-cycle of the preconditioner on the finest level (device arrays). */
+dg_status dg_octree_vcycle(dg_octree* octree, int nrhs, const double* r, double* z, void* stream);
+/* x = A^-1 b by FP64 MG-PCG from x = 0, stopping at ||r|| <= rtol ||b|| (recurrence residual) or
+ * max_iter; stats (host, may be NULL) as for dg_poisson_solve_batch; returns the worst status. */
+dg_status dg_octree_solve(dg_octree* octree, int nrhs, const double* b, double* x, dg_rhs_stats* stats,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,17 @@ class DgError(RuntimeError):
     pass
 
 
+class DgOctreeDesc(ctypes.Structure):
+    _fields_ = [("ne", ctypes.c_int * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("q", ctypes.c_int), ("delta_q", ctypes.c_double), ("max_depth", ctypes.c_int),
+                ("max_elements", ctypes.c_longlong)]
+
+
+DENSITY_FN = ctypes.CFUNCTYPE(None, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2510_21213_amd/build.py")
@@ -101,6 +112,20 @@ def _load():
         "dg_net_load": (I, [P, ctypes.c_char_p]),
         "dg_poisson_attach_guess": (I, [P, P]),
         "dg_profile_read": (I, [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "dg_octree_create": (I, [ctypes.POINTER(DgOctreeDesc), DENSITY_FN, P, ctypes.POINTER(DgOpts),
+                                 ctypes.POINTER(P)]),
+        "dg_octree_destroy": (None, [P]),
+        "dg_octree_info": (I, [P, ctypes.POINTER(LL), ctypes.POINTER(LL), ctypes.POINTER(LL), ctypes.POINTER(I),
+                               ctypes.POINTER(I)]),
+        "dg_octree_level_info": (I, [P, I, ctypes.POINTER(LL), ctypes.POINTER(I), ctypes.POINTER(D),
+                                     ctypes.POINTER(D)]),
+        "dg_octree_elements": (I, [P, P, P]),
+        "dg_octree_nodes": (I, [P, P, P, P]),
+        "dg_octree_boundary_points": (I, [P, P, P, P]),
+        "dg_octree_rhs": (I, [P, I, P, P, P, P]),
+        "dg_octree_apply": (I, [P, I, I, P, P, P]),
+        "dg_octree_vcycle": (I, [P, I, P, P, P]),
+        "dg_octree_solve": (I, [P, I, P, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -425,6 +450,110 @@ class Context:
         li = self.level_info(mesh_id, level)
         n = li["p"] + 1
         return li["ne"][0] * li["ne"][1] * li["ne"][2] * n ** 3
+
+
+class Octree:
+    """Adaptive octree auxiliary mesh with its MG-PCG Poisson solver (dg_octree_*).
+
+    rho: callable rho(x, y, z) on numpy arrays (or None: the base mesh, unrefined); options:
+    fields of dg_opts (FP64 precision only).
+    """
+
+    def __init__(self, ne, lo, hi, q=4, rho=None, delta_q=1e-8, max_depth=3, max_elements=1 << 20, **options):
+        d = DgOctreeDesc()
+        d.ne[:] = [int(v) for v in ne]
+        d.lo[:] = [float(v) for v in lo]
+        d.hi[:] = [float(v) for v in hi]
+        d.q, d.delta_q, d.max_depth, d.max_elements = int(q), float(delta_q), int(max_depth), int(max_elements)
+        self.opts = default_opts(**options)
+        self._err = None
+
+        def cb(n, x, y, z, out, user):
+            try:
+                xa, ya, za = (np.ctypeslib.as_array(a, shape=(n,)) for a in (x, y, z))
+                np.ctypeslib.as_array(out, shape=(n,))[:] = np.asarray(rho(xa, ya, za), dtype=np.float64)
+            except Exception as e:   # a failing density: NaN makes the library reject the mesh
+                self._err = e
+                np.ctypeslib.as_array(out, shape=(n,))[:] = np.nan
+        self._cb = DENSITY_FN(cb) if rho is not None else DENSITY_FN()
+        h = ctypes.c_void_p()
+        code = lib.dg_octree_create(ctypes.byref(d), self._cb, None, ctypes.byref(self.opts), ctypes.byref(h))
+        if self._err is not None:
+            raise self._err
+        _check(code, "octree_create")
+        self._h = h
+        ne_, nd, nb, nl, mg = (ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int(),
+                               ctypes.c_int())
+        _check(lib.dg_octree_info(h, ctypes.byref(ne_), ctypes.byref(nd), ctypes.byref(nb), ctypes.byref(nl),
+                                  ctypes.byref(mg)), "octree_info")
+        self.n_elements, self.n_dofs, self.n_boundary = ne_.value, nd.value, nb.value
+        self.n_levels, self.max_generation = nl.value, mg.value
+        self.q = int(q)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dg_octree_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level):
+        ne, q, lo, hi = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(lib.dg_octree_level_info(self._h, level, ctypes.byref(ne), ctypes.byref(q), ctypes.byref(lo),
+                                        ctypes.byref(hi)), "octree_level_info")
+        return {"n_elements": ne.value, "q": q.value, "lam_lo": lo.value, "lam_hi": hi.value,
+                "n_dofs": ne.value * (q.value + 1) ** 3}
+
+    def elements(self):
+        """(lohi [n_elements, 6], generation [n_elements])."""
+        lohi = np.empty((self.n_elements, 6))
+        gen = np.empty(self.n_elements, dtype=np.int32)
+        _check(lib.dg_octree_elements(self._h, lohi.ctypes.data_as(ctypes.c_void_p),
+                                      gen.ctypes.data_as(ctypes.c_void_p)), "octree_elements")
+        return lohi, gen
+
+    def nodes(self):
+        xyz = np.empty((3, self.n_dofs))
+        _check(lib.dg_octree_nodes(self._h, *(xyz[i].ctypes.data_as(ctypes.c_void_p) for i in range(3))),
+               "octree_nodes")
+        return xyz
+
+    def boundary_points(self):
+        xyz = np.empty((3, max(self.n_boundary, 1)))
+        _check(lib.dg_octree_boundary_points(self._h, *(xyz[i].ctypes.data_as(ctypes.c_void_p) for i in range(3))),
+               "octree_boundary_points")
+        return xyz[:, :self.n_boundary]
+
+    def rhs(self, f, g):
+        nrhs = f.numel() // self.n_dofs
+        b = torch.empty_like(f)
+        _check(lib.dg_octree_rhs(self._h, nrhs, _ptr(f), _ptr(g), _ptr(b), _stream()), "octree_rhs")
+        return b
+
+    def apply(self, u, level=0):
+        n = self.level_info(level)["n_dofs"]
+        y = torch.empty_like(u)
+        _check(lib.dg_octree_apply(self._h, level, u.numel() // n, _ptr(u), _ptr(y), _stream()), "octree_apply")
+        return y
+
+    def vcycle(self, r):
+        z = torch.empty_like(r)
+        _check(lib.dg_octree_vcycle(self._h, r.numel() // self.n_dofs, _ptr(r), _ptr(z), _stream()),
+               "octree_vcycle")
+        return z
+
+    def solve(self, b):
+        """x = A^-1 b (MG-PCG); returns (x, stats list)."""
+        nrhs = b.numel() // self.n_dofs
+        x = torch.empty_like(b)
+        st = (DgRhsStats * max(nrhs, 1))()
+        code = lib.dg_octree_solve(self._h, nrhs, _ptr(b), _ptr(x), st, _stream())
+        _check(code, "octree_solve", allow_warn=True)
+        return x, [_stats(st[i]) for i in range(nrhs)]
 
 
 def _stats(s):

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgpoisson.so")
-SOURCES = ["dg_setup.cpp", "dg_kernels.hip", "dg_api.hip", "dg_net.hip", "dg_boundary.hip", "dg_consumers.hip"]
+SOURCES = ["dg_setup.cpp", "dg_kernels.hip", "dg_api.hip", "dg_net.hip", "dg_boundary.hip", "dg_consumers.hip",
+           "dg_octree.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "--offload-arch=gfx950",
          # no packed FP32 instructions anywhere in device code

@@ -1411,6 +1411,9 @@ dg_status run_guarded(const std::function<void()>& fn) {
 }  // namespace
 
 namespace dg {
+dg_status guarded(const std::function<void()>& fn) { return run_guarded(fn); }
+void hip_fail(const std::string& what) { throw HipError(what); }
+
 const LevelHost& ctx_fine_level(const dg_ctx* ctx, int mesh_id) {
     check_mesh_id(ctx, mesh_id);
     return ctx->meshes[mesh_id].lv[0];

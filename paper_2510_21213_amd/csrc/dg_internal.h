@@ -6,6 +6,7 @@
 
 #include <array>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -141,5 +142,10 @@ std::vector<std::pair<std::array<int, 3>, int>> hierarchy(const int E[3], int p,
 void build_transfer(const LevelHost& fine, const LevelHost& coarse, TransferDev& tr);
 void build_coarse(const LevelHost& L, double eps, CoarseDev& c);
 double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b);
+
+// C ABI error handling shared by the library's modules (dg_api.hip): run fn, map its exceptions to
+// a status and the message of dg_last_error(); hip_fail throws the HIP error kind.
+dg_status guarded(const std::function<void()>& fn);
+[[noreturn]] void hip_fail(const std::string& what);
 
 }  // namespace dg

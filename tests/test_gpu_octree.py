@@ -1,0 +1,178 @@
+"""GPU parity of the adaptive octree path (dg_octree_*) against the octree oracle, through the
+C ABI: the refined mesh (element list, nodes, Dirichlet points) exactly; the operator on every
+multigrid level, the right-hand side, the smoother bounds, one V-cycle and full MG-PCG solves
+at FP64 rounding bars; the polynomial reproduction of the hanging-face discretisation at a size
+the dense oracle cannot solve.
+
+Bars: operator, right-hand side and transfers 1e-12 of the largest entry (FP64 rounding of a
+few hundred terms); Lanczos bounds 1e-9 relative (30 Lanczos steps amplify rounding); one
+V-cycle 1e-9 (smoothing polynomials of degree 6 and 10 in lam_hi); solves at rtol 1e-12 to
+1e-9 of the largest entry and the oracle's iteration count within one.
+"""
+import numpy as np
+import pytest
+
+from oracle import octree, pcg
+
+pytestmark = pytest.mark.gpu
+
+
+def _gauss(a, c):
+    return lambda x, y, z: np.exp(-a * ((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2))
+
+
+def _two_centres(x, y, z):
+    return _gauss(12.0, (0.5, 0.2, -0.3))(x, y, z) + 0.5 * _gauss(30.0, (-0.6, -0.4, 0.5))(x, y, z)
+
+
+_CENTRES = [(0.5, 0.2, -0.3, 12.0), (-0.6, -0.4, 0.5, 30.0), (1.1, -0.9, 0.4, 50.0), (-1.2, 1.0, -0.8, 20.0)]
+
+
+def _molecule(x, y, z):
+    """Four atom-like Gaussians of different widths (the kind of density Sec. 6.2 refines on)."""
+    return sum(np.exp(-a * ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)) for cx, cy, cz, a in _CENTRES)
+
+
+# 6^3 base cells on [-4, 4]^3, degree 4, delta_q 1e-10, three refinements: 1,630 elements, 203,750 nodes
+LARGE = ((6, 6, 6), (-4.0, -4.0, -4.0), (4.0, 4.0, 4.0), 4, 1e-10, 3)
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+# (ne, lo, hi, q, delta_q, max_depth): isotropic and anisotropic (4:1:1-like) base cells
+CASES = [
+    ((2, 2, 2), (-2.0, -2.0, -2.0), (2.0, 2.0, 2.0), 4, 1e-4, 2),
+    ((3, 2, 1), (-2.0, -1.5, -0.8), (2.0, 1.5, 0.8), 2, 1e-5, 3),
+    ((1, 2, 2), (-3.0, -1.5, -1.5), (3.0, 1.5, 1.5), 3, 1e-5, 3),
+    ((2, 2, 2), (-2.0, -2.0, -2.0), (2.0, 2.0, 2.0), 1, 1e-5, 3),
+]
+
+
+def _pair(gpu_lib, case, **opts):
+    ne, lo, hi, q, dq, depth = case
+    g = gpu_lib.Octree(ne, lo, hi, q=q, rho=_two_centres, delta_q=dq, max_depth=depth, **opts)
+    t = octree.Octree(ne, lo, hi, q, rho=_two_centres, delta_q=dq, max_depth=depth)
+    return g, t
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_refined_mesh_matches_oracle(gpu_lib, case):
+    g, t = _pair(gpu_lib, case)
+    cells = t.cells()
+    assert g.n_elements == len(cells) and g.max_generation == t.max_gen and t.max_gen >= 1
+    lohi, gen = g.elements()
+    ref = np.array([np.concatenate(t.bounds(c)) for c in cells])
+    assert np.array_equal(gen, [c.gen for c in cells])
+    assert np.abs(lohi - ref).max() <= 1e-14 * np.abs(ref).max()
+    m = t.mesh()
+    xyz = g.nodes()
+    assert np.abs(xyz - np.array(m.nodes())).max() <= 1e-14 * 4
+    bxyz = g.boundary_points()
+    assert np.abs(bxyz - np.array(m.boundary_points())).max() <= 1e-14 * 4
+    print(f"case {case}: {g.n_elements} elements, {g.n_dofs} nodes, generations {t.max_gen}, {g.n_levels} levels")
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_operator_rhs_bounds_and_vcycle_match_oracle(gpu_lib, case):
+    g, t = _pair(gpu_lib, case)
+    H = octree.Hierarchy(t)
+    assert g.n_levels == len(H.meshes)
+    rng = np.random.default_rng(11)
+    for l, m in enumerate(H.meshes):
+        li = g.level_info(l)
+        assert li["n_elements"] == len(m.cells) and li["q"] == m.q
+        u = rng.standard_normal((2, m.ndof))
+        got = g.apply(_t(u), level=l).cpu().numpy()
+        ref = np.stack([m.apply(u[k]) for k in range(2)])
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), l
+        if l + 1 < len(H.meshes):
+            lo, hi = H.lam[l]
+            assert abs(li["lam_hi"] - hi) <= 1e-9 * hi and abs(li["lam_lo"] - lo) <= 1e-9 * lo, l
+    m = H.meshes[0]
+    X, Y, Z = m.nodes()
+    f = np.stack([_two_centres(X, Y, Z), np.cos(X) * Y])
+    bx, by, bz = m.boundary_points()
+    gb = np.stack([0.2 * np.sin(bx) + by * bz, np.zeros_like(bx)])
+    b = g.rhs(_t(f), _t(gb)).cpu().numpy()
+    bref = np.stack([m.rhs(f[k], gb[k]) for k in range(2)])
+    assert np.abs(b - bref).max() <= 1e-12 * np.abs(bref).max()
+    z = g.vcycle(_t(bref)).cpu().numpy()
+    zref = np.stack([H.vcycle(bref[k]) for k in range(2)])
+    assert np.abs(z - zref).max() <= 1e-9 * np.abs(zref).max()
+
+
+@pytest.mark.parametrize("case", CASES[:3])
+def test_solve_matches_oracle_pcg(gpu_lib, case):
+    g, t = _pair(gpu_lib, case, rtol=1e-12)
+    H = octree.Hierarchy(t)
+    m = H.meshes[0]
+    X, Y, Z = m.nodes()
+    bx, by, bz = m.boundary_points()
+    f = np.stack([_two_centres(X, Y, Z), _gauss(3.0, (0.1, 0.0, 0.2))(X, Y, Z)])
+    gb = np.stack([np.zeros_like(bx), 0.05 * np.cos(bx + by)])
+    b = np.stack([m.rhs(f[k], gb[k]) for k in range(2)])
+    x, st = g.solve(_t(b))
+    x = x.cpu().numpy()
+    for k in range(2):
+        xr, it, rel, _ = pcg.pcg(H.levels[0].A, b[k], H.vcycle, rtol=1e-12)
+        assert st[k]["status"] == 0 and st[k]["rel_residual"] <= 2e-12
+        assert abs(st[k]["iters"] - it) <= 1, (st[k]["iters"], it)
+        assert np.abs(x[k] - xr).max() <= 1e-9 * np.abs(xr).max()
+
+
+def _poly(x, y, z):
+    u = 1.0 + x * x * y - 0.5 * z ** 3 + x * y * z + 0.3 * y ** 3 - x
+    return u, -(2.0 * y - 3.0 * z + 1.8 * y) / (4.0 * np.pi)
+
+
+def test_hanging_faces_reproduce_a_polynomial_at_size(gpu_lib):
+    """Consistency of SIPDG on the hanging-face mesh, checked where no dense oracle reaches: a
+    cubic that solves the PDE is the discrete solution (degree 4, several thousand elements)."""
+    ne, lo, hi, q, dq, depth = LARGE
+    g = gpu_lib.Octree(ne, lo, hi, q=q, rho=_molecule, delta_q=dq, max_depth=depth, rtol=1e-13, max_iter=400)
+    assert g.max_generation == 3 and g.n_elements == 1630
+    xyz = g.nodes()
+    u, f = _poly(*xyz)
+    gu, _ = _poly(*g.boundary_points())
+    b = g.rhs(_t(f[None]), _t(gu[None]))
+    x, st = g.solve(b)
+    print(f"{g.n_elements} elements, {g.n_dofs} nodes: {st[0]['iters']} iterations")
+    assert st[0]["status"] == 0
+    assert np.abs(x.cpu().numpy()[0] - u).max() <= 1e-8 * np.abs(u).max()
+
+
+def test_residual_of_a_large_solve_against_the_oracle_operator(gpu_lib):
+    """Full size: the oracle's matrix-free operator recomputes b - A x of the GPU solution."""
+    ne, lo, hi, q, dq, depth = LARGE
+    g = gpu_lib.Octree(ne, lo, hi, q=q, rho=_molecule, delta_q=dq, max_depth=depth, rtol=1e-10)
+    t = octree.Octree(ne, lo, hi, q, rho=_molecule, delta_q=dq, max_depth=depth)
+    m = t.mesh()
+    assert g.n_elements == len(m.cells)
+    X, Y, Z = m.nodes()
+    f = _molecule(X, Y, Z)
+    bx, by, bz = m.boundary_points()
+    b = m.rhs(f, np.zeros_like(bx))
+    x, st = g.solve(_t(b[None]))
+    x = x.cpu().numpy()[0]
+    rel = np.linalg.norm(b - m.apply(x)) / np.linalg.norm(b)
+    assert st[0]["status"] == 0 and rel <= 2e-10 and abs(rel - st[0]["rel_residual"]) <= 1e-12
+
+
+def test_octree_arguments_are_checked(gpu_lib):
+    with pytest.raises(gpu_lib.DgError):
+        gpu_lib.Octree((9, 1, 1), (0, 0, 0), (1, 1, 1), q=2)          # more than 8 base elements per axis
+    with pytest.raises(gpu_lib.DgError):
+        gpu_lib.Octree((1, 1, 1), (0, 0, 0), (1, 1, 1), q=5)          # degree above 4
+    with pytest.raises(gpu_lib.DgError):
+        gpu_lib.Octree((1, 1, 1), (0, 0, 0), (1, 1, 1), q=2, precision="fp32_pc")
+    with pytest.raises(gpu_lib.DgError, match="max_elements"):
+        gpu_lib.Octree((2, 2, 2), (-2, -2, -2), (2, 2, 2), q=2, rho=_two_centres, delta_q=1e-9, max_depth=4,
+                       max_elements=100)
+    with pytest.raises(gpu_lib.DgError, match="finite"):
+        gpu_lib.Octree((1, 1, 1), (0, 0, 0), (1, 1, 1), q=2, rho=lambda x, y, z: np.nan * x)
+    # no refinement without a density: the base mesh, and its operator equals the uniform GL mesh's
+    o = gpu_lib.Octree((2, 3, 2), (-1.0, 0.0, -2.0), (1.5, 2.0, 1.0), q=3)
+    assert o.n_elements == 12 and o.max_generation == 0
