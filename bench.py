@@ -53,7 +53,8 @@ def parse():
                     help="untimed steps first: the first calls capture the PCG graphs and learn how many "
                          "iteration blocks to replay before a host check")
     ap.add_argument("--config", default="heldout32",
-                    choices=["heldout32", "exchange8", "exchange16", "uneven", "single", "quadrature", "consumers"],
+                    choices=["heldout32", "exchange8", "exchange16", "uneven", "single", "quadrature", "consumers",
+                             "octree"],
                     help="heldout32: 128 held-out pair densities on 32^3 elements p=4 (default); "
                          "exchange8/16: the exchange step of 8/16 orbitals on 16^3 elements p=4; "
                          "uneven: 256 densities over 8^3, 12^3 and 16^3 meshes in one interleaved batch; "
@@ -133,6 +134,8 @@ def main():
         return main_quadrature(args)
     if args.config == "consumers":
         return main_consumers(args)
+    if args.config == "octree":
+        return main_octree(args)
     return main_pairs(args)
 
 
@@ -762,6 +765,115 @@ def cpu_leg_single(args, wl, pots):
                "sample": f"{n} solves of the single-Gaussian problem, oracle MG-PCG FP64 to {wl.rtol}, "
                          f"{it} iterations; set-up excluded"}
     return cpu, check
+
+
+# ---------------------------------------------------------------------------
+# adaptive octree auxiliary mesh
+
+def main_octree(args):
+    """The 36 pair densities of the exchange8 molecule on its adaptive octree mesh (8^3 base
+    elements on [-8, 8]^3, q = 4, refined on the electron density with delta_q = 1e-8, at most 3
+    refinements): a step assembles the right-hand sides and solves them by FP64 MG-PCG to 1e-8
+    over the refinement hierarchy."""
+    import numpy as np
+    import torch
+
+    from paper_2510_21213_amd import binding
+    from workloads import configs
+
+    wl = configs.octree()
+    mesh, orb = wl.meshes[0], wl.orbitals
+    t0 = time.perf_counter()
+    o = binding.Octree(mesh.E, mesh.lo, mesh.hi, q=mesh.p, rho=wl.density, delta_q=wl.delta_q,
+                       max_depth=wl.max_depth, rtol=wl.rtol, max_iter=500)
+    t_setup = time.perf_counter() - t0
+    log(f"octree: {o.n_elements} elements, {o.n_dofs} nodes, {o.n_levels} levels, set-up {t_setup:.2f} s")
+    xyz = o.nodes()
+    bxyz = o.boundary_points()
+    pairs = orb.pairs()                   # the order of Orbitals.pair_potentials
+    psi = np.asarray(orb.values(xyz[0], xyz[1], xyz[2]))
+    f = torch.as_tensor(np.stack([psi[i] * psi[j] for i, j in pairs])).cuda().contiguous()
+    g = torch.as_tensor(orb.pair_potentials(bxyz[0], bxyz[1], bxyz[2])).cuda().contiguous()
+    nrhs = len(pairs)
+
+    def step():
+        b = o.rhs(f, g)
+        return o.solve(b)
+    for _ in range(args.warmup):
+        x, st = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, st = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    iters = [s["iters"] for s in st]
+    log(f"octree: {dt * 1e3:.1f} ms per step, iterations {min(iters)}..{max(iters)}")
+    # dominant kernel: the finest-level operator (k_oct_op<5, APPLY>), timed on the binding's stream
+    u = torch.randn(nrhs * o.n_dofs, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        o.apply(u)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        o.apply(u)
+    e1.record()
+    torch.cuda.synchronize()
+    t_op = e0.elapsed_time(e1) / reps * 1e-3
+    algo = 16.0 * o.n_dofs * nrhs        # read u, write y (FP64); geometry and pieces are < 1 %
+    roof = {"kernel": "k_oct_op<5, APPLY> (finest-level operator, 36 RHS)", "bound": "hbm",
+            "achieved": algo / t_op / 1e9, "peak": 8000.0, "unit": "GB/s", "frac": algo / t_op / 8e12,
+            "traffic": None, "us_per_launch": t_op * 1e6, "algorithmic_bytes_per_launch": algo}
+    # accuracy against the closed-form continuum potentials at the nodes (discretisation error)
+    vall = orb.pair_potentials(xyz[0], xyz[1], xyz[2])
+    xs = x.cpu().numpy().reshape(nrhs, -1)
+    errs = [float(np.linalg.norm(xs[k] - vall[k]) / np.linalg.norm(vall[k])) for k in range(nrhs)]
+    cpu = cpu_leg_octree(args, wl, pairs, iters) if args.cpu_sample > 0 else None
+    line = {
+        "metric": "Poisson RHS solved/sec on the adaptive octree auxiliary mesh (FP64 MG-PCG to 1e-8)",
+        "value": nrhs / dt, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"octree: exchange8 molecule, 36 pair densities, {mesh.E[0]}^3 base elements q={mesh.p} "
+                               f"refined on the electron density (delta_q {wl.delta_q}, depth {wl.max_depth}): "
+                               f"{o.n_elements} elements, {o.n_dofs} nodes, {o.n_levels} levels",
+                   "parallelism": "single GPU"},
+        "iters": {"min": min(iters), "max": max(iters), "mean": float(np.mean(iters))},
+        "max_rel_residual": max(s["rel_residual"] for s in st),
+        "setup_s": t_setup,
+        "rel_L2_err_vs_continuum": {"max": max(errs), "median": float(np.median(errs))},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def cpu_leg_octree(args, wl, pairs, gpu_iters):
+    """The oracle's octree MG-PCG on one pair (set-up excluded): a few iterations timed, scaled by
+    the iteration count of the GPU solve of that pair."""
+    import numpy as np
+
+    from oracle import octree, pcg
+    mesh, orb = wl.meshes[0], wl.orbitals
+    tree = octree.Octree(mesh.E, mesh.lo, mesh.hi, mesh.p, rho=wl.density, delta_q=wl.delta_q,
+                         max_depth=wl.max_depth)
+    H = octree.Hierarchy(tree)
+    m = H.meshes[0]
+    X, Y, Z = m.nodes()
+    bx, by, bz = m.boundary_points()
+    i, j = pairs[0]
+    psi = np.asarray(orb.values(X, Y, Z))
+    g = orb.pair_potentials(bx, by, bz)[0]
+    b = m.rhs(psi[i] * psi[j], g)
+    n_it = 3
+    t0 = time.perf_counter()
+    pcg.pcg(H.levels[0].A, b, H.vcycle, rtol=1e-30, maxit=n_it)
+    per_it = (time.perf_counter() - t0) / n_it
+    solve_s = per_it * gpu_iters[0]
+    return {"value": 1.0 / solve_s, "unit": "RHS/s", "cores": _threads(), "kind": "oracle", **_host(),
+            "sample": f"{n_it} oracle PCG iterations on pair {pairs[0]} of the same mesh ({per_it:.2f} s each), "
+                      f"scaled by the GPU solve's {gpu_iters[0]} iterations; octree and multigrid set-up excluded"}
 
 
 # ---------------------------------------------------------------------------

@@ -47,7 +47,7 @@ struct Piece {
     int nb;        // neighbour element, -1 on the domain boundary
     int s1, s2;    // table entries: this element's face nodes -> the piece's points, along t1 and t2
     int n1, n2;    // the same for the neighbour's face
-    int pad;
+    int face;      // face of this element: 2 d + (upper side), d the normal axis
     double sig;    // penalty of the piece
     double wsc;    // product of the piece's two tangential half-widths
 };
@@ -70,7 +70,11 @@ enum { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2 };
     } while (0)
 
 // y = A u (APPLY), y = f - A u (RESID), or one fused Chebyshev step (CHEB, u = the current
-// correction d): z += d; r -= A d; y = c1 d + c2 D^-1 r.  Grid (element blocks, nrhs).
+// correction d): z += d; r -= A d; y = c1 d + c2 D^-1 r.  Grid (element blocks, nrhs); a block
+// holds EPB = 128 / N^3 element slots of N^3 threads.  The pieces of an element (all six faces,
+// stored consecutively) are taken N at a time, N^2 threads per piece: traces of both sides, the
+// two interpolation passes to the piece's points, the flux, the two transposed passes back onto
+// the element's face nodes; then every node thread adds what the pass's pieces give its own row.
 template <int N, int MODE>
 __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* __restrict__ J,
                                               const int* __restrict__ fstart, const Piece* __restrict__ pcs,
@@ -81,10 +85,11 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
                                               double c2) {
     constexpr int N2 = N * N, N3 = N * N * N, EPB = OT / N3;
     __shared__ double U[EPB][N3];
-    __shared__ double OT_[EPB][N2], OD[EPB][N2], NT[EPB][N2], ND[EPB][N2];
-    __shared__ double X0[EPB][N2], X1[EPB][N2], X2[EPB][N2], X3[EPB][N2];
-    __shared__ double CT[EPB][N2], CD[EPB][N2], FT[EPB][N2], FD[EPB][N2];
-    __shared__ int npc[EPB];
+    // per slot, per piece of the pass (N pieces of N^2 points): own / neighbour trace and normal
+    // derivative, then the interpolation scratch, the flux, and the result on the face nodes
+    __shared__ double A0[EPB][N3], A1[EPB][N3], A2[EPB][N3], A3[EPB][N3];
+    __shared__ double B0[EPB][N3], B1[EPB][N3], B2[EPB][N3], B3[EPB][N3];
+    __shared__ int npc[EPB], ncc[EPB];
     const int rhs = blockIdx.y;
     if (st && !st[rhs].active) return;
     const int t = threadIdx.x, s = t / N3, l = t - s * N3;
@@ -92,7 +97,19 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
     const bool node = s < EPB && e < ne;
     const long long base = (long long)rhs * ne * N3;
     const int i = l % N, j = (l / N) % N, k = l / N2;
+    const int pj = l / N2, fl = l - pj * N2;  // piece of the pass and its point / face node
     if (node) U[s][l] = u[base + (long long)e * N3 + l];
+    int p0 = 0, nconf = 0, np = 0;
+    if (node) {
+        p0 = fstart[2 * e];
+        nconf = fstart[2 * e + 1] - p0;
+        np = fstart[2 * e + 2] - p0;
+    }
+    if (node && l == 0) {
+        npc[s] = np - nconf;
+        ncc[s] = nconf;
+    }
+    if (!node && l == 0 && s < EPB) npc[s] = ncc[s] = 0;
     __syncthreads();
     double acc = 0.0, Jx = 1.0, Jy = 1.0, Jz = 1.0;
     if (node) {
@@ -109,26 +126,27 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
         acc = Jy * Jz / Jx * R.w[j] * R.w[k] * ax + Jx * Jz / Jy * R.w[i] * R.w[k] * ay +
               Jx * Jy / Jz * R.w[i] * R.w[j] * az;
     }
-    for (int fc = 0; fc < 6; ++fc) {
-        const int d = fc >> 1;
-        const double sg = (fc & 1) ? 1.0 : -1.0;
-        // strides of the normal axis and of the tangential axes t1 < t2 in the [k][j][i] array
-        const int sd = d == 0 ? 1 : (d == 1 ? N : N2);
-        const int s1 = d == 0 ? N : 1;
-        const int s2 = d == 2 ? N : N2;
-        const double* vS = (fc & 1) ? R.eR : R.eL;
-        const double* dS = (fc & 1) ? R.dR : R.dL;
-        const double* vO = (fc & 1) ? R.eL : R.eR;  // the neighbour's opposite face
-        const double* dO = (fc & 1) ? R.dL : R.dR;
-        const double Jd = d == 0 ? Jx : (d == 1 ? Jy : Jz);
-        int p0 = 0, np = 0;
-        if (node) {
-            p0 = fstart[e * 6 + fc];
-            np = fstart[e * 6 + fc + 1] - p0;
-        }
-        if (node && l == 0) npc[s] = np;
-        if (node && l < N2) {
-            const int a = l % N, b = l / N;
+    int npmax = 0, ncmax = 0;
+#pragma unroll
+    for (int q = 0; q < EPB; ++q) {
+        npmax = max(npmax, npc[q]);
+        ncmax = max(ncmax, ncc[q]);
+    }
+    const int o = pj * N2;  // this piece's block of N^2 in the slot arrays
+    // conforming pieces and boundary faces (every table entry the identity): the flux at the face
+    // nodes directly, N pieces per pass
+    for (int pass = 0; pass < ncmax; pass += N) {
+        const int pi = pass + pj;
+        if (node && pi < nconf) {
+            const Piece P = pcs[p0 + pi];
+            const bool inner = P.nb >= 0;
+            const int fc = P.face, d = fc >> 1;
+            const int sd = d == 0 ? 1 : (d == 1 ? N : N2);
+            const int s1 = d == 0 ? N : 1;
+            const int s2 = d == 2 ? N : N2;
+            const int a = fl % N, b = fl / N;
+            const double* vS = (fc & 1) ? R.eR : R.eL;
+            const double* dS = (fc & 1) ? R.dR : R.dL;
             double tv = 0.0, dv = 0.0;
 #pragma unroll
             for (int m = 0; m < N; ++m) {
@@ -136,123 +154,184 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
                 tv += vS[m] * x;
                 dv += dS[m] * x;
             }
-            OT_[s][l] = tv;
-            OD[s][l] = dv / Jd;
-            FT[s][l] = 0.0;
-            FD[s][l] = 0.0;
-        }
-        if (!node && l == 0 && s < EPB) npc[s] = 0;
-        __syncthreads();
-        int npmax = 0;
-#pragma unroll
-        for (int q = 0; q < EPB; ++q) npmax = max(npmax, npc[q]);
-        for (int pi = 0; pi < npmax; ++pi) {
-            const bool act = node && pi < np && l < N2;
-            Piece P;
-            P.nb = -1;
-            P.s1 = P.s2 = P.n1 = P.n2 = 0;
-            P.sig = P.wsc = 0.0;
-            if (act) P = pcs[p0 + pi];
-            const bool inner = P.nb >= 0;
-            if (act && inner) {
+            dv /= (d == 0 ? Jx : (d == 1 ? Jy : Jz));
+            double tn = 0.0, dn = 0.0;
+            if (inner) {
+                const double* vO = (fc & 1) ? R.eL : R.eR;
+                const double* dO = (fc & 1) ? R.dL : R.dR;
                 const double* un = u + base + (long long)P.nb * N3;
-                const double Jn = J[3 * P.nb + d];
-                const int a = l % N, b = l / N;
-                double tv = 0.0, dv = 0.0;
 #pragma unroll
                 for (int m = 0; m < N; ++m) {
                     const double x = un[m * sd + a * s1 + b * s2];
-                    tv += vO[m] * x;
-                    dv += dO[m] * x;
+                    tn += vO[m] * x;
+                    dn += dO[m] * x;
                 }
-                NT[s][l] = tv;
-                ND[s][l] = dv / Jn;
+                dn /= J[3 * P.nb + d];
             }
-            __syncthreads();
-            // interpolation along t1: X[b][q1] = sum_a I1[q1][a] F[b][a]
-            if (act) {
-                const int q1 = l % N, b = l / N;
-                const double* Is = tab + (long long)P.s1 * N2 + q1 * N;
-                double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+            const double sg = (fc & 1) ? 1.0 : -1.0;
+            const double jmp = inner ? tv - tn : tv;
+            const double davg = inner ? 0.5 * (dv + dn) : dv;
+            const double half = inner ? 0.5 : 1.0;
+            const double W = R.w[a] * R.w[b] * P.wsc;
+            A2[s][o + fl] = W * (P.sig * jmp - sg * davg);
+            A3[s][o + fl] = W * (-half * jmp);
+        }
+        __syncthreads();
+        if (node) {
+            for (int q = 0; q < N && pass + q < nconf; ++q) {
+                const int fq = pcs[p0 + pass + q].face;
+                const int dq = fq >> 1;
+                const int m = dq == 0 ? i : (dq == 1 ? j : k);
+                const int a = dq == 0 ? j : i;
+                const int b = dq == 2 ? j : k;
+                const double vm = (fq & 1) ? R.eR[m] : R.eL[m];
+                const double dm = (fq & 1) ? R.dR[m] : -R.dL[m];
+                const double Jq = dq == 0 ? Jx : (dq == 1 ? Jy : Jz);
+                acc += vm * A2[s][q * N2 + b * N + a] + dm / Jq * A3[s][q * N2 + b * N + a];
+            }
+        }
+        __syncthreads();
+    }
+    // hanging pieces: interpolation to the piece's points and back
+    p0 += nconf;
+    np -= nconf;
+    for (int pass = 0; pass < npmax; pass += N) {
+        const int pi = pass + pj;
+        const bool act = node && pi < np;
+        Piece P;
+        P.nb = -1;
+        P.s1 = P.s2 = P.n1 = P.n2 = P.face = 0;
+        P.sig = P.wsc = 0.0;
+        if (act) P = pcs[p0 + pi];
+        const bool inner = P.nb >= 0;
+        const int fc = P.face, d = fc >> 1;
+        const int sd = d == 0 ? 1 : (d == 1 ? N : N2);
+        const int s1 = d == 0 ? N : 1;
+        const int s2 = d == 2 ? N : N2;
+        // traces on the face nodes (a, b) = (fl % N, fl / N): own face, and the neighbour's opposite face
+        if (act) {
+            const int a = fl % N, b = fl / N;
+            const double* vS = (fc & 1) ? R.eR : R.eL;
+            const double* dS = (fc & 1) ? R.dR : R.dL;
+            double tv = 0.0, dv = 0.0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const double x = U[s][m * sd + a * s1 + b * s2];
+                tv += vS[m] * x;
+                dv += dS[m] * x;
+            }
+            A0[s][o + fl] = tv;
+            A1[s][o + fl] = dv / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
+            double tn = 0.0, dn = 0.0;
+            if (inner) {
+                const double* vO = (fc & 1) ? R.eL : R.eR;
+                const double* dO = (fc & 1) ? R.dL : R.dR;
+                const double* un = u + base + (long long)P.nb * N3;
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const double x = un[m * sd + a * s1 + b * s2];
+                    tn += vO[m] * x;
+                    dn += dO[m] * x;
+                }
+                dn /= J[3 * P.nb + d];
+            }
+            A2[s][o + fl] = tn;
+            A3[s][o + fl] = dn;
+        }
+        __syncthreads();
+        // interpolation along t1: X[b][q1] = sum_a I1[q1][a] F[b][a]
+        if (act) {
+            const int q1 = fl % N, b = fl / N;
+            const double* Is = tab + (long long)P.s1 * N2 + q1 * N;
+            double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                x0 += Is[a] * A0[s][o + b * N + a];
+                x1 += Is[a] * A1[s][o + b * N + a];
+            }
+            if (inner) {
+                const double* In = tab + (long long)P.n1 * N2 + q1 * N;
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
-                    x0 += Is[a] * OT_[s][b * N + a];
-                    x1 += Is[a] * OD[s][b * N + a];
+                    x2 += In[a] * A2[s][o + b * N + a];
+                    x3 += In[a] * A3[s][o + b * N + a];
                 }
-                if (inner) {
-                    const double* In = tab + (long long)P.n1 * N2 + q1 * N;
-#pragma unroll
-                    for (int a = 0; a < N; ++a) {
-                        x2 += In[a] * NT[s][b * N + a];
-                        x3 += In[a] * ND[s][b * N + a];
-                    }
-                }
-                X0[s][l] = x0;
-                X1[s][l] = x1;
-                X2[s][l] = x2;
-                X3[s][l] = x3;
             }
-            __syncthreads();
-            // along t2, then the flux at the piece point (q2, q1)
-            if (act) {
-                const int q1 = l % N, q2 = l / N;
-                const double* Is = tab + (long long)P.s2 * N2 + q2 * N;
-                double tr = 0.0, dr = 0.0, trn = 0.0, drn = 0.0;
+            B0[s][o + fl] = x0;
+            B1[s][o + fl] = x1;
+            B2[s][o + fl] = x2;
+            B3[s][o + fl] = x3;
+        }
+        __syncthreads();
+        // along t2, and the flux at the piece point (q2, q1); seen from this element (outward
+        // normal sg e_d): [u] = u - u_nb, {d_n u} = sg {du/dx_d}
+        if (act) {
+            const int q1 = fl % N, q2 = fl / N;
+            const double* Is = tab + (long long)P.s2 * N2 + q2 * N;
+            double tr = 0.0, dr = 0.0, trn = 0.0, drn = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                tr += Is[b] * B0[s][o + b * N + q1];
+                dr += Is[b] * B1[s][o + b * N + q1];
+            }
+            if (inner) {
+                const double* In = tab + (long long)P.n2 * N2 + q2 * N;
 #pragma unroll
                 for (int b = 0; b < N; ++b) {
-                    tr += Is[b] * X0[s][b * N + q1];
-                    dr += Is[b] * X1[s][b * N + q1];
+                    trn += In[b] * B2[s][o + b * N + q1];
+                    drn += In[b] * B3[s][o + b * N + q1];
                 }
-                if (inner) {
-                    const double* In = tab + (long long)P.n2 * N2 + q2 * N;
-#pragma unroll
-                    for (int b = 0; b < N; ++b) {
-                        trn += In[b] * X2[s][b * N + q1];
-                        drn += In[b] * X3[s][b * N + q1];
-                    }
-                }
-                // seen from this element (outward normal sg e_d): [u] = u - u_nb, {d_n u} = sg {du/dx_d}
-                const double jmp = inner ? tr - trn : tr;
-                const double davg = inner ? 0.5 * (dr + drn) : dr;
-                const double half = inner ? 0.5 : 1.0;
-                const double W = R.w[q1] * R.w[q2] * P.wsc;
-                CT[s][l] = W * (P.sig * jmp - sg * davg);
-                CD[s][l] = W * (-half * jmp);
             }
-            __syncthreads();
-            // back onto the face nodes: transpose along t2, then along t1
-            if (act) {
-                const int q1 = l % N, b = l / N;
-                double y0 = 0.0, y1 = 0.0;
-#pragma unroll
-                for (int q2 = 0; q2 < N; ++q2) {
-                    const double I = tab[(long long)P.s2 * N2 + q2 * N + b];
-                    y0 += I * CT[s][q2 * N + q1];
-                    y1 += I * CD[s][q2 * N + q1];
-                }
-                X0[s][l] = y0;
-                X1[s][l] = y1;
-            }
-            __syncthreads();
-            if (act) {
-                const int a = l % N, b = l / N;
-                double y0 = 0.0, y1 = 0.0;
-#pragma unroll
-                for (int q1 = 0; q1 < N; ++q1) {
-                    const double I = tab[(long long)P.s1 * N2 + q1 * N + a];
-                    y0 += I * X0[s][b * N + q1];
-                    y1 += I * X1[s][b * N + q1];
-                }
-                FT[s][l] += y0;
-                FD[s][l] += y1;
-            }
-            __syncthreads();
+            const double sg = (fc & 1) ? 1.0 : -1.0;
+            const double jmp = inner ? tr - trn : tr;
+            const double davg = inner ? 0.5 * (dr + drn) : dr;
+            const double half = inner ? 0.5 : 1.0;
+            const double W = R.w[q1] * R.w[q2] * P.wsc;
+            A0[s][o + fl] = W * (P.sig * jmp - sg * davg);
+            A1[s][o + fl] = W * (-half * jmp);
         }
+        __syncthreads();
+        // back onto the face nodes: transpose along t2 ...
+        if (act) {
+            const int q1 = fl % N, b = fl / N;
+            double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+            for (int q2 = 0; q2 < N; ++q2) {
+                const double I = tab[(long long)P.s2 * N2 + q2 * N + b];
+                y0 += I * A0[s][o + q2 * N + q1];
+                y1 += I * A1[s][o + q2 * N + q1];
+            }
+            B0[s][o + fl] = y0;
+            B1[s][o + fl] = y1;
+        }
+        __syncthreads();
+        // ... and along t1
+        if (act) {
+            const int a = fl % N, b = fl / N;
+            double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+            for (int q1 = 0; q1 < N; ++q1) {
+                const double I = tab[(long long)P.s1 * N2 + q1 * N + a];
+                y0 += I * B0[s][o + b * N + q1];
+                y1 += I * B1[s][o + b * N + q1];
+            }
+            A2[s][o + fl] = y0;
+            A3[s][o + fl] = y1;
+        }
+        __syncthreads();
+        // every node adds the pass's pieces: v_s(m) FT[b][a] + sg d_s(m) / J_d FD[b][a]
         if (node) {
-            const int m = d == 0 ? i : (d == 1 ? j : k);
-            const int a = d == 0 ? j : i;
-            const int b = d == 2 ? j : k;
-            acc += vS[m] * FT[s][b * N + a] + sg * dS[m] / Jd * FD[s][b * N + a];
+            for (int q = 0; q < N && pass + q < np; ++q) {
+                const int fq = pcs[p0 + pass + q].face;
+                const int dq = fq >> 1;
+                const int m = dq == 0 ? i : (dq == 1 ? j : k);
+                const int a = dq == 0 ? j : i;
+                const int b = dq == 2 ? j : k;
+                const double vm = (fq & 1) ? R.eR[m] : R.eL[m];
+                const double dm = (fq & 1) ? R.dR[m] : -R.dL[m];
+                const double Jq = dq == 0 ? Jx : (dq == 1 ? Jy : Jz);
+                acc += vm * A2[s][q * N2 + b * N + a] + dm / Jq * A3[s][q * N2 + b * N + a];
+            }
         }
         __syncthreads();
     }
@@ -508,7 +587,7 @@ struct Level {
     long long ndof = 0;
     std::vector<int> cells;               // tree cell of each element
     std::vector<double> Jh;               // half-widths, 3 per element
-    std::vector<int> fsh;                 // piece ranges, 6 per element + 1
+    std::vector<int> fsh;                 // piece ranges: {first, first hanging} per element, + end
     std::vector<Piece> ph;
     std::vector<double> diag;
     double* J = nullptr;
@@ -780,7 +859,8 @@ void build_level(dg_octree& O, Level& L, bool finest) {
                 pa.s2 = pb.n2 = desc(a, t2, plo[1], plen[1]);
                 pa.n1 = pb.s1 = desc(b, t1, plo[0], plen[0]);
                 pa.n2 = pb.s2 = desc(b, t2, plo[1], plen[1]);
-                pa.pad = pb.pad = 0;
+                pa.face = 2 * d + 1;
+                pb.face = 2 * d;
                 pa.sig = pb.sig = pen / hF;
                 pa.wsc = pb.wsc = half[0] * half[1];
                 face[6 * a + 2 * d + 1].push_back(pa);
@@ -800,7 +880,7 @@ void build_level(dg_octree& O, Level& L, bool finest) {
                 Piece p;
                 p.nb = -1;
                 p.s1 = p.s2 = p.n1 = p.n2 = 0;
-                p.pad = 0;
+                p.face = 2 * d + sgi;
                 p.sig = pen / (B[3 * e + d] - A[3 * e + d]);
                 p.wsc = L.Jh[3 * e + t1] * L.Jh[3 * e + t2];
                 face[6 * e + 2 * d + sgi].push_back(p);
@@ -813,14 +893,24 @@ void build_level(dg_octree& O, Level& L, bool finest) {
         O.bsh = bs;
         O.nbp = nbp;
     }
-    L.fsh.assign(6 * (size_t)L.ne + 1, 0);
+    // per element: the conforming pieces and boundary faces, then the hanging pieces (each
+    // group face by face, a face's pieces by neighbour); fsh = {first, first hanging} per element
+    L.fsh.assign(2 * (size_t)L.ne + 1, 0);
     L.ph.clear();
-    for (size_t f = 0; f < face.size(); ++f) {
-        std::sort(face[f].begin(), face[f].end(), [](const Piece& x, const Piece& y) { return x.nb < y.nb; });
-        L.fsh[f] = (int)L.ph.size();
-        for (const Piece& p : face[f]) L.ph.push_back(p);
+    auto conforming = [](const Piece& p) { return p.s1 == 0 && p.s2 == 0 && p.n1 == 0 && p.n2 == 0; };
+    for (int e = 0; e < L.ne; ++e) {
+        for (int fc = 0; fc < 6; ++fc)
+            std::sort(face[6 * e + fc].begin(), face[6 * e + fc].end(),
+                      [](const Piece& x, const Piece& y) { return x.nb < y.nb; });
+        L.fsh[2 * e] = (int)L.ph.size();
+        for (int hang = 0; hang < 2; ++hang) {
+            if (hang) L.fsh[2 * e + 1] = (int)L.ph.size();
+            for (int fc = 0; fc < 6; ++fc)
+                for (const Piece& p : face[6 * e + fc])
+                    if (conforming(p) != (hang == 1)) L.ph.push_back(p);
+        }
     }
-    L.fsh[face.size()] = (int)L.ph.size();
+    L.fsh[2 * (size_t)L.ne] = (int)L.ph.size();
     // diagonal: volume terms and, per piece, sum_q W T^2 sigma - kappa T d_n T (separable)
     std::vector<double> xi, w, D;
     node_rule(L.q, 1, xi, w, D);
@@ -843,14 +933,15 @@ void build_level(dg_octree& O, Level& L, bool finest) {
                 for (int i = 0; i < n; ++i)
                     De[(k * n + j) * n + i] = Jy * Jz / Jx * w[k] * w[j] * K1d[i] + Jx * Jz / Jy * w[k] * K1d[j] * w[i] +
                                               Jx * Jy / Jz * K1d[k] * w[j] * w[i];
-        for (int fc = 0; fc < 6; ++fc) {
+        for (int pi = L.fsh[2 * e]; pi < L.fsh[2 * e + 2]; ++pi) {
+            const Piece& P = L.ph[pi];
+            const int fc = P.face;
             const int d = fc >> 1;
             const double sg = (fc & 1) ? 1.0 : -1.0;
             const std::vector<double>& v = (fc & 1) ? eR : eL;
             const std::vector<double>& dv = (fc & 1) ? dR : dL;
             const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-            for (int pi = L.fsh[6 * e + fc]; pi < L.fsh[6 * e + fc + 1]; ++pi) {
-                const Piece& P = L.ph[pi];
+            {
                 const double kappa = P.nb < 0 ? 2.0 : 1.0;
                 // piece half-widths along t1 and t2: this element's, shrunk by the table level
                 double S1[9] = {0}, S2[9] = {0};

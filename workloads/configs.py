@@ -19,6 +19,13 @@ Workloads (all seeded with numpy.random.default_rng):
                   meshes (p=4, box [-E/2, E/2]^3); each density a sum of 2..12
                   normalised Gaussians (exponents log-uniform in [0.3,10],
                   weights U[0.5,1.5], centres uniform in [-E/4, E/4]^3).  (seed 4)
+* ``octree``      the exchange8 molecule on an adaptive octree auxiliary mesh:
+                  8x8x8 base elements on [-8,8]^3, degree q=4 Gauss-Legendre,
+                  refined on the electron density sum_k psi_k^2 with
+                  delta_q = 1e-8 (the paper's tolerance) and at most 3
+                  refinements per base element; all 36 pair densities as
+                  right-hand sides, Dirichlet data from their closed-form
+                  potentials; tolerance 1e-8.  (seed 2)
 * ``large``       32x32x32 elements, p=4, box [-16,16]^3; molecules of 16..32
                   atoms in [-8,8]^3 with the exchange8 primitive recipe,
                   8 orbitals, 36 pairs per molecule.  (seed 50000+i train,
@@ -124,6 +131,23 @@ def uneven(n_rhs=256, seed=4):
         dens.append(GaussianDensity(rng.uniform(0.5, 1.5, K), _log_uniform(rng, K),
                                     rng.uniform(-E / 4.0, E / 4.0, size=(K, 3))))
     return Workload("uneven", meshes, 4, 1e-8, batch=DensityBatch(dens, mesh_of))
+
+
+def octree():
+    """The octree workload: base mesh, refinement parameters and the molecule's orbitals; the
+    refinement density is ``density`` (the electron density of the occupied orbitals)."""
+    wl = exchange8()
+    wl.name = "octree"
+    wl.meshes = [cube(8, 4, 8.0)]
+    wl.n_levels = None
+    wl.delta_q, wl.max_depth = 1e-8, 3
+    orb = wl.orbitals
+
+    def density(x, y, z):
+        v = np.asarray(orb.values(x, y, z))
+        return (v * v).sum(axis=0)
+    wl.density = density
+    return wl
 
 
 def large_molecule(index, held_out=False, norb=8):
