@@ -126,6 +126,7 @@ def _load():
         "dg_octree_apply": (I, [P, I, I, P, P, P]),
         "dg_octree_vcycle": (I, [P, I, P, P, P]),
         "dg_octree_solve": (I, [P, I, P, P, P, P]),
+        "dg_octree_set_rhs_per_block": (I, [P, I]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -507,6 +508,9 @@ class Octree:
                                         ctypes.byref(hi)), "octree_level_info")
         return {"n_elements": ne.value, "q": q.value, "lam_lo": lo.value, "lam_hi": hi.value,
                 "n_dofs": ne.value * (q.value + 1) ** 3}
+
+    def set_rhs_per_block(self, rb):
+        _check(lib.dg_octree_set_rhs_per_block(self._h, int(rb)), "octree_set_rhs_per_block")
 
     def elements(self):
         """(lohi [n_elements, 6], generation [n_elements])."""

@@ -75,8 +75,8 @@ enum { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2 };
 // stored consecutively) are taken N at a time, N^2 threads per piece: traces of both sides, the
 // two interpolation passes to the piece's points, the flux, the two transposed passes back onto
 // the element's face nodes; then every node thread adds what the pass's pieces give its own row.
-template <int N, int MODE>
-__global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* __restrict__ J,
+template <int N, int MODE, int RB>
+__global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, const double* __restrict__ J,
                                               const int* __restrict__ fstart, const Piece* __restrict__ pcs,
                                               const double* __restrict__ tab, const RhsState* __restrict__ st,
                                               const double* __restrict__ u, double* __restrict__ y,
@@ -84,21 +84,39 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
                                               double* __restrict__ z, const double* __restrict__ dinv, double c1,
                                               double c2) {
     constexpr int N2 = N * N, N3 = N * N * N, EPB = OT / N3;
-    __shared__ double U[EPB][N3];
-    // per slot, per piece of the pass (N pieces of N^2 points): own / neighbour trace and normal
-    // derivative, then the interpolation scratch, the flux, and the result on the face nodes
-    __shared__ double A0[EPB][N3], A1[EPB][N3], A2[EPB][N3], A3[EPB][N3];
-    __shared__ double B0[EPB][N3], B1[EPB][N3], B2[EPB][N3], B3[EPB][N3];
+    __shared__ double U[RB][EPB][N3];
+    // per right-hand side and slot, per piece of the pass (N pieces of N^2 points): own /
+    // neighbour trace and normal derivative, the interpolation scratch, the flux, and the result
+    // on the face nodes
+    __shared__ double A0[RB][EPB][N3], A1[RB][EPB][N3], A2[RB][EPB][N3], A3[RB][EPB][N3];
+    __shared__ double B0[RB][EPB][N3], B1[RB][EPB][N3], B2[RB][EPB][N3], B3[RB][EPB][N3];
     __shared__ int npc[EPB], ncc[EPB];
-    const int rhs = blockIdx.y;
-    if (st && !st[rhs].active) return;
+    __shared__ Ref<N> R;  // the reference data, indexed at run time (from LDS, not the argument block)
+    const int rhs0 = blockIdx.y * RB;
+    bool live[RB];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        live[q] = rhs0 + q < nrhs && (!st || st[rhs0 + q].active);
+        any = any || live[q];
+    }
+    if (!any) return;
     const int t = threadIdx.x, s = t / N3, l = t - s * N3;
     const int e = blockIdx.x * EPB + s;
+    {
+        const double* src = reinterpret_cast<const double*>(&Rarg);
+        double* dst = reinterpret_cast<double*>(&R);
+        for (int q = t; q < (int)(sizeof(Ref<N>) / sizeof(double)); q += OT) dst[q] = src[q];
+    }
     const bool node = s < EPB && e < ne;
-    const long long base = (long long)rhs * ne * N3;
+    const long long estride = (long long)ne * N3;
     const int i = l % N, j = (l / N) % N, k = l / N2;
     const int pj = l / N2, fl = l - pj * N2;  // piece of the pass and its point / face node
-    if (node) U[s][l] = u[base + (long long)e * N3 + l];
+    if (node) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            U[q][s][l] = live[q] ? u[(long long)(rhs0 + q) * estride + (long long)e * N3 + l] : 0.0;
+    }
     int p0 = 0, nconf = 0, np = 0;
     if (node) {
         p0 = fstart[2 * e];
@@ -111,20 +129,27 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
     }
     if (!node && l == 0 && s < EPB) npc[s] = ncc[s] = 0;
     __syncthreads();
-    double acc = 0.0, Jx = 1.0, Jy = 1.0, Jz = 1.0;
+    double acc[RB];
+    double Jx = 1.0, Jy = 1.0, Jz = 1.0;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = 0.0;
     if (node) {
         Jx = J[3 * e];
         Jy = J[3 * e + 1];
         Jz = J[3 * e + 2];
-        double ax = 0.0, ay = 0.0, az = 0.0;
+        const double sx = Jy * Jz / Jx * R.w[j] * R.w[k], sy = Jx * Jz / Jy * R.w[i] * R.w[k],
+                     sz = Jx * Jy / Jz * R.w[i] * R.w[j];
 #pragma unroll
-        for (int a = 0; a < N; ++a) {
-            ax += R.K1[i][a] * U[s][(k * N + j) * N + a];
-            ay += R.K1[j][a] * U[s][(k * N + a) * N + i];
-            az += R.K1[k][a] * U[s][(a * N + j) * N + i];
+        for (int q = 0; q < RB; ++q) {
+            double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                ax += R.K1[i][a] * U[q][s][(k * N + j) * N + a];
+                ay += R.K1[j][a] * U[q][s][(k * N + a) * N + i];
+                az += R.K1[k][a] * U[q][s][(a * N + j) * N + i];
+            }
+            acc[q] = sx * ax + sy * ay + sz * az;
         }
-        acc = Jy * Jz / Jx * R.w[j] * R.w[k] * ax + Jx * Jz / Jy * R.w[i] * R.w[k] * ay +
-              Jx * Jy / Jz * R.w[i] * R.w[j] * az;
     }
     int npmax = 0, ncmax = 0;
 #pragma unroll
@@ -133,6 +158,19 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
         ncmax = max(ncmax, ncc[q]);
     }
     const int o = pj * N2;  // this piece's block of N^2 in the slot arrays
+    // every node adds the pass's pieces (results in A2 / A3): v_s(m) FT[b][a] + sg d_s(m) / J_d FD[b][a]
+#define OCT_GATHER(first, count)                                                                          \
+    for (int q = 0; q < N && q < (count); ++q) {                                                          \
+        const int fq = pcs[(first) + q].face;                                                             \
+        const int dq = fq >> 1;                                                                           \
+        const int m = dq == 0 ? i : (dq == 1 ? j : k);                                                    \
+        const int a = dq == 0 ? j : i;                                                                    \
+        const int b = dq == 2 ? j : k;                                                                    \
+        const double vm = (fq & 1) ? R.eR[m] : R.eL[m];                                                   \
+        const double dm = ((fq & 1) ? R.dR[m] : -R.dL[m]) / (dq == 0 ? Jx : (dq == 1 ? Jy : Jz));         \
+        _Pragma("unroll") for (int c = 0; c < RB; ++c) acc[c] +=                                          \
+            vm * A2[c][s][q * N2 + b * N + a] + dm * A3[c][s][q * N2 + b * N + a];                        \
+    }
     // conforming pieces and boundary faces (every table entry the identity): the flux at the face
     // nodes directly, N pieces per pass
     for (int pass = 0; pass < ncmax; pass += N) {
@@ -147,49 +185,42 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
             const int a = fl % N, b = fl / N;
             const double* vS = (fc & 1) ? R.eR : R.eL;
             const double* dS = (fc & 1) ? R.dR : R.dL;
-            double tv = 0.0, dv = 0.0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const double x = U[s][m * sd + a * s1 + b * s2];
-                tv += vS[m] * x;
-                dv += dS[m] * x;
-            }
-            dv /= (d == 0 ? Jx : (d == 1 ? Jy : Jz));
-            double tn = 0.0, dn = 0.0;
-            if (inner) {
-                const double* vO = (fc & 1) ? R.eL : R.eR;
-                const double* dO = (fc & 1) ? R.dL : R.dR;
-                const double* un = u + base + (long long)P.nb * N3;
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    const double x = un[m * sd + a * s1 + b * s2];
-                    tn += vO[m] * x;
-                    dn += dO[m] * x;
-                }
-                dn /= J[3 * P.nb + d];
-            }
+            const double* vO = (fc & 1) ? R.eL : R.eR;
+            const double* dO = (fc & 1) ? R.dL : R.dR;
+            const double iJ = 1.0 / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
+            const double iJn = inner ? 1.0 / J[3 * P.nb + d] : 0.0;
             const double sg = (fc & 1) ? 1.0 : -1.0;
-            const double jmp = inner ? tv - tn : tv;
-            const double davg = inner ? 0.5 * (dv + dn) : dv;
             const double half = inner ? 0.5 : 1.0;
             const double W = R.w[a] * R.w[b] * P.wsc;
-            A2[s][o + fl] = W * (P.sig * jmp - sg * davg);
-            A3[s][o + fl] = W * (-half * jmp);
-        }
-        __syncthreads();
-        if (node) {
-            for (int q = 0; q < N && pass + q < nconf; ++q) {
-                const int fq = pcs[p0 + pass + q].face;
-                const int dq = fq >> 1;
-                const int m = dq == 0 ? i : (dq == 1 ? j : k);
-                const int a = dq == 0 ? j : i;
-                const int b = dq == 2 ? j : k;
-                const double vm = (fq & 1) ? R.eR[m] : R.eL[m];
-                const double dm = (fq & 1) ? R.dR[m] : -R.dL[m];
-                const double Jq = dq == 0 ? Jx : (dq == 1 ? Jy : Jz);
-                acc += vm * A2[s][q * N2 + b * N + a] + dm / Jq * A3[s][q * N2 + b * N + a];
+            const int lo = a * s1 + b * s2;
+#pragma unroll
+            for (int c = 0; c < RB; ++c) {
+                double tv = 0.0, dv = 0.0, tn = 0.0, dn = 0.0;
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const double x = U[c][s][m * sd + lo];
+                    tv += vS[m] * x;
+                    dv += dS[m] * x;
+                }
+                if (inner && live[c]) {
+                    const double* un = u + (long long)(rhs0 + c) * estride + (long long)P.nb * N3;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        const double x = un[m * sd + lo];
+                        tn += vO[m] * x;
+                        dn += dO[m] * x;
+                    }
+                }
+                dv *= iJ;
+                dn *= iJn;
+                const double jmp = inner ? tv - tn : tv;
+                const double davg = inner ? 0.5 * (dv + dn) : dv;
+                A2[c][s][o + fl] = W * (P.sig * jmp - sg * davg);
+                A3[c][s][o + fl] = W * (-half * jmp);
             }
         }
+        __syncthreads();
+        if (node) { OCT_GATHER(p0 + pass, nconf - pass) }
         __syncthreads();
     }
     // hanging pieces: interpolation to the piece's points and back
@@ -205,149 +236,159 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> R, int ne, const double* _
         if (act) P = pcs[p0 + pi];
         const bool inner = P.nb >= 0;
         const int fc = P.face, d = fc >> 1;
-        const int sd = d == 0 ? 1 : (d == 1 ? N : N2);
-        const int s1 = d == 0 ? N : 1;
-        const int s2 = d == 2 ? N : N2;
         // traces on the face nodes (a, b) = (fl % N, fl / N): own face, and the neighbour's opposite face
         if (act) {
+            const int sd = d == 0 ? 1 : (d == 1 ? N : N2);
+            const int s1 = d == 0 ? N : 1;
+            const int s2 = d == 2 ? N : N2;
             const int a = fl % N, b = fl / N;
+            const int lo = a * s1 + b * s2;
             const double* vS = (fc & 1) ? R.eR : R.eL;
             const double* dS = (fc & 1) ? R.dR : R.dL;
-            double tv = 0.0, dv = 0.0;
+            const double* vO = (fc & 1) ? R.eL : R.eR;
+            const double* dO = (fc & 1) ? R.dL : R.dR;
+            const double iJ = 1.0 / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
+            const double iJn = inner ? 1.0 / J[3 * P.nb + d] : 0.0;
 #pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const double x = U[s][m * sd + a * s1 + b * s2];
-                tv += vS[m] * x;
-                dv += dS[m] * x;
-            }
-            A0[s][o + fl] = tv;
-            A1[s][o + fl] = dv / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
-            double tn = 0.0, dn = 0.0;
-            if (inner) {
-                const double* vO = (fc & 1) ? R.eL : R.eR;
-                const double* dO = (fc & 1) ? R.dL : R.dR;
-                const double* un = u + base + (long long)P.nb * N3;
+            for (int c = 0; c < RB; ++c) {
+                double tv = 0.0, dv = 0.0, tn = 0.0, dn = 0.0;
 #pragma unroll
                 for (int m = 0; m < N; ++m) {
-                    const double x = un[m * sd + a * s1 + b * s2];
-                    tn += vO[m] * x;
-                    dn += dO[m] * x;
+                    const double x = U[c][s][m * sd + lo];
+                    tv += vS[m] * x;
+                    dv += dS[m] * x;
                 }
-                dn /= J[3 * P.nb + d];
+                if (inner && live[c]) {
+                    const double* un = u + (long long)(rhs0 + c) * estride + (long long)P.nb * N3;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        const double x = un[m * sd + lo];
+                        tn += vO[m] * x;
+                        dn += dO[m] * x;
+                    }
+                }
+                A0[c][s][o + fl] = tv;
+                A1[c][s][o + fl] = dv * iJ;
+                A2[c][s][o + fl] = tn;
+                A3[c][s][o + fl] = dn * iJn;
             }
-            A2[s][o + fl] = tn;
-            A3[s][o + fl] = dn;
         }
         __syncthreads();
         // interpolation along t1: X[b][q1] = sum_a I1[q1][a] F[b][a]
         if (act) {
             const int q1 = fl % N, b = fl / N;
-            const double* Is = tab + (long long)P.s1 * N2 + q1 * N;
-            double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+            double Is[N], In[N];
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                x0 += Is[a] * A0[s][o + b * N + a];
-                x1 += Is[a] * A1[s][o + b * N + a];
+                Is[a] = tab[(long long)P.s1 * N2 + q1 * N + a];
+                In[a] = tab[(long long)P.n1 * N2 + q1 * N + a];
             }
-            if (inner) {
-                const double* In = tab + (long long)P.n1 * N2 + q1 * N;
+#pragma unroll
+            for (int c = 0; c < RB; ++c) {
+                double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
-                    x2 += In[a] * A2[s][o + b * N + a];
-                    x3 += In[a] * A3[s][o + b * N + a];
+                    x0 += Is[a] * A0[c][s][o + b * N + a];
+                    x1 += Is[a] * A1[c][s][o + b * N + a];
+                    x2 += In[a] * A2[c][s][o + b * N + a];
+                    x3 += In[a] * A3[c][s][o + b * N + a];
                 }
+                B0[c][s][o + fl] = x0;
+                B1[c][s][o + fl] = x1;
+                B2[c][s][o + fl] = x2;
+                B3[c][s][o + fl] = x3;
             }
-            B0[s][o + fl] = x0;
-            B1[s][o + fl] = x1;
-            B2[s][o + fl] = x2;
-            B3[s][o + fl] = x3;
         }
         __syncthreads();
         // along t2, and the flux at the piece point (q2, q1); seen from this element (outward
         // normal sg e_d): [u] = u - u_nb, {d_n u} = sg {du/dx_d}
         if (act) {
             const int q1 = fl % N, q2 = fl / N;
-            const double* Is = tab + (long long)P.s2 * N2 + q2 * N;
-            double tr = 0.0, dr = 0.0, trn = 0.0, drn = 0.0;
+            double Is[N], In[N];
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-                tr += Is[b] * B0[s][o + b * N + q1];
-                dr += Is[b] * B1[s][o + b * N + q1];
-            }
-            if (inner) {
-                const double* In = tab + (long long)P.n2 * N2 + q2 * N;
-#pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    trn += In[b] * B2[s][o + b * N + q1];
-                    drn += In[b] * B3[s][o + b * N + q1];
-                }
+                Is[b] = tab[(long long)P.s2 * N2 + q2 * N + b];
+                In[b] = tab[(long long)P.n2 * N2 + q2 * N + b];
             }
             const double sg = (fc & 1) ? 1.0 : -1.0;
-            const double jmp = inner ? tr - trn : tr;
-            const double davg = inner ? 0.5 * (dr + drn) : dr;
             const double half = inner ? 0.5 : 1.0;
             const double W = R.w[q1] * R.w[q2] * P.wsc;
-            A0[s][o + fl] = W * (P.sig * jmp - sg * davg);
-            A1[s][o + fl] = W * (-half * jmp);
+#pragma unroll
+            for (int c = 0; c < RB; ++c) {
+                double tr = 0.0, dr = 0.0, trn = 0.0, drn = 0.0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    tr += Is[b] * B0[c][s][o + b * N + q1];
+                    dr += Is[b] * B1[c][s][o + b * N + q1];
+                    trn += In[b] * B2[c][s][o + b * N + q1];
+                    drn += In[b] * B3[c][s][o + b * N + q1];
+                }
+                const double jmp = inner ? tr - trn : tr;
+                const double davg = inner ? 0.5 * (dr + drn) : dr;
+                A0[c][s][o + fl] = W * (P.sig * jmp - sg * davg);
+                A1[c][s][o + fl] = W * (-half * jmp);
+            }
         }
         __syncthreads();
         // back onto the face nodes: transpose along t2 ...
         if (act) {
             const int q1 = fl % N, b = fl / N;
-            double y0 = 0.0, y1 = 0.0;
+            double I2[N];
 #pragma unroll
-            for (int q2 = 0; q2 < N; ++q2) {
-                const double I = tab[(long long)P.s2 * N2 + q2 * N + b];
-                y0 += I * A0[s][o + q2 * N + q1];
-                y1 += I * A1[s][o + q2 * N + q1];
+            for (int q2 = 0; q2 < N; ++q2) I2[q2] = tab[(long long)P.s2 * N2 + q2 * N + b];
+#pragma unroll
+            for (int c = 0; c < RB; ++c) {
+                double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+                for (int q2 = 0; q2 < N; ++q2) {
+                    y0 += I2[q2] * A0[c][s][o + q2 * N + q1];
+                    y1 += I2[q2] * A1[c][s][o + q2 * N + q1];
+                }
+                B0[c][s][o + fl] = y0;
+                B1[c][s][o + fl] = y1;
             }
-            B0[s][o + fl] = y0;
-            B1[s][o + fl] = y1;
         }
         __syncthreads();
         // ... and along t1
         if (act) {
             const int a = fl % N, b = fl / N;
-            double y0 = 0.0, y1 = 0.0;
+            double I1[N];
 #pragma unroll
-            for (int q1 = 0; q1 < N; ++q1) {
-                const double I = tab[(long long)P.s1 * N2 + q1 * N + a];
-                y0 += I * B0[s][o + b * N + q1];
-                y1 += I * B1[s][o + b * N + q1];
+            for (int q1 = 0; q1 < N; ++q1) I1[q1] = tab[(long long)P.s1 * N2 + q1 * N + a];
+#pragma unroll
+            for (int c = 0; c < RB; ++c) {
+                double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+                for (int q1 = 0; q1 < N; ++q1) {
+                    y0 += I1[q1] * B0[c][s][o + b * N + q1];
+                    y1 += I1[q1] * B1[c][s][o + b * N + q1];
+                }
+                A2[c][s][o + fl] = y0;
+                A3[c][s][o + fl] = y1;
             }
-            A2[s][o + fl] = y0;
-            A3[s][o + fl] = y1;
         }
         __syncthreads();
-        // every node adds the pass's pieces: v_s(m) FT[b][a] + sg d_s(m) / J_d FD[b][a]
-        if (node) {
-            for (int q = 0; q < N && pass + q < np; ++q) {
-                const int fq = pcs[p0 + pass + q].face;
-                const int dq = fq >> 1;
-                const int m = dq == 0 ? i : (dq == 1 ? j : k);
-                const int a = dq == 0 ? j : i;
-                const int b = dq == 2 ? j : k;
-                const double vm = (fq & 1) ? R.eR[m] : R.eL[m];
-                const double dm = (fq & 1) ? R.dR[m] : -R.dL[m];
-                const double Jq = dq == 0 ? Jx : (dq == 1 ? Jy : Jz);
-                acc += vm * A2[s][q * N2 + b * N + a] + dm / Jq * A3[s][q * N2 + b * N + a];
-            }
-        }
+        if (node) { OCT_GATHER(p0 + pass, np - pass) }
         __syncthreads();
     }
     if (!node) return;
-    const long long g = base + (long long)e * N3 + l;
-    if constexpr (MODE == OP_APPLY) {
-        y[g] = acc;
-    } else if constexpr (MODE == OP_RESID) {
-        y[g] = f[g] - acc;
-    } else {
-        const double dv = U[s][l];
-        z[g] += dv;
-        const double rn = r[g] - acc;
-        r[g] = rn;
-        y[g] = c1 * dv + c2 * dinv[(long long)e * N3 + l] * rn;
+#pragma unroll
+    for (int c = 0; c < RB; ++c) {
+        if (!live[c]) continue;
+        const long long g = (long long)(rhs0 + c) * estride + (long long)e * N3 + l;
+        if constexpr (MODE == OP_APPLY) {
+            y[g] = acc[c];
+        } else if constexpr (MODE == OP_RESID) {
+            y[g] = f[g] - acc[c];
+        } else {
+            const double dv = U[c][s][l];
+            z[g] += dv;
+            const double rn = r[g] - acc[c];
+            r[g] = rn;
+            y[g] = c1 * dv + c2 * dinv[(long long)e * N3 + l] * rn;
+        }
     }
+#undef OCT_GATHER
 }
 
 // grid (chunks of 256, nrhs): per-node kernels over one level's fields
@@ -615,6 +656,7 @@ struct dg_octree {
     int E[3];
     double lo[3], hi[3], h[3];
     int q = 4;
+    int rhs_per_block = 2;                // right-hand sides per operator work-group (1, 2 or 4)
     dg_opts opts;
     std::vector<dg::oct::TCell> tree;
     int max_gen = 0;
@@ -1005,22 +1047,36 @@ Ref<N> make_ref(int q) {
     return R;
 }
 
+template <int N, int RB>
+void op_launch_nb(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const double* u,
+                  double* y, const double* f, double* r, double* z, double c1, double c2, hipStream_t s) {
+    constexpr int EPB = OT / (N * N * N);
+    static const Ref<N> R = make_ref<N>(N - 1);
+    dim3 grid((L.ne + EPB - 1) / EPB, (nrhs + RB - 1) / RB);
+    const double* tab = O.tab[N];
+    if (mode == OP_APPLY)
+        hipLaunchKernelGGL((k_oct_op<N, OP_APPLY, RB>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs, tab,
+                           st, u, y, f, r, z, L.dinv, c1, c2);
+    else if (mode == OP_RESID)
+        hipLaunchKernelGGL((k_oct_op<N, OP_RESID, RB>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs, tab,
+                           st, u, y, f, r, z, L.dinv, c1, c2);
+    else
+        hipLaunchKernelGGL((k_oct_op<N, OP_CHEB, RB>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs, tab,
+                           st, u, y, f, r, z, L.dinv, c1, c2);
+}
+
+// right-hand sides per work-group: several share the element's geometry, pieces and tables and
+// give each thread independent work between the barriers
 template <int N>
 void op_launch_n(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const double* u,
                  double* y, const double* f, double* r, double* z, double c1, double c2, hipStream_t s) {
-    constexpr int EPB = OT / (N * N * N);
-    static const Ref<N> R = make_ref<N>(N - 1);
-    dim3 grid((L.ne + EPB - 1) / EPB, nrhs);
-    const double* tab = O.tab[N];
-    if (mode == OP_APPLY)
-        hipLaunchKernelGGL((k_oct_op<N, OP_APPLY>), grid, dim3(OT), 0, s, R, L.ne, L.J, L.fstart, L.pcs, tab, st, u, y,
-                           f, r, z, L.dinv, c1, c2);
-    else if (mode == OP_RESID)
-        hipLaunchKernelGGL((k_oct_op<N, OP_RESID>), grid, dim3(OT), 0, s, R, L.ne, L.J, L.fstart, L.pcs, tab, st, u, y,
-                           f, r, z, L.dinv, c1, c2);
+    const int rb = O.rhs_per_block;
+    if (rb >= 4 && nrhs >= 4)
+        op_launch_nb<N, 4>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
+    else if (rb >= 2 && nrhs >= 2)
+        op_launch_nb<N, 2>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
     else
-        hipLaunchKernelGGL((k_oct_op<N, OP_CHEB>), grid, dim3(OT), 0, s, R, L.ne, L.J, L.fstart, L.pcs, tab, st, u, y,
-                           f, r, z, L.dinv, c1, c2);
+        op_launch_nb<N, 1>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
 }
 
 void op_launch(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const double* u, double* y,
@@ -1656,6 +1712,14 @@ dg_status dg_octree_solve(dg_octree* o, int nrhs, const double* b, double* x, dg
         worst = dg::oct::solve(o, nrhs, b, x, stats, (hipStream_t)stream);
     });
     return st != DG_OK ? st : (dg_status)worst;
+}
+
+dg_status dg_octree_set_rhs_per_block(dg_octree* o, int rhs_per_block) {
+    return dg::guarded([&] {
+        if (!o || (rhs_per_block != 1 && rhs_per_block != 2 && rhs_per_block != 4))
+            throw std::invalid_argument("rhs_per_block must be 1, 2 or 4");
+        o->rhs_per_block = rhs_per_block;
+    });
 }
 
 void dg_octree_destroy(dg_octree* o) { dg::oct::destroy(o); }
