@@ -539,7 +539,8 @@ dg_status dg_octree_rhs(dg_octree* octree, int nrhs, const double* f, const doub
 dg_status dg_octree_apply(dg_octree* octree, int level, int nrhs, const double* u, double* y, void* stream);
 /* z = V r, one V-cycle of the preconditioner on the finest level (device arrays). */
 dg_status dg_octree_vcycle(dg_octree* octree, int nrhs, const double* r, double* z, void* stream);
-/* Tuning: right-hand sides per work-group of the octree operator kernels (1, 2 or 4; default 2):
+/* Tuning: right-hand sides per work-group of the octree operator kernels (1, 2 or 4; 0, the
+ * default: 4 at degree 4 and 2 below, the fastest measured on MI355X):
  * the right-hand sides of a work-group share its element's geometry, pieces and tables, and
  * give each thread independent work between its barriers.  Results do not depend on it. */
 dg_status dg_octree_set_rhs_per_block(dg_octree* octree, int rhs_per_block);

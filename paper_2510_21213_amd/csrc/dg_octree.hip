@@ -50,6 +50,7 @@ struct Piece {
     int face;      // face of this element: 2 d + (upper side), d the normal axis
     double sig;    // penalty of the piece
     double wsc;    // product of the piece's two tangential half-widths
+    double ijn;    // 1 / (the neighbour's half-width along the normal), 0 on the boundary
 };
 
 template <int N>
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
             const double* vO = (fc & 1) ? R.eL : R.eR;
             const double* dO = (fc & 1) ? R.dL : R.dR;
             const double iJ = 1.0 / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
-            const double iJn = inner ? 1.0 / J[3 * P.nb + d] : 0.0;
+            const double iJn = P.ijn;
             const double sg = (fc & 1) ? 1.0 : -1.0;
             const double half = inner ? 0.5 : 1.0;
             const double W = R.w[a] * R.w[b] * P.wsc;
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
         Piece P;
         P.nb = -1;
         P.s1 = P.s2 = P.n1 = P.n2 = P.face = 0;
-        P.sig = P.wsc = 0.0;
+        P.sig = P.wsc = P.ijn = 0.0;
         if (act) P = pcs[p0 + pi];
         const bool inner = P.nb >= 0;
         const int fc = P.face, d = fc >> 1;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
             const double* vO = (fc & 1) ? R.eL : R.eR;
             const double* dO = (fc & 1) ? R.dL : R.dR;
             const double iJ = 1.0 / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
-            const double iJn = inner ? 1.0 / J[3 * P.nb + d] : 0.0;
+            const double iJn = P.ijn;
 #pragma unroll
             for (int c = 0; c < RB; ++c) {
                 double tv = 0.0, dv = 0.0, tn = 0.0, dn = 0.0;
@@ -656,7 +657,7 @@ struct dg_octree {
     int E[3];
     double lo[3], hi[3], h[3];
     int q = 4;
-    int rhs_per_block = 2;                // right-hand sides per operator work-group (1, 2 or 4)
+    int rhs_per_block = 0;                // right-hand sides per operator work-group (1, 2, 4; 0 by degree)
     dg_opts opts;
     std::vector<dg::oct::TCell> tree;
     int max_gen = 0;
@@ -905,6 +906,8 @@ void build_level(dg_octree& O, Level& L, bool finest) {
                 pb.face = 2 * d;
                 pa.sig = pb.sig = pen / hF;
                 pa.wsc = pb.wsc = half[0] * half[1];
+                pa.ijn = 1.0 / L.Jh[3 * b + d];
+                pb.ijn = 1.0 / L.Jh[3 * a + d];
                 face[6 * a + 2 * d + 1].push_back(pa);
                 face[6 * b + 2 * d].push_back(pb);
             }
@@ -925,6 +928,7 @@ void build_level(dg_octree& O, Level& L, bool finest) {
                 p.face = 2 * d + sgi;
                 p.sig = pen / (B[3 * e + d] - A[3 * e + d]);
                 p.wsc = L.Jh[3 * e + t1] * L.Jh[3 * e + t2];
+                p.ijn = 0.0;
                 face[6 * e + 2 * d + sgi].push_back(p);
                 if (finest) {
                     bs[6 * e + 2 * d + sgi] = (int)nbp;
@@ -1070,7 +1074,7 @@ void op_launch_nb(const dg_octree& O, const Level& L, int mode, int nrhs, const 
 template <int N>
 void op_launch_n(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const double* u,
                  double* y, const double* f, double* r, double* z, double c1, double c2, hipStream_t s) {
-    const int rb = O.rhs_per_block;
+    const int rb = O.rhs_per_block > 0 ? O.rhs_per_block : (N == 5 ? 4 : 2);  // 0: by degree (measured)
     if (rb >= 4 && nrhs >= 4)
         op_launch_nb<N, 4>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
     else if (rb >= 2 && nrhs >= 2)
@@ -1716,8 +1720,8 @@ dg_status dg_octree_solve(dg_octree* o, int nrhs, const double* b, double* x, dg
 
 dg_status dg_octree_set_rhs_per_block(dg_octree* o, int rhs_per_block) {
     return dg::guarded([&] {
-        if (!o || (rhs_per_block != 1 && rhs_per_block != 2 && rhs_per_block != 4))
-            throw std::invalid_argument("rhs_per_block must be 1, 2 or 4");
+        if (!o || (rhs_per_block != 0 && rhs_per_block != 1 && rhs_per_block != 2 && rhs_per_block != 4))
+            throw std::invalid_argument("rhs_per_block must be 0, 1, 2 or 4");
         o->rhs_per_block = rhs_per_block;
     });
 }
