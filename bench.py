@@ -770,6 +770,12 @@ def cpu_leg_single(args, wl, pots):
 # ---------------------------------------------------------------------------
 # adaptive octree auxiliary mesh
 
+# Chebyshev steps on the octree's degree-4 and degree-2 levels, and on its degree-1 levels: on this
+# mesh the iteration count follows the first alone (6: 30-32 iterations, 8: 23-26, 10: 19-23) and
+# the degree-1 levels' steps only cost time; (8, 4) was the fastest measured on MI355X
+OCTREE_CHEB = (8, 4)
+
+
 def main_octree(args):
     """The 36 pair densities of the exchange8 molecule on its adaptive octree mesh (8^3 base
     elements on [-8, 8]^3, q = 4, refined on the electron density with delta_q = 1e-8, at most 3
@@ -785,7 +791,8 @@ def main_octree(args):
     mesh, orb = wl.meshes[0], wl.orbitals
     t0 = time.perf_counter()
     o = binding.Octree(mesh.E, mesh.lo, mesh.hi, q=mesh.p, rho=wl.density, delta_q=wl.delta_q,
-                       max_depth=wl.max_depth, rtol=wl.rtol, max_iter=500)
+                       max_depth=wl.max_depth, rtol=wl.rtol, max_iter=500, cheb_degree=OCTREE_CHEB[0],
+                       cheb_degree_h=OCTREE_CHEB[1])
     t_setup = time.perf_counter() - t0
     log(f"octree: {o.n_elements} elements, {o.n_dofs} nodes, {o.n_levels} levels, set-up {t_setup:.2f} s")
     xyz = o.nodes()
@@ -837,7 +844,8 @@ def main_octree(args):
         "data": "synthetic",
         "config": {"workload": f"octree: exchange8 molecule, 36 pair densities, {mesh.E[0]}^3 base elements q={mesh.p} "
                                f"refined on the electron density (delta_q {wl.delta_q}, depth {wl.max_depth}): "
-                               f"{o.n_elements} elements, {o.n_dofs} nodes, {o.n_levels} levels",
+                               f"{o.n_elements} elements, {o.n_dofs} nodes, {o.n_levels} levels; Chebyshev "
+                               f"steps {OCTREE_CHEB[0]} (degree 4, 2), {OCTREE_CHEB[1]} (degree 1)",
                    "parallelism": "single GPU"},
         "iters": {"min": min(iters), "max": max(iters), "mean": float(np.mean(iters))},
         "max_rel_residual": max(s["rel_residual"] for s in st),
@@ -858,7 +866,7 @@ def cpu_leg_octree(args, wl, pairs, gpu_iters):
     mesh, orb = wl.meshes[0], wl.orbitals
     tree = octree.Octree(mesh.E, mesh.lo, mesh.hi, mesh.p, rho=wl.density, delta_q=wl.delta_q,
                          max_depth=wl.max_depth)
-    H = octree.Hierarchy(tree)
+    H = octree.Hierarchy(tree, degree=OCTREE_CHEB[0], degree_h=OCTREE_CHEB[1])
     m = H.meshes[0]
     X, Y, Z = m.nodes()
     bx, by, bz = m.boundary_points()

@@ -104,10 +104,13 @@ def test_operator_rhs_bounds_and_vcycle_match_oracle(gpu_lib, case):
     assert np.abs(z - zref).max() <= 1e-9 * np.abs(zref).max()
 
 
-@pytest.mark.parametrize("case", CASES[:3])
-def test_solve_matches_oracle_pcg(gpu_lib, case):
-    g, t = _pair(gpu_lib, case, rtol=1e-12)
-    H = octree.Hierarchy(t)
+@pytest.mark.parametrize("case,cheb", [(CASES[0], (6, 10)), (CASES[1], (6, 10)), (CASES[2], (6, 10)),
+                                       (CASES[0], (8, 4)), (CASES[1], (8, 4))])
+def test_solve_matches_oracle_pcg(gpu_lib, case, cheb):
+    """Full solves; (8, 4) Chebyshev steps (degree >= 2 levels, degree-1 levels) is the octree
+    benchmark's setting, (6, 10) the library default."""
+    g, t = _pair(gpu_lib, case, rtol=1e-12, cheb_degree=cheb[0], cheb_degree_h=cheb[1])
+    H = octree.Hierarchy(t, degree=cheb[0], degree_h=cheb[1])
     m = H.meshes[0]
     X, Y, Z = m.nodes()
     bx, by, bz = m.boundary_points()
