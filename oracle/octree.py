@@ -412,6 +412,21 @@ class Mesh:
         allp = np.concatenate(pts, axis=1)
         return allp[0], allp[1], allp[2]
 
+    def boundary_data(self, f, chunk=256):
+        """Dirichlet data by quadrature (Sec. 6.3): g(r) = sum_q W_q f(x_q) / |r - x_q| at the
+        ``boundary_points``, W_q the physical GL weight of node q (``mass``).  With GL nodes no
+        node lies on the boundary, so every term is finite.  f: [..., ndof]; returns [..., nb]."""
+        f = np.asarray(f, dtype=np.float64)
+        lead = f.shape[:-1]
+        F = (self.mass() * f.reshape(-1, self.ndof)).T                 # [ndof, S]
+        xq = np.stack(self.nodes(), axis=1)                             # [ndof, 3]
+        pts = np.stack(self.boundary_points(), axis=1)                  # [nb, 3]
+        out = np.empty((pts.shape[0], F.shape[1]))
+        for s in range(0, pts.shape[0], chunk):
+            d = np.sqrt(np.sum((pts[s:s + chunk, None, :] - xq[None, :, :]) ** 2, axis=-1))
+            out[s:s + chunk] = (1.0 / d) @ F
+        return out.T.reshape(lead + (pts.shape[0],))
+
     def rhs(self, f, g):
         """b = 4 pi M f + boundary lift of g (f at the nodes, g at ``boundary_points``)."""
         n = self.n

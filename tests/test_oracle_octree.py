@@ -256,3 +256,46 @@ def test_error_falls_at_high_order_on_a_hanging_mesh():
         A, _ = m.dense()
         errs.append(np.abs(np.linalg.solve(A, m.rhs(f, g)) - u).max())
     assert errs[0] < 0.1 and errs[1] < errs[0] / 10   # measured 4.9e-2 and 2.2e-3
+
+
+def test_boundary_data_by_quadrature_brute_force_and_closed_form():
+    """Sec. 6.3's Dirichlet data on the octree grid: the vectorised sum equals explicit loops over
+    every boundary point and node with weights built here from the GL rule; for a Gaussian well
+    inside the box the data approach the closed-form potential erf(sqrt(a) r)/r, and refining
+    the mesh around the Gaussian (the octree's purpose) brings them closer."""
+    from scipy.special import erf
+    from oracle import nodes
+    a, c = 8.0, np.array([0.2, -0.1, 0.15])
+
+    def rho(x, y, z):
+        return (a / np.pi) ** 1.5 * np.exp(-a * ((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2))
+    tree = octree.Octree((2, 1, 1), (-2.0, -1.0, -1.0), (2.0, 1.0, 1.0), 2, manual=lambda cl: cl.gen == 0 and
+                         cl.ix == (1, 0, 0), max_depth=1)
+    m = tree.mesh()
+    f = rho(*m.nodes())
+    g = m.boundary_data(f)
+    xi, w = nodes.gl(2)[:2]
+    bx, by, bz = m.boundary_points()
+    ref = np.zeros_like(g)
+    for e in range(len(m.cells)):
+        lo, hi = m.a[e], m.b[e]
+        for k in range(3):
+            for j in range(3):
+                for i in range(3):
+                    x = [lo[d] + 0.5 * (hi[d] - lo[d]) * (xi[(i, j, k)[d]] + 1.0) for d in range(3)]
+                    W = np.prod([0.5 * (hi[d] - lo[d]) * w[(i, j, k)[d]] for d in range(3)])
+                    fq = rho(*x)
+                    for p in range(len(bx)):
+                        ref[p] += W * fq / np.sqrt((bx[p] - x[0]) ** 2 + (by[p] - x[1]) ** 2 + (bz[p] - x[2]) ** 2)
+    assert np.abs(g - ref).max() <= 1e-13 * np.abs(ref).max()
+    # against the closed form, coarse and refined around the Gaussian
+    errs = []
+    for depth in (0, 3):
+        t = octree.Octree((2, 2, 2), (-3.0,) * 3, (3.0,) * 3, 4, rho=rho, delta_q=1e-6, max_depth=depth)
+        mm = t.mesh()
+        gg = mm.boundary_data(rho(*mm.nodes()))
+        px, py, pz = mm.boundary_points()
+        r = np.sqrt((px - c[0]) ** 2 + (py - c[1]) ** 2 + (pz - c[2]) ** 2)
+        exact = erf(np.sqrt(a) * r) / r
+        errs.append(np.abs(gg - exact).max() / np.abs(exact).max())
+    assert errs[1] < 3e-6 and errs[1] < errs[0] / 1e4     # measured 0.10 (8 cells) and 1.2e-6 (155 cells)
