@@ -533,8 +533,14 @@ dg_status dg_octree_nodes(const dg_octree* octree, double* x, double* y, double*
  * tangential axes, t1 fastest). */
 dg_status dg_octree_boundary_points(const dg_octree* octree, double* x, double* y, double* z);
 /* b = 4 pi M f + Nitsche lift of g (eq. hartree_poisson / fock_poisson on the auxiliary mesh):
- * device arrays f, b [nrhs][n_dofs] and g [nrhs][n_boundary]. */
+ * device arrays f, b [nrhs][n_dofs] and g [nrhs][n_boundary]; g NULL: the Dirichlet data by
+ * quadrature of f (dg_octree_boundary_data; synchronises the stream). */
 dg_status dg_octree_rhs(dg_octree* octree, int nrhs, const double* f, const double* g, double* b, void* stream);
+/* Dirichlet data by quadrature (Sec. 6.3): g_s(r) = sum_q W_q f_s(x_q) / |r - x_q| at the
+ * Dirichlet points, over the finest level's nodes x_q with their GL weights W_q (no node lies on
+ * the boundary).  Device arrays f [nsrc][n_dofs], g [nsrc][n_boundary]; the node tables and the
+ * partial sums are kept by the octree (allocated on first use and when nsrc grows). */
+dg_status dg_octree_boundary_data(dg_octree* octree, int nsrc, const double* f, double* g, void* stream);
 /* y = A u on multigrid level `level` (device arrays [nrhs][level nodes]). */
 dg_status dg_octree_apply(dg_octree* octree, int level, int nrhs, const double* u, double* y, void* stream);
 /* z = V r, one V-cycle of the preconditioner on the finest level (device arrays). */

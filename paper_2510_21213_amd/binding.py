@@ -127,6 +127,7 @@ def _load():
         "dg_octree_vcycle": (I, [P, I, P, P, P]),
         "dg_octree_solve": (I, [P, I, P, P, P, P]),
         "dg_octree_set_rhs_per_block": (I, [P, I]),
+        "dg_octree_boundary_data": (I, [P, I, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -532,7 +533,15 @@ class Octree:
                "octree_boundary_points")
         return xyz[:, :self.n_boundary]
 
-    def rhs(self, f, g):
+    def boundary_data(self, f):
+        """Dirichlet data by quadrature of the sources f [nsrc, n_dofs]: [nsrc, n_boundary]."""
+        nsrc = f.numel() // self.n_dofs
+        g = torch.empty((nsrc, self.n_boundary), dtype=torch.float64, device=f.device)
+        _check(lib.dg_octree_boundary_data(self._h, nsrc, _ptr(f), _ptr(g), _stream()), "octree_boundary_data")
+        return g
+
+    def rhs(self, f, g=None):
+        """b = 4 pi M f + lift(g); g None: the Dirichlet data by quadrature of f."""
         nrhs = f.numel() // self.n_dofs
         b = torch.empty_like(f)
         _check(lib.dg_octree_rhs(self._h, nrhs, _ptr(f), _ptr(g), _ptr(b), _stream()), "octree_rhs")

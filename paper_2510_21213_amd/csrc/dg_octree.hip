@@ -612,6 +612,70 @@ __global__ __launch_bounds__(256) void k_oct_rhs(Ref<N> R, int ne, long long nbp
     b[g] = acc;
 }
 
+// Dirichlet data by quadrature (Sec. 6.3): g_s(r_p) = sum_q W_q f_s(x_q) / |r_p - x_q| over the
+// finest level's nodes (GL nodes: none lies on the boundary, every term is finite).  Grid
+// (point blocks, source blocks of BR, node parts): a thread owns one boundary point and BR
+// sources; the part's nodes stream through LDS in tiles of BT (coordinates and BR weighted
+// values); each part writes its partial sums, added in a fixed order by k_oct_bsum.
+constexpr int BT = 256, BR = 12;
+
+__global__ __launch_bounds__(BT) void k_oct_bdata(long long ndof, int nbp, int nsrc, int tiles_per_part,
+                                                  const double* __restrict__ nx, const double* __restrict__ ny,
+                                                  const double* __restrict__ nz, const double* __restrict__ nw,
+                                                  const double* __restrict__ px, const double* __restrict__ py,
+                                                  const double* __restrict__ pz, const double* __restrict__ f,
+                                                  double* __restrict__ part) {
+    __shared__ double X[BT], Y[BT], Z[BT], V[BR][BT];
+    const int p = blockIdx.x * BT + threadIdx.x;
+    const int s0 = blockIdx.y * BR;
+    const int part_id = blockIdx.z;
+    const double rx = p < nbp ? px[p] : 0.0, ry = p < nbp ? py[p] : 0.0, rz = p < nbp ? pz[p] : 0.0;
+    double acc[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) acc[r] = 0.0;
+    const long long t0 = (long long)part_id * tiles_per_part;
+    for (long long t = t0; t < t0 + tiles_per_part; ++t) {
+        const long long q0 = t * BT;
+        if (q0 >= ndof) break;
+        const long long q = q0 + threadIdx.x;
+        const bool in = q < ndof;
+        X[threadIdx.x] = in ? nx[q] : 0.0;
+        Y[threadIdx.x] = in ? ny[q] : 0.0;
+        Z[threadIdx.x] = in ? nz[q] : 1e30;  // padding far away: contributes 0 * tiny
+        const double w = in ? nw[q] : 0.0;
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+            V[r][threadIdx.x] = (in && s0 + r < nsrc) ? w * f[(long long)(s0 + r) * ndof + q] : 0.0;
+        __syncthreads();
+        const int cnt = (int)min((long long)BT, ndof - q0);
+        for (int k = 0; k < cnt; ++k) {
+            const double dx = rx - X[k], dy = ry - Y[k], dz = rz - Z[k];
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            // hardware estimate of r2^(-1/2) (about 5e-8) refined by two terms of the series
+            // (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - r2 y^2: error O(e^3)
+            double inv = __builtin_amdgcn_rsq(r2);
+            const double e = fma(-(r2 * inv), inv, 1.0);
+            inv = fma(inv * e, fma(0.375, e, 0.5), inv);
+#pragma unroll
+            for (int r = 0; r < BR; ++r) acc[r] += V[r][k] * inv;
+        }
+        __syncthreads();
+    }
+    if (p >= nbp) return;
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+        if (s0 + r < nsrc) part[((long long)part_id * nsrc + s0 + r) * nbp + p] = acc[r];
+}
+
+__global__ __launch_bounds__(256) void k_oct_bsum(int nparts, int nsrc, int nbp, const double* __restrict__ part,
+                                                  double* __restrict__ g) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long long)nsrc * nbp) return;
+    double acc = 0.0;
+    for (int k = 0; k < nparts; ++k) acc += part[(long long)k * nsrc * nbp + i];
+    g[i] = acc;
+}
+
 // ---------------------------------------------------------------------------------------------
 // host side
 
@@ -666,6 +730,10 @@ struct dg_octree {
     double* tab[9] = {};                  // interpolation tables per point count (device)
     std::vector<double> tabh[9];
     int* bstart = nullptr;                // finest level: boundary offsets
+    double* qnodes = nullptr;             // quadrature data: node x, y, z, weight (4 x n_dofs), then the
+                                          // boundary points' x, y, z (3 x n_boundary), built on first use
+    double* qpart = nullptr;              // its partial sums
+    long long qpart_cap = 0;
     std::vector<int> bsh;
     long long nbp = 0;                    // boundary points
     dg::LevelHost base;                   // uniform base mesh at degree 1 (coarsest solve)
@@ -1320,6 +1388,8 @@ void destroy(dg_octree* O) {
     }
     for (auto& t : O->tab) ofree(t);
     ofree(O->bstart);
+    ofree(O->qnodes);
+    ofree(O->qpart);
     ofree(O->cdev);
     for (auto* v : {&O->wf, &O->wz, &O->wr, &O->wd0, &O->wd1, &O->wt})
         for (auto& p : *v) ofree(p);
@@ -1522,8 +1592,16 @@ void level_info(const dg_octree* O, int level, long long* ne, int* q, double* la
     if (lam_hi) *lam_hi = L.lam_hi;
 }
 
+void boundary_data(dg_octree* O, int nsrc, const double* f, double* g, hipStream_t s);
+
 void rhs(dg_octree* O, int nrhs, const double* f, const double* g, double* b, hipStream_t s) {
     const Level& L = O->lv[0];
+    double* gq = nullptr;
+    if (!g && O->nbp > 0) {  // Dirichlet data by quadrature of f
+        gq = oalloc<double>((long long)nrhs * O->nbp);
+        boundary_data(O, nrhs, f, gq, s);
+        g = gq;
+    }
     const double pen = (double)(L.q + 1) * (L.q + 1) / O->opts.penalty_eps;
     const dim3 grid = node_grid(L.ndof, nrhs);
     switch (L.n) {
@@ -1532,6 +1610,52 @@ void rhs(dg_octree* O, int nrhs, const double* f, const double* g, double* b, hi
         case 4: hipLaunchKernelGGL(k_oct_rhs<4>, grid, dim3(256), 0, s, make_ref<4>(3), L.ne, O->nbp, pen, L.J, O->bstart, f, g, b); break;
         case 5: hipLaunchKernelGGL(k_oct_rhs<5>, grid, dim3(256), 0, s, make_ref<5>(4), L.ne, O->nbp, pen, L.J, O->bstart, f, g, b); break;
     }
+    OCHK(hipGetLastError());
+    if (gq) {
+        OCHK(hipStreamSynchronize(s));
+        ofree(gq);
+    }
+}
+
+void boundary_data(dg_octree* O, int nsrc, const double* f, double* g, hipStream_t s) {
+    const Level& L = O->lv[0];
+    const long long nd = L.ndof, nb = O->nbp;
+    if (nsrc == 0 || nb == 0) return;
+    if (!O->qnodes) {
+        std::vector<double> h(4 * nd + 3 * nb);
+        node_coords(O, &h[0], &h[nd], &h[2 * nd]);
+        const int n = L.n;
+        const std::vector<double>& w = O->wgl[n];
+        for (int e = 0; e < L.ne; ++e) {
+            const double J3 = L.Jh[3 * e] * L.Jh[3 * e + 1] * L.Jh[3 * e + 2];
+            for (int k = 0; k < n; ++k)
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < n; ++i)
+                        h[3 * nd + (long long)e * n * n * n + (k * n + j) * n + i] = J3 * w[k] * w[j] * w[i];
+        }
+        boundary_coords(O, &h[4 * nd], &h[4 * nd + nb], &h[4 * nd + 2 * nb]);
+        O->qnodes = upload(h);
+    }
+    const int pblocks = (int)((nb + BT - 1) / BT), sblocks = (nsrc + BR - 1) / BR;
+    const long long tiles = (nd + BT - 1) / BT;
+    // node parts: enough work-groups for several per compute unit
+    long long parts = std::max<long long>(1, std::min<long long>(tiles, (4096 + pblocks * sblocks - 1) /
+                                                                            ((long long)pblocks * sblocks)));
+    parts = std::min<long long>(parts, 65535);
+    const int tpp = (int)((tiles + parts - 1) / parts);
+    parts = (tiles + tpp - 1) / tpp;
+    const long long need = parts * nsrc * nb;
+    if (need > O->qpart_cap) {
+        ofree(O->qpart);
+        O->qpart = oalloc<double>(need);
+        O->qpart_cap = need;
+    }
+    const double* q = O->qnodes;
+    hipLaunchKernelGGL(k_oct_bdata, dim3(pblocks, sblocks, (unsigned)parts), dim3(BT), 0, s, nd, (int)nb, nsrc, tpp,
+                       q, q + nd, q + 2 * nd, q + 3 * nd, q + 4 * nd, q + 4 * nd + nb, q + 4 * nd + 2 * nb, f,
+                       O->qpart);
+    hipLaunchKernelGGL(k_oct_bsum, dim3((unsigned)((nsrc * nb + 255) / 256)), dim3(256), 0, s, (int)parts, nsrc,
+                       (int)nb, O->qpart, g);
     OCHK(hipGetLastError());
 }
 
@@ -1680,9 +1804,19 @@ dg_status dg_octree_rhs(dg_octree* o, int nrhs, const double* f, const double* g
     return dg::guarded([&] {
         if (!o || nrhs < 0) throw std::invalid_argument("bad arguments");
         if (nrhs == 0) return;
-        if (!f || !b || (!g && o->nbp > 0)) throw std::invalid_argument("null argument");
+        if (!f || !b) throw std::invalid_argument("null argument");
         (void)hipSetDevice(o->device);
         dg::oct::rhs(o, nrhs, f, g, b, (hipStream_t)stream);
+    });
+}
+
+dg_status dg_octree_boundary_data(dg_octree* o, int nsrc, const double* f, double* g, void* stream) {
+    return dg::guarded([&] {
+        if (!o || nsrc < 0) throw std::invalid_argument("bad arguments");
+        if (nsrc == 0) return;
+        if (!f || (!g && o->nbp > 0)) throw std::invalid_argument("null argument");
+        (void)hipSetDevice(o->device);
+        dg::oct::boundary_data(o, nsrc, f, g, (hipStream_t)stream);
     });
 }
 

@@ -164,6 +164,23 @@ def test_residual_of_a_large_solve_against_the_oracle_operator(gpu_lib):
     assert st[0]["status"] == 0 and rel <= 2e-10 and abs(rel - st[0]["rel_residual"]) <= 1e-12
 
 
+@pytest.mark.parametrize("case", CASES[:3])
+def test_boundary_data_by_quadrature_matches_oracle(gpu_lib, case):
+    """Sec. 6.3's Dirichlet data on the octree grid, and the right-hand side built from them."""
+    g, t = _pair(gpu_lib, case)
+    m = t.mesh()
+    X, Y, Z = m.nodes()
+    f = np.stack([_two_centres(X, Y, Z), np.cos(X) * _gauss(2.0, (0.0, 0.1, 0.0))(X, Y, Z),
+                  _gauss(6.0, (-0.3, 0.2, 0.1))(X, Y, Z)])
+    got = g.boundary_data(_t(f)).cpu().numpy()
+    ref = m.boundary_data(f)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    b = g.rhs(_t(f)).cpu().numpy()              # no data given: by quadrature
+    bref = np.stack([m.rhs(f[k], ref[k]) for k in range(3)])
+    assert np.abs(b - bref).max() <= 1e-12 * np.abs(bref).max()
+
+
 def test_octree_arguments_are_checked(gpu_lib):
     with pytest.raises(gpu_lib.DgError):
         gpu_lib.Octree((9, 1, 1), (0, 0, 0), (1, 1, 1), q=2)          # more than 8 base elements per axis
