@@ -779,8 +779,9 @@ OCTREE_CHEB = (8, 4)
 def main_octree(args):
     """The 36 pair densities of the exchange8 molecule on its adaptive octree mesh (8^3 base
     elements on [-8, 8]^3, q = 4, refined on the electron density with delta_q = 1e-8, at most 3
-    refinements): a step assembles the right-hand sides and solves them by FP64 MG-PCG to 1e-8
-    over the refinement hierarchy."""
+    refinements): a step assembles the right-hand sides and solves them by MG-PCG to an FP64
+    relative residual of 1e-8 over the refinement hierarchy.  Arms: the V-cycle in FP32 under
+    the FP64 CG (fp32_pc, the line's value) and in FP64 (fp64)."""
     import numpy as np
     import torch
 
@@ -789,53 +790,79 @@ def main_octree(args):
 
     wl = configs.octree()
     mesh, orb = wl.meshes[0], wl.orbitals
-    t0 = time.perf_counter()
-    o = binding.Octree(mesh.E, mesh.lo, mesh.hi, q=mesh.p, rho=wl.density, delta_q=wl.delta_q,
-                       max_depth=wl.max_depth, rtol=wl.rtol, max_iter=500, cheb_degree=OCTREE_CHEB[0],
-                       cheb_degree_h=OCTREE_CHEB[1])
-    t_setup = time.perf_counter() - t0
-    log(f"octree: {o.n_elements} elements, {o.n_dofs} nodes, {o.n_levels} levels, set-up {t_setup:.2f} s")
-    xyz = o.nodes()
-    bxyz = o.boundary_points()
-    pairs = orb.pairs()                   # the order of Orbitals.pair_potentials
-    psi = np.asarray(orb.values(xyz[0], xyz[1], xyz[2]))
-    f = torch.as_tensor(np.stack([psi[i] * psi[j] for i, j in pairs])).cuda().contiguous()
-    g = torch.as_tensor(orb.pair_potentials(bxyz[0], bxyz[1], bxyz[2])).cuda().contiguous()
-    nrhs = len(pairs)
+    arms = {}
+    f = g = None
+    for prec in ("fp32_pc", "fp64"):
+        t0 = time.perf_counter()
+        o = binding.Octree(mesh.E, mesh.lo, mesh.hi, q=mesh.p, rho=wl.density, delta_q=wl.delta_q,
+                           max_depth=wl.max_depth, rtol=wl.rtol, max_iter=500, cheb_degree=OCTREE_CHEB[0],
+                           cheb_degree_h=OCTREE_CHEB[1], precision=prec)
+        t_setup = time.perf_counter() - t0
+        log(f"octree {prec}: {o.n_elements} elements, {o.n_dofs} nodes, {o.n_levels} levels, set-up {t_setup:.2f} s")
+        if f is None:
+            xyz = o.nodes()
+            bxyz = o.boundary_points()
+            pairs = orb.pairs()                   # the order of Orbitals.pair_potentials
+            psi = np.asarray(orb.values(xyz[0], xyz[1], xyz[2]))
+            f = torch.as_tensor(np.stack([psi[i] * psi[j] for i, j in pairs])).cuda().contiguous()
+            g = torch.as_tensor(orb.pair_potentials(bxyz[0], bxyz[1], bxyz[2])).cuda().contiguous()
+            nrhs = len(pairs)
 
-    def step():
-        b = o.rhs(f, g)
-        return o.solve(b)
-    for _ in range(args.warmup):
-        x, st = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        x, st = step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    iters = [s["iters"] for s in st]
-    log(f"octree: {dt * 1e3:.1f} ms per step, iterations {min(iters)}..{max(iters)}")
-    # dominant kernel: the finest-level operator (k_oct_op<5, APPLY>), timed on the binding's stream
-    u = torch.randn(nrhs * o.n_dofs, dtype=torch.float64, device="cuda")
-    for _ in range(3):
-        o.apply(u)
+        def step():
+            b = o.rhs(f, g)
+            return o.solve(b)
+        for _ in range(args.warmup):
+            x, st = step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x, st = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        iters = [s["iters"] for s in st]
+        log(f"octree {prec}: {dt * 1e3:.1f} ms per step, iterations {min(iters)}..{max(iters)}")
+        arms[prec] = {"o": o, "x": x, "dt": dt, "iters": iters, "setup_s": t_setup,
+                      "max_rel_residual": max(s["rel_residual"] for s in st)}
+    o = arms["fp64"]["o"]
+    # dominant kernel family of each arm: the finest-level operator (k_oct_op<5, ...>), APPLY form
+    # timed on the binding's stream with HIP events; algorithmic bytes: read u, write y (geometry
+    # and pieces are < 1 %)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 20
-    e0.record()
-    for _ in range(reps):
-        o.apply(u)
-    e1.record()
-    torch.cuda.synchronize()
-    t_op = e0.elapsed_time(e1) / reps * 1e-3
-    algo = 16.0 * o.n_dofs * nrhs        # read u, write y (FP64); geometry and pieces are < 1 %
-    roof = {"kernel": "k_oct_op<5, APPLY> (finest-level operator, 36 RHS)", "bound": "hbm",
-            "achieved": algo / t_op / 1e9, "peak": 8000.0, "unit": "GB/s", "frac": algo / t_op / 8e12,
-            "traffic": None, "us_per_launch": t_op * 1e6, "algorithmic_bytes_per_launch": algo}
-    # accuracy against the closed-form continuum potentials at the nodes (discretisation error)
+
+    def timed(fn, arg):
+        for _ in range(3):
+            fn(arg)
+        e0.record()
+        for _ in range(reps):
+            fn(arg)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+    u = torch.randn(nrhs * o.n_dofs, dtype=torch.float64, device="cuda")
+    t_op64 = timed(o.apply, u)
+    t_op32 = timed(arms["fp32_pc"]["o"].apply_f32, u.float())
+    algo32, algo64 = 8.0 * o.n_dofs * nrhs, 16.0 * o.n_dofs * nrhs
+
+    def roofline(kernel, algo, t):
+        return {"kernel": kernel, "bound": "hbm", "achieved": algo / t / 1e9, "peak": 8000.0, "unit": "GB/s",
+                "frac": algo / t / 8e12, "traffic": None, "us_per_launch": t * 1e6, "algorithmic_bytes_per_launch": algo}
+    roof = roofline("k_oct_op<5, APPLY, float> (finest-level operator of the FP32 V-cycle, 36 RHS)", algo32, t_op32)
+    roof["fp64_arm"] = roofline("k_oct_op<5, APPLY, double> (36 RHS)", algo64, t_op64)
+    # accuracy against the closed-form continuum potentials at the nodes (discretisation error),
+    # and of the FP32-V-cycle arm against the FP64 one
     vall = orb.pair_potentials(xyz[0], xyz[1], xyz[2])
-    xs = x.cpu().numpy().reshape(nrhs, -1)
-    errs = [float(np.linalg.norm(xs[k] - vall[k]) / np.linalg.norm(vall[k])) for k in range(nrhs)]
+    res = {}
+    x64 = arms["fp64"]["x"].cpu().numpy().reshape(nrhs, -1)
+    for prec, A in arms.items():
+        xs = A["x"].cpu().numpy().reshape(nrhs, -1)
+        errs = [float(np.linalg.norm(xs[k] - vall[k]) / np.linalg.norm(vall[k])) for k in range(nrhs)]
+        dev = max(float(np.linalg.norm(xs[k] - x64[k]) / np.linalg.norm(x64[k])) for k in range(nrhs))
+        res[prec] = {"value": nrhs / A["dt"], "ms_per_step": A["dt"] * 1e3,
+                     "iters": {"min": min(A["iters"]), "max": max(A["iters"]), "mean": float(np.mean(A["iters"]))},
+                     "max_rel_residual": A["max_rel_residual"], "setup_s": A["setup_s"],
+                     "rel_L2_err_vs_continuum": {"max": max(errs), "median": float(np.median(errs))},
+                     "max_rel_L2_dev_vs_fp64_arm": dev}
     # Dirichlet data by quadrature of the pair densities (Sec. 6.3) against the closed forms
     gq = o.boundary_data(f)
     torch.cuda.synchronize()
@@ -846,21 +873,20 @@ def main_octree(args):
     t_q = e0.elapsed_time(e1) * 1e-3
     gq_err = float(((gq - g).abs().max() / g.abs().max()).item())
     log(f"octree: quadrature Dirichlet data {t_q * 1e3:.2f} ms, max rel. deviation from closed form {gq_err:.2e}")
-    cpu = cpu_leg_octree(args, wl, pairs, iters) if args.cpu_sample > 0 else None
+    cpu = cpu_leg_octree(args, wl, pairs, arms["fp64"]["iters"]) if args.cpu_sample > 0 else None
+    head = res["fp32_pc"]
     line = {
-        "metric": "Poisson RHS solved/sec on the adaptive octree auxiliary mesh (FP64 MG-PCG to 1e-8)",
-        "value": nrhs / dt, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
+        "metric": "Poisson RHS solved/sec on the adaptive octree auxiliary mesh (MG-PCG to FP64 residual 1e-8)",
+        "value": head["value"], "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE_OF["fp32_pc"], "data": "synthetic",
         "config": {"workload": f"octree: exchange8 molecule, 36 pair densities, {mesh.E[0]}^3 base elements q={mesh.p} "
                                f"refined on the electron density (delta_q {wl.delta_q}, depth {wl.max_depth}): "
                                f"{o.n_elements} elements, {o.n_dofs} nodes, {o.n_levels} levels; Chebyshev "
                                f"steps {OCTREE_CHEB[0]} (degree 4, 2), {OCTREE_CHEB[1]} (degree 1)",
-                   "parallelism": "single GPU"},
-        "iters": {"min": min(iters), "max": max(iters), "mean": float(np.mean(iters))},
-        "max_rel_residual": max(s["rel_residual"] for s in st),
-        "setup_s": t_setup,
-        "rel_L2_err_vs_continuum": {"max": max(errs), "median": float(np.median(errs))},
+                   "arm": "fp32_pc", "parallelism": "single GPU"},
+        "arms": res,
+        "speedup_vs_fp64": head["value"] / res["fp64"]["value"],
         "roofline": roof,
         "quadrature_data": {"ms": t_q * 1e3, "points": o.n_boundary, "sources": nrhs,
                             "max_rel_dev_vs_closed_form": gq_err,

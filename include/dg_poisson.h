@@ -492,7 +492,8 @@ dg_status dg_poisson_attach_guess(dg_ctx* ctx, dg_net* net);
  * (q+1)^2-point GL rule; Nitsche terms carry the Dirichlet data g on the domain boundary.
  * Multigrid: degree steps q -> q/2 -> .. -> 1 on the leaves, then the tree cut at generation
  * G-1, .., 0 at degree 1; exact fast-diagonalisation solve on the base mesh; Chebyshev-Jacobi
- * smoothing with the dg_opts parameters.  FP64 only. */
+ * smoothing with the dg_opts parameters.  Precision DG_PREC_FP64, or DG_PREC_FP32_PC: the
+ * V-cycle in FP32 preconditioning the FP64 CG (residuals, iterates and stopping test in FP64). */
 typedef struct dg_octree dg_octree;
 
 /* The density: out[i] = rho(x[i], y[i], z[i]) for i < n (host arrays).  Called on the host
@@ -511,7 +512,7 @@ typedef struct {
 } dg_octree_desc;
 
 /* Build the mesh (rho may be NULL: no refinement), its levels and smoother bounds on the current
- * device.  opts NULL: dg_opts_default; precision must be DG_PREC_FP64.  DG_ERR_ARG on bad sizes,
+ * device.  opts NULL: dg_opts_default; precision DG_PREC_FP64 or DG_PREC_FP32_PC.  DG_ERR_ARG on bad sizes,
  * options, a density that is not finite, or more than max_elements elements. */
 dg_status dg_octree_create(const dg_octree_desc* desc, dg_density_fn rho, void* user, const dg_opts* opts,
                            dg_octree** out);
@@ -543,7 +544,10 @@ dg_status dg_octree_rhs(dg_octree* octree, int nrhs, const double* f, const doub
 dg_status dg_octree_boundary_data(dg_octree* octree, int nsrc, const double* f, double* g, void* stream);
 /* y = A u on multigrid level `level` (device arrays [nrhs][level nodes]). */
 dg_status dg_octree_apply(dg_octree* octree, int level, int nrhs, const double* u, double* y, void* stream);
-/* z = V r, one V-cycle of the preconditioner on the finest level (device arrays). */
+/* y = A u on a level in FP32 arithmetic, the operator of the FP32 V-cycle (device float arrays
+ * [nrhs][level nodes]). */
+dg_status dg_octree_apply_f32(dg_octree* octree, int level, int nrhs, const float* u, float* y, void* stream);
+/* z = V r, one FP64 V-cycle of the preconditioner on the finest level (device arrays). */
 dg_status dg_octree_vcycle(dg_octree* octree, int nrhs, const double* r, double* z, void* stream);
 /* Tuning: right-hand sides per work-group of the octree operator kernels (1, 2 or 4; 0, the
  * default: 4 at degree 4 and 2 below, the fastest measured on MI355X):

@@ -128,6 +128,7 @@ def _load():
         "dg_octree_solve": (I, [P, I, P, P, P, P]),
         "dg_octree_set_rhs_per_block": (I, [P, I]),
         "dg_octree_boundary_data": (I, [P, I, P, P, P]),
+        "dg_octree_apply_f32": (I, [P, I, I, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -551,6 +552,14 @@ class Octree:
         n = self.level_info(level)["n_dofs"]
         y = torch.empty_like(u)
         _check(lib.dg_octree_apply(self._h, level, u.numel() // n, _ptr(u), _ptr(y), _stream()), "octree_apply")
+        return y
+
+    def apply_f32(self, u, level=0):
+        """FP32 operator (float32 CUDA tensor)."""
+        n = self.level_info(level)["n_dofs"]
+        y = torch.empty_like(u)
+        _check(lib.dg_octree_apply_f32(self._h, level, u.numel() // n, _ptr_t(u, torch.float32),
+                                       _ptr_t(y, torch.float32), _stream()), "octree_apply_f32")
         return y
 
     def vcycle(self, r):

@@ -22,7 +22,8 @@
 // Multigrid.  Degree steps on the leaves, then mesh steps (the tree cut at generation g, g =
 // G-1 .. 0) at degree 1; the coarsest level is the uniform base mesh at degree 1, solved by
 // fast diagonalisation.  Chebyshev-Jacobi smoothing with the uniform mesh's parameters; the
-// Chebyshev step is fused into the operator kernel's epilogue.
+// Chebyshev step is fused into the operator kernel's epilogue.  The V-cycle runs in FP64, or
+// in FP32 under the FP64 CG (DG_PREC_FP32_PC): the kernels are templated on the field type.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,12 +54,12 @@ struct Piece {
     double ijn;    // 1 / (the neighbour's half-width along the normal), 0 on the boundary
 };
 
-template <int N>
+template <int N, typename T = double>
 struct Ref {
-    double K1[N][N];          // D^T diag(w) D on [-1, 1]
-    double w[N];
-    double eL[N], eR[N];      // basis values at -1 and +1
-    double dL[N], dR[N];      // basis derivatives there (reference coordinate)
+    T K1[N][N];          // D^T diag(w) D on [-1, 1]
+    T w[N];
+    T eL[N], eR[N];      // basis values at -1 and +1
+    T dL[N], dR[N];      // basis derivatives there (reference coordinate)
 };
 
 enum { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2 };
@@ -76,23 +77,22 @@ enum { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2 };
 // stored consecutively) are taken N at a time, N^2 threads per piece: traces of both sides, the
 // two interpolation passes to the piece's points, the flux, the two transposed passes back onto
 // the element's face nodes; then every node thread adds what the pass's pieces give its own row.
-template <int N, int MODE, int RB>
-__global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, const double* __restrict__ J,
+template <int N, int MODE, int RB, typename T>
+__global__ __launch_bounds__(OT) void k_oct_op(Ref<N, double> Rarg, int ne, int nrhs, const double* __restrict__ J,
                                               const int* __restrict__ fstart, const Piece* __restrict__ pcs,
-                                              const double* __restrict__ tab, const RhsState* __restrict__ st,
-                                              const double* __restrict__ u, double* __restrict__ y,
-                                              const double* __restrict__ f, double* __restrict__ r,
-                                              double* __restrict__ z, const double* __restrict__ dinv, double c1,
-                                              double c2) {
+                                              const T* __restrict__ tab, const RhsState* __restrict__ st,
+                                              const T* __restrict__ u, T* __restrict__ y,
+                                              const T* __restrict__ f, T* __restrict__ r,
+                                              T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2) {
     constexpr int N2 = N * N, N3 = N * N * N, EPB = OT / N3;
-    __shared__ double U[RB][EPB][N3];
+    __shared__ T U[RB][EPB][N3];
     // per right-hand side and slot, per piece of the pass (N pieces of N^2 points): own /
     // neighbour trace and normal derivative, the interpolation scratch, the flux, and the result
     // on the face nodes
-    __shared__ double A0[RB][EPB][N3], A1[RB][EPB][N3], A2[RB][EPB][N3], A3[RB][EPB][N3];
-    __shared__ double B0[RB][EPB][N3], B1[RB][EPB][N3], B2[RB][EPB][N3], B3[RB][EPB][N3];
+    __shared__ T A0[RB][EPB][N3], A1[RB][EPB][N3], A2[RB][EPB][N3], A3[RB][EPB][N3];
+    __shared__ T B0[RB][EPB][N3], B1[RB][EPB][N3], B2[RB][EPB][N3], B3[RB][EPB][N3];
     __shared__ int npc[EPB], ncc[EPB];
-    __shared__ Ref<N> R;  // the reference data, indexed at run time (from LDS, not the argument block)
+    __shared__ Ref<N, T> R;  // the reference data, indexed at run time (from LDS, not the argument block)
     const int rhs0 = blockIdx.y * RB;
     bool live[RB];
     bool any = false;
@@ -106,8 +106,8 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
     const int e = blockIdx.x * EPB + s;
     {
         const double* src = reinterpret_cast<const double*>(&Rarg);
-        double* dst = reinterpret_cast<double*>(&R);
-        for (int q = t; q < (int)(sizeof(Ref<N>) / sizeof(double)); q += OT) dst[q] = src[q];
+        T* dst = reinterpret_cast<T*>(&R);
+        for (int q = t; q < (int)(sizeof(Ref<N, double>) / sizeof(double)); q += OT) dst[q] = (T)src[q];
     }
     const bool node = s < EPB && e < ne;
     const long long estride = (long long)ne * N3;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
     if (node) {
 #pragma unroll
         for (int q = 0; q < RB; ++q)
-            U[q][s][l] = live[q] ? u[(long long)(rhs0 + q) * estride + (long long)e * N3 + l] : 0.0;
+            U[q][s][l] = live[q] ? u[(long long)(rhs0 + q) * estride + (long long)e * N3 + l] : T(0);
     }
     int p0 = 0, nconf = 0, np = 0;
     if (node) {
@@ -130,19 +130,19 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
     }
     if (!node && l == 0 && s < EPB) npc[s] = ncc[s] = 0;
     __syncthreads();
-    double acc[RB];
-    double Jx = 1.0, Jy = 1.0, Jz = 1.0;
+    T acc[RB];
+    T Jx = T(1), Jy = T(1), Jz = T(1);
 #pragma unroll
-    for (int q = 0; q < RB; ++q) acc[q] = 0.0;
+    for (int q = 0; q < RB; ++q) acc[q] = T(0);
     if (node) {
-        Jx = J[3 * e];
-        Jy = J[3 * e + 1];
-        Jz = J[3 * e + 2];
-        const double sx = Jy * Jz / Jx * R.w[j] * R.w[k], sy = Jx * Jz / Jy * R.w[i] * R.w[k],
+        Jx = (T)J[3 * e];
+        Jy = (T)J[3 * e + 1];
+        Jz = (T)J[3 * e + 2];
+        const T sx = Jy * Jz / Jx * R.w[j] * R.w[k], sy = Jx * Jz / Jy * R.w[i] * R.w[k],
                      sz = Jx * Jy / Jz * R.w[i] * R.w[j];
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
-            double ax = 0.0, ay = 0.0, az = 0.0;
+            T ax = T(0), ay = T(0), az = T(0);
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 ax += R.K1[i][a] * U[q][s][(k * N + j) * N + a];
@@ -167,8 +167,8 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
         const int m = dq == 0 ? i : (dq == 1 ? j : k);                                                    \
         const int a = dq == 0 ? j : i;                                                                    \
         const int b = dq == 2 ? j : k;                                                                    \
-        const double vm = (fq & 1) ? R.eR[m] : R.eL[m];                                                   \
-        const double dm = ((fq & 1) ? R.dR[m] : -R.dL[m]) / (dq == 0 ? Jx : (dq == 1 ? Jy : Jz));         \
+        const T vm = (fq & 1) ? R.eR[m] : R.eL[m];                                                   \
+        const T dm = ((fq & 1) ? R.dR[m] : -R.dL[m]) / (dq == 0 ? Jx : (dq == 1 ? Jy : Jz));         \
         _Pragma("unroll") for (int c = 0; c < RB; ++c) acc[c] +=                                          \
             vm * A2[c][s][q * N2 + b * N + a] + dm * A3[c][s][q * N2 + b * N + a];                        \
     }
@@ -184,39 +184,39 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
             const int s1 = d == 0 ? N : 1;
             const int s2 = d == 2 ? N : N2;
             const int a = fl % N, b = fl / N;
-            const double* vS = (fc & 1) ? R.eR : R.eL;
-            const double* dS = (fc & 1) ? R.dR : R.dL;
-            const double* vO = (fc & 1) ? R.eL : R.eR;
-            const double* dO = (fc & 1) ? R.dL : R.dR;
-            const double iJ = 1.0 / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
-            const double iJn = P.ijn;
-            const double sg = (fc & 1) ? 1.0 : -1.0;
-            const double half = inner ? 0.5 : 1.0;
-            const double W = R.w[a] * R.w[b] * P.wsc;
+            const T* vS = (fc & 1) ? R.eR : R.eL;
+            const T* dS = (fc & 1) ? R.dR : R.dL;
+            const T* vO = (fc & 1) ? R.eL : R.eR;
+            const T* dO = (fc & 1) ? R.dL : R.dR;
+            const T iJ = T(1) / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
+            const T iJn = (T)P.ijn;
+            const T sg = (fc & 1) ? T(1) : -T(1);
+            const T half = inner ? T(0.5) : T(1);
+            const T W = R.w[a] * R.w[b] * (T)P.wsc;
             const int lo = a * s1 + b * s2;
 #pragma unroll
             for (int c = 0; c < RB; ++c) {
-                double tv = 0.0, dv = 0.0, tn = 0.0, dn = 0.0;
+                T tv = T(0), dv = T(0), tn = T(0), dn = T(0);
 #pragma unroll
                 for (int m = 0; m < N; ++m) {
-                    const double x = U[c][s][m * sd + lo];
+                    const T x = U[c][s][m * sd + lo];
                     tv += vS[m] * x;
                     dv += dS[m] * x;
                 }
                 if (inner && live[c]) {
-                    const double* un = u + (long long)(rhs0 + c) * estride + (long long)P.nb * N3;
+                    const T* un = u + (long long)(rhs0 + c) * estride + (long long)P.nb * N3;
 #pragma unroll
                     for (int m = 0; m < N; ++m) {
-                        const double x = un[m * sd + lo];
+                        const T x = un[m * sd + lo];
                         tn += vO[m] * x;
                         dn += dO[m] * x;
                     }
                 }
                 dv *= iJ;
                 dn *= iJn;
-                const double jmp = inner ? tv - tn : tv;
-                const double davg = inner ? 0.5 * (dv + dn) : dv;
-                A2[c][s][o + fl] = W * (P.sig * jmp - sg * davg);
+                const T jmp = inner ? tv - tn : tv;
+                const T davg = inner ? T(0.5) * (dv + dn) : dv;
+                A2[c][s][o + fl] = W * ((T)P.sig * jmp - sg * davg);
                 A3[c][s][o + fl] = W * (-half * jmp);
             }
         }
@@ -244,26 +244,26 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
             const int s2 = d == 2 ? N : N2;
             const int a = fl % N, b = fl / N;
             const int lo = a * s1 + b * s2;
-            const double* vS = (fc & 1) ? R.eR : R.eL;
-            const double* dS = (fc & 1) ? R.dR : R.dL;
-            const double* vO = (fc & 1) ? R.eL : R.eR;
-            const double* dO = (fc & 1) ? R.dL : R.dR;
-            const double iJ = 1.0 / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
-            const double iJn = P.ijn;
+            const T* vS = (fc & 1) ? R.eR : R.eL;
+            const T* dS = (fc & 1) ? R.dR : R.dL;
+            const T* vO = (fc & 1) ? R.eL : R.eR;
+            const T* dO = (fc & 1) ? R.dL : R.dR;
+            const T iJ = T(1) / (d == 0 ? Jx : (d == 1 ? Jy : Jz));
+            const T iJn = (T)P.ijn;
 #pragma unroll
             for (int c = 0; c < RB; ++c) {
-                double tv = 0.0, dv = 0.0, tn = 0.0, dn = 0.0;
+                T tv = T(0), dv = T(0), tn = T(0), dn = T(0);
 #pragma unroll
                 for (int m = 0; m < N; ++m) {
-                    const double x = U[c][s][m * sd + lo];
+                    const T x = U[c][s][m * sd + lo];
                     tv += vS[m] * x;
                     dv += dS[m] * x;
                 }
                 if (inner && live[c]) {
-                    const double* un = u + (long long)(rhs0 + c) * estride + (long long)P.nb * N3;
+                    const T* un = u + (long long)(rhs0 + c) * estride + (long long)P.nb * N3;
 #pragma unroll
                     for (int m = 0; m < N; ++m) {
-                        const double x = un[m * sd + lo];
+                        const T x = un[m * sd + lo];
                         tn += vO[m] * x;
                         dn += dO[m] * x;
                     }
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
         // interpolation along t1: X[b][q1] = sum_a I1[q1][a] F[b][a]
         if (act) {
             const int q1 = fl % N, b = fl / N;
-            double Is[N], In[N];
+            T Is[N], In[N];
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 Is[a] = tab[(long long)P.s1 * N2 + q1 * N + a];
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
             }
 #pragma unroll
             for (int c = 0; c < RB; ++c) {
-                double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+                T x0 = T(0), x1 = T(0), x2 = T(0), x3 = T(0);
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
                     x0 += Is[a] * A0[c][s][o + b * N + a];
@@ -305,18 +305,18 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
         // normal sg e_d): [u] = u - u_nb, {d_n u} = sg {du/dx_d}
         if (act) {
             const int q1 = fl % N, q2 = fl / N;
-            double Is[N], In[N];
+            T Is[N], In[N];
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 Is[b] = tab[(long long)P.s2 * N2 + q2 * N + b];
                 In[b] = tab[(long long)P.n2 * N2 + q2 * N + b];
             }
-            const double sg = (fc & 1) ? 1.0 : -1.0;
-            const double half = inner ? 0.5 : 1.0;
-            const double W = R.w[q1] * R.w[q2] * P.wsc;
+            const T sg = (fc & 1) ? T(1) : -T(1);
+            const T half = inner ? T(0.5) : T(1);
+            const T W = R.w[q1] * R.w[q2] * (T)P.wsc;
 #pragma unroll
             for (int c = 0; c < RB; ++c) {
-                double tr = 0.0, dr = 0.0, trn = 0.0, drn = 0.0;
+                T tr = T(0), dr = T(0), trn = T(0), drn = T(0);
 #pragma unroll
                 for (int b = 0; b < N; ++b) {
                     tr += Is[b] * B0[c][s][o + b * N + q1];
@@ -324,9 +324,9 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
                     trn += In[b] * B2[c][s][o + b * N + q1];
                     drn += In[b] * B3[c][s][o + b * N + q1];
                 }
-                const double jmp = inner ? tr - trn : tr;
-                const double davg = inner ? 0.5 * (dr + drn) : dr;
-                A0[c][s][o + fl] = W * (P.sig * jmp - sg * davg);
+                const T jmp = inner ? tr - trn : tr;
+                const T davg = inner ? T(0.5) * (dr + drn) : dr;
+                A0[c][s][o + fl] = W * ((T)P.sig * jmp - sg * davg);
                 A1[c][s][o + fl] = W * (-half * jmp);
             }
         }
@@ -334,12 +334,12 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
         // back onto the face nodes: transpose along t2 ...
         if (act) {
             const int q1 = fl % N, b = fl / N;
-            double I2[N];
+            T I2[N];
 #pragma unroll
             for (int q2 = 0; q2 < N; ++q2) I2[q2] = tab[(long long)P.s2 * N2 + q2 * N + b];
 #pragma unroll
             for (int c = 0; c < RB; ++c) {
-                double y0 = 0.0, y1 = 0.0;
+                T y0 = T(0), y1 = T(0);
 #pragma unroll
                 for (int q2 = 0; q2 < N; ++q2) {
                     y0 += I2[q2] * A0[c][s][o + q2 * N + q1];
@@ -353,12 +353,12 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
         // ... and along t1
         if (act) {
             const int a = fl % N, b = fl / N;
-            double I1[N];
+            T I1[N];
 #pragma unroll
             for (int q1 = 0; q1 < N; ++q1) I1[q1] = tab[(long long)P.s1 * N2 + q1 * N + a];
 #pragma unroll
             for (int c = 0; c < RB; ++c) {
-                double y0 = 0.0, y1 = 0.0;
+                T y0 = T(0), y1 = T(0);
 #pragma unroll
                 for (int q1 = 0; q1 < N; ++q1) {
                     y0 += I1[q1] * B0[c][s][o + b * N + q1];
@@ -382,9 +382,9 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
         } else if constexpr (MODE == OP_RESID) {
             y[g] = f[g] - acc[c];
         } else {
-            const double dv = U[c][s][l];
+            const T dv = U[c][s][l];
             z[g] += dv;
-            const double rn = r[g] - acc[c];
+            const T rn = r[g] - acc[c];
             r[g] = rn;
             y[g] = c1 * dv + c2 * dinv[(long long)e * N3 + l] * rn;
         }
@@ -396,25 +396,27 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N> Rarg, int ne, int nrhs, co
 inline dim3 node_grid(long long ndof, int nrhs) { return dim3((unsigned)((ndof + 255) / 256), (unsigned)nrhs); }
 
 // r = f, z = 0, d = c0 D^-1 f (smoothing from a zero start)
+template <typename T>
 __global__ __launch_bounds__(256) void k_oct_start0(long long ndof, const RhsState* __restrict__ st,
-                                                    const double* __restrict__ f, double* __restrict__ r,
-                                                    double* __restrict__ z, double* __restrict__ d,
-                                                    const double* __restrict__ dinv, double c0) {
+                                                    const T* __restrict__ f, T* __restrict__ r,
+                                                    T* __restrict__ z, T* __restrict__ d,
+                                                    const T* __restrict__ dinv, T c0) {
     const int rhs = blockIdx.y;
     if (st && !st[rhs].active) return;
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     if (q >= ndof) return;
     const long long g = (long long)rhs * ndof + q;
-    const double fv = f[g];
+    const T fv = f[g];
     r[g] = fv;
-    z[g] = 0.0;
+    z[g] = T(0);
     d[g] = c0 * dinv[q] * fv;
 }
 
 // d = c0 D^-1 r
+template <typename T>
 __global__ __launch_bounds__(256) void k_oct_dstart(long long ndof, const RhsState* __restrict__ st,
-                                                    const double* __restrict__ r, double* __restrict__ d,
-                                                    const double* __restrict__ dinv, double c0) {
+                                                    const T* __restrict__ r, T* __restrict__ d,
+                                                    const T* __restrict__ dinv, T c0) {
     const int rhs = blockIdx.y;
     if (st && !st[rhs].active) return;
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -424,14 +426,31 @@ __global__ __launch_bounds__(256) void k_oct_dstart(long long ndof, const RhsSta
 }
 
 // z += d
+template <typename T>
 __global__ __launch_bounds__(256) void k_oct_add(long long ndof, const RhsState* __restrict__ st,
-                                                 const double* __restrict__ d, double* __restrict__ z) {
+                                                 const T* __restrict__ d, T* __restrict__ z) {
     const int rhs = blockIdx.y;
     if (st && !st[rhs].active) return;
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     if (q >= ndof) return;
     const long long g = (long long)rhs * ndof + q;
     z[g] += d[g];
+}
+
+// FP32 V-cycle under FP64 CG: the residual narrowed to FP32, the correction widened to FP64
+__global__ __launch_bounds__(256) void k_oct_narrow(long long n, const RhsState* __restrict__ st, long long ndof,
+                                                    const double* __restrict__ a, float* __restrict__ b) {
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    if (st && !st[q / ndof].active) return;
+    b[q] = (float)a[q];
+}
+__global__ __launch_bounds__(256) void k_oct_widen(long long n, const RhsState* __restrict__ st, long long ndof,
+                                                   const float* __restrict__ a, double* __restrict__ b) {
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    if (st && !st[q / ndof].active) return;
+    b[q] = (double)a[q];
 }
 
 // PCG: p = z + beta p
@@ -468,15 +487,15 @@ __global__ __launch_bounds__(256) void k_oct_dscale(long long ndof, const double
 }
 
 // Degree transfers on the same elements: I[f][c] = coarse basis c at fine node f.
-template <int NF, int NC>
+template <int NF, int NC, typename T>
 struct DegI {
-    double I[NF][NC];
+    T I[NF][NC];
 };
 
 // rc = P^T rf, one thread per coarse node
-template <int NF, int NC>
-__global__ __launch_bounds__(256) void k_oct_restrict_deg(DegI<NF, NC> T, int ne, const RhsState* __restrict__ st,
-                                                          const double* __restrict__ rf, double* __restrict__ rc) {
+template <int NF, int NC, typename T>
+__global__ __launch_bounds__(256) void k_oct_restrict_deg(DegI<NF, NC, T> Tm, int ne, const RhsState* __restrict__ st,
+                                                          const T* __restrict__ rf, T* __restrict__ rc) {
     constexpr int F3 = NF * NF * NF, C3 = NC * NC * NC;
     const int rhs = blockIdx.y;
     if (st && !st[rhs].active) return;
@@ -485,25 +504,25 @@ __global__ __launch_bounds__(256) void k_oct_restrict_deg(DegI<NF, NC> T, int ne
     const long long e = q / C3;
     const int l = (int)(q - e * C3);
     const int a = l % NC, b = (l / NC) % NC, c = l / (NC * NC);
-    const double* src = rf + ((long long)rhs * ne + e) * F3;
-    double acc = 0.0;
+    const T* src = rf + ((long long)rhs * ne + e) * F3;
+    T acc = T(0);
     for (int kk = 0; kk < NF; ++kk) {
-        double ay = 0.0;
+        T ay = T(0);
         for (int jj = 0; jj < NF; ++jj) {
-            double ax = 0.0;
+            T ax = T(0);
 #pragma unroll
-            for (int ii = 0; ii < NF; ++ii) ax += T.I[ii][a] * src[(kk * NF + jj) * NF + ii];
-            ay += T.I[jj][b] * ax;
+            for (int ii = 0; ii < NF; ++ii) ax += Tm.I[ii][a] * src[(kk * NF + jj) * NF + ii];
+            ay += Tm.I[jj][b] * ax;
         }
-        acc += T.I[kk][c] * ay;
+        acc += Tm.I[kk][c] * ay;
     }
     rc[(long long)rhs * ne * C3 + q] = acc;
 }
 
 // zf += P zc, one thread per fine node
-template <int NF, int NC>
-__global__ __launch_bounds__(256) void k_oct_prolong_deg(DegI<NF, NC> T, int ne, const RhsState* __restrict__ st,
-                                                         const double* __restrict__ zc, double* __restrict__ zf) {
+template <int NF, int NC, typename T>
+__global__ __launch_bounds__(256) void k_oct_prolong_deg(DegI<NF, NC, T> Tm, int ne, const RhsState* __restrict__ st,
+                                                         const T* __restrict__ zc, T* __restrict__ zf) {
     constexpr int F3 = NF * NF * NF, C3 = NC * NC * NC;
     const int rhs = blockIdx.y;
     if (st && !st[rhs].active) return;
@@ -512,38 +531,39 @@ __global__ __launch_bounds__(256) void k_oct_prolong_deg(DegI<NF, NC> T, int ne,
     const long long e = q / F3;
     const int l = (int)(q - e * F3);
     const int ii = l % NF, jj = (l / NF) % NF, kk = l / (NF * NF);
-    const double* src = zc + ((long long)rhs * ne + e) * C3;
-    double acc = 0.0;
+    const T* src = zc + ((long long)rhs * ne + e) * C3;
+    T acc = T(0);
     for (int c = 0; c < NC; ++c) {
-        double ay = 0.0;
+        T ay = T(0);
         for (int b = 0; b < NC; ++b) {
-            double ax = 0.0;
+            T ax = T(0);
 #pragma unroll
-            for (int a = 0; a < NC; ++a) ax += T.I[ii][a] * src[(c * NC + b) * NC + a];
-            ay += T.I[jj][b] * ax;
+            for (int a = 0; a < NC; ++a) ax += Tm.I[ii][a] * src[(c * NC + b) * NC + a];
+            ay += Tm.I[jj][b] * ax;
         }
-        acc += T.I[kk][c] * ay;
+        acc += Tm.I[kk][c] * ay;
     }
     zf[(long long)rhs * ne * F3 + q] += acc;
 }
 
 // Mesh transfers at degree 1 (2 x 2 x 2 nodes).  Fine element e: parent element par[e] of the
 // coarser mesh and per axis a table entry m[3e + d] (0 same extent, 1 lower half, 2 upper half).
+template <typename T>
 __global__ __launch_bounds__(256) void k_oct_prolong_mesh(int nef, int nec, const int* __restrict__ par,
-                                                          const int* __restrict__ m, const double* __restrict__ tab,
+                                                          const int* __restrict__ m, const T* __restrict__ tab,
                                                           const RhsState* __restrict__ st,
-                                                          const double* __restrict__ zc, double* __restrict__ zf) {
+                                                          const T* __restrict__ zc, T* __restrict__ zf) {
     const int rhs = blockIdx.y;
     if (st && !st[rhs].active) return;
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     if (q >= (long long)nef * 8) return;
     const int e = (int)(q >> 3), l = (int)(q & 7);
     const int ii = l & 1, jj = (l >> 1) & 1, kk = l >> 2;
-    const double* Tx = tab + m[3 * e] * 4 + ii * 2;
-    const double* Ty = tab + m[3 * e + 1] * 4 + jj * 2;
-    const double* Tz = tab + m[3 * e + 2] * 4 + kk * 2;
-    const double* src = zc + ((long long)rhs * nec + par[e]) * 8;
-    double acc = 0.0;
+    const T* Tx = tab + m[3 * e] * 4 + ii * 2;
+    const T* Ty = tab + m[3 * e + 1] * 4 + jj * 2;
+    const T* Tz = tab + m[3 * e + 2] * 4 + kk * 2;
+    const T* src = zc + ((long long)rhs * nec + par[e]) * 8;
+    T acc = T(0);
     for (int c = 0; c < 2; ++c)
         for (int b = 0; b < 2; ++b)
             for (int a = 0; a < 2; ++a) acc += Tz[c] * Ty[b] * Tx[a] * src[(c * 2 + b) * 2 + a];
@@ -551,24 +571,25 @@ __global__ __launch_bounds__(256) void k_oct_prolong_mesh(int nef, int nec, cons
 }
 
 // rc = P^T rf: coarse element c gathers its fine elements kids[kstart[c] .. kstart[c+1])
+template <typename T>
 __global__ __launch_bounds__(256) void k_oct_restrict_mesh(int nef, int nec, const int* __restrict__ kstart,
                                                            const int* __restrict__ kids, const int* __restrict__ m,
-                                                           const double* __restrict__ tab,
+                                                           const T* __restrict__ tab,
                                                            const RhsState* __restrict__ st,
-                                                           const double* __restrict__ rf, double* __restrict__ rc) {
+                                                           const T* __restrict__ rf, T* __restrict__ rc) {
     const int rhs = blockIdx.y;
     if (st && !st[rhs].active) return;
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     if (q >= (long long)nec * 8) return;
     const int c = (int)(q >> 3), l = (int)(q & 7);
     const int a = l & 1, b = (l >> 1) & 1, cc = l >> 2;
-    double acc = 0.0;
+    T acc = T(0);
     for (int t = kstart[c]; t < kstart[c + 1]; ++t) {
         const int e = kids[t];
-        const double* Tx = tab + m[3 * e] * 4;
-        const double* Ty = tab + m[3 * e + 1] * 4;
-        const double* Tz = tab + m[3 * e + 2] * 4;
-        const double* src = rf + ((long long)rhs * nef + e) * 8;
+        const T* Tx = tab + m[3 * e] * 4;
+        const T* Ty = tab + m[3 * e + 1] * 4;
+        const T* Tz = tab + m[3 * e + 2] * 4;
+        const T* src = rf + ((long long)rhs * nef + e) * 8;
         for (int kk = 0; kk < 2; ++kk)
             for (int jj = 0; jj < 2; ++jj)
                 for (int ii = 0; ii < 2; ++ii)
@@ -700,6 +721,7 @@ struct Level {
     int* fstart = nullptr;
     Piece* pcs = nullptr;
     double* dinv = nullptr;
+    float* dinv32 = nullptr;
     // transfer to the next coarser level
     int kind = 0;                         // 1 degree step, 2 mesh step
     std::vector<double> Ideg;             // n_f x n_c
@@ -728,6 +750,9 @@ struct dg_octree {
     std::vector<dg::oct::Level> lv;       // finest first; the last is the base mesh at degree 1
     std::vector<double> xi[9], wgl[9];    // GL nodes and weights per point count
     double* tab[9] = {};                  // interpolation tables per point count (device)
+    float* tab32[9] = {};                 // the same in FP32
+    bool fp32 = false;                    // FP32 V-cycle under FP64 CG (DG_PREC_FP32_PC)
+    float *r32 = nullptr, *z32 = nullptr; // its finest-level input and output
     std::vector<double> tabh[9];
     int* bstart = nullptr;                // finest level: boundary offsets
     double* qnodes = nullptr;             // quadrature data: node x, y, z, weight (4 x n_dofs), then the
@@ -1093,6 +1118,8 @@ void build_level(dg_octree& O, Level& L, bool finest) {
     L.fstart = upload(L.fsh);
     L.pcs = upload(L.ph);
     L.dinv = upload(dinv);
+    std::vector<float> dinv32(dinv.begin(), dinv.end());
+    L.dinv32 = upload(dinv32);
 }
 
 template <int N>
@@ -1119,84 +1146,99 @@ Ref<N> make_ref(int q) {
     return R;
 }
 
-template <int N, int RB>
-void op_launch_nb(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const double* u,
-                  double* y, const double* f, double* r, double* z, double c1, double c2, hipStream_t s) {
+// the level's tables in the field type
+template <typename T>
+const T* tab_of(const dg_octree& O, int n);
+template <>
+const double* tab_of<double>(const dg_octree& O, int n) { return O.tab[n]; }
+template <>
+const float* tab_of<float>(const dg_octree& O, int n) { return O.tab32[n]; }
+template <typename T>
+const T* dinv_of(const Level& L);
+template <>
+const double* dinv_of<double>(const Level& L) { return L.dinv; }
+template <>
+const float* dinv_of<float>(const Level& L) { return L.dinv32; }
+
+template <int N, int RB, typename T>
+void op_launch_nb(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const T* u, T* y,
+                  const T* f, T* r, T* z, double c1, double c2, hipStream_t s) {
     constexpr int EPB = OT / (N * N * N);
     static const Ref<N> R = make_ref<N>(N - 1);
     dim3 grid((L.ne + EPB - 1) / EPB, (nrhs + RB - 1) / RB);
-    const double* tab = O.tab[N];
+    const T* tab = tab_of<T>(O, N);
+    const T* dinv = dinv_of<T>(L);
     if (mode == OP_APPLY)
-        hipLaunchKernelGGL((k_oct_op<N, OP_APPLY, RB>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs, tab,
-                           st, u, y, f, r, z, L.dinv, c1, c2);
+        hipLaunchKernelGGL((k_oct_op<N, OP_APPLY, RB, T>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs,
+                           tab, st, u, y, f, r, z, dinv, (T)c1, (T)c2);
     else if (mode == OP_RESID)
-        hipLaunchKernelGGL((k_oct_op<N, OP_RESID, RB>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs, tab,
-                           st, u, y, f, r, z, L.dinv, c1, c2);
+        hipLaunchKernelGGL((k_oct_op<N, OP_RESID, RB, T>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs,
+                           tab, st, u, y, f, r, z, dinv, (T)c1, (T)c2);
     else
-        hipLaunchKernelGGL((k_oct_op<N, OP_CHEB, RB>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs, tab,
-                           st, u, y, f, r, z, L.dinv, c1, c2);
+        hipLaunchKernelGGL((k_oct_op<N, OP_CHEB, RB, T>), grid, dim3(OT), 0, s, R, L.ne, nrhs, L.J, L.fstart, L.pcs,
+                           tab, st, u, y, f, r, z, dinv, (T)c1, (T)c2);
 }
 
 // right-hand sides per work-group: several share the element's geometry, pieces and tables and
 // give each thread independent work between the barriers
-template <int N>
-void op_launch_n(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const double* u,
-                 double* y, const double* f, double* r, double* z, double c1, double c2, hipStream_t s) {
+template <int N, typename T>
+void op_launch_n(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const T* u, T* y,
+                 const T* f, T* r, T* z, double c1, double c2, hipStream_t s) {
     const int rb = O.rhs_per_block > 0 ? O.rhs_per_block : (N == 5 ? 4 : 2);  // 0: by degree (measured)
     if (rb >= 4 && nrhs >= 4)
-        op_launch_nb<N, 4>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
+        op_launch_nb<N, 4, T>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
     else if (rb >= 2 && nrhs >= 2)
-        op_launch_nb<N, 2>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
+        op_launch_nb<N, 2, T>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
     else
-        op_launch_nb<N, 1>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
+        op_launch_nb<N, 1, T>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s);
 }
 
-void op_launch(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const double* u, double* y,
-               const double* f, double* r, double* z, double c1, double c2, hipStream_t s) {
+template <typename T>
+void op_launch(const dg_octree& O, const Level& L, int mode, int nrhs, const RhsState* st, const T* u, T* y,
+               const T* f, T* r, T* z, double c1, double c2, hipStream_t s) {
     if (nrhs == 0 || L.ne == 0) return;
     switch (L.n) {
-        case 2: op_launch_n<2>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s); break;
-        case 3: op_launch_n<3>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s); break;
-        case 4: op_launch_n<4>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s); break;
-        case 5: op_launch_n<5>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s); break;
+        case 2: op_launch_n<2, T>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s); break;
+        case 3: op_launch_n<3, T>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s); break;
+        case 4: op_launch_n<4, T>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s); break;
+        case 5: op_launch_n<5, T>(O, L, mode, nrhs, st, u, y, f, r, z, c1, c2, s); break;
         default: throw std::invalid_argument("octree operator: degree 1 to 4");
     }
 }
 
-template <int NF, int NC>
-void deg_transfer(const Level& F, bool restrict_, int nrhs, const RhsState* st, const double* a, double* b,
-                  hipStream_t s) {
-    DegI<NF, NC> T;
+template <int NF, int NC, typename T>
+void deg_transfer(const Level& F, bool restrict_, int nrhs, const RhsState* st, const T* a, T* b, hipStream_t s) {
+    DegI<NF, NC, T> Tm;
     for (int f = 0; f < NF; ++f)
-        for (int c = 0; c < NC; ++c) T.I[f][c] = F.Ideg[f * NC + c];
+        for (int c = 0; c < NC; ++c) Tm.I[f][c] = (T)F.Ideg[f * NC + c];
     if (restrict_)
-        hipLaunchKernelGGL((k_oct_restrict_deg<NF, NC>), node_grid((long long)F.ne * NC * NC * NC, nrhs), dim3(256), 0,
-                           s, T, F.ne, st, a, b);
+        hipLaunchKernelGGL((k_oct_restrict_deg<NF, NC, T>), node_grid((long long)F.ne * NC * NC * NC, nrhs), dim3(256),
+                           0, s, Tm, F.ne, st, a, b);
     else
-        hipLaunchKernelGGL((k_oct_prolong_deg<NF, NC>), node_grid((long long)F.ne * NF * NF * NF, nrhs), dim3(256), 0,
-                           s, T, F.ne, st, a, b);
+        hipLaunchKernelGGL((k_oct_prolong_deg<NF, NC, T>), node_grid((long long)F.ne * NF * NF * NF, nrhs), dim3(256),
+                           0, s, Tm, F.ne, st, a, b);
 }
 
 // restrict (rc = R rf) or prolong-and-add (zf += P zc) between level l and l + 1
-void transfer(const dg_octree& O, int l, bool restrict_, int nrhs, const RhsState* st, const double* a, double* b,
+template <typename T>
+void transfer(const dg_octree& O, int l, bool restrict_, int nrhs, const RhsState* st, const T* a, T* b,
               hipStream_t s) {
     const Level& F = O.lv[l];
     const Level& C = O.lv[l + 1];
     if (F.kind == 2) {
         if (restrict_)
-            hipLaunchKernelGGL(k_oct_restrict_mesh, node_grid((long long)C.ne * 8, nrhs), dim3(256), 0, s, F.ne, C.ne,
-                               F.kstart, F.kids, F.msel, O.tab[2], st, a, b);
+            hipLaunchKernelGGL((k_oct_restrict_mesh<T>), node_grid((long long)C.ne * 8, nrhs), dim3(256), 0, s, F.ne,
+                               C.ne, F.kstart, F.kids, F.msel, tab_of<T>(O, 2), st, a, b);
         else
-            hipLaunchKernelGGL(k_oct_prolong_mesh, node_grid((long long)F.ne * 8, nrhs), dim3(256), 0, s, F.ne, C.ne,
-                               F.par, F.msel, O.tab[2], st, a, b);
+            hipLaunchKernelGGL((k_oct_prolong_mesh<T>), node_grid((long long)F.ne * 8, nrhs), dim3(256), 0, s, F.ne,
+                               C.ne, F.par, F.msel, tab_of<T>(O, 2), st, a, b);
         return;
     }
     const int key = F.n * 10 + C.n;
     switch (key) {
-        case 53: deg_transfer<5, 3>(F, restrict_, nrhs, st, a, b, s); break;
-        case 32: deg_transfer<3, 2>(F, restrict_, nrhs, st, a, b, s); break;
-        case 42: deg_transfer<4, 2>(F, restrict_, nrhs, st, a, b, s); break;
-        case 52: deg_transfer<5, 2>(F, restrict_, nrhs, st, a, b, s); break;
+        case 53: deg_transfer<5, 3, T>(F, restrict_, nrhs, st, a, b, s); break;
+        case 32: deg_transfer<3, 2, T>(F, restrict_, nrhs, st, a, b, s); break;
+        case 42: deg_transfer<4, 2, T>(F, restrict_, nrhs, st, a, b, s); break;
         default: throw std::logic_error("octree: no degree transfer for this pair");
     }
 }
@@ -1236,6 +1278,12 @@ void ensure_work(dg_octree& O, int nrhs) {
     O.pz = oalloc<double>(n0);
     O.pp = oalloc<double>(n0);
     O.pq = oalloc<double>(n0);
+    ofree(O.r32);
+    ofree(O.z32);
+    if (O.fp32) {
+        O.r32 = oalloc<float>(n0);
+        O.z32 = oalloc<float>(n0);
+    }
     O.pstride = chunks_of(O.lv[0].ndof);
     O.partial = oalloc<double>((long long)nrhs * O.pstride);
     O.cap = nrhs;
@@ -1249,40 +1297,60 @@ void ensure_state(dg_octree& O, int nrhs) {
 }
 
 // Chebyshev smoothing of level l on f from z (zero_start: z = 0), the work vectors of the level
-void smooth(dg_octree& O, int l, int nrhs, const RhsState* st, const double* f, double* z, bool zero_start,
-            hipStream_t s) {
+// (the FP64 buffers hold FP32 values in their first half when T is float)
+template <typename T>
+void smooth(dg_octree& O, int l, int nrhs, const RhsState* st, const T* f, T* z, bool zero_start, hipStream_t s) {
     const Level& L = O.lv[l];
-    double* r = O.wr[l];
-    double* d0 = O.wd0[l];
-    double* d1 = O.wd1[l];
+    T* r = reinterpret_cast<T*>(O.wr[l]);
+    T* d0 = reinterpret_cast<T*>(O.wd0[l]);
+    T* d1 = reinterpret_cast<T*>(O.wd1[l]);
+    const T* dinv = dinv_of<T>(L);
     if (zero_start) {
-        hipLaunchKernelGGL(k_oct_start0, node_grid(L.ndof, nrhs), dim3(256), 0, s, L.ndof, st, f, r, z, d0, L.dinv,
-                           L.c0);
+        hipLaunchKernelGGL((k_oct_start0<T>), node_grid(L.ndof, nrhs), dim3(256), 0, s, L.ndof, st, f, r, z, d0, dinv,
+                           (T)L.c0);
     } else {
-        op_launch(O, L, OP_RESID, nrhs, st, z, r, f, nullptr, nullptr, 0.0, 0.0, s);
-        hipLaunchKernelGGL(k_oct_dstart, node_grid(L.ndof, nrhs), dim3(256), 0, s, L.ndof, st, r, d0, L.dinv, L.c0);
+        op_launch<T>(O, L, OP_RESID, nrhs, st, z, r, f, nullptr, nullptr, 0.0, 0.0, s);
+        hipLaunchKernelGGL((k_oct_dstart<T>), node_grid(L.ndof, nrhs), dim3(256), 0, s, L.ndof, st, r, d0, dinv,
+                           (T)L.c0);
     }
     for (int k = 1; k < L.degree; ++k) {
-        op_launch(O, L, OP_CHEB, nrhs, st, d0, d1, nullptr, r, z, L.cp[k - 1], L.cr[k - 1], s);
+        op_launch<T>(O, L, OP_CHEB, nrhs, st, d0, d1, nullptr, r, z, L.cp[k - 1], L.cr[k - 1], s);
         std::swap(d0, d1);
     }
-    hipLaunchKernelGGL(k_oct_add, node_grid(L.ndof, nrhs), dim3(256), 0, s, L.ndof, st, d0, z);
+    hipLaunchKernelGGL((k_oct_add<T>), node_grid(L.ndof, nrhs), dim3(256), 0, s, L.ndof, st, d0, z);
 }
 
 // z = V f on level l (f is not modified)
-void vcycle(dg_octree& O, int l, int nrhs, const RhsState* st, const double* f, double* z, hipStream_t s) {
+template <typename T>
+void vcycle(dg_octree& O, int l, int nrhs, const RhsState* st, const T* f, T* z, hipStream_t s) {
     const int nl = (int)O.lv.size();
     if (l == nl - 1) {
-        launch_coarse<double>(O.cdev, O.base, nrhs, st, f, z, O.cscr, s);
+        launch_coarse<T>(O.cdev, O.base, nrhs, st, f, z, O.cscr, s);
         return;
     }
     const Level& L = O.lv[l];
-    smooth(O, l, nrhs, st, f, z, true, s);
-    op_launch(O, L, OP_RESID, nrhs, st, z, O.wt[l], f, nullptr, nullptr, 0.0, 0.0, s);
-    transfer(O, l, true, nrhs, st, O.wt[l], O.wf[l + 1], s);
-    vcycle(O, l + 1, nrhs, st, O.wf[l + 1], O.wz[l + 1], s);
-    transfer(O, l, false, nrhs, st, O.wz[l + 1], z, s);
-    smooth(O, l, nrhs, st, f, z, false, s);
+    T* t = reinterpret_cast<T*>(O.wt[l]);
+    T* fc = reinterpret_cast<T*>(O.wf[l + 1]);
+    T* zc = reinterpret_cast<T*>(O.wz[l + 1]);
+    smooth<T>(O, l, nrhs, st, f, z, true, s);
+    op_launch<T>(O, L, OP_RESID, nrhs, st, z, t, f, nullptr, nullptr, 0.0, 0.0, s);
+    transfer<T>(O, l, true, nrhs, st, t, fc, s);
+    vcycle<T>(O, l + 1, nrhs, st, fc, zc, s);
+    transfer<T>(O, l, false, nrhs, st, zc, z, s);
+    smooth<T>(O, l, nrhs, st, f, z, false, s);
+}
+
+// the preconditioner z = V r at the finest level in the solve's V-cycle precision
+void precondition(dg_octree& O, int nrhs, const RhsState* st, const double* r, double* z, hipStream_t s) {
+    if (!O.fp32) {
+        vcycle<double>(O, 0, nrhs, st, r, z, s);
+        return;
+    }
+    const long long n = O.lv[0].ndof * nrhs;
+    const dim3 g((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_oct_narrow, g, dim3(256), 0, s, n, st, O.lv[0].ndof, r, O.r32);
+    vcycle<float>(O, 0, nrhs, st, O.r32, O.z32, s);
+    hipLaunchKernelGGL(k_oct_widen, g, dim3(256), 0, s, n, st, O.lv[0].ndof, O.z32, z);
 }
 
 void lanczos_bounds(dg_octree& O, int l, hipStream_t s) {
@@ -1315,7 +1383,7 @@ void lanczos_bounds(dg_octree& O, int l, hipStream_t s) {
     const int steps = (int)std::min<long long>(O.opts.lanczos_steps, n);
     for (int k = 0; k < steps; ++k) {
         hipLaunchKernelGGL(k_oct_dscale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, L.dinv, v, tmp);
-        op_launch(O, L, OP_APPLY, 1, nullptr, tmp, w, nullptr, nullptr, nullptr, 0.0, 0.0, s);
+        op_launch<double>(O, L, OP_APPLY, 1, nullptr, tmp, w, nullptr, nullptr, nullptr, 0.0, 0.0, s);
         hipLaunchKernelGGL(k_oct_dscale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, L.dinv, w, w);
         launch_axpby(n, -beta, vp, 1.0, w, s);
         const double alpha = dot(w, v);
@@ -1369,6 +1437,8 @@ void build_tables(dg_octree& O, int n) {
             std::copy(Lm.begin(), Lm.end(), T.begin() + (size_t)table_entry(k, j) * n * n);
         }
     O.tab[n] = upload(T);
+    std::vector<float> T32(T.begin(), T.end());
+    O.tab32[n] = upload(T32);
 }
 
 }  // namespace
@@ -1381,12 +1451,16 @@ void destroy(dg_octree* O) {
         ofree(L.fstart);
         ofree(L.pcs);
         ofree(L.dinv);
+        ofree(L.dinv32);
         ofree(L.par);
         ofree(L.msel);
         ofree(L.kstart);
         ofree(L.kids);
     }
     for (auto& t : O->tab) ofree(t);
+    for (auto& t : O->tab32) ofree(t);
+    ofree(O->r32);
+    ofree(O->z32);
     ofree(O->bstart);
     ofree(O->qnodes);
     ofree(O->qpart);
@@ -1412,7 +1486,8 @@ dg_octree* create(const dg_octree_desc& D, dg_density_fn rho, void* user, const 
     if (D.max_depth < 0 || D.max_depth > KMAX) throw std::invalid_argument("octree max_depth: 0 to 8");
     if (!(D.delta_q > 0.0)) throw std::invalid_argument("octree delta_q must be positive");
     if (D.max_elements < 1) throw std::invalid_argument("octree max_elements must be positive");
-    if (opts.precision != DG_PREC_FP64) throw std::invalid_argument("octree solves run in FP64 precision");
+    if (opts.precision != DG_PREC_FP64 && opts.precision != DG_PREC_FP32_PC)
+        throw std::invalid_argument("octree solves: precision FP64 or FP32_PC");
     if (opts.cheb_degree < 1 || opts.cheb_degree_h < 0 || opts.cheb_ratio <= 1.0 || opts.cheb_safety < 1.0 ||
         opts.lanczos_steps < 2 || !(opts.penalty_eps > 0.0) || !(opts.rtol > 0.0) || opts.max_iter < 0)
         throw std::invalid_argument("invalid solver options");
@@ -1427,6 +1502,7 @@ dg_octree* create(const dg_octree_desc& D, dg_density_fn rho, void* user, const 
         }
         O->q = D.q;
         O->opts = opts;
+        O->fp32 = opts.precision == DG_PREC_FP32_PC;
         for (int n = 2; n <= D.q + 1; ++n) build_tables(*O, n);
         refine(*O, rho, user, D.delta_q, D.max_depth, D.max_elements);
         // levels: degree steps on the leaves, then the tree cut at generation G-1 .. 0 at degree 1
@@ -1661,13 +1737,19 @@ void boundary_data(dg_octree* O, int nsrc, const double* f, double* g, hipStream
 
 void apply(dg_octree* O, int level, int nrhs, const double* u, double* y, hipStream_t s) {
     if (level < 0 || level >= (int)O->lv.size()) throw std::invalid_argument("level out of range");
-    op_launch(*O, O->lv[level], OP_APPLY, nrhs, nullptr, u, y, nullptr, nullptr, nullptr, 0.0, 0.0, s);
+    op_launch<double>(*O, O->lv[level], OP_APPLY, nrhs, nullptr, u, y, nullptr, nullptr, nullptr, 0.0, 0.0, s);
+    OCHK(hipGetLastError());
+}
+
+void apply_f32(dg_octree* O, int level, int nrhs, const float* u, float* y, hipStream_t s) {
+    if (level < 0 || level >= (int)O->lv.size()) throw std::invalid_argument("level out of range");
+    op_launch<float>(*O, O->lv[level], OP_APPLY, nrhs, nullptr, u, y, nullptr, nullptr, nullptr, 0.0, 0.0, s);
     OCHK(hipGetLastError());
 }
 
 void vcycle_once(dg_octree* O, int nrhs, const double* r, double* z, hipStream_t s) {
     ensure_work(*O, nrhs);
-    vcycle(*O, 0, nrhs, nullptr, r, z, s);
+    vcycle<double>(*O, 0, nrhs, nullptr, r, z, s);
     OCHK(hipGetLastError());
 }
 
@@ -1697,11 +1779,11 @@ int solve(dg_octree* O, int nrhs, const double* b, double* x, dg_rhs_stats* stat
     const int every = std::max(1, O->opts.check_every);
     for (int it = 0; it < O->opts.max_iter;) {
         for (int k = 0; k < every && it < O->opts.max_iter; ++k, ++it) {
-            vcycle(*O, 0, nrhs, st, O->pr, O->pz, s);
+            precondition(*O, nrhs, st, O->pr, O->pz, s);
             launch_dot<double, double>(n, nrhs, st, O->pr, O->pz, O->partial, O->pstride, s);
             launch_finalize(FIN_RZ, nrhs, st, O->partial, O->pstride, nc, s);
             hipLaunchKernelGGL(k_oct_pdir, node_grid(n, nrhs), dim3(256), 0, s, n, st, O->pz, O->pp);
-            op_launch(*O, L, OP_APPLY, nrhs, st, O->pp, O->pq, nullptr, nullptr, nullptr, 0.0, 0.0, s);
+            op_launch<double>(*O, L, OP_APPLY, nrhs, st, O->pp, O->pq, nullptr, nullptr, nullptr, 0.0, 0.0, s);
             launch_dot<double, double>(n, nrhs, st, O->pp, O->pq, O->partial, O->pstride, s);
             launch_finalize(FIN_PQ, nrhs, st, O->partial, O->pstride, nc, s);
             hipLaunchKernelGGL(k_oct_xr, node_grid(n, nrhs), dim3(256), 0, s, n, st, O->pp, O->pq, x, O->pr);
@@ -1716,7 +1798,7 @@ int solve(dg_octree* O, int nrhs, const double* b, double* x, dg_rhs_stats* stat
     }
     OCHK(hipGetLastError());
     // FP64 residual of the returned solution
-    op_launch(*O, L, OP_RESID, nrhs, nullptr, x, O->pr, b, nullptr, nullptr, 0.0, 0.0, s);
+    op_launch<double>(*O, L, OP_RESID, nrhs, nullptr, x, O->pr, b, nullptr, nullptr, 0.0, 0.0, s);
     launch_dot<double, double>(n, nrhs, nullptr, O->pr, O->pr, O->partial, O->pstride, s);
     std::vector<double> part((size_t)nrhs * O->pstride);
     OCHK(hipMemcpyAsync(part.data(), O->partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s));
@@ -1827,6 +1909,16 @@ dg_status dg_octree_apply(dg_octree* o, int level, int nrhs, const double* u, do
         if (!u || !y) throw std::invalid_argument("null argument");
         (void)hipSetDevice(o->device);
         dg::oct::apply(o, level, nrhs, u, y, (hipStream_t)stream);
+    });
+}
+
+dg_status dg_octree_apply_f32(dg_octree* o, int level, int nrhs, const float* u, float* y, void* stream) {
+    return dg::guarded([&] {
+        if (!o || nrhs < 0) throw std::invalid_argument("bad arguments");
+        if (nrhs == 0) return;
+        if (!u || !y) throw std::invalid_argument("null argument");
+        (void)hipSetDevice(o->device);
+        dg::oct::apply_f32(o, level, nrhs, u, y, (hipStream_t)stream);
     });
 }
 

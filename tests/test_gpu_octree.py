@@ -181,13 +181,57 @@ def test_boundary_data_by_quadrature_matches_oracle(gpu_lib, case):
     assert np.abs(b - bref).max() <= 1e-12 * np.abs(bref).max()
 
 
+@pytest.mark.parametrize("case", CASES)
+def test_fp32_operator_matches_oracle(gpu_lib, case):
+    """The FP32 V-cycle's operator at every level, to FP32 rounding of the oracle's FP64 result."""
+    import torch
+    g, t = _pair(gpu_lib, case, precision="fp32_pc")
+    H = octree.Hierarchy(t)
+    rng = np.random.default_rng(12)
+    for l, m in enumerate(H.meshes):
+        u = rng.standard_normal((2, m.ndof))
+        got = g.apply_f32(torch.as_tensor(u, dtype=torch.float32).cuda().contiguous(), level=l).cpu().numpy()
+        ref = np.stack([m.apply(u[k].astype(np.float32).astype(np.float64)) for k in range(2)])
+        assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max(), l
+
+
+@pytest.mark.parametrize("case,cheb", [(CASES[0], (6, 10)), (CASES[2], (8, 4)), (LARGE, (8, 4))])
+def test_fp32_pc_solve_matches_the_fp64_solution(gpu_lib, case, cheb):
+    """FP32 V-cycle under FP64 CG: the FP64 residual reaches the tolerance, and the solution agrees
+    with the oracle's FP64 MG-PCG (or, at the large size, with the library's FP64 solve)."""
+    ne, lo, hi, q, dq, depth = case
+    rho = _molecule if case is LARGE else _two_centres
+    kw = dict(rho=rho, delta_q=dq, max_depth=depth, rtol=1e-11, cheb_degree=cheb[0], cheb_degree_h=cheb[1])
+    g32 = gpu_lib.Octree(ne, lo, hi, q=q, precision="fp32_pc", **kw)
+    g64 = gpu_lib.Octree(ne, lo, hi, q=q, **kw)
+    xyz = g32.nodes()
+    bxyz = g32.boundary_points()
+    f = np.stack([rho(*xyz), _gauss(3.0, (0.1, 0.0, 0.2))(*xyz)])
+    gb = np.stack([np.zeros(bxyz.shape[1]), 0.05 * np.cos(bxyz[0] + bxyz[1])])
+    b = g32.rhs(_t(f), _t(gb))
+    x32, st32 = g32.solve(b)
+    x64, st64 = g64.solve(b)
+    x32, x64 = x32.cpu().numpy(), x64.cpu().numpy()
+    for k in range(2):
+        assert st32[k]["status"] == 0 and st32[k]["rel_residual"] <= 2e-11
+        assert st32[k]["iters"] <= st64[k]["iters"] + 3, (st32[k]["iters"], st64[k]["iters"])
+        assert np.abs(x32[k] - x64[k]).max() <= 1e-8 * np.abs(x64[k]).max()
+    if case is not LARGE:
+        t = octree.Octree(ne, lo, hi, q, rho=rho, delta_q=dq, max_depth=depth)
+        H = octree.Hierarchy(t, degree=cheb[0], degree_h=cheb[1])
+        bh = b.cpu().numpy()
+        for k in range(2):
+            xr, _, _, _ = pcg.pcg(H.levels[0].A, bh[k], H.vcycle, rtol=1e-12)
+            assert np.abs(x32[k] - xr).max() <= 1e-8 * np.abs(xr).max()
+
+
 def test_octree_arguments_are_checked(gpu_lib):
     with pytest.raises(gpu_lib.DgError):
         gpu_lib.Octree((9, 1, 1), (0, 0, 0), (1, 1, 1), q=2)          # more than 8 base elements per axis
     with pytest.raises(gpu_lib.DgError):
         gpu_lib.Octree((1, 1, 1), (0, 0, 0), (1, 1, 1), q=5)          # degree above 4
     with pytest.raises(gpu_lib.DgError):
-        gpu_lib.Octree((1, 1, 1), (0, 0, 0), (1, 1, 1), q=2, precision="fp32_pc")
+        gpu_lib.Octree((1, 1, 1), (0, 0, 0), (1, 1, 1), q=2, precision="bf16f_pc")
     with pytest.raises(gpu_lib.DgError, match="max_elements"):
         gpu_lib.Octree((2, 2, 2), (-2, -2, -2), (2, 2, 2), q=2, rho=_two_centres, delta_q=1e-9, max_depth=4,
                        max_elements=100)
