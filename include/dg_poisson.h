@@ -550,7 +550,7 @@ dg_status dg_octree_apply_f32(dg_octree* octree, int level, int nrhs, const floa
 /* z = V r, one FP64 V-cycle of the preconditioner on the finest level (device arrays). */
 dg_status dg_octree_vcycle(dg_octree* octree, int nrhs, const double* r, double* z, void* stream);
 /* Tuning: right-hand sides per work-group of the octree operator kernels (1, 2 or 4; 0, the
- * default: 4 at degree 4 and 2 below, the fastest measured on MI355X):
+ * default: 4 in FP32 and at degree 4 in FP64, 2 below, the fastest measured on MI355X):
  * the right-hand sides of a work-group share its element's geometry, pieces and tables, and
  * give each thread independent work between its barriers.  Results do not depend on it. */
 dg_status dg_octree_set_rhs_per_block(dg_octree* octree, int rhs_per_block);
