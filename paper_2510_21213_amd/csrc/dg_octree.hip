@@ -103,7 +103,11 @@ __global__ __launch_bounds__(OT) void k_oct_op(Ref<N, double> Rarg, int ne, int 
     }
     if (!any) return;
     const int t = threadIdx.x, s = t / N3, l = t - s * N3;
-    const int e = blockIdx.x * EPB + s;
+    // work-groups are dealt to the 8 XCDs in turn; give each XCD a contiguous run of elements
+    // (depth-first order is spatially local), so that neighbour faces are read from its own L2
+    const int nbx = gridDim.x, full = nbx / 8 * 8;
+    const int bx = (int)blockIdx.x < full ? ((int)blockIdx.x % 8) * (nbx / 8) + (int)blockIdx.x / 8 : (int)blockIdx.x;
+    const int e = bx * EPB + s;
     {
         const double* src = reinterpret_cast<const double*>(&Rarg);
         T* dst = reinterpret_cast<T*>(&R);
