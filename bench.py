@@ -848,7 +848,9 @@ def main_octree(args):
         return {"kernel": kernel, "bound": "hbm", "achieved": algo / t / 1e9, "peak": 8000.0, "unit": "GB/s",
                 "frac": algo / t / 8e12, "traffic": None, "us_per_launch": t * 1e6, "algorithmic_bytes_per_launch": algo}
     roof = roofline("k_oct_op<5, APPLY, float> (finest-level operator of the FP32 V-cycle, 36 RHS)", algo32, t_op32)
+    roof["traffic"] = measured_traffic("octree_step_exchange8.md", "dg_octree.hip", "fp32_pc")
     roof["fp64_arm"] = roofline("k_oct_op<5, APPLY, double> (36 RHS)", algo64, t_op64)
+    roof["fp64_arm"]["traffic"] = measured_traffic("octree_step_exchange8.md", "dg_octree.hip", "fp64")
     # accuracy against the closed-form continuum potentials at the nodes (discretisation error),
     # and of the FP32-V-cycle arm against the FP64 one
     vall = orb.pair_potentials(xyz[0], xyz[1], xyz[2])
