@@ -536,6 +536,26 @@ class Hierarchy(_mg.Hierarchy):
         return out.reshape(-1)
 
 
+def exchange(mesh, psi, g_pairs, solve):
+    """Exchange on the octree grid (Sec. 6.1 on the auxiliary mesh of Sec. 6.2): for the pair
+    densities rho_ij = psi_i psi_j (i <= j, row-major pair order) solve for v_ij with Dirichlet data
+    g_pairs[k]; W_k = sum_s psi_s v_ks (pointwise); K_ij = sum_q W_q rho_ij v_ij (the grid's GL
+    quadrature); E_X = sum over ordered pairs.  Returns (v, W, K, E_X)."""
+    n = len(psi)
+    w = mesh.mass()
+    pairs = [(i, j) for i in range(n) for j in range(i, n)]
+
+    def idx(i, j):
+        i, j = min(i, j), max(i, j)
+        return i * n - i * (i - 1) // 2 + (j - i)
+    rho = [psi[i] * psi[j] for i, j in pairs]
+    v = [solve(mesh.rhs(r, g)) for r, g in zip(rho, g_pairs)]
+    K = np.array([float(np.sum(w * r * vv)) for r, vv in zip(rho, v)])
+    W = [sum(psi[s] * v[idx(k, s)] for s in range(n)) for k in range(n)]
+    EX = float(sum((1.0 if i == j else 2.0) * K[q] for q, (i, j) in enumerate(pairs)))
+    return v, W, K, EX
+
+
 class _Coarse:
     """Exact solve on the uniform base mesh at degree 1 (fast diagonalisation), element-major."""
 

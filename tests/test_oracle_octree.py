@@ -299,3 +299,32 @@ def test_boundary_data_by_quadrature_brute_force_and_closed_form():
         exact = erf(np.sqrt(a) * r) / r
         errs.append(np.abs(gg - exact).max() / np.abs(exact).max())
     assert errs[1] < 3e-6 and errs[1] < errs[0] / 1e4     # measured 0.10 (8 cells) and 1.2e-6 (155 cells)
+
+
+def test_exchange_on_an_unrefined_octree_equals_the_uniform_gl_exchange():
+    """W_k, K_ij and E_x on the octree grid: with no refinement the problem is the uniform GL
+    mesh's, so they equal the uniform exchange oracle's (exact solves on both sides)."""
+    from oracle import exchange as uex, fdm, layout
+    from workloads import gaussians
+    E, q, lo, hi = (3, 2, 2), 3, (-3.0, -2.5, -2.0), (3.0, 2.5, 2.0)
+    prims = gaussians.Primitives([0.9, 1.6, 0.7], [[0.3, 0.1, 0.0], [-0.4, 0.0, 0.2], [0.1, -0.3, -0.1]])
+    orb = gaussians.Orbitals(prims, gaussians.lowdin(np.array([[1.0, 0.3], [0.2, -1.0], [0.5, 0.4]]),
+                                                     prims.overlap()))
+    m = octree.Octree(E, lo, hi, q).mesh()
+    A, _ = m.dense()
+    X, Y, Z = m.nodes()
+    psi = list(orb.values(X, Y, Z))
+    bx, by, bz = m.boundary_points()
+    g = orb.pair_potentials(bx, by, bz)
+    v, W, K, EX = octree.exchange(m, psi, list(g), lambda b: np.linalg.solve(A, b))
+    axes = sipdg.make_axes(E, q, lo, hi, family="gl")
+    Xg, Yg, Zg = np.broadcast_arrays(*sipdg.node_grid(axes))
+    psig = list(orb.values(Xg, Yg, Zg))
+    fp = sipdg.face_points(axes)
+    gp = [[orb.pair_potentials(*fp[f])[k] for f in range(6)] for k in range(len(g))]
+    vu, Wu, Ku, EXu = uex.exchange(axes, psig, gp, fdm.FDM(axes).solve)
+    assert np.abs(K - Ku).max() <= 1e-11 * np.abs(Ku).max()
+    assert abs(EX - EXu) <= 1e-11 * abs(EXu)
+    for k in range(len(W)):
+        Wg = layout.to_element_major(Wu[k], E, q + 1)
+        assert np.abs(W[k] - Wg).max() <= 1e-10 * np.abs(Wg).max()
