@@ -549,6 +549,16 @@ dg_status dg_octree_apply(dg_octree* octree, int level, int nrhs, const double* 
 dg_status dg_octree_apply_f32(dg_octree* octree, int level, int nrhs, const float* u, float* y, void* stream);
 /* z = V r, one FP64 V-cycle of the preconditioner on the finest level (device arrays). */
 dg_status dg_octree_vcycle(dg_octree* octree, int nrhs, const double* r, double* z, void* stream);
+/* Exchange on the octree grid (Sec. 6.1): for the orbitals phi [norb][n_dofs] (device, 1 <= norb
+ * <= 64) solve for the potentials v_ij of the pair densities phi_i phi_j (i <= j, row-major pair
+ * order) with Dirichlet data g_pairs [npairs][n_boundary] (device; NULL: by quadrature), then
+ * W [norb][n_dofs] (device, may be NULL): W_k = sum_s phi_s v_ks pointwise, K [npairs] (host, may
+ * be NULL): K_ij = sum_q W_q phi_i phi_j v_ij with the grid's GL weights, *e_x (host, may be NULL)
+ * = sum over ordered pairs.  v_pairs [npairs][n_dofs] (device) receives the potentials if not
+ * NULL.  Solves as dg_octree_solve (stats [npairs], host, may be NULL); synchronises the stream;
+ * returns the worst solve status; allocates its work space. */
+dg_status dg_octree_exchange(dg_octree* octree, int norb, const double* phi, const double* g_pairs, double* v_pairs,
+                             double* W, double* K, double* e_x, dg_rhs_stats* stats, void* stream);
 /* Tuning: right-hand sides per work-group of the octree operator kernels (1, 2 or 4; 0, the
  * default: 4 in FP32 and at degree 4 in FP64, 2 below, the fastest measured on MI355X):
  * the right-hand sides of a work-group share its element's geometry, pieces and tables, and

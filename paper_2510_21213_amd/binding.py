@@ -129,6 +129,7 @@ def _load():
         "dg_octree_set_rhs_per_block": (I, [P, I]),
         "dg_octree_boundary_data": (I, [P, I, P, P, P]),
         "dg_octree_apply_f32": (I, [P, I, I, P, P, P]),
+        "dg_octree_exchange": (I, [P, I, P, P, P, P, P, ctypes.POINTER(D), P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -567,6 +568,21 @@ class Octree:
         _check(lib.dg_octree_vcycle(self._h, r.numel() // self.n_dofs, _ptr(r), _ptr(z), _stream()),
                "octree_vcycle")
         return z
+
+    def exchange(self, phi, g_pairs=None, keep_potentials=False):
+        """(W [norb, n_dofs], K [npairs], E_x, stats, v or None) for orbitals phi [norb, n_dofs];
+        g_pairs None: Dirichlet data by quadrature."""
+        norb = phi.numel() // self.n_dofs
+        npairs = norb * (norb + 1) // 2
+        W = torch.empty((norb, self.n_dofs), dtype=torch.float64, device=phi.device)
+        v = torch.empty((npairs, self.n_dofs), dtype=torch.float64, device=phi.device) if keep_potentials else None
+        K = np.empty(npairs)
+        ex = ctypes.c_double()
+        st = (DgRhsStats * npairs)()
+        code = lib.dg_octree_exchange(self._h, norb, _ptr(phi), _ptr(g_pairs), _ptr(v), _ptr(W),
+                                      K.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ex), st, _stream())
+        _check(code, "octree_exchange", allow_warn=True)
+        return W, K, ex.value, [_stats(st[i]) for i in range(npairs)], v
 
     def solve(self, b):
         """x = A^-1 b (MG-PCG); returns (x, stats list)."""

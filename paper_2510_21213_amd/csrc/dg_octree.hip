@@ -701,6 +701,46 @@ __global__ __launch_bounds__(256) void k_oct_bsum(int nparts, int nsrc, int nbp,
     g[i] = acc;
 }
 
+// Exchange on the octree grid (Sec. 6.1): W_k = sum_s phi_s v_ks pointwise (v_ks = v_sk, row-major
+// pair index of i <= j), and per pair k the partial sums of W_q rho_k v_k over chunks of 1024 nodes
+// (rho_k = phi_i phi_j recomputed), added in a fixed order on the host.
+__global__ __launch_bounds__(256) void k_oct_wk(long long ndof, int norb, const double* __restrict__ phi,
+                                                const double* __restrict__ v, double* __restrict__ W) {
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;
+    if (q >= ndof) return;
+    double acc = 0.0;
+    for (int s = 0; s < norb; ++s) {
+        const int i = min(k, s), j = max(k, s);
+        const int p = i * norb - i * (i - 1) / 2 + (j - i);
+        acc += phi[(long long)s * ndof + q] * v[(long long)p * ndof + q];
+    }
+    W[(long long)k * ndof + q] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_oct_kij(long long ndof, const int* __restrict__ pi, const int* __restrict__ pj,
+                                                 const double* __restrict__ phi, const double* __restrict__ v,
+                                                 const double* __restrict__ w, double* __restrict__ partial,
+                                                 int nchunk) {
+    __shared__ double red[256];
+    const int p = blockIdx.y, c = blockIdx.x;
+    const double* fi = phi + (long long)pi[p] * ndof;
+    const double* fj = phi + (long long)pj[p] * ndof;
+    const double* vp = v + (long long)p * ndof;
+    double acc = 0.0;
+    for (int u = 0; u < 4; ++u) {
+        const long long q = (long long)c * 1024 + u * 256 + threadIdx.x;
+        if (q < ndof) acc += w[q] * fi[q] * fj[q] * vp[q];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long long)p * nchunk + c] = red[0];
+}
+
 // ---------------------------------------------------------------------------------------------
 // host side
 
@@ -1698,11 +1738,12 @@ void rhs(dg_octree* O, int nrhs, const double* f, const double* g, double* b, hi
     }
 }
 
-void boundary_data(dg_octree* O, int nsrc, const double* f, double* g, hipStream_t s) {
+// node coordinates and GL weights of the finest level, then the Dirichlet points (device, once)
+void ensure_qnodes(dg_octree* O) {
     const Level& L = O->lv[0];
     const long long nd = L.ndof, nb = O->nbp;
-    if (nsrc == 0 || nb == 0) return;
-    if (!O->qnodes) {
+    if (O->qnodes) return;
+    {
         std::vector<double> h(4 * nd + 3 * nb);
         node_coords(O, &h[0], &h[nd], &h[2 * nd]);
         const int n = L.n;
@@ -1714,9 +1755,16 @@ void boundary_data(dg_octree* O, int nsrc, const double* f, double* g, hipStream
                     for (int i = 0; i < n; ++i)
                         h[3 * nd + (long long)e * n * n * n + (k * n + j) * n + i] = J3 * w[k] * w[j] * w[i];
         }
-        boundary_coords(O, &h[4 * nd], &h[4 * nd + nb], &h[4 * nd + 2 * nb]);
+        if (nb > 0) boundary_coords(O, &h[4 * nd], &h[4 * nd + nb], &h[4 * nd + 2 * nb]);
         O->qnodes = upload(h);
     }
+}
+
+void boundary_data(dg_octree* O, int nsrc, const double* f, double* g, hipStream_t s) {
+    const Level& L = O->lv[0];
+    const long long nd = L.ndof, nb = O->nbp;
+    if (nsrc == 0 || nb == 0) return;
+    ensure_qnodes(O);
     const int pblocks = (int)((nb + BT - 1) / BT), sblocks = (nsrc + BR - 1) / BR;
     const long long tiles = (nd + BT - 1) / BT;
     // node parts: enough work-groups for several per compute unit
@@ -1827,6 +1875,63 @@ int solve(dg_octree* O, int nrhs, const double* b, double* x, dg_rhs_stats* stat
             stats[i].rel_residual = rel;
         }
     }
+    return worst;
+}
+
+// Exchange: pair densities, their right-hand sides (data given or by quadrature), the solves,
+// W_k and K_ij; returns the worst solve status.
+int exchange(dg_octree* O, int norb, const double* phi, const double* g, double* v_out, double* W, double* K,
+             double* ex, dg_rhs_stats* stats, hipStream_t s) {
+    const long long nd = O->lv[0].ndof;
+    const int np = norb * (norb + 1) / 2;
+    std::vector<int> hi, hj;
+    for (int i = 0; i < norb; ++i)
+        for (int j = i; j < norb; ++j) {
+            hi.push_back(i);
+            hj.push_back(j);
+        }
+    int* dpi = upload(hi);
+    int* dpj = upload(hj);
+    double* rho = oalloc<double>(np * nd);
+    double* b = oalloc<double>(np * nd);
+    double* v = v_out ? v_out : oalloc<double>(np * nd);
+    const int nchunk = chunks_of(nd);
+    double* part = oalloc<double>((long long)np * nchunk);
+    int worst = DG_OK;
+    try {
+        launch_pair_products(nd, np, phi, dpi, dpj, rho, s);
+        rhs(O, np, rho, g, b, s);
+        worst = solve(O, np, b, v, stats, s);
+        if (W) hipLaunchKernelGGL(k_oct_wk, dim3((unsigned)((nd + 255) / 256), norb), dim3(256), 0, s, nd, norb, phi, v, W);
+        ensure_qnodes(O);
+        hipLaunchKernelGGL(k_oct_kij, dim3(nchunk, np), dim3(256), 0, s, nd, dpi, dpj, phi, v, O->qnodes + 3 * nd, part,
+                           nchunk);
+        std::vector<double> hp((size_t)np * nchunk);
+        OCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, s));
+        OCHK(hipStreamSynchronize(s));
+        double e = 0.0;
+        for (int p = 0; p < np; ++p) {
+            double k = 0.0;
+            for (int c = 0; c < nchunk; ++c) k += hp[(size_t)p * nchunk + c];
+            if (K) K[p] = k;
+            e += (hi[p] == hj[p] ? 1.0 : 2.0) * k;
+        }
+        if (ex) *ex = e;
+    } catch (...) {
+        ofree(dpi);
+        ofree(dpj);
+        ofree(rho);
+        ofree(b);
+        if (!v_out) ofree(v);
+        ofree(part);
+        throw;
+    }
+    ofree(dpi);
+    ofree(dpj);
+    ofree(rho);
+    ofree(b);
+    if (!v_out) ofree(v);
+    ofree(part);
     return worst;
 }
 
@@ -1955,6 +2060,17 @@ dg_status dg_octree_set_rhs_per_block(dg_octree* o, int rhs_per_block) {
             throw std::invalid_argument("rhs_per_block must be 0, 1, 2 or 4");
         o->rhs_per_block = rhs_per_block;
     });
+}
+
+dg_status dg_octree_exchange(dg_octree* o, int norb, const double* phi, const double* g_pairs, double* v_pairs,
+                             double* W, double* K, double* e_x, dg_rhs_stats* stats, void* stream) {
+    int worst = DG_OK;
+    const dg_status st = dg::guarded([&] {
+        if (!o || norb < 1 || norb > 64 || !phi) throw std::invalid_argument("bad arguments");
+        (void)hipSetDevice(o->device);
+        worst = dg::oct::exchange(o, norb, phi, g_pairs, v_pairs, W, K, e_x, stats, (hipStream_t)stream);
+    });
+    return st != DG_OK ? st : (dg_status)worst;
 }
 
 void dg_octree_destroy(dg_octree* o) { dg::oct::destroy(o); }

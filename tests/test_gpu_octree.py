@@ -225,6 +225,35 @@ def test_fp32_pc_solve_matches_the_fp64_solution(gpu_lib, case, cheb):
             assert np.abs(x32[k] - xr).max() <= 1e-8 * np.abs(xr).max()
 
 
+@pytest.mark.parametrize("case,quadrature", [(CASES[0], False), (CASES[1], True)])
+def test_exchange_matches_oracle(gpu_lib, case, quadrature):
+    """W_k, K_ij and E_x on the octree grid (Dirichlet data closed-form or by quadrature) against
+    the oracle's exchange with its own MG-PCG solves at the same tolerance."""
+    from workloads import gaussians
+    prims = gaussians.Primitives([0.9, 1.6, 0.7, 2.5], [[0.3, 0.1, 0.0], [-0.4, 0.0, 0.2], [0.1, -0.3, -0.1],
+                                                        [0.5, 0.2, -0.2]])
+    orb = gaussians.Orbitals(prims, gaussians.lowdin(np.array([[1.0, 0.3, 0.1], [0.2, -1.0, 0.4], [0.5, 0.4, -0.6],
+                                                               [0.1, 0.2, 1.0]]), prims.overlap()))
+    g, t = _pair(gpu_lib, case, rtol=1e-12)
+    H = octree.Hierarchy(t)
+    m = H.meshes[0]
+    psi = list(orb.values(*m.nodes()))
+    gp = None if quadrature else orb.pair_potentials(*m.boundary_points())
+    W, K, EX, st, v = g.exchange(_t(np.stack(psi)), None if gp is None else _t(gp), keep_potentials=True)
+    assert all(x["status"] == 0 for x in st)
+    pairs = [(i, j) for i in range(3) for j in range(i, 3)]
+    gref = [m.boundary_data(psi[i] * psi[j]) for i, j in pairs] if quadrature else list(gp)
+    vr, Wr, Kr, EXr = octree.exchange(m, psi, gref, lambda b: pcg.pcg(H.levels[0].A, b, H.vcycle, rtol=1e-12)[0])
+    assert np.abs(K - Kr).max() <= 1e-9 * np.abs(Kr).max()
+    assert abs(EX - EXr) <= 1e-9 * abs(EXr)
+    W = W.cpu().numpy()
+    for k in range(3):
+        assert np.abs(W[k] - Wr[k]).max() <= 1e-8 * np.abs(Wr[k]).max()
+    v = v.cpu().numpy()
+    for k in range(len(pairs)):
+        assert np.abs(v[k] - vr[k]).max() <= 1e-8 * np.abs(vr[k]).max()
+
+
 def test_octree_arguments_are_checked(gpu_lib):
     with pytest.raises(gpu_lib.DgError):
         gpu_lib.Octree((9, 1, 1), (0, 0, 0), (1, 1, 1), q=2)          # more than 8 base elements per axis
