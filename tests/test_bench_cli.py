@@ -47,3 +47,13 @@ def test_headline_counters_match_the_current_kernel_source():
     v = bench.measured_traffic("cheb_step_heldout32.md", "dg_kernels.hip", "bf16f_pc", "valu_busy")
     assert t is not None and t > 0
     assert v is not None and 0 < v <= 1
+
+
+def test_octree_counters_match_the_current_kernel_source():
+    """The octree operator has committed counters for its kernel source as it is, in both arms:
+    the octree line's roofline then reports their traffic."""
+    sys.path.insert(0, ROOT)
+    import bench
+    t32 = bench.measured_traffic("octree_step_exchange8.md", "dg_octree.hip", "fp32_pc")
+    t64 = bench.measured_traffic("octree_step_exchange8.md", "dg_octree.hip", "fp64")
+    assert t32 is not None and t64 is not None and 0 < t32 < t64
