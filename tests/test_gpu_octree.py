@@ -254,6 +254,29 @@ def test_exchange_matches_oracle(gpu_lib, case, quadrature):
         assert np.abs(v[k] - vr[k]).max() <= 1e-8 * np.abs(vr[k]).max()
 
 
+@pytest.mark.parametrize("q,rho", [(1, None), (2, None), (1, "refined")])
+def test_degenerate_hierarchies(gpu_lib, q, rho):
+    """A single level (q = 1, no refinement: the V-cycle is the exact base-mesh solve, so PCG ends
+    in one iteration), degree steps only (no refinement), and refinement at q = 1 (mesh steps
+    only): solves against the oracle's dense solution."""
+    ne, lo, hi = (3, 2, 2), (-1.5, -1.0, -1.0), (1.5, 1.0, 1.0)
+    dens = _two_centres if rho else None
+    g = gpu_lib.Octree(ne, lo, hi, q=q, rho=dens, delta_q=1e-4, max_depth=2, rtol=1e-12)
+    t = octree.Octree(ne, lo, hi, q, rho=dens, delta_q=1e-4, max_depth=2)
+    m = t.mesh()
+    assert g.n_elements == len(m.cells) and g.n_levels == len(octree.Hierarchy(t).meshes)
+    X, Y, Z = m.nodes()
+    bx, by, bz = m.boundary_points()
+    b = m.rhs(_gauss(4.0, (0.2, 0.1, -0.1))(X, Y, Z), 0.1 * np.cos(bx + 2 * by) * bz)
+    x, st = g.solve(_t(b[None]))
+    A, _ = m.dense()
+    ref = np.linalg.solve(A, b)
+    assert st[0]["status"] == 0
+    if g.n_levels == 1:
+        assert st[0]["iters"] == 1
+    assert np.abs(x.cpu().numpy()[0] - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
 def test_octree_arguments_are_checked(gpu_lib):
     with pytest.raises(gpu_lib.DgError):
         gpu_lib.Octree((9, 1, 1), (0, 0, 0), (1, 1, 1), q=2)          # more than 8 base elements per axis
