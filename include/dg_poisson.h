@@ -535,7 +535,7 @@ dg_status dg_octree_nodes(const dg_octree* octree, double* x, double* y, double*
 dg_status dg_octree_boundary_points(const dg_octree* octree, double* x, double* y, double* z);
 /* b = 4 pi M f + Nitsche lift of g (eq. hartree_poisson / fock_poisson on the auxiliary mesh):
  * device arrays f, b [nrhs][n_dofs] and g [nrhs][n_boundary]; g NULL: the Dirichlet data by
- * quadrature of f (dg_octree_boundary_data; synchronises the stream). */
+ * quadrature of f (dg_octree_boundary_data, into work space kept by the octree). */
 dg_status dg_octree_rhs(dg_octree* octree, int nrhs, const double* f, const double* g, double* b, void* stream);
 /* Dirichlet data by quadrature (Sec. 6.3): g_s(r) = sum_q W_q f_s(x_q) / |r - x_q| at the
  * Dirichlet points, over the finest level's nodes x_q with their GL weights W_q (no node lies on
@@ -556,7 +556,8 @@ dg_status dg_octree_vcycle(dg_octree* octree, int nrhs, const double* r, double*
  * be NULL): K_ij = sum_q W_q phi_i phi_j v_ij with the grid's GL weights, *e_x (host, may be NULL)
  * = sum over ordered pairs.  v_pairs [npairs][n_dofs] (device) receives the potentials if not
  * NULL.  Solves as dg_octree_solve (stats [npairs], host, may be NULL); synchronises the stream;
- * returns the worst solve status; allocates its work space. */
+ * returns the worst solve status; its work space is kept by the octree (allocated on the first
+ * call and when a call needs more). */
 dg_status dg_octree_exchange(dg_octree* octree, int norb, const double* phi, const double* g_pairs, double* v_pairs,
                              double* W, double* K, double* e_x, dg_rhs_stats* stats, void* stream);
 /* Tuning: right-hand sides per work-group of the octree operator kernels (1, 2 or 4; 0, the

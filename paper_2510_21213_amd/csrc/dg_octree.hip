@@ -803,6 +803,11 @@ struct dg_octree {
                                           // boundary points' x, y, z (3 x n_boundary), built on first use
     double* qpart = nullptr;              // its partial sums
     long long qpart_cap = 0;
+    // exchange and quadrature-data work space, kept between calls (grows to the largest call)
+    double *xrho = nullptr, *xb = nullptr, *xv = nullptr, *xpart = nullptr, *xg = nullptr;
+    int *xpi = nullptr, *xpj = nullptr;
+    long long xcap = 0, xpart_cap = 0, xg_cap = 0;
+    int xnorb = 0;
     std::vector<int> bsh;
     long long nbp = 0;                    // boundary points
     dg::LevelHost base;                   // uniform base mesh at degree 1 (coarsest solve)
@@ -1509,6 +1514,13 @@ void destroy(dg_octree* O) {
     ofree(O->bstart);
     ofree(O->qnodes);
     ofree(O->qpart);
+    ofree(O->xrho);
+    ofree(O->xb);
+    ofree(O->xv);
+    ofree(O->xpart);
+    ofree(O->xg);
+    ofree(O->xpi);
+    ofree(O->xpj);
     ofree(O->cdev);
     for (auto* v : {&O->wf, &O->wz, &O->wr, &O->wd0, &O->wd1, &O->wt})
         for (auto& p : *v) ofree(p);
@@ -1717,11 +1729,15 @@ void boundary_data(dg_octree* O, int nsrc, const double* f, double* g, hipStream
 
 void rhs(dg_octree* O, int nrhs, const double* f, const double* g, double* b, hipStream_t s) {
     const Level& L = O->lv[0];
-    double* gq = nullptr;
     if (!g && O->nbp > 0) {  // Dirichlet data by quadrature of f
-        gq = oalloc<double>((long long)nrhs * O->nbp);
-        boundary_data(O, nrhs, f, gq, s);
-        g = gq;
+        const long long need = (long long)nrhs * O->nbp;
+        if (need > O->xg_cap) {
+            ofree(O->xg);
+            O->xg = oalloc<double>(need);
+            O->xg_cap = need;
+        }
+        boundary_data(O, nrhs, f, O->xg, s);
+        g = O->xg;
     }
     const double pen = (double)(L.q + 1) * (L.q + 1) / O->opts.penalty_eps;
     const dim3 grid = node_grid(L.ndof, nrhs);
@@ -1732,10 +1748,6 @@ void rhs(dg_octree* O, int nrhs, const double* f, const double* g, double* b, hi
         case 5: hipLaunchKernelGGL(k_oct_rhs<5>, grid, dim3(256), 0, s, make_ref<5>(4), L.ne, O->nbp, pen, L.J, O->bstart, f, g, b); break;
     }
     OCHK(hipGetLastError());
-    if (gq) {
-        OCHK(hipStreamSynchronize(s));
-        ofree(gq);
-    }
 }
 
 // node coordinates and GL weights of the finest level, then the Dirichlet points (device, once)
@@ -1890,48 +1902,47 @@ int exchange(dg_octree* O, int norb, const double* phi, const double* g, double*
             hi.push_back(i);
             hj.push_back(j);
         }
-    int* dpi = upload(hi);
-    int* dpj = upload(hj);
-    double* rho = oalloc<double>(np * nd);
-    double* b = oalloc<double>(np * nd);
-    double* v = v_out ? v_out : oalloc<double>(np * nd);
-    const int nchunk = chunks_of(nd);
-    double* part = oalloc<double>((long long)np * nchunk);
-    int worst = DG_OK;
-    try {
-        launch_pair_products(nd, np, phi, dpi, dpj, rho, s);
-        rhs(O, np, rho, g, b, s);
-        worst = solve(O, np, b, v, stats, s);
-        if (W) hipLaunchKernelGGL(k_oct_wk, dim3((unsigned)((nd + 255) / 256), norb), dim3(256), 0, s, nd, norb, phi, v, W);
-        ensure_qnodes(O);
-        hipLaunchKernelGGL(k_oct_kij, dim3(nchunk, np), dim3(256), 0, s, nd, dpi, dpj, phi, v, O->qnodes + 3 * nd, part,
-                           nchunk);
-        std::vector<double> hp((size_t)np * nchunk);
-        OCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, s));
-        OCHK(hipStreamSynchronize(s));
-        double e = 0.0;
-        for (int p = 0; p < np; ++p) {
-            double k = 0.0;
-            for (int c = 0; c < nchunk; ++c) k += hp[(size_t)p * nchunk + c];
-            if (K) K[p] = k;
-            e += (hi[p] == hj[p] ? 1.0 : 2.0) * k;
-        }
-        if (ex) *ex = e;
-    } catch (...) {
-        ofree(dpi);
-        ofree(dpj);
-        ofree(rho);
-        ofree(b);
-        if (!v_out) ofree(v);
-        ofree(part);
-        throw;
+    if (norb != O->xnorb) {
+        ofree(O->xpi);
+        ofree(O->xpj);
+        O->xpi = upload(hi);
+        O->xpj = upload(hj);
+        O->xnorb = norb;
     }
-    ofree(dpi);
-    ofree(dpj);
-    ofree(rho);
-    ofree(b);
-    if (!v_out) ofree(v);
-    ofree(part);
+    if ((long long)np * nd > O->xcap) {
+        ofree(O->xrho);
+        ofree(O->xb);
+        ofree(O->xv);
+        O->xrho = oalloc<double>(np * nd);
+        O->xb = oalloc<double>(np * nd);
+        O->xv = oalloc<double>(np * nd);
+        O->xcap = np * nd;
+    }
+    const int nchunk = chunks_of(nd);
+    if ((long long)np * nchunk > O->xpart_cap) {
+        ofree(O->xpart);
+        O->xpart = oalloc<double>((long long)np * nchunk);
+        O->xpart_cap = (long long)np * nchunk;
+    }
+    double* v = v_out ? v_out : O->xv;
+    launch_pair_products(nd, np, phi, O->xpi, O->xpj, O->xrho, s);
+    rhs(O, np, O->xrho, g, O->xb, s);
+    const int worst = solve(O, np, O->xb, v, stats, s);
+    if (W) hipLaunchKernelGGL(k_oct_wk, dim3((unsigned)((nd + 255) / 256), norb), dim3(256), 0, s, nd, norb, phi, v, W);
+    ensure_qnodes(O);
+    hipLaunchKernelGGL(k_oct_kij, dim3(nchunk, np), dim3(256), 0, s, nd, O->xpi, O->xpj, phi, v, O->qnodes + 3 * nd,
+                       O->xpart, nchunk);
+    std::vector<double> hp((size_t)np * nchunk);
+    OCHK(hipMemcpyAsync(hp.data(), O->xpart, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, s));
+    OCHK(hipStreamSynchronize(s));
+    double e = 0.0;
+    for (int p = 0; p < np; ++p) {
+        double k = 0.0;
+        for (int c = 0; c < nchunk; ++c) k += hp[(size_t)p * nchunk + c];
+        if (K) K[p] = k;
+        e += (hi[p] == hj[p] ? 1.0 : 2.0) * k;
+    }
+    if (ex) *ex = e;
     return worst;
 }
 
